@@ -1,0 +1,17 @@
+"""Oracle for the space-time heat BEM (arXiv 2102.09811) -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously-correct CPU implementation of everything the HIP path computes.  Only
+``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may import it.
+It shares no code with ``paper_2102_09811_amd`` and does not import it.
+
+* ``oracle.c`` (long double, OpenMP): temporal antiderivatives, triangle and Sauter-Schwab rules,
+  pair classification, block assembly (direct and the paper's i_t order), representation formula.
+* ``downstream.py`` (numpy/scipy, float64): mass matrices, L2 projections, block-Toeplitz apply,
+  right-hand side, time marching, GMRES, L2 / l2 errors.
+"""
+from .core import (lib, build, temporal, blockfun, triangle_rule, ss_rule, gauss_legendre01,
+                   pair_points, assemble, repr_eval)
+from . import downstream
+
+__all__ = ["lib", "build", "temporal", "blockfun", "triangle_rule", "ss_rule",
+           "gauss_legendre01", "pair_points", "assemble", "repr_eval", "downstream"]
