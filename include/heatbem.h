@@ -1,0 +1,166 @@
+/*
+ * heatbem.h -- C ABI of the MI355X (gfx950) space-time boundary element library for the 3D heat
+ * equation, following Zapletal, Watschinger, Of, Merta, "Semi-analytic integration for a parallel
+ * space-time boundary element method modeling the heat equation" (arXiv 2102.09811).
+ *
+ * Problem (Sec. 1): du/dt - alpha Laplace u = 0 in Omega x (0, T), u(x, 0) = 0, with Dirichlet
+ * data on Sigma = dOmega x (0, T).  Omega's boundary is given as a closed triangle mesh Gamma_h
+ * (E_x triangles, N_x vertices); (0, T) is cut into E_t uniform steps of length h = T / E_t
+ * (tensor-product space-time mesh, Sec. 3).
+ *
+ * Conventions for every function:
+ *   - Return value 0 (HB_OK) on success, a negative HB_E* code otherwise; hb_last_error() then
+ *     holds a message.  No C++ exception crosses this boundary.
+ *   - "Device pointer" arguments are addresses in the current HIP device's memory (for example
+ *     the data_ptr() of a PyTorch tensor); "host pointer" arguments are ordinary process memory.
+ *     The caller owns every pointer it passes; the library copies what it keeps.
+ *   - Coefficient vectors are time-major (Sec. 3): entry [i * n + j] is time interval i
+ *     (0-based) and spatial index j.  p0 x p0 vectors (Neumann datum w) have n = E_x;
+ *     p1 x p0 vectors (Dirichlet datum g) have n = N_x.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.  Calls are
+ *     stream-ordered: device outputs are complete when the stream reaches the end of the call.
+ *     A context must not be used from two host threads at once.
+ *   - Block storage: block d of an operator is a dense row-major matrix, blocks stored d-major:
+ *     V: [E_t][E_x][E_x] (p0 test x p0 trial), K: [E_t][E_x][N_x] (p0 test x p1 trial).
+ */
+#ifndef HEATBEM_H
+#define HEATBEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define HB_OK 0
+#define HB_EINVAL (-1)   /* bad argument (size, range, null pointer, unknown enum) */
+#define HB_EMESH (-2)    /* mesh is not a valid closed 2-manifold triangulation */
+#define HB_EORIENT (-3)  /* mesh orientation inconsistent or not outward */
+#define HB_ENOMEM (-4)   /* device or host allocation failed */
+#define HB_EHIP (-5)     /* a HIP runtime call failed */
+#define HB_ENOCONV (-6)  /* iterative solver stopped before reaching the tolerance */
+#define HB_ESTATE (-7)   /* call order violated (e.g. apply before assemble) */
+
+/* ---- operators (bit flags for hb_assemble) ---- */
+#define HB_OP_V 1u /* single-layer operator V_h, Sec. 3.1 */
+#define HB_OP_K 2u /* double-layer operator K_h, Sec. 3.2 */
+
+/* ---- assembly precision ---- */
+#define HB_PREC_FP64 0  /* every quadrature point in double precision */
+#define HB_PREC_MIXED 1 /* separated pairs at d >= mixed_d_min in float (see hb_options) */
+
+/* ---- element types for block copies / storage ---- */
+#define HB_DTYPE_F64 0
+#define HB_DTYPE_F32 1
+
+typedef struct hb_ctx hb_ctx;
+
+typedef struct hb_options {
+  int32_t ss_order;     /* Gauss points per [0,1] coordinate of the regularised rules for
+                           touching pairs (Sec. 5.2, eq. for the [0,1]^4 tensor rule); default 4,
+                           range 1..8. */
+  int32_t d_switch;     /* blocks d >= d_switch are integrated in time by the even Taylor
+                           series of the hat-weighted heat kernel instead of second differences
+                           of G^{dtau dt}; default 8, minimum 8; values >= E_t disable it. */
+  int32_t storage;      /* HB_DTYPE_F64 (default) or HB_DTYPE_F32 block storage. */
+  int32_t mixed_d_min;  /* HB_PREC_MIXED: first d whose separated pairs use float; default 2,
+                           minimum 2 (d = 0, 1 and all touching pairs always use double). */
+  int32_t reserved[12]; /* must be zero */
+} hb_options;
+
+/* Fill *opt with the defaults above. */
+void hb_default_options(hb_options *opt);
+
+/* Host-only mesh check (no GPU use).  verts: host, [n_verts][3] float64; tris: host,
+ * [n_tris][3] int32 vertex indices, counter-clockwise seen from outside.  Validates the mesh as
+ * hb_create does and, if class_counts is not NULL, writes the number of ordered triangle pairs
+ * sharing 0, 1, 2 and 3 vertices (separated, vertex, edge, identical; Sec. 3.1 "Galerkin
+ * weights").  Returns HB_OK, HB_EINVAL, HB_EMESH or HB_EORIENT. */
+int hb_check_mesh(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                  int64_t class_counts[4]);
+
+/* Create a context for mesh Gamma_h, heat capacity alpha > 0, final time T > 0 and n_t >= 1
+ * uniform steps (Sec. 3).  verts/tris are host pointers as for hb_check_mesh.  Validates the
+ * mesh (closed, 2-manifold, consistently and outward oriented, no repeated or coincident
+ * vertices, no degenerate triangle), classifies the triangle pairs, builds the quadrature tables
+ * and uploads geometry to the current device.  opt may be NULL (defaults).  On success *out owns
+ * its device memory until hb_destroy. */
+int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t *tris,
+              int64_t n_tris, double alpha, double T, int32_t n_t, const hb_options *opt);
+
+/* Release everything the context owns.  NULL is accepted.  Waits for the device. */
+void hb_destroy(hb_ctx *ctx);
+
+/* Message of the last failed call on ctx (or of the last failed hb_create / hb_check_mesh when
+ * ctx is NULL).  Valid until the next call on the same context. */
+const char *hb_last_error(const hb_ctx *ctx);
+
+/* Sizes: writes E_x, N_x, E_t, and the number of touching ordered pairs. */
+int hb_sizes(const hb_ctx *ctx, int64_t *n_tris, int64_t *n_verts, int32_t *n_t,
+             int64_t *n_touching);
+
+/* Assemble all E_t blocks of the operators in `ops` (HB_OP_V | HB_OP_K) on the device
+ * (Sec. 3.1 eq. for V_h^d, Sec. 3.2 eq. for K_h^d; assembly order Sec. 5).  Each entry is the
+ * spatial quadrature over a triangle pair of the exact temporal integral: Radon's 7-point rule
+ * on each triangle for separated pairs, Sauter-Schwab [0,1]^4 rules of order opt.ss_order for
+ * pairs sharing a vertex, an edge or the whole triangle.  precision: HB_PREC_FP64 or
+ * HB_PREC_MIXED.  Block storage is allocated on first use and reused. */
+int hb_assemble(hb_ctx *ctx, uint32_t ops, int32_t precision, void *stream);
+
+/* Copy blocks d0 .. d0 + nd - 1 of op (HB_OP_V or HB_OP_K) into dst (layout [nd][rows][cols]
+ * as the block storage), converting to dtype (HB_DTYPE_F64 / HB_DTYPE_F32).  dst is a device
+ * pointer if dst_on_device != 0, else a host pointer (the copy is then synchronous). */
+int hb_get_blocks(hb_ctx *ctx, uint32_t op, int32_t d0, int32_t nd, void *dst, int32_t dtype,
+                  int32_t dst_on_device, void *stream);
+
+/* Block lower-triangular Toeplitz product y^k = sum_{d=0}^{k} A^d x^{k-d} (Sec. 3.1 eq. for
+ * V_h w; Sec. 3.2 eq. for K_h) for op = HB_OP_V (x: E_t x E_x) or HB_OP_K (x: E_t x N_x);
+ * y: E_t x E_x.  x, y: device pointers, float64, time-major, not overlapping. */
+int hb_apply(hb_ctx *ctx, uint32_t op, const double *x, double *y, void *stream);
+
+/* Right-hand side of the Dirichlet system b = (1/2 M_h + K_h) g (Sec. 3.4) with
+ * M_h = h blockdiag(M_x), M_x[l, j] = int phi^0_l phi^1_j.  g: device, E_t x N_x (coefficients
+ * of Dirichlet data in the p1-space / p0-time space); b: device, E_t x E_x. */
+int hb_rhs_dirichlet(hb_ctx *ctx, const double *g, double *b, void *stream);
+
+/* Solvers for V_h w = b (Sec. 3.4). */
+#define HB_SOLVE_GMRES 0      /* unrestarted GMRES in double on the block system */
+#define HB_SOLVE_TIMEMARCH 1  /* block forward substitution with the inverse of V_h^0 */
+
+typedef struct hb_solve_opts {
+  int32_t method;   /* HB_SOLVE_* */
+  int32_t max_iter; /* GMRES iteration cap (default 500 if <= 0) */
+  double tol;       /* relative residual ||b - V_h w|| / ||b|| target (default 1e-8 if <= 0) */
+  int32_t reserved[8];
+} hb_solve_opts;
+
+typedef struct hb_solve_info {
+  int32_t iterations;   /* GMRES iterations (0 for time marching) */
+  double rel_residual;  /* ||b - V_h w|| / ||b|| recomputed in double after the solve */
+  double seconds;       /* wall time of the solve */
+  int32_t reserved[8];
+} hb_solve_info;
+
+/* Solve V_h w = b for w.  b, w: device pointers, E_t x E_x, float64.  info may be NULL.
+ * Returns HB_ENOCONV (w then holds the last iterate) when GMRES hits max_iter first. */
+int hb_solve(hb_ctx *ctx, const double *b, double *w, const hb_solve_opts *opts,
+             hb_solve_info *info, void *stream);
+
+/* Representation formula u = V~ w - W g (Sec. 2, potentials of Sec. 3.5) at P space-time points
+ * pts[P][4] = (x, y, z, t), 0 <= t <= T, off Gamma_h (not checked; accuracy near Gamma_h is
+ * the caller's concern).  w: E_t x E_x Neumann coefficients, g: E_t x N_x Dirichlet
+ * coefficients, u: P outputs.  All device pointers, float64.  The spatial rule is the 7-point
+ * rule of hb_assemble.  sl / dl may be NULL; otherwise they receive V~ w and W g. */
+int hb_eval_repr(hb_ctx *ctx, const double *pts, int64_t P, const double *w, const double *g,
+                 double *u, double *sl, double *dl, void *stream);
+
+/* Durations in milliseconds of the kernels of the last hb_assemble on this context, measured
+ * with HIP events on the caller's stream: [0] separated-pair kernel, [1] touching-pair kernels,
+ * [2] whole call.  Calls hipEventSynchronize. */
+int hb_last_assembly_ms(hb_ctx *ctx, double ms[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEATBEM_H */

@@ -1,0 +1,222 @@
+"""Thin ctypes binding of libheatbem.so (the C ABI declared in include/heatbem.h).
+
+Argument marshalling only: every step of the computation runs in the library's HIP kernels.
+PyTorch supplies device memory and the current stream.  The library must be built
+(``__graft_entry__.build()``); importing this module without it raises immediately.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libheatbem.so")
+
+HB_OK, HB_EINVAL, HB_EMESH, HB_EORIENT, HB_ENOMEM, HB_EHIP, HB_ENOCONV, HB_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+HB_OP_V, HB_OP_K = 1, 2
+HB_PREC_FP64, HB_PREC_MIXED = 0, 1
+HB_DTYPE_F64, HB_DTYPE_F32 = 0, 1
+HB_SOLVE_GMRES, HB_SOLVE_TIMEMARCH = 0, 1
+
+EXPORTED = ["hb_default_options", "hb_check_mesh", "hb_create", "hb_destroy", "hb_last_error",
+            "hb_sizes", "hb_assemble", "hb_get_blocks", "hb_apply", "hb_rhs_dirichlet",
+            "hb_solve", "hb_eval_repr", "hb_last_assembly_ms"]
+
+
+class HBError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("heatbem error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("ss_order", ctypes.c_int32), ("d_switch", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("mixed_d_min", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 12)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("reserved", ctypes.c_int32 * 8)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libheatbem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libheatbem.so not built: run __graft_entry__.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.hb_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.hb_default_options.restype = None
+    L.hb_check_mesh.argtypes = [vp, i64, vp, i64, vp]
+    L.hb_create.argtypes = [ctypes.POINTER(vp), vp, i64, vp, i64, f64, f64, i32, ctypes.POINTER(Options)]
+    L.hb_destroy.argtypes = [vp]
+    L.hb_destroy.restype = None
+    L.hb_last_error.argtypes = [vp]
+    L.hb_last_error.restype = ctypes.c_char_p
+    L.hb_sizes.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    L.hb_assemble.argtypes = [vp, ctypes.c_uint32, i32, vp]
+    L.hb_get_blocks.argtypes = [vp, ctypes.c_uint32, i32, i32, vp, i32, i32, vp]
+    L.hb_apply.argtypes = [vp, ctypes.c_uint32, vp, vp, vp]
+    L.hb_rhs_dirichlet.argtypes = [vp, vp, vp, vp]
+    L.hb_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
+    L.hb_eval_repr.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
+    L.hb_last_assembly_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    for name in EXPORTED:
+        fn = getattr(L, name)
+        if fn.restype is ctypes.c_int:   # default restype
+            fn.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def default_options(**kw):
+    o = Options()
+    lib().hb_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _mesh_arrays(verts, tris):
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
+        raise ValueError("verts must be (N, 3) float64 and tris (E, 3) int32")
+    return v, t
+
+
+def check_mesh(verts, tris):
+    """(status code, class counts [separated, vertex, edge, identical]) -- host only, no GPU."""
+    v, t = _mesh_arrays(verts, tris)
+    counts = np.zeros(4, dtype=np.int64)
+    rc = lib().hb_check_mesh(v.ctypes.data, len(v), t.ctypes.data, len(t), counts.ctypes.data)
+    return rc, counts, lib().hb_last_error(None).decode()
+
+
+def _ptr(tensor):
+    import torch
+    if not isinstance(tensor, torch.Tensor) or not tensor.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not tensor.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(tensor.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """One mesh / time grid on the current device; owns the assembled blocks."""
+
+    def __init__(self, verts, tris, alpha, T, n_t, **opts):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("heatbem needs a HIP device")
+        v, t = _mesh_arrays(verts, tris)
+        self.n_tris, self.n_verts, self.n_t = len(t), len(v), int(n_t)
+        self.alpha, self.T = float(alpha), float(T)
+        o = default_options(**opts)
+        self.storage = o.storage
+        h = ctypes.c_void_p()
+        rc = lib().hb_create(ctypes.byref(h), v.ctypes.data, len(v), t.ctypes.data, len(t),
+                             self.alpha, self.T, self.n_t, ctypes.byref(o))
+        if rc != HB_OK:
+            raise HBError(rc, lib().hb_last_error(None).decode())
+        self._h = h
+
+    def _check(self, rc):
+        if rc != HB_OK:
+            raise HBError(rc, lib().hb_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sizes(self):
+        a, b, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        c = ctypes.c_int32()
+        self._check(lib().hb_sizes(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
+
+    def assemble(self, ops=HB_OP_V | HB_OP_K, precision=HB_PREC_FP64, stream=None):
+        self._check(lib().hb_assemble(self._h, ops, precision, _stream(stream)))
+
+    def last_assembly_ms(self):
+        ms = (ctypes.c_double * 3)()
+        self._check(lib().hb_last_assembly_ms(self._h, ms))
+        return list(ms)
+
+    def blocks(self, op, d0=0, nd=None, dtype=None, device=True, stream=None):
+        """Blocks d0 .. d0+nd-1 of op as a (nd, E_x, cols) tensor (device) or ndarray (host)."""
+        import torch
+        nd = self.n_t - d0 if nd is None else nd
+        cols = self.n_tris if op == HB_OP_V else self.n_verts
+        if dtype is None:
+            dtype = HB_DTYPE_F32 if self.storage == HB_DTYPE_F32 else HB_DTYPE_F64
+        if device:
+            out = torch.empty((nd, self.n_tris, cols), dtype=torch.float64 if dtype == HB_DTYPE_F64 else torch.float32, device="cuda")
+            self._check(lib().hb_get_blocks(self._h, op, d0, nd, _ptr(out), dtype, 1, _stream(stream)))
+            return out
+        out = np.empty((nd, self.n_tris, cols), dtype=np.float64 if dtype == HB_DTYPE_F64 else np.float32)
+        self._check(lib().hb_get_blocks(self._h, op, d0, nd, ctypes.c_void_p(out.ctypes.data), dtype, 0, _stream(stream)))
+        return out
+
+    def apply(self, op, x, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty((self.n_t, self.n_tris), dtype=torch.float64, device="cuda")
+        self._check(lib().hb_apply(self._h, op, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def rhs_dirichlet(self, g, b=None, stream=None):
+        import torch
+        if b is None:
+            b = torch.empty((self.n_t, self.n_tris), dtype=torch.float64, device="cuda")
+        self._check(lib().hb_rhs_dirichlet(self._h, _ptr(g), _ptr(b), _stream(stream)))
+        return b
+
+    def solve(self, b, method=HB_SOLVE_GMRES, tol=1e-8, max_iter=500, w=None, stream=None):
+        import torch
+        if w is None:
+            w = torch.empty((self.n_t, self.n_tris), dtype=torch.float64, device="cuda")
+        o = SolveOpts()
+        o.method, o.tol, o.max_iter = method, tol, max_iter
+        info = SolveInfo()
+        rc = lib().hb_solve(self._h, _ptr(b), _ptr(w), ctypes.byref(o), ctypes.byref(info), _stream(stream))
+        if rc not in (HB_OK, HB_ENOCONV):
+            self._check(rc)
+        return w, {"iterations": info.iterations, "rel_residual": info.rel_residual,
+                   "seconds": info.seconds, "converged": rc == HB_OK}
+
+    def eval_repr(self, pts, w, g, stream=None, parts=False):
+        import torch
+        P = pts.shape[0]
+        u = torch.empty(P, dtype=torch.float64, device="cuda")
+        sl = torch.empty_like(u) if parts else None
+        dl = torch.empty_like(u) if parts else None
+        self._check(lib().hb_eval_repr(self._h, _ptr(pts), P, _ptr(w), _ptr(g), _ptr(u),
+                                       _ptr(sl) if parts else None, _ptr(dl) if parts else None,
+                                       _stream(stream)))
+        return (u, sl, dl) if parts else u

@@ -1,0 +1,649 @@
+// Host runtime of the heat BEM library: mesh validation, triangle-pair classification,
+// quadrature and Taylor tables, device uploads, and the C ABI entry points that manage a context.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hb_internal.h"
+
+namespace {
+
+thread_local std::string g_err;  // last error of calls without a context
+
+typedef long double ld;
+const ld kPi = 3.141592653589793238462643383279502884L;
+
+int fail(hb_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  else g_err = msg;
+  return code;
+}
+
+#define HB_HIP(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? HB_ENOMEM : HB_EHIP,                 \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+// ---------------------------------------------------------------------------------------------
+// Mesh validation: closed, 2-manifold, consistently and outward oriented, no coincident vertices,
+// no degenerate or repeated-vertex triangle, every vertex used.
+// ---------------------------------------------------------------------------------------------
+int validate_mesh(hb_ctx *c, const double *V, int64_t nv, const int32_t *T, int64_t ne) {
+  if (!V || !T) return fail(c, HB_EINVAL, "null mesh pointer");
+  if (nv < 4 || ne < 4) return fail(c, HB_EMESH, "a closed surface needs >= 4 vertices and triangles");
+  if (ne > (int64_t)1 << 24 || nv > (int64_t)1 << 24)
+    return fail(c, HB_EINVAL, "mesh too large");
+  for (int64_t i = 0; i < 3 * nv; ++i)
+    if (!std::isfinite(V[i])) return fail(c, HB_EMESH, "non-finite vertex coordinate");
+  std::vector<int> used(nv, 0);
+  double lo[3] = {V[0], V[1], V[2]}, hi[3] = {V[0], V[1], V[2]};
+  for (int64_t i = 0; i < nv; ++i)
+    for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], V[3 * i + k]); hi[k] = std::max(hi[k], V[3 * i + k]); }
+  double diam2 = 0;
+  for (int k = 0; k < 3; ++k) diam2 += (hi[k] - lo[k]) * (hi[k] - lo[k]);
+  for (int64_t t = 0; t < ne; ++t) {
+    int32_t a = T[3 * t], b = T[3 * t + 1], d = T[3 * t + 2];
+    if (a < 0 || b < 0 || d < 0 || a >= nv || b >= nv || d >= nv)
+      return fail(c, HB_EMESH, "triangle " + std::to_string(t) + " has an out-of-range vertex index");
+    if (a == b || b == d || a == d)
+      return fail(c, HB_EMESH, "triangle " + std::to_string(t) + " repeats a vertex");
+    used[a] = used[b] = used[d] = 1;
+    double e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) { e1[k] = V[3 * b + k] - V[3 * a + k]; e2[k] = V[3 * d + k] - V[3 * a + k]; }
+    double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+           cz = e1[0] * e2[1] - e1[1] * e2[0];
+    if (cx * cx + cy * cy + cz * cz <= 1e-24 * diam2 * diam2)
+      return fail(c, HB_EMESH, "triangle " + std::to_string(t) + " is degenerate");
+  }
+  for (int64_t i = 0; i < nv; ++i)
+    if (!used[i]) return fail(c, HB_EMESH, "vertex " + std::to_string(i) + " belongs to no triangle");
+  // coincident vertices with different indices
+  std::vector<int64_t> ord(nv);
+  for (int64_t i = 0; i < nv; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+    for (int k = 0; k < 3; ++k)
+      if (V[3 * x + k] != V[3 * y + k]) return V[3 * x + k] < V[3 * y + k];
+    return x < y;
+  });
+  for (int64_t i = 1; i < nv; ++i)
+    if (V[3 * ord[i]] == V[3 * ord[i - 1]] && V[3 * ord[i] + 1] == V[3 * ord[i - 1] + 1] &&
+        V[3 * ord[i] + 2] == V[3 * ord[i - 1] + 2])
+      return fail(c, HB_EMESH, "vertices " + std::to_string(ord[i - 1]) + " and " +
+                                   std::to_string(ord[i]) + " coincide");
+  // every undirected edge exactly twice, once in each direction
+  std::map<std::pair<int32_t, int32_t>, std::pair<int, int>> edges;  // (min,max) -> (+dir, -dir)
+  for (int64_t t = 0; t < ne; ++t)
+    for (int k = 0; k < 3; ++k) {
+      int32_t p = T[3 * t + k], q = T[3 * t + (k + 1) % 3];
+      auto &e = edges[{std::min(p, q), std::max(p, q)}];
+      if (p < q) e.first++;
+      else e.second++;
+    }
+  for (auto &kv : edges) {
+    int tot = kv.second.first + kv.second.second;
+    if (tot != 2)
+      return fail(c, HB_EMESH, "edge (" + std::to_string(kv.first.first) + "," +
+                                   std::to_string(kv.first.second) + ") belongs to " +
+                                   std::to_string(tot) + " triangles (mesh not closed/manifold)");
+    if (kv.second.first != 1)
+      return fail(c, HB_EORIENT, "inconsistent orientation at edge (" +
+                                     std::to_string(kv.first.first) + "," +
+                                     std::to_string(kv.first.second) + ")");
+  }
+  // outward: positive enclosed volume
+  ld vol = 0;
+  for (int64_t t = 0; t < ne; ++t) {
+    const double *a = V + 3 * T[3 * t], *b = V + 3 * T[3 * t + 1], *d = V + 3 * T[3 * t + 2];
+    vol += (ld)a[0] * ((ld)b[1] * d[2] - (ld)b[2] * d[1]) - (ld)a[1] * ((ld)b[0] * d[2] - (ld)b[2] * d[0]) +
+           (ld)a[2] * ((ld)b[0] * d[1] - (ld)b[1] * d[0]);
+  }
+  if (!(vol > 0)) return fail(c, HB_EORIENT, "triangles are oriented inward (negative volume)");
+  return HB_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Pair classification by shared vertex indices.  For a touching ordered pair (test l, trial m) the
+// rule expects the shared vertices first and in the same order in both panels:
+//   identical: both panels in the test's order;  edge: (s, t, rest) in both;
+//   vertex: (s, then the other two in the panel's cyclic order) in both.
+// ---------------------------------------------------------------------------------------------
+struct Adjacency {
+  std::vector<int64_t> start;
+  std::vector<int32_t> tri;
+};
+
+Adjacency vertex_triangles(const int32_t *T, int64_t nv, int64_t ne) {
+  Adjacency A;
+  A.start.assign(nv + 1, 0);
+  for (int64_t i = 0; i < 3 * ne; ++i) A.start[T[i] + 1]++;
+  for (int64_t i = 0; i < nv; ++i) A.start[i + 1] += A.start[i];
+  A.tri.resize(3 * ne);
+  std::vector<int64_t> fill(A.start.begin(), A.start.end() - 1);
+  for (int64_t t = 0; t < ne; ++t)
+    for (int k = 0; k < 3; ++k) A.tri[fill[T[3 * t + k]]++] = (int32_t)t;
+  return A;
+}
+
+// Local orders (pl, pm) of the vertices of panels l and m; returns the number of shared vertices.
+int pair_order(const int32_t *tl, const int32_t *tm, int pl[3], int pm[3]) {
+  int where[3] = {-1, -1, -1};  // where[i]: local index in m of vertex i of l
+  int ns = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (tl[i] == tm[j]) { where[i] = j; ++ns; }
+  if (ns == 3) {
+    for (int i = 0; i < 3; ++i) { pl[i] = i; pm[i] = where[i]; }
+  } else if (ns == 2) {
+    int k = 0;
+    for (int i = 0; i < 3; ++i)
+      if (where[i] >= 0) { pl[k] = i; pm[k] = where[i]; ++k; }
+    for (int i = 0; i < 3; ++i)
+      if (where[i] < 0) pl[2] = i;
+    pm[2] = 3 - pm[0] - pm[1];
+  } else if (ns == 1) {
+    int i0 = 0;
+    while (where[i0] < 0) ++i0;
+    pl[0] = i0; pl[1] = (i0 + 1) % 3; pl[2] = (i0 + 2) % 3;
+    int j0 = where[i0];
+    pm[0] = j0; pm[1] = (j0 + 1) % 3; pm[2] = (j0 + 2) % 3;
+  }
+  return ns;
+}
+
+void count_classes(const int32_t *T, int64_t nv, int64_t ne, int64_t counts[4],
+                   std::vector<hb::TouchPair> *out, const double *V) {
+  Adjacency A = vertex_triangles(T, nv, ne);
+  for (int k = 0; k < 4; ++k) counts[k] = 0;
+  std::vector<int64_t> seen(ne, -1);
+  for (int64_t l = 0; l < ne; ++l) {
+    const int32_t *tl = T + 3 * l;
+    for (int k = 0; k < 3; ++k)
+      for (int64_t s = A.start[tl[k]]; s < A.start[tl[k] + 1]; ++s) {
+        int32_t m = A.tri[s];
+        if (seen[m] == l) continue;
+        seen[m] = l;
+        int pl[3], pm[3];
+        const int32_t *tm = T + 3 * m;
+        int ns = pair_order(tl, tm, pl, pm);
+        counts[ns]++;
+        if (out) {
+          hb::TouchPair p{};
+          p.l = (int32_t)l; p.m = m; p.cls = ns;
+          for (int j = 0; j < 3; ++j) p.vtx[j] = tm[pm[j]];
+          for (int cc = 0; cc < 3; ++cc) {
+            p.E1[cc] = V[3 * tl[pl[1]] + cc] - V[3 * tl[pl[0]] + cc];
+            p.E2[cc] = V[3 * tl[pl[2]] + cc] - V[3 * tl[pl[1]] + cc];
+            p.F1[cc] = V[3 * tm[pm[1]] + cc] - V[3 * tm[pm[0]] + cc];
+            p.F2[cc] = V[3 * tm[pm[2]] + cc] - V[3 * tm[pm[1]] + cc];
+          }
+          out->push_back(p);
+        }
+      }
+  }
+  counts[0] = ne * ne - counts[1] - counts[2] - counts[3];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Quadrature and series tables (long double on the host, rounded once).
+// ---------------------------------------------------------------------------------------------
+// Gauss-Legendre on [0,1]: roots of P_n by Newton from Tricomi's initial guesses.
+void legendre01(int n, std::vector<ld> &x, std::vector<ld> &w) {
+  x.resize(n);
+  w.resize(n);
+  for (int k = 1; k <= n; ++k) {
+    ld th = kPi * (4.0L * k - 1.0L) / (4.0L * n + 2.0L);
+    ld t = (1.0L - (n - 1.0L) / (8.0L * n * n * n)) * cosl(th);
+    ld pn = 0, dpn = 0;
+    for (int it = 0; it < 60; ++it) {
+      ld pm1 = 1.0L, p = t;  // P_0, P_1
+      for (int j = 2; j <= n; ++j) {
+        ld pj = ((2 * j - 1) * t * p - (j - 1) * pm1) / j;
+        pm1 = p;
+        p = pj;
+      }
+      if (n == 1) { p = t; pm1 = 1.0L; }
+      pn = p;
+      dpn = n * (pm1 - t * p) / (1.0L - t * t);
+      ld step = pn / dpn;
+      t -= step;
+      if (fabsl(step) <= 1e-20L * fabsl(t) + 1e-22L) break;
+    }
+    {
+      ld pm1 = 1.0L, p = t;
+      for (int j = 2; j <= n; ++j) {
+        ld pj = ((2 * j - 1) * t * p - (j - 1) * pm1) / j;
+        pm1 = p;
+        p = pj;
+      }
+      if (n == 1) { p = t; pm1 = 1.0L; }
+      dpn = n * (pm1 - t * p) / (1.0L - t * t);
+    }
+    x[k - 1] = (1.0L + t) / 2.0L;
+    w[k - 1] = 1.0L / ((1.0L - t * t) * dpn * dpn);
+  }
+}
+
+// Regularised rules (Sauter & Schwab, Sec. 5.2 of their book) written as the coefficients of
+// r = x - y in the edge vectors, so the kernel never subtracts two nearby points:
+//   r = c1 E1 + c2 E2 + c3 F1 + c4 F2,  E1 = a1-a0, E2 = a2-a1 (test), F1 = b1-b0, F2 = b2-b1.
+// Reference panel {0 <= s2 <= s1 <= 1}, chi(s) = v0 + s1 (v1-v0) + s2 (v2-v1).  Each entry holds
+// (c1, c2, c3, c4, weight * Jacobian, trial barycentrics (1-y1, y1-y2, y2)).
+struct SSNode { ld c[4], w, lam[3]; };
+
+void ss_nodes(int cls, int M, std::vector<SSNode> &out) {
+  std::vector<ld> g, gw;
+  legendre01(M, g, gw);
+  out.clear();
+  int nmaps = cls == 3 ? 6 : (cls == 2 ? 5 : 2);
+  for (int s = 0; s < nmaps; ++s)
+    for (int i0 = 0; i0 < M; ++i0)
+      for (int i1 = 0; i1 < M; ++i1)
+        for (int i2 = 0; i2 < M; ++i2)
+          for (int i3 = 0; i3 < M; ++i3) {
+            ld xi = g[i0], a = g[i1], b = g[i2], e = g[i3];
+            ld wt = gw[i0] * gw[i1] * gw[i2] * gw[i3];
+            ld x1, x2, y1, y2, d1, d2, J;  // d1 = x1 - y1, d2 = x2 - y2 in product form
+            if (cls == 3) {
+              J = xi * xi * xi * a * a * b;
+              switch (s) {
+                case 0: x1 = xi; x2 = xi * (1 - a + a * b); y1 = xi * (1 - a * b * e); y2 = xi * (1 - a);
+                        d1 = xi * a * b * e; d2 = xi * a * b; break;
+                case 1: x1 = xi * (1 - a * b * e); x2 = xi * (1 - a); y1 = xi; y2 = xi * (1 - a + a * b);
+                        d1 = -xi * a * b * e; d2 = -xi * a * b; break;
+                case 2: x1 = xi; x2 = xi * a * (1 - b + b * e); y1 = xi * (1 - a * b); y2 = xi * a * (1 - b);
+                        d1 = xi * a * b; d2 = xi * a * b * e; break;
+                case 3: x1 = xi * (1 - a * b); x2 = xi * a * (1 - b); y1 = xi; y2 = xi * a * (1 - b + b * e);
+                        d1 = -xi * a * b; d2 = -xi * a * b * e; break;
+                case 4: x1 = xi * (1 - a * b * e); x2 = xi * a * (1 - b * e); y1 = xi; y2 = xi * a * (1 - b);
+                        d1 = -xi * a * b * e; d2 = xi * a * b * (1 - e); break;
+                default: x1 = xi; x2 = xi * a * (1 - b); y1 = xi * (1 - a * b * e); y2 = xi * a * (1 - b * e);
+                         d1 = xi * a * b * e; d2 = -xi * a * b * (1 - e); break;
+              }
+              (void)x1; (void)x2;
+              out.push_back({{d1, d2, 0, 0}, wt * J, {1 - y1, y1 - y2, y2}});
+            } else if (cls == 2) {
+              J = xi * xi * xi * a * a * (s == 0 ? 1.0L : b);
+              switch (s) {
+                case 0: x1 = xi; x2 = xi * a * e; y1 = xi * (1 - a * b); y2 = xi * a * (1 - b);
+                        d1 = xi * a * b; break;
+                case 1: x1 = xi; x2 = xi * a; y1 = xi * (1 - a * b * e); y2 = xi * a * b * (1 - e);
+                        d1 = xi * a * b * e; break;
+                case 2: x1 = xi * (1 - a * b); x2 = xi * a * (1 - b); y1 = xi; y2 = xi * a * b * e;
+                        d1 = -xi * a * b; break;
+                case 3: x1 = xi * (1 - a * b * e); x2 = xi * a * b * (1 - e); y1 = xi; y2 = xi * a;
+                        d1 = -xi * a * b * e; break;
+                default: x1 = xi * (1 - a * b * e); x2 = xi * a * (1 - b * e); y1 = xi; y2 = xi * a * b;
+                         d1 = -xi * a * b * e; break;
+              }
+              // shared edge: F1 == E1, so r = (x1 - y1) E1 + x2 E2 - y2 F2
+              out.push_back({{d1, x2, 0, -y2}, wt * J, {1 - y1, y1 - y2, y2}});
+            } else {
+              J = xi * xi * xi * b;
+              if (s == 0) { x1 = xi; x2 = xi * a; y1 = xi * b; y2 = xi * b * e; }
+              else { x1 = xi * b; x2 = xi * b * e; y1 = xi; y2 = xi * a; }
+              out.push_back({{x1, x2, -y1, -y2}, wt * J, {1 - y1, y1 - y2, y2}});
+            }
+          }
+}
+
+// Even Taylor series of the hat-weighted kernel in time.  With s = d h and w = rho^2/(4 alpha s),
+//   int_{-h}^{h} (h - |u|) f(s + u) du = sum_k 2 h^{2k+2}/(2k+2)! f^{(2k)}(s),
+// and for f(s) = s^{-p} exp(-a/s):  f^{(n)}(s) = s^{-p-n} exp(-w) Q_n(w),
+//   Q_0 = 1,  Q_{n+1}(w) = (w - n - p) Q_n(w) - w Q_n'(w).
+// So the block integral is h^2 f(s) P_d(w) with P_d(w) = sum_k 2/(2k+2)! d^{-2k} Q_{2k}(w),
+// truncated at k = kTaylorDeg/2 (p = 3/2 for G, p = 5/2 for alpha dG/dn).
+void taylor_poly(ld p, int d, ld out[hb::kTaylorN]) {
+  const int K = hb::kTaylorDeg / 2;
+  std::vector<std::vector<ld>> Q(2 * K + 1);
+  Q[0] = {1.0L};
+  for (int n = 0; n < 2 * K; ++n) {
+    const auto &q = Q[n];
+    std::vector<ld> r(q.size() + 1, 0.0L);
+    for (size_t j = 0; j < q.size(); ++j) {
+      r[j + 1] += q[j];
+      r[j] -= (n + p) * q[j];
+      r[j] -= (ld)j * q[j];
+    }
+    Q[n + 1] = r;
+  }
+  for (int j = 0; j < hb::kTaylorN; ++j) out[j] = 0;
+  ld fact = 2.0L, dpow = 1.0L;  // (2k+2)! starting at k = 0, d^{-2k}
+  for (int k = 0; k <= K; ++k) {
+    if (k > 0) fact *= (ld)(2 * k + 1) * (ld)(2 * k + 2);
+    ld coef = 2.0L / fact * dpow;
+    for (size_t j = 0; j < Q[2 * k].size(); ++j) out[j] += coef * Q[2 * k][j];
+    dpow /= (ld)d * (ld)d;
+  }
+}
+
+int upload(hb_ctx *c, void **dst, const void *src, size_t bytes) {
+  HB_HIP(c, hipMalloc(dst, bytes));
+  HB_HIP(c, hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return HB_OK;
+}
+
+int build_tables(hb_ctx *c) {
+  using namespace hb;
+  AsmParams &p = c->params;
+  p.ne = (int32_t)c->ne;
+  p.nv = (int32_t)c->nv;
+  p.nt = c->nt;
+  p.dsw = c->opt.d_switch;
+  p.alpha = c->alpha;
+  p.h = c->h;
+  ld al = c->alpha, h = c->h;
+  for (int i = 0; i <= kMaxClosed; ++i) {
+    ld delta = i * h;
+    ld sq = sqrtl(al * delta);
+    p.lv.c[i] = i == 0 ? 0.0 : (double)(1.0L / (2.0L * sq));
+    p.lv.s2[i] = (double)(2.0L * al * delta);
+    p.lv.s1[i] = (double)(2.0L * sq / sqrtl(kPi));
+    p.lv.t2[i] = (double)(4.0L * sq / sqrtl(kPi));
+  }
+  // small-z series: sqrt(pi) A(z) = 2/z + z sum a_n z^{2n},  a_n = (-1)^n 2/((n+1)!(2n+1)(2n+3))
+  //                 sqrt(pi) B(z) = 4 z sum b_n z^{2n},     b_n = (-1)^n /(n!(2n+1)(2n+3))
+  ld fact = 1.0L;  // n!
+  for (int n = 0; n < kSeriesN; ++n) {
+    if (n > 0) fact *= n;
+    ld sgn = (n % 2) ? -1.0L : 1.0L;
+    p.serA[n] = (double)(sgn * 2.0L / (fact * (n + 1) * (2 * n + 1) * (2 * n + 3)));
+    p.serB[n] = (double)(sgn / (fact * (2 * n + 1) * (2 * n + 3)));
+  }
+  // Radon's degree-5 rule: centroid, and the orbits of (a, a, 1-2a) for a = (6 -+ sqrt 15)/21
+  ld r15 = sqrtl(15.0L);
+  ld a1 = (6.0L - r15) / 21.0L, a2 = (6.0L + r15) / 21.0L;
+  ld bary[7][3] = {{1 / 3.0L, 1 / 3.0L, 1 / 3.0L},
+                   {1 - 2 * a1, a1, a1}, {a1, 1 - 2 * a1, a1}, {a1, a1, 1 - 2 * a1},
+                   {1 - 2 * a2, a2, a2}, {a2, 1 - 2 * a2, a2}, {a2, a2, 1 - 2 * a2}};
+  ld wts[7] = {0.225L, (155.0L - r15) / 1200.0L, (155.0L - r15) / 1200.0L,
+               (155.0L - r15) / 1200.0L, (155.0L + r15) / 1200.0L,
+               (155.0L + r15) / 1200.0L, (155.0L + r15) / 1200.0L};
+  for (int q = 0; q < 7; ++q) {
+    p.w7[q] = (double)wts[q];
+    for (int k = 0; k < 3; ++k) p.lam7[q][k] = (double)bary[q][k];
+  }
+  p.kV = (double)(1.0L / (8.0L * kPi * al * al));
+  p.kVs = (double)(h / (4.0L * kPi * al));
+  p.kK = (double)(1.0L / (8.0L * kPi * al));
+  p.kKs = (double)(h / (4.0L * kPi));
+
+  // Taylor tables for d >= dsw
+  std::vector<double> tay((size_t)c->nt * 2 * kTaylorN, 0.0), tsc((size_t)c->nt * 3, 0.0);
+  for (int d = std::max(1, p.dsw); d < c->nt; ++d) {
+    ld pv[kTaylorN], pk[kTaylorN];
+    taylor_poly(1.5L, d, pv);
+    taylor_poly(2.5L, d, pk);
+    for (int j = 0; j < kTaylorN; ++j) {
+      tay[((size_t)d * 2 + 0) * kTaylorN + j] = (double)pv[j];
+      tay[((size_t)d * 2 + 1) * kTaylorN + j] = (double)pk[j];
+    }
+    ld s = d * h;
+    tsc[3 * d + 0] = (double)(h * h * powl(4.0L * kPi * al * s, -1.5L));
+    tsc[3 * d + 1] = (double)(h * h / (16.0L * powl(kPi * al, 1.5L) * powl(s, 2.5L)));
+    tsc[3 * d + 2] = (double)(1.0L / (4.0L * al * s));
+  }
+  int rc;
+  if ((rc = upload(c, (void **)&c->d_taylor, tay.data(), tay.size() * sizeof(double)))) return rc;
+  if ((rc = upload(c, (void **)&c->d_tscale, tsc.data(), tsc.size() * sizeof(double)))) return rc;
+
+  // geometry SoA: far-rule nodes, normal, area
+  size_t ne = (size_t)c->ne;
+  std::vector<double> geom(25 * ne);
+  c->area.resize(ne);
+  c->normal.resize(3 * ne);
+  for (size_t t = 0; t < ne; ++t) {
+    const double *v[3] = {&c->verts[3 * c->tris[3 * t]], &c->verts[3 * c->tris[3 * t + 1]],
+                          &c->verts[3 * c->tris[3 * t + 2]]};
+    ld e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) { e1[k] = (ld)v[1][k] - v[0][k]; e2[k] = (ld)v[2][k] - v[0][k]; }
+    ld cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                e1[0] * e2[1] - e1[1] * e2[0]};
+    ld nn = sqrtl(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    c->area[t] = (double)(0.5L * nn);
+    for (int k = 0; k < 3; ++k) c->normal[3 * t + k] = (double)(cr[k] / nn);
+    for (int q = 0; q < 7; ++q)
+      for (int k = 0; k < 3; ++k)
+        geom[(q * 3 + k) * ne + t] =
+            (double)(bary[q][0] * v[0][k] + bary[q][1] * v[1][k] + bary[q][2] * v[2][k]);
+    for (int k = 0; k < 3; ++k) geom[(21 + k) * ne + t] = c->normal[3 * t + k];
+    geom[24 * ne + t] = c->area[t];
+  }
+  if ((rc = upload(c, (void **)&c->d_geom, geom.data(), geom.size() * sizeof(double)))) return rc;
+  if ((rc = upload(c, (void **)&c->d_tris, c->tris.data(), c->tris.size() * sizeof(int32_t)))) return rc;
+  std::vector<double> mass(3 * ne);
+  for (size_t t = 0; t < ne; ++t)
+    for (int k = 0; k < 3; ++k) mass[3 * t + k] = c->area[t] / 3.0;
+  if ((rc = upload(c, (void **)&c->d_mass, mass.data(), mass.size() * sizeof(double)))) return rc;
+
+  // touching pairs (class 3, 2, 1 contiguous), with normals and area factors
+  std::stable_sort(c->touch.begin(), c->touch.end(),
+                   [](const TouchPair &x, const TouchPair &y) { return x.cls > y.cls; });
+  for (auto &tp : c->touch) {
+    for (int k = 0; k < 3; ++k) tp.n[k] = c->normal[3 * tp.m + k];
+    tp.scale = 4.0 * c->area[tp.l] * c->area[tp.m];
+  }
+  if (!c->touch.empty())
+    if ((rc = upload(c, (void **)&c->d_touch, c->touch.data(), c->touch.size() * sizeof(TouchPair))))
+      return rc;
+  // regularised rules
+  for (int cls = 1; cls <= 3; ++cls) {
+    std::vector<SSNode> nodes;
+    ss_nodes(cls, c->opt.ss_order, nodes);
+    int n = (int)nodes.size(), np = (n + 63) / 64 * 64;
+    std::vector<double> tab(8 * (size_t)np, 0.0);
+    for (int i = 0; i < np; ++i) {
+      bool real = i < n;
+      for (int k = 0; k < 4; ++k) tab[(size_t)k * np + i] = real ? (double)nodes[i].c[k] : (k == 0 ? 1.0 : 0.0);
+      tab[(size_t)4 * np + i] = real ? (double)nodes[i].w : 0.0;
+      for (int k = 0; k < 3; ++k) tab[(size_t)(5 + k) * np + i] = real ? (double)nodes[i].lam[k] : 0.0;
+    }
+    c->ss[cls].n = np;
+    if ((rc = upload(c, (void **)&c->ss[cls].d, tab.data(), tab.size() * sizeof(double)))) return rc;
+  }
+  p.taylor = c->d_taylor;
+  p.tscale = c->d_tscale;
+  p.geom = c->d_geom;
+  p.tris = c->d_tris;
+  return HB_OK;
+}
+
+}  // namespace
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+void hb_default_options(hb_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->ss_order = 4;
+  o->d_switch = 8;
+  o->storage = HB_DTYPE_F64;
+  o->mixed_d_min = 2;
+}
+
+int hb_check_mesh(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                  int64_t class_counts[4]) {
+  int rc = validate_mesh(nullptr, verts, n_verts, tris, n_tris);
+  if (rc) return rc;
+  if (class_counts) count_classes(tris, n_verts, n_tris, class_counts, nullptr, nullptr);
+  return HB_OK;
+}
+
+const char *hb_last_error(const hb_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t *tris,
+              int64_t n_tris, double alpha, double T, int32_t n_t, const hb_options *opt) {
+  if (!out) return fail(nullptr, HB_EINVAL, "out is null");
+  *out = nullptr;
+  if (!(alpha > 0) || !std::isfinite(alpha)) return fail(nullptr, HB_EINVAL, "alpha must be > 0");
+  if (!(T > 0) || !std::isfinite(T)) return fail(nullptr, HB_EINVAL, "T must be > 0");
+  if (n_t < 1 || n_t > 65536) return fail(nullptr, HB_EINVAL, "n_t must be in 1..65536");
+  hb_options o;
+  hb_default_options(&o);
+  if (opt) o = *opt;
+  if (o.ss_order < 1 || o.ss_order > 8) return fail(nullptr, HB_EINVAL, "ss_order must be in 1..8");
+  if (o.d_switch != 8 && o.d_switch != 16)
+    return fail(nullptr, HB_EINVAL, "d_switch must be 8 or 16");
+  if (o.storage != HB_DTYPE_F64 && o.storage != HB_DTYPE_F32)
+    return fail(nullptr, HB_EINVAL, "storage must be HB_DTYPE_F64 or HB_DTYPE_F32");
+  if (o.mixed_d_min < 2) return fail(nullptr, HB_EINVAL, "mixed_d_min must be >= 2");
+  for (int i = 0; i < 12; ++i)
+    if (o.reserved[i]) return fail(nullptr, HB_EINVAL, "reserved options must be zero");
+  int rc = validate_mesh(nullptr, verts, n_verts, tris, n_tris);
+  if (rc) return rc;
+  hb_ctx *c = new hb_ctx();
+  c->ne = n_tris;
+  c->nv = n_verts;
+  c->nt = n_t;
+  c->alpha = alpha;
+  c->T = T;
+  c->h = T / n_t;
+  c->opt = o;
+  c->storage_f32 = o.storage == HB_DTYPE_F32;
+  c->verts.assign(verts, verts + 3 * n_verts);
+  c->tris.assign(tris, tris + 3 * n_tris);
+  count_classes(tris, n_verts, n_tris, c->n_class, &c->touch, verts);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(nullptr, HB_EHIP, "no HIP device");
+  }
+  rc = build_tables(c);
+  if (rc) {
+    g_err = c->err;
+    hb_destroy(c);
+    return rc;
+  }
+  for (int i = 0; i < 4; ++i)
+    if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+      hb_destroy(c);
+      return fail(nullptr, HB_EHIP, "hipEventCreate failed");
+    }
+  *out = c;
+  return HB_OK;
+}
+
+void hb_destroy(hb_ctx *c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  void *ptrs[] = {c->d_params, c->d_geom, c->d_tris, c->d_touch, c->d_taylor, c->d_tscale, c->d_mass,
+                  c->d_V, c->d_K, c->d_work, c->d_v0inv, c->ss[1].d, c->ss[2].d, c->ss[3].d};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  for (int i = 0; i < 4; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  delete c;
+}
+
+int hb_sizes(const hb_ctx *c, int64_t *ne, int64_t *nv, int32_t *nt, int64_t *ntouch) {
+  if (!c) return fail(nullptr, HB_EINVAL, "null context");
+  if (ne) *ne = c->ne;
+  if (nv) *nv = c->nv;
+  if (nt) *nt = c->nt;
+  if (ntouch) *ntouch = (int64_t)c->touch.size();
+  return HB_OK;
+}
+
+int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
+  if (!c) return fail(nullptr, HB_EINVAL, "null context");
+  if (ops == 0 || (ops & ~(HB_OP_V | HB_OP_K))) return fail(c, HB_EINVAL, "ops must be a non-empty subset of HB_OP_V | HB_OP_K");
+  if (precision != HB_PREC_FP64 && precision != HB_PREC_MIXED) return fail(c, HB_EINVAL, "unknown precision");
+  hipStream_t s = (hipStream_t)stream;
+  size_t esz = c->storage_f32 ? 4 : 8;
+  size_t nV = (size_t)c->nt * c->ne * c->ne, nK = (size_t)c->nt * c->ne * c->nv;
+  if ((ops & HB_OP_V) && !c->d_V) HB_HIP(c, hipMalloc(&c->d_V, nV * esz));
+  if ((ops & HB_OP_K) && !c->d_K) HB_HIP(c, hipMalloc(&c->d_K, nK * esz));
+  hb::AsmParams &p = c->launch;
+  p = c->params;
+  p.V = c->d_V;
+  p.K = c->d_K;
+  p.do_V = (ops & HB_OP_V) ? 1 : 0;
+  p.do_K = (ops & HB_OP_K) ? 1 : 0;
+  p.mixed_d_min = precision == HB_PREC_MIXED ? c->opt.mixed_d_min : c->nt;
+  if (!c->d_params) HB_HIP(c, hipMalloc(&c->d_params, sizeof(hb::AsmParams)));
+  HB_HIP(c, hipMemcpyAsync(c->d_params, &p, sizeof(p), hipMemcpyHostToDevice, s));
+  // K is accumulated over the (up to three) panels of each trial vertex: clear it first
+  if (p.do_K) HB_HIP(c, hipMemsetAsync(c->d_K, 0, nK * esz, s));
+  HB_HIP(c, hipEventRecord(c->ev[0], s));
+  hb::launch_assemble_separated(c->d_params, p, precision, c->storage_f32, s);
+  HB_HIP(c, hipGetLastError());
+  HB_HIP(c, hipEventRecord(c->ev[1], s));
+  int64_t off = 0;
+  for (int cls = 3; cls >= 1; --cls) {
+    int64_t n = c->n_class[cls];
+    if (n > 0)
+      hb::launch_assemble_touching(c->d_params, p, c->d_touch + off, n, c->ss[cls], c->storage_f32, s);
+    off += n;
+  }
+  HB_HIP(c, hipGetLastError());
+  HB_HIP(c, hipEventRecord(c->ev[2], s));
+  if (p.do_V) c->have_V = true;
+  if (p.do_K) c->have_K = true;
+  c->timed = true;
+  return HB_OK;
+}
+
+int hb_last_assembly_ms(hb_ctx *c, double ms[3]) {
+  if (!c || !ms) return fail(c, HB_EINVAL, "null argument");
+  if (!c->timed) return fail(c, HB_ESTATE, "no assembly has run");
+  HB_HIP(c, hipEventSynchronize(c->ev[2]));
+  float a = 0, b = 0, t = 0;
+  HB_HIP(c, hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
+  HB_HIP(c, hipEventElapsedTime(&b, c->ev[1], c->ev[2]));
+  HB_HIP(c, hipEventElapsedTime(&t, c->ev[0], c->ev[2]));
+  ms[0] = a;
+  ms[1] = b;
+  ms[2] = t;
+  return HB_OK;
+}
+
+int hb_get_blocks(hb_ctx *c, uint32_t op, int32_t d0, int32_t nd, void *dst, int32_t dtype,
+                  int32_t dst_on_device, void *stream) {
+  if (!c || !dst) return fail(c, HB_EINVAL, "null argument");
+  if (op != HB_OP_V && op != HB_OP_K) return fail(c, HB_EINVAL, "op must be HB_OP_V or HB_OP_K");
+  if (d0 < 0 || nd < 0 || d0 + nd > c->nt) return fail(c, HB_EINVAL, "block range out of bounds");
+  if (dtype != HB_DTYPE_F64 && dtype != HB_DTYPE_F32) return fail(c, HB_EINVAL, "bad dtype");
+  bool have = op == HB_OP_V ? c->have_V : c->have_K;
+  if (!have) return fail(c, HB_ESTATE, "operator not assembled");
+  size_t cols = op == HB_OP_V ? (size_t)c->ne : (size_t)c->nv;
+  size_t per = (size_t)c->ne * cols, n = per * nd;
+  size_t esz = c->storage_f32 ? 4 : 8;
+  const char *src = (const char *)(op == HB_OP_V ? c->d_V : c->d_K) + (size_t)d0 * per * esz;
+  hipStream_t s = (hipStream_t)stream;
+  bool same = (dtype == HB_DTYPE_F32) == (c->storage_f32 != 0);
+  if (same) {
+    HB_HIP(c, hipMemcpyAsync(dst, src, n * esz, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (!dst_on_device) HB_HIP(c, hipStreamSynchronize(s));
+    return HB_OK;
+  }
+  // conversion on the host
+  std::vector<char> tmp(n * esz);
+  HB_HIP(c, hipMemcpyAsync(tmp.data(), src, n * esz, hipMemcpyDeviceToHost, s));
+  HB_HIP(c, hipStreamSynchronize(s));
+  size_t osz = dtype == HB_DTYPE_F32 ? 4 : 8;
+  std::vector<char> conv(n * osz);
+  for (size_t i = 0; i < n; ++i) {
+    if (dtype == HB_DTYPE_F32) ((float *)conv.data())[i] = (float)((const double *)tmp.data())[i];
+    else ((double *)conv.data())[i] = (double)((const float *)tmp.data())[i];
+  }
+  if (dst_on_device) {
+    HB_HIP(c, hipMemcpyAsync(dst, conv.data(), n * osz, hipMemcpyHostToDevice, s));
+    HB_HIP(c, hipStreamSynchronize(s));
+  } else {
+    std::memcpy(dst, conv.data(), n * osz);
+  }
+  return HB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Internal declarations shared by the host runtime (hb_host.cpp) and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/heatbem.h"
+
+namespace hb {
+
+// Closed-form levels handled in registers: blocks 0 .. kClosedBlocks-1 come from second
+// differences of G^{dtau dt} at levels 0 .. kClosedBlocks; later blocks use the Taylor form.
+constexpr int kTaylorDeg = 16;       // degree of the Taylor polynomial in w = rho^2/(4 alpha d h)
+constexpr int kTaylorN = kTaylorDeg + 1;
+constexpr int kSeriesN = 14;         // terms of the small-z series of the brackets A(z), B(z)
+constexpr int kMaxClosed = 16;       // largest supported d_switch
+constexpr int kFarN = 7;             // Radon 7-point rule
+
+// Per-level constants of the closed form at delta_i = i h (i = 0 .. d_switch).
+struct LevelConsts {
+  double c[kMaxClosed + 1];   // 1 / (2 sqrt(alpha delta_i))   (z = rho * c)
+  double s2[kMaxClosed + 1];  // 2 alpha delta_i
+  double s1[kMaxClosed + 1];  // 2 sqrt(alpha delta_i) / sqrt(pi)
+  double t2[kMaxClosed + 1];  // 4 sqrt(alpha delta_i) / sqrt(pi)  (rho A(z) as rho -> 0)
+};
+
+struct AsmParams {
+  int32_t ne, nv, nt, dsw;     // E_x, N_x, E_t, first Taylor block
+  int32_t mixed_d_min;         // first d of float separated pairs (>= nt: none)
+  double alpha, h;
+  LevelConsts lv;
+  double serA[kSeriesN];       // z * sum serA[n] z^{2n}  : part of sqrt(pi) A(z) - 2/z
+  double serB[kSeriesN];       // z * sum serB[n] z^{2n}  : sqrt(pi)/4 B(z)
+  double w7[kFarN];            // Radon weights (sum 1)
+  double lam7[kFarN][3];       // Radon barycentric nodes
+  // scale factors applied to the raw sums (see the kernels)
+  double kV;                   // 1 / (8 pi alpha^2)
+  double kVs;                  // h / (4 pi alpha)
+  double kK;                   // 1 / (8 pi alpha)
+  double kKs;                  // h / (4 pi)
+  const double *taylor;        // [nt][2][kTaylorN] Taylor polynomials in w (V, K), d >= dsw
+  const double *tscale;        // [nt][3]: V scale, K scale, c_d = 1/(4 alpha d h)
+  const double *geom;          // SoA [25][ne]: far nodes (q*3+c), normal (21..23), area (24)
+  const int32_t *tris;         // [ne][3]
+  void *V;                     // [nt][ne][ne]
+  void *K;                     // [nt][ne][nv]
+  int32_t do_V, do_K;
+};
+
+// One ordered touching pair (test l, trial m) with the vertex orders of the regularised rule.
+struct TouchPair {
+  int32_t l, m, cls, pad0;
+  int32_t vtx[3], pad1;        // trial vertices in the rule's order (p1 basis lambda_k)
+  double E1[3], E2[3];         // test panel edges  v1-v0, v2-v1 (rule order)
+  double F1[3], F2[3];         // trial panel edges
+  double n[3];                 // trial outward unit normal
+  double scale;                // 4 * area_l * area_m
+};
+
+// Regularised rule of one class, SoA, padded to a multiple of 64 with zero weights.
+struct SSRule {
+  int32_t n = 0;               // padded count
+  double *d = nullptr;         // device: [8][n] = c1, c2, c3, c4, w, lam0, lam1, lam2
+};
+
+// dp: device copy of p (kernels read their parameters from device memory)
+void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, int precision,
+                               int storage_f32, hipStream_t s);
+void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,
+                              int64_t npairs, const SSRule &rule, int storage_f32, hipStream_t s);
+
+// Toeplitz apply (y = A x, time-major), solver and potential kernels
+int apply_toeplitz(const void *blocks, int storage_f32, int nt, int rows, int cols,
+                   const double *x, double *y, hipStream_t s);
+
+}  // namespace hb
+
+struct hb_ctx {
+  std::string err;
+  int64_t ne = 0, nv = 0;
+  int32_t nt = 0;
+  double alpha = 0, T = 0, h = 0;
+  hb_options opt{};
+  std::vector<double> verts;
+  std::vector<int32_t> tris;
+  std::vector<double> area, normal;
+  std::vector<hb::TouchPair> touch;  // sorted by class 3, 2, 1
+  int64_t n_class[4] = {0, 0, 0, 0};
+  int device = 0;
+  // device data
+  double *d_geom = nullptr;
+  int32_t *d_tris = nullptr;
+  hb::TouchPair *d_touch = nullptr;
+  hb::SSRule ss[4];
+  double *d_taylor = nullptr, *d_tscale = nullptr;
+  double *d_mass = nullptr;          // p0 x p1 mass, [ne][3] = area/3 per local vertex
+  void *d_V = nullptr, *d_K = nullptr;
+  bool have_V = false, have_K = false;
+  int storage_f32 = 0;
+  hb::AsmParams params{};            // tables filled at creation
+  hb::AsmParams launch{};            // per-call copy (outputs, ops), source of d_params
+  hb::AsmParams *d_params = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool timed = false;
+  // solver workspace
+  double *d_work = nullptr;
+  size_t work_bytes = 0;
+  double *d_v0inv = nullptr;         // inverse of V^0 (time marching)
+};
