@@ -119,15 +119,18 @@ def rhs_dirichlet(K, Mx, g, h):
 
 
 def time_march(V, b):
-    """Solve V_h w = b by block forward substitution (Cholesky of V^0)."""
+    """Solve V_h w = b by block forward substitution with an LU factorisation of V^0.
+    (V_h^0 is symmetric positive definite in exact arithmetic, but the assembled block is
+    symmetric only up to the regularised rules' error, so a Cholesky factor, which reads one
+    triangle, would solve a different matrix.)"""
     n_t = V.shape[0]
-    c = scipy.linalg.cho_factor(V[0], lower=True)
+    lu = scipy.linalg.lu_factor(V[0])
     w = np.zeros_like(b)
     for k in range(n_t):
         r = b[k].copy()
         for d in range(1, k + 1):
             r -= V[d] @ w[k - d]
-        w[k] = scipy.linalg.cho_solve(c, r)
+        w[k] = scipy.linalg.lu_solve(lu, r)
     return w
 
 
