@@ -46,19 +46,6 @@ static const ld PI_L = 3.141592653589793238462643383279502884L;
 /* Heat kernel and temporal antiderivatives (Sec. 2, Sec. 3.1, Sec. 3.2, formula summary).     */
 /* ------------------------------------------------------------------------------------------ */
 
-/* G_alpha(r, s) for s > 0 (Sec. 2). */
-static ld heat_G(ld rho, ld s, ld alpha) {
-  if (s <= 0.0L) return 0.0L;
-  return powl(4.0L * PI_L * alpha * s, -1.5L) * expl(-rho * rho / (4.0L * alpha * s));
-}
-
-/* alpha dG/dn_y divided by (r . n_y) (Sec. 2). */
-static ld heat_Gn_rn(ld rho, ld s, ld alpha) {
-  if (s <= 0.0L) return 0.0L;
-  return expl(-rho * rho / (4.0L * alpha * s)) /
-         (16.0L * powl(PI_L * alpha, 1.5L) * powl(s, 2.5L));
-}
-
 /* G^{dtau}_alpha(r, delta) = erf(z) / (4 pi alpha rho), z = rho / (2 sqrt(alpha delta));
  * limit delta -> 0+: 1/(4 pi alpha rho); limit rho -> 0+: 1/(4 pi^{3/2} alpha^{3/2} sqrt(delta)). */
 ld or_g1(ld rho, ld delta, ld alpha) {
@@ -158,9 +145,10 @@ static void gauss_legendre01(int n, ld *x, ld *w) {
   }
 }
 
-/* Hat-weighted time integral: h^2 int_{-1}^{1} (1-|u|) f((d+u) h) du, f = G or Gn/(r.n). */
+/* Hat-weighted time integrals h^2 int_{-1}^{1} (1-|u|) f((d+u) h) du for f = G_alpha (out[0]) and
+ * f = alpha dG/dn_y / (r . n_y) (out[1]); both share exp(-rho^2/(4 alpha s)). */
 #define HAT_NT 12
-static ld hat_integral(ld rho, int d, ld h, ld alpha, int which) {
+static void hat_integrals(ld rho, int d, ld h, ld alpha, ld out[2]) {
   static ld gx[HAT_NT], gw[HAT_NT];
   static int ready = 0;
   if (!ready) {
@@ -173,15 +161,28 @@ static ld hat_integral(ld rho, int d, ld h, ld alpha, int which) {
       }
     }
   }
-  ld sum = 0.0L;
+  const ld cG = 1.0L / ((4.0L * PI_L * alpha) * sqrtl(4.0L * PI_L * alpha)); /* (4 pi alpha)^{-3/2} */
+  const ld cK = 1.0L / (16.0L * PI_L * alpha * sqrtl(PI_L * alpha));        /* 1/(16 (pi alpha)^{3/2}) */
+  ld sV = 0.0L, sK = 0.0L;
   for (int i = 0; i < HAT_NT; ++i) {
     /* u in [0,1]: weight (1-u); u in [-1,0]: u = -v, weight (1-v) */
     ld u = gx[i], wt = gw[i] * (1.0L - u);
-    ld s1 = ((ld)d + u) * h, s2 = ((ld)d - u) * h;
-    if (which == 0) sum += wt * (heat_G(rho, s1, alpha) + heat_G(rho, s2, alpha));
-    else sum += wt * (heat_Gn_rn(rho, s1, alpha) + heat_Gn_rn(rho, s2, alpha));
+    for (int sg = -1; sg <= 1; sg += 2) {
+      ld s = ((ld)d + sg * u) * h;
+      ld e = expl(-rho * rho / (4.0L * alpha * s));
+      ld is32 = 1.0L / (s * sqrtl(s));
+      sV += wt * cG * is32 * e;
+      sK += wt * cK * is32 / s * e;
+    }
   }
-  return h * h * sum;
+  out[0] = h * h * sV;
+  out[1] = h * h * sK;
+}
+
+static ld hat_integral(ld rho, int d, ld h, ld alpha, int which) {
+  ld o[2];
+  hat_integrals(rho, d, h, alpha, o);
+  return o[which];
 }
 
 /* Temporal integral modes: 0 = closed form for d <= 16, hat quadrature above; 1 = closed form
@@ -516,8 +517,10 @@ static void assemble_row_direct(const double *verts, const int32_t *tris, int nv
       for (int d = 0; d < nt; ++d) {
         ld v, kr;
         if (use_hat(d, tmode)) {
-          v = hat_integral(rho, d, h, alpha, 0);
-          kr = hat_integral(rho, d, h, alpha, 1);
+          ld o[2];
+          hat_integrals(rho, d, h, alpha, o);
+          v = o[0];
+          kr = o[1];
         } else if (d == 0) { /* eq. for V^0 and K^0 */
           v = h * or_g1(rho, 0.0L, alpha) - fl[2] + fl[0];
           kr = h * or_g1n_rn(rho, 0.0L, alpha) - fl[3] + fl[1];

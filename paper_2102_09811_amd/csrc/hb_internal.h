@@ -8,6 +8,8 @@
 
 #include "../../include/heatbem.h"
 
+struct hb_ctx;
+
 namespace hb {
 
 // Closed-form levels handled in registers: blocks 0 .. kClosedBlocks-1 come from second
@@ -71,9 +73,9 @@ void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, int prec
 void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,
                               int64_t npairs, const SSRule &rule, int storage_f32, hipStream_t s);
 
-// Toeplitz apply (y = A x, time-major), solver and potential kernels
-int apply_toeplitz(const void *blocks, int storage_f32, int nt, int rows, int cols,
-                   const double *x, double *y, hipStream_t s);
+// y = A x for the block-Toeplitz operator with blocks [nt][R][C] (y overwritten, time-major)
+int toeplitz_apply(hb_ctx *c, const void *blocks, int R, int C, const double *x, double *y,
+                   hipStream_t s);
 
 }  // namespace hb
 
@@ -102,6 +104,7 @@ struct hb_ctx {
   hb::AsmParams params{};            // tables filled at creation
   hb::AsmParams launch{};            // per-call copy (outputs, ops), source of d_params
   hb::AsmParams *d_params = nullptr;
+  hb::AsmParams *d_params_repr = nullptr;  // parameter copy read by the potential kernel
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool timed = false;
   // solver workspace

@@ -1,0 +1,595 @@
+// Operations on assembled blocks: block-Toeplitz apply (Sec. 3.1 eq. for V_h w, Sec. 3.2 eq. for
+// K_h), the Dirichlet right-hand side (Sec. 3.4), solvers for V_h w = b, and the representation
+// formula (potentials of Sec. 3.5).  All vectors are time-major: entry [k * n + j].
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hb_internal.h"
+
+namespace hb {
+namespace {
+
+#define HB_CHECK(ctx, call)                                                               \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);                     \
+      return e_ == hipErrorOutOfMemory ? HB_ENOMEM : HB_EHIP;                             \
+    }                                                                                     \
+  } while (0)
+
+// ------------------------------------------------------------------------------------------
+// Block-Toeplitz product Y[k][r] += sum_d sum_c A^d[r][c] X[k-d][c] (only d <= k).
+// Workgroup tile: 64 rows x 64 time steps, 4 x 4 outputs per thread, the reduction over
+// (d, c) staged through LDS 16 columns at a time; blockIdx.z splits the d range and partial
+// tiles are combined with atomics (Y must be zero on entry).
+// ------------------------------------------------------------------------------------------
+constexpr int TR = 64, TKK = 64, TC = 16;
+
+template <typename TA>
+__global__ __launch_bounds__(256) void k_toeplitz(const TA *__restrict__ A,
+                                                  const double *__restrict__ X,
+                                                  double *__restrict__ Y, int nt, int R, int C,
+                                                  int dper) {
+  const int r0 = blockIdx.x * TR, k0 = blockIdx.y * TKK;
+  const int dbeg = blockIdx.z * dper;
+  const int dend = min(min(dbeg + dper, nt), k0 + TKK);
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  __shared__ double As[TC][TR + 2];
+  __shared__ double Xs[TC][TKK + 2];
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int d = dbeg; d < dend; ++d) {
+    const TA *Ad = A + (size_t)d * R * C;
+    for (int c0 = 0; c0 < C; c0 += TC) {
+#pragma unroll
+      for (int e = tid; e < TR * TC; e += 256) {
+        const int rr = e / TC, cc = e % TC;
+        const int r = r0 + rr, c = c0 + cc;
+        As[cc][rr] = (r < R && c < C) ? (double)Ad[(size_t)r * C + c] : 0.0;
+      }
+#pragma unroll
+      for (int e = tid; e < TC * TKK; e += 256) {
+        const int kk = e / TC, cc = e % TC;
+        const int k = k0 + kk, c = c0 + cc, j = k - d;
+        Xs[cc][kk] = (k < nt && j >= 0 && c < C) ? X[(size_t)j * C + c] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int cc = 0; cc < TC; ++cc) {
+        double a[4], x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = As[cc][ty * 4 + i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = Xs[cc][tx * 4 + j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], x[j], acc[i][j]);
+      }
+      __syncthreads();
+    }
+  }
+  if (dbeg >= dend) return;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = k0 + tx * 4 + j;
+    if (k >= nt) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = r0 + ty * 4 + i;
+      if (r < R) atomicAdd(&Y[(size_t)k * R + r], acc[i][j]);
+    }
+  }
+}
+
+__global__ void k_fill(double *__restrict__ y, size_t n, double v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+
+// y_{row} = sum_c A[row][c] x[c], one wave per row; batched over nd matrices A + d * stride
+// writing out[(k_out0 + d) * R + row] = beta * out + alpha * y.
+template <typename TA>
+__global__ __launch_bounds__(256) void k_gemv_rows(const TA *__restrict__ A, size_t stride,
+                                                   const double *__restrict__ x, double *out,
+                                                   int R, int C, double alpha, double beta,
+                                                   size_t out_stride) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int d = blockIdx.y;
+  if (row >= R) return;
+  const TA *a = A + (size_t)d * stride + (size_t)row * C;
+  double s = 0.0;
+  for (int c = lane; c < C; c += 64) s = fma((double)a[c], x[c], s);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) {
+    double *o = out + (size_t)d * out_stride + row;
+    *o = beta * (*o) + alpha * s;
+  }
+}
+
+// b[k][l] += (h/2) sum_{j in panel l} (area_l / 3) g[k][j]   (the 1/2 M_h g part)
+__global__ void k_mass_half(const double *__restrict__ mass, const int32_t *__restrict__ tris,
+                            const double *__restrict__ g, double *__restrict__ b, int nt, int ne,
+                            int nv, double half_h) {
+  const size_t n = (size_t)nt * ne;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i / ne), l = (int)(i % ne);
+    const double *gk = g + (size_t)k * nv;
+    b[i] += half_h * (mass[3 * l] * gk[tris[3 * l]] + mass[3 * l + 1] * gk[tris[3 * l + 1]] +
+                      mass[3 * l + 2] * gk[tris[3 * l + 2]]);
+  }
+}
+
+// ---- Gauss-Jordan inversion of the SPD block V^0 (no pivoting), in place ----
+__global__ void k_gj_save(const double *__restrict__ A, int n, int p, double *rowp, double *colp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    rowp[i] = A[(size_t)p * n + i];
+    colp[i] = A[(size_t)i * n + p];
+  }
+}
+
+__global__ void k_gj_update(double *__restrict__ A, int n, int p, const double *__restrict__ rowp,
+                            const double *__restrict__ colp) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= n) return;
+  const double inv = 1.0 / rowp[p];
+  double v;
+  if (i == p) v = (j == p) ? inv : rowp[j] * inv;
+  else v = (j == p) ? -colp[i] * inv : A[(size_t)i * n + j] - colp[i] * rowp[j] * inv;
+  A[(size_t)i * n + j] = v;
+}
+
+// ---- vector kernels for GMRES ----
+constexpr int kDotChunk = 4096;
+
+// partial[v * nchunk + c] = sum over chunk c of Q[v][i] * w[i]
+__global__ __launch_bounds__(256) void k_multi_dot(const double *__restrict__ Q, size_t ldq,
+                                                   const double *__restrict__ w, size_t n,
+                                                   double *__restrict__ partial, int nchunk) {
+  const int c = blockIdx.x, v = blockIdx.y;
+  const double *q = Q + (size_t)v * ldq;
+  const size_t i0 = (size_t)c * kDotChunk, i1 = min(n, i0 + kDotChunk);
+  double s = 0.0;
+  for (size_t i = i0 + threadIdx.x; i < i1; i += 256) s = fma(q[i], w[i], s);
+  __shared__ double red[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[(size_t)v * nchunk + c] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_sum_partials(const double *__restrict__ partial, int nvec, int nchunk,
+                               double *__restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvec) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += partial[(size_t)v * nchunk + c];
+  out[v] = s;
+}
+
+// w[i] -= sum_v coef[v] Q[v][i]
+__global__ void k_sub_multi(const double *__restrict__ Q, size_t ldq, const double *__restrict__ coef,
+                            int nvec, double *__restrict__ w, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int v = 0; v < nvec; ++v) s = fma(coef[v], Q[(size_t)v * ldq + i], s);
+    w[i] -= s;
+  }
+}
+
+// y[i] = sum_v coef[v] Q[v][i]
+__global__ void k_combine(const double *__restrict__ Q, size_t ldq, const double *__restrict__ coef,
+                          int nvec, double *__restrict__ y, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int v = 0; v < nvec; ++v) s = fma(coef[v], Q[(size_t)v * ldq + i], s);
+    y[i] = s;
+  }
+}
+
+__global__ void k_scale_copy(const double *__restrict__ x, double a, double *__restrict__ y, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+
+__global__ void k_axpby(double a, const double *__restrict__ x, double b, double *__restrict__ y, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+
+inline int grid1d(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 8192); }
+
+// ------------------------------------------------------------------------------------------
+// Representation formula u(x, t_k + eps) = V~ w - W g (Sec. 3.5), one workgroup per point.
+// With s_m = m h + eps and z_m = rho / (2 sqrt(alpha s_m)), the time integral of G over the
+// interval whose distances are (s_{m-1}, s_m) is [erfc z_m - erfc z_{m-1}] / (4 pi alpha rho),
+// and that of alpha dG/dn_y is rn [D(z_m) - D(z_{m-1})] / (4 pi rho^3) with
+// D(z) = erfc z + 2 z e^{-z^2} / sqrt(pi)  (the current, partial interval has s_{-1} = 0, D = 0).
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_repr(const AsmParams *__restrict__ pp,
+                                              const double *__restrict__ pts,
+                                              const double *__restrict__ w,
+                                              const double *__restrict__ g,
+                                              double *__restrict__ u, double *__restrict__ sl,
+                                              double *__restrict__ dl) {
+  const AsmParams &p = *pp;
+  const int pid = blockIdx.x;
+  const double px = pts[4 * pid], py = pts[4 * pid + 1], pz = pts[4 * pid + 2], t = pts[4 * pid + 3];
+  const int ne = p.ne, nv = p.nv, nt = p.nt;
+  int k = (int)floor(t / p.h);
+  k = max(0, min(k, nt));
+  double eps = t - k * p.h;
+  if (eps < 0.0) eps = 0.0;
+  const double c_al = 1.0 / (2.0 * sqrt(p.alpha));
+  constexpr double kTwoInvSqrtPi = 1.1283791670955125739;
+  double accs = 0.0, accd = 0.0;
+  for (int j = threadIdx.x; j < ne; j += 256) {
+    const double area = p.geom[24 * ne + j];
+    const double n0 = p.geom[21 * ne + j], n1 = p.geom[22 * ne + j], n2 = p.geom[23 * ne + j];
+    const int v0 = p.tris[3 * j], v1 = p.tris[3 * j + 1], v2 = p.tris[3 * j + 2];
+    for (int q = 0; q < kFarN; ++q) {
+      const double rx = px - p.geom[(q * 3 + 0) * ne + j];
+      const double ry = py - p.geom[(q * 3 + 1) * ne + j];
+      const double rz = pz - p.geom[(q * 3 + 2) * ne + j];
+      const double rho = sqrt(fma(rx, rx, fma(ry, ry, rz * rz)));
+      const double rn = fma(rx, n0, fma(ry, n1, rz * n2));
+      const double l0 = p.lam7[q][0], l1 = p.lam7[q][1], l2 = p.lam7[q][2];
+      double sv = 0.0, sd = 0.0;
+      // m = 0: the current interval (if any) and the upper end of interval k
+      double ec_prev, D_prev;
+      {
+        if (eps > 0.0) {
+          const double z = rho * c_al / sqrt(eps);
+          const double e = exp(-z * z);
+          ec_prev = erfc(z);
+          D_prev = ec_prev + kTwoInvSqrtPi * z * e;
+          if (k < nt) {
+            sv += w[(size_t)k * ne + j] * ec_prev;
+            const double *gk = g + (size_t)k * nv;
+            sd += (l0 * gk[v0] + l1 * gk[v1] + l2 * gk[v2]) * D_prev;
+          }
+        } else {
+          ec_prev = 0.0;
+          D_prev = 0.0;
+        }
+      }
+      for (int m = 1; m <= k; ++m) {
+        const double z = rho * c_al / sqrt(m * p.h + eps);
+        const double e = exp(-z * z);
+        const double ec = erfc(z);
+        const double D = ec + kTwoInvSqrtPi * z * e;
+        const int i = k - m;  // 0-based interval index
+        sv += w[(size_t)i * ne + j] * (ec - ec_prev);
+        const double *gi = g + (size_t)i * nv;
+        sd += (l0 * gi[v0] + l1 * gi[v1] + l2 * gi[v2]) * (D - D_prev);
+        ec_prev = ec;
+        D_prev = D;
+      }
+      const double Wq = p.w7[q] * area;
+      accs = fma(Wq / rho, sv, accs);
+      accd = fma(Wq * rn / (rho * rho * rho), sd, accd);
+    }
+  }
+  __shared__ double red[2][4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    accs += __shfl_xor(accs, o, 64);
+    accd += __shfl_xor(accd, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = accs;
+    red[1][threadIdx.x >> 6] = accd;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    constexpr double kInv4Pi = 0.079577471545947667884;
+    const double s = (red[0][0] + red[0][1] + red[0][2] + red[0][3]) * kInv4Pi / p.alpha;
+    const double d = (red[1][0] + red[1][1] + red[1][2] + red[1][3]) * kInv4Pi;
+    u[pid] = s - d;
+    if (sl) sl[pid] = s;
+    if (dl) dl[pid] = d;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// host helpers
+// ------------------------------------------------------------------------------------------
+int ensure_work(hb_ctx *c, size_t bytes) {
+  if (c->work_bytes >= bytes) return HB_OK;
+  if (c->d_work) (void)hipFree(c->d_work);
+  c->d_work = nullptr;
+  c->work_bytes = 0;
+  HB_CHECK(c, hipMalloc(&c->d_work, bytes));
+  c->work_bytes = bytes;
+  return HB_OK;
+}
+
+}  // namespace
+
+// y = A x (Toeplitz), y overwritten
+int toeplitz_apply(hb_ctx *c, const void *blocks, int R, int C, const double *x, double *y,
+                   hipStream_t s) {
+  const int nt = c->nt;
+  const size_t ny = (size_t)nt * R;
+  hipLaunchKernelGGL(k_fill, dim3(grid1d(ny)), dim3(256), 0, s, y, ny, 0.0);
+  const int gx = (R + TR - 1) / TR, gy = (nt + TKK - 1) / TKK;
+  // enough workgroups to fill the chip: split d into groups of dper
+  int groups = std::max(1, std::min(nt, 2048 / std::max(1, gx * gy)));
+  const int dper = (nt + groups - 1) / groups;
+  groups = (nt + dper - 1) / dper;
+  if (c->storage_f32)
+    hipLaunchKernelGGL(k_toeplitz<float>, dim3(gx, gy, groups), dim3(256), 0, s,
+                       (const float *)blocks, x, y, nt, R, C, dper);
+  else
+    hipLaunchKernelGGL(k_toeplitz<double>, dim3(gx, gy, groups), dim3(256), 0, s,
+                       (const double *)blocks, x, y, nt, R, C, dper);
+  HB_CHECK(c, hipGetLastError());
+  return HB_OK;
+}
+
+namespace {
+
+// out[(k0 + d) * R + row] = beta * out + alpha * (A^{d_first + d} x), d = 0 .. nd-1
+int gemv_batch(hb_ctx *c, const void *A, size_t stride, int R, int C, int nd, const double *x,
+               double *out, double alpha, double beta, size_t out_stride, hipStream_t s) {
+  if (nd <= 0) return HB_OK;
+  dim3 grid((R + 3) / 4, nd);
+  if (c->storage_f32 && A != (const void *)c->d_v0inv)
+    hipLaunchKernelGGL(k_gemv_rows<float>, grid, dim3(256), 0, s, (const float *)A, stride, x, out,
+                       R, C, alpha, beta, out_stride);
+  else
+    hipLaunchKernelGGL(k_gemv_rows<double>, grid, dim3(256), 0, s, (const double *)A, stride, x,
+                       out, R, C, alpha, beta, out_stride);
+  HB_CHECK(c, hipGetLastError());
+  return HB_OK;
+}
+
+int invert_v0(hb_ctx *c, hipStream_t s) {
+  if (c->d_v0inv) return HB_OK;
+  const int n = (int)c->ne;
+  HB_CHECK(c, hipMalloc(&c->d_v0inv, sizeof(double) * (size_t)n * n + sizeof(double) * 2 * n));
+  double *A = c->d_v0inv, *rowp = A + (size_t)n * n, *colp = rowp + n;
+  if (c->storage_f32) {
+    std::vector<float> tmp((size_t)n * n);
+    HB_CHECK(c, hipMemcpyAsync(tmp.data(), c->d_V, tmp.size() * 4, hipMemcpyDeviceToHost, s));
+    HB_CHECK(c, hipStreamSynchronize(s));
+    std::vector<double> t2(tmp.begin(), tmp.end());
+    HB_CHECK(c, hipMemcpyAsync(A, t2.data(), t2.size() * 8, hipMemcpyHostToDevice, s));
+    HB_CHECK(c, hipStreamSynchronize(s));
+  } else {
+    HB_CHECK(c, hipMemcpyAsync(A, c->d_V, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+  }
+  for (int p = 0; p < n; ++p) {
+    hipLaunchKernelGGL(k_gj_save, dim3((n + 255) / 256), dim3(256), 0, s, A, n, p, rowp, colp);
+    hipLaunchKernelGGL(k_gj_update, dim3((n + 255) / 256, n), dim3(256), 0, s, A, n, p, rowp, colp);
+  }
+  HB_CHECK(c, hipGetLastError());
+  return HB_OK;
+}
+
+// dots out[v] = Q_v . w for v < nvec (device), copied to host hv
+int multi_dot(hb_ctx *c, const double *Q, size_t ldq, int nvec, const double *w, size_t n,
+              double *partial, double *dres, double *hv, hipStream_t s) {
+  const int nchunk = (int)((n + kDotChunk - 1) / kDotChunk);
+  hipLaunchKernelGGL(k_multi_dot, dim3(nchunk, nvec), dim3(256), 0, s, Q, ldq, w, n, partial, nchunk);
+  hipLaunchKernelGGL(k_sum_partials, dim3((nvec + 255) / 256), dim3(256), 0, s, partial, nvec, nchunk, dres);
+  HB_CHECK(c, hipMemcpyAsync(hv, dres, sizeof(double) * nvec, hipMemcpyDeviceToHost, s));
+  HB_CHECK(c, hipStreamSynchronize(s));
+  return HB_OK;
+}
+
+}  // namespace
+
+}  // namespace hb
+
+using namespace hb;
+
+namespace {
+
+int ctx_fail(hb_ctx *c, int code, const std::string &m) {
+  if (c) c->err = m;
+  return code;
+}
+
+// Workspace layout for the solvers (doubles):
+//   GMRES: Q[(m+1) n] | r[n] | partial[(m+1) * nchunk] | dres[m+1] | coef[m+1]
+int gmres(hb_ctx *c, const double *b, double *x, double tol, int maxit, hipStream_t s,
+          hb_solve_info *info) {
+  const size_t n = (size_t)c->nt * c->ne;
+  const int m = maxit;
+  const int nchunk = (int)((n + kDotChunk - 1) / kDotChunk);
+  const size_t need = sizeof(double) * ((size_t)(m + 1) * n + n + (size_t)(m + 1) * nchunk + 2 * (m + 1));
+  int rc = ensure_work(c, need);
+  if (rc) return rc;
+  double *Q = c->d_work, *r = Q + (size_t)(m + 1) * n, *partial = r + n;
+  double *dres = partial + (size_t)(m + 1) * nchunk, *coef = dres + (m + 1);
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1, 0.0), hv(m + 1), hv2(m + 1);
+  double beta;
+  if ((rc = multi_dot(c, b, 0, 1, b, n, partial, dres, &beta, s))) return rc;
+  beta = std::sqrt(beta);
+  if (beta == 0.0) {
+    hipLaunchKernelGGL(k_fill, dim3(grid1d(n)), dim3(256), 0, s, x, n, 0.0);
+    if (info) { info->iterations = 0; info->rel_residual = 0.0; }
+    return HB_OK;
+  }
+  hipLaunchKernelGGL(k_scale_copy, dim3(grid1d(n)), dim3(256), 0, s, b, 1.0 / beta, Q, n);
+  gv[0] = beta;
+  int it = 0;
+  bool conv = false;
+  for (int j = 0; j < m; ++j) {
+    double *wj = Q + (size_t)(j + 1) * n;
+    if ((rc = toeplitz_apply(c, c->d_V, (int)c->ne, (int)c->ne, Q + (size_t)j * n, wj, s))) return rc;
+    // classical Gram-Schmidt, twice
+    if ((rc = multi_dot(c, Q, n, j + 1, wj, n, partial, dres, hv.data(), s))) return rc;
+    hipLaunchKernelGGL(k_sub_multi, dim3(grid1d(n)), dim3(256), 0, s, Q, n, dres, j + 1, wj, n);
+    if ((rc = multi_dot(c, Q, n, j + 1, wj, n, partial, dres, hv2.data(), s))) return rc;
+    hipLaunchKernelGGL(k_sub_multi, dim3(grid1d(n)), dim3(256), 0, s, Q, n, dres, j + 1, wj, n);
+    double nn;
+    if ((rc = multi_dot(c, wj, 0, 1, wj, n, partial, dres, &nn, s))) return rc;
+    nn = std::sqrt(nn);
+    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hv[i] + hv2[i];
+    H[(size_t)(j + 1) * m + j] = nn;
+    if (nn > 0) hipLaunchKernelGGL(k_scale_copy, dim3(grid1d(n)), dim3(256), 0, s, wj, 1.0 / nn, wj, n);
+    for (int i = 0; i < j; ++i) {
+      double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
+      H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
+      H[(size_t)i * m + j] = t;
+    }
+    double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+    double rr = std::hypot(a, bb);
+    cs[j] = a / rr;
+    sn[j] = bb / rr;
+    H[(size_t)j * m + j] = rr;
+    H[(size_t)(j + 1) * m + j] = 0.0;
+    gv[j + 1] = -sn[j] * gv[j];
+    gv[j] = cs[j] * gv[j];
+    it = j + 1;
+    if (std::fabs(gv[j + 1]) / beta <= tol || nn == 0.0) {
+      conv = true;
+      break;
+    }
+  }
+  // y = H^{-1} g, x = Q y
+  std::vector<double> y(it);
+  for (int i = it - 1; i >= 0; --i) {
+    double sacc = gv[i];
+    for (int k = i + 1; k < it; ++k) sacc -= H[(size_t)i * m + k] * y[k];
+    y[i] = sacc / H[(size_t)i * m + i];
+  }
+  HB_CHECK(c, hipMemcpyAsync(coef, y.data(), sizeof(double) * it, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, s, Q, n, coef, it, x, n);
+  HB_CHECK(c, hipGetLastError());
+  if (info) info->iterations = it;
+  return conv ? HB_OK : HB_ENOCONV;
+}
+
+int time_march(hb_ctx *c, const double *b, double *w, hipStream_t s) {
+  const int nt = c->nt, ne = (int)c->ne;
+  const size_t n = (size_t)nt * ne;
+  int rc = invert_v0(c, s);
+  if (rc) return rc;
+  if ((rc = ensure_work(c, sizeof(double) * n))) return rc;
+  double *r = c->d_work;
+  HB_CHECK(c, hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  const size_t blk = (size_t)ne * ne;
+  for (int k = 0; k < nt; ++k) {
+    // w^k = (V^0)^{-1} r^k
+    if ((rc = gemv_batch(c, c->d_v0inv, 0, ne, ne, 1, r + (size_t)k * ne, w + (size_t)k * ne, 1.0,
+                         0.0, 0, s)))
+      return rc;
+    // r^{k+d} -= V^d w^k, d = 1 .. nt-1-k
+    const void *V1 = (const char *)c->d_V + blk * (c->storage_f32 ? 4 : 8);
+    if ((rc = gemv_batch(c, V1, blk, ne, ne, nt - 1 - k, w + (size_t)k * ne, r + (size_t)(k + 1) * ne,
+                         -1.0, 1.0, (size_t)ne, s)))
+      return rc;
+  }
+  return HB_OK;
+}
+
+double rel_residual(hb_ctx *c, const double *b, const double *w, hipStream_t s, int *rc) {
+  const size_t n = (size_t)c->nt * c->ne;
+  *rc = ensure_work(c, sizeof(double) * (2 * n + 64 + (n / kDotChunk + 2)));
+  if (*rc) return -1;
+  double *r = c->d_work + n, *partial = r + n, *dres = partial + (n / kDotChunk + 2);
+  if ((*rc = toeplitz_apply(c, c->d_V, (int)c->ne, (int)c->ne, w, r, s))) return -1;
+  hipLaunchKernelGGL(k_axpby, dim3(grid1d(n)), dim3(256), 0, s, 1.0, b, -1.0, r, n);
+  double rr, bb;
+  if ((*rc = multi_dot(c, r, 0, 1, r, n, partial, dres, &rr, s))) return -1;
+  if ((*rc = multi_dot(c, b, 0, 1, b, n, partial, dres, &bb, s))) return -1;
+  return bb > 0 ? std::sqrt(rr / bb) : 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hb_apply(hb_ctx *c, uint32_t op, const double *x, double *y, void *stream) {
+  if (!c) return HB_EINVAL;
+  if (!x || !y) return ctx_fail(c, HB_EINVAL, "null vector");
+  if (op != HB_OP_V && op != HB_OP_K) return ctx_fail(c, HB_EINVAL, "op must be HB_OP_V or HB_OP_K");
+  if (op == HB_OP_V ? !c->have_V : !c->have_K) return ctx_fail(c, HB_ESTATE, "operator not assembled");
+  return toeplitz_apply(c, op == HB_OP_V ? c->d_V : c->d_K, (int)c->ne,
+                        (int)(op == HB_OP_V ? c->ne : c->nv), x, y, (hipStream_t)stream);
+}
+
+int hb_rhs_dirichlet(hb_ctx *c, const double *g, double *b, void *stream) {
+  if (!c) return HB_EINVAL;
+  if (!g || !b) return ctx_fail(c, HB_EINVAL, "null vector");
+  if (!c->have_K) return ctx_fail(c, HB_ESTATE, "K not assembled");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = toeplitz_apply(c, c->d_K, (int)c->ne, (int)c->nv, g, b, s);
+  if (rc) return rc;
+  const size_t n = (size_t)c->nt * c->ne;
+  hipLaunchKernelGGL(k_mass_half, dim3(grid1d(n)), dim3(256), 0, s, c->d_mass, c->d_tris, g, b,
+                     c->nt, (int)c->ne, (int)c->nv, 0.5 * c->h);
+  HB_CHECK(c, hipGetLastError());
+  return HB_OK;
+}
+
+int hb_solve(hb_ctx *c, const double *b, double *w, const hb_solve_opts *opts, hb_solve_info *info,
+             void *stream) {
+  if (!c) return HB_EINVAL;
+  if (!b || !w) return ctx_fail(c, HB_EINVAL, "null vector");
+  if (!c->have_V) return ctx_fail(c, HB_ESTATE, "V not assembled");
+  hb_solve_opts o{};
+  o.method = HB_SOLVE_GMRES;
+  o.max_iter = 500;
+  o.tol = 1e-8;
+  if (opts) {
+    o = *opts;
+    if (o.max_iter <= 0) o.max_iter = 500;
+    if (!(o.tol > 0)) o.tol = 1e-8;
+  }
+  if (o.method != HB_SOLVE_GMRES && o.method != HB_SOLVE_TIMEMARCH)
+    return ctx_fail(c, HB_EINVAL, "unknown solver method");
+  if (o.max_iter > 5000) return ctx_fail(c, HB_EINVAL, "max_iter must be <= 5000");
+  hipStream_t s = (hipStream_t)stream;
+  hb_solve_info inf{};
+  auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  if (o.method == HB_SOLVE_GMRES) rc = gmres(c, b, w, o.tol, o.max_iter, s, &inf);
+  else rc = time_march(c, b, w, s);
+  if (rc != HB_OK && rc != HB_ENOCONV) return rc;
+  HB_CHECK(c, hipStreamSynchronize(s));
+  auto t1 = std::chrono::steady_clock::now();
+  int rc2 = HB_OK;
+  inf.rel_residual = rel_residual(c, b, w, s, &rc2);
+  if (rc2) return rc2;
+  inf.seconds = std::chrono::duration<double>(t1 - t0).count();
+  if (info) *info = inf;
+  if (rc == HB_ENOCONV) c->err = "GMRES reached max_iter before the tolerance";
+  return rc;
+}
+
+int hb_eval_repr(hb_ctx *c, const double *pts, int64_t P, const double *w, const double *g,
+                 double *u, double *sl, double *dl, void *stream) {
+  if (!c) return HB_EINVAL;
+  if (P < 0) return ctx_fail(c, HB_EINVAL, "P must be >= 0");
+  if (P == 0) return HB_OK;
+  if (!pts || !w || !g || !u) return ctx_fail(c, HB_EINVAL, "null pointer");
+  if (P > (int64_t)1 << 31) return ctx_fail(c, HB_EINVAL, "too many points");
+  hipStream_t s = (hipStream_t)stream;
+  if (!c->d_params_repr) {
+    HB_CHECK(c, hipMalloc(&c->d_params_repr, sizeof(AsmParams)));
+    HB_CHECK(c, hipMemcpy(c->d_params_repr, &c->params, sizeof(AsmParams), hipMemcpyHostToDevice));
+  }
+  hipLaunchKernelGGL(k_repr, dim3((unsigned)P), dim3(256), 0, s, c->d_params_repr, pts, w, g, u, sl, dl);
+  HB_CHECK(c, hipGetLastError());
+  return HB_OK;
+}
+
+}  // extern "C"
