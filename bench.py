@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Benchmark of the space-time heat BEM hot path on one MI355X.
+
+One step = one pass of the whole path over the workload (icosphere, 1280 triangles / 642
+vertices, 64 uniform steps on (0, 1], alpha = 1):
+  1. fused assembly of all V_h^d and K_h^d blocks (FP64),
+  2. Dirichlet right-hand side (1/2 M_h + K_h) g,
+  3. GMRES on V_h w = b to relative residual 1e-8 (FP64),
+  4. representation formula at 10^4 interior space-time points.
+Inputs (mesh, data, points) are synthetic and seeded and already resident on the device when the
+timed region starts.  value = pair-block integrals per second of the whole step:
+E_x^2 * E_t units (one unit = one (test panel, trial panel, d) triple with its V entry and its
+three K contributions) divided by the step time.
+
+Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU = 78.6e12  # MI355X FP64 vector FLOP/s
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops_separated(n_sep_pairs, n_t):
+    """FLOPs the semi-analytic method needs for the separated pairs: per (pair, point pair)
+    15 FLOP of geometry (r, rho, 1/rho, r.n) and per (pair, point pair, level delta = i h,
+    i = 0..E_t) one erf and one exp (60 FLOP together) plus 25 FLOP of bracket arithmetic and
+    accumulation; 49 point pairs of the 7-point rule."""
+    return n_sep_pairs * 49.0 * (15.0 + 85.0 * (n_t + 1))
+
+
+def cpu_baseline(verts, tris, alpha, T, n_t):
+    """The oracle (long double, OpenMP over test rows) on a bounded sample of test rows."""
+    import numpy as np
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rows = np.linspace(0, len(tris) - 1, 2 * threads).astype(np.int32)
+    oracle.assemble(verts, tris, alpha, T, n_t, rows=rows[:1])  # load / warm
+    t0 = time.perf_counter()
+    oracle.assemble(verts, tris, alpha, T, n_t, rows=rows)
+    dt = time.perf_counter() - t0
+    units = len(rows) * len(tris) * n_t
+    return {"value": units / dt, "unit": "pair-block integrals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d test rows x %d trial panels x %d blocks, V and K, %.1f s" % (
+                len(rows), len(tris), n_t, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--points", type=int, default=10000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2102_09811_amd import Context, HB_OP_K, HB_OP_V, HB_SOLVE_GMRES, check_mesh
+    from synthetic import ball_points, exp_solution, icosphere, nodal_samples, space_time_points
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    alpha, T, n_t = 1.0, 1.0, 64
+    verts, tris = icosphere(3)
+    ne, nv = len(tris), len(verts)
+    rc, counts, _ = check_mesh(verts, tris)
+    n_sep = int(counts[0])
+    g = nodal_samples(verts, n_t, T, lambda x, t: exp_solution(x, t, alpha))
+    pts = space_time_points(ball_points(args.points, 0.5, seed=0), 0.25, 0.75, seed=0)
+    ctx = Context(verts, tris, alpha, T, n_t)
+    gd = torch.from_numpy(g).cuda()
+    ptsd = torch.from_numpy(pts).cuda()
+    b = torch.empty((n_t, ne), dtype=torch.float64, device="cuda")
+    w = torch.empty((n_t, ne), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(record):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record(stream)
+        ctx.assemble(HB_OP_V | HB_OP_K)
+        ev[1].record(stream)
+        ctx.rhs_dirichlet(gd, b)
+        ev[2].record(stream)
+        _, info = ctx.solve(b, method=HB_SOLVE_GMRES, tol=1e-8, w=w)
+        ev[3].record(stream)
+        u = ctx.eval_repr(ptsd, w, gd)
+        ev[4].record(stream)
+        if record is not None:
+            torch.cuda.synchronize()
+            record.append({"assemble_ms": ev[0].elapsed_time(ev[1]),
+                           "rhs_ms": ev[1].elapsed_time(ev[2]),
+                           "solve_ms": ev[2].elapsed_time(ev[3]),
+                           "repr_ms": ev[3].elapsed_time(ev[4]),
+                           "kernels_ms": ctx.last_assembly_ms(),
+                           "iterations": info["iterations"],
+                           "rel_residual": info["rel_residual"]})
+        return u
+
+    for i in range(args.warmup):
+        log("warmup %d" % i)
+        step(None)
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(rec)
+        log("step %d: %.2f ms (assemble %.2f, solve %.2f, repr %.2f)" % (
+            i, sum(rec[-1][k] for k in ("assemble_ms", "rhs_ms", "solve_ms", "repr_ms")),
+            rec[-1]["assemble_ms"], rec[-1]["solve_ms"], rec[-1]["repr_ms"]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1000.0 * wall / args.steps
+    units = float(ne) * ne * n_t
+    avg = lambda k: float(np.mean([r[k] for r in rec]))
+    sep_ms = float(np.mean([r["kernels_ms"][0] for r in rec]))
+    touch_ms = float(np.mean([r["kernels_ms"][1] for r in rec]))
+    flops = algorithmic_flops_separated(n_sep, n_t)
+    achieved = flops / (sep_ms * 1e-3) / 1e12
+    out = {
+        "metric": "V_d+K_d pair-block integrals/sec & % VALU peak; solve time to 1e-8 vs FP64",
+        "value": units / (ms_per_step * 1e-3),
+        "unit": "pair-block integrals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "icosphere r=1, 1280 triangles / 642 vertices, E_t=64 on (0,1], "
+                               "alpha=1; assemble V+K, RHS, GMRES 1e-8, repr at %d points"
+                               % args.points,
+                   "E_x": ne, "N_x": nv, "E_t": n_t, "alpha": alpha, "T": T,
+                   "repr_points": args.points, "gmres_tol": 1e-8},
+        "phases_ms": {"assemble": avg("assemble_ms"), "rhs": avg("rhs_ms"),
+                      "solve": avg("solve_ms"), "repr": avg("repr_ms"),
+                      "assemble_separated_kernel": sep_ms, "assemble_touching_kernels": touch_ms},
+        "assembly_units_per_s": units / (avg("assemble_ms") * 1e-3),
+        "solve": {"method": "GMRES fp64", "iterations": int(rec[-1]["iterations"]),
+                  "rel_residual": rec[-1]["rel_residual"], "ms": avg("solve_ms")},
+        "roofline": {"bound": "alu", "kernel": "k_separated (separated-pair assembly)",
+                     "achieved": achieved, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / (PEAK_FP64_VALU / 1e12), "traffic": None,
+                     "algorithmic_flops_per_launch": flops},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(verts, tris, alpha, T, n_t)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
