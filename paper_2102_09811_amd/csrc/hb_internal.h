@@ -111,4 +111,6 @@ struct hb_ctx {
   double *d_work = nullptr;
   size_t work_bytes = 0;
   double *d_v0inv = nullptr;         // inverse of V^0 (time marching)
+  double *d_apply = nullptr;         // per-group partial results of the Toeplitz apply
+  size_t apply_bytes = 0;
 };

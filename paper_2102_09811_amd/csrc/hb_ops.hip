@@ -24,70 +24,102 @@ namespace {
   } while (0)
 
 // ------------------------------------------------------------------------------------------
-// Block-Toeplitz product Y[k][r] += sum_d sum_c A^d[r][c] X[k-d][c] (only d <= k).
-// Workgroup tile: 64 rows x 64 time steps, 4 x 4 outputs per thread, the reduction over
-// (d, c) staged through LDS 16 columns at a time; blockIdx.z splits the d range and partial
-// tiles are combined with atomics (Y must be zero on entry).
+// Block-Toeplitz product Y[k][r] = sum_{d <= k} sum_c A^d[r][c] X[k-d][c] on FP64 MFMA.
+// Workgroup = 64 rows (wave w: rows 16w..16w+15) x all E_t time steps, for the d range of its
+// group g.  Per 16-column slice of A the source vector X[:, slice] is staged in LDS once and
+// reused for every d of the group (the time shift k - d is applied when reading it); per d the
+// 64 x 16 tile of A^d is staged and fed to v_mfma_f64_16x16x4 (A operand: lane l holds
+// A[l % 16][l / 16], B operand: X[l / 16][l % 16]; accumulator register i of lane l holds row
+// l / 16 + 4 i, column l % 16).  Time chunks that end before d are skipped.  Each group writes its partial
+// result P[g][k][r]; k_sum_groups adds the groups (deterministic order).
 // ------------------------------------------------------------------------------------------
-constexpr int TR = 64, TKK = 64, TC = 16;
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int TR = 64;
 
-template <typename TA>
-__global__ __launch_bounds__(256) void k_toeplitz(const TA *__restrict__ A,
-                                                  const double *__restrict__ X,
-                                                  double *__restrict__ Y, int nt, int R, int C,
-                                                  int dper) {
-  const int r0 = blockIdx.x * TR, k0 = blockIdx.y * TKK;
-  const int dbeg = blockIdx.z * dper;
-  const int dend = min(min(dbeg + dper, nt), k0 + TKK);
-  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-  __shared__ double As[TC][TR + 2];
-  __shared__ double Xs[TC][TKK + 2];
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int d = dbeg; d < dend; ++d) {
+// Rounds q = 0 .. nd * nchunk - 1 walk (d, column slice); the tiles of round q + 1 are fetched
+// into registers while round q runs on the MFMA units.
+template <typename TA, int NTC, int TC>
+__global__ __launch_bounds__(256) void k_toeplitz_mfma(const TA *__restrict__ A,
+                                                       const double *__restrict__ X,
+                                                       double *__restrict__ P, int nt, int R,
+                                                       int C, int dper) {
+  constexpr int NT = NTC * 16;                 // padded time extent
+  constexpr int A_PER = TR * TC / 256;         // A tile elements per thread
+  constexpr int X_PER = TC * NT / 256;         // X tile elements per thread
+  const int r0 = blockIdx.x * TR;
+  const int g = blockIdx.y;
+  const int d0 = g * dper, d1 = min(d0 + dper, nt);
+  if (d0 >= d1) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lm = lane & 15, lk = lane >> 4;
+  // row stride TC + 4 doubles: the fragment reads (row = lane % 16, column = lane / 16) hit each
+  // LDS bank pair exactly twice
+  __shared__ double Xs[NT][TC + 4];
+  __shared__ double As[TR][TC + 4];
+  const int nchunk = (C + TC - 1) / TC;
+  const int nround = (d1 - d0) * nchunk;
+  double pa[A_PER], px[X_PER];
+  auto fetch = [&](int q) {
+    const int d = d0 + q / nchunk, c0 = (q % nchunk) * TC;
     const TA *Ad = A + (size_t)d * R * C;
-    for (int c0 = 0; c0 < C; c0 += TC) {
 #pragma unroll
-      for (int e = tid; e < TR * TC; e += 256) {
-        const int rr = e / TC, cc = e % TC;
-        const int r = r0 + rr, c = c0 + cc;
-        As[cc][rr] = (r < R && c < C) ? (double)Ad[(size_t)r * C + c] : 0.0;
-      }
-#pragma unroll
-      for (int e = tid; e < TC * TKK; e += 256) {
-        const int kk = e / TC, cc = e % TC;
-        const int k = k0 + kk, c = c0 + cc, j = k - d;
-        Xs[cc][kk] = (k < nt && j >= 0 && c < C) ? X[(size_t)j * C + c] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int cc = 0; cc < TC; ++cc) {
-        double a[4], x[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = As[cc][ty * 4 + i];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = Xs[cc][tx * 4 + j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], x[j], acc[i][j]);
-      }
-      __syncthreads();
+    for (int i = 0; i < A_PER; ++i) {
+      const int e = tid + 256 * i, rr = e / TC, cc = e % TC, r = r0 + rr, c = c0 + cc;
+      pa[i] = (r < R && c < C) ? (double)Ad[(size_t)r * C + c] : 0.0;
     }
-  }
-  if (dbeg >= dend) return;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int k = k0 + tx * 4 + j;
+    for (int i = 0; i < X_PER; ++i) {
+      const int e = tid + 256 * i, k = e / TC, cc = e % TC, c = c0 + cc, j = k - d;
+      px[i] = (k < nt && j >= 0 && c < C) ? X[(size_t)j * C + c] : 0.0;
+    }
+  };
+  v4d acc[NTC];
+#pragma unroll
+  for (int n = 0; n < NTC; ++n) acc[n] = v4d{0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  for (int q = 0; q < nround; ++q) {
+    const int d = d0 + q / nchunk;
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) {
+      const int e = tid + 256 * i;
+      As[e / TC][e % TC] = pa[i];
+    }
+#pragma unroll
+    for (int i = 0; i < X_PER; ++i) {
+      const int e = tid + 256 * i;
+      Xs[e / TC][e % TC] = px[i];
+    }
+    __syncthreads();
+    if (q + 1 < nround) fetch(q + 1);
+#pragma unroll 2
+    for (int s = 0; s < TC / 4; ++s) {
+      const double a = As[wave * 16 + lm][4 * s + lk];
+#pragma unroll
+      for (int n = 0; n < NTC; ++n) {
+        if (16 * n + 15 < d) continue;  // the whole chunk lies before d
+        acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Xs[16 * n + lm][4 * s + lk], acc[n], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int n = 0; n < NTC; ++n) {
+    const int k = 16 * n + lm;
     if (k >= nt) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int r = r0 + ty * 4 + i;
-      if (r < R) atomicAdd(&Y[(size_t)k * R + r], acc[i][j]);
+      const int r = r0 + wave * 16 + lk + 4 * i;
+      if (r < R) P[((size_t)g * nt + k) * R + r] = acc[n][i];
     }
+  }
+}
+
+// Y[i] = sum_g P[g][i]
+__global__ void k_sum_groups(const double *__restrict__ P, int G, size_t n, double *__restrict__ Y) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += P[(size_t)g * n + i];
+    Y[i] = s;
   }
 }
 
@@ -321,22 +353,46 @@ int ensure_work(hb_ctx *c, size_t bytes) {
 }  // namespace
 
 // y = A x (Toeplitz), y overwritten
+template <typename TA>
+static void launch_toeplitz(int ntc, dim3 grid, hipStream_t s, const TA *A, const double *x,
+                            double *P, int nt, int R, int C, int dper) {
+  switch (ntc) {
+    case 1: hipLaunchKernelGGL((k_toeplitz_mfma<TA, 1, 32>), grid, dim3(256), 0, s, A, x, P, nt, R, C, dper); break;
+    case 2: hipLaunchKernelGGL((k_toeplitz_mfma<TA, 2, 32>), grid, dim3(256), 0, s, A, x, P, nt, R, C, dper); break;
+    case 4: hipLaunchKernelGGL((k_toeplitz_mfma<TA, 4, 32>), grid, dim3(256), 0, s, A, x, P, nt, R, C, dper); break;
+    case 8: hipLaunchKernelGGL((k_toeplitz_mfma<TA, 8, 16>), grid, dim3(256), 0, s, A, x, P, nt, R, C, dper); break;
+    default: hipLaunchKernelGGL((k_toeplitz_mfma<TA, 16, 16>), grid, dim3(256), 0, s, A, x, P, nt, R, C, dper); break;
+  }
+}
+
 int toeplitz_apply(hb_ctx *c, const void *blocks, int R, int C, const double *x, double *y,
                    hipStream_t s) {
   const int nt = c->nt;
-  const size_t ny = (size_t)nt * R;
-  hipLaunchKernelGGL(k_fill, dim3(grid1d(ny)), dim3(256), 0, s, y, ny, 0.0);
-  const int gx = (R + TR - 1) / TR, gy = (nt + TKK - 1) / TKK;
-  // enough workgroups to fill the chip: split d into groups of dper
-  int groups = std::max(1, std::min(nt, 2048 / std::max(1, gx * gy)));
+  if (nt > 256) {
+    c->err = "toeplitz apply supports E_t <= 256";
+    return HB_EINVAL;
+  }
+  const int gx = (R + TR - 1) / TR;
+  int groups = std::max(1, std::min(nt, (2048 + gx - 1) / gx));
   const int dper = (nt + groups - 1) / groups;
   groups = (nt + dper - 1) / dper;
+  const size_t ny = (size_t)nt * R;
+  const size_t need = sizeof(double) * ny * groups;
+  if (c->apply_bytes < need) {
+    if (c->d_apply) (void)hipFree(c->d_apply);
+    c->d_apply = nullptr;
+    c->apply_bytes = 0;
+    HB_CHECK(c, hipMalloc(&c->d_apply, need));
+    c->apply_bytes = need;
+  }
+  int ntc = 1;
+  while (ntc * 16 < nt) ntc *= 2;
+  dim3 grid(gx, groups);
   if (c->storage_f32)
-    hipLaunchKernelGGL(k_toeplitz<float>, dim3(gx, gy, groups), dim3(256), 0, s,
-                       (const float *)blocks, x, y, nt, R, C, dper);
+    launch_toeplitz<float>(ntc, grid, s, (const float *)blocks, x, c->d_apply, nt, R, C, dper);
   else
-    hipLaunchKernelGGL(k_toeplitz<double>, dim3(gx, gy, groups), dim3(256), 0, s,
-                       (const double *)blocks, x, y, nt, R, C, dper);
+    launch_toeplitz<double>(ntc, grid, s, (const double *)blocks, x, c->d_apply, nt, R, C, dper);
+  hipLaunchKernelGGL(k_sum_groups, dim3(grid1d(ny)), dim3(256), 0, s, c->d_apply, groups, ny, y);
   HB_CHECK(c, hipGetLastError());
   return HB_OK;
 }
