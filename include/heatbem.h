@@ -48,7 +48,7 @@ extern "C" {
 
 /* ---- assembly precision ---- */
 #define HB_PREC_FP64 0  /* every quadrature point in double precision */
-#define HB_PREC_MIXED 1 /* separated pairs at d >= mixed_d_min in float (see hb_options) */
+#define HB_PREC_MIXED 1 /* separated pairs at large d in float (see hb_options.mixed_d_min) */
 
 /* ---- element types for block copies / storage ---- */
 #define HB_DTYPE_F64 0
@@ -64,8 +64,10 @@ typedef struct hb_options {
                            series of the hat-weighted heat kernel instead of second differences
                            of G^{dtau dt}; default 8, minimum 8; values >= E_t disable it. */
   int32_t storage;      /* HB_DTYPE_F64 (default) or HB_DTYPE_F32 block storage. */
-  int32_t mixed_d_min;  /* HB_PREC_MIXED: first d whose separated pairs use float; default 2,
-                           minimum 2 (d = 0, 1 and all touching pairs always use double). */
+  int32_t mixed_d_min;  /* HB_PREC_MIXED: separated pairs at d >= max(mixed_d_min, d_switch) are
+                           evaluated in float (kernel value and degree-8 Taylor polynomial, double
+                           accumulation); smaller d, whose second differences cancel, and all
+                           touching pairs stay in double.  Default 8, minimum 2. */
   int32_t reserved[12]; /* must be zero */
 } hb_options;
 
@@ -127,19 +129,23 @@ int hb_rhs_dirichlet(hb_ctx *ctx, const double *g, double *b, void *stream);
 /* Solvers for V_h w = b (Sec. 3.4). */
 #define HB_SOLVE_GMRES 0      /* unrestarted GMRES in double on the block system */
 #define HB_SOLVE_TIMEMARCH 1  /* block forward substitution with the inverse of V_h^0 */
+#define HB_SOLVE_MIXED_IR 2   /* iterative refinement: double residual b - V_h w, corrections from
+                                 GMRES on a float copy of the blocks (float MFMA apply) */
 
 typedef struct hb_solve_opts {
   int32_t method;   /* HB_SOLVE_* */
-  int32_t max_iter; /* GMRES iteration cap (default 500 if <= 0) */
+  int32_t max_iter; /* GMRES iteration cap, per refinement step for HB_SOLVE_MIXED_IR
+                       (default 500 if <= 0) */
   double tol;       /* relative residual ||b - V_h w|| / ||b|| target (default 1e-8 if <= 0) */
   int32_t reserved[8];
 } hb_solve_opts;
 
 typedef struct hb_solve_info {
-  int32_t iterations;   /* GMRES iterations (0 for time marching) */
+  int32_t iterations;   /* GMRES iterations, summed over refinement steps (0 for time marching) */
   double rel_residual;  /* ||b - V_h w|| / ||b|| recomputed in double after the solve */
   double seconds;       /* wall time of the solve */
-  int32_t reserved[8];
+  int32_t refinements;  /* HB_SOLVE_MIXED_IR: outer refinement steps */
+  int32_t reserved[7];
 } hb_solve_info;
 
 /* Solve V_h w = b for w.  b, w: device pointers, E_t x E_x, float64.  info may be NULL.

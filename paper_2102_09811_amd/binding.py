@@ -16,7 +16,7 @@ HB_OK, HB_EINVAL, HB_EMESH, HB_EORIENT, HB_ENOMEM, HB_EHIP, HB_ENOCONV, HB_ESTAT
 HB_OP_V, HB_OP_K = 1, 2
 HB_PREC_FP64, HB_PREC_MIXED = 0, 1
 HB_DTYPE_F64, HB_DTYPE_F32 = 0, 1
-HB_SOLVE_GMRES, HB_SOLVE_TIMEMARCH = 0, 1
+HB_SOLVE_GMRES, HB_SOLVE_TIMEMARCH, HB_SOLVE_MIXED_IR = 0, 1, 2
 
 EXPORTED = ["hb_default_options", "hb_check_mesh", "hb_create", "hb_destroy", "hb_last_error",
             "hb_sizes", "hb_assemble", "hb_get_blocks", "hb_apply", "hb_rhs_dirichlet",
@@ -42,7 +42,8 @@ class SolveOpts(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("reserved", ctypes.c_int32 * 8)]
+                ("seconds", ctypes.c_double), ("refinements", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
 
 
 _lib = None
@@ -208,7 +209,8 @@ class Context:
         if rc not in (HB_OK, HB_ENOCONV):
             self._check(rc)
         return w, {"iterations": info.iterations, "rel_residual": info.rel_residual,
-                   "seconds": info.seconds, "converged": rc == HB_OK}
+                   "seconds": info.seconds, "refinements": info.refinements,
+                   "converged": rc == HB_OK}
 
     def eval_repr(self, pts, w, g, stream=None, parts=False):
         import torch

@@ -25,6 +25,14 @@ constexpr double kInvSqrtPi = 0.56418958354775628695;
 constexpr double kFourInvSqrtPi = 2.2567583341910251478;
 
 template <int N>
+__device__ __forceinline__ float hornerf(const float *__restrict__ c, float x) {
+  float r = c[N - 1];
+#pragma unroll
+  for (int i = N - 2; i >= 0; --i) r = fmaf(r, x, c[i]);
+  return r;
+}
+
+template <int N>
 __device__ __forceinline__ double horner(const double *__restrict__ c, double x) {
   double r = c[N - 1];
 #pragma unroll
@@ -185,7 +193,7 @@ __device__ __forceinline__ void separated_pass(const AsmParams &p, int l, int m,
 // ------------------------------------------------------------------------------------------
 // Separated pairs: workgroup = (test panel l, 256 consecutive trial panels m); lane = m.
 // ------------------------------------------------------------------------------------------
-template <typename TS, int D>
+template <typename TS, int D, bool MIXED>
 __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restrict__ pp) {
   const AsmParams &p = *pp;
   const int l = blockIdx.y;
@@ -235,15 +243,30 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
         const double wa = p.w7[a];
         const double W = wa * wb;
         const double wrn = wa * fma(rx, n0, fma(ry, n1, rz * n2));
+        if (MIXED && d0 >= p.mixed_d_min) {
+          // mixed precision: the kernel value and its polynomial in float (hardware exp,
+          // degree-8 series), the accumulation in double
 #pragma unroll
-        for (int j = 0; j < kLT; ++j) {
-          const int d = min(d0 + j, p.nt - 1);
-          const double w = rho2 * p.tscale[3 * d + 2];
-          const double e = exp(-w);
-          const double pv = horner<kTaylorN>(p.taylor + (size_t)(2 * d) * kTaylorN, w);
-          const double pk = horner<kTaylorN>(p.taylor + (size_t)(2 * d + 1) * kTaylorN, w);
-          TV[j] = fma(W * e, pv, TV[j]);
-          tk[j] = fma(wrn * e, pk, tk[j]);
+          for (int j = 0; j < kLT; ++j) {
+            const int d = min(d0 + j, p.nt - 1);
+            const float w = (float)(rho2 * p.tscale[3 * d + 2]);
+            const float e = __expf(-w);
+            const float pv = hornerf<kTaylorN32>(p.taylor32 + (size_t)(2 * d) * kTaylorN32, w);
+            const float pk = hornerf<kTaylorN32>(p.taylor32 + (size_t)(2 * d + 1) * kTaylorN32, w);
+            TV[j] += W * (double)(e * pv);
+            tk[j] += wrn * (double)(e * pk);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < kLT; ++j) {
+            const int d = min(d0 + j, p.nt - 1);
+            const double w = rho2 * p.tscale[3 * d + 2];
+            const double e = exp(-w);
+            const double pv = horner<kTaylorN>(p.taylor + (size_t)(2 * d) * kTaylorN, w);
+            const double pk = horner<kTaylorN>(p.taylor + (size_t)(2 * d + 1) * kTaylorN, w);
+            TV[j] = fma(W * e, pv, TV[j]);
+            tk[j] = fma(wrn * e, pk, tk[j]);
+          }
         }
       }
 #pragma unroll
@@ -410,16 +433,22 @@ __global__ __launch_bounds__(64, 2) void k_touching(const AsmParams *__restrict_
 
 }  // namespace
 
+template <typename TS, int D>
+static void launch_sep(dim3 grid, hipStream_t s, const AsmParams *dp, bool mixed) {
+  if (mixed) hipLaunchKernelGGL((k_separated<TS, D, true>), grid, dim3(256), 0, s, dp);
+  else hipLaunchKernelGGL((k_separated<TS, D, false>), grid, dim3(256), 0, s, dp);
+}
+
 void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, int precision,
                                int storage_f32, hipStream_t s) {
-  (void)precision;
   dim3 grid((p.ne + 255) / 256, p.ne);
+  const bool mixed = precision == HB_PREC_MIXED;
   if (p.dsw == 16) {
-    if (storage_f32) hipLaunchKernelGGL((k_separated<float, 16>), grid, dim3(256), 0, s, dp);
-    else hipLaunchKernelGGL((k_separated<double, 16>), grid, dim3(256), 0, s, dp);
+    if (storage_f32) launch_sep<float, 16>(grid, s, dp, mixed);
+    else launch_sep<double, 16>(grid, s, dp, mixed);
   } else {
-    if (storage_f32) hipLaunchKernelGGL((k_separated<float, 8>), grid, dim3(256), 0, s, dp);
-    else hipLaunchKernelGGL((k_separated<double, 8>), grid, dim3(256), 0, s, dp);
+    if (storage_f32) launch_sep<float, 8>(grid, s, dp, mixed);
+    else launch_sep<double, 8>(grid, s, dp, mixed);
   }
 }
 

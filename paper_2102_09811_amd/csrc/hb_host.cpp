@@ -302,8 +302,8 @@ void ss_nodes(int cls, int M, std::vector<SSNode> &out) {
 //   Q_0 = 1,  Q_{n+1}(w) = (w - n - p) Q_n(w) - w Q_n'(w).
 // So the block integral is h^2 f(s) P_d(w) with P_d(w) = sum_k 2/(2k+2)! d^{-2k} Q_{2k}(w),
 // truncated at k = kTaylorDeg/2 (p = 3/2 for G, p = 5/2 for alpha dG/dn).
-void taylor_poly(ld p, int d, ld out[hb::kTaylorN]) {
-  const int K = hb::kTaylorDeg / 2;
+void taylor_poly(ld p, int d, ld out[hb::kTaylorN], int deg = hb::kTaylorDeg) {
+  const int K = deg / 2;
   std::vector<std::vector<ld>> Q(2 * K + 1);
   Q[0] = {1.0L};
   for (int n = 0; n < 2 * K; ++n) {
@@ -379,6 +379,7 @@ int build_tables(hb_ctx *c) {
 
   // Taylor tables for d >= dsw
   std::vector<double> tay((size_t)c->nt * 2 * kTaylorN, 0.0), tsc((size_t)c->nt * 3, 0.0);
+  std::vector<float> tay32((size_t)c->nt * 2 * kTaylorN32, 0.0f);
   for (int d = std::max(1, p.dsw); d < c->nt; ++d) {
     ld pv[kTaylorN], pk[kTaylorN];
     taylor_poly(1.5L, d, pv);
@@ -386,6 +387,12 @@ int build_tables(hb_ctx *c) {
     for (int j = 0; j < kTaylorN; ++j) {
       tay[((size_t)d * 2 + 0) * kTaylorN + j] = (double)pv[j];
       tay[((size_t)d * 2 + 1) * kTaylorN + j] = (double)pk[j];
+    }
+    taylor_poly(1.5L, d, pv, kTaylorDeg32);
+    taylor_poly(2.5L, d, pk, kTaylorDeg32);
+    for (int j = 0; j < kTaylorN32; ++j) {
+      tay32[((size_t)d * 2 + 0) * kTaylorN32 + j] = (float)pv[j];
+      tay32[((size_t)d * 2 + 1) * kTaylorN32 + j] = (float)pk[j];
     }
     ld s = d * h;
     tsc[3 * d + 0] = (double)(h * h * powl(4.0L * kPi * al * s, -1.5L));
@@ -395,6 +402,7 @@ int build_tables(hb_ctx *c) {
   int rc;
   if ((rc = upload(c, (void **)&c->d_taylor, tay.data(), tay.size() * sizeof(double)))) return rc;
   if ((rc = upload(c, (void **)&c->d_tscale, tsc.data(), tsc.size() * sizeof(double)))) return rc;
+  if ((rc = upload(c, (void **)&c->d_taylor32, tay32.data(), tay32.size() * sizeof(float)))) return rc;
 
   // geometry SoA: far-rule nodes, normal, area
   size_t ne = (size_t)c->ne;
@@ -451,6 +459,7 @@ int build_tables(hb_ctx *c) {
     if ((rc = upload(c, (void **)&c->ss[cls].d, tab.data(), tab.size() * sizeof(double)))) return rc;
   }
   p.taylor = c->d_taylor;
+  p.taylor32 = c->d_taylor32;
   p.tscale = c->d_tscale;
   p.geom = c->d_geom;
   p.tris = c->d_tris;
@@ -470,7 +479,7 @@ void hb_default_options(hb_options *o) {
   o->ss_order = 4;
   o->d_switch = 8;
   o->storage = HB_DTYPE_F64;
-  o->mixed_d_min = 2;
+  o->mixed_d_min = 8;
 }
 
 int hb_check_mesh(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
@@ -537,8 +546,9 @@ int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t 
 void hb_destroy(hb_ctx *c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
-  void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_taylor, c->d_tscale, c->d_mass,
-                  c->d_V, c->d_K, c->d_work, c->d_v0inv, c->d_apply, c->ss[1].d, c->ss[2].d, c->ss[3].d};
+  void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_taylor,
+                  c->d_taylor32, c->d_V32, c->d_tscale, c->d_mass,
+                  c->d_V, c->d_K, c->d_work, c->d_v0inv, c->d_apply, c->d_ir, c->ss[1].d, c->ss[2].d, c->ss[3].d};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int i = 0; i < 4; ++i)
@@ -588,7 +598,10 @@ int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
   }
   HB_HIP(c, hipGetLastError());
   HB_HIP(c, hipEventRecord(c->ev[2], s));
-  if (p.do_V) c->have_V = true;
+  if (p.do_V) {
+    c->have_V = true;
+    c->V32_valid = false;
+  }
   if (p.do_K) c->have_K = true;
   c->timed = true;
   return HB_OK;

@@ -16,6 +16,8 @@ namespace hb {
 // differences of G^{dtau dt} at levels 0 .. kClosedBlocks; later blocks use the Taylor form.
 constexpr int kTaylorDeg = 16;       // degree of the Taylor polynomial in w = rho^2/(4 alpha d h)
 constexpr int kTaylorN = kTaylorDeg + 1;
+constexpr int kTaylorDeg32 = 8;      // degree used by the float evaluation (mixed precision)
+constexpr int kTaylorN32 = kTaylorDeg32 + 1;
 constexpr int kSeriesN = 14;         // terms of the small-z series of the brackets A(z), B(z)
 constexpr int kMaxClosed = 16;       // largest supported d_switch
 constexpr int kFarN = 7;             // Radon 7-point rule
@@ -43,6 +45,7 @@ struct AsmParams {
   double kK;                   // 1 / (8 pi alpha)
   double kKs;                  // h / (4 pi)
   const double *taylor;        // [nt][2][kTaylorN] Taylor polynomials in w (V, K), d >= dsw
+  const float *taylor32;       // [nt][2][kTaylorN32] shorter series for the float path
   const double *tscale;        // [nt][3]: V scale, K scale, c_d = 1/(4 alpha d h)
   const double *geom;          // SoA [25][ne]: far nodes (q*3+c), normal (21..23), area (24)
   const int32_t *tris;         // [ne][3]
@@ -76,6 +79,9 @@ void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const Tou
 // y = A x for the block-Toeplitz operator with blocks [nt][R][C] (y overwritten, time-major)
 int toeplitz_apply(hb_ctx *c, const void *blocks, int R, int C, const double *x, double *y,
                    hipStream_t s);
+// same product with float blocks on the float MFMA path (float accumulation)
+int toeplitz_apply32(hb_ctx *c, const float *blocks, int R, int C, const double *x, double *y,
+                     hipStream_t s);
 
 }  // namespace hb
 
@@ -97,6 +103,9 @@ struct hb_ctx {
   hb::TouchPair *d_touch = nullptr;
   hb::SSRule ss[4];
   double *d_taylor = nullptr, *d_tscale = nullptr;
+  float *d_taylor32 = nullptr;
+  float *d_V32 = nullptr;            // float copy of V for the mixed-precision inner solver
+  bool V32_valid = false;
   double *d_mass = nullptr;          // p0 x p1 mass, [ne][3] = area/3 per local vertex
   void *d_V = nullptr, *d_K = nullptr;
   bool have_V = false, have_K = false;
@@ -111,6 +120,8 @@ struct hb_ctx {
   double *d_work = nullptr;
   size_t work_bytes = 0;
   double *d_v0inv = nullptr;         // inverse of V^0 (time marching)
+  double *d_ir = nullptr;            // iterative refinement: x, r, correction
+  size_t ir_bytes = 0;
   double *d_apply = nullptr;         // per-group partial results of the Toeplitz apply
   size_t apply_bytes = 0;
 };

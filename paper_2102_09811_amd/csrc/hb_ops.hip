@@ -123,6 +123,98 @@ __global__ void k_sum_groups(const double *__restrict__ P, int G, size_t n, doub
   }
 }
 
+// The same product with float blocks on v_mfma_f32_16x16x4f32: the source vector is rounded to
+// float when staged, products accumulate in float per group, groups are added in double.
+// (accumulator register i of lane l holds row 4 (l / 16) + i, column l % 16 for this opcode)
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int NTC, int TC>
+__global__ __launch_bounds__(256) void k_toeplitz_mfma32(const float *__restrict__ A,
+                                                         const double *__restrict__ X,
+                                                         float *__restrict__ P, int nt, int R,
+                                                         int C, int dper) {
+  constexpr int NT = NTC * 16;
+  constexpr int A_PER = TR * TC / 256;
+  constexpr int X_PER = TC * NT / 256;
+  const int r0 = blockIdx.x * TR;
+  const int g = blockIdx.y;
+  const int d0 = g * dper, d1 = min(d0 + dper, nt);
+  if (d0 >= d1) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lm = lane & 15, lk = lane >> 4;
+  __shared__ float Xs[NT][TC + 4];
+  __shared__ float As[TR][TC + 4];
+  const int nchunk = (C + TC - 1) / TC;
+  const int nround = (d1 - d0) * nchunk;
+  float pa[A_PER], px[X_PER];
+  auto fetch = [&](int q) {
+    const int d = d0 + q / nchunk, c0 = (q % nchunk) * TC;
+    const float *Ad = A + (size_t)d * R * C;
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) {
+      const int e = tid + 256 * i, rr = e / TC, cc = e % TC, r = r0 + rr, c = c0 + cc;
+      pa[i] = (r < R && c < C) ? Ad[(size_t)r * C + c] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < X_PER; ++i) {
+      const int e = tid + 256 * i, k = e / TC, cc = e % TC, c = c0 + cc, j = k - d;
+      px[i] = (k < nt && j >= 0 && c < C) ? (float)X[(size_t)j * C + c] : 0.0f;
+    }
+  };
+  v4f acc[NTC];
+#pragma unroll
+  for (int n = 0; n < NTC; ++n) acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
+  fetch(0);
+  for (int q = 0; q < nround; ++q) {
+    const int d = d0 + q / nchunk;
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) {
+      const int e = tid + 256 * i;
+      As[e / TC][e % TC] = pa[i];
+    }
+#pragma unroll
+    for (int i = 0; i < X_PER; ++i) {
+      const int e = tid + 256 * i;
+      Xs[e / TC][e % TC] = px[i];
+    }
+    __syncthreads();
+    if (q + 1 < nround) fetch(q + 1);
+#pragma unroll 2
+    for (int s = 0; s < TC / 4; ++s) {
+      const float a = As[wave * 16 + lm][4 * s + lk];
+#pragma unroll
+      for (int n = 0; n < NTC; ++n) {
+        if (16 * n + 15 < d) continue;
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Xs[16 * n + lm][4 * s + lk], acc[n], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int n = 0; n < NTC; ++n) {
+    const int k = 16 * n + lm;
+    if (k >= nt) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = r0 + wave * 16 + 4 * lk + i;
+      if (r < R) P[((size_t)g * nt + k) * R + r] = acc[n][i];
+    }
+  }
+}
+
+__global__ void k_sum_groups32(const float *__restrict__ P, int G, size_t n, double *__restrict__ Y) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += (double)P[(size_t)g * n + i];
+    Y[i] = s;
+  }
+}
+
+__global__ void k_to_float(const double *__restrict__ x, float *__restrict__ y, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
 __global__ void k_fill(double *__restrict__ y, size_t n, double v) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     y[i] = v;
@@ -397,6 +489,48 @@ int toeplitz_apply(hb_ctx *c, const void *blocks, int R, int C, const double *x,
   return HB_OK;
 }
 
+static int apply_groups(int R, int nt, int *dper_out) {
+  const int gx = (R + TR - 1) / TR;
+  int groups = std::max(1, std::min(nt, (2048 + gx - 1) / gx));
+  const int dper = (nt + groups - 1) / groups;
+  *dper_out = dper;
+  return (nt + dper - 1) / dper;
+}
+
+int toeplitz_apply32(hb_ctx *c, const float *blocks, int R, int C, const double *x, double *y,
+                     hipStream_t s) {
+  const int nt = c->nt;
+  if (nt > 256) {
+    c->err = "toeplitz apply supports E_t <= 256";
+    return HB_EINVAL;
+  }
+  int dper;
+  const int groups = apply_groups(R, nt, &dper);
+  const size_t ny = (size_t)nt * R;
+  const size_t need = sizeof(float) * ny * groups;
+  if (c->apply_bytes < need) {
+    if (c->d_apply) (void)hipFree(c->d_apply);
+    c->d_apply = nullptr;
+    c->apply_bytes = 0;
+    HB_CHECK(c, hipMalloc(&c->d_apply, need));
+    c->apply_bytes = need;
+  }
+  float *P = (float *)c->d_apply;
+  int ntc = 1;
+  while (ntc * 16 < nt) ntc *= 2;
+  dim3 grid((R + TR - 1) / TR, groups);
+  switch (ntc) {
+    case 1: hipLaunchKernelGGL((k_toeplitz_mfma32<1, 32>), grid, dim3(256), 0, s, blocks, x, P, nt, R, C, dper); break;
+    case 2: hipLaunchKernelGGL((k_toeplitz_mfma32<2, 32>), grid, dim3(256), 0, s, blocks, x, P, nt, R, C, dper); break;
+    case 4: hipLaunchKernelGGL((k_toeplitz_mfma32<4, 32>), grid, dim3(256), 0, s, blocks, x, P, nt, R, C, dper); break;
+    case 8: hipLaunchKernelGGL((k_toeplitz_mfma32<8, 32>), grid, dim3(256), 0, s, blocks, x, P, nt, R, C, dper); break;
+    default: hipLaunchKernelGGL((k_toeplitz_mfma32<16, 16>), grid, dim3(256), 0, s, blocks, x, P, nt, R, C, dper); break;
+  }
+  hipLaunchKernelGGL(k_sum_groups32, dim3(grid1d(ny)), dim3(256), 0, s, P, groups, ny, y);
+  HB_CHECK(c, hipGetLastError());
+  return HB_OK;
+}
+
 namespace {
 
 // out[(k0 + d) * R + row] = beta * out + alpha * (A^{d_first + d} x), d = 0 .. nd-1
@@ -463,7 +597,24 @@ int ctx_fail(hb_ctx *c, int code, const std::string &m) {
 
 // Workspace layout for the solvers (doubles):
 //   GMRES: Q[(m+1) n] | r[n] | partial[(m+1) * nchunk] | dres[m+1] | coef[m+1]
-int gmres(hb_ctx *c, const double *b, double *x, double tol, int maxit, hipStream_t s,
+// V_h x with the double blocks (op 0) or with the float copy on the float MFMA path (op 1)
+int apply_V(hb_ctx *c, int op, const double *x, double *y, hipStream_t s) {
+  if (op == 0) return toeplitz_apply(c, c->d_V, (int)c->ne, (int)c->ne, x, y, s);
+  const float *V32 = c->storage_f32 ? (const float *)c->d_V : c->d_V32;
+  return toeplitz_apply32(c, V32, (int)c->ne, (int)c->ne, x, y, s);
+}
+
+int ensure_V32(hb_ctx *c, hipStream_t s) {
+  if (c->storage_f32 || c->V32_valid) return HB_OK;
+  const size_t n = (size_t)c->nt * c->ne * c->ne;
+  if (!c->d_V32) HB_CHECK(c, hipMalloc(&c->d_V32, n * sizeof(float)));
+  hipLaunchKernelGGL(k_to_float, dim3(grid1d(n)), dim3(256), 0, s, (const double *)c->d_V, c->d_V32, n);
+  HB_CHECK(c, hipGetLastError());
+  c->V32_valid = true;
+  return HB_OK;
+}
+
+int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, hipStream_t s,
           hb_solve_info *info) {
   const size_t n = (size_t)c->nt * c->ne;
   const int m = maxit;
@@ -488,7 +639,7 @@ int gmres(hb_ctx *c, const double *b, double *x, double tol, int maxit, hipStrea
   bool conv = false;
   for (int j = 0; j < m; ++j) {
     double *wj = Q + (size_t)(j + 1) * n;
-    if ((rc = toeplitz_apply(c, c->d_V, (int)c->ne, (int)c->ne, Q + (size_t)j * n, wj, s))) return rc;
+    if ((rc = apply_V(c, op, Q + (size_t)j * n, wj, s))) return rc;
     // classical Gram-Schmidt, twice
     if ((rc = multi_dot(c, Q, n, j + 1, wj, n, partial, dres, hv.data(), s))) return rc;
     hipLaunchKernelGGL(k_sub_multi, dim3(grid1d(n)), dim3(256), 0, s, Q, n, dres, j + 1, wj, n);
@@ -556,6 +707,65 @@ int time_march(hb_ctx *c, const double *b, double *w, hipStream_t s) {
   return HB_OK;
 }
 
+// Iterative refinement: x_{i+1} = x_i + d_i with V32 d_i ~= b - V_h x_i (GMRES on the float
+// operator to relative tolerance inner_tol); residuals in double with the double operator.
+int mixed_ir(hb_ctx *c, const double *b, double *x, double tol, int maxit, hipStream_t s,
+             hb_solve_info *info) {
+  const size_t n = (size_t)c->nt * c->ne;
+  int rc = ensure_V32(c, s);
+  if (rc) return rc;
+  if (c->ir_bytes < 2 * n * sizeof(double) + 64 * sizeof(double)) {
+    if (c->d_ir) (void)hipFree(c->d_ir);
+    c->d_ir = nullptr;
+    c->ir_bytes = 0;
+    HB_CHECK(c, hipMalloc(&c->d_ir, 2 * n * sizeof(double) + 64 * sizeof(double)));
+    c->ir_bytes = 2 * n * sizeof(double) + 64 * sizeof(double);
+  }
+  double *r = c->d_ir, *dlt = r + n;
+  const double inner_tol = 1e-4;
+  hipLaunchKernelGGL(k_fill, dim3(grid1d(n)), dim3(256), 0, s, x, n, 0.0);
+  HB_CHECK(c, hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // norms via the GMRES dot kernels (scratch behind the correction vector is not needed)
+  auto norm = [&](const double *v, double *out) -> int {
+    const int nchunk = (int)((n + kDotChunk - 1) / kDotChunk);
+    if (c->work_bytes < sizeof(double) * (nchunk + 2)) {
+      int r2 = ensure_work(c, sizeof(double) * (nchunk + 2));
+      if (r2) return r2;
+    }
+    double *partial = c->d_work, *dres = partial + nchunk;
+    int r2 = multi_dot(c, v, 0, 1, v, n, partial, dres, out, s);
+    *out = std::sqrt(*out);
+    return r2;
+  };
+  double bn;
+  if ((rc = norm(b, &bn))) return rc;
+  if (bn == 0.0) return HB_OK;
+  int total_it = 0, outer = 0;
+  bool conv = false;
+  for (; outer < 12; ++outer) {
+    if (outer > 0) {
+      if ((rc = apply_V(c, 0, x, r, s))) return rc;
+      hipLaunchKernelGGL(k_axpby, dim3(grid1d(n)), dim3(256), 0, s, 1.0, b, -1.0, r, n);
+    }
+    double rn;
+    if ((rc = norm(r, &rn))) return rc;
+    if (rn <= tol * bn) {
+      conv = true;
+      break;
+    }
+    hb_solve_info in{};
+    rc = gmres(c, 1, r, dlt, inner_tol, maxit, s, &in);
+    if (rc != HB_OK && rc != HB_ENOCONV) return rc;
+    total_it += in.iterations;
+    hipLaunchKernelGGL(k_axpby, dim3(grid1d(n)), dim3(256), 0, s, 1.0, dlt, 1.0, x, n);
+  }
+  if (info) {
+    info->iterations = total_it;
+    info->refinements = outer;
+  }
+  return conv ? HB_OK : HB_ENOCONV;
+}
+
 double rel_residual(hb_ctx *c, const double *b, const double *w, hipStream_t s, int *rc) {
   const size_t n = (size_t)c->nt * c->ne;
   *rc = ensure_work(c, sizeof(double) * (2 * n + 64 + (n / kDotChunk + 2)));
@@ -610,14 +820,15 @@ int hb_solve(hb_ctx *c, const double *b, double *w, const hb_solve_opts *opts, h
     if (o.max_iter <= 0) o.max_iter = 500;
     if (!(o.tol > 0)) o.tol = 1e-8;
   }
-  if (o.method != HB_SOLVE_GMRES && o.method != HB_SOLVE_TIMEMARCH)
+  if (o.method != HB_SOLVE_GMRES && o.method != HB_SOLVE_TIMEMARCH && o.method != HB_SOLVE_MIXED_IR)
     return ctx_fail(c, HB_EINVAL, "unknown solver method");
   if (o.max_iter > 5000) return ctx_fail(c, HB_EINVAL, "max_iter must be <= 5000");
   hipStream_t s = (hipStream_t)stream;
   hb_solve_info inf{};
   auto t0 = std::chrono::steady_clock::now();
   int rc;
-  if (o.method == HB_SOLVE_GMRES) rc = gmres(c, b, w, o.tol, o.max_iter, s, &inf);
+  if (o.method == HB_SOLVE_GMRES) rc = gmres(c, 0, b, w, o.tol, o.max_iter, s, &inf);
+  else if (o.method == HB_SOLVE_MIXED_IR) rc = mixed_ir(c, b, w, o.tol, o.max_iter, s, &inf);
   else rc = time_march(c, b, w, s);
   if (rc != HB_OK && rc != HB_ENOCONV) return rc;
   HB_CHECK(c, hipStreamSynchronize(s));

@@ -1,0 +1,97 @@
+"""Mixed precision (float separated pairs at large d, float-MFMA apply, iterative refinement)
+against the double path.
+
+Bars: per-block max error relative to the block's max, mixed vs double assembly, <= 1e-6 for
+every d, V and K; the float apply agrees with the double apply of the same (float-rounded)
+blocks to 1e-5; the refinement solve reaches ||b - V_h w|| / ||b|| <= 1e-8 with the double
+operator.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import downstream as ds
+from synthetic import cube, exp_solution, icosphere, nodal_samples
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def per_block_rel(A, B):
+    """max |A^d - B^d| / max |A^d| per block, on the device."""
+    import torch
+    num = (A - B).abs().reshape(A.shape[0], -1).amax(1)
+    den = A.abs().reshape(A.shape[0], -1).amax(1)
+    return (num / den).cpu().numpy()
+
+
+@pytest.mark.parametrize("mesh,nt,alpha", [("cube4", 16, 1.0), ("cube4", 40, 0.5),
+                                           ("icosphere3", 64, 1.0)])
+def test_mixed_assembly_per_block(mesh, nt, alpha):
+    from paper_2102_09811_amd import Context, HB_OP_K, HB_OP_V, HB_PREC_MIXED
+    v, t = cube(4) if mesh == "cube4" else icosphere(3)
+    say("mixed assembly %s nt=%d alpha=%g" % (mesh, nt, alpha))
+    ctx = Context(v, t, alpha, 1.0, nt)
+    ctx.assemble()
+    V64, K64 = ctx.blocks(HB_OP_V), ctx.blocks(HB_OP_K)
+    ctx.assemble(precision=HB_PREC_MIXED)
+    Vm, Km = ctx.blocks(HB_OP_V), ctx.blocks(HB_OP_K)
+    eV, eK = per_block_rel(V64, Vm), per_block_rel(K64, Km)
+    say("max e_V=%.2e max e_K=%.2e; d<8 identical: %s" % (eV.max(), eK.max(),
+        bool((eV[:8] == 0).all() and (eK[:8] <= 1e-14).all())))
+    assert eV.max() <= 1e-6 and eK.max() <= 1e-6
+    assert np.all(eV[:min(8, nt)] == 0.0)               # closed-form blocks stay in double
+    if nt > 8:
+        assert eV[8:].max() > 0.0                        # the float path was taken
+    ctx.close()
+
+
+def test_float_apply_and_refinement_solve():
+    import torch
+    from paper_2102_09811_amd import Context, HB_OP_V, HB_SOLVE_GMRES, HB_SOLVE_MIXED_IR
+    v, t = icosphere(3)
+    nt = 64
+    say("float apply / refinement on icosphere3 nt=64")
+    ctx = Context(v, t, 1.0, 1.0, nt)
+    ctx.assemble()
+    g = nodal_samples(v, nt, 1.0, lambda x, tt: exp_solution(x, tt, 1.0))
+    gd = torch.from_numpy(g).cuda()
+    b = ctx.rhs_dirichlet(gd)
+    w64, i64 = ctx.solve(b, method=HB_SOLVE_GMRES, tol=1e-8)
+    wm, im = ctx.solve(b, method=HB_SOLVE_MIXED_IR, tol=1e-8)
+    say("gmres: it=%d res=%.2e %.1f ms | mixed: it=%d ref=%d res=%.2e %.1f ms" % (
+        i64["iterations"], i64["rel_residual"], 1e3 * i64["seconds"], im["iterations"],
+        im["refinements"], im["rel_residual"], 1e3 * im["seconds"]))
+    assert im["converged"] and im["rel_residual"] <= 1e-8
+    rel = float((wm - w64).norm() / w64.norm())
+    assert rel <= 1e-5, rel
+    ctx.close()
+
+
+def test_cube3072_nt128_mixed_error():
+    """3072-triangle cube, 128 steps, alpha in {0.5, 1, 2}: mixed vs double per-block error."""
+    from paper_2102_09811_amd import Context, HB_OP_K, HB_OP_V, HB_PREC_MIXED
+    v, t = cube(16)
+    for alpha in (0.5, 1.0, 2.0):
+        say("cube16 nt=128 alpha=%g" % alpha)
+        ctx = Context(v, t, alpha, 1.0, 128)
+        worst = {}
+        for op in (HB_OP_V, HB_OP_K):
+            ctx.assemble(op)
+            ref = ctx.blocks(op)
+            ctx.assemble(op, precision=HB_PREC_MIXED)
+            e = per_block_rel(ref, ctx.blocks(op))
+            del ref
+            worst[op] = e
+        say("alpha=%g: max e_V=%.2e (d=%d) max e_K=%.2e (d=%d)" % (
+            alpha, worst[HB_OP_V].max(), worst[HB_OP_V].argmax(), worst[HB_OP_K].max(),
+            worst[HB_OP_K].argmax()))
+        assert worst[HB_OP_V].max() <= 1e-6 and worst[HB_OP_K].max() <= 1e-6
+        ctx.close()
+        import torch
+        torch.cuda.empty_cache()
