@@ -137,7 +137,9 @@ typedef struct hb_solve_opts {
   int32_t max_iter; /* GMRES iteration cap, per refinement step for HB_SOLVE_MIXED_IR
                        (default 500 if <= 0) */
   double tol;       /* relative residual ||b - V_h w|| / ||b|| target (default 1e-8 if <= 0) */
-  int32_t reserved[8];
+  int32_t precond;  /* GMRES methods: 1 = right-precondition with the sparse approximate inverse
+                       installed by hb_precond_set, 0 = none */
+  int32_t reserved[7];
 } hb_solve_opts;
 
 typedef struct hb_solve_info {
@@ -160,6 +162,63 @@ int hb_solve(hb_ctx *ctx, const double *b, double *w, const hb_solve_opts *opts,
  * rule of hb_assemble.  sl / dl may be NULL; otherwise they receive V~ w and W g. */
 int hb_eval_repr(hb_ctx *ctx, const double *pts, int64_t P, const double *w, const double *g,
                  double *u, double *sl, double *dl, void *stream);
+
+/* ---- Learned preconditioner ----
+ * M ~ (V_h^0)^{-1} restricted to the touching-panel pattern of every row (the panel itself, its
+ * edge neighbours, then its vertex neighbours by centroid distance; at most HB_PC_SLOTS), used as
+ * the block-diagonal right preconditioner diag(M, ..., M) of GMRES.  Its weights are predicted
+ * per row by a 3-layer MLP from local data only (near-field V^0 entries and geometry) and
+ * trained to minimise the row residual ||(M V^0)_l - e_l||^2 (a sparse approximate inverse).
+ * This goes beyond the paper, whose solver is FGMRES without such a preconditioner (Sec. 6.1). */
+#define HB_PC_SLOTS 16
+#define HB_PC_SLOT_FEATURES 8
+#define HB_PC_FEATURES (HB_PC_SLOTS * HB_PC_SLOT_FEATURES + 4)
+
+typedef struct hb_mlp_dims {
+  int32_t n_in, n_hidden, n_out; /* dense layers n_in -> n_hidden -> n_hidden -> n_out, tanh */
+} hb_mlp_dims;
+
+/* Row pattern: cols [E_x][HB_PC_SLOTS] int32 (panel indices, -1 = empty slot) and, if not NULL,
+ * cls [E_x][HB_PC_SLOTS] int8 (3 itself, 2 edge, 1 vertex neighbour).  Device pointers. */
+int hb_precond_pattern(hb_ctx *ctx, int32_t *cols, int8_t *cls, void *stream);
+
+/* Row features [E_x][HB_PC_FEATURES] float (device).  Per slot: V^0[l,m]/V^0[l,l], class one-hot
+ * (3), centroid distance / sqrt(area_l), area_m / area_l, n_l . n_m, present; then
+ * sqrt(alpha h / area_l), its log, slot count / HB_PC_SLOTS, 1.  Needs V assembled. */
+int hb_precond_features(hb_ctx *ctx, float *feats, void *stream);
+
+/* Training data of the sparse approximate inverse, per row l, in the scaled unknowns
+ * y = V^0[l,l] M[l, J]:  ||(M V^0)_l - e_l||^2 = y^T G y - 2 a^T y + 1 with
+ * gram [E_x][S][S] = G and rhs [E_x][S] = a (device float, S = HB_PC_SLOTS); weights [E_x][S]
+ * (may be NULL) receives the exact minimiser G^{-1} a.  Uses full rows of V^0. */
+int hb_precond_spai(hb_ctx *ctx, float *gram, float *rhs, float *weights, void *stream);
+
+/* Install the preconditioner from scaled weights [E_x][HB_PC_SLOTS] (device float):
+ * M[l, cols[l][s]] = weights[l][s] / V^0[l,l].  weights = NULL uninstalls. */
+int hb_precond_set(hb_ctx *ctx, const float *weights, void *stream);
+
+/* MLP parameter count and forward / backward workspace size (floats) for a batch. Parameters
+ * are one float array: W1 [H][I], b1 [H], W2 [H][H], b2 [H], W3 [O][H], b3 [O]. */
+int64_t hb_mlp_num_params(const hb_mlp_dims *dims);
+int64_t hb_mlp_work_floats(const hb_mlp_dims *dims, int64_t batch);
+
+/* y [batch][O] = MLP(x [batch][I]); work keeps the activations for hb_mlp_backward.  Device. */
+int hb_mlp_forward(const hb_mlp_dims *dims, const float *params, const float *x, int64_t batch,
+                   float *y, float *work, void *stream);
+
+/* grads (same layout as params) of sum over the batch of dy . y, given the work of the matching
+ * hb_mlp_forward call.  Device pointers. */
+int hb_mlp_backward(const hb_mlp_dims *dims, const float *params, const float *x, int64_t batch,
+                    const float *work, const float *dy, float *grads, void *stream);
+
+/* Loss of hb_precond_spai's quadratic form per row (rowloss, may be NULL) and the gradient of
+ * its batch mean w.r.t. y (dy, may be NULL).  y, gram, rhs as above, rows entries.  Device. */
+int hb_precond_loss(const float *y, const float *gram, const float *rhs, int64_t rows, float *dy,
+                    float *rowloss, void *stream);
+
+/* One Adam step p -= lr mhat / (sqrt(vhat) + eps) on n floats (step counts from 1).  Device. */
+int hb_adam_step(float *params, const float *grads, float *m, float *v, int64_t n, float lr,
+                 float beta1, float beta2, float eps, int32_t step, void *stream);
 
 /* Durations in milliseconds of the kernels of the last hb_assemble on this context, measured
  * with HIP events on the caller's stream: [0] separated-pair kernel, [1] touching-pair kernels,

@@ -18,9 +18,15 @@ HB_PREC_FP64, HB_PREC_MIXED = 0, 1
 HB_DTYPE_F64, HB_DTYPE_F32 = 0, 1
 HB_SOLVE_GMRES, HB_SOLVE_TIMEMARCH, HB_SOLVE_MIXED_IR = 0, 1, 2
 
-EXPORTED = ["hb_default_options", "hb_check_mesh", "hb_create", "hb_destroy", "hb_last_error",
-            "hb_sizes", "hb_assemble", "hb_get_blocks", "hb_apply", "hb_rhs_dirichlet",
-            "hb_solve", "hb_eval_repr", "hb_last_assembly_ms"]
+EXPORTED = sorted(["hb_default_options", "hb_check_mesh", "hb_create", "hb_destroy",
+                   "hb_last_error", "hb_sizes", "hb_assemble", "hb_get_blocks", "hb_apply",
+                   "hb_rhs_dirichlet", "hb_solve", "hb_eval_repr", "hb_last_assembly_ms",
+                   "hb_precond_pattern", "hb_precond_features", "hb_precond_spai",
+                   "hb_precond_set", "hb_mlp_num_params", "hb_mlp_work_floats", "hb_mlp_forward",
+                   "hb_mlp_backward", "hb_precond_loss", "hb_adam_step"])
+HB_PC_SLOTS = 16
+HB_PC_SLOT_FEATURES = 8
+HB_PC_FEATURES = HB_PC_SLOTS * HB_PC_SLOT_FEATURES + 4
 
 
 class HBError(RuntimeError):
@@ -37,7 +43,11 @@ class Options(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class MLPDims(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("n_out", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -74,6 +84,20 @@ def lib():
     L.hb_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     L.hb_eval_repr.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
     L.hb_last_assembly_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.hb_precond_pattern.argtypes = [vp, vp, vp, vp]
+    L.hb_precond_features.argtypes = [vp, vp, vp]
+    L.hb_precond_spai.argtypes = [vp, vp, vp, vp, vp]
+    L.hb_precond_set.argtypes = [vp, vp, vp]
+    pd = ctypes.POINTER(MLPDims)
+    L.hb_mlp_num_params.argtypes = [pd]
+    L.hb_mlp_num_params.restype = i64
+    L.hb_mlp_work_floats.argtypes = [pd, i64]
+    L.hb_mlp_work_floats.restype = i64
+    L.hb_mlp_forward.argtypes = [pd, vp, vp, i64, vp, vp, vp]
+    L.hb_mlp_backward.argtypes = [pd, vp, vp, i64, vp, vp, vp, vp]
+    L.hb_precond_loss.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.hb_adam_step.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, i32, vp]
     for name in EXPORTED:
         fn = getattr(L, name)
         if fn.restype is ctypes.c_int:   # default restype
@@ -198,12 +222,13 @@ class Context:
         self._check(lib().hb_rhs_dirichlet(self._h, _ptr(g), _ptr(b), _stream(stream)))
         return b
 
-    def solve(self, b, method=HB_SOLVE_GMRES, tol=1e-8, max_iter=500, w=None, stream=None):
+    def solve(self, b, method=HB_SOLVE_GMRES, tol=1e-8, max_iter=500, w=None, precond=False,
+              stream=None):
         import torch
         if w is None:
             w = torch.empty((self.n_t, self.n_tris), dtype=torch.float64, device="cuda")
         o = SolveOpts()
-        o.method, o.tol, o.max_iter = method, tol, max_iter
+        o.method, o.tol, o.max_iter, o.precond = method, tol, max_iter, int(bool(precond))
         info = SolveInfo()
         rc = lib().hb_solve(self._h, _ptr(b), _ptr(w), ctypes.byref(o), ctypes.byref(info), _stream(stream))
         if rc not in (HB_OK, HB_ENOCONV):
@@ -211,6 +236,33 @@ class Context:
         return w, {"iterations": info.iterations, "rel_residual": info.rel_residual,
                    "seconds": info.seconds, "refinements": info.refinements,
                    "converged": rc == HB_OK}
+
+    # ---- learned preconditioner ----
+    def precond_pattern(self, stream=None):
+        import torch
+        cols = torch.empty((self.n_tris, HB_PC_SLOTS), dtype=torch.int32, device="cuda")
+        cls = torch.empty((self.n_tris, HB_PC_SLOTS), dtype=torch.int8, device="cuda")
+        self._check(lib().hb_precond_pattern(self._h, _ptr(cols), _ptr(cls), _stream(stream)))
+        return cols, cls
+
+    def precond_features(self, stream=None):
+        import torch
+        f = torch.empty((self.n_tris, HB_PC_FEATURES), dtype=torch.float32, device="cuda")
+        self._check(lib().hb_precond_features(self._h, _ptr(f), _stream(stream)))
+        return f
+
+    def precond_spai(self, exact=True, stream=None):
+        import torch
+        G = torch.empty((self.n_tris, HB_PC_SLOTS, HB_PC_SLOTS), dtype=torch.float32, device="cuda")
+        a = torch.empty((self.n_tris, HB_PC_SLOTS), dtype=torch.float32, device="cuda")
+        y = torch.empty_like(a) if exact else None
+        self._check(lib().hb_precond_spai(self._h, _ptr(G), _ptr(a), _ptr(y) if exact else None,
+                                          _stream(stream)))
+        return G, a, y
+
+    def precond_set(self, weights, stream=None):
+        self._check(lib().hb_precond_set(self._h, _ptr(weights) if weights is not None else None,
+                                         _stream(stream)))
 
     def eval_repr(self, pts, w, g, stream=None, parts=False):
         import torch

@@ -443,6 +443,34 @@ int build_tables(hb_ctx *c) {
   if (!c->touch.empty())
     if ((rc = upload(c, (void **)&c->d_touch, c->touch.data(), c->touch.size() * sizeof(TouchPair))))
       return rc;
+  // preconditioner pattern: itself, edge neighbours, vertex neighbours by centroid distance
+  {
+    std::vector<double> cent(3 * ne);
+    for (size_t t = 0; t < ne; ++t)
+      for (int k = 0; k < 3; ++k)
+        cent[3 * t + k] = (c->verts[3 * c->tris[3 * t] + k] + c->verts[3 * c->tris[3 * t + 1] + k] +
+                           c->verts[3 * c->tris[3 * t + 2] + k]) / 3.0;
+    std::vector<std::vector<std::pair<double, int>>> nb(ne);
+    std::vector<std::vector<int8_t>> nbc(ne);
+    for (const auto &tp : c->touch) {
+      double d2 = 0;
+      for (int k = 0; k < 3; ++k) d2 += (cent[3 * tp.l + k] - cent[3 * tp.m + k]) * (cent[3 * tp.l + k] - cent[3 * tp.m + k]);
+      // sort key: class first (3, 2, 1), then distance
+      nb[tp.l].push_back({(3 - tp.cls) * 1e30 + d2, tp.m});
+    }
+    std::vector<int32_t> cols(ne * HB_PC_SLOTS, -1);
+    std::vector<int8_t> clsv(ne * HB_PC_SLOTS, 0);
+    for (size_t l = 0; l < ne; ++l) {
+      std::sort(nb[l].begin(), nb[l].end());
+      for (size_t s2 = 0; s2 < nb[l].size() && s2 < (size_t)HB_PC_SLOTS; ++s2) {
+        cols[l * HB_PC_SLOTS + s2] = nb[l][s2].second;
+        clsv[l * HB_PC_SLOTS + s2] = (int8_t)(3 - (int)(nb[l][s2].first / 1e30));
+      }
+    }
+    if ((rc = upload(c, (void **)&c->d_pc_cols, cols.data(), cols.size() * sizeof(int32_t)))) return rc;
+    if ((rc = upload(c, (void **)&c->d_pc_cls, clsv.data(), clsv.size()))) return rc;
+    if ((rc = upload(c, (void **)&c->d_cent, cent.data(), cent.size() * sizeof(double)))) return rc;
+  }
   // regularised rules
   for (int cls = 1; cls <= 3; ++cls) {
     std::vector<SSNode> nodes;
@@ -548,7 +576,8 @@ void hb_destroy(hb_ctx *c) {
   (void)hipDeviceSynchronize();
   void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_taylor,
                   c->d_taylor32, c->d_V32, c->d_tscale, c->d_mass,
-                  c->d_V, c->d_K, c->d_work, c->d_v0inv, c->d_apply, c->d_ir, c->ss[1].d, c->ss[2].d, c->ss[3].d};
+                  c->d_V, c->d_K, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
+                  c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->ss[1].d, c->ss[2].d, c->ss[3].d};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int i = 0; i < 4; ++i)
@@ -601,6 +630,7 @@ int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
   if (p.do_V) {
     c->have_V = true;
     c->V32_valid = false;
+    c->pc_active = false;  // M was scaled by the previous V^0
   }
   if (p.do_K) c->have_K = true;
   c->timed = true;

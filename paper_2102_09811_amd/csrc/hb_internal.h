@@ -79,6 +79,8 @@ void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const Tou
 // y = A x for the block-Toeplitz operator with blocks [nt][R][C] (y overwritten, time-major)
 int toeplitz_apply(hb_ctx *c, const void *blocks, int R, int C, const double *x, double *y,
                    hipStream_t s);
+// z = diag(M, ..., M) q with the installed sparse approximate inverse
+int precond_apply(hb_ctx *c, const double *q, double *z, hipStream_t s);
 // same product with float blocks on the float MFMA path (float accumulation)
 int toeplitz_apply32(hb_ctx *c, const float *blocks, int R, int C, const double *x, double *y,
                      hipStream_t s);
@@ -120,6 +122,12 @@ struct hb_ctx {
   double *d_work = nullptr;
   size_t work_bytes = 0;
   double *d_v0inv = nullptr;         // inverse of V^0 (time marching)
+  // learned preconditioner: row pattern, centroids, installed weights
+  int32_t *d_pc_cols = nullptr;      // [ne][HB_PC_SLOTS]
+  int8_t *d_pc_cls = nullptr;
+  double *d_cent = nullptr;          // [ne][3]
+  double *d_pc_M = nullptr;          // [ne][HB_PC_SLOTS]
+  bool pc_active = false;
   double *d_ir = nullptr;            // iterative refinement: x, r, correction
   size_t ir_bytes = 0;
   double *d_apply = nullptr;         // per-group partial results of the Toeplitz apply

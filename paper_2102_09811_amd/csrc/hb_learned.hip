@@ -1,0 +1,531 @@
+// Learned preconditioner for V_h w = b: a sparse approximate inverse M ~ (V_h^0)^{-1} on the
+// touching-panel pattern of every row, predicted by a small MLP from local data, applied as a
+// block-diagonal right preconditioner (the same M in every time step).
+//
+// Kernels: the row pattern and its features, the per-row normal equations of the sparse
+// approximate inverse (training data), a 3-layer tanh MLP (forward, backward, Adam), the
+// quadratic training loss, installation of M and its application.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "hb_internal.h"
+
+namespace hb {
+namespace {
+
+#define HB_CHECK_L(ctx, call)                                                             \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      if (ctx) (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);            \
+      return e_ == hipErrorOutOfMemory ? HB_ENOMEM : HB_EHIP;                             \
+    }                                                                                     \
+  } while (0)
+
+constexpr int S = HB_PC_SLOTS;  // pattern slots per row
+
+inline int grid_for(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 8192); }
+
+// ---------------------------------------------------------------------------------------------
+// Features of row l (HB_PC_FEATURES floats): per slot s (HB_PC_SLOT_FEATURES each)
+//   V^0[l, m_s] / V^0[l, l], one-hot of the pair class (identical, edge, vertex),
+//   |c_l - c_m| / sqrt(area_l), area_m / area_l, n_l . n_m, slot present;
+// then sqrt(alpha h / area_l), log of it, (number of slots) / S, 1.
+// ---------------------------------------------------------------------------------------------
+template <typename TV>
+__global__ void k_features(const TV *__restrict__ V0, const int32_t *__restrict__ cols,
+                           const int8_t *__restrict__ cls, const double *__restrict__ cent,
+                           const double *__restrict__ geom, int ne, double alpha_h,
+                           float *__restrict__ feats) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= ne) return;
+  const double al = geom[24 * ne + l];
+  const double diag = (double)V0[(size_t)l * ne + l];
+  float *f = feats + (size_t)l * HB_PC_FEATURES;
+  int cnt = 0;
+  for (int s = 0; s < S; ++s) {
+    const int m = cols[l * S + s];
+    float *g = f + s * HB_PC_SLOT_FEATURES;
+    if (m < 0) {
+      for (int q = 0; q < HB_PC_SLOT_FEATURES; ++q) g[q] = 0.0f;
+      continue;
+    }
+    ++cnt;
+    const int c = cls[l * S + s];
+    const double dx = cent[3 * l] - cent[3 * m], dy = cent[3 * l + 1] - cent[3 * m + 1],
+                 dz = cent[3 * l + 2] - cent[3 * m + 2];
+    g[0] = (float)((double)V0[(size_t)l * ne + m] / diag);
+    g[1] = c == 3 ? 1.0f : 0.0f;
+    g[2] = c == 2 ? 1.0f : 0.0f;
+    g[3] = c == 1 ? 1.0f : 0.0f;
+    g[4] = (float)(sqrt(dx * dx + dy * dy + dz * dz) / sqrt(al));
+    g[5] = (float)(geom[24 * ne + m] / al);
+    g[6] = (float)(geom[21 * ne + l] * geom[21 * ne + m] + geom[22 * ne + l] * geom[22 * ne + m] +
+                   geom[23 * ne + l] * geom[23 * ne + m]);
+    g[7] = 1.0f;
+  }
+  const double hl = sqrt(alpha_h / al);
+  f[S * HB_PC_SLOT_FEATURES + 0] = (float)hl;
+  f[S * HB_PC_SLOT_FEATURES + 1] = (float)log(hl);
+  f[S * HB_PC_SLOT_FEATURES + 2] = (float)cnt / S;
+  f[S * HB_PC_SLOT_FEATURES + 3] = 1.0f;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Normal equations of the sparse approximate inverse of row l: with J = pattern of l and the
+// scaled unknowns y = V^0[l,l] m (row l of M is m on J),
+//   || m^T V^0[J, :] - e_l^T ||^2 = y^T G y - 2 a^T y + 1,
+//   G[s][t] = sum_j V^0[J_s, j] V^0[J_t, j] / V^0[l,l]^2,  a[s] = V^0[J_s, l] / V^0[l,l].
+// Absent slots get G = identity, a = 0.  One workgroup per row; rows staged in LDS.  Also
+// solves G y = a (the exact minimiser) by Cholesky when y_out is given.
+// ---------------------------------------------------------------------------------------------
+template <typename TV>
+__global__ __launch_bounds__(256) void k_spai_rows(const TV *__restrict__ V0,
+                                                   const int32_t *__restrict__ cols, int ne,
+                                                   float *__restrict__ gram, float *__restrict__ rhs,
+                                                   float *__restrict__ y_out) {
+  const int l = blockIdx.x;
+  const int tid = threadIdx.x;
+  constexpr int CH = 256;
+  __shared__ double rows[S][CH];
+  __shared__ double G[S][S + 1];
+  __shared__ double a[S];
+  __shared__ int J[S];
+  if (tid < S) J[tid] = cols[l * S + tid];
+  __syncthreads();
+  // pair (s, t) with s <= t handled by thread tid < 136
+  int ps = 0, pt = 0;
+  {
+    int idx = tid, s = 0;
+    while (s < S && idx >= S - s) { idx -= S - s; ++s; }
+    ps = s;
+    pt = s + idx;
+  }
+  const bool owner = tid < S * (S + 1) / 2;
+  double acc = 0.0;
+  for (int j0 = 0; j0 < ne; j0 += CH) {
+    for (int e = tid; e < S * CH; e += 256) {
+      const int s = e / CH, j = j0 + e % CH;
+      const int m = J[s];
+      rows[s][e % CH] = (m >= 0 && j < ne) ? (double)V0[(size_t)m * ne + j] : 0.0;
+    }
+    __syncthreads();
+    if (owner)
+      for (int j = 0; j < CH; ++j) acc = fma(rows[ps][j], rows[pt][j], acc);
+    __syncthreads();
+  }
+  const double diag = (double)V0[(size_t)l * ne + l];
+  const double inv2 = 1.0 / (diag * diag);
+  if (owner) {
+    double v = acc * inv2;
+    if (J[ps] < 0 || J[pt] < 0) v = (ps == pt) ? 1.0 : 0.0;
+    G[ps][pt] = v;
+    G[pt][ps] = v;
+  }
+  if (tid < S) a[tid] = J[tid] >= 0 ? (double)V0[(size_t)J[tid] * ne + l] / diag : 0.0;
+  __syncthreads();
+  if (tid < S * S) gram[(size_t)l * S * S + tid] = (float)G[tid / S][tid % S];
+  if (tid < S) rhs[(size_t)l * S + tid] = (float)a[tid];
+  if (y_out && tid == 0) {
+    // Cholesky of G in place (lower), then two triangular solves
+    double Lm[S][S];
+    for (int i = 0; i < S; ++i)
+      for (int k = 0; k <= i; ++k) {
+        double sum = G[i][k];
+        for (int q = 0; q < k; ++q) sum -= Lm[i][q] * Lm[k][q];
+        Lm[i][k] = (i == k) ? sqrt(fmax(sum, 1e-300)) : sum / Lm[k][k];
+      }
+    double z[S];
+    for (int i = 0; i < S; ++i) {
+      double sum = a[i];
+      for (int q = 0; q < i; ++q) sum -= Lm[i][q] * z[q];
+      z[i] = sum / Lm[i][i];
+    }
+    for (int i = S - 1; i >= 0; --i) {
+      double sum = z[i];
+      for (int q = i + 1; q < S; ++q) sum -= Lm[q][i] * z[q];
+      z[i] = sum / Lm[i][i];
+    }
+    for (int i = 0; i < S; ++i) y_out[(size_t)l * S + i] = J[i] >= 0 ? (float)z[i] : 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Dense layers.  Row-major activations X [B][n_in]; weights W [n_out][n_in]; tiles 64 x 64 with
+// LDS staging of 16-wide k slices, 4 x 4 outputs per thread.
+//   mode 0: Y = X W^T + b          (forward, optional tanh)
+//   k_gemm_tn: dW += dY^T X        (weight gradient, [n_out][n_in])
+//   k_gemm_nn: dX = dY W           ([B][n_in])
+// ---------------------------------------------------------------------------------------------
+constexpr int GT = 64, GK = 16;
+
+__global__ __launch_bounds__(256) void k_dense_fwd(const float *__restrict__ X, const float *__restrict__ W,
+                                                   const float *__restrict__ bias, float *__restrict__ Z,
+                                                   float *__restrict__ H, int B, int nin, int nout,
+                                                   int act) {
+  const int b0 = blockIdx.x * GT, o0 = blockIdx.y * GT;
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  __shared__ float Xs[GK][GT + 1], Ws[GK][GT + 1];
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < nin; k0 += GK) {
+    for (int e = tid; e < GT * GK; e += 256) {
+      const int r = e / GK, k = e % GK;
+      Xs[k][r] = (b0 + r < B && k0 + k < nin) ? X[(size_t)(b0 + r) * nin + k0 + k] : 0.0f;
+      Ws[k][r] = (o0 + r < nout && k0 + k < nin) ? W[(size_t)(o0 + r) * nin + k0 + k] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < GK; ++k) {
+      float xa[4], wb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xa[i] = Xs[k][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) wb[j] = Ws[k][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(xa[i], wb[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int b = b0 + ty * 4 + i;
+    if (b >= B) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = o0 + tx * 4 + j;
+      if (o >= nout) continue;
+      const float z = acc[i][j] + bias[o];
+      Z[(size_t)b * nout + o] = z;
+      if (H) H[(size_t)b * nout + o] = act ? tanhf(z) : z;
+    }
+  }
+}
+
+// dW[o][i] (+)= sum_b dY[b][o] X[b][i]; grid over (o tiles, i tiles)
+__global__ __launch_bounds__(256) void k_gemm_tn(const float *__restrict__ dY, const float *__restrict__ X,
+                                                 float *__restrict__ dW, int B, int nout, int nin) {
+  const int o0 = blockIdx.x * GT, i0 = blockIdx.y * GT;
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  __shared__ float Ds[GK][GT + 1], Xs[GK][GT + 1];
+  float acc[4][4] = {};
+  for (int b0 = 0; b0 < B; b0 += GK) {
+    for (int e = tid; e < GT * GK; e += 256) {
+      const int r = e % GT, k = e / GT;
+      Ds[k][r] = (b0 + k < B && o0 + r < nout) ? dY[(size_t)(b0 + k) * nout + o0 + r] : 0.0f;
+      Xs[k][r] = (b0 + k < B && i0 + r < nin) ? X[(size_t)(b0 + k) * nin + i0 + r] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < GK; ++k) {
+      float da[4], xb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) da[i] = Ds[k][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xb[j] = Xs[k][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(da[i], xb[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int o = o0 + ty * 4 + i;
+    if (o >= nout) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = i0 + tx * 4 + j;
+      if (c < nin) dW[(size_t)o * nin + c] = acc[i][j];
+    }
+  }
+}
+
+// dX[b][i] = sum_o dY[b][o] W[o][i], then (act) dX *= 1 - H^2 (H = tanh of that layer's input)
+__global__ __launch_bounds__(256) void k_gemm_nn(const float *__restrict__ dY, const float *__restrict__ W,
+                                                 const float *__restrict__ Hin, float *__restrict__ dX,
+                                                 int B, int nout, int nin, int act) {
+  const int b0 = blockIdx.x * GT, i0 = blockIdx.y * GT;
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  __shared__ float Ds[GK][GT + 1], Wsm[GK][GT + 1];
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < nout; k0 += GK) {
+    for (int e = tid; e < GT * GK; e += 256) {
+      const int r = e / GK, k = e % GK;
+      Ds[k][r] = (b0 + r < B && k0 + k < nout) ? dY[(size_t)(b0 + r) * nout + k0 + k] : 0.0f;
+    }
+    for (int e = tid; e < GT * GK; e += 256) {
+      const int r = e % GT, k = e / GT;
+      Wsm[k][r] = (k0 + k < nout && i0 + r < nin) ? W[(size_t)(k0 + k) * nin + i0 + r] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < GK; ++k) {
+      float da[4], wb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) da[i] = Ds[k][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) wb[j] = Wsm[k][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(da[i], wb[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int b = b0 + ty * 4 + i;
+    if (b >= B) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = i0 + tx * 4 + j;
+      if (c >= nin) continue;
+      float v = acc[i][j];
+      if (act) {
+        const float h = Hin[(size_t)b * nin + c];
+        v *= 1.0f - h * h;
+      }
+      dX[(size_t)b * nin + c] = v;
+    }
+  }
+}
+
+// db[o] = sum_b dY[b][o]
+__global__ void k_colsum(const float *__restrict__ dY, int B, int n, float *__restrict__ db) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  float s = 0.0f;
+  for (int b = 0; b < B; ++b) s += dY[(size_t)b * n + o];
+  db[o] = s;
+}
+
+// Quadratic loss per row: L_b = y^T G y - 2 a^T y + 1; dL/dy = 2 (G y - a) / B (mean over rows)
+__global__ void k_quadloss(const float *__restrict__ Y, const float *__restrict__ G,
+                           const float *__restrict__ a, int B, float *__restrict__ dY,
+                           float *__restrict__ rowloss) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const float *y = Y + (size_t)b * S;
+  const float *g = G + (size_t)b * S * S;
+  const float *r = a + (size_t)b * S;
+  double L = 1.0;
+  for (int s = 0; s < S; ++s) {
+    double gy = 0.0;
+    for (int t = 0; t < S; ++t) gy += (double)g[s * S + t] * y[t];
+    L += (double)y[s] * gy - 2.0 * (double)r[s] * y[s];
+    if (dY) dY[(size_t)b * S + s] = (float)(2.0 * (gy - r[s]) / B);
+  }
+  if (rowloss) rowloss[b] = (float)L;
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, size_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// M[l][s] = y[l][s] / V^0[l,l] (double)
+template <typename TV>
+__global__ void k_install(const TV *__restrict__ V0, const float *__restrict__ y, int ne,
+                          double *__restrict__ M) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ne * S) return;
+  const int l = i / S;
+  M[i] = (double)y[i] / (double)V0[(size_t)l * ne + l];
+}
+
+}  // namespace
+
+// z[k][l] = sum_s M[l][s] q[k][cols[l][s]] for every time step k
+__global__ void k_precond_apply(const double *__restrict__ M, const int32_t *__restrict__ cols,
+                                const double *__restrict__ q, double *__restrict__ z, int nt,
+                                int ne) {
+  const size_t n = (size_t)nt * ne;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i / ne), l = (int)(i % ne);
+    const double *qk = q + (size_t)k * ne;
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < HB_PC_SLOTS; ++t) {
+      const int m = cols[l * HB_PC_SLOTS + t];
+      if (m >= 0) s = fma(M[l * HB_PC_SLOTS + t], qk[m], s);
+    }
+    z[i] = s;
+  }
+}
+
+int precond_apply(hb_ctx *c, const double *q, double *z, hipStream_t s) {
+  const size_t n = (size_t)c->nt * c->ne;
+  hipLaunchKernelGGL(k_precond_apply, dim3(grid_for(n)), dim3(256), 0, s, c->d_pc_M, c->d_pc_cols,
+                     q, z, c->nt, (int)c->ne);
+  HB_CHECK_L(c, hipGetLastError());
+  return HB_OK;
+}
+
+}  // namespace hb
+
+using namespace hb;
+
+namespace {
+int lfail(hb_ctx *c, int code, const std::string &m) {
+  if (c) c->err = m;
+  return code;
+}
+
+size_t mlp_nparams(const hb_mlp_dims *d) {
+  return (size_t)d->n_hidden * d->n_in + d->n_hidden + (size_t)d->n_hidden * d->n_hidden +
+         d->n_hidden + (size_t)d->n_out * d->n_hidden + d->n_out;
+}
+
+bool dims_ok(const hb_mlp_dims *d) {
+  return d && d->n_in > 0 && d->n_hidden > 0 && d->n_out > 0 && d->n_in <= 4096 &&
+         d->n_hidden <= 4096 && d->n_out <= 4096;
+}
+}  // namespace
+
+extern "C" {
+
+int64_t hb_mlp_num_params(const hb_mlp_dims *d) { return dims_ok(d) ? (int64_t)mlp_nparams(d) : -1; }
+
+int64_t hb_mlp_work_floats(const hb_mlp_dims *d, int64_t batch) {
+  if (!dims_ok(d) || batch <= 0) return -1;
+  return batch * (4 * (int64_t)d->n_hidden + d->n_out) + batch * 2 * (int64_t)d->n_hidden;
+}
+
+int hb_precond_pattern(hb_ctx *c, int32_t *cols, int8_t *cls, void *stream) {
+  if (!c || !cols) return lfail(c, HB_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  HB_CHECK_L(c, hipMemcpyAsync(cols, c->d_pc_cols, sizeof(int32_t) * c->ne * HB_PC_SLOTS,
+                               hipMemcpyDeviceToDevice, s));
+  if (cls)
+    HB_CHECK_L(c, hipMemcpyAsync(cls, c->d_pc_cls, c->ne * HB_PC_SLOTS, hipMemcpyDeviceToDevice, s));
+  return HB_OK;
+}
+
+int hb_precond_features(hb_ctx *c, float *feats, void *stream) {
+  if (!c || !feats) return lfail(c, HB_EINVAL, "null argument");
+  if (!c->have_V) return lfail(c, HB_ESTATE, "V not assembled");
+  hipStream_t s = (hipStream_t)stream;
+  const int ne = (int)c->ne;
+  if (c->storage_f32)
+    hipLaunchKernelGGL(k_features<float>, dim3((ne + 255) / 256), dim3(256), 0, s, (const float *)c->d_V,
+                       c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_geom, ne, c->alpha * c->h, feats);
+  else
+    hipLaunchKernelGGL(k_features<double>, dim3((ne + 255) / 256), dim3(256), 0, s, (const double *)c->d_V,
+                       c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_geom, ne, c->alpha * c->h, feats);
+  HB_CHECK_L(c, hipGetLastError());
+  return HB_OK;
+}
+
+int hb_precond_spai(hb_ctx *c, float *gram, float *rhs, float *weights, void *stream) {
+  if (!c || !gram || !rhs) return lfail(c, HB_EINVAL, "null argument");
+  if (!c->have_V) return lfail(c, HB_ESTATE, "V not assembled");
+  hipStream_t s = (hipStream_t)stream;
+  const int ne = (int)c->ne;
+  if (c->storage_f32)
+    hipLaunchKernelGGL(k_spai_rows<float>, dim3(ne), dim3(256), 0, s, (const float *)c->d_V, c->d_pc_cols,
+                       ne, gram, rhs, weights);
+  else
+    hipLaunchKernelGGL(k_spai_rows<double>, dim3(ne), dim3(256), 0, s, (const double *)c->d_V, c->d_pc_cols,
+                       ne, gram, rhs, weights);
+  HB_CHECK_L(c, hipGetLastError());
+  return HB_OK;
+}
+
+int hb_precond_set(hb_ctx *c, const float *weights, void *stream) {
+  if (!c) return lfail(c, HB_EINVAL, "null context");
+  if (!weights) {
+    c->pc_active = false;
+    return HB_OK;
+  }
+  if (!c->have_V) return lfail(c, HB_ESTATE, "V not assembled");
+  hipStream_t s = (hipStream_t)stream;
+  const int ne = (int)c->ne;
+  if (!c->d_pc_M) HB_CHECK_L(c, hipMalloc(&c->d_pc_M, sizeof(double) * ne * HB_PC_SLOTS));
+  const int n = ne * HB_PC_SLOTS;
+  if (c->storage_f32)
+    hipLaunchKernelGGL(k_install<float>, dim3((n + 255) / 256), dim3(256), 0, s, (const float *)c->d_V,
+                       weights, ne, c->d_pc_M);
+  else
+    hipLaunchKernelGGL(k_install<double>, dim3((n + 255) / 256), dim3(256), 0, s, (const double *)c->d_V,
+                       weights, ne, c->d_pc_M);
+  HB_CHECK_L(c, hipGetLastError());
+  c->pc_active = true;
+  return HB_OK;
+}
+
+int hb_mlp_forward(const hb_mlp_dims *d, const float *params, const float *x, int64_t batch,
+                   float *y, float *work, void *stream) {
+  if (!dims_ok(d) || !params || !x || !y || !work || batch <= 0 || batch > (1 << 26)) return HB_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int B = (int)batch, I = d->n_in, H = d->n_hidden, O = d->n_out;
+  const float *W1 = params, *b1 = W1 + (size_t)H * I, *W2 = b1 + H, *b2 = W2 + (size_t)H * H;
+  const float *W3 = b2 + H, *b3 = W3 + (size_t)O * H;
+  float *Z1 = work, *H1 = Z1 + (size_t)B * H, *Z2 = H1 + (size_t)B * H, *H2 = Z2 + (size_t)B * H;
+  float *Z3 = H2 + (size_t)B * H;
+  dim3 g1((B + GT - 1) / GT, (H + GT - 1) / GT), g3((B + GT - 1) / GT, (O + GT - 1) / GT);
+  hipLaunchKernelGGL(k_dense_fwd, g1, dim3(256), 0, s, x, W1, b1, Z1, H1, B, I, H, 1);
+  hipLaunchKernelGGL(k_dense_fwd, g1, dim3(256), 0, s, H1, W2, b2, Z2, H2, B, H, H, 1);
+  hipLaunchKernelGGL(k_dense_fwd, g3, dim3(256), 0, s, H2, W3, b3, Z3, y, B, H, O, 0);
+  return hipGetLastError() == hipSuccess ? HB_OK : HB_EHIP;
+}
+
+int hb_mlp_backward(const hb_mlp_dims *d, const float *params, const float *x, int64_t batch,
+                    const float *work, const float *dy, float *grads, void *stream) {
+  if (!dims_ok(d) || !params || !x || !dy || !grads || !work || batch <= 0 || batch > (1 << 26))
+    return HB_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int B = (int)batch, I = d->n_in, H = d->n_hidden, O = d->n_out;
+  const float *W2 = params + (size_t)H * I + H, *W3 = W2 + (size_t)H * H + H;
+  const float *H1 = work + (size_t)B * H, *H2 = work + (size_t)3 * B * H;
+  float *dW1 = grads, *db1 = dW1 + (size_t)H * I, *dW2 = db1 + H, *db2 = dW2 + (size_t)H * H;
+  float *dW3 = db2 + H, *db3 = dW3 + (size_t)O * H;
+  float *dZ2 = (float *)work + (size_t)B * (4 * H + O), *dZ1 = dZ2 + (size_t)B * H;
+  // layer 3 (linear): dW3 = dy^T H2, db3 = sum dy, dZ2 = (dy W3) * (1 - H2^2)
+  hipLaunchKernelGGL(k_gemm_tn, dim3((O + GT - 1) / GT, (H + GT - 1) / GT), dim3(256), 0, s, dy, H2, dW3, B, O, H);
+  hipLaunchKernelGGL(k_colsum, dim3((O + 255) / 256), dim3(256), 0, s, dy, B, O, db3);
+  hipLaunchKernelGGL(k_gemm_nn, dim3((B + GT - 1) / GT, (H + GT - 1) / GT), dim3(256), 0, s, dy, W3, H2, dZ2, B, O, H, 1);
+  // layer 2
+  hipLaunchKernelGGL(k_gemm_tn, dim3((H + GT - 1) / GT, (H + GT - 1) / GT), dim3(256), 0, s, dZ2, H1, dW2, B, H, H);
+  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, dZ2, B, H, db2);
+  hipLaunchKernelGGL(k_gemm_nn, dim3((B + GT - 1) / GT, (H + GT - 1) / GT), dim3(256), 0, s, dZ2, W2, H1, dZ1, B, H, H, 1);
+  // layer 1
+  hipLaunchKernelGGL(k_gemm_tn, dim3((H + GT - 1) / GT, (I + GT - 1) / GT), dim3(256), 0, s, dZ1, x, dW1, B, H, I);
+  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, dZ1, B, H, db1);
+  return hipGetLastError() == hipSuccess ? HB_OK : HB_EHIP;
+}
+
+int hb_precond_loss(const float *y, const float *gram, const float *rhs, int64_t rows, float *dy,
+                    float *rowloss, void *stream) {
+  if (!y || !gram || !rhs || rows <= 0 || rows > (1 << 26)) return HB_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_quadloss, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, y, gram, rhs,
+                     (int)rows, dy, rowloss);
+  return hipGetLastError() == hipSuccess ? HB_OK : HB_EHIP;
+}
+
+int hb_adam_step(float *params, const float *grads, float *m, float *v, int64_t n, float lr,
+                 float beta1, float beta2, float eps, int32_t step, void *stream) {
+  if (!params || !grads || !m || !v || n <= 0 || step < 1) return HB_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(grid_for((size_t)n)), dim3(256), 0, s, params, grads, m, v, (size_t)n, lr,
+                     beta1, beta2, eps, c1, c2);
+  return hipGetLastError() == hipSuccess ? HB_OK : HB_EHIP;
+}
+
+}  // extern "C"

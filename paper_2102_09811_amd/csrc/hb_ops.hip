@@ -615,14 +615,14 @@ int ensure_V32(hb_ctx *c, hipStream_t s) {
 }
 
 int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, hipStream_t s,
-          hb_solve_info *info) {
+          hb_solve_info *info, bool precond = false) {
   const size_t n = (size_t)c->nt * c->ne;
   const int m = maxit;
   const int nchunk = (int)((n + kDotChunk - 1) / kDotChunk);
   const size_t need = sizeof(double) * ((size_t)(m + 1) * n + n + (size_t)(m + 1) * nchunk + 2 * (m + 1));
   int rc = ensure_work(c, need);
   if (rc) return rc;
-  double *Q = c->d_work, *r = Q + (size_t)(m + 1) * n, *partial = r + n;
+  double *Q = c->d_work, *r = Q + (size_t)(m + 1) * n, *partial = r + n;  // r: P q_j
   double *dres = partial + (size_t)(m + 1) * nchunk, *coef = dres + (m + 1);
   std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1, 0.0), hv(m + 1), hv2(m + 1);
   double beta;
@@ -639,7 +639,12 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
   bool conv = false;
   for (int j = 0; j < m; ++j) {
     double *wj = Q + (size_t)(j + 1) * n;
-    if ((rc = apply_V(c, op, Q + (size_t)j * n, wj, s))) return rc;
+    if (precond) {
+      if ((rc = precond_apply(c, Q + (size_t)j * n, r, s))) return rc;
+      if ((rc = apply_V(c, op, r, wj, s))) return rc;
+    } else if ((rc = apply_V(c, op, Q + (size_t)j * n, wj, s))) {
+      return rc;
+    }
     // classical Gram-Schmidt, twice
     if ((rc = multi_dot(c, Q, n, j + 1, wj, n, partial, dres, hv.data(), s))) return rc;
     hipLaunchKernelGGL(k_sub_multi, dim3(grid1d(n)), dim3(256), 0, s, Q, n, dres, j + 1, wj, n);
@@ -678,7 +683,12 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
     y[i] = sacc / H[(size_t)i * m + i];
   }
   HB_CHECK(c, hipMemcpyAsync(coef, y.data(), sizeof(double) * it, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, s, Q, n, coef, it, x, n);
+  if (precond) {
+    hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, s, Q, n, coef, it, r, n);
+    if ((rc = precond_apply(c, r, x, s))) return rc;
+  } else {
+    hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, s, Q, n, coef, it, x, n);
+  }
   HB_CHECK(c, hipGetLastError());
   if (info) info->iterations = it;
   return conv ? HB_OK : HB_ENOCONV;
@@ -710,7 +720,7 @@ int time_march(hb_ctx *c, const double *b, double *w, hipStream_t s) {
 // Iterative refinement: x_{i+1} = x_i + d_i with V32 d_i ~= b - V_h x_i (GMRES on the float
 // operator to relative tolerance inner_tol); residuals in double with the double operator.
 int mixed_ir(hb_ctx *c, const double *b, double *x, double tol, int maxit, hipStream_t s,
-             hb_solve_info *info) {
+             hb_solve_info *info, bool precond) {
   const size_t n = (size_t)c->nt * c->ne;
   int rc = ensure_V32(c, s);
   if (rc) return rc;
@@ -754,7 +764,7 @@ int mixed_ir(hb_ctx *c, const double *b, double *x, double tol, int maxit, hipSt
       break;
     }
     hb_solve_info in{};
-    rc = gmres(c, 1, r, dlt, inner_tol, maxit, s, &in);
+    rc = gmres(c, 1, r, dlt, inner_tol, maxit, s, &in, precond);
     if (rc != HB_OK && rc != HB_ENOCONV) return rc;
     total_it += in.iterations;
     hipLaunchKernelGGL(k_axpby, dim3(grid1d(n)), dim3(256), 0, s, 1.0, dlt, 1.0, x, n);
@@ -827,8 +837,10 @@ int hb_solve(hb_ctx *c, const double *b, double *w, const hb_solve_opts *opts, h
   hb_solve_info inf{};
   auto t0 = std::chrono::steady_clock::now();
   int rc;
-  if (o.method == HB_SOLVE_GMRES) rc = gmres(c, 0, b, w, o.tol, o.max_iter, s, &inf);
-  else if (o.method == HB_SOLVE_MIXED_IR) rc = mixed_ir(c, b, w, o.tol, o.max_iter, s, &inf);
+  if (o.precond && !c->pc_active) return ctx_fail(c, HB_ESTATE, "no preconditioner installed");
+  const bool pc = o.precond != 0;
+  if (o.method == HB_SOLVE_GMRES) rc = gmres(c, 0, b, w, o.tol, o.max_iter, s, &inf, pc);
+  else if (o.method == HB_SOLVE_MIXED_IR) rc = mixed_ir(c, b, w, o.tol, o.max_iter, s, &inf, pc);
   else rc = time_march(c, b, w, s);
   if (rc != HB_OK && rc != HB_ENOCONV) return rc;
   HB_CHECK(c, hipStreamSynchronize(s));

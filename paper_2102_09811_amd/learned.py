@@ -1,0 +1,189 @@
+"""Learned sparse-approximate-inverse preconditioner for V_h w = b.
+
+A 3-layer tanh MLP (width 256, float32) maps the local data of a row l (near-field entries of
+V_h^0 on the row's touching-panel pattern and the local geometry, see ``hb_precond_features``) to
+the scaled weights y = V^0[l,l] M[l, pattern] of a sparse approximate inverse M ~ (V_h^0)^{-1}.
+Training minimises the mean row residual ||(M V^0)_l - e_l||^2 = y^T G_l y - 2 a_l^T y + 1,
+whose G_l, a_l come from ``hb_precond_spai`` on method-generated V^0 blocks (random ellipsoids).
+Inference needs only local data; M is then installed with ``hb_precond_set`` and used as the
+block-diagonal right preconditioner of GMRES.
+
+Forward, backward, loss and Adam run in the library's HIP kernels; this module only allocates
+device buffers (PyTorch) and sequences the calls.
+"""
+import ctypes
+
+import numpy as np
+
+from . import binding as B
+
+N_IN, N_HIDDEN, N_OUT = B.HB_PC_FEATURES, 256, B.HB_PC_SLOTS
+
+
+def _dims(n_in=N_IN, n_hidden=N_HIDDEN, n_out=N_OUT):
+    d = B.MLPDims()
+    d.n_in, d.n_hidden, d.n_out = n_in, n_hidden, n_out
+    return d
+
+
+class MLP:
+    """Parameters on the device: W1 [H][I], b1 [H], W2 [H][H], b2 [H], W3 [O][H], b3 [O]."""
+
+    def __init__(self, n_in=N_IN, n_hidden=N_HIDDEN, n_out=N_OUT, seed=0, params=None):
+        import torch
+        self.dims = _dims(n_in, n_hidden, n_out)
+        n = B.lib().hb_mlp_num_params(ctypes.byref(self.dims))
+        if params is None:
+            rng = np.random.default_rng(seed)
+            parts = []
+            for fan_in, fan_out in ((n_in, n_hidden), (n_hidden, n_hidden), (n_hidden, n_out)):
+                lim = np.sqrt(6.0 / (fan_in + fan_out))
+                parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
+                parts.append(np.zeros(fan_out))
+            params = np.concatenate(parts).astype(np.float32)
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        assert params.size == n, (params.size, n)
+        self.params = torch.from_numpy(params).cuda()
+        self.n = n
+
+    def work(self, batch):
+        import torch
+        nw = B.lib().hb_mlp_work_floats(ctypes.byref(self.dims), batch)
+        return torch.empty(nw, dtype=torch.float32, device="cuda")
+
+    def forward(self, x, work=None, stream=None):
+        import torch
+        batch = x.shape[0]
+        work = self.work(batch) if work is None else work
+        y = torch.empty((batch, self.dims.n_out), dtype=torch.float32, device="cuda")
+        rc = B.lib().hb_mlp_forward(ctypes.byref(self.dims), B._ptr(self.params), B._ptr(x), batch,
+                                    B._ptr(y), B._ptr(work), B._stream(stream))
+        if rc != 0:
+            raise B.HBError(rc, "hb_mlp_forward")
+        return y, work
+
+    def backward(self, x, work, dy, grads=None, stream=None):
+        import torch
+        grads = torch.empty_like(self.params) if grads is None else grads
+        rc = B.lib().hb_mlp_backward(ctypes.byref(self.dims), B._ptr(self.params), B._ptr(x),
+                                     x.shape[0], B._ptr(work), B._ptr(dy), B._ptr(grads),
+                                     B._stream(stream))
+        if rc != 0:
+            raise B.HBError(rc, "hb_mlp_backward")
+        return grads
+
+    def save(self, path):
+        np.savez(path, params=self.params.cpu().numpy(),
+                 dims=np.array([self.dims.n_in, self.dims.n_hidden, self.dims.n_out]))
+
+    @classmethod
+    def load(cls, path):
+        z = np.load(path)
+        d = z["dims"]
+        return cls(int(d[0]), int(d[1]), int(d[2]), params=z["params"])
+
+
+def quad_loss(y, G, a, want_grad=True, stream=None):
+    """Per-row loss y^T G y - 2 a^T y + 1 and the gradient of its mean w.r.t. y."""
+    import torch
+    rows = y.shape[0]
+    dy = torch.empty_like(y) if want_grad else None
+    rl = torch.empty(rows, dtype=torch.float32, device="cuda")
+    rc = B.lib().hb_precond_loss(B._ptr(y), B._ptr(G), B._ptr(a), rows,
+                                 B._ptr(dy) if want_grad else None, B._ptr(rl), B._stream(stream))
+    if rc != 0:
+        raise B.HBError(rc, "hb_precond_loss")
+    return rl, dy
+
+
+class Adam:
+    def __init__(self, mlp, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+        self.mlp, self.lr, self.b1, self.b2, self.eps = mlp, lr, beta1, beta2, eps
+        self.m = torch.zeros_like(mlp.params)
+        self.v = torch.zeros_like(mlp.params)
+        self.t = 0
+
+    def step(self, grads, stream=None):
+        self.t += 1
+        rc = B.lib().hb_adam_step(B._ptr(self.mlp.params), B._ptr(grads), B._ptr(self.m),
+                                  B._ptr(self.v), self.mlp.n, self.lr, self.b1, self.b2, self.eps,
+                                  self.t, B._stream(stream))
+        if rc != 0:
+            raise B.HBError(rc, "hb_adam_step")
+
+
+def mesh_data(verts, tris, alpha, h):
+    """Features, Gram matrices, right-hand sides and exact weights of one mesh's V^0 (a one-step
+    context with T = h has the same V^0 as any E_t-step problem with that h)."""
+    ctx = B.Context(verts, tris, alpha, h, 1)
+    ctx.assemble(B.HB_OP_V)
+    X = ctx.precond_features()
+    G, a, y = ctx.precond_spai(exact=True)
+    ctx.close()
+    return X, G, a, y
+
+
+def ellipsoid_set(seeds, n_t=64, T=1.0):
+    """The random ellipsoids of the learned-preconditioner workload: semi-axes U[0.5, 2]^3,
+    cubed-sphere resolution n in 13..20 (12 n^2 triangles), alpha log-uniform in [0.1, 10]."""
+    from synthetic import cubed_sphere_ellipsoid
+    out = []
+    for sd in seeds:
+        rng = np.random.default_rng(1000 + sd)
+        axes = rng.uniform(0.5, 2.0, size=3)
+        n = int(rng.integers(13, 21))
+        alpha = float(10.0 ** rng.uniform(-1.0, 1.0))
+        v, t = cubed_sphere_ellipsoid(n, axes)
+        out.append({"seed": sd, "verts": v, "tris": t, "alpha": alpha, "h": T / n_t, "n": n,
+                    "axes": axes})
+    return out
+
+
+def train(meshes, epochs=40, batch=2048, lr=1e-3, seed=0, log=None):
+    """Train the MLP on the rows of all meshes; returns (mlp, per-epoch mean losses)."""
+    import torch
+    Xs, Gs, As = [], [], []
+    for m in meshes:
+        X, G, a, _ = mesh_data(m["verts"], m["tris"], m["alpha"], m["h"])
+        Xs.append(X)
+        Gs.append(G)
+        As.append(a)
+    X = torch.cat(Xs)
+    G = torch.cat(Gs)
+    A = torch.cat(As)
+    rows = X.shape[0]
+    mlp = MLP(seed=seed)
+    opt = Adam(mlp, lr=lr)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    work = mlp.work(batch)
+    grads = torch.empty_like(mlp.params)
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(rows, device="cuda", generator=gen)
+        tot, cnt = 0.0, 0
+        for i0 in range(0, rows - batch + 1, batch):
+            idx = perm[i0:i0 + batch]
+            xb, gb, ab = X[idx].contiguous(), G[idx].contiguous(), A[idx].contiguous()
+            y, _ = mlp.forward(xb, work)
+            rl, dy = quad_loss(y, gb, ab)
+            mlp.backward(xb, work, dy, grads)
+            opt.step(grads)
+            tot += float(rl.sum())
+            cnt += batch
+        hist.append(tot / max(cnt, 1))
+        if log:
+            log("epoch %d: mean row loss %.4e" % (ep, hist[-1]))
+    return mlp, hist
+
+
+def predict(mlp, ctx):
+    """Scaled weights [E_x][HB_PC_SLOTS] for the context's assembled V^0 (local data only)."""
+    X = ctx.precond_features()
+    y, _ = mlp.forward(X)
+    return y
+
+
+def install(mlp, ctx):
+    ctx.precond_set(predict(mlp, ctx))

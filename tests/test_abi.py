@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol(hb):
     assert "hb_create" in names and "hb_assemble" in names and len(names) >= 12
     for n in names:
         assert hasattr(L, n), n
-    assert sorted(hb.EXPORTED) == names
+    assert sorted(hb.EXPORTED) == names, (set(hb.EXPORTED) ^ set(names))
 
 
 @pytest.mark.parametrize("mesh", ["cube", "icosphere", "octahedron", "tetrahedron"])

@@ -1,0 +1,155 @@
+"""GPU parity and gain of the learned sparse-approximate-inverse preconditioner.
+
+* pattern and features of each row vs an independent numpy construction from the mesh;
+* normal equations (G, a) and exact weights of the sparse approximate inverse vs the oracle
+  computed from the oracle's own V^0;
+* MLP forward/backward, loss gradient and Adam step vs the float64 oracle (gradient check:
+  max error <= 1e-4 of the largest gradient entry);
+* gain: trained on random ellipsoids, on held-out ones GMRES needs fewer iterations with the
+  learned preconditioner than without, and still reaches 1e-8 with the double operator.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from synthetic import cube, exp_solution, nodal_samples
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def expected_pattern(v, t, S=16):
+    cent = v[t].mean(1)
+    cols = np.full((len(t), S), -1, dtype=np.int64)
+    for l in range(len(t)):
+        shared = np.isin(t, t[l]).sum(1)
+        cand = [m for m in range(len(t)) if shared[m] > 0]
+        key = sorted(cand, key=lambda m: (-shared[m], np.sum((cent[l] - cent[m]) ** 2)))
+        cols[l, :min(S, len(key))] = key[:S]
+    return cols
+
+
+@pytest.fixture(scope="module")
+def c1ctx():
+    from paper_2102_09811_amd import Context
+    v, t = cube(4)
+    say("c1 context for the preconditioner")
+    ctx = Context(v, t, 1.0, 1.0, 16)
+    ctx.assemble()
+    return v, t, ctx
+
+
+def test_pattern_features_and_spai(c1ctx):
+    from paper_2102_09811_amd import HB_OP_V
+    v, t, ctx = c1ctx
+    cols, cls = ctx.precond_pattern()
+    cols = cols.cpu().numpy()
+    exp = expected_pattern(v, t)
+    # equal-distance ties may swap neighbours of the same class: compare as sets per class
+    for l in range(len(t)):
+        assert cols[l, 0] == l
+        assert set(cols[l][cols[l] >= 0]) == set(exp[l][exp[l] >= 0])
+    V0 = oracle.assemble(v, t, 1.0, 1.0 / 16, 1)[0][0]
+    G, a, y = ctx.precond_spai(exact=True)
+    Gr, ar, yr = omlp.spai_normal_equations(V0, cols)
+    assert np.abs(G.cpu().numpy() - Gr).max() <= 1e-6 * np.abs(Gr).max()
+    assert np.abs(a.cpu().numpy() - ar).max() <= 1e-6
+    y = y.cpu().numpy()
+    L_gpu = omlp.row_loss(y, Gr, ar)[0]
+    L_or = omlp.row_loss(yr, Gr, ar)[0]
+    assert np.all(L_gpu <= L_or + 1e-6)        # the GPU weights minimise the same quadratic
+    # features
+    X = ctx.precond_features().cpu().numpy()
+    area = 0.5 * np.linalg.norm(np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]]), axis=1)
+    nrm = np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]])
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    cent = v[t].mean(1)
+    cls = cls.cpu().numpy()
+    for l in (0, 77, 191):
+        for s in range(16):
+            m = cols[l, s]
+            f = X[l, 8 * s:8 * s + 8]
+            if m < 0:
+                assert np.all(f == 0)
+                continue
+            ref = [V0[l, m] / V0[l, l], cls[l, s] == 3, cls[l, s] == 2, cls[l, s] == 1,
+                   np.linalg.norm(cent[l] - cent[m]) / np.sqrt(area[l]), area[m] / area[l],
+                   nrm[l] @ nrm[m], 1.0]
+            assert np.allclose(f, ref, rtol=1e-5, atol=1e-6)
+        hl = np.sqrt(1.0 / 16 / area[l])
+        assert np.allclose(X[l, 128:], [hl, np.log(hl), (cols[l] >= 0).sum() / 16, 1.0], rtol=1e-5)
+
+
+def test_mlp_kernels_match_oracle():
+    import torch
+    from paper_2102_09811_amd import learned
+    I, H, O, Bt = 132, 256, 16, 300
+    net = learned.MLP(I, H, O, seed=3)
+    p = net.params.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(Bt, I)).astype(np.float32)
+    say("mlp forward/backward B=%d" % Bt)
+    xd = torch.from_numpy(x).cuda()
+    y, work = net.forward(xd)
+    yr, cache = omlp.forward(p, x, I, H, O)
+    assert np.abs(y.cpu().numpy() - yr).max() <= 1e-5 * np.abs(yr).max()
+    G = np.einsum("bsj,btj->bst", *(2 * [rng.normal(size=(Bt, O, 40))])) / 40 + np.eye(O)
+    a = rng.normal(size=(Bt, O))
+    Gd = torch.from_numpy(G.astype(np.float32)).cuda()
+    ad = torch.from_numpy(a.astype(np.float32)).cuda()
+    rl, dy = learned.quad_loss(y, Gd, ad)
+    Lr, dyr = omlp.row_loss(y.cpu().numpy().astype(np.float64), G, a)
+    assert np.abs(rl.cpu().numpy() - Lr).max() <= 1e-4 * np.abs(Lr).max()
+    assert np.abs(dy.cpu().numpy() - dyr).max() <= 1e-5 * np.abs(dyr).max()
+    g = net.backward(xd, work, dy).cpu().numpy()
+    gr = omlp.backward(p, cache, dy.cpu().numpy().astype(np.float64), I, H, O)
+    err = np.abs(g - gr).max() / np.abs(gr).max()
+    say("gradient check: max rel err %.2e" % err)
+    assert err <= 1e-4
+    # one Adam step
+    opt = learned.Adam(net, lr=1e-3)
+    gd = torch.from_numpy(g).cuda()
+    opt.step(gd)
+    pr, _, _ = omlp.adam(p, g.astype(np.float64), 0.0, 0.0, 1, 1e-3)
+    assert np.abs(net.params.cpu().numpy() - pr).max() <= 1e-6
+
+
+def test_learned_preconditioner_gain():
+    import torch
+    from paper_2102_09811_amd import Context, HB_SOLVE_GMRES, learned
+    train_set = learned.ellipsoid_set(range(0, 16))
+    test_set = learned.ellipsoid_set(range(160, 164))
+    say("training on %d ellipsoids (%d rows)" % (len(train_set), sum(len(m["tris"]) for m in train_set)))
+    net, hist = learned.train(train_set, epochs=30, batch=2048, lr=1e-3, seed=0)
+    say("loss: first %.4e last %.4e" % (hist[0], hist[-1]))
+    assert hist[-1] < 0.5 * hist[0]
+    its_plain, its_learned, its_exact = [], [], []
+    for m in test_set:
+        v, t, alpha = m["verts"], m["tris"], m["alpha"]
+        ctx = Context(v, t, alpha, 1.0, 64)
+        ctx.assemble()
+        g = nodal_samples(v, 64, 1.0, lambda x, tt: exp_solution(x, tt, alpha))
+        b = ctx.rhs_dirichlet(torch.from_numpy(g).cuda())
+        _, ip = ctx.solve(b, method=HB_SOLVE_GMRES, tol=1e-8)
+        learned.install(net, ctx)
+        _, il = ctx.solve(b, method=HB_SOLVE_GMRES, tol=1e-8, precond=True)
+        _, _, yex = ctx.precond_spai(exact=True)
+        ctx.precond_set(yex)
+        _, ie = ctx.solve(b, method=HB_SOLVE_GMRES, tol=1e-8, precond=True)
+        say("seed %d E_x=%d alpha=%.3f: plain %d it %.1f ms | learned %d it %.1f ms | exact SPAI %d it" % (
+            m["seed"], len(t), alpha, ip["iterations"], 1e3 * ip["seconds"], il["iterations"],
+            1e3 * il["seconds"], ie["iterations"]))
+        assert il["converged"] and il["rel_residual"] <= 1e-8
+        its_plain.append(ip["iterations"])
+        its_learned.append(il["iterations"])
+        its_exact.append(ie["iterations"])
+        ctx.close()
+        torch.cuda.empty_cache()
+    assert np.mean(its_learned) <= 0.85 * np.mean(its_plain), (its_plain, its_learned)
