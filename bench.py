@@ -5,8 +5,14 @@ One step = one pass of the whole path over the workload (icosphere, 1280 triangl
 vertices, 64 uniform steps on (0, 1], alpha = 1):
   1. fused assembly of all V_h^d and K_h^d blocks (FP64),
   2. Dirichlet right-hand side (1/2 M_h + K_h) g,
-  3. GMRES on V_h w = b to relative residual 1e-8 (FP64),
-  4. representation formula at 10^4 interior space-time points.
+  3. learned preconditioner for this V_h^0 (features, MLP inference, installation),
+  4. right-preconditioned GMRES on V_h w = b to relative residual 1e-8, the residual taken with the
+     double-precision operator,
+  5. representation formula at 10^4 interior space-time points.
+The MLP is trained before the timed region on random ellipsoids (the learned-preconditioner
+workload), never on this mesh.  After the timed steps every solver is timed on the same b:
+plain double GMRES (the reference), time marching, mixed-precision refinement, learned GMRES and
+learned + mixed, each to 1e-8.
 Inputs (mesh, data, points) are synthetic and seeded and already resident on the device when the
 timed region starts.  value = pair-block integrals per second of the whole step:
 E_x^2 * E_t units (one unit = one (test panel, trial panel, d) triple with its V entry and its
@@ -56,6 +62,43 @@ def cpu_baseline(verts, tris, alpha, T, n_t):
                 len(rows), len(tris), n_t, dt)}
 
 
+def compare_solvers(ctx, b, net):
+    """Every solver on the same right-hand side, each to relative residual 1e-8 measured with the
+    double operator; wall time of the whole call (median of 3)."""
+    import numpy as np
+    from paper_2102_09811_amd import HB_SOLVE_GMRES, HB_SOLVE_MIXED_IR, HB_SOLVE_TIMEMARCH, learned
+    cases = [("gmres_fp64", HB_SOLVE_GMRES, False), ("time_marching", HB_SOLVE_TIMEMARCH, False),
+             ("mixed_ir", HB_SOLVE_MIXED_IR, False), ("learned_gmres", HB_SOLVE_GMRES, True),
+             ("learned_mixed_ir", HB_SOLVE_MIXED_IR, True)]
+    learned.install(net, ctx)
+    res = {}
+    for name, method, pc in cases:
+        ctx.solve(b, method=method, tol=1e-8, precond=pc)  # warm (time marching: inverse of V^0)
+        times, info = [], None
+        for _ in range(3):
+            _, info = ctx.solve(b, method=method, tol=1e-8, precond=pc)
+            times.append(1e3 * info["seconds"])
+        res[name] = {"ms": float(np.median(times)), "iterations": info["iterations"],
+                     "refinements": info["refinements"], "rel_residual": info["rel_residual"],
+                     "converged": info["converged"]}
+        log("solve %-16s %8.2f ms  it=%d res=%.2e" % (name, res[name]["ms"], info["iterations"],
+                                                      info["rel_residual"]))
+    # time marching including the Gauss-Jordan inverse of V^0 (needed once per assembled V^0)
+    from paper_2102_09811_amd import HB_OP_V
+    ctx.assemble(HB_OP_V)
+    _, info = ctx.solve(b, method=HB_SOLVE_TIMEMARCH, tol=1e-8)
+    res["time_marching_with_inverse"] = {"ms": 1e3 * info["seconds"], "iterations": 0,
+                                         "refinements": 0, "rel_residual": info["rel_residual"],
+                                         "converged": info["converged"]}
+    log("solve %-16s %8.2f ms (first call after assembly)" % ("time_marching+inv",
+                                                               res["time_marching_with_inverse"]["ms"]))
+    learned.install(net, ctx)
+    base = res["gmres_fp64"]["ms"]
+    for name in res:
+        res[name]["speedup_vs_gmres_fp64"] = base / res[name]["ms"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +106,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--points", type=int, default=10000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the solver comparison")
+    ap.add_argument("--train-meshes", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1",
@@ -71,7 +116,8 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2102_09811_amd import Context, HB_OP_K, HB_OP_V, HB_SOLVE_GMRES, check_mesh
+    from paper_2102_09811_amd import (Context, HB_OP_K, HB_OP_V, HB_PREC_MIXED, HB_SOLVE_GMRES,
+                                      HB_SOLVE_MIXED_IR, HB_SOLVE_TIMEMARCH, check_mesh, learned)
     from synthetic import ball_points, exp_solution, icosphere, nodal_samples, space_time_points
 
     assert torch.cuda.is_available(), "no GPU"
@@ -83,6 +129,11 @@ def main():
     n_sep = int(counts[0])
     g = nodal_samples(verts, n_t, T, lambda x, t: exp_solution(x, t, alpha))
     pts = space_time_points(ball_points(args.points, 0.5, seed=0), 0.25, 0.75, seed=0)
+    log("training the learned preconditioner on %d ellipsoids" % args.train_meshes)
+    t_train = time.perf_counter()
+    net, hist = learned.train(learned.ellipsoid_set(range(args.train_meshes)), epochs=30)
+    t_train = time.perf_counter() - t_train
+    log("trained in %.1f s, loss %.3e -> %.3e" % (t_train, hist[0], hist[-1]))
     ctx = Context(verts, tris, alpha, T, n_t)
     gd = torch.from_numpy(g).cuda()
     ptsd = torch.from_numpy(pts).cuda()
@@ -97,7 +148,8 @@ def main():
         ev[1].record(stream)
         ctx.rhs_dirichlet(gd, b)
         ev[2].record(stream)
-        _, info = ctx.solve(b, method=HB_SOLVE_GMRES, tol=1e-8, w=w)
+        learned.install(net, ctx)
+        _, info = ctx.solve(b, method=HB_SOLVE_GMRES, tol=1e-8, w=w, precond=True)
         ev[3].record(stream)
         u = ctx.eval_repr(ptsd, w, gd)
         ev[4].record(stream)
@@ -149,13 +201,28 @@ def main():
                       "solve": avg("solve_ms"), "repr": avg("repr_ms"),
                       "assemble_separated_kernel": sep_ms, "assemble_touching_kernels": touch_ms},
         "assembly_units_per_s": units / (avg("assemble_ms") * 1e-3),
-        "solve": {"method": "GMRES fp64", "iterations": int(rec[-1]["iterations"]),
+        "solve": {"method": "learned-preconditioned GMRES (double operator)",
+                  "iterations": int(rec[-1]["iterations"]),
                   "rel_residual": rec[-1]["rel_residual"], "ms": avg("solve_ms")},
+        "learned_training_s": t_train,
         "roofline": {"bound": "alu", "kernel": "k_separated (separated-pair assembly)",
                      "achieved": achieved, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / (PEAK_FP64_VALU / 1e12), "traffic": None,
                      "algorithmic_flops_per_launch": flops},
     }
+    if not args.no_compare:
+        log("solver comparison")
+        out["solve_comparison"] = compare_solvers(ctx, b, net)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ctx.assemble(HB_OP_V | HB_OP_K, precision=HB_PREC_MIXED)
+        ev0.record(stream)
+        ctx.assemble(HB_OP_V | HB_OP_K, precision=HB_PREC_MIXED)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_mixed = ev0.elapsed_time(ev1)
+        out["mixed_assembly"] = {"ms": ms_mixed, "units_per_s": units / (ms_mixed * 1e-3),
+                                 "separated_kernel_ms": ctx.last_assembly_ms()[0]}
+        ctx.assemble(HB_OP_V | HB_OP_K)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(verts, tris, alpha, T, n_t)

@@ -630,6 +630,7 @@ int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
   if (p.do_V) {
     c->have_V = true;
     c->V32_valid = false;
+    c->v0inv_valid = false;
     c->pc_active = false;  // M was scaled by the previous V^0
   }
   if (p.do_K) c->have_K = true;

@@ -122,6 +122,7 @@ struct hb_ctx {
   double *d_work = nullptr;
   size_t work_bytes = 0;
   double *d_v0inv = nullptr;         // inverse of V^0 (time marching)
+  bool v0inv_valid = false;          // cleared whenever V is reassembled
   // learned preconditioner: row pattern, centroids, installed weights
   int32_t *d_pc_cols = nullptr;      // [ne][HB_PC_SLOTS]
   int8_t *d_pc_cls = nullptr;

@@ -549,9 +549,10 @@ int gemv_batch(hb_ctx *c, const void *A, size_t stride, int R, int C, int nd, co
 }
 
 int invert_v0(hb_ctx *c, hipStream_t s) {
-  if (c->d_v0inv) return HB_OK;
+  if (c->v0inv_valid) return HB_OK;
   const int n = (int)c->ne;
-  HB_CHECK(c, hipMalloc(&c->d_v0inv, sizeof(double) * (size_t)n * n + sizeof(double) * 2 * n));
+  if (!c->d_v0inv)
+    HB_CHECK(c, hipMalloc(&c->d_v0inv, sizeof(double) * (size_t)n * n + sizeof(double) * 2 * n));
   double *A = c->d_v0inv, *rowp = A + (size_t)n * n, *colp = rowp + n;
   if (c->storage_f32) {
     std::vector<float> tmp((size_t)n * n);
@@ -568,6 +569,7 @@ int invert_v0(hb_ctx *c, hipStream_t s) {
     hipLaunchKernelGGL(k_gj_update, dim3((n + 255) / 256, n), dim3(256), 0, s, A, n, p, rowp, colp);
   }
   HB_CHECK(c, hipGetLastError());
+  c->v0inv_valid = true;
   return HB_OK;
 }
 
