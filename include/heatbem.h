@@ -64,10 +64,11 @@ typedef struct hb_options {
                            series of the hat-weighted heat kernel instead of second differences
                            of G^{dtau dt}; default 8, minimum 8; values >= E_t disable it. */
   int32_t storage;      /* HB_DTYPE_F64 (default) or HB_DTYPE_F32 block storage. */
-  int32_t mixed_d_min;  /* HB_PREC_MIXED: separated pairs at d >= max(mixed_d_min, d_switch) are
-                           evaluated in float (kernel value and degree-8 Taylor polynomial, double
-                           accumulation); smaller d, whose second differences cancel, and all
-                           touching pairs stay in double.  Default 8, minimum 2. */
+  int32_t mixed_d_min;  /* HB_PREC_MIXED: separated pairs at d >= max(mixed_d_min, d_switch),
+                           rounded up to an even d, are evaluated in float (kernel value and a
+                           Taylor polynomial of degree 8, 6 or 4 as d grows, double accumulation);
+                           smaller d, whose second differences cancel, and all touching pairs stay
+                           in double.  Default 8, minimum 2. */
   int32_t reserved[12]; /* must be zero */
 } hb_options;
 

@@ -40,6 +40,34 @@ __device__ __forceinline__ double horner(const double *__restrict__ c, double x)
   return r;
 }
 
+// e^{-w} for w >= 0: Cody-Waite reduction w = k ln2 - r with the ln2 split of fdlibm, the degree-12
+// Taylor polynomial of e^r on |r| <= ln2/2 (truncation < 2e-16 relative), then 2^k by ldexp, which
+// also underflows gracefully; inputs are clamped at 1000 where the result is 0.  Max relative error
+// about 1.5 ulp, and no range branches or selects.
+__device__ __forceinline__ double exp_neg(double w) {
+  constexpr double kLog2e = 1.4426950408889634;
+  constexpr double kLn2Hi = 6.93147180369123816490e-01;
+  constexpr double kLn2Lo = 1.90821492927058770002e-10;
+  const double t = -fmin(w, 1000.0);
+  const double k = rint(t * kLog2e);
+  double r = fma(k, -kLn2Hi, t);
+  r = fma(k, -kLn2Lo, r);
+  double q = 1.0 / 479001600.0;
+  q = fma(q, r, 1.0 / 39916800.0);
+  q = fma(q, r, 1.0 / 3628800.0);
+  q = fma(q, r, 1.0 / 362880.0);
+  q = fma(q, r, 1.0 / 40320.0);
+  q = fma(q, r, 1.0 / 5040.0);
+  q = fma(q, r, 1.0 / 720.0);
+  q = fma(q, r, 1.0 / 120.0);
+  q = fma(q, r, 1.0 / 24.0);
+  q = fma(q, r, 1.0 / 6.0);
+  q = fma(q, r, 0.5);
+  q = fma(q, r, 1.0);
+  q = fma(q, r, 1.0);
+  return ldexp(q, (int)k);
+}
+
 // One closed-form level: rA = rho A(z), kB = B(z) / rho.
 __device__ __forceinline__ void closed_level(const AsmParams &p, int i, double rho,
                                              double inv_rho, double &rA, double &kB) {
@@ -52,7 +80,7 @@ __device__ __forceinline__ void closed_level(const AsmParams &p, int i, double r
     rA = fma(rho * z * kInvSqrtPi, sa, p.lv.t2[i]);
     kB = kFourInvSqrtPi * c * sb;
   } else {
-    const double e = exp(-z * z);
+    const double e = exp_neg(z * z);
     const double er = erf(z);
     const double es = er * p.lv.s2[i] * inv_rho;   // erf * 2 alpha delta / rho
     const double ps = e * p.lv.s1[i];              // e^{-z^2} 2 sqrt(alpha delta)/sqrt(pi)
@@ -74,7 +102,6 @@ __device__ __forceinline__ void add_block_K(const AsmParams &p, int d, int l, in
 }
 
 constexpr int kLC = 2;  // closed-form levels per pass over the quadrature points
-constexpr int kLT = 1;  // Taylor blocks per pass over the quadrature points
 
 // Level sums of one pass: S[0], S[1] carry levels i0-2, i0-1; S[2 + j] is level i0 + j.
 struct LevelSums {
@@ -134,38 +161,133 @@ __device__ __forceinline__ void shift_carry(LevelSums &S) {
   for (int j = 2; j < kLC + 2; ++j) S.V[j] = S.K[j][0] = S.K[j][1] = S.K[j][2] = 0.0;
 }
 
-// One pass of the separated kernel over the 49 point pairs for closed-form levels I0..I0+kLC-1,
-// then the blocks it completes; recurses to the next pass at compile time.
+// ------------------------------------------------------------------------------------------
+// Separated pairs.  Both panels use the same 7-point rule, so the ordered pairs (l, m) and (m, l)
+// share all 49 point pairs (r changes sign, rho does not): one lane evaluates the unordered pair
+// m > l once and emits both orders.  V^d[l][m] = V^d[m][l]; the double layer differs only in the
+// normal and the p1 basis:  (l, m) uses r . n_m and the basis at the m-nodes,  (m, l) uses
+// -r . n_l and the basis at the l-nodes.  Workgroup = (test panel l, 256 consecutive m); lane = m.
+// ------------------------------------------------------------------------------------------
+struct SymSums {
+  double V[kLC + 2];
+  double K1[kLC + 2][3];  // order (l, m): trial m
+  double K2[kLC + 2][3];  // order (m, l): trial l
+};
+
+__device__ __forceinline__ void shift_sym(SymSums &S) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    S.V[c] = S.V[kLC + c];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      S.K1[c][q] = S.K1[kLC + c][q];
+      S.K2[c][q] = S.K2[kLC + c][q];
+    }
+  }
+#pragma unroll
+  for (int j = 2; j < kLC + 2; ++j) {
+    S.V[j] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) S.K1[j][q] = S.K2[j][q] = 0.0;
+  }
+}
+
+// Blocks completed by the pass over levels i0 .. i0+kLC-1, both orders.
+template <typename TS, int D>
+__device__ __forceinline__ void emit_sym(const AsmParams &p, int i0, int l, int m,
+                                         const int vl[3], const int vm[3], double scale,
+                                         const SymSums &S, double sV, const double sK1[3],
+                                         const double sK2[3]) {
+  const int i1 = min(i0 + kLC - 1, D);
+#pragma unroll
+  for (int j = 0; j < kLC + 1; ++j) {
+    const int d = i0 - 1 + j;
+    if (d < 0 || d > i1 - 1 || d >= D || d >= p.nt) continue;
+    const int c = d - i0 + 2;
+    double v, k1[3], k2[3];
+    if (d == 0) {
+      v = p.kVs * sV + p.kV * (S.V[c] - S.V[c + 1]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        k1[q] = p.kKs * sK1[q] + p.kK * (S.K1[c + 1][q] - S.K1[c][q]);
+        k2[q] = p.kKs * sK2[q] + p.kK * (S.K2[c + 1][q] - S.K2[c][q]);
+      }
+    } else {
+      v = p.kV * (2.0 * S.V[c] - S.V[c + 1] - S.V[c - 1]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        k1[q] = -p.kK * (2.0 * S.K1[c][q] - S.K1[c + 1][q] - S.K1[c - 1][q]);
+        k2[q] = -p.kK * (2.0 * S.K2[c][q] - S.K2[c + 1][q] - S.K2[c - 1][q]);
+      }
+    }
+    if (p.do_V) {
+      store_block<TS>(p, d, l, m, v * scale);
+      store_block<TS>(p, d, m, l, v * scale);
+    }
+    if (p.do_K) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        add_block_K<TS>(p, d, l, vm[q], k1[q] * scale);
+        add_block_K<TS>(p, d, m, vl[q], k2[q] * scale);
+      }
+    }
+  }
+}
+
+// Read-only tables of the separated kernel, passed as restrict kernel arguments so that uniform
+// reads (test nodes of l, polynomial coefficients) become scalar loads.
+struct SepTabs {
+  const double *__restrict__ geom;      // SoA [25][ne]
+  const double *__restrict__ tscale;    // [nt][3]
+  const double *__restrict__ taylor;    // [nt][2][kTaylorN]
+  const float *__restrict__ taylor32;   // [nt][2][kTaylorN32]
+  const int *__restrict__ tdeg;         // [nt][2]
+};
+
+// Per-lane data of an unordered separated pair.
+struct SepLane {
+  const double *xg;        // test nodes of l: xg[(a*3+c)*ne]
+  double nm[3], nl[3];     // unit normals of m and l
+  double shift;            // inactive lanes integrate a far-away copy and store nothing
+};
+
 template <typename TS, int D, int I0>
-__device__ __forceinline__ void separated_pass(const AsmParams &p, int l, int m, const int vtx[3],
-                                               bool touch, double n0, double n1, double n2,
-                                               double scale, double shift, const double *xg,
-                                               LevelSums &S, double &sV, double sK[3]) {
+__device__ __forceinline__ void sym_pass(const AsmParams &p, const SepTabs &T, int l, int m,
+                                         const int vl[3], const int vm[3], bool active,
+                                         double scale, const SepLane &L, SymSums &S, double &sV,
+                                         double sK1[3], double sK2[3]) {
   if constexpr (I0 <= D) {
     const int ne = p.ne;
 #pragma unroll 1
     for (int b = 0; b < kFarN; ++b) {
-      const double y0 = p.geom[(b * 3 + 0) * ne + m] + shift;
-      const double y1 = p.geom[(b * 3 + 1) * ne + m];
-      const double y2 = p.geom[(b * 3 + 2) * ne + m];
+      const double y0 = T.geom[(b * 3 + 0) * ne + m] + L.shift;
+      const double y1 = T.geom[(b * 3 + 1) * ne + m];
+      const double y2 = T.geom[(b * 3 + 2) * ne + m];
       const double wb = p.w7[b];
       double tK[kLC], tsK = 0.0;
 #pragma unroll
       for (int j = 0; j < kLC; ++j) tK[j] = 0.0;
 #pragma unroll 1
       for (int a = 0; a < kFarN; ++a) {
-        const double rx = xg[(a * 3 + 0) * ne] - y0;
-        const double ry = xg[(a * 3 + 1) * ne] - y1;
-        const double rz = xg[(a * 3 + 2) * ne] - y2;
+        const double rx = L.xg[(a * 3 + 0) * ne] - y0;
+        const double ry = L.xg[(a * 3 + 1) * ne] - y1;
+        const double rz = L.xg[(a * 3 + 2) * ne] - y2;
         const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
         const double rho = sqrt(rho2);
         const double inv_rho = 1.0 / rho;
         const double wa = p.w7[a];
         const double W = wa * wb;
-        const double wrn = wa * fma(rx, n0, fma(ry, n1, rz * n2));
+        const double wrn1 = wa * fma(rx, L.nm[0], fma(ry, L.nm[1], rz * L.nm[2]));
+        const double wrn2 = -W * fma(rx, L.nl[0], fma(ry, L.nl[1], rz * L.nl[2]));
+        const double la0 = p.lam7[a][0], la1 = p.lam7[a][1], la2 = p.lam7[a][2];
         if constexpr (I0 == 0) {
           sV = fma(W, inv_rho, sV);
-          tsK = fma(wrn, inv_rho * inv_rho * inv_rho, tsK);
+          const double i3 = inv_rho * inv_rho * inv_rho;
+          tsK = fma(wrn1, i3, tsK);
+          const double u = wrn2 * i3;
+          sK2[0] = fma(u, la0, sK2[0]);
+          sK2[1] = fma(u, la1, sK2[1]);
+          sK2[2] = fma(u, la2, sK2[2]);
         }
 #pragma unroll
         for (int j = 0; j < kLC; ++j) {
@@ -173,119 +295,227 @@ __device__ __forceinline__ void separated_pass(const AsmParams &p, int l, int m,
           double rA, kB;
           level_terms(p, I0 + j, rho, inv_rho, rA, kB);
           S.V[2 + j] = fma(W, rA, S.V[2 + j]);
-          tK[j] = fma(wrn, kB, tK[j]);
+          tK[j] = fma(wrn1, kB, tK[j]);
+          const double u = wrn2 * kB;
+          S.K2[2 + j][0] = fma(u, la0, S.K2[2 + j][0]);
+          S.K2[2 + j][1] = fma(u, la1, S.K2[2 + j][1]);
+          S.K2[2 + j][2] = fma(u, la2, S.K2[2 + j][2]);
         }
       }
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const double phi = wb * p.lam7[b][k];
 #pragma unroll
-        for (int j = 0; j < kLC; ++j) S.K[2 + j][k] = fma(phi, tK[j], S.K[2 + j][k]);
-        if constexpr (I0 == 0) sK[k] = fma(phi, tsK, sK[k]);
+        for (int j = 0; j < kLC; ++j) S.K1[2 + j][k] = fma(phi, tK[j], S.K1[2 + j][k]);
+        if constexpr (I0 == 0) sK1[k] = fma(phi, tsK, sK1[k]);
       }
     }
-    if (!touch) emit_pass<TS, D>(p, I0, l, m, vtx, scale, S, sV, sK);
-    shift_carry(S);
-    separated_pass<TS, D, I0 + kLC>(p, l, m, vtx, touch, n0, n1, n2, scale, shift, xg, S, sV, sK);
+    if (active) emit_sym<TS, D>(p, I0, l, m, vl, vm, scale, S, sV, sK1, sK2);
+    shift_sym(S);
+    sym_pass<TS, D, I0 + kLC>(p, T, l, m, vl, vm, active, scale, L, S, sV, sK1, sK2);
   }
 }
 
-// ------------------------------------------------------------------------------------------
-// Separated pairs: workgroup = (test panel l, 256 consecutive trial panels m); lane = m.
-// ------------------------------------------------------------------------------------------
+// Taylor blocks d0 and d0 + 1 of an unordered separated pair (both of polynomial length N; the
+// second is a copy of the first when d0 + 1 = nt, and then not stored).  r, rho^2 and the two
+// normal products are formed once per point pair for both blocks.  Sums per block: TV (V),
+// TK1 (trial m) and TK2 (trial l).
+struct TaylorSums {
+  double V[2], K1[2][3], K2[2][3];
+};
+
+template <int N>
+__device__ __forceinline__ void sym_taylor2(const AsmParams &p, const SepTabs &T, int d0, int m,
+                                            const SepLane &L, TaylorSums &R) {
+  const int ne = p.ne;
+  const int d1 = min(d0 + 1, p.nt - 1);
+  const double c0 = T.tscale[3 * d0 + 2], c1 = T.tscale[3 * d1 + 2];
+  const double *cv0 = T.taylor + (size_t)(2 * d0) * kTaylorN, *ck0 = cv0 + kTaylorN;
+  const double *cv1 = T.taylor + (size_t)(2 * d1) * kTaylorN, *ck1 = cv1 + kTaylorN;
+#pragma unroll 1
+  for (int b = 0; b < kFarN; ++b) {
+    const double y0 = T.geom[(b * 3 + 0) * ne + m] + L.shift;
+    const double y1 = T.geom[(b * 3 + 1) * ne + m];
+    const double y2 = T.geom[(b * 3 + 2) * ne + m];
+    const double wb = p.w7[b];
+    double tv0 = 0.0, tv1 = 0.0, tk0 = 0.0, tk1 = 0.0;
+#pragma unroll 1
+    for (int a = 0; a < kFarN; ++a) {
+      const double rx = L.xg[(a * 3 + 0) * ne] - y0;
+      const double ry = L.xg[(a * 3 + 1) * ne] - y1;
+      const double rz = L.xg[(a * 3 + 2) * ne] - y2;
+      const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
+      const double wa = p.w7[a];
+      const double wrn1 = wa * fma(rx, L.nm[0], fma(ry, L.nm[1], rz * L.nm[2]));
+      const double wrn2 = -(wa * wb) * fma(rx, L.nl[0], fma(ry, L.nl[1], rz * L.nl[2]));
+      const double w0 = rho2 * c0, w1 = rho2 * c1;
+      const double e0 = exp_neg(w0), e1 = exp_neg(w1);
+      const double pk0 = horner<N>(ck0, w0) * e0, pk1 = horner<N>(ck1, w1) * e1;
+      tv0 = fma(wa * e0, horner<N>(cv0, w0), tv0);
+      tv1 = fma(wa * e1, horner<N>(cv1, w1), tv1);
+      tk0 = fma(wrn1, pk0, tk0);
+      tk1 = fma(wrn1, pk1, tk1);
+      const double u0 = wrn2 * pk0, u1 = wrn2 * pk1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double la = p.lam7[a][k];
+        R.K2[0][k] = fma(u0, la, R.K2[0][k]);
+        R.K2[1][k] = fma(u1, la, R.K2[1][k]);
+      }
+    }
+    R.V[0] = fma(wb, tv0, R.V[0]);
+    R.V[1] = fma(wb, tv1, R.V[1]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double phi = wb * p.lam7[b][k];
+      R.K1[0][k] = fma(phi, tk0, R.K1[0][k]);
+      R.K1[1][k] = fma(phi, tk1, R.K1[1][k]);
+    }
+  }
+}
+
+// The same in float (hardware exp, shorter series), accumulated in double per trial node.
+template <int N>
+__device__ __forceinline__ void sym_taylor2_32(const AsmParams &p, const SepTabs &T, int d0, int m,
+                                               const SepLane &L, TaylorSums &R) {
+  const int ne = p.ne;
+  const int d1 = min(d0 + 1, p.nt - 1);
+  const double c0 = T.tscale[3 * d0 + 2], c1 = T.tscale[3 * d1 + 2];
+  const float *cv0 = T.taylor32 + (size_t)(2 * d0) * kTaylorN32, *ck0 = cv0 + kTaylorN32;
+  const float *cv1 = T.taylor32 + (size_t)(2 * d1) * kTaylorN32, *ck1 = cv1 + kTaylorN32;
+#pragma unroll 1
+  for (int b = 0; b < kFarN; ++b) {
+    const double y0 = T.geom[(b * 3 + 0) * ne + m] + L.shift;
+    const double y1 = T.geom[(b * 3 + 1) * ne + m];
+    const double y2 = T.geom[(b * 3 + 2) * ne + m];
+    const double wb = p.w7[b];
+    float tv0 = 0.0f, tv1 = 0.0f, tk0 = 0.0f, tk1 = 0.0f;
+    float t20[3] = {0.0f, 0.0f, 0.0f}, t21[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+    for (int a = 0; a < kFarN; ++a) {
+      const double rx = L.xg[(a * 3 + 0) * ne] - y0;
+      const double ry = L.xg[(a * 3 + 1) * ne] - y1;
+      const double rz = L.xg[(a * 3 + 2) * ne] - y2;
+      const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
+      const float wa = (float)p.w7[a];
+      const float rn1 = wa * (float)fma(rx, L.nm[0], fma(ry, L.nm[1], rz * L.nm[2]));
+      const float rn2 = -wa * (float)fma(rx, L.nl[0], fma(ry, L.nl[1], rz * L.nl[2]));
+      const float w0 = (float)(rho2 * c0), w1 = (float)(rho2 * c1);
+      const float e0 = __expf(-w0), e1 = __expf(-w1);
+      const float pk0 = hornerf<N>(ck0, w0) * e0, pk1 = hornerf<N>(ck1, w1) * e1;
+      tv0 = fmaf(wa * e0, hornerf<N>(cv0, w0), tv0);
+      tv1 = fmaf(wa * e1, hornerf<N>(cv1, w1), tv1);
+      tk0 = fmaf(rn1, pk0, tk0);
+      tk1 = fmaf(rn1, pk1, tk1);
+      const float u0 = rn2 * pk0, u1 = rn2 * pk1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float la = (float)p.lam7[a][k];
+        t20[k] = fmaf(u0, la, t20[k]);
+        t21[k] = fmaf(u1, la, t21[k]);
+      }
+    }
+    R.V[0] = fma(wb, (double)tv0, R.V[0]);
+    R.V[1] = fma(wb, (double)tv1, R.V[1]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double phi = wb * p.lam7[b][k];
+      R.K1[0][k] = fma(phi, (double)tk0, R.K1[0][k]);
+      R.K1[1][k] = fma(phi, (double)tk1, R.K1[1][k]);
+      R.K2[0][k] = fma(wb, (double)t20[k], R.K2[0][k]);
+      R.K2[1][k] = fma(wb, (double)t21[k], R.K2[1][k]);
+    }
+  }
+}
+
 template <typename TS, int D, bool MIXED>
-__global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restrict__ pp) {
+__global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restrict__ pp,
+                                                      const double *__restrict__ geom,
+                                                      const double *__restrict__ tscale,
+                                                      const double *__restrict__ taylor,
+                                                      const float *__restrict__ taylor32,
+                                                      const int *__restrict__ tdeg) {
   const AsmParams &p = *pp;
+  const SepTabs T{geom, tscale, taylor, taylor32, tdeg};
   const int l = blockIdx.y;
+  if ((int)(blockIdx.x * 256 + 255) <= l) return;  // the whole tile has m <= l
   const int m = blockIdx.x * 256 + threadIdx.x;
   if (m >= p.ne) return;
   const int ne = p.ne;
-  const int32_t *tl = p.tris + 3 * l;
-  const int vtx[3] = {p.tris[3 * m], p.tris[3 * m + 1], p.tris[3 * m + 2]};
+  const int vl[3] = {p.tris[3 * l], p.tris[3 * l + 1], p.tris[3 * l + 2]};
+  const int vm[3] = {p.tris[3 * m], p.tris[3 * m + 1], p.tris[3 * m + 2]};
   bool touch = false;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) touch |= tl[i] == vtx[j];
-  const double n0 = p.geom[21 * ne + m], n1 = p.geom[22 * ne + m], n2 = p.geom[23 * ne + m];
-  const double scale = p.geom[24 * ne + l] * p.geom[24 * ne + m];
-  // touching lanes integrate a far-away copy of their panel and store nothing
-  const double shift = touch ? 1.0e3 : 0.0;
-  const double *xg = p.geom + l;  // test nodes: xg[(a*3+c)*ne]
+    for (int j = 0; j < 3; ++j) touch |= vl[i] == vm[j];
+  const bool active = !touch && m > l;
+  SepLane L;
+  L.xg = geom + l;
+  L.nm[0] = geom[21 * ne + m];
+  L.nm[1] = geom[22 * ne + m];
+  L.nm[2] = geom[23 * ne + m];
+  L.nl[0] = geom[21 * ne + l];
+  L.nl[1] = geom[22 * ne + l];
+  L.nl[2] = geom[23 * ne + l];
+  L.shift = active ? 0.0 : 1.0e3;
+  const double scale = geom[24 * ne + l] * geom[24 * ne + m];
 
   // ---- closed-form levels 0 .. D, kLC per pass ----
-  LevelSums S;
+  {
+    SymSums S;
 #pragma unroll
-  for (int j = 0; j < kLC + 2; ++j) S.V[j] = S.K[j][0] = S.K[j][1] = S.K[j][2] = 0.0;
-  double sV = 0.0, sK[3] = {0.0, 0.0, 0.0};
-  separated_pass<TS, D, 0>(p, l, m, vtx, touch, n0, n1, n2, scale, shift, xg, S, sV, sK);
+    for (int j = 0; j < kLC + 2; ++j) {
+      S.V[j] = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) S.K1[j][q] = S.K2[j][q] = 0.0;
+    }
+    double sV = 0.0, sK1[3] = {0.0, 0.0, 0.0}, sK2[3] = {0.0, 0.0, 0.0};
+    sym_pass<TS, D, 0>(p, T, l, m, vl, vm, active, scale, L, S, sV, sK1, sK2);
+  }
 
-  // ---- Taylor blocks d = D .. nt-1, kLT at a time ----
-  for (int d0 = D; d0 < p.nt; d0 += kLT) {
-    double TV[kLT], TK[kLT][3];
+  // ---- Taylor blocks d = D .. nt-1, two per pass; the polynomial length is chosen per pair of
+  // blocks (the length classes start at even d, so both blocks of a pass share it) ----
+  for (int d = D; d < p.nt; d += 2) {
+    TaylorSums R;
 #pragma unroll
-    for (int j = 0; j < kLT; ++j) TV[j] = TK[j][0] = TK[j][1] = TK[j][2] = 0.0;
-#pragma unroll 1
-    for (int b = 0; b < kFarN; ++b) {
-      const double y0 = p.geom[(b * 3 + 0) * ne + m] + shift;
-      const double y1 = p.geom[(b * 3 + 1) * ne + m];
-      const double y2 = p.geom[(b * 3 + 2) * ne + m];
-      const double wb = p.w7[b];
-      double tk[kLT];
+    for (int j = 0; j < 2; ++j) {
+      R.V[j] = 0.0;
 #pragma unroll
-      for (int j = 0; j < kLT; ++j) tk[j] = 0.0;
-#pragma unroll 1
-      for (int a = 0; a < kFarN; ++a) {
-        const double rx = xg[(a * 3 + 0) * ne] - y0;
-        const double ry = xg[(a * 3 + 1) * ne] - y1;
-        const double rz = xg[(a * 3 + 2) * ne] - y2;
-        const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
-        const double wa = p.w7[a];
-        const double W = wa * wb;
-        const double wrn = wa * fma(rx, n0, fma(ry, n1, rz * n2));
-        if (MIXED && d0 >= p.mixed_d_min) {
-          // mixed precision: the kernel value and its polynomial in float (hardware exp,
-          // degree-8 series), the accumulation in double
-#pragma unroll
-          for (int j = 0; j < kLT; ++j) {
-            const int d = min(d0 + j, p.nt - 1);
-            const float w = (float)(rho2 * p.tscale[3 * d + 2]);
-            const float e = __expf(-w);
-            const float pv = hornerf<kTaylorN32>(p.taylor32 + (size_t)(2 * d) * kTaylorN32, w);
-            const float pk = hornerf<kTaylorN32>(p.taylor32 + (size_t)(2 * d + 1) * kTaylorN32, w);
-            TV[j] += W * (double)(e * pv);
-            tk[j] += wrn * (double)(e * pk);
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < kLT; ++j) {
-            const int d = min(d0 + j, p.nt - 1);
-            const double w = rho2 * p.tscale[3 * d + 2];
-            const double e = exp(-w);
-            const double pv = horner<kTaylorN>(p.taylor + (size_t)(2 * d) * kTaylorN, w);
-            const double pk = horner<kTaylorN>(p.taylor + (size_t)(2 * d + 1) * kTaylorN, w);
-            TV[j] = fma(W * e, pv, TV[j]);
-            tk[j] = fma(wrn * e, pk, tk[j]);
-          }
-        }
+      for (int k = 0; k < 3; ++k) R.K1[j][k] = R.K2[j][k] = 0.0;
+    }
+    if (MIXED && d >= p.mixed_d_min) {
+      switch (T.tdeg[2 * d + 1]) {
+        case 8: sym_taylor2_32<kTaylorN32>(p, T, d, m, L, R); break;
+        case 6: sym_taylor2_32<7>(p, T, d, m, L, R); break;
+        default: sym_taylor2_32<5>(p, T, d, m, L, R); break;
       }
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double phi = wb * p.lam7[b][k];
-#pragma unroll
-        for (int j = 0; j < kLT; ++j) TK[j][k] = fma(phi, tk[j], TK[j][k]);
+    } else {
+      switch (T.tdeg[2 * d]) {
+        case 14: sym_taylor2<15>(p, T, d, m, L, R); break;
+        case 12: sym_taylor2<13>(p, T, d, m, L, R); break;
+        case 10: sym_taylor2<11>(p, T, d, m, L, R); break;
+        case 8: sym_taylor2<9>(p, T, d, m, L, R); break;
+        default: sym_taylor2<7>(p, T, d, m, L, R); break;
       }
     }
-    if (!touch) {
+    if (active) {
 #pragma unroll
-      for (int j = 0; j < kLT; ++j) {
-        const int d = d0 + j;
-        if (d >= p.nt) continue;
-        if (p.do_V) store_block<TS>(p, d, l, m, TV[j] * p.tscale[3 * d] * scale);
+      for (int j = 0; j < 2; ++j) {
+        const int dj = d + j;
+        if (dj >= p.nt) break;
+        if (p.do_V) {
+          const double v = R.V[j] * T.tscale[3 * dj] * scale;
+          store_block<TS>(p, dj, l, m, v);
+          store_block<TS>(p, dj, m, l, v);
+        }
         if (p.do_K) {
-          const double ks = p.tscale[3 * d + 1] * scale;
+          const double ks = T.tscale[3 * dj + 1] * scale;
 #pragma unroll
-          for (int k = 0; k < 3; ++k) add_block_K<TS>(p, d, l, vtx[k], TK[j][k] * ks);
+          for (int k = 0; k < 3; ++k) {
+            add_block_K<TS>(p, dj, l, vm[k], R.K1[j][k] * ks);
+            add_block_K<TS>(p, dj, m, vl[k], R.K2[j][k] * ks);
+          }
         }
       }
     }
@@ -325,6 +555,26 @@ __device__ __forceinline__ TouchPoint touch_point(const TouchPair &tp, const dou
   t.l1 = tab[6 * ntab + q];
   t.l2 = tab[7 * ntab + q];
   return t;
+}
+
+// Taylor block d of one touching pair: lane partial sums over its rule points.
+template <int N>
+__device__ __forceinline__ void touch_taylor(const AsmParams &p, const TouchPair &tp,
+                                             const double *__restrict__ tab, int ntab, int lane,
+                                             int d, double &TV, double TK[3]) {
+  const double cd = p.tscale[3 * d + 2];
+  const double *cv = p.taylor + (size_t)(2 * d) * kTaylorN, *ck = cv + kTaylorN;
+#pragma unroll 1
+  for (int q = lane; q < ntab; q += 64) {
+    const TouchPoint t = touch_point(tp, tab, ntab, q, false);
+    const double w = t.rho2 * cd;
+    const double e = exp(-w);
+    TV = fma(t.W * e, horner<N>(cv, w), TV);
+    const double u = t.wrn * e * horner<N>(ck, w);
+    TK[0] = fma(u, t.l0, TK[0]);
+    TK[1] = fma(u, t.l1, TK[1]);
+    TK[2] = fma(u, t.l2, TK[2]);
+  }
 }
 
 template <typename TS, int D, int I0>
@@ -388,44 +638,24 @@ __global__ __launch_bounds__(64, 2) void k_touching(const AsmParams *__restrict_
   double sV = 0.0, sK[3] = {0.0, 0.0, 0.0};
   touching_pass<TS, D, 0>(p, tp, tab, ntab, lane, l, m, vtx, S, sV, sK);
 
-  for (int d0 = D; d0 < p.nt; d0 += kLT) {
-    double TV[kLT], TK[kLT][3];
-#pragma unroll
-    for (int j = 0; j < kLT; ++j) TV[j] = TK[j][0] = TK[j][1] = TK[j][2] = 0.0;
-#pragma unroll 1
-    for (int q = lane; q < ntab; q += 64) {
-      const TouchPoint t = touch_point(tp, tab, ntab, q, false);
-#pragma unroll
-      for (int j = 0; j < kLT; ++j) {
-        const int d = min(d0 + j, p.nt - 1);
-        const double w = t.rho2 * p.tscale[3 * d + 2];
-        const double e = exp(-w);
-        const double pv = horner<kTaylorN>(p.taylor + (size_t)(2 * d) * kTaylorN, w);
-        const double pk = horner<kTaylorN>(p.taylor + (size_t)(2 * d + 1) * kTaylorN, w);
-        TV[j] = fma(t.W * e, pv, TV[j]);
-        const double u = t.wrn * e * pk;
-        TK[j][0] = fma(u, t.l0, TK[j][0]);
-        TK[j][1] = fma(u, t.l1, TK[j][1]);
-        TK[j][2] = fma(u, t.l2, TK[j][2]);
-      }
+  for (int d = D; d < p.nt; ++d) {
+    double TV = 0.0, TK[3] = {0.0, 0.0, 0.0};
+    switch (p.tdeg[2 * d]) {
+      case 14: touch_taylor<15>(p, tp, tab, ntab, lane, d, TV, TK); break;
+      case 12: touch_taylor<13>(p, tp, tab, ntab, lane, d, TV, TK); break;
+      case 10: touch_taylor<11>(p, tp, tab, ntab, lane, d, TV, TK); break;
+      case 8: touch_taylor<9>(p, tp, tab, ntab, lane, d, TV, TK); break;
+      default: touch_taylor<7>(p, tp, tab, ntab, lane, d, TV, TK); break;
     }
+    TV = wave_sum(TV);
 #pragma unroll
-    for (int j = 0; j < kLT; ++j) {
-      TV[j] = wave_sum(TV[j]);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) TK[j][k] = wave_sum(TK[j][k]);
-    }
+    for (int k = 0; k < 3; ++k) TK[k] = wave_sum(TK[k]);
     if (lane == 0) {
+      if (p.do_V) store_block<TS>(p, d, l, m, TV * p.tscale[3 * d] * tp.scale);
+      if (p.do_K) {
+        const double ks = p.tscale[3 * d + 1] * tp.scale;
 #pragma unroll
-      for (int j = 0; j < kLT; ++j) {
-        const int d = d0 + j;
-        if (d >= p.nt) continue;
-        if (p.do_V) store_block<TS>(p, d, l, m, TV[j] * p.tscale[3 * d] * tp.scale);
-        if (p.do_K) {
-          const double ks = p.tscale[3 * d + 1] * tp.scale;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) add_block_K<TS>(p, d, l, vtx[k], TK[j][k] * ks);
-        }
+        for (int k = 0; k < 3; ++k) add_block_K<TS>(p, d, l, vtx[k], TK[k] * ks);
       }
     }
   }
@@ -434,9 +664,14 @@ __global__ __launch_bounds__(64, 2) void k_touching(const AsmParams *__restrict_
 }  // namespace
 
 template <typename TS, int D>
-static void launch_sep(dim3 grid, hipStream_t s, const AsmParams *dp, bool mixed) {
-  if (mixed) hipLaunchKernelGGL((k_separated<TS, D, true>), grid, dim3(256), 0, s, dp);
-  else hipLaunchKernelGGL((k_separated<TS, D, false>), grid, dim3(256), 0, s, dp);
+static void launch_sep(dim3 grid, hipStream_t s, const AsmParams *dp, const AsmParams &hp,
+                       bool mixed) {
+  if (mixed)
+    hipLaunchKernelGGL((k_separated<TS, D, true>), grid, dim3(256), 0, s, dp, hp.geom, hp.tscale,
+                       hp.taylor, hp.taylor32, hp.tdeg);
+  else
+    hipLaunchKernelGGL((k_separated<TS, D, false>), grid, dim3(256), 0, s, dp, hp.geom, hp.tscale,
+                       hp.taylor, hp.taylor32, hp.tdeg);
 }
 
 void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, int precision,
@@ -444,11 +679,11 @@ void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, int prec
   dim3 grid((p.ne + 255) / 256, p.ne);
   const bool mixed = precision == HB_PREC_MIXED;
   if (p.dsw == 16) {
-    if (storage_f32) launch_sep<float, 16>(grid, s, dp, mixed);
-    else launch_sep<double, 16>(grid, s, dp, mixed);
+    if (storage_f32) launch_sep<float, 16>(grid, s, dp, p, mixed);
+    else launch_sep<double, 16>(grid, s, dp, p, mixed);
   } else {
-    if (storage_f32) launch_sep<float, 8>(grid, s, dp, mixed);
-    else launch_sep<double, 8>(grid, s, dp, mixed);
+    if (storage_f32) launch_sep<float, 8>(grid, s, dp, p, mixed);
+    else launch_sep<double, 8>(grid, s, dp, p, mixed);
   }
 }
 

@@ -377,19 +377,26 @@ int build_tables(hb_ctx *c) {
   p.kK = (double)(1.0L / (8.0L * kPi * al));
   p.kKs = (double)(h / (4.0L * kPi));
 
-  // Taylor tables for d >= dsw
+  // Taylor tables for d >= dsw.  The series converges like d^{-2k}: the truncation order is
+  // chosen per d so that the dropped terms stay below ~1e-15 of the block scale (double path) or
+  // ~1e-9 (float path), which shortens the polynomial as d grows.
+  auto deg64 = [](int d) { return d < 12 ? 14 : d < 16 ? 12 : d < 32 ? 10 : d < 64 ? 8 : 6; };
+  auto deg32 = [](int d) { return d < 12 ? 8 : d < 24 ? 6 : 4; };
   std::vector<double> tay((size_t)c->nt * 2 * kTaylorN, 0.0), tsc((size_t)c->nt * 3, 0.0);
   std::vector<float> tay32((size_t)c->nt * 2 * kTaylorN32, 0.0f);
+  std::vector<int32_t> tdeg((size_t)c->nt * 2, 0);
   for (int d = std::max(1, p.dsw); d < c->nt; ++d) {
     ld pv[kTaylorN], pk[kTaylorN];
-    taylor_poly(1.5L, d, pv);
-    taylor_poly(2.5L, d, pk);
+    tdeg[2 * d] = deg64(d);
+    tdeg[2 * d + 1] = deg32(d);
+    taylor_poly(1.5L, d, pv, tdeg[2 * d]);
+    taylor_poly(2.5L, d, pk, tdeg[2 * d]);
     for (int j = 0; j < kTaylorN; ++j) {
       tay[((size_t)d * 2 + 0) * kTaylorN + j] = (double)pv[j];
       tay[((size_t)d * 2 + 1) * kTaylorN + j] = (double)pk[j];
     }
-    taylor_poly(1.5L, d, pv, kTaylorDeg32);
-    taylor_poly(2.5L, d, pk, kTaylorDeg32);
+    taylor_poly(1.5L, d, pv, tdeg[2 * d + 1]);
+    taylor_poly(2.5L, d, pk, tdeg[2 * d + 1]);
     for (int j = 0; j < kTaylorN32; ++j) {
       tay32[((size_t)d * 2 + 0) * kTaylorN32 + j] = (float)pv[j];
       tay32[((size_t)d * 2 + 1) * kTaylorN32 + j] = (float)pk[j];
@@ -403,6 +410,7 @@ int build_tables(hb_ctx *c) {
   if ((rc = upload(c, (void **)&c->d_taylor, tay.data(), tay.size() * sizeof(double)))) return rc;
   if ((rc = upload(c, (void **)&c->d_tscale, tsc.data(), tsc.size() * sizeof(double)))) return rc;
   if ((rc = upload(c, (void **)&c->d_taylor32, tay32.data(), tay32.size() * sizeof(float)))) return rc;
+  if ((rc = upload(c, (void **)&c->d_tdeg, tdeg.data(), tdeg.size() * sizeof(int32_t)))) return rc;
 
   // geometry SoA: far-rule nodes, normal, area
   size_t ne = (size_t)c->ne;
@@ -488,6 +496,7 @@ int build_tables(hb_ctx *c) {
   }
   p.taylor = c->d_taylor;
   p.taylor32 = c->d_taylor32;
+  p.tdeg = c->d_tdeg;
   p.tscale = c->d_tscale;
   p.geom = c->d_geom;
   p.tris = c->d_tris;
@@ -575,7 +584,7 @@ void hb_destroy(hb_ctx *c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
   void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_taylor,
-                  c->d_taylor32, c->d_V32, c->d_tscale, c->d_mass,
+                  c->d_taylor32, c->d_tdeg, c->d_V32, c->d_tscale, c->d_mass,
                   c->d_V, c->d_K, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->ss[1].d, c->ss[2].d, c->ss[3].d};
   for (void *p : ptrs)

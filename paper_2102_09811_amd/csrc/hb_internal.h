@@ -46,6 +46,7 @@ struct AsmParams {
   double kKs;                  // h / (4 pi)
   const double *taylor;        // [nt][2][kTaylorN] Taylor polynomials in w (V, K), d >= dsw
   const float *taylor32;       // [nt][2][kTaylorN32] shorter series for the float path
+  const int32_t *tdeg;         // [nt][2]: polynomial degree of block d, double and float path
   const double *tscale;        // [nt][3]: V scale, K scale, c_d = 1/(4 alpha d h)
   const double *geom;          // SoA [25][ne]: far nodes (q*3+c), normal (21..23), area (24)
   const int32_t *tris;         // [ne][3]
@@ -106,6 +107,7 @@ struct hb_ctx {
   hb::SSRule ss[4];
   double *d_taylor = nullptr, *d_tscale = nullptr;
   float *d_taylor32 = nullptr;
+  int32_t *d_tdeg = nullptr;
   float *d_V32 = nullptr;            // float copy of V for the mixed-precision inner solver
   bool V32_valid = false;
   double *d_mass = nullptr;          // p0 x p1 mass, [ne][3] = area/3 per local vertex
