@@ -62,13 +62,13 @@ typedef struct hb_options {
                            range 1..8. */
   int32_t d_switch;     /* blocks d >= d_switch are integrated in time by the even Taylor
                            series of the hat-weighted heat kernel instead of second differences
-                           of G^{dtau dt}; default 8, minimum 8; values >= E_t disable it. */
+                           of G^{dtau dt}; one of 3 (default), 8 or 16. */
   int32_t storage;      /* HB_DTYPE_F64 (default) or HB_DTYPE_F32 block storage. */
-  int32_t mixed_d_min;  /* HB_PREC_MIXED: separated pairs at d >= max(mixed_d_min, d_switch),
-                           rounded up to an even d, are evaluated in float (kernel value and a
-                           Taylor polynomial of degree 8, 6 or 4 as d grows, double accumulation);
-                           smaller d, whose second differences cancel, and all touching pairs stay
-                           in double.  Default 8, minimum 2. */
+  int32_t mixed_d_min;  /* HB_PREC_MIXED: separated pairs at d >= d0 are evaluated in float,
+                           where d0 is the first d >= max(mixed_d_min, d_switch) with d - d_switch
+                           even (kernel value and a Taylor polynomial of degree 8, 6 or 4 as d
+                           grows, double accumulation); smaller d and all touching pairs stay in
+                           double.  Default 8, minimum 2. */
   int32_t reserved[12]; /* must be zero */
 } hb_options;
 
@@ -108,7 +108,9 @@ int hb_sizes(const hb_ctx *ctx, int64_t *n_tris, int64_t *n_verts, int32_t *n_t,
  * spatial quadrature over a triangle pair of the exact temporal integral: Radon's 7-point rule
  * on each triangle for separated pairs, Sauter-Schwab [0,1]^4 rules of order opt.ss_order for
  * pairs sharing a vertex, an edge or the whole triangle.  precision: HB_PREC_FP64 or
- * HB_PREC_MIXED.  Block storage is allocated on first use and reused. */
+ * HB_PREC_MIXED.  Block storage is allocated on first use and reused; the double layer also
+ * keeps a workspace of the size of K (its separated-pair contributions of the transposed order,
+ * folded into K at the end of the call). */
 int hb_assemble(hb_ctx *ctx, uint32_t ops, int32_t precision, void *stream);
 
 /* Copy blocks d0 .. d0 + nd - 1 of op (HB_OP_V or HB_OP_K) into dst (layout [nd][rows][cols]

@@ -16,6 +16,8 @@
 // Spatial part: Radon's 7-point rule on both panels for separated pairs (k_separated), regularised
 // [0,1]^4 rules for touching pairs (k_touching).  V entries are stored by their single owner; K
 // contributions are added to the three trial vertices with atomics.
+#include <algorithm>
+
 #include "hb_internal.h"
 
 namespace hb {
@@ -99,6 +101,14 @@ template <typename TS>
 __device__ __forceinline__ void add_block_K(const AsmParams &p, int d, int l, int j, double v) {
   TS *K = (TS *)p.K;
   atomicAdd(&K[((size_t)d * p.ne + l) * p.nv + j], (TS)v);
+}
+
+// Transposed-order double-layer contribution of a separated pair: row m, trial vertex j, kept
+// vertex-major in KT so that the lanes (consecutive m) of a wave add to contiguous addresses.
+template <typename TS>
+__device__ __forceinline__ void add_block_KT(const AsmParams &p, int d, int m, int j, double v) {
+  TS *KT = (TS *)p.KT;
+  atomicAdd(&KT[((size_t)d * p.nv + j) * p.ne + m], (TS)v);
 }
 
 constexpr int kLC = 2;  // closed-form levels per pass over the quadrature points
@@ -228,7 +238,7 @@ __device__ __forceinline__ void emit_sym(const AsmParams &p, int i0, int l, int 
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         add_block_K<TS>(p, d, l, vm[q], k1[q] * scale);
-        add_block_K<TS>(p, d, m, vl[q], k2[q] * scale);
+        add_block_KT<TS>(p, d, m, vl[q], k2[q] * scale);
       }
     }
   }
@@ -474,8 +484,8 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
     sym_pass<TS, D, 0>(p, T, l, m, vl, vm, active, scale, L, S, sV, sK1, sK2);
   }
 
-  // ---- Taylor blocks d = D .. nt-1, two per pass; the polynomial length is chosen per pair of
-  // blocks (the length classes start at even d, so both blocks of a pass share it) ----
+  // ---- Taylor blocks d = D .. nt-1, two per pass, with the polynomial length of the pair's
+  // first block (the tables hold both blocks at that degree) ----
   for (int d = D; d < p.nt; d += 2) {
     TaylorSums R;
 #pragma unroll
@@ -492,6 +502,11 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
       }
     } else {
       switch (T.tdeg[2 * d]) {
+        case 28: sym_taylor2<29>(p, T, d, m, L, R); break;
+        case 24: sym_taylor2<25>(p, T, d, m, L, R); break;
+        case 20: sym_taylor2<21>(p, T, d, m, L, R); break;
+        case 18: sym_taylor2<19>(p, T, d, m, L, R); break;
+        case 16: sym_taylor2<17>(p, T, d, m, L, R); break;
         case 14: sym_taylor2<15>(p, T, d, m, L, R); break;
         case 12: sym_taylor2<13>(p, T, d, m, L, R); break;
         case 10: sym_taylor2<11>(p, T, d, m, L, R); break;
@@ -514,7 +529,7 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
             add_block_K<TS>(p, dj, l, vm[k], R.K1[j][k] * ks);
-            add_block_K<TS>(p, dj, m, vl[k], R.K2[j][k] * ks);
+            add_block_KT<TS>(p, dj, m, vl[k], R.K2[j][k] * ks);
           }
         }
       }
@@ -568,7 +583,7 @@ __device__ __forceinline__ void touch_taylor(const AsmParams &p, const TouchPair
   for (int q = lane; q < ntab; q += 64) {
     const TouchPoint t = touch_point(tp, tab, ntab, q, false);
     const double w = t.rho2 * cd;
-    const double e = exp(-w);
+    const double e = exp_neg(w);
     TV = fma(t.W * e, horner<N>(cv, w), TV);
     const double u = t.wrn * e * horner<N>(ck, w);
     TK[0] = fma(u, t.l0, TK[0]);
@@ -641,6 +656,11 @@ __global__ __launch_bounds__(64, 2) void k_touching(const AsmParams *__restrict_
   for (int d = D; d < p.nt; ++d) {
     double TV = 0.0, TK[3] = {0.0, 0.0, 0.0};
     switch (p.tdeg[2 * d]) {
+      case 28: touch_taylor<29>(p, tp, tab, ntab, lane, d, TV, TK); break;
+      case 24: touch_taylor<25>(p, tp, tab, ntab, lane, d, TV, TK); break;
+      case 20: touch_taylor<21>(p, tp, tab, ntab, lane, d, TV, TK); break;
+      case 18: touch_taylor<19>(p, tp, tab, ntab, lane, d, TV, TK); break;
+      case 16: touch_taylor<17>(p, tp, tab, ntab, lane, d, TV, TK); break;
       case 14: touch_taylor<15>(p, tp, tab, ntab, lane, d, TV, TK); break;
       case 12: touch_taylor<13>(p, tp, tab, ntab, lane, d, TV, TK); break;
       case 10: touch_taylor<11>(p, tp, tab, ntab, lane, d, TV, TK); break;
@@ -678,24 +698,77 @@ void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, int prec
                                int storage_f32, hipStream_t s) {
   dim3 grid((p.ne + 255) / 256, p.ne);
   const bool mixed = precision == HB_PREC_MIXED;
-  if (p.dsw == 16) {
-    if (storage_f32) launch_sep<float, 16>(grid, s, dp, p, mixed);
-    else launch_sep<double, 16>(grid, s, dp, p, mixed);
-  } else {
-    if (storage_f32) launch_sep<float, 8>(grid, s, dp, p, mixed);
-    else launch_sep<double, 8>(grid, s, dp, p, mixed);
+  switch (p.dsw) {
+    case 16:
+      if (storage_f32) launch_sep<float, 16>(grid, s, dp, p, mixed);
+      else launch_sep<double, 16>(grid, s, dp, p, mixed);
+      break;
+    case 8:
+      if (storage_f32) launch_sep<float, 8>(grid, s, dp, p, mixed);
+      else launch_sep<double, 8>(grid, s, dp, p, mixed);
+      break;
+    default:
+      if (storage_f32) launch_sep<float, 3>(grid, s, dp, p, mixed);
+      else launch_sep<double, 3>(grid, s, dp, p, mixed);
+      break;
   }
+}
+
+// K[d][m][j] += KT[d][j][m] through a 64 x 64 tile in LDS, coalesced on both sides.
+template <typename TS>
+__global__ __launch_bounds__(256) void k_fold_KT(const TS *__restrict__ KT, TS *__restrict__ K,
+                                                 int ne, int nv, int nt) {
+  __shared__ TS tile[64][65];
+  const int j0 = blockIdx.x * 64, m0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int d = blockIdx.z; d < nt; d += gridDim.z) {
+    const TS *src = KT + (size_t)d * nv * ne;
+    TS *dst = K + (size_t)d * ne * nv;
+    for (int r = ty; r < 64; r += 4) {
+      const int j = j0 + r, m = m0 + tx;
+      tile[r][tx] = (j < nv && m < ne) ? src[(size_t)j * ne + m] : TS(0);
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+      const int m = m0 + r, j = j0 + tx;
+      if (m < ne && j < nv) dst[(size_t)m * nv + j] += tile[tx][r];
+    }
+    __syncthreads();
+  }
+}
+
+void launch_fold_KT(const AsmParams &p, int storage_f32, hipStream_t s) {
+  dim3 grid((p.nv + 63) / 64, (p.ne + 63) / 64, std::min(p.nt, 4096));
+  if (storage_f32)
+    hipLaunchKernelGGL(k_fold_KT<float>, grid, dim3(256), 0, s, (const float *)p.KT,
+                       (float *)p.K, p.ne, p.nv, p.nt);
+  else
+    hipLaunchKernelGGL(k_fold_KT<double>, grid, dim3(256), 0, s, (const double *)p.KT,
+                       (double *)p.K, p.ne, p.nv, p.nt);
+}
+
+template <typename TS, int D>
+static void launch_touch(dim3 grid, hipStream_t s, const AsmParams *dp, const TouchPair *pairs,
+                         const SSRule &rule) {
+  hipLaunchKernelGGL((k_touching<TS, D>), grid, dim3(64), 0, s, dp, pairs, rule.d, rule.n);
 }
 
 void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,
                               int64_t npairs, const SSRule &rule, int storage_f32, hipStream_t s) {
   dim3 grid((unsigned)npairs);
-  if (p.dsw == 16) {
-    if (storage_f32) hipLaunchKernelGGL((k_touching<float, 16>), grid, dim3(64), 0, s, dp, pairs, rule.d, rule.n);
-    else hipLaunchKernelGGL((k_touching<double, 16>), grid, dim3(64), 0, s, dp, pairs, rule.d, rule.n);
-  } else {
-    if (storage_f32) hipLaunchKernelGGL((k_touching<float, 8>), grid, dim3(64), 0, s, dp, pairs, rule.d, rule.n);
-    else hipLaunchKernelGGL((k_touching<double, 8>), grid, dim3(64), 0, s, dp, pairs, rule.d, rule.n);
+  switch (p.dsw) {
+    case 16:
+      if (storage_f32) launch_touch<float, 16>(grid, s, dp, pairs, rule);
+      else launch_touch<double, 16>(grid, s, dp, pairs, rule);
+      break;
+    case 8:
+      if (storage_f32) launch_touch<float, 8>(grid, s, dp, pairs, rule);
+      else launch_touch<double, 8>(grid, s, dp, pairs, rule);
+      break;
+    default:
+      if (storage_f32) launch_touch<float, 3>(grid, s, dp, pairs, rule);
+      else launch_touch<double, 3>(grid, s, dp, pairs, rule);
+      break;
   }
 }
 

@@ -378,17 +378,23 @@ int build_tables(hb_ctx *c) {
   p.kKs = (double)(h / (4.0L * kPi));
 
   // Taylor tables for d >= dsw.  The series converges like d^{-2k}: the truncation order is
-  // chosen per d so that the dropped terms stay below ~1e-15 of the block scale (double path) or
-  // ~1e-9 (float path), which shortens the polynomial as d grows.
-  auto deg64 = [](int d) { return d < 12 ? 14 : d < 16 ? 12 : d < 32 ? 10 : d < 64 ? 8 : 6; };
+  // chosen per d so that the dropped terms stay below ~2e-16 of the block scale (double path) or
+  // ~1e-9 (float path), which shortens the polynomial as d grows.  The separated-pair kernel
+  // evaluates blocks in pairs (dsw, dsw+1), (dsw+2, dsw+3), ... with one polynomial length, so
+  // each block takes the degree of the first block of its pair.
+  auto deg64 = [](int d) {
+    return d < 4 ? 28 : d < 5 ? 24 : d < 6 ? 20 : d < 7 ? 18 : d < 8 ? 16 : d < 12 ? 14
+         : d < 16 ? 12 : d < 32 ? 10 : d < 64 ? 8 : 6;
+  };
   auto deg32 = [](int d) { return d < 12 ? 8 : d < 24 ? 6 : 4; };
+  auto pass_start = [&](int d) { return d - ((d - p.dsw) & 1); };
   std::vector<double> tay((size_t)c->nt * 2 * kTaylorN, 0.0), tsc((size_t)c->nt * 3, 0.0);
   std::vector<float> tay32((size_t)c->nt * 2 * kTaylorN32, 0.0f);
   std::vector<int32_t> tdeg((size_t)c->nt * 2, 0);
   for (int d = std::max(1, p.dsw); d < c->nt; ++d) {
     ld pv[kTaylorN], pk[kTaylorN];
-    tdeg[2 * d] = deg64(d);
-    tdeg[2 * d + 1] = deg32(d);
+    tdeg[2 * d] = deg64(pass_start(d));
+    tdeg[2 * d + 1] = deg32(pass_start(d));
     taylor_poly(1.5L, d, pv, tdeg[2 * d]);
     taylor_poly(2.5L, d, pk, tdeg[2 * d]);
     for (int j = 0; j < kTaylorN; ++j) {
@@ -514,7 +520,7 @@ void hb_default_options(hb_options *o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
   o->ss_order = 4;
-  o->d_switch = 8;
+  o->d_switch = 3;
   o->storage = HB_DTYPE_F64;
   o->mixed_d_min = 8;
 }
@@ -540,8 +546,8 @@ int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t 
   hb_default_options(&o);
   if (opt) o = *opt;
   if (o.ss_order < 1 || o.ss_order > 8) return fail(nullptr, HB_EINVAL, "ss_order must be in 1..8");
-  if (o.d_switch != 8 && o.d_switch != 16)
-    return fail(nullptr, HB_EINVAL, "d_switch must be 8 or 16");
+  if (o.d_switch != 3 && o.d_switch != 8 && o.d_switch != 16)
+    return fail(nullptr, HB_EINVAL, "d_switch must be 3, 8 or 16");
   if (o.storage != HB_DTYPE_F64 && o.storage != HB_DTYPE_F32)
     return fail(nullptr, HB_EINVAL, "storage must be HB_DTYPE_F64 or HB_DTYPE_F32");
   if (o.mixed_d_min < 2) return fail(nullptr, HB_EINVAL, "mixed_d_min must be >= 2");
@@ -585,7 +591,7 @@ void hb_destroy(hb_ctx *c) {
   (void)hipDeviceSynchronize();
   void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_taylor,
                   c->d_taylor32, c->d_tdeg, c->d_V32, c->d_tscale, c->d_mass,
-                  c->d_V, c->d_K, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
+                  c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->ss[1].d, c->ss[2].d, c->ss[3].d};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -612,20 +618,29 @@ int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
   size_t nV = (size_t)c->nt * c->ne * c->ne, nK = (size_t)c->nt * c->ne * c->nv;
   if ((ops & HB_OP_V) && !c->d_V) HB_HIP(c, hipMalloc(&c->d_V, nV * esz));
   if ((ops & HB_OP_K) && !c->d_K) HB_HIP(c, hipMalloc(&c->d_K, nK * esz));
+  if ((ops & HB_OP_K) && !c->d_KT) HB_HIP(c, hipMalloc(&c->d_KT, nK * esz));
   hb::AsmParams &p = c->launch;
   p = c->params;
   p.V = c->d_V;
   p.K = c->d_K;
+  p.KT = c->d_KT;
   p.do_V = (ops & HB_OP_V) ? 1 : 0;
   p.do_K = (ops & HB_OP_K) ? 1 : 0;
   p.mixed_d_min = precision == HB_PREC_MIXED ? c->opt.mixed_d_min : c->nt;
   if (!c->d_params) HB_HIP(c, hipMalloc(&c->d_params, sizeof(hb::AsmParams)));
   HB_HIP(c, hipMemcpyAsync(c->d_params, &p, sizeof(p), hipMemcpyHostToDevice, s));
   // K is accumulated over the (up to three) panels of each trial vertex: clear it first
-  if (p.do_K) HB_HIP(c, hipMemsetAsync(c->d_K, 0, nK * esz, s));
+  if (p.do_K) {
+    HB_HIP(c, hipMemsetAsync(c->d_K, 0, nK * esz, s));
+    HB_HIP(c, hipMemsetAsync(c->d_KT, 0, nK * esz, s));
+  }
   HB_HIP(c, hipEventRecord(c->ev[0], s));
   hb::launch_assemble_separated(c->d_params, p, precision, c->storage_f32, s);
   HB_HIP(c, hipGetLastError());
+  if (p.do_K) {
+    hb::launch_fold_KT(p, c->storage_f32, s);
+    HB_HIP(c, hipGetLastError());
+  }
   HB_HIP(c, hipEventRecord(c->ev[1], s));
   int64_t off = 0;
   for (int cls = 3; cls >= 1; --cls) {

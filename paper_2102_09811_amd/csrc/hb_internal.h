@@ -12,9 +12,9 @@ struct hb_ctx;
 
 namespace hb {
 
-// Closed-form levels handled in registers: blocks 0 .. kClosedBlocks-1 come from second
-// differences of G^{dtau dt} at levels 0 .. kClosedBlocks; later blocks use the Taylor form.
-constexpr int kTaylorDeg = 16;       // degree of the Taylor polynomial in w = rho^2/(4 alpha d h)
+// Blocks 0 .. d_switch-1 come from second differences of G^{dtau dt} at the closed-form levels
+// 0 .. d_switch; later blocks use the Taylor form, whose degree falls as d grows (28 at d = 3).
+constexpr int kTaylorDeg = 28;       // largest degree of the Taylor polynomial in w = rho^2/(4 alpha d h)
 constexpr int kTaylorN = kTaylorDeg + 1;
 constexpr int kTaylorDeg32 = 8;      // degree used by the float evaluation (mixed precision)
 constexpr int kTaylorN32 = kTaylorDeg32 + 1;
@@ -52,6 +52,9 @@ struct AsmParams {
   const int32_t *tris;         // [ne][3]
   void *V;                     // [nt][ne][ne]
   void *K;                     // [nt][ne][nv]
+  void *KT;                    // [nt][nv][ne]: double-layer contributions of the transposed order
+                               // of separated pairs, vertex-major so that a wave's atomics are
+                               // contiguous; folded into K after the separated kernel
   int32_t do_V, do_K;
 };
 
@@ -74,6 +77,7 @@ struct SSRule {
 // dp: device copy of p (kernels read their parameters from device memory)
 void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, int precision,
                                int storage_f32, hipStream_t s);
+void launch_fold_KT(const AsmParams &p, int storage_f32, hipStream_t s);
 void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,
                               int64_t npairs, const SSRule &rule, int storage_f32, hipStream_t s);
 
@@ -111,7 +115,7 @@ struct hb_ctx {
   float *d_V32 = nullptr;            // float copy of V for the mixed-precision inner solver
   bool V32_valid = false;
   double *d_mass = nullptr;          // p0 x p1 mass, [ne][3] = area/3 per local vertex
-  void *d_V = nullptr, *d_K = nullptr;
+  void *d_V = nullptr, *d_K = nullptr, *d_KT = nullptr;
   bool have_V = false, have_K = false;
   int storage_f32 = 0;
   hb::AsmParams params{};            // tables filled at creation

@@ -40,6 +40,7 @@ CASES = {
     "octa_nt3": (octahedron, 2.0, 1.0, 3, {}),
     "cube2_nt40": (lambda: cube(2), 0.5, 1.0, 40, {}),
     "cube4_nt16": (lambda: cube(4), 1.0, 1.0, 16, {}),
+    "cube4_nt16_dsw8": (lambda: cube(4), 1.0, 1.0, 16, {"d_switch": 8}),
     "cube4_nt16_dsw16": (lambda: cube(4), 1.0, 1.0, 16, {"d_switch": 16}),
     "cube4_nt12_ss6": (lambda: cube(4), 0.7, 1.5, 12, {"ss_order": 6}),
 }
@@ -58,7 +59,7 @@ def test_blocks_match_oracle(name):
     if opts.get("d_switch") == 16:
         # all blocks from second differences of G^{dtau dt}: the rounding error of the three
         # O(sqrt(d h)) terms is amplified ~4 d^2 relative to the block (the reason the default
-        # path switches to the Taylor form at d = 8)
+        # path switches to the Taylor form at d = 3)
         d = np.arange(nt)
         assert np.all(eV[:8] <= TOL) and np.all(eK[:8] <= TOL), (eV, eK)
         assert np.all(eV <= 2e-14 * np.maximum(d, 1) ** 2), eV
