@@ -572,23 +572,32 @@ __device__ __forceinline__ TouchPoint touch_point(const TouchPair &tp, const dou
   return t;
 }
 
-// Taylor block d of one touching pair: lane partial sums over its rule points.
+// Taylor blocks d0 and d0 + 1 of one touching pair (polynomial length N, the second block a copy
+// of the first when d0 + 1 = nt): lane partial sums over its rule points, the rule point shared
+// by both blocks.
 template <int N>
-__device__ __forceinline__ void touch_taylor(const AsmParams &p, const TouchPair &tp,
-                                             const double *__restrict__ tab, int ntab, int lane,
-                                             int d, double &TV, double TK[3]) {
-  const double cd = p.tscale[3 * d + 2];
-  const double *cv = p.taylor + (size_t)(2 * d) * kTaylorN, *ck = cv + kTaylorN;
+__device__ __forceinline__ void touch_taylor2(const AsmParams &p, const SepTabs &T,
+                                              const TouchPair &tp, const double *__restrict__ tab,
+                                              int ntab, int lane, int d0, TaylorSums &R) {
+  const int d1 = min(d0 + 1, p.nt - 1);
+  const double c0 = T.tscale[3 * d0 + 2], c1 = T.tscale[3 * d1 + 2];
+  const double *cv0 = T.taylor + (size_t)(2 * d0) * kTaylorN, *ck0 = cv0 + kTaylorN;
+  const double *cv1 = T.taylor + (size_t)(2 * d1) * kTaylorN, *ck1 = cv1 + kTaylorN;
 #pragma unroll 1
   for (int q = lane; q < ntab; q += 64) {
     const TouchPoint t = touch_point(tp, tab, ntab, q, false);
-    const double w = t.rho2 * cd;
-    const double e = exp_neg(w);
-    TV = fma(t.W * e, horner<N>(cv, w), TV);
-    const double u = t.wrn * e * horner<N>(ck, w);
-    TK[0] = fma(u, t.l0, TK[0]);
-    TK[1] = fma(u, t.l1, TK[1]);
-    TK[2] = fma(u, t.l2, TK[2]);
+    const double w0 = t.rho2 * c0, w1 = t.rho2 * c1;
+    const double e0 = exp_neg(w0), e1 = exp_neg(w1);
+    R.V[0] = fma(t.W * e0, horner<N>(cv0, w0), R.V[0]);
+    R.V[1] = fma(t.W * e1, horner<N>(cv1, w1), R.V[1]);
+    const double u0 = t.wrn * e0 * horner<N>(ck0, w0);
+    const double u1 = t.wrn * e1 * horner<N>(ck1, w1);
+    R.K1[0][0] = fma(u0, t.l0, R.K1[0][0]);
+    R.K1[0][1] = fma(u0, t.l1, R.K1[0][1]);
+    R.K1[0][2] = fma(u0, t.l2, R.K1[0][2]);
+    R.K1[1][0] = fma(u1, t.l0, R.K1[1][0]);
+    R.K1[1][1] = fma(u1, t.l1, R.K1[1][1]);
+    R.K1[1][2] = fma(u1, t.l2, R.K1[1][2]);
   }
 }
 
@@ -638,10 +647,14 @@ __device__ __forceinline__ void touching_pass(const AsmParams &p, const TouchPai
 }
 
 template <typename TS, int D>
-__global__ __launch_bounds__(64, 2) void k_touching(const AsmParams *__restrict__ pp,
+__global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict__ pp,
                                                     const TouchPair *__restrict__ pairs,
-                                                    const double *__restrict__ tab, int ntab) {
+                                                    const double *__restrict__ tab, int ntab,
+                                                    const double *__restrict__ tscale,
+                                                    const double *__restrict__ taylor,
+                                                    const int *__restrict__ tdeg) {
   const AsmParams &p = *pp;
+  const SepTabs T{nullptr, tscale, taylor, nullptr, tdeg};
   const TouchPair &tp = pairs[blockIdx.x];
   const int lane = threadIdx.x;
   const int l = tp.l, m = tp.m;
@@ -653,29 +666,43 @@ __global__ __launch_bounds__(64, 2) void k_touching(const AsmParams *__restrict_
   double sV = 0.0, sK[3] = {0.0, 0.0, 0.0};
   touching_pass<TS, D, 0>(p, tp, tab, ntab, lane, l, m, vtx, S, sV, sK);
 
-  for (int d = D; d < p.nt; ++d) {
-    double TV = 0.0, TK[3] = {0.0, 0.0, 0.0};
-    switch (p.tdeg[2 * d]) {
-      case 28: touch_taylor<29>(p, tp, tab, ntab, lane, d, TV, TK); break;
-      case 24: touch_taylor<25>(p, tp, tab, ntab, lane, d, TV, TK); break;
-      case 20: touch_taylor<21>(p, tp, tab, ntab, lane, d, TV, TK); break;
-      case 18: touch_taylor<19>(p, tp, tab, ntab, lane, d, TV, TK); break;
-      case 16: touch_taylor<17>(p, tp, tab, ntab, lane, d, TV, TK); break;
-      case 14: touch_taylor<15>(p, tp, tab, ntab, lane, d, TV, TK); break;
-      case 12: touch_taylor<13>(p, tp, tab, ntab, lane, d, TV, TK); break;
-      case 10: touch_taylor<11>(p, tp, tab, ntab, lane, d, TV, TK); break;
-      case 8: touch_taylor<9>(p, tp, tab, ntab, lane, d, TV, TK); break;
-      default: touch_taylor<7>(p, tp, tab, ntab, lane, d, TV, TK); break;
+  for (int d = D; d < p.nt; d += 2) {
+    TaylorSums R;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      R.V[j] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) R.K1[j][k] = 0.0;
     }
-    TV = wave_sum(TV);
+    switch (T.tdeg[2 * d]) {
+      case 28: touch_taylor2<29>(p, T, tp, tab, ntab, lane, d, R); break;
+      case 24: touch_taylor2<25>(p, T, tp, tab, ntab, lane, d, R); break;
+      case 20: touch_taylor2<21>(p, T, tp, tab, ntab, lane, d, R); break;
+      case 18: touch_taylor2<19>(p, T, tp, tab, ntab, lane, d, R); break;
+      case 16: touch_taylor2<17>(p, T, tp, tab, ntab, lane, d, R); break;
+      case 14: touch_taylor2<15>(p, T, tp, tab, ntab, lane, d, R); break;
+      case 12: touch_taylor2<13>(p, T, tp, tab, ntab, lane, d, R); break;
+      case 10: touch_taylor2<11>(p, T, tp, tab, ntab, lane, d, R); break;
+      case 8: touch_taylor2<9>(p, T, tp, tab, ntab, lane, d, R); break;
+      default: touch_taylor2<7>(p, T, tp, tab, ntab, lane, d, R); break;
+    }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) TK[k] = wave_sum(TK[k]);
+    for (int j = 0; j < 2; ++j) {
+      R.V[j] = wave_sum(R.V[j]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) R.K1[j][k] = wave_sum(R.K1[j][k]);
+    }
     if (lane == 0) {
-      if (p.do_V) store_block<TS>(p, d, l, m, TV * p.tscale[3 * d] * tp.scale);
-      if (p.do_K) {
-        const double ks = p.tscale[3 * d + 1] * tp.scale;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) add_block_K<TS>(p, d, l, vtx[k], TK[k] * ks);
+      for (int j = 0; j < 2; ++j) {
+        const int dj = d + j;
+        if (dj >= p.nt) break;
+        if (p.do_V) store_block<TS>(p, dj, l, m, R.V[j] * T.tscale[3 * dj] * tp.scale);
+        if (p.do_K) {
+          const double ks = T.tscale[3 * dj + 1] * tp.scale;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) add_block_K<TS>(p, dj, l, vtx[k], R.K1[j][k] * ks);
+        }
       }
     }
   }
@@ -748,9 +775,10 @@ void launch_fold_KT(const AsmParams &p, int storage_f32, hipStream_t s) {
 }
 
 template <typename TS, int D>
-static void launch_touch(dim3 grid, hipStream_t s, const AsmParams *dp, const TouchPair *pairs,
-                         const SSRule &rule) {
-  hipLaunchKernelGGL((k_touching<TS, D>), grid, dim3(64), 0, s, dp, pairs, rule.d, rule.n);
+static void launch_touch(dim3 grid, hipStream_t s, const AsmParams *dp, const AsmParams &hp,
+                         const TouchPair *pairs, const SSRule &rule) {
+  hipLaunchKernelGGL((k_touching<TS, D>), grid, dim3(64), 0, s, dp, pairs, rule.d, rule.n,
+                     hp.tscale, hp.taylor, hp.tdeg);
 }
 
 void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,
@@ -758,16 +786,16 @@ void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const Tou
   dim3 grid((unsigned)npairs);
   switch (p.dsw) {
     case 16:
-      if (storage_f32) launch_touch<float, 16>(grid, s, dp, pairs, rule);
-      else launch_touch<double, 16>(grid, s, dp, pairs, rule);
+      if (storage_f32) launch_touch<float, 16>(grid, s, dp, p, pairs, rule);
+      else launch_touch<double, 16>(grid, s, dp, p, pairs, rule);
       break;
     case 8:
-      if (storage_f32) launch_touch<float, 8>(grid, s, dp, pairs, rule);
-      else launch_touch<double, 8>(grid, s, dp, pairs, rule);
+      if (storage_f32) launch_touch<float, 8>(grid, s, dp, p, pairs, rule);
+      else launch_touch<double, 8>(grid, s, dp, p, pairs, rule);
       break;
     default:
-      if (storage_f32) launch_touch<float, 3>(grid, s, dp, pairs, rule);
-      else launch_touch<double, 3>(grid, s, dp, pairs, rule);
+      if (storage_f32) launch_touch<float, 3>(grid, s, dp, p, pairs, rule);
+      else launch_touch<double, 3>(grid, s, dp, p, pairs, rule);
       break;
   }
 }
