@@ -24,185 +24,181 @@ namespace {
   } while (0)
 
 // ------------------------------------------------------------------------------------------
-// Block-Toeplitz product Y[k][r] = sum_{d <= k} sum_c A^d[r][c] X[k-d][c] on FP64 MFMA.
-// Workgroup = 64 rows (wave w: rows 16w..16w+15) x all E_t time steps, for the d range of its
-// group g.  Per 16-column slice of A the source vector X[:, slice] is staged in LDS once and
-// reused for every d of the group (the time shift k - d is applied when reading it); per d the
-// 64 x 16 tile of A^d is staged and fed to v_mfma_f64_16x16x4 (A operand: lane l holds
-// A[l % 16][l / 16], B operand: X[l / 16][l % 16]; accumulator register i of lane l holds row
-// l / 16 + 4 i, column l % 16).  Time chunks that end before d are skipped.  Each group writes its partial
-// result P[g][k][r]; k_sum_groups adds the groups (deterministic order).
+// Block-Toeplitz product Y[k][r] = sum_{d <= k} sum_c A^d[r][c] X[k-d][c] on MFMA
+// (v_mfma_f64_16x16x4 for double blocks, v_mfma_f32_16x16x4 for float blocks).
+// Workgroup = 64 rows (wave w: rows 16w..16w+15) x all E_t time steps, for the column chunks of
+// its group g and the d range of its slice z.  Per 32-column chunk the source X[:, chunk] is
+// staged in LDS once, behind 16 zero rows, and serves every d (the time shift k - d is applied
+// when reading it).  A streams from HBM straight into MFMA fragments: lane l (lm = l % 16,
+// lk = l / 16) loads the 8 consecutive entries A^d[row 16w + lm][c0 + 8 lk .. + 8] and feeds entry
+// s as the k = lk operand of step s, matched by the B operand X[time 16n + lm - d][c0 + 8 lk + s]
+// (the steps cover the 32 columns in a permuted order).  The next d's fragment is loaded while
+// the current one runs.  Time chunks that end before d are skipped.  Each (g, z) writes the
+// partial result P[g][z][k][r]; k_sum_groups adds them in a fixed order.
 // ------------------------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int TR = 64;
-
-// Rounds q = 0 .. nd * nchunk - 1 walk (d, column slice); the tiles of round q + 1 are fetched
-// into registers while round q runs on the MFMA units.
-template <typename TA, int NTC, int TC>
-__global__ __launch_bounds__(256) void k_toeplitz_mfma(const TA *__restrict__ A,
-                                                       const double *__restrict__ X,
-                                                       double *__restrict__ P, int nt, int R,
-                                                       int C, int dper) {
-  constexpr int NT = NTC * 16;                 // padded time extent
-  constexpr int A_PER = TR * TC / 256;         // A tile elements per thread
-  constexpr int X_PER = TC * NT / 256;         // X tile elements per thread
-  const int r0 = blockIdx.x * TR;
-  const int g = blockIdx.y;
-  const int d0 = g * dper, d1 = min(d0 + dper, nt);
-  if (d0 >= d1) return;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int lm = lane & 15, lk = lane >> 4;
-  // row stride TC + 4 doubles: the fragment reads (row = lane % 16, column = lane / 16) hit each
-  // LDS bank pair exactly twice
-  __shared__ double Xs[NT][TC + 4];
-  __shared__ double As[TR][TC + 4];
-  const int nchunk = (C + TC - 1) / TC;
-  const int nround = (d1 - d0) * nchunk;
-  double pa[A_PER], px[X_PER];
-  auto fetch = [&](int q) {
-    const int d = d0 + q / nchunk, c0 = (q % nchunk) * TC;
-    const TA *Ad = A + (size_t)d * R * C;
-#pragma unroll
-    for (int i = 0; i < A_PER; ++i) {
-      const int e = tid + 256 * i, rr = e / TC, cc = e % TC, r = r0 + rr, c = c0 + cc;
-      pa[i] = (r < R && c < C) ? (double)Ad[(size_t)r * C + c] : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < X_PER; ++i) {
-      const int e = tid + 256 * i, k = e / TC, cc = e % TC, c = c0 + cc, j = k - d;
-      px[i] = (k < nt && j >= 0 && c < C) ? X[(size_t)j * C + c] : 0.0;
-    }
-  };
-  v4d acc[NTC];
-#pragma unroll
-  for (int n = 0; n < NTC; ++n) acc[n] = v4d{0.0, 0.0, 0.0, 0.0};
-  fetch(0);
-  for (int q = 0; q < nround; ++q) {
-    const int d = d0 + q / nchunk;
-#pragma unroll
-    for (int i = 0; i < A_PER; ++i) {
-      const int e = tid + 256 * i;
-      As[e / TC][e % TC] = pa[i];
-    }
-#pragma unroll
-    for (int i = 0; i < X_PER; ++i) {
-      const int e = tid + 256 * i;
-      Xs[e / TC][e % TC] = px[i];
-    }
-    __syncthreads();
-    if (q + 1 < nround) fetch(q + 1);
-#pragma unroll 2
-    for (int s = 0; s < TC / 4; ++s) {
-      const double a = As[wave * 16 + lm][4 * s + lk];
-#pragma unroll
-      for (int n = 0; n < NTC; ++n) {
-        if (16 * n + 15 < d) continue;  // the whole chunk lies before d
-        acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Xs[16 * n + lm][4 * s + lk], acc[n], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int n = 0; n < NTC; ++n) {
-    const int k = 16 * n + lm;
-    if (k >= nt) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = r0 + wave * 16 + lk + 4 * i;
-      if (r < R) P[((size_t)g * nt + k) * R + r] = acc[n][i];
-    }
-  }
-}
-
-// Y[i] = sum_g P[g][i]
-__global__ void k_sum_groups(const double *__restrict__ P, int G, size_t n, double *__restrict__ Y) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int g = 0; g < G; ++g) s += P[(size_t)g * n + i];
-    Y[i] = s;
-  }
-}
-
-// The same product with float blocks on v_mfma_f32_16x16x4f32: the source vector is rounded to
-// float when staged, products accumulate in float per group, groups are added in double.
-// (accumulator register i of lane l holds row 4 (l / 16) + i, column l % 16 for this opcode)
 typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int TR = 64;   // rows per workgroup
+constexpr int kTC = 32;  // columns per chunk
+constexpr int kXS = kTC + 1;
 
-template <int NTC, int TC>
-__global__ __launch_bounds__(256) void k_toeplitz_mfma32(const float *__restrict__ A,
-                                                         const double *__restrict__ X,
-                                                         float *__restrict__ P, int nt, int R,
-                                                         int C, int dper) {
-  constexpr int NT = NTC * 16;
-  constexpr int A_PER = TR * TC / 256;
-  constexpr int X_PER = TC * NT / 256;
-  const int r0 = blockIdx.x * TR;
-  const int g = blockIdx.y;
-  const int d0 = g * dper, d1 = min(d0 + dper, nt);
-  if (d0 >= d1) return;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int lm = lane & 15, lk = lane >> 4;
-  __shared__ float Xs[NT][TC + 4];
-  __shared__ float As[TR][TC + 4];
-  const int nchunk = (C + TC - 1) / TC;
-  const int nround = (d1 - d0) * nchunk;
-  float pa[A_PER], px[X_PER];
-  auto fetch = [&](int q) {
-    const int d = d0 + q / nchunk, c0 = (q % nchunk) * TC;
-    const float *Ad = A + (size_t)d * R * C;
+template <typename TA> struct Mfma;
+template <> struct Mfma<double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator register i of lane (lm, lk) holds row lk + 4 i, column lm
+  static __device__ __forceinline__ int row(int lk, int i) { return lk + 4 * i; }
+};
+template <> struct Mfma<float> {
+  typedef v4f acc_t;
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator register i of lane (lm, lk) holds row 4 lk + i, column lm
+  static __device__ __forceinline__ int row(int lk, int i) { return 4 * lk + i; }
+};
+
+// This lane's 8 consecutive entries of a block row (zero outside the block).  vec: the row
+// segment is 16-byte aligned and inside the block.
+template <typename TA>
+__device__ __forceinline__ void load_frag(TA (&a)[8], const TA *__restrict__ p, bool vec,
+                                          bool full, bool row_ok, int ncol) {
+  if (vec) {
+    if constexpr (sizeof(TA) == 8) {
+      typedef double v2 __attribute__((ext_vector_type(2)));
+      const v2 *q = (const v2 *)p;
 #pragma unroll
-    for (int i = 0; i < A_PER; ++i) {
-      const int e = tid + 256 * i, rr = e / TC, cc = e % TC, r = r0 + rr, c = c0 + cc;
-      pa[i] = (r < R && c < C) ? Ad[(size_t)r * C + c] : 0.0f;
-    }
+      for (int i = 0; i < 4; ++i) {
+        const v2 t = q[i];
+        a[2 * i] = t[0];
+        a[2 * i + 1] = t[1];
+      }
+    } else {
+      typedef float v4 __attribute__((ext_vector_type(4)));
+      const v4 *q = (const v4 *)p;
 #pragma unroll
-    for (int i = 0; i < X_PER; ++i) {
-      const int e = tid + 256 * i, k = e / TC, cc = e % TC, c = c0 + cc, j = k - d;
-      px[i] = (k < nt && j >= 0 && c < C) ? (float)X[(size_t)j * C + c] : 0.0f;
-    }
-  };
-  v4f acc[NTC];
-#pragma unroll
-  for (int n = 0; n < NTC; ++n) acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
-  fetch(0);
-  for (int q = 0; q < nround; ++q) {
-    const int d = d0 + q / nchunk;
-#pragma unroll
-    for (int i = 0; i < A_PER; ++i) {
-      const int e = tid + 256 * i;
-      As[e / TC][e % TC] = pa[i];
-    }
-#pragma unroll
-    for (int i = 0; i < X_PER; ++i) {
-      const int e = tid + 256 * i;
-      Xs[e / TC][e % TC] = px[i];
-    }
-    __syncthreads();
-    if (q + 1 < nround) fetch(q + 1);
-#pragma unroll 2
-    for (int s = 0; s < TC / 4; ++s) {
-      const float a = As[wave * 16 + lm][4 * s + lk];
-#pragma unroll
-      for (int n = 0; n < NTC; ++n) {
-        if (16 * n + 15 < d) continue;
-        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Xs[16 * n + lm][4 * s + lk], acc[n], 0, 0, 0);
+      for (int i = 0; i < 2; ++i) {
+        const v4 t = q[i];
+        a[4 * i] = t[0];
+        a[4 * i + 1] = t[1];
+        a[4 * i + 2] = t[2];
+        a[4 * i + 3] = t[3];
       }
     }
-    __syncthreads();
+  } else if (full) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) a[s] = p[s];
+  } else {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) a[s] = (row_ok && s < ncol) ? p[s] : TA(0);
   }
+}
+
+// MFMA steps of block d with fragment a for the time chunks NS..NTC-1.
+template <typename TA, int NTC, int NS>
+__device__ __forceinline__ void toeplitz_block(typename Mfma<TA>::acc_t (&acc)[NTC], const TA (&a)[8],
+                                               const TA *Xs, int d, int lm, int lk) {
+#pragma unroll
+  for (int n = NS; n < NTC; ++n) {
+    const TA *xb = Xs + (16 + 16 * n + lm - d) * kXS + 8 * lk;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc[n] = Mfma<TA>::mma(a[s], xb[s], acc[n]);
+  }
+}
+
+// Blocks d = dlo .. dhi-1, all of whose nonzero output times lie in the time chunks NS..NTC-1.
+// On entry a holds the fragment of block max(d0, 16 NS) (if that block is in range); two
+// fragment buffers alternate, the next block's loads in flight while a block is multiplied.
+template <typename TA, int NTC, int NS>
+struct ToeplitzRange {
+  typedef typename Mfma<TA>::acc_t acc_t;
+  static __device__ __forceinline__ void run(acc_t (&acc)[NTC], TA (&a)[8], const TA *Xs,
+                                             const TA *arow, size_t blk, int d0, int d1, bool vec,
+                                             bool full, bool row_ok, int ncol, int lm, int lk) {
+    if constexpr (NS < NTC) {
+      const int dlo = max(d0, 16 * NS), dhi = min(d1, 16 * NS + 16);
+      int d = dlo;
+      for (; d + 1 < dhi; d += 2) {
+        TA b[8];
+        load_frag(b, arow + (size_t)(d + 1) * blk, vec, full, row_ok, ncol);
+        toeplitz_block<TA, NTC, NS>(acc, a, Xs, d, lm, lk);
+        if (d + 2 < d1) load_frag(a, arow + (size_t)(d + 2) * blk, vec, full, row_ok, ncol);
+        toeplitz_block<TA, NTC, NS>(acc, b, Xs, d + 1, lm, lk);
+      }
+      if (d < dhi) {
+        TA b[8];
+        if (d + 1 < d1) load_frag(b, arow + (size_t)(d + 1) * blk, vec, full, row_ok, ncol);
+        toeplitz_block<TA, NTC, NS>(acc, a, Xs, d, lm, lk);
+        if (d + 1 < d1) {
+#pragma unroll
+          for (int s = 0; s < 8; ++s) a[s] = b[s];
+        }
+      }
+      ToeplitzRange<TA, NTC, NS + 1>::run(acc, a, Xs, arow, blk, d0, d1, vec, full, row_ok, ncol,
+                                          lm, lk);
+    }
+  }
+};
+
+template <typename TA, int NTC>
+__global__ __launch_bounds__(256) void k_toeplitz(const TA *__restrict__ A,
+                                                  const double *__restrict__ X,
+                                                  TA *__restrict__ P, int nt, int R, int C,
+                                                  int cpg, int dper) {
+  typedef Mfma<TA> M;
+  constexpr int NT = 16 * NTC;
+  __shared__ TA Xs[(NT + 16) * kXS];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, lm = lane & 15, lk = lane >> 4;
+  const int r = blockIdx.x * TR + 16 * w + lm;  // A row of this lane's fragments
+  const int g = blockIdx.y, z = blockIdx.z;
+  const int nchunk = (C + kTC - 1) / kTC;
+  const int q0 = g * cpg, q1 = min(q0 + cpg, nchunk);
+  const int d0 = z * dper, d1 = min(d0 + dper, nt);
+  typename M::acc_t acc[NTC];
+#pragma unroll
+  for (int n = 0; n < NTC; ++n) acc[n] = M::zero();
+  const size_t blk = (size_t)R * C;
+  for (int q = q0; q < q1 && d0 < d1; ++q) {
+    const int c0 = q * kTC;
+    __syncthreads();  // the previous chunk is no longer read
+    for (int e = tid; e < (NT + 16) * kTC; e += 256) {
+      const int row = e / kTC, col = e % kTC, j = row - 16, c = c0 + col;
+      Xs[row * kXS + col] = (j >= 0 && j < nt && c < C) ? (TA)X[(size_t)j * C + c] : TA(0);
+    }
+    __syncthreads();
+    const int cb = c0 + 8 * lk;
+    const bool row_ok = r < R;
+    const bool full = row_ok && cb + 8 <= C;
+    const int ncol = C - cb;
+    const TA *arow = A + (size_t)(row_ok ? r : 0) * C + cb;
+    // 16-byte aligned rows: every block starts aligned (blocks are R*C elements apart and the
+    // storage is 256-byte aligned) when R*C and C are multiples of 16 / sizeof(TA)
+    constexpr int kAl = 16 / sizeof(TA);
+    const bool vec = full && (C % kAl == 0) && (blk % kAl == 0);
+    TA a[8];
+    load_frag(a, arow + (size_t)d0 * blk, vec, full, row_ok, ncol);
+    ToeplitzRange<TA, NTC, 0>::run(acc, a, Xs, arow, blk, d0, d1, vec, full, row_ok, ncol, lm, lk);
+  }
+  const int part = g * gridDim.z + z;
 #pragma unroll
   for (int n = 0; n < NTC; ++n) {
     const int k = 16 * n + lm;
     if (k >= nt) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int r = r0 + wave * 16 + 4 * lk + i;
-      if (r < R) P[((size_t)g * nt + k) * R + r] = acc[n][i];
+      const int rr = blockIdx.x * TR + 16 * w + M::row(lk, i);
+      if (rr < R) P[((size_t)part * nt + k) * R + rr] = acc[n][i];
     }
   }
 }
 
-__global__ void k_sum_groups32(const float *__restrict__ P, int G, size_t n, double *__restrict__ Y) {
+// Y[i] = sum_g P[g][i], added in double in a fixed order
+template <typename TP>
+__global__ void k_sum_groups(const TP *__restrict__ P, int G, size_t n, double *__restrict__ Y) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     double s = 0.0;
     for (int g = 0; g < G; ++g) s += (double)P[(size_t)g * n + i];
@@ -445,90 +441,70 @@ int ensure_work(hb_ctx *c, size_t bytes) {
 }  // namespace
 
 // y = A x (Toeplitz), y overwritten
+// Split of the product over workgroups: 64-row tiles x column groups (cpg chunks each) x d
+// slices (dper blocks each), aiming at >= 768 workgroups with as few partial results as possible.
+struct ApplySplit {
+  int rt, nchunk, cpg, groups, dper, slices;
+};
+
+static ApplySplit apply_split(int R, int C, int nt) {
+  ApplySplit a;
+  a.rt = (R + TR - 1) / TR;
+  a.nchunk = (C + kTC - 1) / kTC;
+  const int want = 768;
+  int groups = std::max(1, std::min(a.nchunk, (want + a.rt - 1) / a.rt));
+  a.cpg = (a.nchunk + groups - 1) / groups;
+  a.groups = (a.nchunk + a.cpg - 1) / a.cpg;
+  int slices = std::max(1, std::min(std::max(1, nt / 8), (want + a.rt * a.groups - 1) / (a.rt * a.groups)));
+  a.dper = (nt + slices - 1) / slices;
+  a.slices = (nt + a.dper - 1) / a.dper;
+  return a;
+}
+
 template <typename TA>
-static void launch_toeplitz(int ntc, dim3 grid, hipStream_t s, const TA *A, const double *x,
-                            double *P, int nt, int R, int C, int dper) {
-  switch (ntc) {
-    case 1: hipLaunchKernelGGL((k_toeplitz_mfma<TA, 1, 32>), grid, dim3(256), 0, s, A, x, P, nt, R, C, dper); break;
-    case 2: hipLaunchKernelGGL((k_toeplitz_mfma<TA, 2, 32>), grid, dim3(256), 0, s, A, x, P, nt, R, C, dper); break;
-    case 4: hipLaunchKernelGGL((k_toeplitz_mfma<TA, 4, 32>), grid, dim3(256), 0, s, A, x, P, nt, R, C, dper); break;
-    case 8: hipLaunchKernelGGL((k_toeplitz_mfma<TA, 8, 16>), grid, dim3(256), 0, s, A, x, P, nt, R, C, dper); break;
-    default: hipLaunchKernelGGL((k_toeplitz_mfma<TA, 16, 16>), grid, dim3(256), 0, s, A, x, P, nt, R, C, dper); break;
+static int launch_toeplitz(hb_ctx *c, const TA *A, int R, int C, const double *x, double *y,
+                           hipStream_t s) {
+  const int nt = c->nt;
+  if (nt > 256) {
+    c->err = "toeplitz apply supports E_t <= 256";
+    return HB_EINVAL;
   }
+  const ApplySplit sp = apply_split(R, C, nt);
+  const int parts = sp.groups * sp.slices;
+  const size_t ny = (size_t)nt * R;
+  const size_t need = sizeof(TA) * ny * parts;
+  if (c->apply_bytes < need) {
+    if (c->d_apply) (void)hipFree(c->d_apply);
+    c->d_apply = nullptr;
+    c->apply_bytes = 0;
+    HB_CHECK(c, hipMalloc(&c->d_apply, need));
+    c->apply_bytes = need;
+  }
+  TA *P = (TA *)c->d_apply;
+  int ntc = 1;
+  while (ntc * 16 < nt) ntc *= 2;
+  dim3 grid(sp.rt, sp.groups, sp.slices);
+  switch (ntc) {
+    case 1: hipLaunchKernelGGL((k_toeplitz<TA, 1>), grid, dim3(256), 0, s, A, x, P, nt, R, C, sp.cpg, sp.dper); break;
+    case 2: hipLaunchKernelGGL((k_toeplitz<TA, 2>), grid, dim3(256), 0, s, A, x, P, nt, R, C, sp.cpg, sp.dper); break;
+    case 4: hipLaunchKernelGGL((k_toeplitz<TA, 4>), grid, dim3(256), 0, s, A, x, P, nt, R, C, sp.cpg, sp.dper); break;
+    case 8: hipLaunchKernelGGL((k_toeplitz<TA, 8>), grid, dim3(256), 0, s, A, x, P, nt, R, C, sp.cpg, sp.dper); break;
+    default: hipLaunchKernelGGL((k_toeplitz<TA, 16>), grid, dim3(256), 0, s, A, x, P, nt, R, C, sp.cpg, sp.dper); break;
+  }
+  hipLaunchKernelGGL(k_sum_groups<TA>, dim3(grid1d(ny)), dim3(256), 0, s, P, parts, ny, y);
+  HB_CHECK(c, hipGetLastError());
+  return HB_OK;
 }
 
 int toeplitz_apply(hb_ctx *c, const void *blocks, int R, int C, const double *x, double *y,
                    hipStream_t s) {
-  const int nt = c->nt;
-  if (nt > 256) {
-    c->err = "toeplitz apply supports E_t <= 256";
-    return HB_EINVAL;
-  }
-  const int gx = (R + TR - 1) / TR;
-  int groups = std::max(1, std::min(nt, (2048 + gx - 1) / gx));
-  const int dper = (nt + groups - 1) / groups;
-  groups = (nt + dper - 1) / dper;
-  const size_t ny = (size_t)nt * R;
-  const size_t need = sizeof(double) * ny * groups;
-  if (c->apply_bytes < need) {
-    if (c->d_apply) (void)hipFree(c->d_apply);
-    c->d_apply = nullptr;
-    c->apply_bytes = 0;
-    HB_CHECK(c, hipMalloc(&c->d_apply, need));
-    c->apply_bytes = need;
-  }
-  int ntc = 1;
-  while (ntc * 16 < nt) ntc *= 2;
-  dim3 grid(gx, groups);
-  if (c->storage_f32)
-    launch_toeplitz<float>(ntc, grid, s, (const float *)blocks, x, c->d_apply, nt, R, C, dper);
-  else
-    launch_toeplitz<double>(ntc, grid, s, (const double *)blocks, x, c->d_apply, nt, R, C, dper);
-  hipLaunchKernelGGL(k_sum_groups, dim3(grid1d(ny)), dim3(256), 0, s, c->d_apply, groups, ny, y);
-  HB_CHECK(c, hipGetLastError());
-  return HB_OK;
-}
-
-static int apply_groups(int R, int nt, int *dper_out) {
-  const int gx = (R + TR - 1) / TR;
-  int groups = std::max(1, std::min(nt, (2048 + gx - 1) / gx));
-  const int dper = (nt + groups - 1) / groups;
-  *dper_out = dper;
-  return (nt + dper - 1) / dper;
+  if (c->storage_f32) return launch_toeplitz<float>(c, (const float *)blocks, R, C, x, y, s);
+  return launch_toeplitz<double>(c, (const double *)blocks, R, C, x, y, s);
 }
 
 int toeplitz_apply32(hb_ctx *c, const float *blocks, int R, int C, const double *x, double *y,
                      hipStream_t s) {
-  const int nt = c->nt;
-  if (nt > 256) {
-    c->err = "toeplitz apply supports E_t <= 256";
-    return HB_EINVAL;
-  }
-  int dper;
-  const int groups = apply_groups(R, nt, &dper);
-  const size_t ny = (size_t)nt * R;
-  const size_t need = sizeof(float) * ny * groups;
-  if (c->apply_bytes < need) {
-    if (c->d_apply) (void)hipFree(c->d_apply);
-    c->d_apply = nullptr;
-    c->apply_bytes = 0;
-    HB_CHECK(c, hipMalloc(&c->d_apply, need));
-    c->apply_bytes = need;
-  }
-  float *P = (float *)c->d_apply;
-  int ntc = 1;
-  while (ntc * 16 < nt) ntc *= 2;
-  dim3 grid((R + TR - 1) / TR, groups);
-  switch (ntc) {
-    case 1: hipLaunchKernelGGL((k_toeplitz_mfma32<1, 32>), grid, dim3(256), 0, s, blocks, x, P, nt, R, C, dper); break;
-    case 2: hipLaunchKernelGGL((k_toeplitz_mfma32<2, 32>), grid, dim3(256), 0, s, blocks, x, P, nt, R, C, dper); break;
-    case 4: hipLaunchKernelGGL((k_toeplitz_mfma32<4, 32>), grid, dim3(256), 0, s, blocks, x, P, nt, R, C, dper); break;
-    case 8: hipLaunchKernelGGL((k_toeplitz_mfma32<8, 32>), grid, dim3(256), 0, s, blocks, x, P, nt, R, C, dper); break;
-    default: hipLaunchKernelGGL((k_toeplitz_mfma32<16, 16>), grid, dim3(256), 0, s, blocks, x, P, nt, R, C, dper); break;
-  }
-  hipLaunchKernelGGL(k_sum_groups32, dim3(grid1d(ny)), dim3(256), 0, s, P, groups, ny, y);
-  HB_CHECK(c, hipGetLastError());
-  return HB_OK;
+  return launch_toeplitz<float>(c, blocks, R, C, x, y, s);
 }
 
 namespace {
