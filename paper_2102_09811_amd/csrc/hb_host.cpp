@@ -592,7 +592,7 @@ void hb_destroy(hb_ctx *c) {
   void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_taylor,
                   c->d_taylor32, c->d_tdeg, c->d_V32, c->d_tscale, c->d_mass,
                   c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
-                  c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->ss[1].d, c->ss[2].d, c->ss[3].d};
+                  c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int i = 0; i < 4; ++i)

@@ -21,6 +21,8 @@ constexpr int kTaylorN32 = kTaylorDeg32 + 1;
 constexpr int kSeriesN = 14;         // terms of the small-z series of the brackets A(z), B(z)
 constexpr int kMaxClosed = 16;       // largest supported d_switch
 constexpr int kFarN = 7;             // Radon 7-point rule
+constexpr int kReprDeg = 20;         // largest degree of the potentials' Taylor polynomials
+constexpr int kReprQ = kReprDeg / 2 + 1;
 
 // Per-level constants of the closed form at delta_i = i h (i = 0 .. d_switch).
 struct LevelConsts {
@@ -137,6 +139,7 @@ struct hb_ctx {
   bool pc_active = false;
   double *d_ir = nullptr;            // iterative refinement: x, r, correction
   size_t ir_bytes = 0;
+  double *d_reprq = nullptr;         // potentials: Q_{2k}(w) / (2k+1)! for p = 3/2 and 5/2
   double *d_apply = nullptr;         // per-group partial results of the Toeplitz apply
   size_t apply_bytes = 0;
 };

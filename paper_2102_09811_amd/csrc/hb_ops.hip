@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "hb_device.h"
 #include "hb_internal.h"
 
 namespace hb {
@@ -333,76 +334,176 @@ __global__ void k_axpby(double a, const double *__restrict__ x, double b, double
 
 inline int grid1d(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 8192); }
 
-// ------------------------------------------------------------------------------------------
-// Representation formula u(x, t_k + eps) = V~ w - W g (Sec. 3.5), one workgroup per point.
-// With s_m = m h + eps and z_m = rho / (2 sqrt(alpha s_m)), the time integral of G over the
-// interval whose distances are (s_{m-1}, s_m) is [erfc z_m - erfc z_{m-1}] / (4 pi alpha rho),
-// and that of alpha dG/dn_y is rn [D(z_m) - D(z_{m-1})] / (4 pi rho^3) with
-// D(z) = erfc z + 2 z e^{-z^2} / sqrt(pi)  (the current, partial interval has s_{-1} = 0, D = 0).
-// ------------------------------------------------------------------------------------------
+// ---- representation formula ----
+// One workgroup per point (x, t), lanes over panels j.  With k = floor(t / h) and eps = t - k h,
+// interval i = k - m (m >= 1) is seen at the time distances delta in [s_m - h/2, s_m + h/2],
+// s_m = (m - 1/2) h + eps, and the current interval k at delta in [0, eps].  The time integrals
+// of the heat kernel G and of the double-layer kernel (r . n_y) / (2 delta) G over an interval:
+//   closed form (the current interval and m = 1, 2): differences of erfc(z) and of
+//     D(z) = erfc(z) + 2 z e^{-z^2} / sqrt(pi),  z = rho / (2 sqrt(alpha delta));
+//   Taylor form (m >= 3): the even series of the interval average around s_m,
+//     int G = h (4 pi alpha s)^{-3/2} e^{-w} S_{3/2}(w),
+//     int (r . n)/(2 delta) G = (r . n)/2 (4 pi alpha)^{-3/2} h s^{-5/2} e^{-w} S_{5/2}(w),
+//     S_p(w) = sum_k eps_m^{2k} / (2k+1)! Q^p_{2k}(w),  w = rho^2 / (4 alpha s),  eps_m = h / (2 s),
+//   truncated so that the dropped terms stay below ~6e-16 of the interval's scale (eps_m <=
+//   1 / (2m - 1)).  The workgroup tabulates the coefficients of S_{3/2}, S_{5/2} in w for every m
+//   in LDS; each lane then walks (panel, m, node), reusing the interval's data and coefficients
+//   for the 7 nodes of its panel.
+constexpr int kReprClosed = 2;  // intervals m = 1, 2 behind the current one in closed form
+
+__device__ __forceinline__ int repr_deg(int m) {
+  return m < 4 ? 20 : m < 6 ? 16 : m < 8 ? 14 : m < 16 ? 12 : m < 32 ? 10 : 8;
+}
+
+// LDS offset of the table of interval m (m >= 3): [c_m, prefV_m, prefK_m, S_3/2 coefficients,
+// S_5/2 coefficients], deg(m) + 1 coefficients each.
+__device__ __forceinline__ int repr_off(int m) {
+  int off = 0;
+  const int lo[6] = {3, 4, 6, 8, 16, 32}, hi[6] = {4, 6, 8, 16, 32, 1 << 30};
+  const int deg[6] = {20, 16, 14, 12, 10, 8};
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const int n = max(0, min(m, hi[c]) - lo[c]);
+    off += n * (3 + 2 * (deg[c] + 1));
+  }
+  return off;
+}
+
+template <int N>
+__device__ __forceinline__ void repr_taylor(const AsmParams &p, const double *__restrict__ tab,
+                                            const double *__restrict__ w,
+                                            const double *__restrict__ g, int k, int mlo, int mhi,
+                                            int j, int v0, int v1, int v2, double area,
+                                            const double (&r2)[kFarN], const double (&rn)[kFarN],
+                                            double &accs, double &accd) {
+  const int ne = p.ne, nv = p.nv;
+#pragma unroll 1
+  for (int m = mlo; m < mhi; ++m) {
+    const double *T = tab + repr_off(m);
+    const double cm = T[0];
+    const int i = k - m;
+    const double wi = w[(size_t)i * ne + j] * T[1] * area;
+    const double *gi = g + (size_t)i * nv;
+    const double pk = T[2] * area;
+    const double g0 = gi[v0] * pk, g1 = gi[v1] * pk, g2 = gi[v2] * pk;
+    double e[kFarN];
+    {
+      double c[N];
+#pragma unroll
+      for (int n = 0; n < N; ++n) c[n] = T[3 + n];
+#pragma unroll
+      for (int q = 0; q < kFarN; ++q) {
+        const double x = r2[q] * cm;
+        e[q] = exp_neg(x);
+        accs = fma(p.w7[q] * wi * e[q], horner<N>(c, x), accs);
+      }
+    }
+    {
+      double c[N];
+#pragma unroll
+      for (int n = 0; n < N; ++n) c[n] = T[3 + N + n];
+#pragma unroll
+      for (int q = 0; q < kFarN; ++q) {
+        const double x = r2[q] * cm;
+        const double gq = fma(p.lam7[q][0], g0, fma(p.lam7[q][1], g1, p.lam7[q][2] * g2));
+        accd = fma(p.w7[q] * rn[q] * gq * e[q], horner<N>(c, x), accd);
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_repr(const AsmParams *__restrict__ pp,
+                                              const double *__restrict__ qtab,
                                               const double *__restrict__ pts,
                                               const double *__restrict__ w,
                                               const double *__restrict__ g,
                                               double *__restrict__ u, double *__restrict__ sl,
                                               double *__restrict__ dl) {
+  extern __shared__ double tab[];
   const AsmParams &p = *pp;
   const int pid = blockIdx.x;
   const double px = pts[4 * pid], py = pts[4 * pid + 1], pz = pts[4 * pid + 2], t = pts[4 * pid + 3];
   const int ne = p.ne, nv = p.nv, nt = p.nt;
-  int k = (int)floor(t / p.h);
+  const double h = p.h, al = p.alpha;
+  int k = (int)floor(t / h);
   k = max(0, min(k, nt));
-  double eps = t - k * p.h;
+  double eps = t - k * h;
   if (eps < 0.0) eps = 0.0;
-  const double c_al = 1.0 / (2.0 * sqrt(p.alpha));
+  constexpr double kPi = 3.14159265358979323846;
+  // per-interval tables, one thread per m
+  for (int m = kReprClosed + 1 + threadIdx.x; m <= k; m += blockDim.x) {
+    double *T = tab + repr_off(m);
+    const int D = repr_deg(m), N = D + 1;
+    const double sm = (m - 0.5) * h + eps;
+    const double em = h / (2.0 * sm), e2 = em * em;
+    T[0] = 1.0 / (4.0 * al * sm);
+    T[1] = 4.0 * kPi * al * h * pow(4.0 * kPi * al * sm, -1.5);
+    T[2] = 2.0 * kPi * pow(4.0 * kPi * al, -1.5) * h * pow(sm, -2.5);
+    for (int pq = 0; pq < 2; ++pq) {
+      const double *Q = qtab + (size_t)pq * kReprQ * (kReprDeg + 1);
+      for (int jj = 0; jj < N; ++jj) {
+        double c = 0.0;
+        for (int kk = D / 2; kk >= 0; --kk)
+          c = fma(c, e2, 2 * kk >= jj ? Q[kk * (kReprDeg + 1) + jj] : 0.0);
+        T[3 + pq * N + jj] = c;
+      }
+    }
+  }
+  __syncthreads();
+
+  const double c_al = 1.0 / (2.0 * sqrt(al));
   constexpr double kTwoInvSqrtPi = 1.1283791670955125739;
   double accs = 0.0, accd = 0.0;
-  for (int j = threadIdx.x; j < ne; j += 256) {
+  for (int j = threadIdx.x; j < ne; j += blockDim.x) {
     const double area = p.geom[24 * ne + j];
     const double n0 = p.geom[21 * ne + j], n1 = p.geom[22 * ne + j], n2 = p.geom[23 * ne + j];
     const int v0 = p.tris[3 * j], v1 = p.tris[3 * j + 1], v2 = p.tris[3 * j + 2];
+    double r2[kFarN], rn[kFarN];
+#pragma unroll
     for (int q = 0; q < kFarN; ++q) {
       const double rx = px - p.geom[(q * 3 + 0) * ne + j];
       const double ry = py - p.geom[(q * 3 + 1) * ne + j];
       const double rz = pz - p.geom[(q * 3 + 2) * ne + j];
-      const double rho = sqrt(fma(rx, rx, fma(ry, ry, rz * rz)));
-      const double rn = fma(rx, n0, fma(ry, n1, rz * n2));
+      r2[q] = fma(rx, rx, fma(ry, ry, rz * rz));
+      const double rho = sqrt(r2[q]);
+      rn[q] = fma(rx, n0, fma(ry, n1, rz * n2));
+      const double Wq = p.w7[q] * area;
+      // closed form: current interval and m = 1 .. min(k, kReprClosed)
       const double l0 = p.lam7[q][0], l1 = p.lam7[q][1], l2 = p.lam7[q][2];
-      double sv = 0.0, sd = 0.0;
-      // m = 0: the current interval (if any) and the upper end of interval k
-      double ec_prev, D_prev;
-      {
-        if (eps > 0.0) {
-          const double z = rho * c_al / sqrt(eps);
-          const double e = exp(-z * z);
-          ec_prev = erfc(z);
-          D_prev = ec_prev + kTwoInvSqrtPi * z * e;
-          if (k < nt) {
-            sv += w[(size_t)k * ne + j] * ec_prev;
-            const double *gk = g + (size_t)k * nv;
-            sd += (l0 * gk[v0] + l1 * gk[v1] + l2 * gk[v2]) * D_prev;
-          }
-        } else {
-          ec_prev = 0.0;
-          D_prev = 0.0;
+      double sv = 0.0, sd = 0.0, ec_prev = 0.0, D_prev = 0.0;
+      if (eps > 0.0) {
+        const double z = rho * c_al / sqrt(eps);
+        ec_prev = erfc(z);
+        D_prev = ec_prev + kTwoInvSqrtPi * z * exp_neg(z * z);
+        if (k < nt) {
+          sv += w[(size_t)k * ne + j] * ec_prev;
+          const double *gk = g + (size_t)k * nv;
+          sd += (l0 * gk[v0] + l1 * gk[v1] + l2 * gk[v2]) * D_prev;
         }
       }
-      for (int m = 1; m <= k; ++m) {
-        const double z = rho * c_al / sqrt(m * p.h + eps);
-        const double e = exp(-z * z);
+      const int mc = min(k, kReprClosed);
+      for (int m = 1; m <= mc; ++m) {
+        const double z = rho * c_al / sqrt(m * h + eps);
         const double ec = erfc(z);
-        const double D = ec + kTwoInvSqrtPi * z * e;
-        const int i = k - m;  // 0-based interval index
+        const double D = ec + kTwoInvSqrtPi * z * exp_neg(z * z);
+        const int i = k - m;
         sv += w[(size_t)i * ne + j] * (ec - ec_prev);
         const double *gi = g + (size_t)i * nv;
         sd += (l0 * gi[v0] + l1 * gi[v1] + l2 * gi[v2]) * (D - D_prev);
         ec_prev = ec;
         D_prev = D;
       }
-      const double Wq = p.w7[q] * area;
       accs = fma(Wq / rho, sv, accs);
-      accd = fma(Wq * rn / (rho * rho * rho), sd, accd);
+      accd = fma(Wq * rn[q] / (rho * r2[q]), sd, accd);
     }
+    // Taylor form for m = 3 .. k, by degree class
+    const int m0 = kReprClosed + 1;
+    repr_taylor<21>(p, tab, w, g, k, m0, min(k + 1, 4), j, v0, v1, v2, area, r2, rn, accs, accd);
+    repr_taylor<17>(p, tab, w, g, k, 4, min(k + 1, 6), j, v0, v1, v2, area, r2, rn, accs, accd);
+    repr_taylor<15>(p, tab, w, g, k, 6, min(k + 1, 8), j, v0, v1, v2, area, r2, rn, accs, accd);
+    repr_taylor<13>(p, tab, w, g, k, 8, min(k + 1, 16), j, v0, v1, v2, area, r2, rn, accs, accd);
+    repr_taylor<11>(p, tab, w, g, k, 16, min(k + 1, 32), j, v0, v1, v2, area, r2, rn, accs, accd);
+    repr_taylor<9>(p, tab, w, g, k, 32, k + 1, j, v0, v1, v2, area, r2, rn, accs, accd);
   }
   __shared__ double red[2][4];
 #pragma unroll
@@ -844,7 +945,42 @@ int hb_eval_repr(hb_ctx *c, const double *pts, int64_t P, const double *w, const
     HB_CHECK(c, hipMalloc(&c->d_params_repr, sizeof(AsmParams)));
     HB_CHECK(c, hipMemcpy(c->d_params_repr, &c->params, sizeof(AsmParams), hipMemcpyHostToDevice));
   }
-  hipLaunchKernelGGL(k_repr, dim3((unsigned)P), dim3(256), 0, s, c->d_params_repr, pts, w, g, u, sl, dl);
+  if (!c->d_reprq) {
+    // Q^p_{2k}(w) / (2k+1)! for p = 3/2, 5/2 (Q_0 = 1, Q_{n+1} = (w - n - p) Q_n - w Q_n'), the
+    // building blocks of the interval averages of the potentials' time integrals
+    std::vector<double> q(2 * kReprQ * (kReprDeg + 1), 0.0);
+    for (int pq = 0; pq < 2; ++pq) {
+      const long double pw = pq == 0 ? 1.5L : 2.5L;
+      std::vector<long double> cur(1, 1.0L);
+      long double fact = 1.0L;  // (n+1)! for n = 0
+      for (int n = 0; n <= kReprDeg; ++n) {
+        if (n > 0) fact *= (long double)(n + 1);
+        if (n % 2 == 0)
+          for (size_t jj = 0; jj < cur.size(); ++jj)
+            q[((size_t)pq * kReprQ + n / 2) * (kReprDeg + 1) + jj] = (double)(cur[jj] / fact);
+        std::vector<long double> nx(cur.size() + 1, 0.0L);
+        for (size_t jj = 0; jj < cur.size(); ++jj) {
+          nx[jj + 1] += cur[jj];
+          nx[jj] -= ((long double)n + pw + (long double)jj) * cur[jj];
+        }
+        cur.swap(nx);
+      }
+    }
+    HB_CHECK(c, hipMalloc(&c->d_reprq, q.size() * sizeof(double)));
+    HB_CHECK(c, hipMemcpy(c->d_reprq, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  // per-interval coefficient tables of the largest interval count
+  int moff = 0;
+  {
+    const int lo[6] = {3, 4, 6, 8, 16, 32}, hi[6] = {4, 6, 8, 16, 32, 1 << 30};
+    const int deg[6] = {20, 16, 14, 12, 10, 8};
+    for (int cl = 0; cl < 6; ++cl)
+      moff += std::max(0, std::min(c->nt + 1, hi[cl]) - lo[cl]) * (3 + 2 * (deg[cl] + 1));
+  }
+  const size_t lds = std::max<size_t>(8, sizeof(double) * (size_t)moff);
+  if (lds > 160 * 1024) return ctx_fail(c, HB_EINVAL, "E_t too large for the potential kernel");
+  hipLaunchKernelGGL(k_repr, dim3((unsigned)P), dim3(256), lds, s, c->d_params_repr, c->d_reprq,
+                     pts, w, g, u, sl, dl);
   HB_CHECK(c, hipGetLastError());
   return HB_OK;
 }

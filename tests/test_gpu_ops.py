@@ -14,8 +14,8 @@ import pytest
 
 import oracle
 from oracle import downstream as ds
-from synthetic import (ExactSolution, box_points, cube, exp_solution, icosphere, nodal_samples,
-                       space_time_points)
+from synthetic import (ExactSolution, ball_points, box_points, cube, exp_solution, icosphere,
+                       nodal_samples, space_time_points)
 
 pytestmark = pytest.mark.gpu
 
@@ -136,6 +136,47 @@ def test_repr_matches_oracle(torch, c1):
     assert rel_inf(sl.cpu().numpy(), slr) <= 1e-11
     assert rel_inf(dl.cpu().numpy(), dlr) <= 1e-11
     assert rel_inf(u.cpu().numpy(), slr - dlr) <= 1e-11
+
+
+@pytest.mark.parametrize("alpha", [0.3, 2.0])
+def test_repr_long_history(torch, alpha):
+    """E_t = 70: every interval-distance class of the potential evaluation (closed form near the
+    point's time, Taylor polynomials of degree 20 .. 8 further back), t anywhere in (0, T]."""
+    from paper_2102_09811_amd import Context
+    v, t = cube(2)
+    nt = 70
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal((nt, len(t)))
+    g = rng.standard_normal((nt, len(v)))
+    pts = space_time_points(box_points(160, 0.1, 0.9, seed=6), 0.0, 1.0, seed=6)
+    pts[:4, 3] = [1.0, 0.5, 3.0 / nt, 2.5 / nt]
+    say("repr long history alpha=%g P=%d" % (alpha, len(pts)))
+    ctx = Context(v, t, alpha, 1.0, nt)
+    u, sl, dl = ctx.eval_repr(torch.from_numpy(pts).cuda(), torch.from_numpy(w).cuda(),
+                              torch.from_numpy(g).cuda(), parts=True)
+    slr, dlr = oracle.repr_eval(v, t, alpha, 1.0, nt, w, g, pts)
+    assert rel_inf(sl.cpu().numpy(), slr) <= 1e-11
+    assert rel_inf(dl.cpu().numpy(), dlr) <= 1e-11
+    assert rel_inf(u.cpu().numpy(), slr - dlr) <= 1e-11
+
+
+def test_repr_full_size_sampled(torch):
+    """The benchmarked potential evaluation (1280-triangle sphere, 64 steps, points in the ball of
+    radius 0.5 with t in [0.25, 0.75]) on 48 of its points against the oracle."""
+    from paper_2102_09811_amd import Context
+    v, t = icosphere(3)
+    nt = 64
+    rng = np.random.default_rng(8)
+    w = rng.standard_normal((nt, len(t)))
+    g = rng.standard_normal((nt, len(v)))
+    pts = space_time_points(ball_points(10000, 0.5, seed=0), 0.25, 0.75, seed=0)[::208][:48]
+    say("repr icosphere3 nt=64 P=%d" % len(pts))
+    ctx = Context(v, t, 1.0, 1.0, nt)
+    u, sl, dl = ctx.eval_repr(torch.from_numpy(np.ascontiguousarray(pts)).cuda(),
+                              torch.from_numpy(w).cuda(), torch.from_numpy(g).cuda(), parts=True)
+    slr, dlr = oracle.repr_eval(v, t, 1.0, 1.0, nt, w, g, pts)
+    assert rel_inf(sl.cpu().numpy(), slr) <= 1e-11
+    assert rel_inf(dl.cpu().numpy(), dlr) <= 1e-11
 
 
 def test_dirichlet_pipeline_table61(torch):
