@@ -597,6 +597,9 @@ void hb_destroy(hb_ctx *c) {
     if (p) (void)hipFree(p);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->ev_step) (void)hipEventDestroy(c->ev_step);
+  if (c->ev_prev) (void)hipEventDestroy(c->ev_prev);
+  if (c->h_res) (void)hipHostFree(c->h_res);
   delete c;
 }
 

@@ -303,15 +303,6 @@ __global__ void k_sum_partials(const double *__restrict__ partial, int nvec, int
 }
 
 // w[i] -= sum_v coef[v] Q[v][i]
-__global__ void k_sub_multi(const double *__restrict__ Q, size_t ldq, const double *__restrict__ coef,
-                            int nvec, double *__restrict__ w, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int v = 0; v < nvec; ++v) s = fma(coef[v], Q[(size_t)v * ldq + i], s);
-    w[i] -= s;
-  }
-}
-
 // y[i] = sum_v coef[v] Q[v][i]
 __global__ void k_combine(const double *__restrict__ Q, size_t ldq, const double *__restrict__ coef,
                           int nvec, double *__restrict__ y, size_t n) {
@@ -325,6 +316,87 @@ __global__ void k_combine(const double *__restrict__ Q, size_t ldq, const double
 __global__ void k_scale_copy(const double *__restrict__ x, double a, double *__restrict__ y, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     y[i] = a * x[i];
+}
+
+// Classical Gram-Schmidt update w -= sum_v c_v Q[v] with c_v the sum of the partial dot products
+// partial[v][0..nchunk) of Q[v] and w (each block sums them into LDS first).  With norm_partial,
+// each block also writes the sum of its updated w_i^2.
+__global__ __launch_bounds__(256) void k_cgs_sub(const double *__restrict__ Q, size_t ldq,
+                                                 const double *__restrict__ partial, int nchunk,
+                                                 int nvec, double *__restrict__ w, size_t n,
+                                                 double *__restrict__ norm_partial) {
+  extern __shared__ double coef[];
+  for (int v = threadIdx.x; v < nvec; v += blockDim.x) {
+    double c = 0.0;
+    for (int k = 0; k < nchunk; ++k) c += partial[(size_t)v * nchunk + k];
+    coef[v] = c;
+  }
+  __syncthreads();
+  double sq = 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int v = 0; v < nvec; ++v) acc = fma(coef[v], Q[(size_t)v * ldq + i], acc);
+    const double wi = w[i] - acc;
+    w[i] = wi;
+    sq = fma(wi, wi, sq);
+  }
+  if (norm_partial) {
+    __shared__ double red[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) norm_partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  }
+}
+
+// Arnoldi step j on the device: column j of the Hessenberg matrix H (row-major, m columns) from
+// the two Gram-Schmidt passes (partial sums p1, p2) and the norm (partials pn), the earlier Givens
+// rotations applied to it, the new rotation, the rotated right-hand side g, 1 / ||w|| for the
+// normalisation and the residual estimate |g_{j+1}| / beta in res[j].
+__global__ __launch_bounds__(256) void k_arnoldi(double *__restrict__ H, int m, int j,
+                                                 const double *__restrict__ p1,
+                                                 const double *__restrict__ p2, int nchunk,
+                                                 const double *__restrict__ pn, int npn,
+                                                 double *__restrict__ cs, double *__restrict__ sn,
+                                                 double *__restrict__ g, double beta,
+                                                 double *__restrict__ inv_nn,
+                                                 double *__restrict__ res) {
+  __shared__ double red[4];
+  for (int v = threadIdx.x; v <= j; v += blockDim.x) {
+    double c = 0.0;
+    for (int k = 0; k < nchunk; ++k) c += p1[(size_t)v * nchunk + k] + p2[(size_t)v * nchunk + k];
+    H[(size_t)v * m + j] = c;
+  }
+  double sq = 0.0;
+  for (int b = threadIdx.x; b < npn; b += blockDim.x) sq += pn[b];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double nn = sqrt(fmax(red[0] + red[1] + red[2] + red[3], 0.0));
+  *inv_nn = nn > 0.0 ? 1.0 / nn : 0.0;
+  for (int i = 0; i < j; ++i) {
+    const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+    H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+    H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = H[(size_t)j * m + j];
+  const double rr = hypot(a, nn);
+  const double cj = rr > 0.0 ? a / rr : 1.0, sj = rr > 0.0 ? nn / rr : 0.0;
+  cs[j] = cj;
+  sn[j] = sj;
+  H[(size_t)j * m + j] = rr;
+  g[j + 1] = -sj * g[j];
+  g[j] = cj * g[j];
+  res[j] = nn > 0.0 ? fabs(g[j + 1]) / beta : 0.0;
+}
+
+__global__ void k_scale_dev(double *__restrict__ y, const double *__restrict__ a, size_t n) {
+  const double f = *a;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] *= f;
 }
 
 __global__ void k_axpby(double a, const double *__restrict__ x, double b, double *__restrict__ y, size_t n) {
@@ -693,29 +765,51 @@ int ensure_V32(hb_ctx *c, hipStream_t s) {
   return HB_OK;
 }
 
+// Unrestarted GMRES (right-preconditioned by the learned block-diagonal map when precond) with
+// classical Gram-Schmidt applied twice.  The Arnoldi recurrence (Hessenberg column, Givens
+// rotations, residual estimate) stays on the device; the host learns each step's residual
+// estimate one step late through pinned memory while the next step is already queued, so the GPU
+// never waits for the host (a converged solve computes one surplus step, which is discarded).
 int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, hipStream_t s,
           hb_solve_info *info, bool precond = false) {
   const size_t n = (size_t)c->nt * c->ne;
   const int m = maxit;
   const int nchunk = (int)((n + kDotChunk - 1) / kDotChunk);
-  const size_t need = sizeof(double) * ((size_t)(m + 1) * n + n + (size_t)(m + 1) * nchunk + 2 * (m + 1));
+  const int nblk = grid1d(n);
+  const size_t need = sizeof(double) * ((size_t)(m + 1) * n + n + 2 * (size_t)(m + 1) * nchunk +
+                                        nblk + (size_t)(m + 1) * m + 4 * (size_t)(m + 1) + 4);
   int rc = ensure_work(c, need);
   if (rc) return rc;
-  double *Q = c->d_work, *r = Q + (size_t)(m + 1) * n, *partial = r + n;  // r: P q_j
-  double *dres = partial + (size_t)(m + 1) * nchunk, *coef = dres + (m + 1);
-  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1, 0.0), hv(m + 1), hv2(m + 1);
+  double *Q = c->d_work, *r = Q + (size_t)(m + 1) * n;  // r: P q_j
+  double *p1 = r + n, *p2 = p1 + (size_t)(m + 1) * nchunk, *pn = p2 + (size_t)(m + 1) * nchunk;
+  double *dH = pn + nblk, *dcs = dH + (size_t)(m + 1) * m, *dsn = dcs + (m + 1);
+  double *dg = dsn + (m + 1), *dres = dg + (m + 1), *dinv = dres + (m + 1);
+  if (!c->h_res || c->h_res_n < m + 1) {
+    if (c->h_res) (void)hipHostFree(c->h_res);
+    c->h_res = nullptr;
+    c->h_res_n = 0;
+    HB_CHECK(c, hipHostMalloc((void **)&c->h_res, sizeof(double) * (m + 1)));
+    c->h_res_n = m + 1;
+  }
+  if (!c->ev_step) HB_CHECK(c, hipEventCreateWithFlags(&c->ev_step, hipEventDisableTiming));
+  if (!c->ev_prev) HB_CHECK(c, hipEventCreateWithFlags(&c->ev_prev, hipEventDisableTiming));
   double beta;
-  if ((rc = multi_dot(c, b, 0, 1, b, n, partial, dres, &beta, s))) return rc;
-  beta = std::sqrt(beta);
+  {
+    std::vector<double> tmp(1);
+    if ((rc = multi_dot(c, b, 0, 1, b, n, p1, dres, tmp.data(), s))) return rc;
+    beta = std::sqrt(tmp[0]);
+  }
   if (beta == 0.0) {
     hipLaunchKernelGGL(k_fill, dim3(grid1d(n)), dim3(256), 0, s, x, n, 0.0);
     if (info) { info->iterations = 0; info->rel_residual = 0.0; }
     return HB_OK;
   }
   hipLaunchKernelGGL(k_scale_copy, dim3(grid1d(n)), dim3(256), 0, s, b, 1.0 / beta, Q, n);
-  gv[0] = beta;
+  HB_CHECK(c, hipMemcpyAsync(dg, &beta, sizeof(double), hipMemcpyHostToDevice, s));
+  HB_CHECK(c, hipStreamSynchronize(s));  // beta is read from the host stack above
   int it = 0;
   bool conv = false;
+  auto converged = [&](int jj) { return c->h_res[jj] <= tol; };
   for (int j = 0; j < m; ++j) {
     double *wj = Q + (size_t)(j + 1) * n;
     if (precond) {
@@ -724,43 +818,47 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
     } else if ((rc = apply_V(c, op, Q + (size_t)j * n, wj, s))) {
       return rc;
     }
-    // classical Gram-Schmidt, twice
-    if ((rc = multi_dot(c, Q, n, j + 1, wj, n, partial, dres, hv.data(), s))) return rc;
-    hipLaunchKernelGGL(k_sub_multi, dim3(grid1d(n)), dim3(256), 0, s, Q, n, dres, j + 1, wj, n);
-    if ((rc = multi_dot(c, Q, n, j + 1, wj, n, partial, dres, hv2.data(), s))) return rc;
-    hipLaunchKernelGGL(k_sub_multi, dim3(grid1d(n)), dim3(256), 0, s, Q, n, dres, j + 1, wj, n);
-    double nn;
-    if ((rc = multi_dot(c, wj, 0, 1, wj, n, partial, dres, &nn, s))) return rc;
-    nn = std::sqrt(nn);
-    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hv[i] + hv2[i];
-    H[(size_t)(j + 1) * m + j] = nn;
-    if (nn > 0) hipLaunchKernelGGL(k_scale_copy, dim3(grid1d(n)), dim3(256), 0, s, wj, 1.0 / nn, wj, n);
-    for (int i = 0; i < j; ++i) {
-      double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
-      H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
-      H[(size_t)i * m + j] = t;
+    const size_t shm = sizeof(double) * (j + 1);
+    hipLaunchKernelGGL(k_multi_dot, dim3(nchunk, j + 1), dim3(256), 0, s, Q, n, wj, n, p1, nchunk);
+    hipLaunchKernelGGL(k_cgs_sub, dim3(nblk), dim3(256), shm, s, Q, n, p1, nchunk, j + 1, wj, n,
+                       (double *)nullptr);
+    hipLaunchKernelGGL(k_multi_dot, dim3(nchunk, j + 1), dim3(256), 0, s, Q, n, wj, n, p2, nchunk);
+    hipLaunchKernelGGL(k_cgs_sub, dim3(nblk), dim3(256), shm, s, Q, n, p2, nchunk, j + 1, wj, n, pn);
+    hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(256), 0, s, dH, m, j, p1, p2, nchunk, pn, nblk,
+                       dcs, dsn, dg, beta, dinv, dres);
+    hipLaunchKernelGGL(k_scale_dev, dim3(grid1d(n)), dim3(256), 0, s, wj, dinv, n);
+    HB_CHECK(c, hipGetLastError());
+    HB_CHECK(c, hipMemcpyAsync(c->h_res + j, dres + j, sizeof(double), hipMemcpyDeviceToHost, s));
+    HB_CHECK(c, hipEventRecord(c->ev_step, s));
+    // step j is queued; look at step j - 1 (finished or about to) while it runs
+    if (j > 0) {
+      HB_CHECK(c, hipEventSynchronize(c->ev_prev));
+      if (converged(j - 1)) {
+        it = j;
+        conv = true;
+        break;
+      }
     }
-    double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
-    double rr = std::hypot(a, bb);
-    cs[j] = a / rr;
-    sn[j] = bb / rr;
-    H[(size_t)j * m + j] = rr;
-    H[(size_t)(j + 1) * m + j] = 0.0;
-    gv[j + 1] = -sn[j] * gv[j];
-    gv[j] = cs[j] * gv[j];
+    std::swap(c->ev_step, c->ev_prev);
     it = j + 1;
-    if (std::fabs(gv[j + 1]) / beta <= tol || nn == 0.0) {
-      conv = true;
-      break;
-    }
   }
-  // y = H^{-1} g, x = Q y
-  std::vector<double> y(it);
+  if (!conv) {
+    HB_CHECK(c, hipStreamSynchronize(s));
+    conv = it > 0 && converged(it - 1);
+  }
+  // y = R^{-1} g over the first it columns, x = (P) Q y
+  std::vector<double> R((size_t)it * m), gh(it), y(it);
+  HB_CHECK(c, hipStreamSynchronize(s));
+  if (it > 0) {
+    HB_CHECK(c, hipMemcpy(R.data(), dH, sizeof(double) * (size_t)it * m, hipMemcpyDeviceToHost));
+    HB_CHECK(c, hipMemcpy(gh.data(), dg, sizeof(double) * it, hipMemcpyDeviceToHost));
+  }
   for (int i = it - 1; i >= 0; --i) {
-    double sacc = gv[i];
-    for (int k = i + 1; k < it; ++k) sacc -= H[(size_t)i * m + k] * y[k];
-    y[i] = sacc / H[(size_t)i * m + i];
+    double sacc = gh[i];
+    for (int k = i + 1; k < it; ++k) sacc -= R[(size_t)i * m + k] * y[k];
+    y[i] = sacc / R[(size_t)i * m + i];
   }
+  double *coef = dres;  // no longer needed
   HB_CHECK(c, hipMemcpyAsync(coef, y.data(), sizeof(double) * it, hipMemcpyHostToDevice, s));
   if (precond) {
     hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, s, Q, n, coef, it, r, n);
@@ -769,6 +867,7 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
     hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, s, Q, n, coef, it, x, n);
   }
   HB_CHECK(c, hipGetLastError());
+  HB_CHECK(c, hipStreamSynchronize(s));  // y lives on the host stack
   if (info) info->iterations = it;
   return conv ? HB_OK : HB_ENOCONV;
 }
