@@ -6,8 +6,9 @@ vertices, 64 uniform steps on (0, 1], alpha = 1):
   1. fused assembly of all V_h^d and K_h^d blocks (FP64),
   2. Dirichlet right-hand side (1/2 M_h + K_h) g,
   3. learned preconditioner for this V_h^0 (features, MLP inference, installation),
-  4. right-preconditioned GMRES on V_h w = b to relative residual 1e-8, the residual taken with the
-     double-precision operator,
+  4. learned + mixed-precision solve of V_h w = b to relative residual 1e-8 taken with the
+     double-precision operator: refinement steps whose corrections come from right-preconditioned
+     GMRES on the float copy of V_h (the paper solves with FGMRES to 1e-8),
   5. representation formula at 10^4 interior space-time points.
 The MLP is trained before the timed region on random ellipsoids (the learned-preconditioner
 workload), never on this mesh.  After the timed steps every solver is timed on the same b:
@@ -38,10 +39,11 @@ def log(msg):
 
 
 def algorithmic_flops_separated(n_sep_pairs, n_t):
-    """FLOPs the semi-analytic method needs for the separated pairs: per (pair, point pair)
-    15 FLOP of geometry (r, rho, 1/rho, r.n) and per (pair, point pair, level delta = i h,
+    """FLOPs the semi-analytic method needs for the separated pairs: per (ordered pair, point
+    pair) 15 FLOP of geometry (r, rho, 1/rho, r.n) and per (pair, point pair, level delta = i h,
     i = 0..E_t) one erf and one exp (60 FLOP together) plus 25 FLOP of bracket arithmetic and
-    accumulation; 49 point pairs of the 7-point rule."""
+    accumulation; 49 point pairs of the 7-point rule.  Every ordered pair is counted (the unit
+    count of the metric); the kernel itself evaluates each unordered pair once."""
     return n_sep_pairs * 49.0 * (15.0 + 85.0 * (n_t + 1))
 
 
@@ -149,7 +151,7 @@ def main():
         ctx.rhs_dirichlet(gd, b)
         ev[2].record(stream)
         learned.install(net, ctx)
-        _, info = ctx.solve(b, method=HB_SOLVE_GMRES, tol=1e-8, w=w, precond=True)
+        _, info = ctx.solve(b, method=HB_SOLVE_MIXED_IR, tol=1e-8, w=w, precond=True)
         ev[3].record(stream)
         u = ctx.eval_repr(ptsd, w, gd)
         ev[4].record(stream)
@@ -201,14 +203,17 @@ def main():
                       "solve": avg("solve_ms"), "repr": avg("repr_ms"),
                       "assemble_separated_kernel": sep_ms, "assemble_touching_kernels": touch_ms},
         "assembly_units_per_s": units / (avg("assemble_ms") * 1e-3),
-        "solve": {"method": "learned-preconditioned GMRES (double operator)",
+        "solve": {"method": "learned-preconditioned mixed-precision refinement (float inner "
+                            "GMRES, residual with the double operator)",
                   "iterations": int(rec[-1]["iterations"]),
                   "rel_residual": rec[-1]["rel_residual"], "ms": avg("solve_ms")},
         "learned_training_s": t_train,
-        "roofline": {"bound": "alu", "kernel": "k_separated (separated-pair assembly)",
+        "roofline": {"bound": "alu",
+                     "kernel": "k_separated + k_fold_KT (separated-pair assembly)",
                      "achieved": achieved, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / (PEAK_FP64_VALU / 1e12), "traffic": None,
-                     "algorithmic_flops_per_launch": flops},
+                     "algorithmic_flops_per_launch": flops,
+                     "frac_unordered_pairs": 0.5 * achieved / (PEAK_FP64_VALU / 1e12)},
     }
     if not args.no_compare:
         log("solver comparison")

@@ -207,18 +207,22 @@ __global__ __launch_bounds__(256) void k_dense_fwd(const float *__restrict__ X, 
   }
 }
 
-// dW[o][i] (+)= sum_b dY[b][o] X[b][i]; grid over (o tiles, i tiles)
+// dW[o][i] = sum_b dY[b][o] X[b][i] over the rows of chunk blockIdx.z (rows per chunk: rpc),
+// written to dW + blockIdx.z * nout * nin; grid over (o tiles, i tiles, row chunks)
 __global__ __launch_bounds__(256) void k_gemm_tn(const float *__restrict__ dY, const float *__restrict__ X,
-                                                 float *__restrict__ dW, int B, int nout, int nin) {
+                                                 float *__restrict__ dW, int B, int nout, int nin,
+                                                 int rpc) {
   const int o0 = blockIdx.x * GT, i0 = blockIdx.y * GT;
   const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
   __shared__ float Ds[GK][GT + 1], Xs[GK][GT + 1];
   float acc[4][4] = {};
-  for (int b0 = 0; b0 < B; b0 += GK) {
+  const int bb = blockIdx.z * rpc, be = min(B, bb + rpc);
+  dW += (size_t)blockIdx.z * nout * nin;
+  for (int b0 = bb; b0 < be; b0 += GK) {
     for (int e = tid; e < GT * GK; e += 256) {
       const int r = e % GT, k = e / GT;
-      Ds[k][r] = (b0 + k < B && o0 + r < nout) ? dY[(size_t)(b0 + k) * nout + o0 + r] : 0.0f;
-      Xs[k][r] = (b0 + k < B && i0 + r < nin) ? X[(size_t)(b0 + k) * nin + i0 + r] : 0.0f;
+      Ds[k][r] = (b0 + k < be && o0 + r < nout) ? dY[(size_t)(b0 + k) * nout + o0 + r] : 0.0f;
+      Xs[k][r] = (b0 + k < be && i0 + r < nin) ? X[(size_t)(b0 + k) * nin + i0 + r] : 0.0f;
     }
     __syncthreads();
 #pragma unroll
@@ -297,14 +301,30 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const float *__restrict__ dY, c
   }
 }
 
-// db[o] = sum_b dY[b][o]
-__global__ void k_colsum(const float *__restrict__ dY, int B, int n, float *__restrict__ db) {
+// db[o] = sum_b dY[b][o] over the rows of chunk blockIdx.y, written to db + blockIdx.y * n
+__global__ void k_colsum(const float *__restrict__ dY, int B, int n, float *__restrict__ db,
+                         int rpc) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= n) return;
+  const int bb = blockIdx.y * rpc, be = min(B, bb + rpc);
   float s = 0.0f;
-  for (int b = 0; b < B; ++b) s += dY[(size_t)b * n + o];
-  db[o] = s;
+  for (int b = bb; b < be; ++b) s += dY[(size_t)b * n + o];
+  db[(size_t)blockIdx.y * n + o] = s;
 }
+
+// out[i] = sum_c P[c][i] in a fixed order (deterministic reduction of the row-chunk partials)
+__global__ void k_sum_chunks(const float *__restrict__ P, int nc, size_t n, float *__restrict__ out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    float acc = 0.0f;
+    for (int c = 0; c < nc; ++c) acc += P[(size_t)c * n + i];
+    out[i] = acc;
+  }
+}
+
+// Row chunks of the weight / bias gradients: enough workgroups to fill the chip, at most
+// kMaxChunks partial copies (kept in the backward workspace).
+constexpr int kMaxChunks = 32;
+inline int grad_chunks(int B) { return std::max(1, std::min(kMaxChunks, (B + 127) / 128)); }
 
 // Quadratic loss per row: L_b = y^T G y - 2 a^T y + 1; dL/dy = 2 (G y - a) / B (mean over rows)
 __global__ void k_quadloss(const float *__restrict__ Y, const float *__restrict__ G,
@@ -403,7 +423,8 @@ int64_t hb_mlp_num_params(const hb_mlp_dims *d) { return dims_ok(d) ? (int64_t)m
 
 int64_t hb_mlp_work_floats(const hb_mlp_dims *d, int64_t batch) {
   if (!dims_ok(d) || batch <= 0) return -1;
-  return batch * (4 * (int64_t)d->n_hidden + d->n_out) + batch * 2 * (int64_t)d->n_hidden;
+  const int64_t H = d->n_hidden, wmax = H * std::max<int64_t>(std::max<int64_t>(H, d->n_in), d->n_out);
+  return batch * (4 * H + d->n_out) + batch * 2 * H + (int64_t)kMaxChunks * (wmax + H);
 }
 
 int hb_precond_pattern(hb_ctx *c, int32_t *cols, int8_t *cls, void *stream) {
@@ -495,17 +516,31 @@ int hb_mlp_backward(const hb_mlp_dims *d, const float *params, const float *x, i
   float *dW1 = grads, *db1 = dW1 + (size_t)H * I, *dW2 = db1 + H, *db2 = dW2 + (size_t)H * H;
   float *dW3 = db2 + H, *db3 = dW3 + (size_t)O * H;
   float *dZ2 = (float *)work + (size_t)B * (4 * H + O), *dZ1 = dZ2 + (size_t)B * H;
+  // row-chunk partials of the weight and bias gradients, then a fixed-order sum
+  const int nc = grad_chunks(B), rpc = (B + nc - 1) / nc;
+  const int64_t wmax = (int64_t)H * std::max(std::max(H, I), O);
+  float *Pw = dZ1 + (size_t)B * H, *Pb = Pw + (size_t)kMaxChunks * wmax;
+  auto weight_grad = [&](const float *dY, const float *X, float *dW, int nout, int nin) {
+    hipLaunchKernelGGL(k_gemm_tn, dim3((nout + GT - 1) / GT, (nin + GT - 1) / GT, nc), dim3(256), 0, s,
+                       dY, X, Pw, B, nout, nin, rpc);
+    const size_t n = (size_t)nout * nin;
+    hipLaunchKernelGGL(k_sum_chunks, dim3(grid_for(n)), dim3(256), 0, s, Pw, nc, n, dW);
+  };
+  auto bias_grad = [&](const float *dY, float *db, int n) {
+    hipLaunchKernelGGL(k_colsum, dim3((n + 255) / 256, nc), dim3(256), 0, s, dY, B, n, Pb, rpc);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(grid_for((size_t)n)), dim3(256), 0, s, Pb, nc, (size_t)n, db);
+  };
   // layer 3 (linear): dW3 = dy^T H2, db3 = sum dy, dZ2 = (dy W3) * (1 - H2^2)
-  hipLaunchKernelGGL(k_gemm_tn, dim3((O + GT - 1) / GT, (H + GT - 1) / GT), dim3(256), 0, s, dy, H2, dW3, B, O, H);
-  hipLaunchKernelGGL(k_colsum, dim3((O + 255) / 256), dim3(256), 0, s, dy, B, O, db3);
+  weight_grad(dy, H2, dW3, O, H);
+  bias_grad(dy, db3, O);
   hipLaunchKernelGGL(k_gemm_nn, dim3((B + GT - 1) / GT, (H + GT - 1) / GT), dim3(256), 0, s, dy, W3, H2, dZ2, B, O, H, 1);
   // layer 2
-  hipLaunchKernelGGL(k_gemm_tn, dim3((H + GT - 1) / GT, (H + GT - 1) / GT), dim3(256), 0, s, dZ2, H1, dW2, B, H, H);
-  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, dZ2, B, H, db2);
+  weight_grad(dZ2, H1, dW2, H, H);
+  bias_grad(dZ2, db2, H);
   hipLaunchKernelGGL(k_gemm_nn, dim3((B + GT - 1) / GT, (H + GT - 1) / GT), dim3(256), 0, s, dZ2, W2, H1, dZ1, B, H, H, 1);
   // layer 1
-  hipLaunchKernelGGL(k_gemm_tn, dim3((H + GT - 1) / GT, (I + GT - 1) / GT), dim3(256), 0, s, dZ1, x, dW1, B, H, I);
-  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, dZ1, B, H, db1);
+  weight_grad(dZ1, x, dW1, H, I);
+  bias_grad(dZ1, db1, H);
   return hipGetLastError() == hipSuccess ? HB_OK : HB_EHIP;
 }
 
