@@ -133,7 +133,8 @@ __device__ __forceinline__ void shift_carry(LevelSums &S) {
 // share all 49 point pairs (r changes sign, rho does not): one lane evaluates the unordered pair
 // m > l once and emits both orders.  V^d[l][m] = V^d[m][l]; the double layer differs only in the
 // normal and the p1 basis:  (l, m) uses r . n_m and the basis at the m-nodes,  (m, l) uses
-// -r . n_l and the basis at the l-nodes.  Workgroup = (test panel l, 256 consecutive m); lane = m.
+// -r . n_l and the basis at the l-nodes.  Each wave takes one task from a host list: test panel l
+// and the 64 trial panels m0 .. m0+63 (m0 > l, lanes past E_x idle); lane = m.
 // ------------------------------------------------------------------------------------------
 struct SymSums {
   double V[kLC + 2];
@@ -401,12 +402,15 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
                                                       const double *__restrict__ tscale,
                                                       const double *__restrict__ taylor,
                                                       const float *__restrict__ taylor32,
-                                                      const int *__restrict__ tdeg) {
+                                                      const int *__restrict__ tdeg,
+                                                      const int *__restrict__ tasks, int ntasks) {
   const AsmParams &p = *pp;
   const SepTabs T{geom, tscale, taylor, taylor32, tdeg};
-  const int l = blockIdx.y;
-  if ((int)(blockIdx.x * 256 + 255) <= l) return;  // the whole tile has m <= l
-  const int m = blockIdx.x * 256 + threadIdx.x;
+  // one task per wave: test panel l and the 64 trial panels m0 .. m0+63 (all > l)
+  const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (task >= ntasks) return;
+  const int l = __builtin_amdgcn_readfirstlane(tasks[2 * task]);
+  const int m = __builtin_amdgcn_readfirstlane(tasks[2 * task + 1]) + (threadIdx.x & 63);
   if (m >= p.ne) return;
   const int ne = p.ne;
   const int vl[3] = {p.tris[3 * l], p.tris[3 * l + 1], p.tris[3 * l + 2]};
@@ -669,31 +673,32 @@ __global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict_
 
 template <typename TS, int D>
 static void launch_sep(dim3 grid, hipStream_t s, const AsmParams *dp, const AsmParams &hp,
-                       bool mixed) {
+                       const int32_t *tasks, int ntasks, bool mixed) {
   if (mixed)
     hipLaunchKernelGGL((k_separated<TS, D, true>), grid, dim3(256), 0, s, dp, hp.geom, hp.tscale,
-                       hp.taylor, hp.taylor32, hp.tdeg);
+                       hp.taylor, hp.taylor32, hp.tdeg, tasks, ntasks);
   else
     hipLaunchKernelGGL((k_separated<TS, D, false>), grid, dim3(256), 0, s, dp, hp.geom, hp.tscale,
-                       hp.taylor, hp.taylor32, hp.tdeg);
+                       hp.taylor, hp.taylor32, hp.tdeg, tasks, ntasks);
 }
 
-void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, int precision,
-                               int storage_f32, hipStream_t s) {
-  dim3 grid((p.ne + 255) / 256, p.ne);
+void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, const int32_t *tasks,
+                               int64_t ntasks, int precision, int storage_f32, hipStream_t s) {
+  dim3 grid((unsigned)((ntasks + 3) / 4));
+  const int nt4 = (int)ntasks;
   const bool mixed = precision == HB_PREC_MIXED;
   switch (p.dsw) {
     case 16:
-      if (storage_f32) launch_sep<float, 16>(grid, s, dp, p, mixed);
-      else launch_sep<double, 16>(grid, s, dp, p, mixed);
+      if (storage_f32) launch_sep<float, 16>(grid, s, dp, p, tasks, nt4, mixed);
+      else launch_sep<double, 16>(grid, s, dp, p, tasks, nt4, mixed);
       break;
     case 8:
-      if (storage_f32) launch_sep<float, 8>(grid, s, dp, p, mixed);
-      else launch_sep<double, 8>(grid, s, dp, p, mixed);
+      if (storage_f32) launch_sep<float, 8>(grid, s, dp, p, tasks, nt4, mixed);
+      else launch_sep<double, 8>(grid, s, dp, p, tasks, nt4, mixed);
       break;
     default:
-      if (storage_f32) launch_sep<float, 3>(grid, s, dp, p, mixed);
-      else launch_sep<double, 3>(grid, s, dp, p, mixed);
+      if (storage_f32) launch_sep<float, 3>(grid, s, dp, p, tasks, nt4, mixed);
+      else launch_sep<double, 3>(grid, s, dp, p, tasks, nt4, mixed);
       break;
   }
 }

@@ -457,6 +457,19 @@ int build_tables(hb_ctx *c) {
   if (!c->touch.empty())
     if ((rc = upload(c, (void **)&c->d_touch, c->touch.data(), c->touch.size() * sizeof(TouchPair))))
       return rc;
+  // separated pairs, unordered (m > l): one wave task per 64 trial panels of a test row
+  {
+    std::vector<int32_t> tasks;
+    for (int64_t l = 0; l < (int64_t)ne; ++l)
+      for (int64_t m0 = l + 1; m0 < (int64_t)ne; m0 += 64) {
+        tasks.push_back((int32_t)l);
+        tasks.push_back((int32_t)m0);
+      }
+    c->n_sep_tasks = (int64_t)tasks.size() / 2;
+    if (!tasks.empty())
+      if ((rc = upload(c, (void **)&c->d_sep_tasks, tasks.data(), tasks.size() * sizeof(int32_t))))
+        return rc;
+  }
   // preconditioner pattern: itself, edge neighbours, vertex neighbours by centroid distance
   {
     std::vector<double> cent(3 * ne);
@@ -589,7 +602,7 @@ int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t 
 void hb_destroy(hb_ctx *c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
-  void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_taylor,
+  void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_sep_tasks, c->d_taylor,
                   c->d_taylor32, c->d_tdeg, c->d_V32, c->d_tscale, c->d_mass,
                   c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d};
@@ -638,7 +651,9 @@ int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
     HB_HIP(c, hipMemsetAsync(c->d_KT, 0, nK * esz, s));
   }
   HB_HIP(c, hipEventRecord(c->ev[0], s));
-  hb::launch_assemble_separated(c->d_params, p, precision, c->storage_f32, s);
+  if (c->n_sep_tasks > 0)
+    hb::launch_assemble_separated(c->d_params, p, c->d_sep_tasks, c->n_sep_tasks, precision,
+                                  c->storage_f32, s);
   HB_HIP(c, hipGetLastError());
   if (p.do_K) {
     hb::launch_fold_KT(p, c->storage_f32, s);

@@ -77,8 +77,8 @@ struct SSRule {
 };
 
 // dp: device copy of p (kernels read their parameters from device memory)
-void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, int precision,
-                               int storage_f32, hipStream_t s);
+void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, const int32_t *tasks,
+                               int64_t ntasks, int precision, int storage_f32, hipStream_t s);
 void launch_fold_KT(const AsmParams &p, int storage_f32, hipStream_t s);
 void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,
                               int64_t npairs, const SSRule &rule, int storage_f32, hipStream_t s);
@@ -110,6 +110,8 @@ struct hb_ctx {
   double *d_geom = nullptr;
   int32_t *d_tris = nullptr;
   hb::TouchPair *d_touch = nullptr;
+  int32_t *d_sep_tasks = nullptr;    // [n][2]: (test panel l, first trial panel m0 > l) per wave
+  int64_t n_sep_tasks = 0;
   hb::SSRule ss[4];
   double *d_taylor = nullptr, *d_tscale = nullptr;
   float *d_taylor32 = nullptr;
