@@ -397,7 +397,7 @@ __device__ __forceinline__ void sym_taylor2_32(const AsmParams &p, const SepTabs
 }
 
 template <typename TS, int D, bool MIXED>
-__global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restrict__ pp,
+__global__ __launch_bounds__(256, 3) void k_separated(const AsmParams *__restrict__ pp,
                                                       const double *__restrict__ geom,
                                                       const double *__restrict__ tscale,
                                                       const double *__restrict__ taylor,
