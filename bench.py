@@ -33,6 +33,15 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU = 78.6e12  # MI355X FP64 vector FLOP/s
 
+# HBM traffic of the separated-pair assembly (k_separated + k_fold_KT, one launch each) on this
+# workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of `bench.py --assembly-only`,
+# each scaled by the reading of the same counter for a plain 256 MiB device copy taken in the same
+# run (FETCH_SIZE reads 0.500x, WRITE_SIZE 1.000x of the copied bytes).  Valid only for the
+# assembly source they were taken on (sha256 prefix below); reported as null otherwise.
+TRAFFIC = {"source_sha256": "160af4dd88c04b07",
+           "fetch_kib": 257442.1 + 460173.1, "fetch_scale": 262144.0 / 131087.7,
+           "write_kib": 7437088.1 + 424960.0, "write_scale": 262144.0 / 262144.0}
+
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -47,12 +56,46 @@ def algorithmic_flops_separated(n_sep_pairs, n_t):
     return n_sep_pairs * 49.0 * (15.0 + 85.0 * (n_t + 1))
 
 
+def assembly_traffic_bytes():
+    """HBM bytes per separated-pair assembly launch from the committed counter runs, or None when
+    the assembly source has changed since they were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2102_09811_amd", "csrc", "hb_assemble.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if sha != TRAFFIC["source_sha256"]:
+        return None
+    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] +
+                     TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
+
+
+def assembly_only(args):
+    """Counter runs: two assemblies of the benchmarked workload, then a plain 256 MiB device copy
+    (the calibration of the HBM byte counters)."""
+    import torch
+    from paper_2102_09811_amd import Context, HB_OP_K, HB_OP_V
+    from synthetic import icosphere
+    verts, tris = icosphere(3)
+    ctx = Context(verts, tris, 1.0, 1.0, 64)
+    for _ in range(2):
+        ctx.assemble(HB_OP_V | HB_OP_K)
+    torch.cuda.synchronize()
+    log("assembly kernels ms: separated+fold %.3f, touching %.3f" % tuple(ctx.last_assembly_ms()[:2]))
+    a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ctx.close()
+    log("calibration copy: 256 MiB read, 256 MiB written")
+    return 0
+
+
 def cpu_baseline(verts, tris, alpha, T, n_t):
     """The oracle (long double, OpenMP over test rows) on a bounded sample of test rows."""
     import numpy as np
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    rows = np.linspace(0, len(tris) - 1, 2 * threads).astype(np.int32)
+    rows = np.linspace(0, len(tris) - 1, 4 * threads).astype(np.int32)
     oracle.assemble(verts, tris, alpha, T, n_t, rows=rows[:1])  # load / warm
     t0 = time.perf_counter()
     oracle.assemble(verts, tris, alpha, T, n_t, rows=rows)
@@ -110,11 +153,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the solver comparison")
     ap.add_argument("--train-meshes", type=int, default=16)
+    ap.add_argument("--assembly-only", action="store_true",
+                    help="two assemblies and a 256 MiB calibration copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         return 2
+
+    if args.assembly_only:
+        return assembly_only(args)
 
     import numpy as np
     import torch
@@ -211,7 +259,8 @@ def main():
         "roofline": {"bound": "alu",
                      "kernel": "k_separated + k_fold_KT (separated-pair assembly)",
                      "achieved": achieved, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / (PEAK_FP64_VALU / 1e12), "traffic": None,
+                     "frac": achieved / (PEAK_FP64_VALU / 1e12),
+                     "traffic": assembly_traffic_bytes(),
                      "algorithmic_flops_per_launch": flops,
                      "frac_unordered_pairs": 0.5 * achieved / (PEAK_FP64_VALU / 1e12)},
     }
