@@ -148,7 +148,8 @@ typedef struct hb_solve_opts {
 typedef struct hb_solve_info {
   int32_t iterations;   /* GMRES iterations, summed over refinement steps (0 for time marching) */
   double rel_residual;  /* ||b - V_h w|| / ||b|| recomputed in double after the solve */
-  double seconds;       /* wall time of the solve */
+  double seconds;       /* wall time of the solve (work queued before it on the stream is
+                           drained before the clock starts) */
   int32_t refinements;  /* HB_SOLVE_MIXED_IR: outer refinement steps */
   int32_t reserved[7];
 } hb_solve_info;

@@ -122,6 +122,31 @@ def test_solvers_reach_tolerance(torch, c1, method):
         assert info["iterations"] > 3
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_time_marching_long(torch, storage):
+    """E_t = 70 (chunks of 8 steps, the last one partial): time marching against the oracle's LU
+    time marching on the same blocks, double and float block storage."""
+    from paper_2102_09811_amd import Context, HB_DTYPE_F32, HB_OP_V, HB_SOLVE_TIMEMARCH
+    v, t = cube(2)
+    nt = 70
+    opts = {"storage": HB_DTYPE_F32} if storage == "f32" else {}
+    say("time marching cube2 nt=%d storage=%s" % (nt, storage))
+    ctx = Context(v, t, 0.7, 1.0, nt, **opts)
+    ctx.assemble()
+    Vg = ctx.blocks(HB_OP_V, device=False).astype(np.float64)
+    rng = np.random.default_rng(21)
+    b = rng.standard_normal((nt, len(t)))
+    w, info = ctx.solve(torch.from_numpy(b).cuda(), method=HB_SOLVE_TIMEMARCH)
+    w = w.cpu().numpy()
+    wr = ds.time_march(Vg, b)
+    say("time marching %s: rel diff %.2e, residual %.2e" % (storage, rel_inf(w, wr), info["rel_residual"]))
+    # float storage: the history products run on float MFMA (sources rounded to float)
+    assert rel_inf(w, wr) <= (1e-10 if storage == "f64" else 1e-5)
+    res = np.linalg.norm(b - ds.toeplitz_apply(Vg, w)) / np.linalg.norm(b)
+    assert res <= (1e-12 if storage == "f64" else 1e-5), res
+    ctx.close()
+
+
 def test_repr_matches_oracle(torch, c1):
     v, t, ctx, Vr, Kr = c1
     rng = np.random.default_rng(11)
