@@ -1,0 +1,99 @@
+"""The large workload at full size: cube surface with 6144 triangles / 3074 vertices (16 x 16
+squares per face, each split in 4 through its centre), 256 steps on (0, 1], alpha = 1, float block
+storage (38.7 GB of V blocks + 19.3 GB of K blocks).
+
+Checked on samples the oracle can afford:
+- mixed-precision assembly: every block of 8 test rows against the oracle (long-double closed form)
+  within 1e-6 block-relative (the row sample's own maximum as the scale);
+- time marching on a random right-hand side: the device residual and the residual of the sampled
+  rows recomputed in double from the stored blocks;
+- potentials at 10^5 points: 16 of them against the oracle to 1e-10.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import box_points, cube4, space_time_points
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_large_cube_float_storage():
+    import torch
+    from paper_2102_09811_amd import (Context, HB_DTYPE_F32, HB_OP_K, HB_OP_V, HB_PREC_MIXED,
+                                      HB_SOLVE_TIMEMARCH)
+    v, t = cube4(16)
+    ne, nv, nt, alpha = len(t), len(v), 256, 1.0
+    assert (ne, nv) == (6144, 3074)
+    say("large: cube4(16) %d / %d, E_t = %d, float storage" % (ne, nv, nt))
+    ctx = Context(v, t, alpha, 1.0, nt, storage=HB_DTYPE_F32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.assemble(HB_OP_V | HB_OP_K, precision=HB_PREC_MIXED)
+    torch.cuda.synchronize()
+    say("mixed assembly %.3f s (kernels %s ms)" % (time.perf_counter() - t0, ctx.last_assembly_ms()))
+
+    rows = np.linspace(0, ne - 1, 8).astype(np.int64)
+    rows_t = torch.from_numpy(rows).cuda()
+    Vg = np.empty((nt, len(rows), ne))
+    Kg = np.empty((nt, len(rows), nv))
+    for d0 in range(0, nt, 16):
+        Vg[d0:d0 + 16] = ctx.blocks(HB_OP_V, d0, 16)[:, rows_t, :].double().cpu().numpy()
+        Kg[d0:d0 + 16] = ctx.blocks(HB_OP_K, d0, 16)[:, rows_t, :].double().cpu().numpy()
+        torch.cuda.empty_cache()
+    say("oracle: %d rows x all blocks (long-double closed form)" % len(rows))
+    t0 = time.perf_counter()
+    Vr, Kr = oracle.assemble(v, t, alpha, 1.0, nt, rows=rows.astype(np.int32), tmode=1)
+    say("oracle %.1f s" % (time.perf_counter() - t0))
+    eV = np.abs(Vg - Vr).max(axis=(1, 2)) / np.abs(Vr).max(axis=(1, 2))
+    eK = np.abs(Kg - Kr).max(axis=(1, 2)) / np.abs(Kr).max(axis=(1, 2))
+    say("sampled rows: max e_V = %.2e (d=%d), max e_K = %.2e (d=%d)" % (
+        eV.max(), eV.argmax(), eK.max(), eK.argmax()))
+    assert eV.max() <= 1e-6 and eK.max() <= 1e-6
+
+    # time marching (float blocks; the inverse of V^0 in double)
+    rng = np.random.default_rng(17)
+    b = rng.standard_normal((nt, ne))
+    bd = torch.from_numpy(b).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w, info = ctx.solve(bd, method=HB_SOLVE_TIMEMARCH)
+    torch.cuda.synchronize()
+    say("time marching %.3f s, device residual %.2e" % (time.perf_counter() - t0,
+                                                       info["rel_residual"]))
+    assert info["rel_residual"] <= 1e-5
+    wh = w.cpu().numpy()
+    # residual of the sampled rows with the stored blocks, in double
+    res = b[:, rows].copy()
+    for d in range(nt):
+        res[d:] -= wh[:nt - d] @ Vg[d].T
+    rel = np.abs(res).max() / np.abs(b[:, rows]).max()
+    say("sampled-row residual (double, stored blocks) %.2e" % rel)
+    assert rel <= 1e-5
+
+    # potentials at 10^5 points in [0.25, 0.75]^3 x [0.25, 0.75]
+    g = rng.standard_normal((nt, nv))
+    pts = space_time_points(box_points(100000, 0.25, 0.75, seed=0), 0.25, 0.75, seed=0)
+    ptsd = torch.from_numpy(pts).cuda()
+    gd = torch.from_numpy(g).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = ctx.eval_repr(ptsd, w, gd)
+    torch.cuda.synchronize()
+    say("potentials at %d points %.3f s" % (len(pts), time.perf_counter() - t0))
+    sel = np.linspace(0, len(pts) - 1, 16).astype(np.int64)
+    slr, dlr = oracle.repr_eval(v, t, alpha, 1.0, nt, wh, g, pts[sel])
+    ur = slr - dlr
+    err = np.abs(u.cpu().numpy()[sel] - ur).max() / np.abs(ur).max()
+    say("potentials: sampled relative error %.2e" % err)
+    assert err <= 1e-10
+    ctx.close()
+    torch.cuda.empty_cache()
