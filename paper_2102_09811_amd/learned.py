@@ -187,3 +187,74 @@ def predict(mlp, ctx):
 
 def install(mlp, ctx):
     ctx.precond_set(predict(mlp, ctx))
+
+
+def evaluate(mlp, meshes, n_t=64, T=1.0, tol=1e-8, log=None):
+    """GMRES on the Dirichlet system of each mesh (data exp(alpha t + x.e), E_t steps): plain,
+    with the learned preconditioner, and with the exact sparse approximate inverse on the same
+    pattern.  Returns one record per mesh (iterations and solve seconds)."""
+    import torch
+    from synthetic import exp_solution, nodal_samples
+    out = []
+    for m in meshes:
+        v, t, alpha = m["verts"], m["tris"], m["alpha"]
+        ctx = B.Context(v, t, alpha, T, n_t)
+        ctx.assemble()
+        g = nodal_samples(v, n_t, T, lambda x, tt: exp_solution(x, tt, alpha))
+        b = ctx.rhs_dirichlet(torch.from_numpy(g).cuda())
+        _, ip = ctx.solve(b, method=B.HB_SOLVE_GMRES, tol=tol)
+        install(mlp, ctx)
+        _, il = ctx.solve(b, method=B.HB_SOLVE_GMRES, tol=tol, precond=True)
+        _, _, yex = ctx.precond_spai(exact=True)
+        ctx.precond_set(yex)
+        _, ie = ctx.solve(b, method=B.HB_SOLVE_GMRES, tol=tol, precond=True)
+        rec = {"seed": m["seed"], "E_x": len(t), "alpha": alpha,
+               "plain_it": ip["iterations"], "plain_s": ip["seconds"],
+               "learned_it": il["iterations"], "learned_s": il["seconds"],
+               "learned_res": il["rel_residual"], "exact_spai_it": ie["iterations"]}
+        out.append(rec)
+        if log:
+            log("seed %(seed)d E_x=%(E_x)d alpha=%(alpha).3f: plain %(plain_it)d it, learned "
+                "%(learned_it)d it, exact SPAI %(exact_spai_it)d it" % rec)
+        ctx.close()
+        torch.cuda.empty_cache()
+    return out
+
+
+def main(argv=None):
+    """Train on ellipsoid seeds 0 .. n_train-1, evaluate on seeds 160 .. 160+n_test-1."""
+    import argparse
+    import json
+    import sys
+    import time
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--train", type=int, default=160)
+    ap.add_argument("--test", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--save", default=None, help="write the trained parameters (npz)")
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print("[learned] " + msg, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    train_set = ellipsoid_set(range(args.train))
+    log("training on %d ellipsoids (%d rows)" % (len(train_set), sum(len(m["tris"]) for m in train_set)))
+    mlp, hist = train(train_set, epochs=args.epochs)
+    t_train = time.perf_counter() - t0
+    log("trained in %.1f s, loss %.3e -> %.3e" % (t_train, hist[0], hist[-1]))
+    if args.save:
+        mlp.save(args.save)
+    recs = evaluate(mlp, ellipsoid_set(range(160, 160 + args.test)), log=log)
+    mean = lambda k: float(np.mean([r[k] for r in recs]))
+    summary = {"train_meshes": args.train, "test_meshes": args.test, "epochs": args.epochs,
+               "train_seconds": t_train, "loss_first": hist[0], "loss_last": hist[-1],
+               "mean_plain_it": mean("plain_it"), "mean_learned_it": mean("learned_it"),
+               "mean_exact_spai_it": mean("exact_spai_it"), "mean_plain_s": mean("plain_s"),
+               "mean_learned_s": mean("learned_s"), "meshes": recs}
+    print(json.dumps(summary), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
