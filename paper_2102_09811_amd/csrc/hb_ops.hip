@@ -462,11 +462,19 @@ __global__ __launch_bounds__(256) void k_arnoldi(double *__restrict__ H, int m, 
                                                  double *__restrict__ g, double beta,
                                                  double *__restrict__ inv_nn,
                                                  double *__restrict__ res) {
+  // the column and the earlier rotations are staged in LDS (dynamic: 3 (j+1) doubles), so the
+  // sequential rotation sweep of thread 0 runs at LDS latency
+  extern __shared__ double sh[];
+  double *hc = sh, *sc = sh + (j + 1), *ss = sc + (j + 1);
   __shared__ double red[4];
   for (int v = threadIdx.x; v <= j; v += blockDim.x) {
     double c = 0.0;
     for (int k = 0; k < nchunk; ++k) c += p1[(size_t)v * nchunk + k] + p2[(size_t)v * nchunk + k];
-    H[(size_t)v * m + j] = c;
+    hc[v] = c;
+    if (v < j) {
+      sc[v] = cs[v];
+      ss[v] = sn[v];
+    }
   }
   double sq = 0.0;
   for (int b = threadIdx.x; b < npn; b += blockDim.x) sq += pn[b];
@@ -474,23 +482,28 @@ __global__ __launch_bounds__(256) void k_arnoldi(double *__restrict__ H, int m, 
   for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  const double nn = sqrt(fmax(red[0] + red[1] + red[2] + red[3], 0.0));
-  *inv_nn = nn > 0.0 ? 1.0 / nn : 0.0;
-  for (int i = 0; i < j; ++i) {
-    const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
-    H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
-    H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+  if (threadIdx.x == 0) {
+    const double nn = sqrt(fmax(red[0] + red[1] + red[2] + red[3], 0.0));
+    *inv_nn = nn > 0.0 ? 1.0 / nn : 0.0;
+    double a = hc[0];
+    for (int i = 0; i < j; ++i) {
+      const double b = hc[i + 1];
+      hc[i] = sc[i] * a + ss[i] * b;
+      a = -ss[i] * a + sc[i] * b;
+    }
+    const double rr = hypot(a, nn);
+    const double cj = rr > 0.0 ? a / rr : 1.0, sj = rr > 0.0 ? nn / rr : 0.0;
+    cs[j] = cj;
+    sn[j] = sj;
+    hc[j] = rr;
+    const double gj = g[j];
+    g[j + 1] = -sj * gj;
+    g[j] = cj * gj;
+    res[j] = nn > 0.0 ? fabs(g[j + 1]) / beta : 0.0;
   }
-  const double a = H[(size_t)j * m + j];
-  const double rr = hypot(a, nn);
-  const double cj = rr > 0.0 ? a / rr : 1.0, sj = rr > 0.0 ? nn / rr : 0.0;
-  cs[j] = cj;
-  sn[j] = sj;
-  H[(size_t)j * m + j] = rr;
-  g[j + 1] = -sj * g[j];
-  g[j] = cj * g[j];
-  res[j] = nn > 0.0 ? fabs(g[j + 1]) / beta : 0.0;
+  __syncthreads();
+  for (int v = threadIdx.x; v <= j; v += blockDim.x) H[(size_t)v * m + j] = hc[v];
+  if (threadIdx.x == 0) H[(size_t)(j + 1) * m + j] = 0.0;
 }
 
 __global__ void k_scale_dev(double *__restrict__ y, const double *__restrict__ a, size_t n) {
@@ -937,8 +950,8 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
                        (double *)nullptr);
     hipLaunchKernelGGL(k_multi_dot, dim3(nchunk, j + 1), dim3(256), 0, s, Q, n, wj, n, p2, nchunk);
     hipLaunchKernelGGL(k_cgs_sub, dim3(nblk), dim3(256), shm, s, Q, n, p2, nchunk, j + 1, wj, n, pn);
-    hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(256), 0, s, dH, m, j, p1, p2, nchunk, pn, nblk,
-                       dcs, dsn, dg, beta, dinv, dres);
+    hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(256), sizeof(double) * 3 * (j + 1), s, dH, m, j, p1,
+                       p2, nchunk, pn, nblk, dcs, dsn, dg, beta, dinv, dres);
     hipLaunchKernelGGL(k_scale_dev, dim3(grid1d(n)), dim3(256), 0, s, wj, dinv, n);
     HB_CHECK(c, hipGetLastError());
     HB_CHECK(c, hipMemcpyAsync(c->h_res + j, dres + j, sizeof(double), hipMemcpyDeviceToHost, s));
