@@ -83,7 +83,7 @@ void hb_default_options(hb_options *opt);
 int hb_check_mesh(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
                   int64_t class_counts[4]);
 
-/* Create a context for mesh Gamma_h, heat capacity alpha > 0, final time T > 0 and n_t >= 1
+/* Create a context for mesh Gamma_h, heat capacity alpha > 0, final time T > 0 and 1 <= n_t <= 65536
  * uniform steps (Sec. 3).  verts/tris are host pointers as for hb_check_mesh.  Validates the
  * mesh (closed, 2-manifold, consistently and outward oriented, no repeated or coincident
  * vertices, no degenerate triangle), classifies the triangle pairs, builds the quadrature tables
@@ -121,7 +121,9 @@ int hb_get_blocks(hb_ctx *ctx, uint32_t op, int32_t d0, int32_t nd, void *dst, i
 
 /* Block lower-triangular Toeplitz product y^k = sum_{d=0}^{k} A^d x^{k-d} (Sec. 3.1 eq. for
  * V_h w; Sec. 3.2 eq. for K_h) for op = HB_OP_V (x: E_t x E_x) or HB_OP_K (x: E_t x N_x);
- * y: E_t x E_x.  x, y: device pointers, float64, time-major, not overlapping. */
+ * y: E_t x E_x.  x, y: device pointers, float64, time-major, not overlapping.  Supports
+ * E_t <= 256 (HB_EINVAL beyond); float block storage multiplies in float (x rounded to float) with
+ * the partial sums added in double. */
 int hb_apply(hb_ctx *ctx, uint32_t op, const double *x, double *y, void *stream);
 
 /* Right-hand side of the Dirichlet system b = (1/2 M_h + K_h) g (Sec. 3.4) with
@@ -155,7 +157,8 @@ typedef struct hb_solve_info {
 } hb_solve_info;
 
 /* Solve V_h w = b for w.  b, w: device pointers, E_t x E_x, float64.  info may be NULL.
- * Returns HB_ENOCONV (w then holds the last iterate) when GMRES hits max_iter first. */
+ * Returns HB_ENOCONV (w then holds the last iterate) when GMRES hits max_iter first.  All
+ * methods use the block-Toeplitz product, so E_t <= 256. */
 int hb_solve(hb_ctx *ctx, const double *b, double *w, const hb_solve_opts *opts,
              hb_solve_info *info, void *stream);
 
@@ -163,7 +166,9 @@ int hb_solve(hb_ctx *ctx, const double *b, double *w, const hb_solve_opts *opts,
  * pts[P][4] = (x, y, z, t), 0 <= t <= T, off Gamma_h (not checked; accuracy near Gamma_h is
  * the caller's concern).  w: E_t x E_x Neumann coefficients, g: E_t x N_x Dirichlet
  * coefficients, u: P outputs.  All device pointers, float64.  The spatial rule is the 7-point
- * rule of hb_assemble.  sl / dl may be NULL; otherwise they receive V~ w and W g. */
+ * rule of hb_assemble.  sl / dl may be NULL; otherwise they receive V~ w and W g.  Each point's
+ * interval coefficients live in one workgroup's LDS, which bounds E_t at about 900 (HB_EINVAL
+ * beyond). */
 int hb_eval_repr(hb_ctx *ctx, const double *pts, int64_t P, const double *w, const double *g,
                  double *u, double *sl, double *dl, void *stream);
 
