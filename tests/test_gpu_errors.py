@@ -1,0 +1,90 @@
+"""Error paths and edge cases of the C ABI on a device context.  Every case here is rejected (or
+handled) by the library's host-side checks before any kernel is launched."""
+import numpy as np
+import pytest
+
+from synthetic import cube, tetrahedron
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available()
+    return _t
+
+
+def test_call_order_and_arguments(torch):
+    from paper_2102_09811_amd import (HB_EINVAL, HB_ESTATE, HB_OP_K, HB_OP_V, Context, HBError)
+    v, t = tetrahedron()
+    ctx = Context(v, t, 1.0, 1.0, 4)
+    x = torch.zeros((4, len(t)), dtype=torch.float64, device="cuda")
+    with pytest.raises(HBError) as e:          # nothing assembled yet
+        ctx.apply(HB_OP_V, x)
+    assert e.value.code == HB_ESTATE
+    with pytest.raises(HBError) as e:
+        ctx.solve(x)
+    assert e.value.code == HB_ESTATE
+    for ops in (0, 4):
+        with pytest.raises(HBError) as e:
+            ctx.assemble(ops)
+        assert e.value.code == HB_EINVAL
+    with pytest.raises(HBError) as e:
+        ctx.assemble(HB_OP_V | HB_OP_K, precision=7)
+    assert e.value.code == HB_EINVAL
+    ctx.assemble()
+    with pytest.raises(HBError) as e:          # block range past E_t
+        ctx.blocks(HB_OP_V, 3, 2)
+    assert e.value.code == HB_EINVAL
+    with pytest.raises(HBError) as e:          # no preconditioner installed
+        ctx.solve(x + 1.0, precond=True)
+    assert e.value.code == HB_ESTATE
+    with pytest.raises(HBError) as e:
+        ctx.solve(x + 1.0, method=9)
+    assert e.value.code == HB_EINVAL
+    ctx.close()
+
+
+def test_gmres_reports_no_convergence(torch):
+    from paper_2102_09811_amd import Context
+    v, t = cube(2)
+    ctx = Context(v, t, 1.0, 1.0, 8)
+    ctx.assemble()
+    b = torch.from_numpy(np.random.default_rng(3).standard_normal((8, len(t)))).cuda()
+    w, info = ctx.solve(b, tol=1e-12, max_iter=3)
+    assert not info["converged"] and info["iterations"] == 3
+    assert np.isfinite(w.cpu().numpy()).all()
+    w, info = ctx.solve(b, tol=1e-8)
+    assert info["converged"] and info["rel_residual"] <= 1e-8
+    ctx.close()
+
+
+def test_time_limits(torch):
+    """E_t = 300: assembly works; the Toeplitz product (and so every solver) refuses E_t > 256;
+    potentials still work.  E_t = 1000: the potentials refuse (LDS table)."""
+    from paper_2102_09811_amd import HB_EINVAL, HB_OP_V, Context, HBError
+    v, t = tetrahedron()
+    ctx = Context(v, t, 1.0, 1.0, 300)
+    ctx.assemble()
+    x = torch.zeros((300, len(t)), dtype=torch.float64, device="cuda")
+    with pytest.raises(HBError) as e:
+        ctx.apply(HB_OP_V, x)
+    assert e.value.code == HB_EINVAL
+    with pytest.raises(HBError) as e:
+        ctx.solve(x + 1.0)
+    assert e.value.code == HB_EINVAL
+    pts = torch.tensor([[0.1, 0.1, 0.1, 0.5]], dtype=torch.float64, device="cuda")
+    g = torch.zeros((300, len(v)), dtype=torch.float64, device="cuda")
+    u = ctx.eval_repr(pts, x, g)
+    assert float(u.abs().max()) == 0.0
+    empty = torch.zeros((0, 4), dtype=torch.float64, device="cuda")
+    assert ctx.eval_repr(empty, x, g).numel() == 0
+    ctx.close()
+    ctx = Context(v, t, 1.0, 1.0, 1000)
+    x = torch.zeros((1000, len(t)), dtype=torch.float64, device="cuda")
+    g = torch.zeros((1000, len(v)), dtype=torch.float64, device="cuda")
+    with pytest.raises(HBError) as e:
+        ctx.eval_repr(pts, x, g)
+    assert e.value.code == HB_EINVAL
+    ctx.close()
