@@ -66,9 +66,10 @@ typedef struct hb_options {
   int32_t storage;      /* HB_DTYPE_F64 (default) or HB_DTYPE_F32 block storage. */
   int32_t mixed_d_min;  /* HB_PREC_MIXED: separated pairs at d >= d0 are evaluated in float,
                            where d0 is the first d >= max(mixed_d_min, d_switch) with d - d_switch
-                           even (kernel value and a Taylor polynomial of degree 8, 6 or 4 as d
-                           grows, double accumulation); smaller d and all touching pairs stay in
-                           double.  Default 8, minimum 2. */
+                           even (kernel value and a Taylor polynomial of degree 16 at d = 3 down
+                           to 4 as d grows, truncation below 2e-9 of the block scale; double
+                           accumulation); the closed-form blocks d < d_switch and all touching
+                           pairs stay in double.  Default 3 (every Taylor block), minimum 2. */
   int32_t reserved[12]; /* must be zero */
 } hb_options;
 

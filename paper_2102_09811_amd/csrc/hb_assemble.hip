@@ -457,7 +457,10 @@ __global__ __launch_bounds__(256, 3) void k_separated(const AsmParams *__restric
     }
     if (MIXED && d >= p.mixed_d_min) {
       switch (T.tdeg[2 * d + 1]) {
-        case 8: sym_taylor2_32<kTaylorN32>(p, T, d, m, L, R); break;
+        case 16: sym_taylor2_32<17>(p, T, d, m, L, R); break;
+        case 12: sym_taylor2_32<13>(p, T, d, m, L, R); break;
+        case 10: sym_taylor2_32<11>(p, T, d, m, L, R); break;
+        case 8: sym_taylor2_32<9>(p, T, d, m, L, R); break;
         case 6: sym_taylor2_32<7>(p, T, d, m, L, R); break;
         default: sym_taylor2_32<5>(p, T, d, m, L, R); break;
       }

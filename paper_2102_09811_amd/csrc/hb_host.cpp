@@ -386,7 +386,9 @@ int build_tables(hb_ctx *c) {
     return d < 4 ? 28 : d < 5 ? 24 : d < 6 ? 20 : d < 7 ? 18 : d < 8 ? 16 : d < 12 ? 14
          : d < 16 ? 12 : d < 32 ? 10 : d < 64 ? 8 : 6;
   };
-  auto deg32 = [](int d) { return d < 12 ? 8 : d < 24 ? 6 : 4; };
+  auto deg32 = [](int d) {
+    return d < 4 ? 16 : d < 5 ? 12 : d < 7 ? 10 : d < 12 ? 8 : d < 24 ? 6 : 4;
+  };
   auto pass_start = [&](int d) { return d - ((d - p.dsw) & 1); };
   std::vector<double> tay((size_t)c->nt * 2 * kTaylorN, 0.0), tsc((size_t)c->nt * 3, 0.0);
   std::vector<float> tay32((size_t)c->nt * 2 * kTaylorN32, 0.0f);
@@ -535,7 +537,7 @@ void hb_default_options(hb_options *o) {
   o->ss_order = 4;
   o->d_switch = 3;
   o->storage = HB_DTYPE_F64;
-  o->mixed_d_min = 8;
+  o->mixed_d_min = 3;
 }
 
 int hb_check_mesh(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,

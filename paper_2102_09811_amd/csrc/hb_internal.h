@@ -16,7 +16,7 @@ namespace hb {
 // 0 .. d_switch; later blocks use the Taylor form, whose degree falls as d grows (28 at d = 3).
 constexpr int kTaylorDeg = 28;       // largest degree of the Taylor polynomial in w = rho^2/(4 alpha d h)
 constexpr int kTaylorN = kTaylorDeg + 1;
-constexpr int kTaylorDeg32 = 8;      // degree used by the float evaluation (mixed precision)
+constexpr int kTaylorDeg32 = 16;     // largest degree of the float evaluation (mixed precision)
 constexpr int kTaylorN32 = kTaylorDeg32 + 1;
 constexpr int kSeriesN = 14;         // terms of the small-z series of the brackets A(z), B(z)
 constexpr int kMaxClosed = 16;       // largest supported d_switch
