@@ -613,13 +613,17 @@ __device__ __forceinline__ void touching_pass(const AsmParams &p, const TouchPai
 template <typename TS, int D>
 __global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict__ pp,
                                                     const TouchPair *__restrict__ pairs,
-                                                    const double *__restrict__ tab, int ntab,
+                                                    RuleTabs rules,
                                                     const double *__restrict__ tscale,
                                                     const double *__restrict__ taylor,
                                                     const int *__restrict__ tdeg) {
   const AsmParams &p = *pp;
   const SepTabs T{nullptr, tscale, taylor, nullptr, tdeg};
   const TouchPair &tp = pairs[blockIdx.x];
+  // the pair's class (3 identical, 2 edge, 1 vertex) picks its regularised rule
+  const int cls = __builtin_amdgcn_readfirstlane(tp.cls);
+  const double *__restrict__ tab = rules.d[cls];
+  const int ntab = rules.n[cls];
   const int lane = threadIdx.x;
   const int l = tp.l, m = tp.m;
   const int vtx[3] = {tp.vtx[0], tp.vtx[1], tp.vtx[2]};
@@ -741,14 +745,20 @@ void launch_fold_KT(const AsmParams &p, int storage_f32, hipStream_t s) {
 
 template <typename TS, int D>
 static void launch_touch(dim3 grid, hipStream_t s, const AsmParams *dp, const AsmParams &hp,
-                         const TouchPair *pairs, const SSRule &rule) {
-  hipLaunchKernelGGL((k_touching<TS, D>), grid, dim3(64), 0, s, dp, pairs, rule.d, rule.n,
-                     hp.tscale, hp.taylor, hp.tdeg);
+                         const TouchPair *pairs, const RuleTabs &rule) {
+  hipLaunchKernelGGL((k_touching<TS, D>), grid, dim3(64), 0, s, dp, pairs, rule, hp.tscale,
+                     hp.taylor, hp.tdeg);
 }
 
 void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,
-                              int64_t npairs, const SSRule &rule, int storage_f32, hipStream_t s) {
+                              int64_t npairs, const SSRule rules[4], int storage_f32,
+                              hipStream_t s) {
   dim3 grid((unsigned)npairs);
+  RuleTabs rule{};
+  for (int c = 1; c <= 3; ++c) {
+    rule.d[c] = rules[c].d;
+    rule.n[c] = rules[c].n;
+  }
   switch (p.dsw) {
     case 16:
       if (storage_f32) launch_touch<float, 16>(grid, s, dp, p, pairs, rule);

@@ -662,13 +662,11 @@ int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
     HB_HIP(c, hipGetLastError());
   }
   HB_HIP(c, hipEventRecord(c->ev[1], s));
-  int64_t off = 0;
-  for (int cls = 3; cls >= 1; --cls) {
-    int64_t n = c->n_class[cls];
-    if (n > 0)
-      hb::launch_assemble_touching(c->d_params, p, c->d_touch + off, n, c->ss[cls], c->storage_f32, s);
-    off += n;
-  }
+  // all touching pairs in one launch (the list is sorted identical, edge, vertex: the longest
+  // pairs start first and the classes overlap)
+  const int64_t ntouch = c->n_class[1] + c->n_class[2] + c->n_class[3];
+  if (ntouch > 0)
+    hb::launch_assemble_touching(c->d_params, p, c->d_touch, ntouch, c->ss, c->storage_f32, s);
   HB_HIP(c, hipGetLastError());
   HB_HIP(c, hipEventRecord(c->ev[2], s));
   if (p.do_V) {

@@ -76,12 +76,19 @@ struct SSRule {
   double *d = nullptr;         // device: [8][n] = c1, c2, c3, c4, w, lam0, lam1, lam2
 };
 
+// The three classes' rule tables as one kernel argument (index = shared vertices, 1..3).
+struct RuleTabs {
+  const double *d[4];
+  int32_t n[4];
+};
+
 // dp: device copy of p (kernels read their parameters from device memory)
 void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, const int32_t *tasks,
                                int64_t ntasks, int precision, int storage_f32, hipStream_t s);
 void launch_fold_KT(const AsmParams &p, int storage_f32, hipStream_t s);
 void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,
-                              int64_t npairs, const SSRule &rule, int storage_f32, hipStream_t s);
+                              int64_t npairs, const SSRule rules[4], int storage_f32,
+                              hipStream_t s);
 
 // y = A x for the block-Toeplitz operator with blocks [nt][R][C] (y overwritten, time-major)
 int toeplitz_apply(hb_ctx *c, const void *blocks, int R, int C, const double *x, double *y,
