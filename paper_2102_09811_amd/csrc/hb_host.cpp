@@ -634,8 +634,14 @@ int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   size_t esz = c->storage_f32 ? 4 : 8;
   size_t nV = (size_t)c->nt * c->ne * c->ne, nK = (size_t)c->nt * c->ne * c->nv;
-  if ((ops & HB_OP_V) && !c->d_V) HB_HIP(c, hipMalloc(&c->d_V, nV * esz));
-  if ((ops & HB_OP_K) && !c->d_K) HB_HIP(c, hipMalloc(&c->d_K, nK * esz));
+  if ((ops & HB_OP_V) && !c->d_V) {
+    HB_HIP(c, hipMalloc(&c->d_V, nV * esz + hb::kBlockPad));
+    HB_HIP(c, hipMemsetAsync((char *)c->d_V + nV * esz, 0, hb::kBlockPad, s));
+  }
+  if ((ops & HB_OP_K) && !c->d_K) {
+    HB_HIP(c, hipMalloc(&c->d_K, nK * esz + hb::kBlockPad));
+    HB_HIP(c, hipMemsetAsync((char *)c->d_K + nK * esz, 0, hb::kBlockPad, s));
+  }
   if ((ops & HB_OP_K) && !c->d_KT) HB_HIP(c, hipMalloc(&c->d_KT, nK * esz));
   hb::AsmParams &p = c->launch;
   p = c->params;

@@ -28,14 +28,15 @@ namespace {
 // Block-Toeplitz product Y[k][r] = sum_{d <= k} sum_c A^d[r][c] X[k-d][c] on MFMA
 // (v_mfma_f64_16x16x4 for double blocks, v_mfma_f32_16x16x4 for float blocks).
 // Workgroup = 64 rows (wave w: rows 16w..16w+15) x all E_t time steps, for the column chunks of
-// its group g and the d range of its slice z.  Per 32-column chunk the source X[:, chunk] is
-// staged in LDS once, behind 16 zero rows, and serves every d (the time shift k - d is applied
-// when reading it).  A streams from HBM straight into MFMA fragments: lane l (lm = l % 16,
-// lk = l / 16) loads the 8 consecutive entries A^d[row 16w + lm][c0 + 8 lk .. + 8] and feeds entry
-// s as the k = lk operand of step s, matched by the B operand X[time 16n + lm - d][c0 + 8 lk + s]
-// (the steps cover the 32 columns in a permuted order).  The next d's fragment is loaded while
-// the current one runs.  Time chunks that end before d are skipped.  Each (g, z) writes the
-// partial result P[g][z][k][r]; k_sum_groups adds them in a fixed order.
+// its group g and the blocks d = dlo + z, dlo + z + slices, ... of its slice z.  Per 32-column
+// chunk the source X[:, chunk] is staged in LDS once, behind 16 zero rows, and serves every d
+// (the time shift k - d is applied when reading it).  A streams from HBM straight into MFMA
+// fragments: lane l (lm = l % 16, lk = l / 16) loads the 8 consecutive entries
+// A^d[row 16w + lm][c0 + 8 lk .. + 8] and feeds entry s as the k = lk operand of step s, matched
+// by the B operand X[time 16n + lm - d][c0 + 8 lk + s] (the steps cover the 32 columns in a
+// permuted order).  The next d's fragment is loaded while the current one runs.  Time chunks
+// that end before d are skipped.  Each (g, z) writes the partial result P[g][z][k][r];
+// k_sum_groups adds them in a fixed order.
 // ------------------------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -63,51 +64,21 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int lk, int i) { return 4 * lk + i; }
 };
 
-// This lane's 8 consecutive entries of a block row (zero outside the block).  vec: the row
-// segment is 16-byte aligned and inside the block.
+// This lane's 8 consecutive entries of a block row.  No bounds test: rows past the block are
+// clamped by the caller (their outputs are never stored), entries past the row end belong to the
+// next row or to the zeroed tail of the storage (hb_internal.h: kBlockPad) and meet zeros of the
+// staged X, so every fragment is two (float) or four (double) plain 16-byte loads.
 template <typename TA>
-__device__ __forceinline__ void load_frag(TA (&a)[8], const TA *__restrict__ p, bool vec,
-                                          bool full, bool row_ok, int ncol) {
-  if (vec) {
-    if constexpr (sizeof(TA) == 8) {
-      typedef double v2 __attribute__((ext_vector_type(2)));
-      const v2 *q = (const v2 *)p;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const v2 t = q[i];
-        a[2 * i] = t[0];
-        a[2 * i + 1] = t[1];
-      }
-    } else {
-      typedef float v4 __attribute__((ext_vector_type(4)));
-      const v4 *q = (const v4 *)p;
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const v4 t = q[i];
-        a[4 * i] = t[0];
-        a[4 * i + 1] = t[1];
-        a[4 * i + 2] = t[2];
-        a[4 * i + 3] = t[3];
-      }
-    }
-  } else if (full) {
-#pragma unroll
-    for (int s = 0; s < 8; ++s) a[s] = p[s];
-  } else {
-#pragma unroll
-    for (int s = 0; s < 8; ++s) a[s] = (row_ok && s < ncol) ? p[s] : TA(0);
-  }
+__device__ __forceinline__ void load_frag(TA (&a)[8], const TA *__restrict__ p) {
+  __builtin_memcpy(a, p, 8 * sizeof(TA));
 }
 
-// MFMA steps of block d with fragment a for the time chunks NS..NTC-1.
+// MFMA steps of block d with fragment a for the time chunks NS..NTC-1 (sources outside the
+// requested time window are staged as zeros, so no chunk needs a runtime skip: a data-dependent
+// branch here costs the accumulators their registers).
 template <typename TA, int NTC, int NS>
 __device__ __forceinline__ void toeplitz_block(typename Mfma<TA>::acc_t (&acc)[NTC], const TA (&a)[8],
-                                               const TA *Xs, int d, int jlo, int jhi, int lm,
-                                               int lk) {
-  // (sources outside [jlo, jhi) are staged as zeros, so no chunk needs a runtime skip: a
-  // data-dependent branch here costs the accumulators their registers)
-  (void)jlo;
-  (void)jhi;
+                                               const TA *Xs, int d, int lm, int lk) {
 #pragma unroll
   for (int n = NS; n < NTC; ++n) {
     const TA *xb = Xs + (16 + 16 * n + lm - d) * kXS + 8 * lk;
@@ -116,37 +87,36 @@ __device__ __forceinline__ void toeplitz_block(typename Mfma<TA>::acc_t (&acc)[N
   }
 }
 
-// Blocks d = dlo .. dhi-1, all of whose nonzero output times lie in the time chunks NS..NTC-1.
-// On entry a holds the fragment of block max(d0, 16 NS) (if that block is in range); two
-// fragment buffers alternate, the next block's loads in flight while a block is multiplied.
+// The blocks d0, d0 + ds, d0 + 2 ds, ... below d1 whose nonzero output times all lie in the time
+// chunks NS..NTC-1.  On entry a holds the fragment of the first such block at or after 16 NS (if
+// there is one); two fragment buffers alternate, the next block's loads in flight while a block
+// is multiplied.
 template <typename TA, int NTC, int NS>
 struct ToeplitzRange {
   typedef typename Mfma<TA>::acc_t acc_t;
   static __device__ __forceinline__ void run(acc_t (&acc)[NTC], TA (&a)[8], const TA *Xs,
-                                             const TA *arow, size_t blk, int d0, int d1, int jlo,
-                                             int jhi, bool vec, bool full, bool row_ok, int ncol,
+                                             const TA *arow, size_t blk, int d0, int d1, int ds,
                                              int lm, int lk) {
     if constexpr (NS < NTC) {
-      const int dlo = max(d0, 16 * NS), dhi = min(d1, 16 * NS + 16);
-      int d = dlo;
-      for (; d + 1 < dhi; d += 2) {
+      const int lo = max(d0, 16 * NS), dhi = min(d1, 16 * NS + 16);
+      int d = d0 + (lo - d0 + ds - 1) / ds * ds;
+      for (; d + ds < dhi; d += 2 * ds) {
         TA b[8];
-        load_frag(b, arow + (size_t)(d + 1) * blk, vec, full, row_ok, ncol);
-        toeplitz_block<TA, NTC, NS>(acc, a, Xs, d, jlo, jhi, lm, lk);
-        if (d + 2 < d1) load_frag(a, arow + (size_t)(d + 2) * blk, vec, full, row_ok, ncol);
-        toeplitz_block<TA, NTC, NS>(acc, b, Xs, d + 1, jlo, jhi, lm, lk);
+        load_frag(b, arow + (size_t)(d + ds) * blk);
+        toeplitz_block<TA, NTC, NS>(acc, a, Xs, d, lm, lk);
+        if (d + 2 * ds < d1) load_frag(a, arow + (size_t)(d + 2 * ds) * blk);
+        toeplitz_block<TA, NTC, NS>(acc, b, Xs, d + ds, lm, lk);
       }
       if (d < dhi) {
         TA b[8];
-        if (d + 1 < d1) load_frag(b, arow + (size_t)(d + 1) * blk, vec, full, row_ok, ncol);
-        toeplitz_block<TA, NTC, NS>(acc, a, Xs, d, jlo, jhi, lm, lk);
-        if (d + 1 < d1) {
+        if (d + ds < d1) load_frag(b, arow + (size_t)(d + ds) * blk);
+        toeplitz_block<TA, NTC, NS>(acc, a, Xs, d, lm, lk);
+        if (d + ds < d1) {
 #pragma unroll
           for (int s = 0; s < 8; ++s) a[s] = b[s];
         }
       }
-      ToeplitzRange<TA, NTC, NS + 1>::run(acc, a, Xs, arow, blk, d0, d1, jlo, jhi, vec, full,
-                                          row_ok, ncol, lm, lk);
+      ToeplitzRange<TA, NTC, NS + 1>::run(acc, a, Xs, arow, blk, d0, d1, ds, lm, lk);
     }
   }
 };
@@ -155,8 +125,7 @@ template <typename TA, int NTC>
 __global__ __launch_bounds__(256) void k_toeplitz(const TA *__restrict__ A,
                                                   const double *__restrict__ X,
                                                   TA *__restrict__ P, int nt, int R, int C,
-                                                  int cpg, int dper, int dlo, int dhi, int jlo,
-                                                  int jhi) {
+                                                  int cpg, int dlo, int dhi, int jlo, int jhi) {
   typedef Mfma<TA> M;
   constexpr int NT = 16 * NTC;
   __shared__ TA Xs[(NT + 16) * kXS];
@@ -165,7 +134,7 @@ __global__ __launch_bounds__(256) void k_toeplitz(const TA *__restrict__ A,
   const int g = blockIdx.y, z = blockIdx.z;
   const int nchunk = (C + kTC - 1) / kTC;
   const int q0 = g * cpg, q1 = min(q0 + cpg, nchunk);
-  const int d0 = dlo + z * dper, d1 = min(d0 + dper, dhi);
+  const int d0 = dlo + z, d1 = dhi, ds = gridDim.z;  // interleaved: equal work per slice
   typename M::acc_t acc[NTC];
 #pragma unroll
   for (int n = 0; n < NTC; ++n) acc[n] = M::zero();
@@ -178,19 +147,10 @@ __global__ __launch_bounds__(256) void k_toeplitz(const TA *__restrict__ A,
       Xs[row * kXS + col] = (j >= jlo && j < jhi && c < C) ? (TA)X[(size_t)j * C + c] : TA(0);
     }
     __syncthreads();
-    const int cb = c0 + 8 * lk;
-    const bool row_ok = r < R;
-    const bool full = row_ok && cb + 8 <= C;
-    const int ncol = C - cb;
-    const TA *arow = A + (size_t)(row_ok ? r : 0) * C + cb;
-    // 16-byte aligned rows: every block starts aligned (blocks are R*C elements apart and the
-    // storage is 256-byte aligned) when R*C and C are multiples of 16 / sizeof(TA)
-    constexpr int kAl = 16 / sizeof(TA);
-    const bool vec = full && (C % kAl == 0) && (blk % kAl == 0);
+    const TA *arow = A + (size_t)min(r, R - 1) * C + c0 + 8 * lk;
     TA a[8];
-    load_frag(a, arow + (size_t)d0 * blk, vec, full, row_ok, ncol);
-    ToeplitzRange<TA, NTC, 0>::run(acc, a, Xs, arow, blk, d0, d1, jlo, jhi, vec, full, row_ok,
-                                   ncol, lm, lk);
+    load_frag(a, arow + (size_t)d0 * blk);
+    ToeplitzRange<TA, NTC, 0>::run(acc, a, Xs, arow, blk, d0, d1, ds, lm, lk);
   }
   const int part = g * gridDim.z + z;
 #pragma unroll
@@ -211,7 +171,15 @@ __global__ void k_sum_groups(const TP *__restrict__ P, int G, size_t n, double *
                              int sub, size_t i0) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     double s = 0.0;
-    for (int g = 0; g < G; ++g) s += (double)P[(size_t)g * n + i];
+    int g = 0;
+    for (; g + 8 <= G; g += 8) {  // eight loads in flight, added in order
+      TP v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = P[(size_t)(g + u) * n + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += (double)v[u];
+    }
+    for (; g < G; ++g) s += (double)P[(size_t)g * n + i];
     if (!sub) Y[i] = s;
     else if (i >= i0) Y[i] -= s;
   }
@@ -453,7 +421,8 @@ __global__ __launch_bounds__(256) void k_cgs_sub(const double *__restrict__ Q, s
 // Arnoldi step j on the device: column j of the Hessenberg matrix H (row-major, m columns) from
 // the two Gram-Schmidt passes (partial sums p1, p2) and the norm (partials pn), the earlier Givens
 // rotations applied to it, the new rotation, the rotated right-hand side g, 1 / ||w|| for the
-// normalisation and the residual estimate |g_{j+1}| / beta in res[j].
+// normalisation and the residual estimate |g_{j+1}| / beta in res[j], written straight into
+// host memory (coherent pinned memory mapped into the device's address space).
 __global__ __launch_bounds__(256) void k_arnoldi(double *__restrict__ H, int m, int j,
                                                  const double *__restrict__ p1,
                                                  const double *__restrict__ p2, int nchunk,
@@ -728,22 +697,22 @@ int ensure_work(hb_ctx *c, size_t bytes) {
 
 // y = A x (Toeplitz), y overwritten
 // Split of the product over workgroups: 64-row tiles x column groups (cpg chunks each) x d
-// slices (dper blocks each), aiming at >= 768 workgroups with as few partial results as possible.
+// slices (slice z takes every slices-th block from dlo + z, so all slices carry the same work),
+// aiming at >= kApplyWant workgroups with as few partial results as possible.
+constexpr int kApplyWant = 768;
 struct ApplySplit {
-  int rt, nchunk, cpg, groups, dper, slices;
+  int rt, nchunk, cpg, groups, slices;
 };
 
-static ApplySplit apply_split(int R, int C, int nt) {
+static ApplySplit apply_split(int R, int C, int nd) {
   ApplySplit a;
   a.rt = (R + TR - 1) / TR;
   a.nchunk = (C + kTC - 1) / kTC;
-  const int want = 768;
-  int groups = std::max(1, std::min(a.nchunk, (want + a.rt - 1) / a.rt));
+  const int want = kApplyWant;
+  const int groups = std::max(1, std::min(a.nchunk, (want + a.rt - 1) / a.rt));
   a.cpg = (a.nchunk + groups - 1) / groups;
   a.groups = (a.nchunk + a.cpg - 1) / a.cpg;
-  int slices = std::max(1, std::min(std::max(1, nt / 8), (want + a.rt * a.groups - 1) / (a.rt * a.groups)));
-  a.dper = (nt + slices - 1) / slices;
-  a.slices = (nt + a.dper - 1) / a.dper;
+  a.slices = std::max(1, std::min(std::max(1, nd / 8), (want + a.rt * a.groups - 1) / (a.rt * a.groups)));
   return a;
 }
 
@@ -779,7 +748,7 @@ static int launch_toeplitz(hb_ctx *c, const TA *A, int R, int C, const double *x
   dim3 grid(sp.rt, sp.groups, sp.slices);
 #define HB_TOEP(NTC_)                                                                          \
   hipLaunchKernelGGL((k_toeplitz<TA, NTC_>), grid, dim3(256), 0, s, A, x, P, nt, R, C, sp.cpg, \
-                     sp.dper, dlo, dhi, jlo, jhi)
+                     dlo, dhi, jlo, jhi)
   switch (ntc) {
     case 1: HB_TOEP(1); break;
     case 2: HB_TOEP(2); break;
@@ -884,7 +853,10 @@ int apply_V(hb_ctx *c, int op, const double *x, double *y, hipStream_t s) {
 int ensure_V32(hb_ctx *c, hipStream_t s) {
   if (c->storage_f32 || c->V32_valid) return HB_OK;
   const size_t n = (size_t)c->nt * c->ne * c->ne;
-  if (!c->d_V32) HB_CHECK(c, hipMalloc(&c->d_V32, n * sizeof(float)));
+  if (!c->d_V32) {
+    HB_CHECK(c, hipMalloc(&c->d_V32, n * sizeof(float) + kBlockPad));
+    HB_CHECK(c, hipMemsetAsync((char *)c->d_V32 + n * sizeof(float), 0, kBlockPad, s));
+  }
   hipLaunchKernelGGL(k_to_float, dim3(grid1d(n)), dim3(256), 0, s, (const double *)c->d_V, c->d_V32, n);
   HB_CHECK(c, hipGetLastError());
   c->V32_valid = true;
@@ -914,9 +886,12 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
     if (c->h_res) (void)hipHostFree(c->h_res);
     c->h_res = nullptr;
     c->h_res_n = 0;
-    HB_CHECK(c, hipHostMalloc((void **)&c->h_res, sizeof(double) * (m + 1)));
+    HB_CHECK(c, hipHostMalloc((void **)&c->h_res, sizeof(double) * (m + 1),
+                              hipHostMallocMapped | hipHostMallocCoherent));
     c->h_res_n = m + 1;
   }
+  double *res_dev = nullptr;  // the device's address of h_res
+  HB_CHECK(c, hipHostGetDevicePointer((void **)&res_dev, c->h_res, 0));
   if (!c->ev_step) HB_CHECK(c, hipEventCreateWithFlags(&c->ev_step, hipEventDisableTiming));
   if (!c->ev_prev) HB_CHECK(c, hipEventCreateWithFlags(&c->ev_prev, hipEventDisableTiming));
   double beta;
@@ -951,10 +926,9 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
     hipLaunchKernelGGL(k_multi_dot, dim3(nchunk, j + 1), dim3(256), 0, s, Q, n, wj, n, p2, nchunk);
     hipLaunchKernelGGL(k_cgs_sub, dim3(nblk), dim3(256), shm, s, Q, n, p2, nchunk, j + 1, wj, n, pn);
     hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(256), sizeof(double) * 3 * (j + 1), s, dH, m, j, p1,
-                       p2, nchunk, pn, nblk, dcs, dsn, dg, beta, dinv, dres);
+                       p2, nchunk, pn, nblk, dcs, dsn, dg, beta, dinv, res_dev);
     hipLaunchKernelGGL(k_scale_dev, dim3(grid1d(n)), dim3(256), 0, s, wj, dinv, n);
     HB_CHECK(c, hipGetLastError());
-    HB_CHECK(c, hipMemcpyAsync(c->h_res + j, dres + j, sizeof(double), hipMemcpyDeviceToHost, s));
     HB_CHECK(c, hipEventRecord(c->ev_step, s));
     // step j is queued; look at step j - 1 (finished or about to) while it runs
     if (j > 0) {
