@@ -210,6 +210,7 @@ struct SepTabs {
   const double *__restrict__ taylor;    // [nt][2][kTaylorN]
   const float *__restrict__ taylor32;   // [nt][2][kTaylorN32]
   const int *__restrict__ tdeg;         // [nt][2]
+  const double *etab;                   // LDS: 2^{-j/64}, j < 64 (exp_neg_t)
 };
 
 // Per-lane data of an unordered separated pair.
@@ -317,7 +318,7 @@ __device__ __forceinline__ void sym_taylor2(const AsmParams &p, const SepTabs &T
       const double wrn1 = wa * fma(rx, L.nm[0], fma(ry, L.nm[1], rz * L.nm[2]));
       const double wrn2 = -(wa * wb) * fma(rx, L.nl[0], fma(ry, L.nl[1], rz * L.nl[2]));
       const double w0 = rho2 * c0, w1 = rho2 * c1;
-      const double e0 = exp_neg(w0), e1 = exp_neg(w1);
+      const double e0 = exp_neg_t(w0, T.etab), e1 = exp_neg_t(w1, T.etab);
       const double pk0 = horner<N>(ck0, w0) * e0, pk1 = horner<N>(ck1, w1) * e1;
       tv0 = fma(wa * e0, horner<N>(cv0, w0), tv0);
       tv1 = fma(wa * e1, horner<N>(cv1, w1), tv1);
@@ -405,7 +406,10 @@ __global__ __launch_bounds__(256, 3) void k_separated(const AsmParams *__restric
                                                       const int *__restrict__ tdeg,
                                                       const int *__restrict__ tasks, int ntasks) {
   const AsmParams &p = *pp;
-  const SepTabs T{geom, tscale, taylor, taylor32, tdeg};
+  __shared__ double etab[64];
+  stage_exp_tab(etab);
+  __syncthreads();
+  const SepTabs T{geom, tscale, taylor, taylor32, tdeg, etab};
   // one task per wave: test panel l and the 64 trial panels m0 .. m0+63 (all > l)
   const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (task >= ntasks) return;
@@ -551,7 +555,7 @@ __device__ __forceinline__ void touch_taylor2(const AsmParams &p, const SepTabs 
   for (int q = lane; q < ntab; q += 64) {
     const TouchPoint t = touch_point(tp, tab, ntab, q, false);
     const double w0 = t.rho2 * c0, w1 = t.rho2 * c1;
-    const double e0 = exp_neg(w0), e1 = exp_neg(w1);
+    const double e0 = exp_neg_t(w0, T.etab), e1 = exp_neg_t(w1, T.etab);
     R.V[0] = fma(t.W * e0, horner<N>(cv0, w0), R.V[0]);
     R.V[1] = fma(t.W * e1, horner<N>(cv1, w1), R.V[1]);
     const double u0 = t.wrn * e0 * horner<N>(ck0, w0);
@@ -618,7 +622,10 @@ __global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict_
                                                     const double *__restrict__ taylor,
                                                     const int *__restrict__ tdeg) {
   const AsmParams &p = *pp;
-  const SepTabs T{nullptr, tscale, taylor, nullptr, tdeg};
+  __shared__ double etab[64];
+  stage_exp_tab(etab);
+  __syncthreads();
+  const SepTabs T{nullptr, tscale, taylor, nullptr, tdeg, etab};
   const TouchPair &tp = pairs[blockIdx.x];
   // the pair's class (3 identical, 2 edge, 1 vertex) picks its regularised rule
   const int cls = __builtin_amdgcn_readfirstlane(tp.cls);

@@ -529,7 +529,7 @@ __device__ __forceinline__ void repr_taylor(const AsmParams &p, const double *__
                                             const double *__restrict__ g, int k, int mlo, int mhi,
                                             int j, int v0, int v1, int v2, double area,
                                             const double (&r2)[kFarN], const double (&rn)[kFarN],
-                                            double &accs, double &accd) {
+                                            const double *etab, double &accs, double &accd) {
   const int ne = p.ne, nv = p.nv;
 #pragma unroll 1
   for (int m = mlo; m < mhi; ++m) {
@@ -548,7 +548,7 @@ __device__ __forceinline__ void repr_taylor(const AsmParams &p, const double *__
 #pragma unroll
       for (int q = 0; q < kFarN; ++q) {
         const double x = r2[q] * cm;
-        e[q] = exp_neg(x);
+        e[q] = exp_neg_t(x, etab);
         accs = fma(p.w7[q] * wi * e[q], horner<N>(c, x), accs);
       }
     }
@@ -566,7 +566,7 @@ __device__ __forceinline__ void repr_taylor(const AsmParams &p, const double *__
   }
 }
 
-__global__ __launch_bounds__(256) void k_repr(const AsmParams *__restrict__ pp,
+__global__ __launch_bounds__(256, 2) void k_repr(const AsmParams *__restrict__ pp,
                                               const double *__restrict__ qtab,
                                               const double *__restrict__ pts,
                                               const double *__restrict__ w,
@@ -584,6 +584,8 @@ __global__ __launch_bounds__(256) void k_repr(const AsmParams *__restrict__ pp,
   double eps = t - k * h;
   if (eps < 0.0) eps = 0.0;
   constexpr double kPi = 3.14159265358979323846;
+  __shared__ double etab[64];
+  stage_exp_tab(etab);
   // per-interval tables, one thread per m
   for (int m = kReprClosed + 1 + threadIdx.x; m <= k; m += blockDim.x) {
     double *T = tab + repr_off(m);
@@ -652,12 +654,12 @@ __global__ __launch_bounds__(256) void k_repr(const AsmParams *__restrict__ pp,
     }
     // Taylor form for m = 3 .. k, by degree class
     const int m0 = kReprClosed + 1;
-    repr_taylor<21>(p, tab, w, g, k, m0, min(k + 1, 4), j, v0, v1, v2, area, r2, rn, accs, accd);
-    repr_taylor<17>(p, tab, w, g, k, 4, min(k + 1, 6), j, v0, v1, v2, area, r2, rn, accs, accd);
-    repr_taylor<15>(p, tab, w, g, k, 6, min(k + 1, 8), j, v0, v1, v2, area, r2, rn, accs, accd);
-    repr_taylor<13>(p, tab, w, g, k, 8, min(k + 1, 16), j, v0, v1, v2, area, r2, rn, accs, accd);
-    repr_taylor<11>(p, tab, w, g, k, 16, min(k + 1, 32), j, v0, v1, v2, area, r2, rn, accs, accd);
-    repr_taylor<9>(p, tab, w, g, k, 32, k + 1, j, v0, v1, v2, area, r2, rn, accs, accd);
+    repr_taylor<21>(p, tab, w, g, k, m0, min(k + 1, 4), j, v0, v1, v2, area, r2, rn, etab, accs, accd);
+    repr_taylor<17>(p, tab, w, g, k, 4, min(k + 1, 6), j, v0, v1, v2, area, r2, rn, etab, accs, accd);
+    repr_taylor<15>(p, tab, w, g, k, 6, min(k + 1, 8), j, v0, v1, v2, area, r2, rn, etab, accs, accd);
+    repr_taylor<13>(p, tab, w, g, k, 8, min(k + 1, 16), j, v0, v1, v2, area, r2, rn, etab, accs, accd);
+    repr_taylor<11>(p, tab, w, g, k, 16, min(k + 1, 32), j, v0, v1, v2, area, r2, rn, etab, accs, accd);
+    repr_taylor<9>(p, tab, w, g, k, 32, k + 1, j, v0, v1, v2, area, r2, rn, etab, accs, accd);
   }
   __shared__ double red[2][4];
 #pragma unroll
