@@ -55,7 +55,7 @@ def project_p1p0(verts, tris, n_t, T, fn, q_space=8, q_time=8):
     """Coefficients (E_t, N_x) of the L2(Sigma_h) projection of fn(x (n,3), t (n,)) into X^{1,0}."""
     area, _ = geometry(verts, tris)
     lam, wq, x, times, wt = _space_time_nodes(verts, tris, n_t, T, q_space, q_time)
-    M = mass_p1p1(verts, tris)
+    Mc = scipy.linalg.cho_factor(mass_p1p1(verts, tris))  # one Cholesky factor for every step
     E, nq = x.shape[0], x.shape[1]
     out = np.empty((n_t, len(verts)))
     h = T / n_t
@@ -66,7 +66,7 @@ def project_p1p0(verts, tris, n_t, T, fn, q_space=8, q_time=8):
             g = fn(xf, np.full(len(xf), t)).reshape(E, nq)
             for k in range(3):
                 np.add.at(rhs, tris[:, k], wt[a] * area * (g * (wq * lam[:, k])[None, :]).sum(1))
-        out[i] = scipy.linalg.solve(M, rhs / h, assume_a="pos")
+        out[i] = scipy.linalg.cho_solve(Mc, rhs / h)
     return out
 
 
