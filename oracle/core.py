@@ -38,6 +38,7 @@ def lib():
         L.or_gauss_legendre01.argtypes = [i32, _dp, _dp]
         L.or_pair_points.argtypes = [_dp, _ip, i32, i32, i32, _dp, _dp, _dp, _dp,
                                      ctypes.POINTER(ctypes.c_int)]
+        L.or_assemble_d2.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, _dp]
         L.or_assemble.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, _ip, i32, i32, i32,
                                   _dp, _dp]
         L.or_repr.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, _dp, _dp, _dp, i32, i32, i32,
@@ -68,12 +69,13 @@ def temporal(which, rho, delta, alpha):
 
 
 def blockfun(which, rho, d, h, alpha, tmode=0):
-    """Exact per-point temporal block integrals: V^d(r) ('V') or K^d(r)/(r.n) ('K').
+    """Exact per-point temporal block integrals: V^d(r) ('V'), K^d(r)/(r.n) ('K') or the
+    hypersingular part D^{2,d}(r) ('D2', Sec. 3.3, closed form only).
     tmode 0: closed form for d <= 16, hat quadrature above; 1: closed form; 2: hat for d >= 2."""
     rho, d = np.broadcast_arrays(_f64(rho), np.asarray(d))
     rho, d = _f64(rho.ravel()), _i32(d.ravel())
     out = np.empty_like(rho)
-    lib().or_blockfun(0 if which == "V" else 1, rho, d, len(rho), float(h), float(alpha),
+    lib().or_blockfun({"V": 0, "K": 1, "D2": 2}[which], rho, d, len(rho), float(h), float(alpha),
                       int(tmode), out)
     return out
 
@@ -143,3 +145,17 @@ def repr_eval(verts, tris, alpha, T, n_t, w, u, pts, rule_kind=0, rule_order=7):
     if rc != 0:
         raise ValueError("or_repr failed")
     return sl, dl
+
+
+def assemble_d2(verts, tris, alpha, T, n_t, ss_order=4):
+    """Blocks D_h^{2,d} (n_t, N_x, N_x) of the hypersingular operator's second part (Sec. 3.3):
+    p1 x p1 with n(x) . n(y) and the kernel D^{2,d}, every ordered panel pair, the same rules as
+    for V and K."""
+    verts, tris = _f64(verts), _i32(tris)
+    ne, nv = len(tris), len(verts)
+    D2 = np.empty((n_t, nv, nv))
+    rc = lib().or_assemble_d2(verts.ravel(), nv, tris.ravel(), ne, float(alpha), float(T), n_t,
+                              ss_order, D2)
+    if rc != 0:
+        raise ValueError("or_assemble_d2 failed (%d)" % rc)
+    return D2

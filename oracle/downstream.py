@@ -7,6 +7,8 @@
 * time marching (block forward substitution with a Cholesky factor of V^0) and unrestarted
   GMRES with zero initial guess (the paper solves with FGMRES to relative accuracy 1e-8, Sec. 6.1)
 * relative L2(Sigma_h) errors and the relative l2 point error              (Sec. 6.1)
+* surface curls of the p1 basis, D_h^{1,d} = T^T (alpha^2 V^d (x) I_3) T,
+  D_h = D_h^1 + D_h^2 and the Neumann right-hand side (1/2 M_h^T - K_h^T) h  (Sec. 3.3, 3.4)
 
 Vectors are time-major: row i of an (E_t, n) array holds the coefficients of interval i+1.
 """
@@ -189,3 +191,52 @@ def block_rel_error(A, B):
     num = np.abs(A - B).reshape(A.shape[0], -1).max(1)
     den = np.abs(A).reshape(A.shape[0], -1).max(1)
     return num / np.where(den > 0, den, 1.0)
+
+
+def surface_curls(verts, tris):
+    """curl_Gamma of the three local p1 basis functions on each panel, (E, 3 local, 3 coords):
+    curl = n x grad_Gamma lambda_k = (x_{k+1} - x_{k+2}) / (2 area) (Sec. 2, surface curl)."""
+    v = verts[tris]                                   # (E, 3, 3)
+    area, _ = geometry(verts, tris)
+    out = np.empty_like(v)
+    for k in range(3):
+        out[:, k, :] = (v[:, (k + 1) % 3, :] - v[:, (k + 2) % 3, :]) / (2.0 * area[:, None])
+    return out
+
+
+def assemble_d1(V, verts, tris, alpha):
+    """D_h^{1,d} = T^T (alpha^2 V^d (x) I_3) T with T_o[m, j] the o-th component of the surface
+    curl of phi^1_j on panel m (Sec. 3.3, eq. for D_h^{1,d})."""
+    curls = surface_curls(verts, tris)
+    ne, nv = len(tris), len(verts)
+    D1 = np.zeros((V.shape[0], nv, nv))
+    for o in range(3):
+        To = np.zeros((ne, nv))
+        for k in range(3):
+            np.add.at(To, (np.arange(ne), tris[:, k]), curls[:, k, o])
+        for d in range(V.shape[0]):
+            D1[d] += alpha * alpha * (To.T @ V[d] @ To)
+    return D1
+
+
+def rhs_neumann(K, Mx, psi, h):
+    """(1/2 M_h^T - K_h^T) psi with the blockwise transposes (Sec. 3.4, the Neumann system; the
+    remark on K_T'): M_h = h blockdiag(M_x), K^T = the blocks K^d transposed one by one."""
+    return 0.5 * h * (psi @ Mx) - toeplitz_apply(np.ascontiguousarray(K.transpose(0, 2, 1)), psi)
+
+
+def l2_error_p1p0(verts, tris, n_t, T, coeffs, fn, q_space=8, q_time=8):
+    """Relative L2(Sigma_h) error of the p1 (space) x p0 (time) function `coeffs` (E_t, N_x)
+    against fn(x, t)."""
+    area, _ = geometry(verts, tris)
+    lam, wq, x, times, wt = _space_time_nodes(verts, tris, n_t, T, q_space, q_time)
+    E, nq = x.shape[0], x.shape[1]
+    num = den = 0.0
+    for i in range(n_t):
+        uh = np.einsum("qk,ek->eq", lam, coeffs[i][tris])
+        for a, t in enumerate(times[i]):
+            g = fn(x.reshape(-1, 3), np.full(E * nq, t)).reshape(E, nq)
+            e = g - uh
+            num += wt[a] * np.sum(area[:, None] * wq[None, :] * e * e)
+            den += wt[a] * np.sum(area[:, None] * wq[None, :] * g * g)
+    return float(np.sqrt(num / den))

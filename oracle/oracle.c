@@ -21,6 +21,8 @@
  *   - the paper's assembly order: loop over delta = i_t h, evaluate
  *     once, scatter to blocks i_t-1, i_t, i_t+1                     (Sec. 5.1, Tables 5.1/5.2, Sec. 5.2)
  *   - single- and double-layer potentials (representation formula) (Sec. 3.5)
+ *   - the second part D^{2,d}(r) of the hypersingular operator and its Galerkin blocks
+ *     (p1 x p1 with n(x) . n(y))                                     (Sec. 3.3, eq. for D^{2,d})
  *
  * Readings where the paper is silent (each is also listed in the design notes):
  *   - Small-argument series for the double-layer bracket (it cancels like 1/z^2 when
@@ -211,6 +213,25 @@ ld or_Kd_rn(ld rho, int d, ld h, ld alpha, int mode) {
          or_Fn_rn(rho, (d - 1) * h, alpha);
 }
 
+/* D^{2,d}(r) of Sec. 3.3 (second part of the hypersingular operator, eq. for D^{2,d}):
+ *   d = 0:  alpha int_0^h G(r, t) dt = erfc(z_1) / (4 pi rho),
+ *   d >= 1: alpha [int_{dh}^{(d+1)h} G(r, s) ds - int_{(d-1)h}^{dh} G(r, s) ds]
+ *         = [erfc(z_{d+1}) - 2 erfc(z_d) + erfc(z_{d-1})] / (4 pi rho),   erfc(z_0) = 0,
+ * with z_i = rho / (2 sqrt(alpha i h)): the second difference of -alpha G^{dt} = alpha G^{dtau},
+ * using int_0^delta G(r, s) ds = erfc(z) / (4 pi alpha rho).  Where all arguments are below 1 the
+ * same difference is taken of -erf (erf(z_0) = 1), since the erfc values then sit near 1. */
+ld or_D2d(ld rho, int d, ld h, ld alpha) {
+  const ld c = 1.0L / (4.0L * PI_L * rho);
+  if (d == 0) return erfcl(rho / (2.0L * sqrtl(alpha * h))) * c;
+  const ld zp = rho / (2.0L * sqrtl(alpha * (d + 1) * h)), z0 = rho / (2.0L * sqrtl(alpha * d * h));
+  if (d >= 2) {
+    const ld zm = rho / (2.0L * sqrtl(alpha * (d - 1) * h));
+    if (zm < 1.0L) return -(erfl(zp) - 2.0L * erfl(z0) + erfl(zm)) * c;
+    return (erfcl(zp) - 2.0L * erfcl(z0) + erfcl(zm)) * c;
+  }
+  return (erfcl(zp) - 2.0L * erfcl(z0)) * c;
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Spatial quadrature (Sec. 3.1 "Galerkin weights", Sec. 5.2).                                 */
 /* Reference triangle T = {(x1, x2): 0 <= x2 <= x1 <= 1}, mapped by                             */
@@ -392,7 +413,7 @@ static int classify(const int32_t *ta, const int32_t *tb, int pa[3], int pb[3]) 
  * physical measure ds_x ds_y carried by the point), and the trial p1 basis values phi[k] for the
  * trial panel's ORIGINAL local vertex k.  Returns the count.  cap bounds the arrays. */
 typedef struct {
-  ld x[3], y[3], W, phi[3];
+  ld x[3], y[3], W, phi[3], phix[3]; /* phix: test p1 basis values, test panel's own vertex order */
 } qpt_t;
 
 static ld *g_ss_x[4], *g_ss_y[4], *g_ss_w[4];
@@ -452,6 +473,7 @@ static int pair_points(const double *verts, const int32_t *tris, int a, int b, q
         }
         q[n].W = g_w7[i] * g_w7[j] * A.area * B.area;
         for (int k = 0; k < 3; ++k) q[n].phi[k] = g_r7[j][k];
+        for (int k = 0; k < 3; ++k) q[n].phix[k] = g_r7[i][k];
         ++n;
       }
     return n;
@@ -465,6 +487,8 @@ static int pair_points(const double *verts, const int32_t *tris, int a, int b, q
     /* barycentric coordinates of the trial point w.r.t. the permuted vertices pb[0..2] */
     ld lam[3] = {1.0L - yh1, yh1 - yh2, yh2};
     for (int k = 0; k < 3; ++k) q[n].phi[pb[k]] = lam[k];
+    ld lax[3] = {1.0L - xh1, xh1 - xh2, xh2};
+    for (int k = 0; k < 3; ++k) q[n].phix[pa[k]] = lax[k];
     ++n;
   }
   return n;
@@ -622,6 +646,59 @@ int or_assemble(const double *verts, int nv, const int32_t *tris, int ne, double
 }
 
 /* ------------------------------------------------------------------------------------------ */
+/* Galerkin blocks of the second part of the hypersingular operator (Sec. 3.3):                */
+/*   D2^d[i][j] = int int n(x) . n(y) phi^1_i(x) phi^1_j(y) D^{2,d}(x - y) ds_y ds_x,           */
+/* every ordered panel pair with the same rules as V and K.  D2 out: [n_t][n_verts][n_verts].    */
+/* ------------------------------------------------------------------------------------------ */
+int or_assemble_d2(const double *verts, int nv, const int32_t *tris, int ne, double alpha,
+                   double T, int nt, int ss_order, double *D2) {
+  if (nt < 1 || ne < 1 || nv < 3 || alpha <= 0 || T <= 0) return -1;
+  prepare_rules(ss_order);
+  ld h = (ld)T / (ld)nt, al = (ld)alpha;
+  ld *DL = (ld *)calloc((size_t)nt * nv * nv, sizeof(ld));
+#pragma omp parallel
+  {
+    qpt_t *q = (qpt_t *)malloc(sizeof(qpt_t) * max_points(ss_order));
+    ld *acc = (ld *)malloc(sizeof(ld) * 9 * nt);
+    ld *rows = (ld *)malloc(sizeof(ld) * 3 * nt * (size_t)nv); /* the test panel's three rows */
+    tri_t A, B;
+#pragma omp for schedule(dynamic)
+    for (int a = 0; a < ne; ++a) {
+      make_tri(verts, tris + 3 * a, &A);
+      for (size_t i = 0; i < 3 * (size_t)nt * nv; ++i) rows[i] = 0.0L;
+      for (int b = 0; b < ne; ++b) {
+        make_tri(verts, tris + 3 * b, &B);
+        const ld nn = A.n[0] * B.n[0] + A.n[1] * B.n[1] + A.n[2] * B.n[2];
+        int n = pair_points(verts, tris, a, b, q);
+        for (int i = 0; i < 9 * nt; ++i) acc[i] = 0.0L;
+        for (int i = 0; i < n; ++i) {
+          ld r[3] = {q[i].x[0] - q[i].y[0], q[i].x[1] - q[i].y[1], q[i].x[2] - q[i].y[2]};
+          ld rho = sqrtl(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+          for (int d = 0; d < nt; ++d) {
+            ld v = q[i].W * or_D2d(rho, d, h, al);
+            for (int k = 0; k < 3; ++k)
+              for (int l = 0; l < 3; ++l) acc[9 * d + 3 * k + l] += v * q[i].phix[k] * q[i].phi[l];
+          }
+        }
+        for (int d = 0; d < nt; ++d)
+          for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l)
+              rows[((size_t)k * nt + d) * nv + tris[3 * b + l]] += nn * acc[9 * d + 3 * k + l];
+      }
+#pragma omp critical(oracle_d2_rows)
+      for (int k = 0; k < 3; ++k)
+        for (int d = 0; d < nt; ++d)
+          for (int j = 0; j < nv; ++j)
+            DL[((size_t)d * nv + tris[3 * a + k]) * nv + j] += rows[((size_t)k * nt + d) * nv + j];
+    }
+    free(q); free(acc); free(rows);
+  }
+  for (size_t i = 0; i < (size_t)nt * nv * nv; ++i) D2[i] = (double)DL[i];
+  free(DL);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* Representation formula (Sec. 3.5): u(x, t) = (V~ w)(x, t) - (W u)(x, t) at points off Gamma. */
 /* w: [n_t][n_tris] (p0 x p0 coefficients), u: [n_t][n_verts] (p1 x p0 coefficients),           */
 /* pts: [P][4] = (x, y, z, t) with 0 <= t <= T.  The spatial rule is the same triangle rule as    */
@@ -711,7 +788,9 @@ void or_temporal(int which, const double *rho, const double *delta, int n, doubl
 void or_blockfun(int which, const double *rho, const int32_t *d, int n, double h, double alpha,
                  int tmode, double *out) {
   for (int i = 0; i < n; ++i) {
-    ld v = which == 0 ? or_Vd(rho[i], d[i], h, alpha, tmode) : or_Kd_rn(rho[i], d[i], h, alpha, tmode);
+    ld v = which == 0 ? or_Vd(rho[i], d[i], h, alpha, tmode)
+         : which == 1 ? or_Kd_rn(rho[i], d[i], h, alpha, tmode)
+                      : or_D2d(rho[i], d[i], h, alpha);
     out[i] = (double)v;
   }
 }
