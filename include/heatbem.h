@@ -45,6 +45,9 @@ extern "C" {
 /* ---- operators (bit flags for hb_assemble) ---- */
 #define HB_OP_V 1u /* single-layer operator V_h, Sec. 3.1 */
 #define HB_OP_K 2u /* double-layer operator K_h, Sec. 3.2 */
+#define HB_OP_D 4u /* hypersingular operator D_h = D_h^1 + D_h^2, Sec. 3.3 (p1 x p1, N_x x N_x) */
+#define HB_OP_KT 8u /* hb_apply only: K_h^T, the blocks of K_h transposed one by one (Sec. 3.2 remark
+                      on K_T'), x: E_t x E_x, y: E_t x N_x */
 
 /* ---- assembly precision ---- */
 #define HB_PREC_FP64 0  /* every quadrature point in double precision */
@@ -104,25 +107,32 @@ const char *hb_last_error(const hb_ctx *ctx);
 int hb_sizes(const hb_ctx *ctx, int64_t *n_tris, int64_t *n_verts, int32_t *n_t,
              int64_t *n_touching);
 
-/* Assemble all E_t blocks of the operators in `ops` (HB_OP_V | HB_OP_K) on the device
+/* Assemble all E_t blocks of the operators in `ops` (HB_OP_V | HB_OP_K | HB_OP_D) on the device
  * (Sec. 3.1 eq. for V_h^d, Sec. 3.2 eq. for K_h^d; assembly order Sec. 5).  Each entry is the
  * spatial quadrature over a triangle pair of the exact temporal integral: Radon's 7-point rule
  * on each triangle for separated pairs, Sauter-Schwab [0,1]^4 rules of order opt.ss_order for
  * pairs sharing a vertex, an edge or the whole triangle.  precision: HB_PREC_FP64 or
  * HB_PREC_MIXED.  Block storage is allocated on first use and reused; the double layer also
  * keeps a workspace of the size of K (its separated-pair contributions of the transposed order,
- * folded into K at the end of the call). */
+ * folded into K at the end of the call).
+ * HB_OP_D (Sec. 3.3): D_h^d = D_h^{1,d} + D_h^{2,d}, N_x x N_x blocks in the storage type.
+ * D_h^{1,d} = T^T (alpha^2 V_h^d (x) I_3) T is formed from the assembled V_h and the surface
+ * curls of the p1 basis (so V_h must be assembled before or in the same call, else HB_ESTATE);
+ * D_h^{2,d} = int int n(x).n(y) phi_i phi_j D^{2,d} with the same rules as V_h, in double whatever
+ * the precision argument.  D keeps a workspace of its own size. */
 int hb_assemble(hb_ctx *ctx, uint32_t ops, int32_t precision, void *stream);
 
-/* Copy blocks d0 .. d0 + nd - 1 of op (HB_OP_V or HB_OP_K) into dst (layout [nd][rows][cols]
+/* Copy blocks d0 .. d0 + nd - 1 of op (HB_OP_V, HB_OP_K or HB_OP_D) into dst (layout [nd][rows][cols]
  * as the block storage), converting to dtype (HB_DTYPE_F64 / HB_DTYPE_F32).  dst is a device
  * pointer if dst_on_device != 0, else a host pointer (the copy is then synchronous). */
 int hb_get_blocks(hb_ctx *ctx, uint32_t op, int32_t d0, int32_t nd, void *dst, int32_t dtype,
                   int32_t dst_on_device, void *stream);
 
 /* Block lower-triangular Toeplitz product y^k = sum_{d=0}^{k} A^d x^{k-d} (Sec. 3.1 eq. for
- * V_h w; Sec. 3.2 eq. for K_h) for op = HB_OP_V (x: E_t x E_x) or HB_OP_K (x: E_t x N_x);
- * y: E_t x E_x.  x, y: device pointers, float64, time-major, not overlapping.  Supports
+ * V_h w; Sec. 3.2 eq. for K_h; Sec. 3.3) for op = HB_OP_V (x: E_t x E_x) or HB_OP_K (x: E_t x N_x),
+ * y: E_t x E_x; op = HB_OP_D (x, y: E_t x N_x); op = HB_OP_KT (x: E_t x E_x, y: E_t x N_x; the
+ * transposed blocks are formed once per assembly of K in a buffer of the size of K).
+ * x, y: device pointers, float64, time-major, not overlapping.  Supports
  * E_t <= 256 (HB_EINVAL beyond); float block storage multiplies in float (x rounded to float) with
  * the partial sums added in double. */
 int hb_apply(hb_ctx *ctx, uint32_t op, const double *x, double *y, void *stream);
@@ -131,6 +141,11 @@ int hb_apply(hb_ctx *ctx, uint32_t op, const double *x, double *y, void *stream)
  * M_h = h blockdiag(M_x), M_x[l, j] = int phi^0_l phi^1_j.  g: device, E_t x N_x (coefficients
  * of Dirichlet data in the p1-space / p0-time space); b: device, E_t x E_x. */
 int hb_rhs_dirichlet(hb_ctx *ctx, const double *g, double *b, void *stream);
+
+/* Right-hand side of the Neumann system b = (1/2 M_h^T - K_h^T) psi (Sec. 3.4, the hypersingular
+ * equation with the blockwise transposes).  psi: device, E_t x E_x (coefficients of the Neumann
+ * datum alpha du/dn in the p0-space / p0-time space); b: device, E_t x N_x.  Needs K_h. */
+int hb_rhs_neumann(hb_ctx *ctx, const double *psi, double *b, void *stream);
 
 /* Solvers for V_h w = b (Sec. 3.4). */
 #define HB_SOLVE_GMRES 0      /* unrestarted GMRES in double on the block system */
@@ -162,6 +177,13 @@ typedef struct hb_solve_info {
  * methods use the block-Toeplitz product, so E_t <= 256. */
 int hb_solve(hb_ctx *ctx, const double *b, double *w, const hb_solve_opts *opts,
              hb_solve_info *info, void *stream);
+
+/* Solve the Neumann system D_h u = b for u (Sec. 3.4) by unrestarted GMRES in double on the block
+ * system (the paper uses FGMRES).  b, u: device pointers, E_t x N_x, float64.  opts: method must
+ * be HB_SOLVE_GMRES and precond 0 (HB_EINVAL otherwise); tol and max_iter as for hb_solve.  Needs
+ * HB_OP_D assembled (HB_ESTATE).  info->rel_residual is ||b - D_h u|| / ||b||. */
+int hb_solve_neumann(hb_ctx *ctx, const double *b, double *u, const hb_solve_opts *opts,
+                     hb_solve_info *info, void *stream);
 
 /* Representation formula u = V~ w - W g (Sec. 2, potentials of Sec. 3.5) at P space-time points
  * pts[P][4] = (x, y, z, t), 0 <= t <= T, off Gamma_h (not checked; accuracy near Gamma_h is

@@ -13,14 +13,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libheatbem.so")
 
 HB_OK, HB_EINVAL, HB_EMESH, HB_EORIENT, HB_ENOMEM, HB_EHIP, HB_ENOCONV, HB_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
-HB_OP_V, HB_OP_K = 1, 2
+HB_OP_V, HB_OP_K, HB_OP_D, HB_OP_KT = 1, 2, 4, 8
 HB_PREC_FP64, HB_PREC_MIXED = 0, 1
 HB_DTYPE_F64, HB_DTYPE_F32 = 0, 1
 HB_SOLVE_GMRES, HB_SOLVE_TIMEMARCH, HB_SOLVE_MIXED_IR = 0, 1, 2
 
 EXPORTED = sorted(["hb_default_options", "hb_check_mesh", "hb_create", "hb_destroy",
                    "hb_last_error", "hb_sizes", "hb_assemble", "hb_get_blocks", "hb_apply",
-                   "hb_rhs_dirichlet", "hb_solve", "hb_eval_repr", "hb_last_assembly_ms",
+                   "hb_rhs_dirichlet", "hb_rhs_neumann", "hb_solve", "hb_solve_neumann",
+                   "hb_eval_repr", "hb_last_assembly_ms",
                    "hb_precond_pattern", "hb_precond_features", "hb_precond_spai",
                    "hb_precond_set", "hb_mlp_num_params", "hb_mlp_work_floats", "hb_mlp_forward",
                    "hb_mlp_backward", "hb_precond_loss", "hb_adam_step"])
@@ -82,6 +83,8 @@ def lib():
     L.hb_apply.argtypes = [vp, ctypes.c_uint32, vp, vp, vp]
     L.hb_rhs_dirichlet.argtypes = [vp, vp, vp, vp]
     L.hb_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
+    L.hb_rhs_neumann.argtypes = [vp, vp, vp, vp]
+    L.hb_solve_neumann.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     L.hb_eval_repr.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
     L.hb_last_assembly_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.hb_precond_pattern.argtypes = [vp, vp, vp, vp]
@@ -194,24 +197,27 @@ class Context:
         return list(ms)
 
     def blocks(self, op, d0=0, nd=None, dtype=None, device=True, stream=None):
-        """Blocks d0 .. d0+nd-1 of op as a (nd, E_x, cols) tensor (device) or ndarray (host)."""
+        """Blocks d0 .. d0+nd-1 of op as a (nd, rows, cols) tensor (device) or ndarray (host):
+        rows E_x (V, K) or N_x (D), cols E_x (V) or N_x (K, D)."""
         import torch
         nd = self.n_t - d0 if nd is None else nd
+        rows = self.n_verts if op == HB_OP_D else self.n_tris
         cols = self.n_tris if op == HB_OP_V else self.n_verts
         if dtype is None:
             dtype = HB_DTYPE_F32 if self.storage == HB_DTYPE_F32 else HB_DTYPE_F64
         if device:
-            out = torch.empty((nd, self.n_tris, cols), dtype=torch.float64 if dtype == HB_DTYPE_F64 else torch.float32, device="cuda")
+            out = torch.empty((nd, rows, cols), dtype=torch.float64 if dtype == HB_DTYPE_F64 else torch.float32, device="cuda")
             self._check(lib().hb_get_blocks(self._h, op, d0, nd, _ptr(out), dtype, 1, _stream(stream)))
             return out
-        out = np.empty((nd, self.n_tris, cols), dtype=np.float64 if dtype == HB_DTYPE_F64 else np.float32)
+        out = np.empty((nd, rows, cols), dtype=np.float64 if dtype == HB_DTYPE_F64 else np.float32)
         self._check(lib().hb_get_blocks(self._h, op, d0, nd, ctypes.c_void_p(out.ctypes.data), dtype, 0, _stream(stream)))
         return out
 
     def apply(self, op, x, y=None, stream=None):
         import torch
         if y is None:
-            y = torch.empty((self.n_t, self.n_tris), dtype=torch.float64, device="cuda")
+            rows = self.n_verts if op in (HB_OP_D, HB_OP_KT) else self.n_tris
+            y = torch.empty((self.n_t, rows), dtype=torch.float64, device="cuda")
         self._check(lib().hb_apply(self._h, op, _ptr(x), _ptr(y), _stream(stream)))
         return y
 
@@ -221,6 +227,29 @@ class Context:
             b = torch.empty((self.n_t, self.n_tris), dtype=torch.float64, device="cuda")
         self._check(lib().hb_rhs_dirichlet(self._h, _ptr(g), _ptr(b), _stream(stream)))
         return b
+
+    def rhs_neumann(self, psi, b=None, stream=None):
+        """b = (1/2 M_h^T - K_h^T) psi; psi: (E_t, E_x), b: (E_t, N_x)."""
+        import torch
+        if b is None:
+            b = torch.empty((self.n_t, self.n_verts), dtype=torch.float64, device="cuda")
+        self._check(lib().hb_rhs_neumann(self._h, _ptr(psi), _ptr(b), _stream(stream)))
+        return b
+
+    def solve_neumann(self, b, tol=1e-8, max_iter=500, u=None, stream=None):
+        """D_h u = b by GMRES; b, u: (E_t, N_x)."""
+        import torch
+        if u is None:
+            u = torch.empty((self.n_t, self.n_verts), dtype=torch.float64, device="cuda")
+        o = SolveOpts()
+        o.method, o.tol, o.max_iter, o.precond = HB_SOLVE_GMRES, tol, max_iter, 0
+        info = SolveInfo()
+        rc = lib().hb_solve_neumann(self._h, _ptr(b), _ptr(u), ctypes.byref(o), ctypes.byref(info),
+                                    _stream(stream))
+        if rc not in (HB_OK, HB_ENOCONV):
+            self._check(rc)
+        return u, {"iterations": info.iterations, "rel_residual": info.rel_residual,
+                   "seconds": info.seconds, "converged": rc == HB_OK}
 
     def solve(self, b, method=HB_SOLVE_GMRES, tol=1e-8, max_iter=500, w=None, precond=False,
               stream=None):

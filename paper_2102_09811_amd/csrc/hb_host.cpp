@@ -180,6 +180,7 @@ void count_classes(const int32_t *T, int64_t nv, int64_t ne, int64_t counts[4],
           hb::TouchPair p{};
           p.l = (int32_t)l; p.m = m; p.cls = ns;
           for (int j = 0; j < 3; ++j) p.vtx[j] = tm[pm[j]];
+          for (int j = 0; j < 3; ++j) p.vtxl[j] = tl[pl[j]];
           for (int cc = 0; cc < 3; ++cc) {
             p.E1[cc] = V[3 * tl[pl[1]] + cc] - V[3 * tl[pl[0]] + cc];
             p.E2[cc] = V[3 * tl[pl[2]] + cc] - V[3 * tl[pl[1]] + cc];
@@ -237,8 +238,9 @@ void legendre01(int n, std::vector<ld> &x, std::vector<ld> &w) {
 // r = x - y in the edge vectors, so the kernel never subtracts two nearby points:
 //   r = c1 E1 + c2 E2 + c3 F1 + c4 F2,  E1 = a1-a0, E2 = a2-a1 (test), F1 = b1-b0, F2 = b2-b1.
 // Reference panel {0 <= s2 <= s1 <= 1}, chi(s) = v0 + s1 (v1-v0) + s2 (v2-v1).  Each entry holds
-// (c1, c2, c3, c4, weight * Jacobian, trial barycentrics (1-y1, y1-y2, y2)).
-struct SSNode { ld c[4], w, lam[3]; };
+// (c1, c2, c3, c4, weight * Jacobian, trial barycentrics (1-y1, y1-y2, y2), test barycentrics
+// (1-x1, x1-x2, x2)).
+struct SSNode { ld c[4], w, lam[3], lamx[3]; };
 
 void ss_nodes(int cls, int M, std::vector<SSNode> &out) {
   std::vector<ld> g, gw;
@@ -269,8 +271,7 @@ void ss_nodes(int cls, int M, std::vector<SSNode> &out) {
                 default: x1 = xi; x2 = xi * a * (1 - b); y1 = xi * (1 - a * b * e); y2 = xi * a * (1 - b * e);
                          d1 = xi * a * b * e; d2 = -xi * a * b * (1 - e); break;
               }
-              (void)x1; (void)x2;
-              out.push_back({{d1, d2, 0, 0}, wt * J, {1 - y1, y1 - y2, y2}});
+              out.push_back({{d1, d2, 0, 0}, wt * J, {1 - y1, y1 - y2, y2}, {1 - x1, x1 - x2, x2}});
             } else if (cls == 2) {
               J = xi * xi * xi * a * a * (s == 0 ? 1.0L : b);
               switch (s) {
@@ -286,12 +287,12 @@ void ss_nodes(int cls, int M, std::vector<SSNode> &out) {
                          d1 = -xi * a * b * e; break;
               }
               // shared edge: F1 == E1, so r = (x1 - y1) E1 + x2 E2 - y2 F2
-              out.push_back({{d1, x2, 0, -y2}, wt * J, {1 - y1, y1 - y2, y2}});
+              out.push_back({{d1, x2, 0, -y2}, wt * J, {1 - y1, y1 - y2, y2}, {1 - x1, x1 - x2, x2}});
             } else {
               J = xi * xi * xi * b;
               if (s == 0) { x1 = xi; x2 = xi * a; y1 = xi * b; y2 = xi * b * e; }
               else { x1 = xi * b; x2 = xi * b * e; y1 = xi; y2 = xi * a; }
-              out.push_back({{x1, x2, -y1, -y2}, wt * J, {1 - y1, y1 - y2, y2}});
+              out.push_back({{x1, x2, -y1, -y2}, wt * J, {1 - y1, y1 - y2, y2}, {1 - x1, x1 - x2, x2}});
             }
           }
 }
@@ -322,6 +323,34 @@ void taylor_poly(ld p, int d, ld out[hb::kTaylorN], int deg = hb::kTaylorDeg) {
     if (k > 0) fact *= (ld)(2 * k + 1) * (ld)(2 * k + 2);
     ld coef = 2.0L / fact * dpow;
     for (size_t j = 0; j < Q[2 * k].size(); ++j) out[j] += coef * Q[2 * k][j];
+    dpow /= (ld)d * (ld)d;
+  }
+}
+
+// Odd Taylor series of D^{2,d} (Sec. 3.3): alpha h int_{-1}^{1} sgn(u) G(r, (d+u) h) du
+//   = alpha h G(r, dh) sum_k 2 d^{-(2k+1)} Q_{2k+1}(w) / (2k+2)!  (Q_n as above, p = 3/2),
+// truncated at k = deg/2: a polynomial of degree deg + 1 in w.
+void taylor_poly_odd(int d, int deg, ld *out, int len) {
+  const int K = deg / 2;
+  const ld p = 1.5L;
+  std::vector<std::vector<ld>> Q(2 * K + 2);
+  Q[0] = {1.0L};
+  for (int n = 0; n < 2 * K + 1; ++n) {
+    const auto &q = Q[n];
+    std::vector<ld> r(q.size() + 1, 0.0L);
+    for (size_t j = 0; j < q.size(); ++j) {
+      r[j + 1] += q[j];
+      r[j] -= (n + p) * q[j];
+      r[j] -= (ld)j * q[j];
+    }
+    Q[n + 1] = r;
+  }
+  for (int j = 0; j < len; ++j) out[j] = 0;
+  ld fact = 2.0L, dpow = 1.0L / (ld)d;  // (2k+2)!, d^{-(2k+1)}
+  for (int k = 0; k <= K; ++k) {
+    if (k > 0) fact *= (ld)(2 * k + 1) * (ld)(2 * k + 2);
+    const ld coef = 2.0L / fact * dpow;
+    for (size_t j = 0; j < Q[2 * k + 1].size() && (int)j < len; ++j) out[j] += coef * Q[2 * k + 1][j];
     dpow /= (ld)d * (ld)d;
   }
 }
@@ -420,6 +449,7 @@ int build_tables(hb_ctx *c) {
   if ((rc = upload(c, (void **)&c->d_taylor32, tay32.data(), tay32.size() * sizeof(float)))) return rc;
   if ((rc = upload(c, (void **)&c->d_tdeg, tdeg.data(), tdeg.size() * sizeof(int32_t)))) return rc;
 
+
   // geometry SoA: far-rule nodes, normal, area
   size_t ne = (size_t)c->ne;
   std::vector<double> geom(25 * ne);
@@ -455,6 +485,8 @@ int build_tables(hb_ctx *c) {
   for (auto &tp : c->touch) {
     for (int k = 0; k < 3; ++k) tp.n[k] = c->normal[3 * tp.m + k];
     tp.scale = 4.0 * c->area[tp.l] * c->area[tp.m];
+    tp.nn = 0.0;
+    for (int k = 0; k < 3; ++k) tp.nn += c->normal[3 * tp.l + k] * c->normal[3 * tp.m + k];
   }
   if (!c->touch.empty())
     if ((rc = upload(c, (void **)&c->d_touch, c->touch.data(), c->touch.size() * sizeof(TouchPair))))
@@ -500,17 +532,59 @@ int build_tables(hb_ctx *c) {
     if ((rc = upload(c, (void **)&c->d_pc_cls, clsv.data(), clsv.size()))) return rc;
     if ((rc = upload(c, (void **)&c->d_cent, cent.data(), cent.size() * sizeof(double)))) return rc;
   }
+  // hypersingular operator: odd Taylor tables of D^{2,d} (d >= kD2Closed), their scales, the
+  // surface curls of the local p1 basis and the vertex -> (panel, local index) lists
+  {
+    auto d2deg = [](int d) { return d < 12 ? 14 : d < 16 ? 12 : d < 32 ? 10 : d < 64 ? 8 : 6; };
+    std::vector<double> d2tab((size_t)c->nt * kTaylorND, 0.0), d2sc(c->nt, 0.0);
+    std::vector<int32_t> d2len(c->nt, 0);
+    for (int d = kD2Closed; d < c->nt; ++d) {
+      ld poly[kTaylorND];
+      const int deg = d2deg(d);
+      d2len[d] = deg + 2;
+      taylor_poly_odd(d, deg, poly, kTaylorND);
+      for (int j = 0; j < kTaylorND; ++j) d2tab[(size_t)d * kTaylorND + j] = (double)poly[j];
+      d2sc[d] = (double)(al * h * powl(4.0L * kPi * al * d * h, -1.5L));
+    }
+    if ((rc = upload(c, (void **)&c->d_d2tab, d2tab.data(), d2tab.size() * sizeof(double)))) return rc;
+    if ((rc = upload(c, (void **)&c->d_d2scale, d2sc.data(), d2sc.size() * sizeof(double)))) return rc;
+    if ((rc = upload(c, (void **)&c->d_d2len, d2len.data(), d2len.size() * sizeof(int32_t)))) return rc;
+    const size_t ne_ = c->ne;
+    std::vector<double> curl(9 * ne_);
+    for (size_t t = 0; t < ne_; ++t) {
+      const double *x[3] = {&c->verts[3 * c->tris[3 * t]], &c->verts[3 * c->tris[3 * t + 1]],
+                            &c->verts[3 * c->tris[3 * t + 2]]};
+      for (int k = 0; k < 3; ++k)  // curl of lambda_k = n x grad lambda_k = (x_{k+1} - x_{k+2}) / (2 area)
+        for (int q = 0; q < 3; ++q)
+          curl[9 * t + 3 * k + q] = (x[(k + 1) % 3][q] - x[(k + 2) % 3][q]) / (2.0 * c->area[t]);
+    }
+    if ((rc = upload(c, (void **)&c->d_curl, curl.data(), curl.size() * sizeof(double)))) return rc;
+    Adjacency A = vertex_triangles(c->tris.data(), c->nv, c->ne);
+    std::vector<int32_t> vstart(c->nv + 1), vadj(6 * ne_);
+    for (int64_t i = 0; i <= c->nv; ++i) vstart[i] = (int32_t)A.start[i];
+    for (int64_t i = 0; i < c->nv; ++i)
+      for (int64_t e = A.start[i]; e < A.start[i + 1]; ++e) {
+        const int32_t t = A.tri[e];
+        int k = 0;
+        while (c->tris[3 * t + k] != (int32_t)i) ++k;
+        vadj[2 * e] = t;
+        vadj[2 * e + 1] = k;
+      }
+    if ((rc = upload(c, (void **)&c->d_vstart, vstart.data(), vstart.size() * sizeof(int32_t)))) return rc;
+    if ((rc = upload(c, (void **)&c->d_vadj, vadj.data(), vadj.size() * sizeof(int32_t)))) return rc;
+  }
   // regularised rules
   for (int cls = 1; cls <= 3; ++cls) {
     std::vector<SSNode> nodes;
     ss_nodes(cls, c->opt.ss_order, nodes);
     int n = (int)nodes.size(), np = (n + 63) / 64 * 64;
-    std::vector<double> tab(8 * (size_t)np, 0.0);
+    std::vector<double> tab(11 * (size_t)np, 0.0);
     for (int i = 0; i < np; ++i) {
       bool real = i < n;
       for (int k = 0; k < 4; ++k) tab[(size_t)k * np + i] = real ? (double)nodes[i].c[k] : (k == 0 ? 1.0 : 0.0);
       tab[(size_t)4 * np + i] = real ? (double)nodes[i].w : 0.0;
       for (int k = 0; k < 3; ++k) tab[(size_t)(5 + k) * np + i] = real ? (double)nodes[i].lam[k] : 0.0;
+      for (int k = 0; k < 3; ++k) tab[(size_t)(8 + k) * np + i] = real ? (double)nodes[i].lamx[k] : 0.0;
     }
     c->ss[cls].n = np;
     if ((rc = upload(c, (void **)&c->ss[cls].d, tab.data(), tab.size() * sizeof(double)))) return rc;
@@ -607,7 +681,9 @@ void hb_destroy(hb_ctx *c) {
   void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_sep_tasks, c->d_taylor,
                   c->d_taylor32, c->d_tdeg, c->d_V32, c->d_tscale, c->d_mass,
                   c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
-                  c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d};
+                  c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d,
+                  c->d_D, c->d_Dw, c->d_Kt, c->d_d2tab, c->d_d2scale, c->d_d2len, c->d_curl, c->d_vstart,
+                  c->d_vadj};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int i = 0; i < 4; ++i)
@@ -627,11 +703,35 @@ int hb_sizes(const hb_ctx *c, int64_t *ne, int64_t *nv, int32_t *nt, int64_t *nt
   return HB_OK;
 }
 
+// D_h (Sec. 3.3) from the assembled V_h; the kernels read the parameters of the last assembly.
+static int assemble_d(hb_ctx *c, hipStream_t s) {
+  const size_t nD = (size_t)c->nt * c->nv * c->nv, esz = c->storage_f32 ? 4 : 8;
+  if (!c->d_D) {
+    HB_HIP(c, hipMalloc(&c->d_D, nD * esz + hb::kBlockPad));
+    HB_HIP(c, hipMemsetAsync((char *)c->d_D + nD * esz, 0, hb::kBlockPad, s));
+  }
+  if (!c->d_Dw) HB_HIP(c, hipMalloc(&c->d_Dw, nD * esz));
+  if (!c->d_params) {
+    c->launch = c->params;
+    c->launch.V = c->d_V;
+    HB_HIP(c, hipMalloc(&c->d_params, sizeof(hb::AsmParams)));
+    HB_HIP(c, hipMemcpyAsync(c->d_params, &c->launch, sizeof(c->launch), hipMemcpyHostToDevice, s));
+  }
+  int rc = hb::launch_assemble_d(c, s);
+  if (rc) return fail(c, rc, "hypersingular assembly launch failed");
+  c->have_D = true;
+  return HB_OK;
+}
+
 int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
   if (!c) return fail(nullptr, HB_EINVAL, "null context");
-  if (ops == 0 || (ops & ~(HB_OP_V | HB_OP_K))) return fail(c, HB_EINVAL, "ops must be a non-empty subset of HB_OP_V | HB_OP_K");
+  if (ops == 0 || (ops & ~(HB_OP_V | HB_OP_K | HB_OP_D)))
+    return fail(c, HB_EINVAL, "ops must be a non-empty subset of HB_OP_V | HB_OP_K | HB_OP_D");
   if (precision != HB_PREC_FP64 && precision != HB_PREC_MIXED) return fail(c, HB_EINVAL, "unknown precision");
+  if ((ops & HB_OP_D) && !(ops & HB_OP_V) && !c->have_V)
+    return fail(c, HB_ESTATE, "HB_OP_D needs V (assembled before or in the same call)");
   hipStream_t s = (hipStream_t)stream;
+  if (!(ops & (HB_OP_V | HB_OP_K))) return assemble_d(c, s);
   size_t esz = c->storage_f32 ? 4 : 8;
   size_t nV = (size_t)c->nt * c->ne * c->ne, nK = (size_t)c->nt * c->ne * c->nv;
   if ((ops & HB_OP_V) && !c->d_V) {
@@ -681,8 +781,12 @@ int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
     c->v0inv_valid = false;
     c->pc_active = false;  // M was scaled by the previous V^0
   }
-  if (p.do_K) c->have_K = true;
+  if (p.do_K) {
+    c->have_K = true;
+    c->Kt_valid = false;
+  }
   c->timed = true;
+  if (ops & HB_OP_D) return assemble_d(c, s);
   return HB_OK;
 }
 
@@ -703,15 +807,18 @@ int hb_last_assembly_ms(hb_ctx *c, double ms[3]) {
 int hb_get_blocks(hb_ctx *c, uint32_t op, int32_t d0, int32_t nd, void *dst, int32_t dtype,
                   int32_t dst_on_device, void *stream) {
   if (!c || !dst) return fail(c, HB_EINVAL, "null argument");
-  if (op != HB_OP_V && op != HB_OP_K) return fail(c, HB_EINVAL, "op must be HB_OP_V or HB_OP_K");
+  if (op != HB_OP_V && op != HB_OP_K && op != HB_OP_D)
+    return fail(c, HB_EINVAL, "op must be HB_OP_V, HB_OP_K or HB_OP_D");
   if (d0 < 0 || nd < 0 || d0 + nd > c->nt) return fail(c, HB_EINVAL, "block range out of bounds");
   if (dtype != HB_DTYPE_F64 && dtype != HB_DTYPE_F32) return fail(c, HB_EINVAL, "bad dtype");
-  bool have = op == HB_OP_V ? c->have_V : c->have_K;
+  bool have = op == HB_OP_V ? c->have_V : op == HB_OP_K ? c->have_K : c->have_D;
   if (!have) return fail(c, HB_ESTATE, "operator not assembled");
+  const size_t rows = op == HB_OP_D ? (size_t)c->nv : (size_t)c->ne;
   size_t cols = op == HB_OP_V ? (size_t)c->ne : (size_t)c->nv;
-  size_t per = (size_t)c->ne * cols, n = per * nd;
+  size_t per = rows * cols, n = per * nd;
   size_t esz = c->storage_f32 ? 4 : 8;
-  const char *src = (const char *)(op == HB_OP_V ? c->d_V : c->d_K) + (size_t)d0 * per * esz;
+  const void *base = op == HB_OP_V ? c->d_V : op == HB_OP_K ? c->d_K : c->d_D;
+  const char *src = (const char *)base + (size_t)d0 * per * esz;
   hipStream_t s = (hipStream_t)stream;
   bool same = (dtype == HB_DTYPE_F32) == (c->storage_f32 != 0);
   if (same) {

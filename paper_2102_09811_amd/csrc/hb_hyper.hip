@@ -1,0 +1,327 @@
+// Hypersingular operator of the heat equation (Sec. 3.3): D_h^d = D_h^{1,d} + D_h^{2,d}, and the
+// blockwise transpose used for K_h^T in the Neumann system (Sec. 3.4).
+//
+// D^{2,d}(r), the kernel of the second part (Sec. 3.3, eq. for D^{2,d}), with z_i = rho / (2 sqrt(
+// alpha i h)) and int_0^delta G(r, s) ds = erfc(z) / (4 pi alpha rho):
+//   d = 0:  alpha int_0^h G = erfc(z_1) / (4 pi rho);
+//   d >= 1: alpha [int_{dh}^{(d+1)h} G - int_{(d-1)h}^{dh} G]
+//         = [erfc(z_{d+1}) - 2 erfc(z_d) + erfc(z_{d-1})] / (4 pi rho),  erfc(z_0) = 0,
+//     taken as minus the same difference of erf when z_{d-1} < 1 (the erfc values then sit near 1);
+//   d >= kD2Closed: the same integral as alpha h int_{-1}^{1} sgn(u) G(r, (d+u) h) du, expanded in
+//     u around dh.  Only odd derivatives survive: with f(s) = s^{-3/2} e^{-a/s},
+//     f^{(n)}(s) = s^{-3/2-n} e^{-w} Q_n(w) (w = rho^2 / (4 alpha d h)), so
+//     D^{2,d} = alpha h G(r, dh) sum_k 2 d^{-(2k+1)} Q_{2k+1}(w) / (2k+2)!,
+//     a polynomial in w tabulated on the host; no cancelling differences remain.
+// Blocks (Sec. 3.3, Galerkin matrix D_h^2): p1 test x p1 trial with n(x) . n(y), the same rules as
+// V_h.  Separated pairs: one wave per test panel l and 64 trial panels m > l (the unordered pair
+// once), Radon's rule on both panels, contributions added to the workspace row block of l; then
+// D^2 = W + W^T.  Touching pairs: one wave per ordered pair, the regularised rule of its class.
+// D_h^{1,d} = T^T (alpha^2 V^d (x) I_3) T (Sec. 3.3, eq. for D_h^{1,d}) is added entry by entry
+// from V_h^d and the surface curls of the local p1 basis.
+#include "hb_device.h"
+#include "hb_internal.h"
+
+namespace hb {
+namespace {
+
+constexpr double kInv4Pi = 0.079577471545947667884;
+
+__device__ __forceinline__ double d2_closed(double rho, int d, double ah) {
+  const double c = kInv4Pi / rho;
+  const double zp = 0.5 * rho / sqrt(ah * (d + 1));
+  if (d == 0) return erfc(zp) * c;
+  const double z0 = 0.5 * rho / sqrt(ah * d);
+  if (d == 1) return (erfc(zp) - 2.0 * erfc(z0)) * c;
+  const double zm = 0.5 * rho / sqrt(ah * (d - 1));
+  if (zm < 1.0) return -(erf(zp) - 2.0 * erf(z0) + erf(zm)) * c;
+  return (erfc(zp) - 2.0 * erfc(z0) + erfc(zm)) * c;
+}
+
+// Value of D^{2,d} at rho^2 (N = 0: closed form; else the Taylor polynomial with N coefficients).
+template <int N>
+__device__ __forceinline__ double d2_value(double rho2, int d, double ah, double cw, double sc,
+                                           const double *__restrict__ tab, const double *etab) {
+  if constexpr (N == 0) {
+    return d2_closed(sqrt(rho2), d, ah);
+  } else {
+    const double w = rho2 * cw;
+    return sc * exp_neg_t(w, etab) * horner<N>(tab, w);
+  }
+}
+
+// One block d of a separated pair: S[a][b] = sum over the 7 x 7 point pairs of the weights, the
+// kernel and the test / trial barycentrics.
+template <int N>
+__device__ __forceinline__ void d2_sep_block(const AsmParams &p, int l, int m, int d, double ah,
+                                             const double *__restrict__ d2tab,
+                                             const double *__restrict__ d2scale,
+                                             const double *__restrict__ tscale,
+                                             const double *etab, double S[3][3]) {
+  const int ne = p.ne;
+  const double cw = N ? tscale[3 * d + 2] : 0.0, sc = N ? d2scale[d] : 0.0;
+  const double *tab = d2tab + (size_t)d * kTaylorND;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) S[i][j] = 0.0;
+#pragma unroll 1
+  for (int a = 0; a < kFarN; ++a) {
+    const double x0 = p.geom[(a * 3 + 0) * ne + l], x1 = p.geom[(a * 3 + 1) * ne + l],
+                 x2 = p.geom[(a * 3 + 2) * ne + l];
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll 1
+    for (int b = 0; b < kFarN; ++b) {
+      const double rx = x0 - p.geom[(b * 3 + 0) * ne + m];
+      const double ry = x1 - p.geom[(b * 3 + 1) * ne + m];
+      const double rz = x2 - p.geom[(b * 3 + 2) * ne + m];
+      const double v = p.w7[b] * d2_value<N>(fma(rx, rx, fma(ry, ry, rz * rz)), d, ah, cw, sc, tab, etab);
+      t0 = fma(v, p.lam7[b][0], t0);
+      t1 = fma(v, p.lam7[b][1], t1);
+      t2 = fma(v, p.lam7[b][2], t2);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double wa = p.w7[a] * p.lam7[a][i];
+      S[i][0] = fma(wa, t0, S[i][0]);
+      S[i][1] = fma(wa, t1, S[i][1]);
+      S[i][2] = fma(wa, t2, S[i][2]);
+    }
+  }
+}
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_d2_separated(const AsmParams *__restrict__ pp,
+                                                      const double *__restrict__ tscale,
+                                                      const double *__restrict__ d2tab,
+                                                      const double *__restrict__ d2scale,
+                                                      const int32_t *__restrict__ d2len,
+                                                      const int32_t *__restrict__ tasks,
+                                                      int ntasks, TS *__restrict__ Dw) {
+  const AsmParams &p = *pp;
+  __shared__ double etab[64];
+  stage_exp_tab(etab);
+  __syncthreads();
+  const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (task >= ntasks) return;
+  const int l = __builtin_amdgcn_readfirstlane(tasks[2 * task]);
+  const int m = __builtin_amdgcn_readfirstlane(tasks[2 * task + 1]) + (threadIdx.x & 63);
+  const int ne = p.ne, nv = p.nv;
+  if (m >= ne) return;
+  const int vl[3] = {p.tris[3 * l], p.tris[3 * l + 1], p.tris[3 * l + 2]};
+  const int vm[3] = {p.tris[3 * m], p.tris[3 * m + 1], p.tris[3 * m + 2]};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (vl[i] == vm[j]) return;  // touching: handled by the regularised rules
+  const double nn = p.geom[21 * ne + l] * p.geom[21 * ne + m] +
+                    p.geom[22 * ne + l] * p.geom[22 * ne + m] +
+                    p.geom[23 * ne + l] * p.geom[23 * ne + m];
+  const double scale = nn * p.geom[24 * ne + l] * p.geom[24 * ne + m];
+  const double ah = p.alpha * p.h;
+  for (int d = 0; d < p.nt; ++d) {
+    double S[3][3];
+    if (d < kD2Closed) {
+      d2_sep_block<0>(p, l, m, d, ah, d2tab, d2scale, tscale, etab, S);
+    } else {
+      switch (d2len[d]) {
+        case 16: d2_sep_block<16>(p, l, m, d, ah, d2tab, d2scale, tscale, etab, S); break;
+        case 14: d2_sep_block<14>(p, l, m, d, ah, d2tab, d2scale, tscale, etab, S); break;
+        case 12: d2_sep_block<12>(p, l, m, d, ah, d2tab, d2scale, tscale, etab, S); break;
+        case 10: d2_sep_block<10>(p, l, m, d, ah, d2tab, d2scale, tscale, etab, S); break;
+        default: d2_sep_block<8>(p, l, m, d, ah, d2tab, d2scale, tscale, etab, S); break;
+      }
+    }
+    TS *Db = Dw + (size_t)d * nv * nv;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) atomicAdd(&Db[(size_t)vl[i] * nv + vm[j]], (TS)(scale * S[i][j]));
+  }
+}
+
+// D[d] = W[d] + W[d]^T, 64 x 64 tiles through LDS
+template <typename TS>
+__global__ __launch_bounds__(256) void k_sym_blocks(const TS *__restrict__ W, TS *__restrict__ D, int n) {
+  __shared__ TS tile[64][65];
+  const size_t off = (size_t)blockIdx.z * n * n;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  // tile of W^T: rows j0.., columns i0.. of W
+  for (int r = ty; r < 64; r += 4) {
+    const int row = j0 + r, col = i0 + tx;
+    tile[r][tx] = (row < n && col < n) ? W[off + (size_t)row * n + col] : TS(0);
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int row = i0 + r, col = j0 + tx;
+    if (row < n && col < n) D[off + (size_t)row * n + col] = W[off + (size_t)row * n + col] + tile[tx][r];
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void d2_touch_block(const TouchPair &tp, const double *__restrict__ tab,
+                                               int ntab, int lane, int d, double ah, double cw,
+                                               double sc, const double *__restrict__ poly,
+                                               const double *etab, double S[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) S[k] = 0.0;
+#pragma unroll 1
+  for (int q = lane; q < ntab; q += 64) {
+    const double a1 = tab[q], a2 = tab[ntab + q], a3 = tab[2 * ntab + q], a4 = tab[3 * ntab + q];
+    const double rx = a1 * tp.E1[0] + a2 * tp.E2[0] + a3 * tp.F1[0] + a4 * tp.F2[0];
+    const double ry = a1 * tp.E1[1] + a2 * tp.E2[1] + a3 * tp.F1[1] + a4 * tp.F2[1];
+    const double rz = a1 * tp.E1[2] + a2 * tp.E2[2] + a3 * tp.F1[2] + a4 * tp.F2[2];
+    const double v = tab[4 * ntab + q] *
+                     d2_value<N>(fma(rx, rx, fma(ry, ry, rz * rz)), d, ah, cw, sc, poly, etab);
+    const double ly0 = tab[5 * ntab + q], ly1 = tab[6 * ntab + q], ly2 = tab[7 * ntab + q];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double u = v * tab[(8 + i) * ntab + q];
+      S[3 * i + 0] = fma(u, ly0, S[3 * i + 0]);
+      S[3 * i + 1] = fma(u, ly1, S[3 * i + 1]);
+      S[3 * i + 2] = fma(u, ly2, S[3 * i + 2]);
+    }
+  }
+}
+
+template <typename TS>
+__global__ __launch_bounds__(64) void k_d2_touching(const AsmParams *__restrict__ pp,
+                                                    const TouchPair *__restrict__ pairs,
+                                                    RuleTabs rules,
+                                                    const double *__restrict__ tscale,
+                                                    const double *__restrict__ d2tab,
+                                                    const double *__restrict__ d2scale,
+                                                    const int32_t *__restrict__ d2len,
+                                                    TS *__restrict__ D) {
+  const AsmParams &p = *pp;
+  __shared__ double etab[64];
+  stage_exp_tab(etab);
+  __syncthreads();
+  const TouchPair &tp = pairs[blockIdx.x];
+  const int cls = __builtin_amdgcn_readfirstlane(tp.cls);
+  const double *__restrict__ tab = rules.d[cls];
+  const int ntab = rules.n[cls];
+  const int lane = threadIdx.x, nv = p.nv;
+  const double ah = p.alpha * p.h, f = tp.scale * tp.nn;
+  for (int d = 0; d < p.nt; ++d) {
+    double S[9];
+    const double cw = tscale[3 * d + 2], sc = d2scale[d];
+    const double *poly = d2tab + (size_t)d * kTaylorND;
+    if (d < kD2Closed) {
+      d2_touch_block<0>(tp, tab, ntab, lane, d, ah, 0.0, 0.0, poly, etab, S);
+    } else {
+      switch (d2len[d]) {
+        case 16: d2_touch_block<16>(tp, tab, ntab, lane, d, ah, cw, sc, poly, etab, S); break;
+        case 14: d2_touch_block<14>(tp, tab, ntab, lane, d, ah, cw, sc, poly, etab, S); break;
+        case 12: d2_touch_block<12>(tp, tab, ntab, lane, d, ah, cw, sc, poly, etab, S); break;
+        case 10: d2_touch_block<10>(tp, tab, ntab, lane, d, ah, cw, sc, poly, etab, S); break;
+        default: d2_touch_block<8>(tp, tab, ntab, lane, d, ah, cw, sc, poly, etab, S); break;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) S[k] += __shfl_xor(S[k], o, 64);
+    if (lane < 9) {
+      double v = S[0];
+#pragma unroll
+      for (int k = 1; k < 9; ++k)
+        if (lane == k) v = S[k];
+      atomicAdd(&D[((size_t)d * nv + tp.vtxl[lane / 3]) * nv + tp.vtx[lane % 3]], (TS)(f * v));
+    }
+  }
+}
+
+// D[d][i][j] += alpha^2 sum_{(n, a) at i} sum_{(m, b) at j} curl_a(n) . curl_b(m) V[d][n][m]
+template <typename TS>
+__global__ __launch_bounds__(256) void k_d1(const TS *__restrict__ V, TS *__restrict__ D,
+                                            const double *__restrict__ curl,
+                                            const int32_t *__restrict__ vstart,
+                                            const int32_t *__restrict__ vadj, int ne, int nv,
+                                            double a2) {
+  const int j = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y, d = blockIdx.z;
+  if (j >= nv) return;
+  const TS *Vd = V + (size_t)d * ne * ne;
+  const int j0 = vstart[j], j1 = vstart[j + 1];
+  double acc = 0.0;
+  for (int s = vstart[i]; s < vstart[i + 1]; ++s) {
+    const int n = vadj[2 * s], a = vadj[2 * s + 1];
+    const double c0 = curl[9 * n + 3 * a], c1 = curl[9 * n + 3 * a + 1], c2 = curl[9 * n + 3 * a + 2];
+    const TS *row = Vd + (size_t)n * ne;
+    for (int t = j0; t < j1; ++t) {
+      const int m = vadj[2 * t], b = vadj[2 * t + 1];
+      const double dot = c0 * curl[9 * m + 3 * b] + c1 * curl[9 * m + 3 * b + 1] + c2 * curl[9 * m + 3 * b + 2];
+      acc = fma(dot, (double)row[m], acc);
+    }
+  }
+  TS *out = D + ((size_t)d * nv + i) * nv + j;
+  *out = (TS)((double)*out + a2 * acc);
+}
+
+// dst[d] = src[d]^T for blocks [nt][R][C], 64 x 64 tiles through LDS
+template <typename TS>
+__global__ __launch_bounds__(256) void k_transpose_blocks(const TS *__restrict__ src,
+                                                          TS *__restrict__ dst, int R, int C) {
+  __shared__ TS tile[64][65];
+  const size_t off = (size_t)blockIdx.z * R * C;
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int row = r0 + r, col = c0 + tx;
+    if (row < R && col < C) tile[r][tx] = src[off + (size_t)row * C + col];
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int row = c0 + r, col = r0 + tx;  // dst is C x R
+    if (row < C && col < R) dst[off + (size_t)row * R + col] = tile[tx][r];
+  }
+}
+
+template <typename TS>
+int assemble_d_typed(hb_ctx *c, hipStream_t s) {
+  const int nt = c->nt, ne = (int)c->ne, nv = (int)c->nv;
+  const size_t nD = (size_t)nt * nv * nv;
+  TS *D = (TS *)c->d_D, *W = (TS *)c->d_Dw;
+  if (hipMemsetAsync(W, 0, nD * sizeof(TS), s) != hipSuccess) return HB_EHIP;
+  if (c->n_sep_tasks > 0)
+    hipLaunchKernelGGL((k_d2_separated<TS>), dim3((unsigned)((c->n_sep_tasks + 3) / 4)), dim3(256),
+                       0, s, c->d_params, c->d_tscale, c->d_d2tab, c->d_d2scale, c->d_d2len,
+                       c->d_sep_tasks, (int)c->n_sep_tasks, W);
+  const dim3 tiles((nv + 63) / 64, (nv + 63) / 64, nt);
+  hipLaunchKernelGGL((k_sym_blocks<TS>), tiles, dim3(256), 0, s, W, D, nv);
+  if (!c->touch.empty()) {
+    RuleTabs rt{};
+    for (int k = 1; k <= 3; ++k) {
+      rt.d[k] = c->ss[k].d;
+      rt.n[k] = c->ss[k].n;
+    }
+    hipLaunchKernelGGL((k_d2_touching<TS>), dim3((unsigned)c->touch.size()), dim3(64), 0, s,
+                       c->d_params, c->d_touch, rt, c->d_tscale, c->d_d2tab, c->d_d2scale,
+                       c->d_d2len, D);
+  }
+  hipLaunchKernelGGL((k_d1<TS>), dim3((nv + 255) / 256, nv, nt), dim3(256), 0, s,
+                     (const TS *)c->d_V, D, c->d_curl, c->d_vstart, c->d_vadj, ne, nv,
+                     c->alpha * c->alpha);
+  return hipGetLastError() == hipSuccess ? HB_OK : HB_EHIP;
+}
+
+template <typename TS>
+void transpose_typed(const void *src, void *dst, int R, int C, int nt, hipStream_t s) {
+  hipLaunchKernelGGL((k_transpose_blocks<TS>), dim3((C + 63) / 64, (R + 63) / 64, nt), dim3(256),
+                     0, s, (const TS *)src, (TS *)dst, R, C);
+}
+
+}  // namespace
+
+int launch_assemble_d(hb_ctx *c, hipStream_t s) {
+  return c->storage_f32 ? assemble_d_typed<float>(c, s) : assemble_d_typed<double>(c, s);
+}
+
+int launch_transpose_blocks(hb_ctx *c, const void *src, void *dst, int R, int C, hipStream_t s) {
+  if (c->storage_f32) transpose_typed<float>(src, dst, R, C, c->nt, s);
+  else transpose_typed<double>(src, dst, R, C, c->nt, s);
+  return hipGetLastError() == hipSuccess ? HB_OK : HB_EHIP;
+}
+
+}  // namespace hb

@@ -71,12 +71,15 @@ struct TouchPair {
   double F1[3], F2[3];         // trial panel edges
   double n[3];                 // trial outward unit normal
   double scale;                // 4 * area_l * area_m
+  int32_t vtxl[3], pad2;       // test vertices in the rule's order (hypersingular p1 x p1 blocks)
+  double nn;                   // n_l . n_m
 };
 
 // Regularised rule of one class, SoA, padded to a multiple of 64 with zero weights.
 struct SSRule {
   int32_t n = 0;               // padded count
-  double *d = nullptr;         // device: [8][n] = c1, c2, c3, c4, w, lam0, lam1, lam2
+  double *d = nullptr;         // device: [11][n] = c1, c2, c3, c4, w, lam0, lam1, lam2 (trial),
+                               // lamx0, lamx1, lamx2 (test barycentrics, rule order)
 };
 
 // The three classes' rule tables as one kernel argument (index = shared vertices, 1..3).
@@ -92,6 +95,14 @@ void launch_fold_KT(const AsmParams &p, int storage_f32, hipStream_t s);
 void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,
                               int64_t npairs, const SSRule rules[4], int storage_f32,
                               hipStream_t s);
+
+// Hypersingular operator (Sec. 3.3): D_h^d = D_h^{1,d} + D_h^{2,d} into c->d_D (needs V_h);
+// Taylor form of D^{2,d} from block kD2Closed on, closed form below.
+constexpr int kD2Closed = 8;
+constexpr int kTaylorND = 16;        // coefficients of the odd Taylor polynomial of D^{2,d}, d >= 8
+int launch_assemble_d(hb_ctx *c, hipStream_t s);
+// blockwise transpose [nt][R][C] -> [nt][C][R]
+int launch_transpose_blocks(hb_ctx *c, const void *src, void *dst, int R, int C, hipStream_t s);
 
 // y = A x for the block-Toeplitz operator with blocks [nt][R][C] (y overwritten, time-major)
 int toeplitz_apply(hb_ctx *c, const void *blocks, int R, int C, const double *x, double *y,
@@ -131,6 +142,17 @@ struct hb_ctx {
   double *d_mass = nullptr;          // p0 x p1 mass, [ne][3] = area/3 per local vertex
   void *d_V = nullptr, *d_K = nullptr, *d_KT = nullptr;
   bool have_V = false, have_K = false;
+  // hypersingular operator: blocks [nt][nv][nv], workspace of the separated pairs' half, tables
+  void *d_D = nullptr, *d_Dw = nullptr;
+  bool have_D = false;
+  void *d_Kt = nullptr;              // K^d transposed block by block (K_h^T of the Neumann system)
+  bool Kt_valid = false;
+  double *d_d2tab = nullptr;         // [nt][kTaylorND]: odd Taylor polynomial of D^{2,d}
+  double *d_d2scale = nullptr;       // [nt]: alpha h (4 pi alpha d h)^{-3/2}
+  int32_t *d_d2len = nullptr;        // [nt]: coefficients used at block d (0 below kD2Closed)
+  double *d_curl = nullptr;          // [ne][3][3]: surface curls of the local p1 basis
+  int32_t *d_vstart = nullptr;       // [nv+1] CSR vertex -> (panel, local index)
+  int32_t *d_vadj = nullptr;         // [3 ne][2]
   int storage_f32 = 0;
   hb::AsmParams params{};            // tables filled at creation
   hb::AsmParams launch{};            // per-call copy (outputs, ops), source of d_params

@@ -230,6 +230,21 @@ __global__ void k_mass_half(const double *__restrict__ mass, const int32_t *__re
   }
 }
 
+// Neumann right-hand side: on entry b = K_h^T psi; b[k][i] <- half_h sum over the panels l at
+// vertex i of (area_l / 3) psi[k][l] - b[k][i], i.e. b = 1/2 M_h^T psi - K_h^T psi.
+__global__ void k_mass_half_T(const double *__restrict__ mass, const int32_t *__restrict__ vstart,
+                              const int32_t *__restrict__ vadj, const double *__restrict__ psi,
+                              double *__restrict__ b, int nt, int ne, int nv, double half_h) {
+  const size_t n = (size_t)nt * nv;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i / nv), v = (int)(i % nv);
+    const double *pk = psi + (size_t)k * ne;
+    double acc = 0.0;
+    for (int e = vstart[v]; e < vstart[v + 1]; ++e) acc = fma(mass[3 * vadj[2 * e] + vadj[2 * e + 1]], pk[vadj[2 * e]], acc);
+    b[i] = half_h * acc - b[i];
+  }
+}
+
 // ---- inverse of V^0 by blocked Gauss-Jordan elimination (no pivoting), in place ----
 // Panel p of kGJB columns / rows (R = C = [p0, p0 + b)): with Ainv = A[R, C]^{-1},
 //   A[R, :]      <- Ainv A[R, :]                 (Ainv in the pivot columns)
@@ -845,9 +860,11 @@ int ctx_fail(hb_ctx *c, int code, const std::string &m) {
 
 // Workspace layout for the solvers (doubles):
 //   GMRES: Q[(m+1) n] | r[n] | partial[(m+1) * nchunk] | dres[m+1] | coef[m+1]
-// V_h x with the double blocks (op 0) or with the float copy on the float MFMA path (op 1)
+// V_h x with the double blocks (op 0) or with the float copy on the float MFMA path (op 1);
+// op 2: D_h x (the Neumann system)
 int apply_V(hb_ctx *c, int op, const double *x, double *y, hipStream_t s) {
   if (op == 0) return toeplitz_apply(c, c->d_V, (int)c->ne, (int)c->ne, x, y, s);
+  if (op == 2) return toeplitz_apply(c, c->d_D, (int)c->nv, (int)c->nv, x, y, s);
   const float *V32 = c->storage_f32 ? (const float *)c->d_V : c->d_V32;
   return toeplitz_apply32(c, V32, (int)c->ne, (int)c->ne, x, y, s);
 }
@@ -872,7 +889,7 @@ int ensure_V32(hb_ctx *c, hipStream_t s) {
 // never waits for the host (a converged solve computes one surplus step, which is discarded).
 int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, hipStream_t s,
           hb_solve_info *info, bool precond = false) {
-  const size_t n = (size_t)c->nt * c->ne;
+  const size_t n = (size_t)c->nt * (op == 2 ? c->nv : c->ne);
   const int m = maxit;
   const int nchunk = (int)((n + kDotChunk - 1) / kDotChunk);
   const int nblk = grid1d(n);
@@ -1075,12 +1092,13 @@ int mixed_ir(hb_ctx *c, const double *b, double *x, double tol, int maxit, hipSt
   return conv ? HB_OK : HB_ENOCONV;
 }
 
-double rel_residual(hb_ctx *c, const double *b, const double *w, hipStream_t s, int *rc) {
-  const size_t n = (size_t)c->nt * c->ne;
+double rel_residual(hb_ctx *c, const double *b, const double *w, hipStream_t s, int *rc,
+                    int op = 0) {
+  const size_t n = (size_t)c->nt * (op == 2 ? c->nv : c->ne);
   *rc = ensure_work(c, sizeof(double) * (2 * n + 64 + (n / kDotChunk + 2)));
   if (*rc) return -1;
   double *r = c->d_work + n, *partial = r + n, *dres = partial + (n / kDotChunk + 2);
-  if ((*rc = toeplitz_apply(c, c->d_V, (int)c->ne, (int)c->ne, w, r, s))) return -1;
+  if ((*rc = apply_V(c, op == 2 ? 2 : 0, w, r, s))) return -1;
   hipLaunchKernelGGL(k_axpby, dim3(grid1d(n)), dim3(256), 0, s, 1.0, b, -1.0, r, n);
   double rr, bb;
   if ((*rc = multi_dot(c, r, 0, 1, r, n, partial, dres, &rr, s))) return -1;
@@ -1092,13 +1110,88 @@ double rel_residual(hb_ctx *c, const double *b, const double *w, hipStream_t s, 
 
 extern "C" {
 
+// K_h^T: the transposed blocks are formed once per assembly of K
+static int ensure_Kt(hb_ctx *c, hipStream_t s) {
+  if (c->Kt_valid) return HB_OK;
+  const size_t bytes = (size_t)c->nt * c->ne * c->nv * (c->storage_f32 ? 4 : 8);
+  if (!c->d_Kt) {
+    HB_CHECK(c, hipMalloc(&c->d_Kt, bytes + kBlockPad));
+    HB_CHECK(c, hipMemsetAsync((char *)c->d_Kt + bytes, 0, kBlockPad, s));
+  }
+  int rc = launch_transpose_blocks(c, c->d_K, c->d_Kt, (int)c->ne, (int)c->nv, s);
+  if (rc) return ctx_fail(c, rc, "block transpose launch failed");
+  c->Kt_valid = true;
+  return HB_OK;
+}
+
 int hb_apply(hb_ctx *c, uint32_t op, const double *x, double *y, void *stream) {
   if (!c) return HB_EINVAL;
   if (!x || !y) return ctx_fail(c, HB_EINVAL, "null vector");
-  if (op != HB_OP_V && op != HB_OP_K) return ctx_fail(c, HB_EINVAL, "op must be HB_OP_V or HB_OP_K");
+  hipStream_t s = (hipStream_t)stream;
+  if (op == HB_OP_D) {
+    if (!c->have_D) return ctx_fail(c, HB_ESTATE, "operator not assembled");
+    return toeplitz_apply(c, c->d_D, (int)c->nv, (int)c->nv, x, y, s);
+  }
+  if (op == HB_OP_KT) {
+    if (!c->have_K) return ctx_fail(c, HB_ESTATE, "operator not assembled");
+    int rc = ensure_Kt(c, s);
+    if (rc) return rc;
+    return toeplitz_apply(c, c->d_Kt, (int)c->nv, (int)c->ne, x, y, s);
+  }
+  if (op != HB_OP_V && op != HB_OP_K)
+    return ctx_fail(c, HB_EINVAL, "op must be HB_OP_V, HB_OP_K, HB_OP_D or HB_OP_KT");
   if (op == HB_OP_V ? !c->have_V : !c->have_K) return ctx_fail(c, HB_ESTATE, "operator not assembled");
   return toeplitz_apply(c, op == HB_OP_V ? c->d_V : c->d_K, (int)c->ne,
-                        (int)(op == HB_OP_V ? c->ne : c->nv), x, y, (hipStream_t)stream);
+                        (int)(op == HB_OP_V ? c->ne : c->nv), x, y, s);
+}
+
+int hb_rhs_neumann(hb_ctx *c, const double *psi, double *b, void *stream) {
+  if (!c) return HB_EINVAL;
+  if (!psi || !b) return ctx_fail(c, HB_EINVAL, "null vector");
+  if (!c->have_K) return ctx_fail(c, HB_ESTATE, "K not assembled");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = ensure_Kt(c, s);
+  if (rc) return rc;
+  if ((rc = toeplitz_apply(c, c->d_Kt, (int)c->nv, (int)c->ne, psi, b, s))) return rc;
+  const size_t n = (size_t)c->nt * c->nv;
+  hipLaunchKernelGGL(k_mass_half_T, dim3(grid1d(n)), dim3(256), 0, s, c->d_mass, c->d_vstart,
+                     c->d_vadj, psi, b, c->nt, (int)c->ne, (int)c->nv, 0.5 * c->h);
+  HB_CHECK(c, hipGetLastError());
+  return HB_OK;
+}
+
+int hb_solve_neumann(hb_ctx *c, const double *b, double *u, const hb_solve_opts *opts,
+                     hb_solve_info *info, void *stream) {
+  if (!c) return HB_EINVAL;
+  if (!b || !u) return ctx_fail(c, HB_EINVAL, "null vector");
+  if (!c->have_D) return ctx_fail(c, HB_ESTATE, "D not assembled");
+  hb_solve_opts o{};
+  o.method = HB_SOLVE_GMRES;
+  o.max_iter = 500;
+  o.tol = 1e-8;
+  if (opts) {
+    o = *opts;
+    if (o.max_iter <= 0) o.max_iter = 500;
+    if (!(o.tol > 0)) o.tol = 1e-8;
+  }
+  if (o.method != HB_SOLVE_GMRES || o.precond)
+    return ctx_fail(c, HB_EINVAL, "the Neumann system is solved by plain GMRES only");
+  if (o.max_iter > 5000) return ctx_fail(c, HB_EINVAL, "max_iter must be <= 5000");
+  hipStream_t s = (hipStream_t)stream;
+  hb_solve_info inf{};
+  HB_CHECK(c, hipStreamSynchronize(s));
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = gmres(c, 2, b, u, o.tol, o.max_iter, s, &inf, false);
+  if (rc != HB_OK && rc != HB_ENOCONV) return rc;
+  HB_CHECK(c, hipStreamSynchronize(s));
+  auto t1 = std::chrono::steady_clock::now();
+  int rc2 = HB_OK;
+  inf.rel_residual = rel_residual(c, b, u, s, &rc2, 2);
+  if (rc2) return rc2;
+  inf.seconds = std::chrono::duration<double>(t1 - t0).count();
+  if (info) *info = inf;
+  if (rc == HB_ENOCONV) c->err = "GMRES reached max_iter before the tolerance";
+  return rc;
 }
 
 int hb_rhs_dirichlet(hb_ctx *c, const double *g, double *b, void *stream) {
