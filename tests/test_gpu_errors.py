@@ -88,3 +88,34 @@ def test_time_limits(torch):
         ctx.eval_repr(pts, x, g)
     assert e.value.code == HB_EINVAL
     ctx.close()
+
+
+def test_neumann_call_order_and_arguments(torch):
+    from paper_2102_09811_amd import (HB_EINVAL, HB_ESTATE, HB_OP_D, HB_OP_K, HB_OP_KT, HB_OP_V,
+                                      HB_SOLVE_TIMEMARCH, Context, HBError)
+    v, t = tetrahedron()
+    ctx = Context(v, t, 1.0, 1.0, 4)
+    psi = torch.zeros((4, len(t)), dtype=torch.float64, device="cuda")
+    b = torch.zeros((4, len(v)), dtype=torch.float64, device="cuda")
+    for call in (lambda: ctx.rhs_neumann(psi), lambda: ctx.solve_neumann(b),
+                 lambda: ctx.apply(HB_OP_D, b), lambda: ctx.apply(HB_OP_KT, psi),
+                 lambda: ctx.assemble(HB_OP_D)):
+        with pytest.raises(HBError) as e:
+            call()
+        assert e.value.code == HB_ESTATE
+    with pytest.raises(HBError) as e:
+        ctx.assemble(16)
+    assert e.value.code == HB_EINVAL
+    ctx.assemble(HB_OP_V | HB_OP_K | HB_OP_D)
+    from paper_2102_09811_amd import binding
+    import ctypes
+    o = binding.SolveOpts()
+    o.method, o.tol, o.max_iter = HB_SOLVE_TIMEMARCH, 1e-8, 10
+    info = binding.SolveInfo()
+    u = torch.zeros_like(b)
+    rc = binding.lib().hb_solve_neumann(ctx._h, binding._ptr(b + 1.0), binding._ptr(u), ctypes.byref(o),
+                                        ctypes.byref(info), None)
+    assert rc == HB_EINVAL
+    u, info = ctx.solve_neumann(b)       # zero right-hand side: zero solution, no iterations
+    assert info["converged"] and float(u.abs().max()) == 0.0
+    ctx.close()

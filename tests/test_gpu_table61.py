@@ -75,7 +75,8 @@ def test_table61_dirichlet_convergence():
         say("  GPU: assembly %.3f s, rhs + GMRES %.3f s (%d iterations, residual %.1e), "
             "potentials %.3f s; errors on the host" % (t1 - t0, t2 - t1, info["iterations"],
                                                       info["rel_residual"], t3 - t2))
-        assert info["converged"] and info["rel_residual"] <= 1e-8
+        # GMRES stops on its estimate; the recomputed residual may exceed 1e-8 by rounding
+        assert info["converged"] and info["rel_residual"] <= 2e-8
         e_w = ds.l2_error_p0(v, t, nt, T, w, flux)
         wp = ds.project_p0p0(v, t, nt, T, flux)
         e_p = ds.l2_error_p0(v, t, nt, T, wp, flux)
