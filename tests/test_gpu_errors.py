@@ -26,7 +26,7 @@ def test_call_order_and_arguments(torch):
     with pytest.raises(HBError) as e:
         ctx.solve(x)
     assert e.value.code == HB_ESTATE
-    for ops in (0, 4):
+    for ops in (0, 16, 32):
         with pytest.raises(HBError) as e:
             ctx.assemble(ops)
         assert e.value.code == HB_EINVAL
