@@ -48,6 +48,8 @@ extern "C" {
 #define HB_OP_D 4u /* hypersingular operator D_h = D_h^1 + D_h^2, Sec. 3.3 (p1 x p1, N_x x N_x) */
 #define HB_OP_KT 8u /* hb_apply only: K_h^T, the blocks of K_h transposed one by one (Sec. 3.2 remark
                       on K_T'), x: E_t x E_x, y: E_t x N_x */
+#define HB_OP_V11 16u /* single layer between p1 functions, V_h^{11} (N_x x N_x), the matrix of the
+                         paper's preconditioner for D_h (Sec. 6.1) */
 
 /* ---- assembly precision ---- */
 #define HB_PREC_FP64 0  /* every quadrature point in double precision */
@@ -107,7 +109,8 @@ const char *hb_last_error(const hb_ctx *ctx);
 int hb_sizes(const hb_ctx *ctx, int64_t *n_tris, int64_t *n_verts, int32_t *n_t,
              int64_t *n_touching);
 
-/* Assemble all E_t blocks of the operators in `ops` (HB_OP_V | HB_OP_K | HB_OP_D) on the device
+/* Assemble all E_t blocks of the operators in `ops` (HB_OP_V | HB_OP_K | HB_OP_D | HB_OP_V11) on
+ * the device
  * (Sec. 3.1 eq. for V_h^d, Sec. 3.2 eq. for K_h^d; assembly order Sec. 5).  Each entry is the
  * spatial quadrature over a triangle pair of the exact temporal integral: Radon's 7-point rule
  * on each triangle for separated pairs, Sauter-Schwab [0,1]^4 rules of order opt.ss_order for
@@ -119,10 +122,13 @@ int hb_sizes(const hb_ctx *ctx, int64_t *n_tris, int64_t *n_verts, int32_t *n_t,
  * D_h^{1,d} = T^T (alpha^2 V_h^d (x) I_3) T is formed from the assembled V_h and the surface
  * curls of the p1 basis (so V_h must be assembled before or in the same call, else HB_ESTATE);
  * D_h^{2,d} = int int n(x).n(y) phi_i phi_j D^{2,d} with the same rules as V_h, in double whatever
- * the precision argument.  D keeps a workspace of its own size. */
+ * the precision argument.  D keeps a workspace of its own size.
+ * HB_OP_V11: V_h^{11,d} = int int phi_i phi_j V^d (p1 x p1, N_x x N_x; the kernel, rules and
+ * temporal forms of V_h), sharing D's workspace. */
 int hb_assemble(hb_ctx *ctx, uint32_t ops, int32_t precision, void *stream);
 
-/* Copy blocks d0 .. d0 + nd - 1 of op (HB_OP_V, HB_OP_K or HB_OP_D) into dst (layout [nd][rows][cols]
+/* Copy blocks d0 .. d0 + nd - 1 of op (HB_OP_V, HB_OP_K, HB_OP_D or HB_OP_V11) into dst (layout
+ * [nd][rows][cols]
  * as the block storage), converting to dtype (HB_DTYPE_F64 / HB_DTYPE_F32).  dst is a device
  * pointer if dst_on_device != 0, else a host pointer (the copy is then synchronous). */
 int hb_get_blocks(hb_ctx *ctx, uint32_t op, int32_t d0, int32_t nd, void *dst, int32_t dtype,
@@ -130,7 +136,7 @@ int hb_get_blocks(hb_ctx *ctx, uint32_t op, int32_t d0, int32_t nd, void *dst, i
 
 /* Block lower-triangular Toeplitz product y^k = sum_{d=0}^{k} A^d x^{k-d} (Sec. 3.1 eq. for
  * V_h w; Sec. 3.2 eq. for K_h; Sec. 3.3) for op = HB_OP_V (x: E_t x E_x) or HB_OP_K (x: E_t x N_x),
- * y: E_t x E_x; op = HB_OP_D (x, y: E_t x N_x); op = HB_OP_KT (x: E_t x E_x, y: E_t x N_x; the
+ * y: E_t x E_x; op = HB_OP_D or HB_OP_V11 (x, y: E_t x N_x); op = HB_OP_KT (x: E_t x E_x, y: E_t x N_x; the
  * transposed blocks are formed once per assembly of K in a buffer of the size of K).
  * x, y: device pointers, float64, time-major, not overlapping.  Supports
  * E_t <= 256 (HB_EINVAL beyond); float block storage multiplies in float (x rounded to float) with

@@ -39,6 +39,7 @@ def lib():
         L.or_pair_points.argtypes = [_dp, _ip, i32, i32, i32, _dp, _dp, _dp, _dp,
                                      ctypes.POINTER(ctypes.c_int)]
         L.or_assemble_d2.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, _dp]
+        L.or_assemble_v11.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, _dp]
         L.or_assemble.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, _ip, i32, i32, i32,
                                   _dp, _dp]
         L.or_repr.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, _dp, _dp, _dp, i32, i32, i32,
@@ -159,3 +160,16 @@ def assemble_d2(verts, tris, alpha, T, n_t, ss_order=4):
     if rc != 0:
         raise ValueError("or_assemble_d2 failed (%d)" % rc)
     return D2
+
+
+def assemble_v11(verts, tris, alpha, T, n_t, ss_order=4):
+    """Blocks V_h^{11,d} (n_t, N_x, N_x): the single layer between p1 test and p1 trial functions
+    (the matrix of the operator preconditioner for D_h, Sec. 6.1), same rules as V_h."""
+    verts, tris = _f64(verts), _i32(tris)
+    ne, nv = len(tris), len(verts)
+    V11 = np.empty((n_t, nv, nv))
+    rc = lib().or_assemble_v11(verts.ravel(), nv, tris.ravel(), ne, float(alpha), float(T), n_t,
+                               ss_order, V11)
+    if rc != 0:
+        raise ValueError("or_assemble_v11 failed (%d)" % rc)
+    return V11

@@ -23,6 +23,7 @@
  *   - single- and double-layer potentials (representation formula) (Sec. 3.5)
  *   - the second part D^{2,d}(r) of the hypersingular operator and its Galerkin blocks
  *     (p1 x p1 with n(x) . n(y))                                     (Sec. 3.3, eq. for D^{2,d})
+ *   - the single layer between p1 functions, V_h^{11}                (Sec. 6.1, preconditioner of D_h)
  *
  * Readings where the paper is silent (each is also listed in the design notes):
  *   - Small-argument series for the double-layer bracket (it cancels like 1/z^2 when
@@ -650,8 +651,24 @@ int or_assemble(const double *verts, int nv, const int32_t *tris, int ne, double
 /*   D2^d[i][j] = int int n(x) . n(y) phi^1_i(x) phi^1_j(y) D^{2,d}(x - y) ds_y ds_x,           */
 /* every ordered panel pair with the same rules as V and K.  D2 out: [n_t][n_verts][n_verts].    */
 /* ------------------------------------------------------------------------------------------ */
+/* which = 0: V^{11} blocks, the single layer between p1 test and p1 trial functions (the matrix
+ * of the paper's operator preconditioner for D_h, Sec. 6.1): kernel V^d(r), no normal factor;
+ * which = 1: D^2 blocks as above. */
+static int assemble_p1p1(const double *verts, int nv, const int32_t *tris, int ne, double alpha,
+                         double T, int nt, int ss_order, int which, double *D2);
+
 int or_assemble_d2(const double *verts, int nv, const int32_t *tris, int ne, double alpha,
                    double T, int nt, int ss_order, double *D2) {
+  return assemble_p1p1(verts, nv, tris, ne, alpha, T, nt, ss_order, 1, D2);
+}
+
+int or_assemble_v11(const double *verts, int nv, const int32_t *tris, int ne, double alpha,
+                    double T, int nt, int ss_order, double *V11) {
+  return assemble_p1p1(verts, nv, tris, ne, alpha, T, nt, ss_order, 0, V11);
+}
+
+static int assemble_p1p1(const double *verts, int nv, const int32_t *tris, int ne, double alpha,
+                         double T, int nt, int ss_order, int which, double *D2) {
   if (nt < 1 || ne < 1 || nv < 3 || alpha <= 0 || T <= 0) return -1;
   prepare_rules(ss_order);
   ld h = (ld)T / (ld)nt, al = (ld)alpha;
@@ -668,14 +685,14 @@ int or_assemble_d2(const double *verts, int nv, const int32_t *tris, int ne, dou
       for (size_t i = 0; i < 3 * (size_t)nt * nv; ++i) rows[i] = 0.0L;
       for (int b = 0; b < ne; ++b) {
         make_tri(verts, tris + 3 * b, &B);
-        const ld nn = A.n[0] * B.n[0] + A.n[1] * B.n[1] + A.n[2] * B.n[2];
+        const ld nn = which ? A.n[0] * B.n[0] + A.n[1] * B.n[1] + A.n[2] * B.n[2] : 1.0L;
         int n = pair_points(verts, tris, a, b, q);
         for (int i = 0; i < 9 * nt; ++i) acc[i] = 0.0L;
         for (int i = 0; i < n; ++i) {
           ld r[3] = {q[i].x[0] - q[i].y[0], q[i].x[1] - q[i].y[1], q[i].x[2] - q[i].y[2]};
           ld rho = sqrtl(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
           for (int d = 0; d < nt; ++d) {
-            ld v = q[i].W * or_D2d(rho, d, h, al);
+            ld v = q[i].W * (which ? or_D2d(rho, d, h, al) : or_Vd(rho, d, h, al, 0));
             for (int k = 0; k < 3; ++k)
               for (int l = 0; l < 3; ++l) acc[9 * d + 3 * k + l] += v * q[i].phix[k] * q[i].phi[l];
           }

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libheatbem.so")
 
 HB_OK, HB_EINVAL, HB_EMESH, HB_EORIENT, HB_ENOMEM, HB_EHIP, HB_ENOCONV, HB_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
-HB_OP_V, HB_OP_K, HB_OP_D, HB_OP_KT = 1, 2, 4, 8
+HB_OP_V, HB_OP_K, HB_OP_D, HB_OP_KT, HB_OP_V11 = 1, 2, 4, 8, 16
 HB_PREC_FP64, HB_PREC_MIXED = 0, 1
 HB_DTYPE_F64, HB_DTYPE_F32 = 0, 1
 HB_SOLVE_GMRES, HB_SOLVE_TIMEMARCH, HB_SOLVE_MIXED_IR = 0, 1, 2
@@ -198,10 +198,10 @@ class Context:
 
     def blocks(self, op, d0=0, nd=None, dtype=None, device=True, stream=None):
         """Blocks d0 .. d0+nd-1 of op as a (nd, rows, cols) tensor (device) or ndarray (host):
-        rows E_x (V, K) or N_x (D), cols E_x (V) or N_x (K, D)."""
+        rows E_x (V, K) or N_x (D, V11), cols E_x (V) or N_x (K, D, V11)."""
         import torch
         nd = self.n_t - d0 if nd is None else nd
-        rows = self.n_verts if op == HB_OP_D else self.n_tris
+        rows = self.n_verts if op in (HB_OP_D, HB_OP_V11) else self.n_tris
         cols = self.n_tris if op == HB_OP_V else self.n_verts
         if dtype is None:
             dtype = HB_DTYPE_F32 if self.storage == HB_DTYPE_F32 else HB_DTYPE_F64
@@ -216,7 +216,7 @@ class Context:
     def apply(self, op, x, y=None, stream=None):
         import torch
         if y is None:
-            rows = self.n_verts if op in (HB_OP_D, HB_OP_KT) else self.n_tris
+            rows = self.n_verts if op in (HB_OP_D, HB_OP_KT, HB_OP_V11) else self.n_tris
             y = torch.empty((self.n_t, rows), dtype=torch.float64, device="cuda")
         self._check(lib().hb_apply(self._h, op, _ptr(x), _ptr(y), _stream(stream)))
         return y

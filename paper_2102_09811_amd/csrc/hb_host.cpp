@@ -682,7 +682,7 @@ void hb_destroy(hb_ctx *c) {
                   c->d_taylor32, c->d_tdeg, c->d_V32, c->d_tscale, c->d_mass,
                   c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d,
-                  c->d_D, c->d_Dw, c->d_Kt, c->d_d2tab, c->d_d2scale, c->d_d2len, c->d_curl, c->d_vstart,
+                  c->d_D, c->d_Dw, c->d_V11, c->d_Kt, c->d_d2tab, c->d_d2scale, c->d_d2len, c->d_curl, c->d_vstart,
                   c->d_vadj};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -703,35 +703,47 @@ int hb_sizes(const hb_ctx *c, int64_t *ne, int64_t *nv, int32_t *nt, int64_t *nt
   return HB_OK;
 }
 
-// D_h (Sec. 3.3) from the assembled V_h; the kernels read the parameters of the last assembly.
-static int assemble_d(hb_ctx *c, hipStream_t s) {
+// The p1 x p1 operators: V_h^{11} (Sec. 6.1) and D_h (Sec. 3.3, from the assembled V_h); the kernels
+// read the parameters of the last assembly (uploaded here if none has run).
+static int assemble_p1(hb_ctx *c, uint32_t ops, hipStream_t s) {
   const size_t nD = (size_t)c->nt * c->nv * c->nv, esz = c->storage_f32 ? 4 : 8;
-  if (!c->d_D) {
-    HB_HIP(c, hipMalloc(&c->d_D, nD * esz + hb::kBlockPad));
-    HB_HIP(c, hipMemsetAsync((char *)c->d_D + nD * esz, 0, hb::kBlockPad, s));
-  }
-  if (!c->d_Dw) HB_HIP(c, hipMalloc(&c->d_Dw, nD * esz));
   if (!c->d_params) {
     c->launch = c->params;
     c->launch.V = c->d_V;
     HB_HIP(c, hipMalloc(&c->d_params, sizeof(hb::AsmParams)));
     HB_HIP(c, hipMemcpyAsync(c->d_params, &c->launch, sizeof(c->launch), hipMemcpyHostToDevice, s));
   }
-  int rc = hb::launch_assemble_d(c, s);
-  if (rc) return fail(c, rc, "hypersingular assembly launch failed");
-  c->have_D = true;
+  if (!c->d_Dw) HB_HIP(c, hipMalloc(&c->d_Dw, nD * esz));
+  if (ops & HB_OP_V11) {
+    if (!c->d_V11) {
+      HB_HIP(c, hipMalloc(&c->d_V11, nD * esz + hb::kBlockPad));
+      HB_HIP(c, hipMemsetAsync((char *)c->d_V11 + nD * esz, 0, hb::kBlockPad, s));
+    }
+    int rc = hb::launch_assemble_v11(c, s);
+    if (rc) return fail(c, rc, "V11 assembly launch failed");
+    c->have_V11 = true;
+  }
+  if (ops & HB_OP_D) {
+    if (!c->d_D) {
+      HB_HIP(c, hipMalloc(&c->d_D, nD * esz + hb::kBlockPad));
+      HB_HIP(c, hipMemsetAsync((char *)c->d_D + nD * esz, 0, hb::kBlockPad, s));
+    }
+    int rc = hb::launch_assemble_d(c, s);
+    if (rc) return fail(c, rc, "hypersingular assembly launch failed");
+    c->have_D = true;
+  }
   return HB_OK;
 }
 
 int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
   if (!c) return fail(nullptr, HB_EINVAL, "null context");
-  if (ops == 0 || (ops & ~(HB_OP_V | HB_OP_K | HB_OP_D)))
-    return fail(c, HB_EINVAL, "ops must be a non-empty subset of HB_OP_V | HB_OP_K | HB_OP_D");
+  if (ops == 0 || (ops & ~(HB_OP_V | HB_OP_K | HB_OP_D | HB_OP_V11)))
+    return fail(c, HB_EINVAL, "ops must be a non-empty subset of HB_OP_V | HB_OP_K | HB_OP_D | HB_OP_V11");
   if (precision != HB_PREC_FP64 && precision != HB_PREC_MIXED) return fail(c, HB_EINVAL, "unknown precision");
   if ((ops & HB_OP_D) && !(ops & HB_OP_V) && !c->have_V)
     return fail(c, HB_ESTATE, "HB_OP_D needs V (assembled before or in the same call)");
   hipStream_t s = (hipStream_t)stream;
-  if (!(ops & (HB_OP_V | HB_OP_K))) return assemble_d(c, s);
+  if (!(ops & (HB_OP_V | HB_OP_K))) return assemble_p1(c, ops, s);
   size_t esz = c->storage_f32 ? 4 : 8;
   size_t nV = (size_t)c->nt * c->ne * c->ne, nK = (size_t)c->nt * c->ne * c->nv;
   if ((ops & HB_OP_V) && !c->d_V) {
@@ -786,7 +798,7 @@ int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
     c->Kt_valid = false;
   }
   c->timed = true;
-  if (ops & HB_OP_D) return assemble_d(c, s);
+  if (ops & (HB_OP_D | HB_OP_V11)) return assemble_p1(c, ops, s);
   return HB_OK;
 }
 
@@ -807,17 +819,18 @@ int hb_last_assembly_ms(hb_ctx *c, double ms[3]) {
 int hb_get_blocks(hb_ctx *c, uint32_t op, int32_t d0, int32_t nd, void *dst, int32_t dtype,
                   int32_t dst_on_device, void *stream) {
   if (!c || !dst) return fail(c, HB_EINVAL, "null argument");
-  if (op != HB_OP_V && op != HB_OP_K && op != HB_OP_D)
-    return fail(c, HB_EINVAL, "op must be HB_OP_V, HB_OP_K or HB_OP_D");
+  if (op != HB_OP_V && op != HB_OP_K && op != HB_OP_D && op != HB_OP_V11)
+    return fail(c, HB_EINVAL, "op must be HB_OP_V, HB_OP_K, HB_OP_D or HB_OP_V11");
   if (d0 < 0 || nd < 0 || d0 + nd > c->nt) return fail(c, HB_EINVAL, "block range out of bounds");
   if (dtype != HB_DTYPE_F64 && dtype != HB_DTYPE_F32) return fail(c, HB_EINVAL, "bad dtype");
-  bool have = op == HB_OP_V ? c->have_V : op == HB_OP_K ? c->have_K : c->have_D;
+  const bool p1p1 = op == HB_OP_D || op == HB_OP_V11;
+  bool have = op == HB_OP_V ? c->have_V : op == HB_OP_K ? c->have_K : op == HB_OP_D ? c->have_D : c->have_V11;
   if (!have) return fail(c, HB_ESTATE, "operator not assembled");
-  const size_t rows = op == HB_OP_D ? (size_t)c->nv : (size_t)c->ne;
+  const size_t rows = p1p1 ? (size_t)c->nv : (size_t)c->ne;
   size_t cols = op == HB_OP_V ? (size_t)c->ne : (size_t)c->nv;
   size_t per = rows * cols, n = per * nd;
   size_t esz = c->storage_f32 ? 4 : 8;
-  const void *base = op == HB_OP_V ? c->d_V : op == HB_OP_K ? c->d_K : c->d_D;
+  const void *base = op == HB_OP_V ? c->d_V : op == HB_OP_K ? c->d_K : op == HB_OP_D ? c->d_D : c->d_V11;
   const char *src = (const char *)base + (size_t)d0 * per * esz;
   hipStream_t s = (hipStream_t)stream;
   bool same = (dtype == HB_DTYPE_F32) == (c->storage_f32 != 0);

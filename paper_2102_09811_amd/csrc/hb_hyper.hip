@@ -18,6 +18,10 @@
 // D^2 = W + W^T.  Touching pairs: one wave per ordered pair, the regularised rule of its class.
 // D_h^{1,d} = T^T (alpha^2 V^d (x) I_3) T (Sec. 3.3, eq. for D_h^{1,d}) is added entry by entry
 // from V_h^d and the surface curls of the local p1 basis.
+// The same p1 x p1 kernels assemble V_h^{11}, the single layer between p1 functions (the matrix
+// of the paper's preconditioner for D_h, Sec. 6.1), with the kernel V^d(r) of V_h: closed form
+// (second differences of G^{dtau dt} = rho A(z) / (8 pi alpha^2)) below d_switch, the even Taylor
+// tables of V_h above, and no normal factor.
 #include "hb_device.h"
 #include "hb_internal.h"
 
@@ -37,29 +41,73 @@ __device__ __forceinline__ double d2_closed(double rho, int d, double ah) {
   return (erfc(zp) - 2.0 * erfc(z0) + erfc(zm)) * c;
 }
 
-// Value of D^{2,d} at rho^2 (N = 0: closed form; else the Taylor polynomial with N coefficients).
-template <int N>
-__device__ __forceinline__ double d2_value(double rho2, int d, double ah, double cw, double sc,
-                                           const double *__restrict__ tab, const double *etab) {
+constexpr int kKindV11 = 0, kKindD2 = 1;
+constexpr double kInvSqrtPi = 0.56418958354775628695;
+
+// rho A(z) at level i (G^{dtau dt}(rho, i h) = kV rho A(z)): the small-z series below z = 1/2
+__device__ __forceinline__ double rA_level(const AsmParams &p, int i, double rho) {
+  if (i == 0) return rho;
+  const double z = rho * p.lv.c[i];
+  if (z < 0.5) return fma(rho * z * kInvSqrtPi, horner<kSeriesN>(p.serA, z * z), p.lv.t2[i]);
+  const double er = erf(z);
+  return fma(rho, er, er * p.lv.s2[i] / rho) + exp_neg(z * z) * p.lv.s1[i];
+}
+
+// V^d(rho) in closed form (Sec. 3.1, eq. for V^0 and the second difference for V^d)
+__device__ __forceinline__ double v_closed(const AsmParams &p, double rho, int d) {
+  if (d == 0) return p.kVs / rho - p.kV * (rA_level(p, 1, rho) - rho);
+  return p.kV * (2.0 * rA_level(p, d, rho) - rA_level(p, d + 1, rho) - rA_level(p, d - 1, rho));
+}
+
+// Kernel value at rho^2 for block d (N = 0: closed form; else the Taylor polynomial with N
+// coefficients, scale sc, w = rho^2 cw)
+template <int KIND, int N>
+__device__ __forceinline__ double kern_value(const AsmParams &p, double rho2, int d, double ah,
+                                             double cw, double sc, const double *__restrict__ tab,
+                                             const double *etab) {
   if constexpr (N == 0) {
-    return d2_closed(sqrt(rho2), d, ah);
+    if constexpr (KIND == kKindD2) return d2_closed(sqrt(rho2), d, ah);
+    else return v_closed(p, sqrt(rho2), d);
   } else {
     const double w = rho2 * cw;
     return sc * exp_neg_t(w, etab) * horner<N>(tab, w);
   }
 }
 
+// Per-block Taylor data of kind KIND: polynomial, its length, scale and w factor
+struct P1Tabs {
+  const double *tscale, *d2tab, *d2scale, *taylor;
+  const int32_t *d2len, *tdeg;
+};
+
+template <int KIND>
+__device__ __forceinline__ int block_len(const AsmParams &p, const P1Tabs &T, int d) {
+  if constexpr (KIND == kKindD2) return d < kD2Closed ? 0 : T.d2len[d];
+  else return d < p.dsw ? 0 : T.tdeg[2 * d] + 1;
+}
+
+template <int KIND>
+__device__ __forceinline__ void block_tab(const P1Tabs &T, int d, double &cw, double &sc,
+                                          const double *&tab) {
+  cw = T.tscale[3 * d + 2];
+  if constexpr (KIND == kKindD2) {
+    sc = T.d2scale[d];
+    tab = T.d2tab + (size_t)d * kTaylorND;
+  } else {
+    sc = T.tscale[3 * d];
+    tab = T.taylor + (size_t)(2 * d) * kTaylorN;
+  }
+}
+
 // One block d of a separated pair: S[a][b] = sum over the 7 x 7 point pairs of the weights, the
 // kernel and the test / trial barycentrics.
-template <int N>
-__device__ __forceinline__ void d2_sep_block(const AsmParams &p, int l, int m, int d, double ah,
-                                             const double *__restrict__ d2tab,
-                                             const double *__restrict__ d2scale,
-                                             const double *__restrict__ tscale,
-                                             const double *etab, double S[3][3]) {
+template <int KIND, int N>
+__device__ __forceinline__ void p1_sep_block(const AsmParams &p, int l, int m, int d, double ah,
+                                             const P1Tabs &T, const double *etab, double S[3][3]) {
   const int ne = p.ne;
-  const double cw = N ? tscale[3 * d + 2] : 0.0, sc = N ? d2scale[d] : 0.0;
-  const double *tab = d2tab + (size_t)d * kTaylorND;
+  double cw = 0.0, sc = 0.0;
+  const double *tab = nullptr;
+  if constexpr (N > 0) block_tab<KIND>(T, d, cw, sc, tab);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -74,7 +122,7 @@ __device__ __forceinline__ void d2_sep_block(const AsmParams &p, int l, int m, i
       const double rx = x0 - p.geom[(b * 3 + 0) * ne + m];
       const double ry = x1 - p.geom[(b * 3 + 1) * ne + m];
       const double rz = x2 - p.geom[(b * 3 + 2) * ne + m];
-      const double v = p.w7[b] * d2_value<N>(fma(rx, rx, fma(ry, ry, rz * rz)), d, ah, cw, sc, tab, etab);
+      const double v = p.w7[b] * kern_value<KIND, N>(p, fma(rx, rx, fma(ry, ry, rz * rz)), d, ah, cw, sc, tab, etab);
       t0 = fma(v, p.lam7[b][0], t0);
       t1 = fma(v, p.lam7[b][1], t1);
       t2 = fma(v, p.lam7[b][2], t2);
@@ -89,14 +137,70 @@ __device__ __forceinline__ void d2_sep_block(const AsmParams &p, int l, int m, i
   }
 }
 
-template <typename TS>
-__global__ __launch_bounds__(256) void k_d2_separated(const AsmParams *__restrict__ pp,
-                                                      const double *__restrict__ tscale,
-                                                      const double *__restrict__ d2tab,
-                                                      const double *__restrict__ d2scale,
-                                                      const int32_t *__restrict__ d2len,
+// One block of a separated / touching pair as a functor templated on the polynomial length.
+template <int KIND>
+struct SepBlock {
+  const AsmParams &p;
+  int l, m, d;
+  double ah;
+  const P1Tabs &T;
+  const double *etab;
+  double (&S)[3][3];
+  template <int N>
+  __device__ __forceinline__ void operator()() const {
+    p1_sep_block<KIND, N>(p, l, m, d, ah, T, etab, S);
+  }
+};
+
+template <int KIND, int N>
+__device__ __forceinline__ void p1_touch_block(const AsmParams &p, const TouchPair &tp,
+                                               const double *__restrict__ tab, int ntab, int lane,
+                                               int d, double ah, const P1Tabs &T,
+                                               const double *etab, double S[9]);
+
+template <int KIND>
+struct TouchBlock {
+  const AsmParams &p;
+  const TouchPair &tp;
+  const double *tab;
+  int ntab, lane, d;
+  double ah;
+  const P1Tabs &T;
+  const double *etab;
+  double (&S)[9];
+  template <int N>
+  __device__ __forceinline__ void operator()() const {
+    p1_touch_block<KIND, N>(p, tp, tab, ntab, lane, d, ah, T, etab, S);
+  }
+};
+
+// Dispatch of one block to the polynomial length of its table (0: closed form).
+template <int KIND, typename F>
+__device__ __forceinline__ void by_len(int len, F &&f) {
+  switch (len) {
+    case 0: f.template operator()<0>(); break;
+    case 29: if constexpr (KIND == kKindV11) f.template operator()<29>(); break;
+    case 25: if constexpr (KIND == kKindV11) f.template operator()<25>(); break;
+    case 21: if constexpr (KIND == kKindV11) f.template operator()<21>(); break;
+    case 19: if constexpr (KIND == kKindV11) f.template operator()<19>(); break;
+    case 17: if constexpr (KIND == kKindV11) f.template operator()<17>(); break;
+    case 16: if constexpr (KIND == kKindD2) f.template operator()<16>(); break;
+    case 15: if constexpr (KIND == kKindV11) f.template operator()<15>(); break;
+    case 14: if constexpr (KIND == kKindD2) f.template operator()<14>(); break;
+    case 13: if constexpr (KIND == kKindV11) f.template operator()<13>(); break;
+    case 12: if constexpr (KIND == kKindD2) f.template operator()<12>(); break;
+    case 11: if constexpr (KIND == kKindV11) f.template operator()<11>(); break;
+    case 10: if constexpr (KIND == kKindD2) f.template operator()<10>(); break;
+    case 9: if constexpr (KIND == kKindV11) f.template operator()<9>(); break;
+    case 8: if constexpr (KIND == kKindD2) f.template operator()<8>(); break;
+    default: if constexpr (KIND == kKindV11) f.template operator()<7>(); break;
+  }
+}
+
+template <int KIND, typename TS>
+__global__ __launch_bounds__(256) void k_p1_separated(const AsmParams *__restrict__ pp, P1Tabs T,
                                                       const int32_t *__restrict__ tasks,
-                                                      int ntasks, TS *__restrict__ Dw) {
+                                                      int ntasks, TS *__restrict__ W) {
   const AsmParams &p = *pp;
   __shared__ double etab[64];
   stage_exp_tab(etab);
@@ -114,29 +218,20 @@ __global__ __launch_bounds__(256) void k_d2_separated(const AsmParams *__restric
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       if (vl[i] == vm[j]) return;  // touching: handled by the regularised rules
-  const double nn = p.geom[21 * ne + l] * p.geom[21 * ne + m] +
-                    p.geom[22 * ne + l] * p.geom[22 * ne + m] +
-                    p.geom[23 * ne + l] * p.geom[23 * ne + m];
+  const double nn = KIND == kKindD2 ? p.geom[21 * ne + l] * p.geom[21 * ne + m] +
+                                          p.geom[22 * ne + l] * p.geom[22 * ne + m] +
+                                          p.geom[23 * ne + l] * p.geom[23 * ne + m]
+                                    : 1.0;
   const double scale = nn * p.geom[24 * ne + l] * p.geom[24 * ne + m];
   const double ah = p.alpha * p.h;
   for (int d = 0; d < p.nt; ++d) {
-    double S[3][3];
-    if (d < kD2Closed) {
-      d2_sep_block<0>(p, l, m, d, ah, d2tab, d2scale, tscale, etab, S);
-    } else {
-      switch (d2len[d]) {
-        case 16: d2_sep_block<16>(p, l, m, d, ah, d2tab, d2scale, tscale, etab, S); break;
-        case 14: d2_sep_block<14>(p, l, m, d, ah, d2tab, d2scale, tscale, etab, S); break;
-        case 12: d2_sep_block<12>(p, l, m, d, ah, d2tab, d2scale, tscale, etab, S); break;
-        case 10: d2_sep_block<10>(p, l, m, d, ah, d2tab, d2scale, tscale, etab, S); break;
-        default: d2_sep_block<8>(p, l, m, d, ah, d2tab, d2scale, tscale, etab, S); break;
-      }
-    }
-    TS *Db = Dw + (size_t)d * nv * nv;
+    double S[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    by_len<KIND>(block_len<KIND>(p, T, d), SepBlock<KIND>{p, l, m, d, ah, T, etab, S});
+    TS *Wb = W + (size_t)d * nv * nv;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) atomicAdd(&Db[(size_t)vl[i] * nv + vm[j]], (TS)(scale * S[i][j]));
+      for (int j = 0; j < 3; ++j) atomicAdd(&Wb[(size_t)vl[i] * nv + vm[j]], (TS)(scale * S[i][j]));
   }
 }
 
@@ -159,11 +254,14 @@ __global__ __launch_bounds__(256) void k_sym_blocks(const TS *__restrict__ W, TS
   }
 }
 
-template <int N>
-__device__ __forceinline__ void d2_touch_block(const TouchPair &tp, const double *__restrict__ tab,
-                                               int ntab, int lane, int d, double ah, double cw,
-                                               double sc, const double *__restrict__ poly,
+template <int KIND, int N>
+__device__ __forceinline__ void p1_touch_block(const AsmParams &p, const TouchPair &tp,
+                                               const double *__restrict__ tab, int ntab, int lane,
+                                               int d, double ah, const P1Tabs &T,
                                                const double *etab, double S[9]) {
+  double cw = 0.0, sc = 0.0;
+  const double *poly = nullptr;
+  if constexpr (N > 0) block_tab<KIND>(T, d, cw, sc, poly);
 #pragma unroll
   for (int k = 0; k < 9; ++k) S[k] = 0.0;
 #pragma unroll 1
@@ -173,7 +271,7 @@ __device__ __forceinline__ void d2_touch_block(const TouchPair &tp, const double
     const double ry = a1 * tp.E1[1] + a2 * tp.E2[1] + a3 * tp.F1[1] + a4 * tp.F2[1];
     const double rz = a1 * tp.E1[2] + a2 * tp.E2[2] + a3 * tp.F1[2] + a4 * tp.F2[2];
     const double v = tab[4 * ntab + q] *
-                     d2_value<N>(fma(rx, rx, fma(ry, ry, rz * rz)), d, ah, cw, sc, poly, etab);
+                     kern_value<KIND, N>(p, fma(rx, rx, fma(ry, ry, rz * rz)), d, ah, cw, sc, poly, etab);
     const double ly0 = tab[5 * ntab + q], ly1 = tab[6 * ntab + q], ly2 = tab[7 * ntab + q];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -185,15 +283,10 @@ __device__ __forceinline__ void d2_touch_block(const TouchPair &tp, const double
   }
 }
 
-template <typename TS>
-__global__ __launch_bounds__(64) void k_d2_touching(const AsmParams *__restrict__ pp,
+template <int KIND, typename TS>
+__global__ __launch_bounds__(64) void k_p1_touching(const AsmParams *__restrict__ pp,
                                                     const TouchPair *__restrict__ pairs,
-                                                    RuleTabs rules,
-                                                    const double *__restrict__ tscale,
-                                                    const double *__restrict__ d2tab,
-                                                    const double *__restrict__ d2scale,
-                                                    const int32_t *__restrict__ d2len,
-                                                    TS *__restrict__ D) {
+                                                    RuleTabs rules, P1Tabs T, TS *__restrict__ D) {
   const AsmParams &p = *pp;
   __shared__ double etab[64];
   stage_exp_tab(etab);
@@ -203,22 +296,10 @@ __global__ __launch_bounds__(64) void k_d2_touching(const AsmParams *__restrict_
   const double *__restrict__ tab = rules.d[cls];
   const int ntab = rules.n[cls];
   const int lane = threadIdx.x, nv = p.nv;
-  const double ah = p.alpha * p.h, f = tp.scale * tp.nn;
+  const double ah = p.alpha * p.h, f = tp.scale * (KIND == kKindD2 ? tp.nn : 1.0);
   for (int d = 0; d < p.nt; ++d) {
-    double S[9];
-    const double cw = tscale[3 * d + 2], sc = d2scale[d];
-    const double *poly = d2tab + (size_t)d * kTaylorND;
-    if (d < kD2Closed) {
-      d2_touch_block<0>(tp, tab, ntab, lane, d, ah, 0.0, 0.0, poly, etab, S);
-    } else {
-      switch (d2len[d]) {
-        case 16: d2_touch_block<16>(tp, tab, ntab, lane, d, ah, cw, sc, poly, etab, S); break;
-        case 14: d2_touch_block<14>(tp, tab, ntab, lane, d, ah, cw, sc, poly, etab, S); break;
-        case 12: d2_touch_block<12>(tp, tab, ntab, lane, d, ah, cw, sc, poly, etab, S); break;
-        case 10: d2_touch_block<10>(tp, tab, ntab, lane, d, ah, cw, sc, poly, etab, S); break;
-        default: d2_touch_block<8>(tp, tab, ntab, lane, d, ah, cw, sc, poly, etab, S); break;
-      }
-    }
+    double S[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    by_len<KIND>(block_len<KIND>(p, T, d), TouchBlock<KIND>{p, tp, tab, ntab, lane, d, ah, T, etab, S});
 #pragma unroll
     for (int k = 0; k < 9; ++k)
 #pragma unroll
@@ -278,28 +359,38 @@ __global__ __launch_bounds__(256) void k_transpose_blocks(const TS *__restrict__
   }
 }
 
-template <typename TS>
-int assemble_d_typed(hb_ctx *c, hipStream_t s) {
-  const int nt = c->nt, ne = (int)c->ne, nv = (int)c->nv;
+// p1 x p1 blocks of kind KIND into out: separated pairs into the workspace, out = W + W^T, then
+// the touching pairs
+template <int KIND, typename TS>
+int assemble_p1p1(hb_ctx *c, TS *out, hipStream_t s) {
+  const int nt = c->nt, nv = (int)c->nv;
   const size_t nD = (size_t)nt * nv * nv;
-  TS *D = (TS *)c->d_D, *W = (TS *)c->d_Dw;
+  TS *W = (TS *)c->d_Dw;
+  P1Tabs T{c->d_tscale, c->d_d2tab, c->d_d2scale, c->d_taylor, c->d_d2len, c->d_tdeg};
   if (hipMemsetAsync(W, 0, nD * sizeof(TS), s) != hipSuccess) return HB_EHIP;
   if (c->n_sep_tasks > 0)
-    hipLaunchKernelGGL((k_d2_separated<TS>), dim3((unsigned)((c->n_sep_tasks + 3) / 4)), dim3(256),
-                       0, s, c->d_params, c->d_tscale, c->d_d2tab, c->d_d2scale, c->d_d2len,
-                       c->d_sep_tasks, (int)c->n_sep_tasks, W);
+    hipLaunchKernelGGL((k_p1_separated<KIND, TS>), dim3((unsigned)((c->n_sep_tasks + 3) / 4)),
+                       dim3(256), 0, s, c->d_params, T, c->d_sep_tasks, (int)c->n_sep_tasks, W);
   const dim3 tiles((nv + 63) / 64, (nv + 63) / 64, nt);
-  hipLaunchKernelGGL((k_sym_blocks<TS>), tiles, dim3(256), 0, s, W, D, nv);
+  hipLaunchKernelGGL((k_sym_blocks<TS>), tiles, dim3(256), 0, s, W, out, nv);
   if (!c->touch.empty()) {
     RuleTabs rt{};
     for (int k = 1; k <= 3; ++k) {
       rt.d[k] = c->ss[k].d;
       rt.n[k] = c->ss[k].n;
     }
-    hipLaunchKernelGGL((k_d2_touching<TS>), dim3((unsigned)c->touch.size()), dim3(64), 0, s,
-                       c->d_params, c->d_touch, rt, c->d_tscale, c->d_d2tab, c->d_d2scale,
-                       c->d_d2len, D);
+    hipLaunchKernelGGL((k_p1_touching<KIND, TS>), dim3((unsigned)c->touch.size()), dim3(64), 0, s,
+                       c->d_params, c->d_touch, rt, T, out);
   }
+  return hipGetLastError() == hipSuccess ? HB_OK : HB_EHIP;
+}
+
+template <typename TS>
+int assemble_d_typed(hb_ctx *c, hipStream_t s) {
+  const int nt = c->nt, ne = (int)c->ne, nv = (int)c->nv;
+  TS *D = (TS *)c->d_D;
+  int rc = assemble_p1p1<kKindD2, TS>(c, D, s);
+  if (rc) return rc;
   hipLaunchKernelGGL((k_d1<TS>), dim3((nv + 255) / 256, nv, nt), dim3(256), 0, s,
                      (const TS *)c->d_V, D, c->d_curl, c->d_vstart, c->d_vadj, ne, nv,
                      c->alpha * c->alpha);
@@ -316,6 +407,11 @@ void transpose_typed(const void *src, void *dst, int R, int C, int nt, hipStream
 
 int launch_assemble_d(hb_ctx *c, hipStream_t s) {
   return c->storage_f32 ? assemble_d_typed<float>(c, s) : assemble_d_typed<double>(c, s);
+}
+
+int launch_assemble_v11(hb_ctx *c, hipStream_t s) {
+  return c->storage_f32 ? assemble_p1p1<kKindV11, float>(c, (float *)c->d_V11, s)
+                        : assemble_p1p1<kKindV11, double>(c, (double *)c->d_V11, s);
 }
 
 int launch_transpose_blocks(hb_ctx *c, const void *src, void *dst, int R, int C, hipStream_t s) {

@@ -101,6 +101,9 @@ void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const Tou
 constexpr int kD2Closed = 8;
 constexpr int kTaylorND = 16;        // coefficients of the odd Taylor polynomial of D^{2,d}, d >= 8
 int launch_assemble_d(hb_ctx *c, hipStream_t s);
+// V_h^{11}: the single layer between p1 test and trial functions (the paper's preconditioner
+// matrix for D_h, Sec. 6.1) into c->d_V11, same rules and temporal forms as V_h
+int launch_assemble_v11(hb_ctx *c, hipStream_t s);
 // blockwise transpose [nt][R][C] -> [nt][C][R]
 int launch_transpose_blocks(hb_ctx *c, const void *src, void *dst, int R, int C, hipStream_t s);
 
@@ -145,6 +148,8 @@ struct hb_ctx {
   // hypersingular operator: blocks [nt][nv][nv], workspace of the separated pairs' half, tables
   void *d_D = nullptr, *d_Dw = nullptr;
   bool have_D = false;
+  void *d_V11 = nullptr;             // [nt][nv][nv]: single layer between p1 functions
+  bool have_V11 = false;
   void *d_Kt = nullptr;              // K^d transposed block by block (K_h^T of the Neumann system)
   bool Kt_valid = false;
   double *d_d2tab = nullptr;         // [nt][kTaylorND]: odd Taylor polynomial of D^{2,d}

@@ -1128,9 +1128,9 @@ int hb_apply(hb_ctx *c, uint32_t op, const double *x, double *y, void *stream) {
   if (!c) return HB_EINVAL;
   if (!x || !y) return ctx_fail(c, HB_EINVAL, "null vector");
   hipStream_t s = (hipStream_t)stream;
-  if (op == HB_OP_D) {
-    if (!c->have_D) return ctx_fail(c, HB_ESTATE, "operator not assembled");
-    return toeplitz_apply(c, c->d_D, (int)c->nv, (int)c->nv, x, y, s);
+  if (op == HB_OP_D || op == HB_OP_V11) {
+    if (op == HB_OP_D ? !c->have_D : !c->have_V11) return ctx_fail(c, HB_ESTATE, "operator not assembled");
+    return toeplitz_apply(c, op == HB_OP_D ? c->d_D : c->d_V11, (int)c->nv, (int)c->nv, x, y, s);
   }
   if (op == HB_OP_KT) {
     if (!c->have_K) return ctx_fail(c, HB_ESTATE, "operator not assembled");
@@ -1139,7 +1139,7 @@ int hb_apply(hb_ctx *c, uint32_t op, const double *x, double *y, void *stream) {
     return toeplitz_apply(c, c->d_Kt, (int)c->nv, (int)c->ne, x, y, s);
   }
   if (op != HB_OP_V && op != HB_OP_K)
-    return ctx_fail(c, HB_EINVAL, "op must be HB_OP_V, HB_OP_K, HB_OP_D or HB_OP_KT");
+    return ctx_fail(c, HB_EINVAL, "op must be HB_OP_V, HB_OP_K, HB_OP_D, HB_OP_V11 or HB_OP_KT");
   if (op == HB_OP_V ? !c->have_V : !c->have_K) return ctx_fail(c, HB_ESTATE, "operator not assembled");
   return toeplitz_apply(c, op == HB_OP_V ? c->d_V : c->d_K, (int)c->ne,
                         (int)(op == HB_OP_V ? c->ne : c->nv), x, y, s);

@@ -26,7 +26,7 @@ def test_call_order_and_arguments(torch):
     with pytest.raises(HBError) as e:
         ctx.solve(x)
     assert e.value.code == HB_ESTATE
-    for ops in (0, 16, 32):
+    for ops in (0, 32, 64):
         with pytest.raises(HBError) as e:
             ctx.assemble(ops)
         assert e.value.code == HB_EINVAL
@@ -104,7 +104,7 @@ def test_neumann_call_order_and_arguments(torch):
             call()
         assert e.value.code == HB_ESTATE
     with pytest.raises(HBError) as e:
-        ctx.assemble(16)
+        ctx.assemble(32)
     assert e.value.code == HB_EINVAL
     ctx.assemble(HB_OP_V | HB_OP_K | HB_OP_D)
     from paper_2102_09811_amd import binding

@@ -112,3 +112,23 @@ def test_neumann_products_rhs_and_solve(torch):
     ur = ds.time_march(D, br)
     assert np.abs(u.cpu().numpy() - ur).max() <= 1e-8 * np.abs(ur).max()
     ctx.close()
+
+
+@pytest.mark.parametrize("case,opts", [("octa_nt12", {}), ("cube2_nt40", {}),
+                                       ("cube4_nt16", {}), ("cube4_nt16", {"d_switch": 8})])
+def test_V11_blocks_match_oracle(torch, case, opts):
+    """V_h^{11} (p1 x p1 single layer, the paper's preconditioner matrix for D_h) against the
+    oracle's closed form in long double, block-relative 1e-12 (d_switch 8 moves blocks 3..7 from
+    the Taylor form to the closed form)."""
+    from paper_2102_09811_amd import HB_OP_V11, Context
+    mesh, args, alpha, nt = CASES[case]
+    v, t = mesh(*args)
+    say("V11 blocks %s %s" % (case, opts))
+    ctx = Context(v, t, alpha, 1.0, nt, **opts)
+    ctx.assemble(HB_OP_V11)
+    Vg = ctx.blocks(HB_OP_V11).cpu().numpy()
+    Vr = oracle.assemble_v11(v, t, alpha, 1.0, nt)
+    e = ds.block_rel_error(Vr, Vg)
+    say("  max e_V11 = %.2e (block %d)" % (e.max(), e.argmax()))
+    assert e.max() <= 1e-12
+    ctx.close()

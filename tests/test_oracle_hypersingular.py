@@ -8,7 +8,9 @@ against mathematics the oracle does not use.
 * D_h^1 annihilates spatially constant functions and is symmetric when V_h^d is;
 * D_h^2 blocks are symmetric up to the regularised rules' error (exactly for separated pairs);
 * end to end: the Neumann problem of Sec. 6.1 on the coarsest mesh (192 triangles, 8 steps)
-  against the errors printed in Table 6.2.
+  against the errors printed in Table 6.2;
+* the p1 single layer V_h^{11} (the matrix of the paper's preconditioner for D_h) sums to the p0
+  single layer over all entries (the p1 basis is a partition of unity).
 """
 import mpmath as mp
 import numpy as np
@@ -113,3 +115,18 @@ def test_neumann_coarsest_level_table62():
     assert abs(e_u / 3.14e-1 - 1) < 0.03
     assert abs(e_p / 2.50e-1 - 1) < 0.05
     assert abs(e_r / 5.16e-2 - 1) < 0.25
+
+
+def test_V11_partition_of_unity_and_symmetry():
+    """The p1 basis sums to one on every panel, so sum_{i,j} V11^d[i][j] = sum_{l,m} V^d[l][m]
+    (V_h from the p0 assembly, a different code path), and V11 is symmetric up to the
+    regularised rules' error."""
+    v, t = octahedron()
+    nt = 6
+    V, _ = oracle.assemble(v, t, 0.8, 1.0, nt)
+    V11 = oracle.assemble_v11(v, t, 0.8, 1.0, nt)
+    s11 = V11.reshape(nt, -1).sum(1)
+    s0 = V.reshape(nt, -1).sum(1)
+    assert np.abs(s11 - s0).max() <= 1e-13 * np.abs(s0).max()
+    asym = np.abs(V11 - V11.transpose(0, 2, 1)).max() / np.abs(V11).max()
+    assert asym < 1e-4
