@@ -186,8 +186,11 @@ int hb_solve(hb_ctx *ctx, const double *b, double *w, const hb_solve_opts *opts,
 
 /* Solve the Neumann system D_h u = b for u (Sec. 3.4) by unrestarted GMRES in double on the block
  * system (the paper uses FGMRES).  b, u: device pointers, E_t x N_x, float64.  opts: method must
- * be HB_SOLVE_GMRES and precond 0 (HB_EINVAL otherwise); tol and max_iter as for hb_solve.  Needs
- * HB_OP_D assembled (HB_ESTATE).  info->rel_residual is ||b - D_h u|| / ||b||. */
+ * be HB_SOLVE_GMRES (HB_EINVAL otherwise); tol and max_iter as for hb_solve; precond 1 applies
+ * the operator preconditioner M_h^{-1} V_h^{11} M_h^{-1} from the right (Sec. 6.1: V_h^{11} as its
+ * essential part; M_h = h blockdiag(M), M the p1 mass matrix, inverted once per context), which
+ * needs HB_OP_V11 assembled.  Needs HB_OP_D assembled (HB_ESTATE).  info->rel_residual is
+ * ||b - D_h u|| / ||b||. */
 int hb_solve_neumann(hb_ctx *ctx, const double *b, double *u, const hb_solve_opts *opts,
                      hb_solve_info *info, void *stream);
 

@@ -236,13 +236,14 @@ class Context:
         self._check(lib().hb_rhs_neumann(self._h, _ptr(psi), _ptr(b), _stream(stream)))
         return b
 
-    def solve_neumann(self, b, tol=1e-8, max_iter=500, u=None, stream=None):
-        """D_h u = b by GMRES; b, u: (E_t, N_x)."""
+    def solve_neumann(self, b, tol=1e-8, max_iter=500, u=None, precond=False, stream=None):
+        """D_h u = b by GMRES; b, u: (E_t, N_x); precond: the operator preconditioner
+        M_h^{-1} V_h^{11} M_h^{-1} (needs HB_OP_V11 assembled)."""
         import torch
         if u is None:
             u = torch.empty((self.n_t, self.n_verts), dtype=torch.float64, device="cuda")
         o = SolveOpts()
-        o.method, o.tol, o.max_iter, o.precond = HB_SOLVE_GMRES, tol, max_iter, 0
+        o.method, o.tol, o.max_iter, o.precond = HB_SOLVE_GMRES, tol, max_iter, int(bool(precond))
         info = SolveInfo()
         rc = lib().hb_solve_neumann(self._h, _ptr(b), _ptr(u), ctypes.byref(o), ctypes.byref(info),
                                     _stream(stream))

@@ -682,7 +682,7 @@ void hb_destroy(hb_ctx *c) {
                   c->d_taylor32, c->d_tdeg, c->d_V32, c->d_tscale, c->d_mass,
                   c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d,
-                  c->d_D, c->d_Dw, c->d_V11, c->d_Kt, c->d_d2tab, c->d_d2scale, c->d_d2len, c->d_curl, c->d_vstart,
+                  c->d_D, c->d_Dw, c->d_V11, c->d_minv, c->d_pcw, c->d_Kt, c->d_d2tab, c->d_d2scale, c->d_d2len, c->d_curl, c->d_vstart,
                   c->d_vadj};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);

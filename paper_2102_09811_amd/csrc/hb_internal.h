@@ -150,6 +150,10 @@ struct hb_ctx {
   bool have_D = false;
   void *d_V11 = nullptr;             // [nt][nv][nv]: single layer between p1 functions
   bool have_V11 = false;
+  double *d_minv = nullptr;          // inverse of the p1 mass matrix (+ elimination workspace)
+  bool minv_valid = false;
+  double *d_pcw = nullptr;           // operator preconditioner: two vectors of E_t x N_x
+  size_t pcw_n = 0;
   void *d_Kt = nullptr;              // K^d transposed block by block (K_h^T of the Neumann system)
   bool Kt_valid = false;
   double *d_d2tab = nullptr;         // [nt][kTaylorND]: odd Taylor polynomial of D^{2,d}

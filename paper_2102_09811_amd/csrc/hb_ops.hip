@@ -810,6 +810,19 @@ int gemv_batch(hb_ctx *c, const void *A, size_t stride, int R, int C, int nd, co
   return HB_OK;
 }
 
+// In-place inverse of the n x n double matrix A by blocked Gauss-Jordan elimination (no pivoting:
+// A is V_h^0 or a mass matrix, both symmetric positive definite); T, Cc, Ainv: workspace.
+void gj_invert(double *A, int n, double *T, double *Cc, double *Ainv, hipStream_t s) {
+  const dim3 tiles((n + 63) / 64, (n + 63) / 64);
+  for (int p0 = 0; p0 < n; p0 += kGJB) {
+    const int b = std::min(kGJB, n - p0);
+    hipLaunchKernelGGL(k_gjb_pivot, dim3(1), dim3(256), 0, s, A, n, p0, b, Ainv);
+    hipLaunchKernelGGL(k_gjb_rows, dim3(grid1d((size_t)kGJB * n)), dim3(256), 0, s, A, n, p0, b,
+                       Ainv, T, Cc);
+    hipLaunchKernelGGL(k_gjb_update, tiles, dim3(256), 0, s, A, n, p0, b, T, Cc);
+  }
+}
+
 int invert_v0(hb_ctx *c, hipStream_t s) {
   if (c->v0inv_valid) return HB_OK;
   const int n = (int)c->ne;
@@ -821,16 +834,34 @@ int invert_v0(hb_ctx *c, hipStream_t s) {
     hipLaunchKernelGGL(k_f32_to_f64, dim3(grid1d(nn)), dim3(256), 0, s, (const float *)c->d_V, A, nn);
   else
     HB_CHECK(c, hipMemcpyAsync(A, c->d_V, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-  const dim3 tiles((n + 63) / 64, (n + 63) / 64);
-  for (int p0 = 0; p0 < n; p0 += kGJB) {
-    const int b = std::min(kGJB, n - p0);
-    hipLaunchKernelGGL(k_gjb_pivot, dim3(1), dim3(256), 0, s, A, n, p0, b, Ainv);
-    hipLaunchKernelGGL(k_gjb_rows, dim3(grid1d((size_t)kGJB * n)), dim3(256), 0, s, A, n, p0, b,
-                       Ainv, T, Cc);
-    hipLaunchKernelGGL(k_gjb_update, tiles, dim3(256), 0, s, A, n, p0, b, T, Cc);
-  }
+  gj_invert(A, n, T, Cc, Ainv, s);
   HB_CHECK(c, hipGetLastError());
   c->v0inv_valid = true;
+  return HB_OK;
+}
+
+// Inverse of the p1 mass matrix M[i][j] = int phi^1_i phi^1_j (sum over the panels at i and j of
+// area (1 + [i == j]) / 12), formed once per context; the operator preconditioner of the
+// Neumann system applies M_h^{-1} = (h M)^{-1} in every time step.
+int ensure_minv(hb_ctx *c, hipStream_t s) {
+  if (c->minv_valid) return HB_OK;
+  const int n = (int)c->nv;
+  const size_t nn = (size_t)n * n;
+  if (!c->d_minv)
+    HB_CHECK(c, hipMalloc(&c->d_minv, sizeof(double) * (nn + 2 * (size_t)kGJB * n + kGJB * kGJB)));
+  std::vector<double> M(nn, 0.0);
+  for (int64_t t = 0; t < c->ne; ++t)
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        M[(size_t)c->tris[3 * t + a] * n + c->tris[3 * t + b]] += c->area[t] * (a == b ? 2.0 : 1.0) / 12.0;
+  double *A = c->d_minv, *T = A + nn, *Cc = T + (size_t)kGJB * n, *Ainv = Cc + (size_t)kGJB * n;
+  HB_CHECK(c, hipMemcpyAsync(A, M.data(), sizeof(double) * nn, hipMemcpyHostToDevice, s));
+  gj_invert(A, n, T, Cc, Ainv, s);
+  // the Toeplitz product's fragment loads may read past the last row: zeros there
+  HB_CHECK(c, hipMemsetAsync(A + nn, 0, kBlockPad, s));
+  HB_CHECK(c, hipGetLastError());
+  HB_CHECK(c, hipStreamSynchronize(s));  // M lives on the host stack
+  c->minv_valid = true;
   return HB_OK;
 }
 
@@ -882,13 +913,40 @@ int ensure_V32(hb_ctx *c, hipStream_t s) {
   return HB_OK;
 }
 
+// Operator preconditioner of the Neumann system (the paper's use of V_h^{11}, Sec. 6.1):
+// z = M_h^{-1} V_h^{11} M_h^{-1} q with M_h = h blockdiag(M), M the p1 mass matrix.
+int op_precond_apply(hb_ctx *c, const double *q, double *z, hipStream_t s) {
+  const size_t n = (size_t)c->nt * c->nv;
+  if (!c->d_pcw || c->pcw_n < n) {
+    if (c->d_pcw) (void)hipFree(c->d_pcw);
+    c->d_pcw = nullptr;
+    c->pcw_n = 0;
+    HB_CHECK(c, hipMalloc(&c->d_pcw, sizeof(double) * 2 * n));
+    c->pcw_n = n;
+  }
+  double *t1 = c->d_pcw, *t2 = t1 + n;
+  const int nv = (int)c->nv, nt = c->nt;
+  int rc = launch_toeplitz<double>(c, c->d_minv, nv, nv, q, t1, s, 0, 1, 0, nt, false, 0);
+  if (rc) return rc;
+  if ((rc = toeplitz_apply(c, c->d_V11, nv, nv, t1, t2, s))) return rc;
+  if ((rc = launch_toeplitz<double>(c, c->d_minv, nv, nv, t2, z, s, 0, 1, 0, nt, false, 0))) return rc;
+  hipLaunchKernelGGL(k_axpby, dim3(grid1d(n)), dim3(256), 0, s, 1.0 / (c->h * c->h), z, 0.0, z, n);
+  HB_CHECK(c, hipGetLastError());
+  return HB_OK;
+}
+
+// z = P q: 1 the learned block-diagonal map (V_h), 2 the operator preconditioner (D_h)
+int pc_apply(hb_ctx *c, int kind, const double *q, double *z, hipStream_t s) {
+  return kind == 2 ? op_precond_apply(c, q, z, s) : precond_apply(c, q, z, s);
+}
+
 // Unrestarted GMRES (right-preconditioned by the learned block-diagonal map when precond) with
 // classical Gram-Schmidt applied twice.  The Arnoldi recurrence (Hessenberg column, Givens
 // rotations, residual estimate) stays on the device; the host learns each step's residual
 // estimate one step late through pinned memory while the next step is already queued, so the GPU
 // never waits for the host (a converged solve computes one surplus step, which is discarded).
 int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, hipStream_t s,
-          hb_solve_info *info, bool precond = false) {
+          hb_solve_info *info, int precond = 0) {
   const size_t n = (size_t)c->nt * (op == 2 ? c->nv : c->ne);
   const int m = maxit;
   const int nchunk = (int)((n + kDotChunk - 1) / kDotChunk);
@@ -933,7 +991,7 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
   for (int j = 0; j < m; ++j) {
     double *wj = Q + (size_t)(j + 1) * n;
     if (precond) {
-      if ((rc = precond_apply(c, Q + (size_t)j * n, r, s))) return rc;
+      if ((rc = pc_apply(c, precond, Q + (size_t)j * n, r, s))) return rc;
       if ((rc = apply_V(c, op, r, wj, s))) return rc;
     } else if ((rc = apply_V(c, op, Q + (size_t)j * n, wj, s))) {
       return rc;
@@ -981,7 +1039,7 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
   HB_CHECK(c, hipMemcpyAsync(coef, y.data(), sizeof(double) * it, hipMemcpyHostToDevice, s));
   if (precond) {
     hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, s, Q, n, coef, it, r, n);
-    if ((rc = precond_apply(c, r, x, s))) return rc;
+    if ((rc = pc_apply(c, precond, r, x, s))) return rc;
   } else {
     hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, s, Q, n, coef, it, x, n);
   }
@@ -1174,14 +1232,18 @@ int hb_solve_neumann(hb_ctx *c, const double *b, double *u, const hb_solve_opts 
     if (o.max_iter <= 0) o.max_iter = 500;
     if (!(o.tol > 0)) o.tol = 1e-8;
   }
-  if (o.method != HB_SOLVE_GMRES || o.precond)
-    return ctx_fail(c, HB_EINVAL, "the Neumann system is solved by plain GMRES only");
+  if (o.method != HB_SOLVE_GMRES)
+    return ctx_fail(c, HB_EINVAL, "the Neumann system is solved by GMRES only");
+  if (o.precond != 0 && o.precond != 1) return ctx_fail(c, HB_EINVAL, "precond must be 0 or 1");
+  if (o.precond && !c->have_V11) return ctx_fail(c, HB_ESTATE, "the preconditioner needs HB_OP_V11");
   if (o.max_iter > 5000) return ctx_fail(c, HB_EINVAL, "max_iter must be <= 5000");
   hipStream_t s = (hipStream_t)stream;
   hb_solve_info inf{};
   HB_CHECK(c, hipStreamSynchronize(s));
   auto t0 = std::chrono::steady_clock::now();
-  int rc = gmres(c, 2, b, u, o.tol, o.max_iter, s, &inf, false);
+  int rc;
+  if (o.precond && (rc = ensure_minv(c, s))) return rc;
+  rc = gmres(c, 2, b, u, o.tol, o.max_iter, s, &inf, o.precond ? 2 : 0);
   if (rc != HB_OK && rc != HB_ENOCONV) return rc;
   HB_CHECK(c, hipStreamSynchronize(s));
   auto t1 = std::chrono::steady_clock::now();

@@ -111,6 +111,14 @@ def test_neumann_products_rhs_and_solve(torch):
     assert info["converged"] and info["rel_residual"] <= 1e-10
     ur = ds.time_march(D, br)
     assert np.abs(u.cpu().numpy() - ur).max() <= 1e-8 * np.abs(ur).max()
+    # with the operator preconditioner M_h^{-1} V^11 M_h^{-1}: same solution, fewer iterations
+    from paper_2102_09811_amd import HB_OP_V11
+    ctx.assemble(HB_OP_V11)
+    up, infp = ctx.solve_neumann(b, tol=1e-10, precond=True)
+    say("preconditioned: %d iterations, residual %.1e" % (infp["iterations"], infp["rel_residual"]))
+    assert infp["converged"] and infp["rel_residual"] <= 1e-10
+    assert infp["iterations"] < info["iterations"]
+    assert np.abs(up.cpu().numpy() - ur).max() <= 1e-8 * np.abs(ur).max()
     ctx.close()
 
 
