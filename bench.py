@@ -144,6 +144,35 @@ def compare_solvers(ctx, b, net):
     return res
 
 
+def neumann_timings(ctx, stream):
+    """Hypersingular side of the same workload (outside the timed step): assembly of D_h and
+    V_h^{11} (p1 x p1 blocks) from the assembled V_h, and GMRES on D_h u = (1/2 M_h^T - K_h^T) psi
+    for a synthetic Neumann datum psi, plain and with the operator preconditioner."""
+    import numpy as np
+    import torch
+    from paper_2102_09811_amd import HB_OP_D, HB_OP_V11
+    res = {}
+    for name, op in (("assemble_D_ms", HB_OP_D), ("assemble_V11_ms", HB_OP_V11)):
+        ctx.assemble(op)                       # first call allocates
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.assemble(op)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1)
+    psi = torch.from_numpy(np.random.default_rng(5).standard_normal((ctx.n_t, ctx.n_tris))).cuda()
+    b = ctx.rhs_neumann(psi)
+    ctx.solve_neumann(b, precond=True)        # inverts the mass matrix once
+    for key, pc in (("gmres", False), ("gmres_operator_precond", True)):
+        u, info = ctx.solve_neumann(b, tol=1e-8, precond=pc)
+        res[key] = {"ms": info["seconds"] * 1e3, "iterations": info["iterations"],
+                    "rel_residual": info["rel_residual"]}
+        log("neumann %-24s %7.2f ms  it=%d res=%.2e" % (key, info["seconds"] * 1e3,
+                                                       info["iterations"], info["rel_residual"]))
+    log("assembly D %.2f ms, V11 %.2f ms" % (res["assemble_D_ms"], res["assemble_V11_ms"]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +306,7 @@ def main():
         out["mixed_assembly"] = {"ms": ms_mixed, "units_per_s": units / (ms_mixed * 1e-3),
                                  "separated_kernel_ms": ctx.last_assembly_ms()[0]}
         ctx.assemble(HB_OP_V | HB_OP_K)
+        out["neumann"] = neumann_timings(ctx, stream)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(verts, tris, alpha, T, n_t)
