@@ -173,6 +173,24 @@ def neumann_timings(ctx, stream):
     return res
 
 
+def nearfield_timings(ctx, stream, radius=0.35):
+    """Near-field assembly (outside the timed step): the per-pair blocks of V_h and K_h for the
+    pairs within `radius` (centroid distance) plus the touching ones."""
+    import torch
+    start, cols = ctx.nearfield_pattern(radius)
+    ctx.assemble_nearfield()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.assemble_nearfield()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    units = len(cols) * ctx.n_t
+    log("near field r=%g: %d pairs (%.1f per row), %.2f ms, %.3g pair-blocks/s" % (
+        radius, len(cols), len(cols) / ctx.n_tris, ms, units / (ms * 1e-3)))
+    return {"radius": radius, "pairs": int(len(cols)), "ms": ms, "pair_blocks_per_s": units / (ms * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,6 +325,7 @@ def main():
                                  "separated_kernel_ms": ctx.last_assembly_ms()[0]}
         ctx.assemble(HB_OP_V | HB_OP_K)
         out["neumann"] = neumann_timings(ctx, stream)
+        out["nearfield"] = nearfield_timings(ctx, stream)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(verts, tris, alpha, T, n_t)

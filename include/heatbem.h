@@ -127,6 +127,22 @@ int hb_sizes(const hb_ctx *ctx, int64_t *n_tris, int64_t *n_verts, int32_t *n_t,
  * temporal forms of V_h), sharing D's workspace. */
 int hb_assemble(hb_ctx *ctx, uint32_t ops, int32_t precision, void *stream);
 
+/* Near field (the paper's outlook, Sec. 6.2: with a fast multipole method the formulae give the
+ * near-field entries only).  hb_nearfield_pattern lists, per test panel l, the trial panels m whose
+ * centroid lies within `radius` of l's, plus every panel touching l (shared vertex), sorted by m:
+ * row_start[E_x + 1] (int64) and cols[nnz] (int32), host arrays, either may be NULL (nnz is always
+ * written, so a first call with NULL arrays sizes them).  The pattern is kept for
+ * hb_assemble_nearfield.  radius >= 0 and finite, else HB_EINVAL. */
+int hb_nearfield_pattern(hb_ctx *ctx, double radius, int64_t *nnz, int64_t *row_start,
+                         int32_t *cols);
+
+/* Blocks of the near-field pairs of the last pattern, per pair: V[d][e] = V_h^d[l][cols[e]] and
+ * K[d][e][k] = the contribution of panel cols[e] through its local vertex k (the p1 trial function
+ * restricted to that panel; K_h^d[l][j] sums these over the panels at vertex j).  V: E_t x nnz,
+ * K: E_t x nnz x 3, device float64.  Same kernels, rules and temporal forms as hb_assemble
+ * (precision FP64).  HB_ESTATE without a pattern. */
+int hb_assemble_nearfield(hb_ctx *ctx, double *V, double *K, void *stream);
+
 /* Copy blocks d0 .. d0 + nd - 1 of op (HB_OP_V, HB_OP_K, HB_OP_D or HB_OP_V11) into dst (layout
  * [nd][rows][cols]
  * as the block storage), converting to dtype (HB_DTYPE_F64 / HB_DTYPE_F32).  dst is a device

@@ -12,8 +12,8 @@ It shares no code with ``paper_2102_09811_amd`` and does not import it.
   GMRES, L2 / l2 errors.
 """
 from .core import (lib, build, temporal, blockfun, triangle_rule, ss_rule, gauss_legendre01,
-                   pair_points, assemble, assemble_d2, assemble_v11, repr_eval)
+                   pair_points, assemble, assemble_d2, assemble_v11, pair_blocks, repr_eval)
 from . import downstream
 
 __all__ = ["lib", "build", "temporal", "blockfun", "triangle_rule", "ss_rule",
-           "gauss_legendre01", "pair_points", "assemble", "assemble_d2", "assemble_v11", "repr_eval", "downstream"]
+           "gauss_legendre01", "pair_points", "assemble", "assemble_d2", "assemble_v11", "pair_blocks", "repr_eval", "downstream"]

@@ -40,6 +40,7 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int)]
         L.or_assemble_d2.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, _dp]
         L.or_assemble_v11.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, _dp]
+        L.or_pair_blocks.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, i32, i32, _dp, _dp]
         L.or_assemble.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, _ip, i32, i32, i32,
                                   _dp, _dp]
         L.or_repr.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, _dp, _dp, _dp, i32, i32, i32,
@@ -173,3 +174,16 @@ def assemble_v11(verts, tris, alpha, T, n_t, ss_order=4):
     if rc != 0:
         raise ValueError("or_assemble_v11 failed (%d)" % rc)
     return V11
+
+
+def pair_blocks(verts, tris, alpha, T, n_t, a, b, ss_order=4):
+    """One ordered panel pair (test a, trial b): V (n_t,) = V_h^d[a][b] and K (n_t, 3) = the
+    contributions of panel b to row a of K_h^d through its local vertices."""
+    verts, tris = _f64(verts), _i32(tris)
+    V = np.empty(n_t)
+    K = np.empty((n_t, 3))
+    rc = lib().or_pair_blocks(verts.ravel(), len(verts), tris.ravel(), len(tris), float(alpha),
+                              float(T), n_t, ss_order, int(a), int(b), V, K.ravel())
+    if rc != 0:
+        raise ValueError("or_pair_blocks failed (%d)" % rc)
+    return V, K

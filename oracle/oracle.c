@@ -569,6 +569,35 @@ static void assemble_row_direct(const double *verts, const int32_t *tris, int nv
   }
 }
 
+/* One ordered panel pair (test a, trial b), every block: V_h^d[a][b] and the contributions of
+ * panel b to row a of K_h^d through its local vertices k (out V[nt], K[nt][3]); the same
+ * per-point temporal integrals as the direct assembly (temporal mode 0). */
+int or_pair_blocks(const double *verts, int nv, const int32_t *tris, int ne, double alpha,
+                   double T, int nt, int ss_order, int a, int b, double *V, double *K) {
+  if (nt < 1 || a < 0 || b < 0 || a >= ne || b >= ne || nv < 3) return -1;
+  prepare_rules(ss_order);
+  qpt_t *q = (qpt_t *)malloc(sizeof(qpt_t) * max_points(ss_order));
+  tri_t B;
+  make_tri(verts, tris + 3 * b, &B);
+  const ld h = (ld)T / nt, al = (ld)alpha;
+  int n = pair_points(verts, tris, a, b, q);
+  for (int d = 0; d < nt; ++d) {
+    ld vd = 0.0L, kd[3] = {0.0L, 0.0L, 0.0L};
+    for (int i = 0; i < n; ++i) {
+      ld r[3] = {q[i].x[0] - q[i].y[0], q[i].x[1] - q[i].y[1], q[i].x[2] - q[i].y[2]};
+      ld rho = sqrtl(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+      ld rn = r[0] * B.n[0] + r[1] * B.n[1] + r[2] * B.n[2];
+      vd += q[i].W * or_Vd(rho, d, h, al, 0);
+      ld kv = q[i].W * rn * or_Kd_rn(rho, d, h, al, 0);
+      for (int k = 0; k < 3; ++k) kd[k] += kv * q[i].phi[k];
+    }
+    V[d] = (double)vd;
+    for (int k = 0; k < 3; ++k) K[3 * d + k] = (double)kd[k];
+  }
+  free(q);
+  return 0;
+}
+
 int or_assemble(const double *verts, int nv, const int32_t *tris, int ne, double alpha, double T,
                 int nt, int ss_order, const int32_t *rows, int nrows, int method, int tmode,
                 double *V, double *K) {

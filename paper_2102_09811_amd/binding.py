@@ -21,6 +21,7 @@ HB_SOLVE_GMRES, HB_SOLVE_TIMEMARCH, HB_SOLVE_MIXED_IR = 0, 1, 2
 EXPORTED = sorted(["hb_default_options", "hb_check_mesh", "hb_create", "hb_destroy",
                    "hb_last_error", "hb_sizes", "hb_assemble", "hb_get_blocks", "hb_apply",
                    "hb_rhs_dirichlet", "hb_rhs_neumann", "hb_solve", "hb_solve_neumann",
+                   "hb_nearfield_pattern", "hb_assemble_nearfield",
                    "hb_eval_repr", "hb_last_assembly_ms",
                    "hb_precond_pattern", "hb_precond_features", "hb_precond_spai",
                    "hb_precond_set", "hb_mlp_num_params", "hb_mlp_work_floats", "hb_mlp_forward",
@@ -84,6 +85,8 @@ def lib():
     L.hb_rhs_dirichlet.argtypes = [vp, vp, vp, vp]
     L.hb_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     L.hb_rhs_neumann.argtypes = [vp, vp, vp, vp]
+    L.hb_nearfield_pattern.argtypes = [vp, f64, ctypes.POINTER(i64), vp, vp]
+    L.hb_assemble_nearfield.argtypes = [vp, vp, vp, vp]
     L.hb_solve_neumann.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     L.hb_eval_repr.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
     L.hb_last_assembly_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
@@ -227,6 +230,27 @@ class Context:
             b = torch.empty((self.n_t, self.n_tris), dtype=torch.float64, device="cuda")
         self._check(lib().hb_rhs_dirichlet(self._h, _ptr(g), _ptr(b), _stream(stream)))
         return b
+
+    def nearfield_pattern(self, radius):
+        """(row_start (E_x + 1,) int64, cols (nnz,) int32): near-field pairs within `radius`
+        (centroid distance) plus every touching pair; kept for assemble_nearfield."""
+        nnz = ctypes.c_int64()
+        self._check(lib().hb_nearfield_pattern(self._h, float(radius), ctypes.byref(nnz), None, None))
+        start = np.empty(self.n_tris + 1, dtype=np.int64)
+        cols = np.empty(max(nnz.value, 1), dtype=np.int32)
+        self._check(lib().hb_nearfield_pattern(self._h, float(radius), ctypes.byref(nnz),
+                                               start.ctypes.data, cols.ctypes.data))
+        self._near_nnz = nnz.value
+        return start, cols[:nnz.value]
+
+    def assemble_nearfield(self, stream=None):
+        """(V (E_t, nnz), K (E_t, nnz, 3)) device float64 for the last near-field pattern."""
+        import torch
+        nnz = getattr(self, "_near_nnz", 0)
+        V = torch.empty((self.n_t, max(nnz, 1)), dtype=torch.float64, device="cuda")
+        K = torch.empty((self.n_t, max(nnz, 1), 3), dtype=torch.float64, device="cuda")
+        self._check(lib().hb_assemble_nearfield(self._h, _ptr(V), _ptr(K), _stream(stream)))
+        return V[:, :nnz], K[:, :nnz]
 
     def rhs_neumann(self, psi, b=None, stream=None):
         """b = (1/2 M_h^T - K_h^T) psi; psi: (E_t, E_x), b: (E_t, N_x)."""

@@ -18,35 +18,12 @@
 // contributions are added to the three trial vertices with atomics.
 #include <algorithm>
 
+#include "hb_closed.h"
 #include "hb_device.h"
 #include "hb_internal.h"
 
 namespace hb {
 namespace {
-
-constexpr double kInvSqrtPi = 0.56418958354775628695;
-constexpr double kFourInvSqrtPi = 2.2567583341910251478;
-
-// One closed-form level: rA = rho A(z), kB = B(z) / rho.
-__device__ __forceinline__ void closed_level(const AsmParams &p, int i, double rho,
-                                             double inv_rho, double &rA, double &kB) {
-  const double c = p.lv.c[i];
-  const double z = rho * c;
-  if (z < 0.5) {
-    const double z2 = z * z;
-    const double sa = horner<kSeriesN>(p.serA, z2);
-    const double sb = horner<kSeriesN>(p.serB, z2);
-    rA = fma(rho * z * kInvSqrtPi, sa, p.lv.t2[i]);
-    kB = kFourInvSqrtPi * c * sb;
-  } else {
-    const double e = exp_neg(z * z);
-    const double er = erf(z);
-    const double es = er * p.lv.s2[i] * inv_rho;   // erf * 2 alpha delta / rho
-    const double ps = e * p.lv.s1[i];              // e^{-z^2} 2 sqrt(alpha delta)/sqrt(pi)
-    rA = fma(rho, er, es) + ps;
-    kB = inv_rho * (er + (ps - es) * inv_rho);
-  }
-}
 
 template <typename TS>
 __device__ __forceinline__ void store_block(const AsmParams &p, int d, int l, int m, double v) {
@@ -75,17 +52,6 @@ struct LevelSums {
   double V[kLC + 2];
   double K[kLC + 2][3];
 };
-
-// rho A and B / rho at level i (i = 0: the delta -> 0 limits A = B = 1).
-__device__ __forceinline__ void level_terms(const AsmParams &p, int i, double rho, double inv_rho,
-                                            double &rA, double &kB) {
-  if (i == 0) {
-    rA = rho;
-    kB = inv_rho;
-  } else {
-    closed_level(p, i, rho, inv_rho, rA, kB);
-  }
-}
 
 // Emit the blocks completed by the pass over levels i0 .. i0+kLC-1 (clipped to D).
 template <typename TS, int D>

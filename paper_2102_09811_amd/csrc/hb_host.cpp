@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <unordered_map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -682,7 +683,7 @@ void hb_destroy(hb_ctx *c) {
                   c->d_taylor32, c->d_tdeg, c->d_V32, c->d_tscale, c->d_mass,
                   c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d,
-                  c->d_D, c->d_Dw, c->d_V11, c->d_minv, c->d_pcw, c->d_Kt, c->d_d2tab, c->d_d2scale, c->d_d2len, c->d_curl, c->d_vstart,
+                  c->d_D, c->d_Dw, c->d_V11, c->d_minv, c->d_pcw, c->d_Kt, c->d_near_sep, c->d_near_touch, c->d_d2tab, c->d_d2scale, c->d_d2len, c->d_curl, c->d_vstart,
                   c->d_vadj};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -813,6 +814,108 @@ int hb_last_assembly_ms(hb_ctx *c, double ms[3]) {
   ms[0] = a;
   ms[1] = b;
   ms[2] = t;
+  return HB_OK;
+}
+
+int hb_nearfield_pattern(hb_ctx *c, double radius, int64_t *nnz, int64_t *row_start,
+                         int32_t *cols) {
+  if (!c || !nnz) return fail(c, HB_EINVAL, "null argument");
+  if (!(radius >= 0) || !std::isfinite(radius)) return fail(c, HB_EINVAL, "radius must be finite and >= 0");
+  const int64_t ne = c->ne;
+  // centroids binned in cells of edge max(radius, tiny): candidates come from the 27 cells around
+  std::vector<double> cent(3 * ne);
+  double lo[3] = {1e300, 1e300, 1e300};
+  for (int64_t t = 0; t < ne; ++t)
+    for (int k = 0; k < 3; ++k) {
+      cent[3 * t + k] = (c->verts[3 * c->tris[3 * t] + k] + c->verts[3 * c->tris[3 * t + 1] + k] +
+                         c->verts[3 * c->tris[3 * t + 2] + k]) / 3.0;
+      lo[k] = std::min(lo[k], cent[3 * t + k]);
+    }
+  const double cell = std::max(radius, 1e-12);
+  auto key = [&](int64_t i, int64_t j, int64_t k) { return (i * 2097152 + j) * 2097152 + k; };
+  std::unordered_map<int64_t, std::vector<int32_t>> grid;
+  std::vector<int64_t> ci(3 * ne);
+  for (int64_t t = 0; t < ne; ++t) {
+    for (int k = 0; k < 3; ++k) ci[3 * t + k] = (int64_t)std::min((cent[3 * t + k] - lo[k]) / cell, 2.0e6);
+    grid[key(ci[3 * t], ci[3 * t + 1], ci[3 * t + 2])].push_back((int32_t)t);
+  }
+  std::unordered_map<int64_t, int32_t> touch_idx;  // (l, m) -> index in the touching list
+  std::vector<std::vector<int32_t>> touch_row(ne);
+  for (size_t i = 0; i < c->touch.size(); ++i) {
+    touch_idx[(int64_t)c->touch[i].l * ne + c->touch[i].m] = (int32_t)i;
+    touch_row[c->touch[i].l].push_back(c->touch[i].m);
+  }
+  c->near_start.assign(ne + 1, 0);
+  c->near_cols.clear();
+  const double r2 = radius * radius;
+  std::vector<int32_t> row;
+  for (int64_t l = 0; l < ne; ++l) {
+    row.clear();
+    for (int64_t di = -1; di <= 1; ++di)
+      for (int64_t dj = -1; dj <= 1; ++dj)
+        for (int64_t dk = -1; dk <= 1; ++dk) {
+          auto it = grid.find(key(ci[3 * l] + di, ci[3 * l + 1] + dj, ci[3 * l + 2] + dk));
+          if (it == grid.end()) continue;
+          for (int32_t m : it->second) {
+            double dd = 0;
+            for (int k = 0; k < 3; ++k) dd += (cent[3 * l + k] - cent[3 * m + k]) * (cent[3 * l + k] - cent[3 * m + k]);
+            if (dd <= r2) row.push_back(m);
+          }
+        }
+    row.insert(row.end(), touch_row[l].begin(), touch_row[l].end());  // every touching pair
+    std::sort(row.begin(), row.end());
+    row.erase(std::unique(row.begin(), row.end()), row.end());
+    c->near_cols.insert(c->near_cols.end(), row.begin(), row.end());
+    c->near_start[l + 1] = (int64_t)c->near_cols.size();
+  }
+  const int64_t n = (int64_t)c->near_cols.size();
+  std::vector<int32_t> sep, tch;
+  for (int64_t l = 0; l < ne; ++l)
+    for (int64_t e = c->near_start[l]; e < c->near_start[l + 1]; ++e) {
+      const int32_t m = c->near_cols[e];
+      auto it = touch_idx.find(l * ne + m);
+      if (it == touch_idx.end()) {
+        sep.push_back((int32_t)l);
+        sep.push_back(m);
+        sep.push_back((int32_t)e);
+      } else {
+        const hb::TouchPair &tp = c->touch[it->second];
+        tch.push_back(it->second);
+        tch.push_back((int32_t)e);
+        for (int j = 0; j < 3; ++j) {
+          int k = 0;
+          while (c->tris[3 * m + k] != tp.vtx[j]) ++k;
+          tch.push_back(k);
+        }
+      }
+    }
+  if (c->d_near_sep) (void)hipFree(c->d_near_sep);
+  if (c->d_near_touch) (void)hipFree(c->d_near_touch);
+  c->d_near_sep = c->d_near_touch = nullptr;
+  c->near_nnz = -1;
+  int rc;
+  if (!sep.empty() && (rc = upload(c, (void **)&c->d_near_sep, sep.data(), sep.size() * sizeof(int32_t)))) return rc;
+  if (!tch.empty() && (rc = upload(c, (void **)&c->d_near_touch, tch.data(), tch.size() * sizeof(int32_t)))) return rc;
+  c->near_nsep = (int64_t)sep.size() / 3;
+  c->near_ntouch = (int64_t)tch.size() / 5;
+  c->near_nnz = n;
+  *nnz = n;
+  if (row_start) std::memcpy(row_start, c->near_start.data(), sizeof(int64_t) * (ne + 1));
+  if (cols) std::memcpy(cols, c->near_cols.data(), sizeof(int32_t) * n);
+  return HB_OK;
+}
+
+int hb_assemble_nearfield(hb_ctx *c, double *V, double *K, void *stream) {
+  if (!c || !V || !K) return fail(c, HB_EINVAL, "null argument");
+  if (c->near_nnz < 0) return fail(c, HB_ESTATE, "no near-field pattern (hb_nearfield_pattern)");
+  hipStream_t s = (hipStream_t)stream;
+  if (!c->d_params) {
+    c->launch = c->params;
+    HB_HIP(c, hipMalloc(&c->d_params, sizeof(hb::AsmParams)));
+    HB_HIP(c, hipMemcpyAsync(c->d_params, &c->launch, sizeof(c->launch), hipMemcpyHostToDevice, s));
+  }
+  int rc = hb::launch_assemble_near(c, V, K, s);
+  if (rc) return fail(c, rc, "near-field assembly launch failed");
   return HB_OK;
 }
 

@@ -22,6 +22,7 @@
 // of the paper's preconditioner for D_h, Sec. 6.1), with the kernel V^d(r) of V_h: closed form
 // (second differences of G^{dtau dt} = rho A(z) / (8 pi alpha^2)) below d_switch, the even Taylor
 // tables of V_h above, and no normal factor.
+#include "hb_closed.h"
 #include "hb_device.h"
 #include "hb_internal.h"
 
@@ -42,15 +43,12 @@ __device__ __forceinline__ double d2_closed(double rho, int d, double ah) {
 }
 
 constexpr int kKindV11 = 0, kKindD2 = 1;
-constexpr double kInvSqrtPi = 0.56418958354775628695;
 
-// rho A(z) at level i (G^{dtau dt}(rho, i h) = kV rho A(z)): the small-z series below z = 1/2
+// rho A(z) at level i (G^{dtau dt}(rho, i h) = kV rho A(z))
 __device__ __forceinline__ double rA_level(const AsmParams &p, int i, double rho) {
-  if (i == 0) return rho;
-  const double z = rho * p.lv.c[i];
-  if (z < 0.5) return fma(rho * z * kInvSqrtPi, horner<kSeriesN>(p.serA, z * z), p.lv.t2[i]);
-  const double er = erf(z);
-  return fma(rho, er, er * p.lv.s2[i] / rho) + exp_neg(z * z) * p.lv.s1[i];
+  double rA, kB;
+  level_terms(p, i, rho, 1.0 / rho, rA, kB);
+  return rA;
 }
 
 // V^d(rho) in closed form (Sec. 3.1, eq. for V^0 and the second difference for V^d)

@@ -104,6 +104,8 @@ int launch_assemble_d(hb_ctx *c, hipStream_t s);
 // V_h^{11}: the single layer between p1 test and trial functions (the paper's preconditioner
 // matrix for D_h, Sec. 6.1) into c->d_V11, same rules and temporal forms as V_h
 int launch_assemble_v11(hb_ctx *c, hipStream_t s);
+// Near-field blocks of the listed ordered pairs (hb_nearfield_pattern): V[d][e], K[d][e][3]
+int launch_assemble_near(hb_ctx *c, double *V, double *K, hipStream_t s);
 // blockwise transpose [nt][R][C] -> [nt][C][R]
 int launch_transpose_blocks(hb_ctx *c, const void *src, void *dst, int R, int C, hipStream_t s);
 
@@ -154,6 +156,12 @@ struct hb_ctx {
   bool minv_valid = false;
   double *d_pcw = nullptr;           // operator preconditioner: two vectors of E_t x N_x
   size_t pcw_n = 0;
+  // near-field pattern: ordered pairs (l, m) by rows; separated entries (l, m, entry) and
+  // touching entries (touching-list index, entry, local trial vertex of rule vertex 0, 1, 2)
+  int64_t near_nnz = -1, near_nsep = 0, near_ntouch = 0;
+  std::vector<int64_t> near_start;
+  std::vector<int32_t> near_cols;
+  int32_t *d_near_sep = nullptr, *d_near_touch = nullptr;
   void *d_Kt = nullptr;              // K^d transposed block by block (K_h^T of the Neumann system)
   bool Kt_valid = false;
   double *d_d2tab = nullptr;         // [nt][kTaylorND]: odd Taylor polynomial of D^{2,d}

@@ -1,0 +1,99 @@
+"""GPU near-field assembly (the paper's outlook, Sec. 6.2: with a fast multipole method the
+formulae give the near-field entries only) against the oracle.
+
+* the pattern, bit-exact: trial panels whose centroid lies within the radius, plus every
+  touching panel, sorted per row (numpy brute force on the host);
+* the per-pair blocks V[d][e], K[d][e][k] against the oracle's per-pair long-double values,
+  block-relative 1e-12, on a small mesh at E_t = 40 (closed-form and Taylor blocks, separated
+  and all three touching classes) and on sampled pairs of the 1280-panel sphere at E_t = 64;
+* the near-field V entries against the full assembly's.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import cube, icosphere
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def brute_pattern(v, t, radius):
+    cent = v[t].mean(axis=1)
+    d2 = ((cent[:, None, :] - cent[None, :, :]) ** 2).sum(-1)
+    share = (t[:, None, :, None] == t[None, :, None, :]).any(axis=(2, 3))
+    return (d2 <= radius * radius) | share
+
+
+def check_pattern(start, cols, mask):
+    assert start[0] == 0 and start[-1] == len(cols)
+    for l in range(mask.shape[0]):
+        row = cols[start[l]:start[l + 1]]
+        assert np.array_equal(row, np.nonzero(mask[l])[0]), l
+
+
+def test_nearfield_small_mesh_all_entries():
+    import torch
+    from paper_2102_09811_amd import HB_EINVAL, HB_ESTATE, Context, HBError
+    v, t = cube(2)
+    alpha, nt, radius = 1.0, 40, 0.8
+    ctx = Context(v, t, alpha, 1.0, nt)
+    with pytest.raises(HBError) as e:
+        ctx.assemble_nearfield()
+    assert e.value.code == HB_ESTATE
+    with pytest.raises(HBError) as e:
+        ctx.nearfield_pattern(-1.0)
+    assert e.value.code == HB_EINVAL
+    start, cols = ctx.nearfield_pattern(radius)
+    check_pattern(start, cols, brute_pattern(v, t, radius))
+    say("near field cube2: %d of %d pairs" % (len(cols), len(t) ** 2))
+    Vn, Kn = ctx.assemble_nearfield()
+    Vn, Kn = Vn.cpu().numpy(), Kn.cpu().numpy()
+    Vr, Kr = np.empty_like(Vn), np.empty_like(Kn)
+    for l in range(len(t)):
+        for e in range(start[l], start[l + 1]):
+            Vr[:, e], Kr[:, e, :] = oracle.pair_blocks(v, t, alpha, 1.0, nt, l, cols[e])
+    eV = (np.abs(Vn - Vr).max(1) / np.abs(Vr).max(1)).max()
+    eK = (np.abs(Kn - Kr).reshape(nt, -1).max(1) / np.abs(Kr).reshape(nt, -1).max(1)).max()
+    say("  max e_V = %.2e, max e_K = %.2e" % (eV, eK))
+    assert eV <= 1e-12 and eK <= 1e-12
+    ctx.close()
+
+
+def test_nearfield_sphere_sampled():
+    import torch
+    from paper_2102_09811_amd import HB_OP_V, Context
+    v, t = icosphere(3)
+    alpha, nt, radius = 1.0, 64, 0.35
+    ctx = Context(v, t, alpha, 1.0, nt)
+    start, cols = ctx.nearfield_pattern(radius)
+    check_pattern(start, cols, brute_pattern(v, t, radius))
+    say("near field icosphere3 r=%g: %d pairs (%.1f per row)" % (radius, len(cols), len(cols) / len(t)))
+    Vn, Kn = ctx.assemble_nearfield()
+    torch.cuda.synchronize()
+    Vn, Kn = Vn.cpu().numpy(), Kn.cpu().numpy()
+    ctx.assemble(HB_OP_V)
+    Vd = ctx.blocks(HB_OP_V).cpu().numpy()
+    rows = np.repeat(np.arange(len(t)), np.diff(start))
+    assert np.abs(Vd[:, rows, cols] - Vn).max() <= 1e-13 * np.abs(Vn).max()
+    rng = np.random.default_rng(3)
+    sample = np.concatenate([rng.choice(len(cols), 120, replace=False),
+                             [start[5] + k for k in range(start[6] - start[5])]])
+    dV = np.zeros(nt)
+    dK = np.zeros(nt)
+    for e in sample:
+        pv, pk = oracle.pair_blocks(v, t, alpha, 1.0, nt, rows[e], cols[e])
+        dV = np.maximum(dV, np.abs(Vn[:, e] - pv))
+        dK = np.maximum(dK, np.abs(Kn[:, e] - pk).max(1))
+    eV = (dV / np.abs(Vn).max(1)).max()
+    eK = (dK / np.abs(Kn).reshape(nt, -1).max(1)).max()
+    say("  sampled %d pairs: max e_V = %.2e, max e_K = %.2e (relative to each block's maximum)" %
+        (len(sample), eV, eK))
+    assert eV <= 1e-12 and eK <= 1e-12
+    ctx.close()

@@ -127,3 +127,19 @@ def test_dirichlet_convergence_table61(level):
     assert abs(e_r / gold[2] - 1) < 0.25
     assert resid <= 1e-8
     assert np.abs(w - wg).max() <= 1e-6 * np.abs(w).max()
+
+
+def test_pair_blocks_sum_to_assembled_rows():
+    """The per-pair blocks (near-field output format) against the row assembly: V entries equal,
+    and the pair contributions scattered to the trial vertices sum to K_h^d."""
+    from synthetic import octahedron
+    v, t = octahedron()
+    nt = 5
+    V, K = oracle.assemble(v, t, 0.9, 1.0, nt, rows=np.array([2], dtype=np.int32))
+    Ks = np.zeros((nt, len(v)))
+    for m in range(len(t)):
+        pv, pk = oracle.pair_blocks(v, t, 0.9, 1.0, nt, 2, m)
+        assert np.abs(pv - V[:, 0, m]).max() <= 1e-15 * np.abs(V).max()
+        for k in range(3):
+            Ks[:, t[m, k]] += pk[:, k]
+    assert np.abs(Ks - K[:, 0, :]).max() <= 1e-14 * np.abs(K).max()
