@@ -124,7 +124,8 @@ int hb_sizes(const hb_ctx *ctx, int64_t *n_tris, int64_t *n_verts, int32_t *n_t,
  * D_h^{2,d} = int int n(x).n(y) phi_i phi_j D^{2,d} with the same rules as V_h, in double whatever
  * the precision argument.  D keeps a workspace of its own size.
  * HB_OP_V11: V_h^{11,d} = int int phi_i phi_j V^d (p1 x p1, N_x x N_x; the kernel, rules and
- * temporal forms of V_h), sharing D's workspace. */
+ * temporal forms of V_h), sharing D's workspace: assemblies of D and V11 on one context must not
+ * overlap on different streams. */
 int hb_assemble(hb_ctx *ctx, uint32_t ops, int32_t precision, void *stream);
 
 /* Near field (the paper's outlook, Sec. 6.2: with a fast multipole method the formulae give the
