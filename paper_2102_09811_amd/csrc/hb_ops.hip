@@ -601,24 +601,32 @@ __global__ __launch_bounds__(256, 2) void k_repr(const AsmParams *__restrict__ p
   constexpr double kPi = 3.14159265358979323846;
   __shared__ double etab[64];
   stage_exp_tab(etab);
-  // per-interval tables, one thread per m
-  for (int m = kReprClosed + 1 + threadIdx.x; m <= k; m += blockDim.x) {
-    double *T = tab + repr_off(m);
+  // the series' coefficient table Q, staged once per workgroup
+  constexpr int kQn = 2 * kReprQ * (kReprDeg + 1);
+  __shared__ double qs[kQn];
+  for (int i = threadIdx.x; i < kQn; i += blockDim.x) qs[i] = qtab[i];
+  __syncthreads();
+  // per-interval tables: one thread per (interval m, series, coefficient), so that the long
+  // tables of the near intervals are spread over the workgroup
+  constexpr int kItems = 2 * (kReprDeg + 1);
+  const int nitems = max(0, k - kReprClosed) * kItems;
+  for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
+    const int m = kReprClosed + 1 + it / kItems;
+    const int pq = (it % kItems) / (kReprDeg + 1), jj = it % (kReprDeg + 1);
     const int D = repr_deg(m), N = D + 1;
+    if (jj >= N) continue;
+    double *T = tab + repr_off(m);
     const double sm = (m - 0.5) * h + eps;
     const double em = h / (2.0 * sm), e2 = em * em;
-    T[0] = 1.0 / (4.0 * al * sm);
-    T[1] = 4.0 * kPi * al * h * pow(4.0 * kPi * al * sm, -1.5);
-    T[2] = 2.0 * kPi * pow(4.0 * kPi * al, -1.5) * h * pow(sm, -2.5);
-    for (int pq = 0; pq < 2; ++pq) {
-      const double *Q = qtab + (size_t)pq * kReprQ * (kReprDeg + 1);
-      for (int jj = 0; jj < N; ++jj) {
-        double c = 0.0;
-        for (int kk = D / 2; kk >= 0; --kk)
-          c = fma(c, e2, 2 * kk >= jj ? Q[kk * (kReprDeg + 1) + jj] : 0.0);
-        T[3 + pq * N + jj] = c;
-      }
+    if (pq == 0 && jj == 0) {
+      T[0] = 1.0 / (4.0 * al * sm);
+      T[1] = 4.0 * kPi * al * h * pow(4.0 * kPi * al * sm, -1.5);
+      T[2] = 2.0 * kPi * pow(4.0 * kPi * al, -1.5) * h * pow(sm, -2.5);
     }
+    const double *Q = qs + pq * kReprQ * (kReprDeg + 1);
+    double c = 0.0;
+    for (int kk = D / 2; kk >= 0; --kk) c = fma(c, e2, 2 * kk >= jj ? Q[kk * (kReprDeg + 1) + jj] : 0.0);
+    T[3 + pq * N + jj] = c;
   }
   __syncthreads();
 
@@ -1356,7 +1364,9 @@ int hb_eval_repr(hb_ctx *c, const double *pts, int64_t P, const double *w, const
       moff += std::max(0, std::min(c->nt + 1, hi[cl]) - lo[cl]) * (3 + 2 * (deg[cl] + 1));
   }
   const size_t lds = std::max<size_t>(8, sizeof(double) * (size_t)moff);
-  if (lds > 160 * 1024) return ctx_fail(c, HB_EINVAL, "E_t too large for the potential kernel");
+  // 160 KiB of LDS per workgroup, less the kernel's static arrays (Q, the exp table, the reduction)
+  if (lds + sizeof(double) * (2 * kReprQ * (kReprDeg + 1) + 64 + 8) > 160 * 1024)
+    return ctx_fail(c, HB_EINVAL, "E_t too large for the potential kernel");
   hipLaunchKernelGGL(k_repr, dim3((unsigned)P), dim3(256), lds, s, c->d_params_repr, c->d_reprq,
                      pts, w, g, u, sl, dl);
   HB_CHECK(c, hipGetLastError());
