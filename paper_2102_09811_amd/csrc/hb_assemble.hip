@@ -97,10 +97,11 @@ __device__ __forceinline__ void shift_carry(LevelSums &S) {
 // ------------------------------------------------------------------------------------------
 // Separated pairs.  Both panels use the same 7-point rule, so the ordered pairs (l, m) and (m, l)
 // share all 49 point pairs (r changes sign, rho does not): one lane evaluates the unordered pair
-// m > l once and emits both orders.  V^d[l][m] = V^d[m][l]; the double layer differs only in the
+// {l, m} once and emits both orders.  V^d[l][m] = V^d[m][l]; the double layer differs only in the
 // normal and the p1 basis:  (l, m) uses r . n_m and the basis at the m-nodes,  (m, l) uses
 // -r . n_l and the basis at the l-nodes.  Each wave takes one task from a host list: test panel l
-// and the 64 trial panels m0 .. m0+63 (m0 > l, lanes past E_x idle); lane = m.
+// and up to 64 trial panels m0, m0 + 1, ... modulo E_x (a round-robin pairing: every unordered
+// pair occurs once and every row fills whole waves but the last); lane i takes m0 + i.
 // ------------------------------------------------------------------------------------------
 struct SymSums {
   double V[kLC + 2];
@@ -376,13 +377,16 @@ __global__ __launch_bounds__(256, 3) void k_separated(const AsmParams *__restric
   stage_exp_tab(etab);
   __syncthreads();
   const SepTabs T{geom, tscale, taylor, taylor32, tdeg, etab};
-  // one task per wave: test panel l and the 64 trial panels m0 .. m0+63 (all > l)
+  // one task per wave: test panel l and up to 64 trial panels m0, m0 + 1, ... (mod E_x); every
+  // unordered pair of panels occurs in exactly one task
   const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (task >= ntasks) return;
-  const int l = __builtin_amdgcn_readfirstlane(tasks[2 * task]);
-  const int m = __builtin_amdgcn_readfirstlane(tasks[2 * task + 1]) + (threadIdx.x & 63);
-  if (m >= p.ne) return;
+  const int l = __builtin_amdgcn_readfirstlane(tasks[3 * task]);
+  const int lane = threadIdx.x & 63;
+  if (lane >= __builtin_amdgcn_readfirstlane(tasks[3 * task + 2])) return;
   const int ne = p.ne;
+  int m = __builtin_amdgcn_readfirstlane(tasks[3 * task + 1]) + lane;
+  if (m >= ne) m -= ne;
   const int vl[3] = {p.tris[3 * l], p.tris[3 * l + 1], p.tris[3 * l + 2]};
   const int vm[3] = {p.tris[3 * m], p.tris[3 * m + 1], p.tris[3 * m + 2]};
   bool touch = false;
@@ -390,7 +394,7 @@ __global__ __launch_bounds__(256, 3) void k_separated(const AsmParams *__restric
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) touch |= vl[i] == vm[j];
-  const bool active = !touch && m > l;
+  const bool active = !touch;
   SepLane L;
   L.xg = geom + l;
   L.nm[0] = geom[21 * ne + m];

@@ -492,15 +492,22 @@ int build_tables(hb_ctx *c) {
   if (!c->touch.empty())
     if ((rc = upload(c, (void **)&c->d_touch, c->touch.data(), c->touch.size() * sizeof(TouchPair))))
       return rc;
-  // separated pairs, unordered (m > l): one wave task per 64 trial panels of a test row
+  // separated pairs, unordered, each once: test row l takes the next np(l) panels l+1, l+2, ...
+  // modulo E_x (round-robin pairing: with E_x odd every row has (E_x-1)/2 partners, with E_x even
+  // the rows l < E_x/2 have E_x/2 and the others E_x/2 - 1), so that all rows carry the same
+  // number of full 64-lane waves instead of a ragged last wave per row; one wave per 64 partners
   {
     std::vector<int32_t> tasks;
-    for (int64_t l = 0; l < (int64_t)ne; ++l)
-      for (int64_t m0 = l + 1; m0 < (int64_t)ne; m0 += 64) {
+    const int64_t n = (int64_t)ne, half = n / 2;
+    for (int64_t l = 0; l < n; ++l) {
+      const int64_t np = (n % 2 == 0 && l >= half) ? half - 1 : half;  // n odd: half = (n-1)/2
+      for (int64_t c0 = 0; c0 < np; c0 += 64) {
         tasks.push_back((int32_t)l);
-        tasks.push_back((int32_t)m0);
+        tasks.push_back((int32_t)((l + 1 + c0) % n));
+        tasks.push_back((int32_t)std::min<int64_t>(64, np - c0));
       }
-    c->n_sep_tasks = (int64_t)tasks.size() / 2;
+    }
+    c->n_sep_tasks = (int64_t)tasks.size() / 3;
     if (!tasks.empty())
       if ((rc = upload(c, (void **)&c->d_sep_tasks, tasks.data(), tasks.size() * sizeof(int32_t))))
         return rc;

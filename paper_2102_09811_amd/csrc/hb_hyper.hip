@@ -13,8 +13,8 @@
 //     D^{2,d} = alpha h G(r, dh) sum_k 2 d^{-(2k+1)} Q_{2k+1}(w) / (2k+2)!,
 //     a polynomial in w tabulated on the host; no cancelling differences remain.
 // Blocks (Sec. 3.3, Galerkin matrix D_h^2): p1 test x p1 trial with n(x) . n(y), the same rules as
-// V_h.  Separated pairs: one wave per test panel l and 64 trial panels m > l (the unordered pair
-// once), Radon's rule on both panels, contributions added to the workspace row block of l; then
+// V_h.  Separated pairs: the task list of the V_h / K_h assembly (test panel l and up to 64
+// trial panels, each unordered pair once), Radon's rule on both panels, contributions added to the workspace row block of l; then
 // D^2 = W + W^T.  Touching pairs: one wave per ordered pair, the regularised rule of its class.
 // D_h^{1,d} = T^T (alpha^2 V^d (x) I_3) T (Sec. 3.3, eq. for D_h^{1,d}) is added entry by entry
 // from V_h^d and the surface curls of the local p1 basis.
@@ -205,10 +205,12 @@ __global__ __launch_bounds__(256) void k_p1_separated(const AsmParams *__restric
   __syncthreads();
   const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (task >= ntasks) return;
-  const int l = __builtin_amdgcn_readfirstlane(tasks[2 * task]);
-  const int m = __builtin_amdgcn_readfirstlane(tasks[2 * task + 1]) + (threadIdx.x & 63);
+  const int l = __builtin_amdgcn_readfirstlane(tasks[3 * task]);
+  const int lane = threadIdx.x & 63;
+  if (lane >= __builtin_amdgcn_readfirstlane(tasks[3 * task + 2])) return;
   const int ne = p.ne, nv = p.nv;
-  if (m >= ne) return;
+  int m = __builtin_amdgcn_readfirstlane(tasks[3 * task + 1]) + lane;
+  if (m >= ne) m -= ne;
   const int vl[3] = {p.tris[3 * l], p.tris[3 * l + 1], p.tris[3 * l + 2]};
   const int vm[3] = {p.tris[3 * m], p.tris[3 * m + 1], p.tris[3 * m + 2]};
 #pragma unroll

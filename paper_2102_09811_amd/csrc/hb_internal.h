@@ -136,7 +136,8 @@ struct hb_ctx {
   double *d_geom = nullptr;
   int32_t *d_tris = nullptr;
   hb::TouchPair *d_touch = nullptr;
-  int32_t *d_sep_tasks = nullptr;    // [n][2]: (test panel l, first trial panel m0 > l) per wave
+  int32_t *d_sep_tasks = nullptr;    // [n][3]: (test panel l, first trial panel m0, lanes) per wave;
+                                     // lane i takes trial panel (m0 + i) mod E_x
   int64_t n_sep_tasks = 0;
   hb::SSRule ss[4];
   double *d_taylor = nullptr, *d_tscale = nullptr;
