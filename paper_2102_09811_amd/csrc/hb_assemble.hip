@@ -378,8 +378,9 @@ __global__ __launch_bounds__(256, 3) void k_separated(const AsmParams *__restric
   __syncthreads();
   const SepTabs T{geom, tscale, taylor, taylor32, tdeg, etab};
   // one task per wave: test panel l and up to 64 trial panels m0, m0 + 1, ... (mod E_x); every
-  // unordered pair of panels occurs in exactly one task
-  const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
+  // unordered pair of panels occurs in exactly one task.  Consecutive rows l, l + 1 mirror their V
+  // entries into neighbouring columns, so the blocks of one XCD take consecutive tasks.
+  const int task = xcd_block() * 4 + (threadIdx.x >> 6);
   if (task >= ntasks) return;
   const int l = __builtin_amdgcn_readfirstlane(tasks[3 * task]);
   const int lane = threadIdx.x & 63;

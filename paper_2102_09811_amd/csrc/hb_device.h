@@ -96,4 +96,14 @@ __device__ __forceinline__ double exp_neg_t(double w, const double *__restrict__
   return ldexp(etab[ki & 63] * q, -(ki >> 6));
 }
 
+
+// Workgroups are dealt to the 8 XCDs (each with its own L2) in turn.  This renumbers them so that
+// each XCD takes a contiguous range of blocks (a bijection of [0, gridDim.x)): neighbouring tasks
+// then write neighbouring addresses through the same L2.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb >> 3, r = nb & 7, x = b & 7, s = b >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
+}
+
 }  // namespace hb
