@@ -38,9 +38,9 @@ PEAK_FP64_VALU = 78.6e12  # MI355X FP64 vector FLOP/s
 # each scaled by the reading of the same counter for a plain 256 MiB device copy taken in the same
 # run (FETCH_SIZE reads 0.500x, WRITE_SIZE 1.000x of the copied bytes).  Valid only for the
 # assembly source they were taken on (sha256 prefix below); reported as null otherwise.
-TRAFFIC = {"source_sha256": "61fb8672a5cae0c0",
-           "fetch_kib": 253823.1 + 460173.7, "fetch_scale": 262144.0 / 131087.2,
-           "write_kib": 7433397.2 + 424960.0, "write_scale": 262144.0 / 262144.0}
+TRAFFIC = {"source_sha256": "0e43edb9a61c2960",
+           "fetch_kib": 120610.6 + 460171.0, "fetch_scale": 262144.0 / 131087.2,
+           "write_kib": 5937060.0 + 424960.0, "write_scale": 262144.0 / 262144.0}
 
 
 def log(msg):
