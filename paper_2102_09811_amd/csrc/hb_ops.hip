@@ -490,6 +490,31 @@ __global__ __launch_bounds__(256) void k_arnoldi(double *__restrict__ H, int m, 
   if (threadIdx.x == 0) H[(size_t)(j + 1) * m + j] = 0.0;
 }
 
+// y = R^{-1} g for the first it columns of the rotated Hessenberg matrix (row-major, leading
+// dimension m): the upper triangle and g staged in LDS (it <= kBacksubMax), then column by column,
+// the updates of one column spread over the workgroup.
+constexpr int kBacksubMax = 88;  // (it^2 + 2 it) doubles stay within 64 KiB of LDS
+__global__ __launch_bounds__(256) void k_backsub(const double *__restrict__ R, int m,
+                                                 const double *__restrict__ g, int it,
+                                                 double *__restrict__ y) {
+  extern __shared__ double sh[];
+  double *Rs = sh, *gs = sh + (size_t)it * it, *ys = gs + it;
+  for (int idx = threadIdx.x; idx < it * it; idx += blockDim.x) {
+    const int i = idx / it, k = idx % it;
+    Rs[idx] = k >= i ? R[(size_t)i * m + k] : 0.0;
+  }
+  for (int i = threadIdx.x; i < it; i += blockDim.x) gs[i] = g[i];
+  __syncthreads();
+  for (int i = it - 1; i >= 0; --i) {
+    if (threadIdx.x == 0) ys[i] = gs[i] / Rs[(size_t)i * it + i];
+    __syncthreads();
+    const double yi = ys[i];
+    for (int r = threadIdx.x; r < i; r += blockDim.x) gs[r] -= Rs[(size_t)r * it + i] * yi;
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < it; i += blockDim.x) y[i] = ys[i];
+}
+
 __global__ void k_scale_dev(double *__restrict__ y, const double *__restrict__ a, size_t n) {
   const double f = *a;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -991,11 +1016,15 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
     return HB_OK;
   }
   hipLaunchKernelGGL(k_scale_copy, dim3(grid1d(n)), dim3(256), 0, s, b, 1.0 / beta, Q, n);
-  HB_CHECK(c, hipMemcpyAsync(dg, &beta, sizeof(double), hipMemcpyHostToDevice, s));
-  HB_CHECK(c, hipStreamSynchronize(s));  // beta is read from the host stack above
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, dg, (size_t)1, beta);
   int it = 0;
   bool conv = false;
   auto converged = [&](int jj) { return c->h_res[jj] <= tol; };
+  // the estimate after step jj + 1 extrapolated from steps jj - 1 and jj is within twice tol
+  auto near_tol = [&](int jj) {
+    const double r0 = c->h_res[jj - 1], r1 = c->h_res[jj];
+    return r0 > 0.0 && r1 * (r1 / r0) <= 2.0 * tol;
+  };
   for (int j = 0; j < m; ++j) {
     double *wj = Q + (size_t)(j + 1) * n;
     if (precond) {
@@ -1023,6 +1052,16 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
         conv = true;
         break;
       }
+      // step j may be the last: wait for it before queueing another one, which would otherwise
+      // be computed for nothing
+      if (j >= 2 && near_tol(j - 1)) {
+        HB_CHECK(c, hipEventSynchronize(c->ev_step));
+        if (converged(j)) {
+          it = j + 1;
+          conv = true;
+          break;
+        }
+      }
     }
     std::swap(c->ev_step, c->ev_prev);
     it = j + 1;
@@ -1032,19 +1071,24 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
     conv = it > 0 && converged(it - 1);
   }
   // y = R^{-1} g over the first it columns, x = (P) Q y
-  std::vector<double> R((size_t)it * m), gh(it), y(it);
-  HB_CHECK(c, hipStreamSynchronize(s));
-  if (it > 0) {
+  double *coef = dres;  // no longer needed
+  std::vector<double> y;
+  if (it > kBacksubMax) {
+    std::vector<double> R((size_t)it * m), gh(it);
+    y.resize(it);
+    HB_CHECK(c, hipStreamSynchronize(s));
     HB_CHECK(c, hipMemcpy(R.data(), dH, sizeof(double) * (size_t)it * m, hipMemcpyDeviceToHost));
     HB_CHECK(c, hipMemcpy(gh.data(), dg, sizeof(double) * it, hipMemcpyDeviceToHost));
+    for (int i = it - 1; i >= 0; --i) {
+      double sacc = gh[i];
+      for (int k = i + 1; k < it; ++k) sacc -= R[(size_t)i * m + k] * y[k];
+      y[i] = sacc / R[(size_t)i * m + i];
+    }
+    HB_CHECK(c, hipMemcpyAsync(coef, y.data(), sizeof(double) * it, hipMemcpyHostToDevice, s));
+  } else if (it > 0) {
+    hipLaunchKernelGGL(k_backsub, dim3(1), dim3(256), sizeof(double) * ((size_t)it * it + 2 * it), s,
+                       dH, m, dg, it, coef);
   }
-  for (int i = it - 1; i >= 0; --i) {
-    double sacc = gh[i];
-    for (int k = i + 1; k < it; ++k) sacc -= R[(size_t)i * m + k] * y[k];
-    y[i] = sacc / R[(size_t)i * m + i];
-  }
-  double *coef = dres;  // no longer needed
-  HB_CHECK(c, hipMemcpyAsync(coef, y.data(), sizeof(double) * it, hipMemcpyHostToDevice, s));
   if (precond) {
     hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, s, Q, n, coef, it, r, n);
     if ((rc = pc_apply(c, precond, r, x, s))) return rc;
@@ -1052,7 +1096,7 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
     hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, s, Q, n, coef, it, x, n);
   }
   HB_CHECK(c, hipGetLastError());
-  HB_CHECK(c, hipStreamSynchronize(s));  // y lives on the host stack
+  if (!y.empty()) HB_CHECK(c, hipStreamSynchronize(s));  // the host copy of y is read until here
   if (info) info->iterations = it;
   return conv ? HB_OK : HB_ENOCONV;
 }
