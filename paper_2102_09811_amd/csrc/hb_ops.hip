@@ -978,8 +978,9 @@ int pc_apply(hb_ctx *c, int kind, const double *q, double *z, hipStream_t s) {
 // rotations, residual estimate) stays on the device; the host learns each step's residual
 // estimate one step late through pinned memory while the next step is already queued, so the GPU
 // never waits for the host (a converged solve computes one surplus step, which is discarded).
+// bnorm: ||b|| when the caller has it (computed as here: the dot kernels, then sqrt), else < 0
 int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, hipStream_t s,
-          hb_solve_info *info, int precond = 0) {
+          hb_solve_info *info, int precond = 0, double bnorm = -1.0) {
   const size_t n = (size_t)c->nt * (op == 2 ? c->nv : c->ne);
   const int m = maxit;
   const int nchunk = (int)((n + kDotChunk - 1) / kDotChunk);
@@ -1004,8 +1005,8 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
   HB_CHECK(c, hipHostGetDevicePointer((void **)&res_dev, c->h_res, 0));
   if (!c->ev_step) HB_CHECK(c, hipEventCreateWithFlags(&c->ev_step, hipEventDisableTiming));
   if (!c->ev_prev) HB_CHECK(c, hipEventCreateWithFlags(&c->ev_prev, hipEventDisableTiming));
-  double beta;
-  {
+  double beta = bnorm;
+  if (beta < 0.0) {
     std::vector<double> tmp(1);
     if ((rc = multi_dot(c, b, 0, 1, b, n, p1, dres, tmp.data(), s))) return rc;
     beta = std::sqrt(tmp[0]);
@@ -1183,14 +1184,14 @@ int mixed_ir(hb_ctx *c, const double *b, double *x, double tol, int maxit, hipSt
       if ((rc = apply_V(c, 0, x, r, s))) return rc;
       hipLaunchKernelGGL(k_axpby, dim3(grid1d(n)), dim3(256), 0, s, 1.0, b, -1.0, r, n);
     }
-    double rn;
-    if ((rc = norm(r, &rn))) return rc;
+    double rn = bn;  // r = b while x = 0
+    if (outer > 0 && (rc = norm(r, &rn))) return rc;
     if (rn <= tol * bn) {
       conv = true;
       break;
     }
     hb_solve_info in{};
-    rc = gmres(c, 1, r, dlt, inner_tol, maxit, s, &in, precond);
+    rc = gmres(c, 1, r, dlt, inner_tol, maxit, s, &in, precond, rn);
     if (rc != HB_OK && rc != HB_ENOCONV) return rc;
     total_it += in.iterations;
     hipLaunchKernelGGL(k_axpby, dim3(grid1d(n)), dim3(256), 0, s, 1.0, dlt, 1.0, x, n);
