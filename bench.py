@@ -90,6 +90,45 @@ def assembly_only(args):
     return 0
 
 
+def apply_only(args):
+    """Counter runs of the block-Toeplitz products of the benchmarked workload: 1 + 10 products with
+    the double V_h blocks, 1 + 10 with K_h, 1 + 10 with the V_h blocks in float storage (the kernel
+    of the mixed solve's inner products), then the 256 MiB calibration copy."""
+    import torch
+    from paper_2102_09811_amd import HB_DTYPE_F32, HB_OP_K, HB_OP_V, Context
+    from synthetic import icosphere
+    verts, tris = icosphere(3)
+    ne, nv, nt = len(tris), len(verts), 64
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(nt, ne, dtype=torch.float64, device="cuda", generator=gen)
+    xg = torch.randn(nt, nv, dtype=torch.float64, device="cuda", generator=gen)
+    y = torch.empty_like(x)
+    for storage in (None, HB_DTYPE_F32):
+        ctx = Context(verts, tris, 1.0, 1.0, nt) if storage is None else \
+            Context(verts, tris, 1.0, 1.0, nt, storage=storage)
+        ctx.assemble(HB_OP_V | HB_OP_K)
+        ops = ((HB_OP_V, x), (HB_OP_K, xg)) if storage is None else ((HB_OP_V, x),)
+        for op, xx in ops:
+            ctx.apply(op, xx, y)  # first call allocates the partial sums
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                ctx.apply(op, xx, y)
+            e1.record()
+            torch.cuda.synchronize()
+            log("apply %s %s: %.1f us per product" % ("V" if op == HB_OP_V else "K",
+                                                     "float" if storage else "double",
+                                                     e0.elapsed_time(e1) * 100.0))
+        ctx.close()
+    a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log("calibration copy: 256 MiB read, 256 MiB written")
+    return 0
+
+
 def cpu_baseline(verts, tris, alpha, T, n_t):
     """The oracle (long double, OpenMP over test rows) on a bounded sample of test rows."""
     import numpy as np
@@ -202,6 +241,8 @@ def main():
     ap.add_argument("--train-meshes", type=int, default=16)
     ap.add_argument("--assembly-only", action="store_true",
                     help="two assemblies and a 256 MiB calibration copy (for counter runs)")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="block-Toeplitz products and a 256 MiB calibration copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1",
@@ -210,6 +251,8 @@ def main():
 
     if args.assembly_only:
         return assembly_only(args)
+    if args.apply_only:
+        return apply_only(args)
 
     import numpy as np
     import torch
