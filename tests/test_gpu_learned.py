@@ -147,9 +147,13 @@ def test_learned_preconditioner_gain():
             m["seed"], len(t), alpha, ip["iterations"], 1e3 * ip["seconds"], il["iterations"],
             1e3 * il["seconds"], ie["iterations"]))
         assert il["converged"] and il["rel_residual"] <= 1e-8
+        # the plain runs pass 88 steps, where y = R^{-1} g is solved on the host instead of the
+        # device; the recomputed residual may exceed the GMRES estimate by rounding
+        assert ip["converged"] and ip["rel_residual"] <= 2e-8
         its_plain.append(ip["iterations"])
         its_learned.append(il["iterations"])
         its_exact.append(ie["iterations"])
         ctx.close()
         torch.cuda.empty_cache()
     assert np.mean(its_learned) <= 0.85 * np.mean(its_plain), (its_plain, its_learned)
+    assert max(its_plain) > 88 and min(its_learned) <= 88, (its_plain, its_learned)
