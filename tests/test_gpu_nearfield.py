@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synthetic import cube, icosphere
+from synthetic import cube, icosphere, octahedron
 
 pytestmark = pytest.mark.gpu
 
@@ -96,4 +96,34 @@ def test_nearfield_sphere_sampled():
     say("  sampled %d pairs: max e_V = %.2e, max e_K = %.2e (relative to each block's maximum)" %
         (len(sample), eV, eK))
     assert eV <= 1e-12 and eK <= 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("radius", [0.0, 1e6])
+def test_nearfield_degenerate_radii(radius):
+    """Radius 0: the pattern is the touching pairs alone (each panel with itself and its edge and
+    vertex neighbours); a radius beyond the mesh: every pair, and the near-field blocks are the
+    full assembly's V and K (the K parts scattered to the trial vertices)."""
+    import torch
+    from paper_2102_09811_amd import HB_OP_K, HB_OP_V, Context
+    v, t = octahedron()
+    nt = 7
+    ctx = Context(v, t, 0.8, 1.0, nt)
+    start, cols = ctx.nearfield_pattern(radius)
+    check_pattern(start, cols, brute_pattern(v, t, radius))
+    share = (t[:, None, :, None] == t[None, :, None, :]).any(axis=(2, 3))
+    assert len(cols) == (share.sum() if radius == 0.0 else len(t) ** 2)
+    Vn, Kn = ctx.assemble_nearfield()
+    Vn, Kn = Vn.cpu().numpy(), Kn.cpu().numpy()
+    ctx.assemble(HB_OP_V | HB_OP_K)
+    Vd = ctx.blocks(HB_OP_V).cpu().numpy()
+    Kd = ctx.blocks(HB_OP_K).cpu().numpy()
+    rows = np.repeat(np.arange(len(t)), np.diff(start))
+    assert np.abs(Vd[:, rows, cols] - Vn).max() <= 1e-13 * np.abs(Vd).max()
+    if radius > 0.0:
+        Ks = np.zeros_like(Kd)
+        for e in range(len(cols)):
+            for k in range(3):
+                Ks[:, rows[e], t[cols[e], k]] += Kn[:, e, k]
+        assert np.abs(Ks - Kd).max() <= 1e-13 * np.abs(Kd).max()
     ctx.close()
