@@ -657,6 +657,12 @@ __global__ __launch_bounds__(256, 2) void k_repr(const AsmParams *__restrict__ p
 
   const double c_al = 1.0 / (2.0 * sqrt(al));
   constexpr double kTwoInvSqrtPi = 1.1283791670955125739;
+  // z = rho cz[m] at the closed-form levels: the current interval (time distance eps) and the
+  // intervals m = 1 .. kReprClosed behind it (m h + eps); the same for every panel of the point
+  double cz[kReprClosed + 1];
+  cz[0] = eps > 0.0 ? c_al / sqrt(eps) : 0.0;
+#pragma unroll
+  for (int m = 1; m <= kReprClosed; ++m) cz[m] = c_al / sqrt(m * h + eps);
   double accs = 0.0, accd = 0.0;
   for (int j = threadIdx.x; j < ne; j += blockDim.x) {
     const double area = p.geom[24 * ne + j];
@@ -676,7 +682,7 @@ __global__ __launch_bounds__(256, 2) void k_repr(const AsmParams *__restrict__ p
       const double l0 = p.lam7[q][0], l1 = p.lam7[q][1], l2 = p.lam7[q][2];
       double sv = 0.0, sd = 0.0, ec_prev = 0.0, D_prev = 0.0;
       if (eps > 0.0) {
-        const double z = rho * c_al / sqrt(eps);
+        const double z = rho * cz[0];
         ec_prev = erfc(z);
         D_prev = ec_prev + kTwoInvSqrtPi * z * exp_neg(z * z);
         if (k < nt) {
@@ -686,8 +692,10 @@ __global__ __launch_bounds__(256, 2) void k_repr(const AsmParams *__restrict__ p
         }
       }
       const int mc = min(k, kReprClosed);
-      for (int m = 1; m <= mc; ++m) {
-        const double z = rho * c_al / sqrt(m * h + eps);
+#pragma unroll
+      for (int m = 1; m <= kReprClosed; ++m) {
+        if (m > mc) break;
+        const double z = rho * cz[m];
         const double ec = erfc(z);
         const double D = ec + kTwoInvSqrtPi * z * exp_neg(z * z);
         const int i = k - m;
@@ -697,8 +705,9 @@ __global__ __launch_bounds__(256, 2) void k_repr(const AsmParams *__restrict__ p
         ec_prev = ec;
         D_prev = D;
       }
-      accs = fma(Wq / rho, sv, accs);
-      accd = fma(Wq * rn[q] / (rho * r2[q]), sd, accd);
+      const double ir = 1.0 / rho;
+      accs = fma(Wq * ir, sv, accs);
+      accd = fma(Wq * rn[q] * (ir * ir * ir), sd, accd);
     }
     // Taylor form for m = 3 .. k, by degree class
     const int m0 = kReprClosed + 1;
