@@ -31,13 +31,15 @@ namespace {
 
 constexpr double kInv4Pi = 0.079577471545947667884;
 
-__device__ __forceinline__ double d2_closed(double rho, int d, double ah) {
+// z at level i is rho p.lv.c[i] (c[i] = 1 / (2 sqrt(alpha i h)), tabulated per context)
+static_assert(kD2Closed <= kMaxClosed, "the closed-form D^2 blocks read levels up to kD2Closed");
+__device__ __forceinline__ double d2_closed(const AsmParams &p, double rho, int d) {
   const double c = kInv4Pi / rho;
-  const double zp = 0.5 * rho / sqrt(ah * (d + 1));
+  const double zp = rho * p.lv.c[d + 1];
   if (d == 0) return erfc(zp) * c;
-  const double z0 = 0.5 * rho / sqrt(ah * d);
+  const double z0 = rho * p.lv.c[d];
   if (d == 1) return (erfc(zp) - 2.0 * erfc(z0)) * c;
-  const double zm = 0.5 * rho / sqrt(ah * (d - 1));
+  const double zm = rho * p.lv.c[d - 1];
   if (zm < 1.0) return -(erf(zp) - 2.0 * erf(z0) + erf(zm)) * c;
   return (erfc(zp) - 2.0 * erfc(z0) + erfc(zm)) * c;
 }
@@ -64,7 +66,7 @@ __device__ __forceinline__ double kern_value(const AsmParams &p, double rho2, in
                                              double cw, double sc, const double *__restrict__ tab,
                                              const double *etab) {
   if constexpr (N == 0) {
-    if constexpr (KIND == kKindD2) return d2_closed(sqrt(rho2), d, ah);
+    if constexpr (KIND == kKindD2) return d2_closed(p, sqrt(rho2), d);
     else return v_closed(p, sqrt(rho2), d);
   } else {
     const double w = rho2 * cw;
