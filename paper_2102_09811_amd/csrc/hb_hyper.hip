@@ -47,16 +47,18 @@ __device__ __forceinline__ double d2_closed(const AsmParams &p, double rho, int 
 constexpr int kKindV11 = 0, kKindD2 = 1;
 
 // rho A(z) at level i (G^{dtau dt}(rho, i h) = kV rho A(z))
-__device__ __forceinline__ double rA_level(const AsmParams &p, int i, double rho) {
+__device__ __forceinline__ double rA_level(const AsmParams &p, int i, double rho, double inv_rho) {
   double rA, kB;
-  level_terms(p, i, rho, 1.0 / rho, rA, kB);
+  level_terms(p, i, rho, inv_rho, rA, kB);
   return rA;
 }
 
 // V^d(rho) in closed form (Sec. 3.1, eq. for V^0 and the second difference for V^d)
 __device__ __forceinline__ double v_closed(const AsmParams &p, double rho, int d) {
-  if (d == 0) return p.kVs / rho - p.kV * (rA_level(p, 1, rho) - rho);
-  return p.kV * (2.0 * rA_level(p, d, rho) - rA_level(p, d + 1, rho) - rA_level(p, d - 1, rho));
+  const double ir = 1.0 / rho;
+  if (d == 0) return p.kVs * ir - p.kV * (rA_level(p, 1, rho, ir) - rho);
+  return p.kV * (2.0 * rA_level(p, d, rho, ir) - rA_level(p, d + 1, rho, ir) -
+                 rA_level(p, d - 1, rho, ir));
 }
 
 // Kernel value at rho^2 for block d (N = 0: closed form; else the Taylor polynomial with N
