@@ -197,7 +197,8 @@ typedef struct hb_solve_info {
 
 /* Solve V_h w = b for w.  b, w: device pointers, E_t x E_x, float64.  info may be NULL.
  * Returns HB_ENOCONV (w then holds the last iterate) when GMRES hits max_iter first.  All
- * methods use the block-Toeplitz product, so E_t <= 256. */
+ * methods use the block-Toeplitz product, so E_t <= 256.  The call returns once w and the
+ * residual check are complete on `stream` (it synchronizes with the stream). */
 int hb_solve(hb_ctx *ctx, const double *b, double *w, const hb_solve_opts *opts,
              hb_solve_info *info, void *stream);
 
@@ -207,7 +208,7 @@ int hb_solve(hb_ctx *ctx, const double *b, double *w, const hb_solve_opts *opts,
  * the operator preconditioner M_h^{-1} V_h^{11} M_h^{-1} from the right (Sec. 6.1: V_h^{11} as its
  * essential part; M_h = h blockdiag(M), M the p1 mass matrix, inverted once per context), which
  * needs HB_OP_V11 assembled.  Needs HB_OP_D assembled (HB_ESTATE).  info->rel_residual is
- * ||b - D_h u|| / ||b||. */
+ * ||b - D_h u|| / ||b||.  Returns once u is complete on `stream`, as hb_solve. */
 int hb_solve_neumann(hb_ctx *ctx, const double *b, double *u, const hb_solve_opts *opts,
                      hb_solve_info *info, void *stream);
 
