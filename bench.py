@@ -146,6 +146,22 @@ def cpu_baseline(verts, tris, alpha, T, n_t):
                 len(rows), len(tris), n_t, dt)}
 
 
+def mixed_block_errors(ctx, mixed):
+    """Per-block error of the mixed-precision assembly against the double one, for every d and
+    for V_h and K_h: max |A_mixed^d - A^d| / max |A^d| (device; the blocks below the first float
+    block are double in both and equal)."""
+    from paper_2102_09811_amd import HB_OP_K, HB_OP_V
+    res = {}
+    for op, name in ((HB_OP_V, "V"), (HB_OP_K, "K")):
+        ref = ctx.blocks(op)
+        err = (mixed[op] - ref).abs().amax(dim=(1, 2)) / ref.abs().amax(dim=(1, 2))
+        e = err.cpu().tolist()
+        res["max_block_rel_err_" + name] = max(e)
+        res["block_rel_err_" + name] = [float("%.3g" % x) for x in e]
+        del ref
+    return res
+
+
 def compare_solvers(ctx, b, net):
     """Every solver on the same right-hand side, each to relative residual 1e-8 measured with the
     double operator; wall time of the whole call (median of 3)."""
@@ -366,7 +382,10 @@ def main():
         ms_mixed = ev0.elapsed_time(ev1)
         out["mixed_assembly"] = {"ms": ms_mixed, "units_per_s": units / (ms_mixed * 1e-3),
                                  "separated_kernel_ms": ctx.last_assembly_ms()[0]}
+        mixed = {op: ctx.blocks(op) for op in (HB_OP_V, HB_OP_K)}
         ctx.assemble(HB_OP_V | HB_OP_K)
+        out["mixed_assembly"].update(mixed_block_errors(ctx, mixed))
+        del mixed
         out["neumann"] = neumann_timings(ctx, stream)
         out["nearfield"] = nearfield_timings(ctx, stream)
     if not args.no_cpu_baseline:
