@@ -98,3 +98,33 @@ def test_separated_entries_against_brute_force():
     assert v2 < 1e-6 and k2 < 1e-5, errs
     assert v0 / v1 > 15 and k0 / k1 > 15, errs
     assert v1 / v2 > 30 and k1 / k2 > 30, errs
+
+
+def test_touching_entries_against_brute_force():
+    """Identical, edge- and vertex-sharing panels of the octahedron.  From block d = 2 on the time
+    integral stays away from s = 0, the integrand is smooth on the pair and the brute force above
+    converges; the oracle's regularised (Sauter-Schwab type) rules must approach it quickly as
+    their order grows (Gauss order 4, the production order, then 6 and 8).  Blocks 0 and 1 are
+    singular: there the rules must converge among themselves.  K of an identical (flat) pair
+    vanishes."""
+    from synthetic import octahedron
+    v, t = octahedron()
+    share = [len(set(t[0]) & set(t[m])) for m in range(len(t))]
+    Kscale = None
+    for name, m in (("edge", share.index(2)), ("vertex", share.index(1)), ("identical", 0)):
+        Vb, Kb = brute_blocks(v, t, 0, m, n_space=16)
+        Vb2, Kb2 = brute_blocks(v, t, 0, m, n_space=20)
+        assert np.abs(Vb2[2:] - Vb[2:]).max() <= 1e-13 * np.abs(Vb[2:]).max()
+        res = {so: oracle.pair_blocks(v, t, ALPHA, T, NT, 0, m, ss_order=so) for so in (4, 6, 8)}
+        eV = {so: np.abs(res[so][0][2:] - Vb2[2:]).max() / np.abs(Vb2[2:]).max() for so in res}
+        assert eV[4] < 1e-4 and eV[8] < 1e-9 and eV[4] / eV[8] > 1e3, (name, eV)
+        if name == "identical":
+            assert np.abs(res[4][1]).max() <= 1e-12 * Kscale
+        else:
+            Kscale = np.abs(Kb2).max() if Kscale is None else max(Kscale, np.abs(Kb2).max())
+            eK = {so: np.abs(res[so][1][2:] - Kb2[2:]).max() / np.abs(Kb2[2:]).max() for so in res}
+            assert eK[4] < 1e-3 and eK[8] < 1e-8 and eK[4] / eK[8] > 1e3, (name, eK)
+        # singular blocks 0, 1: the rules converge among themselves
+        V4, V6, V8 = (res[so][0][:2] for so in (4, 6, 8))
+        d46, d68 = np.abs(V4 - V8).max(), np.abs(V6 - V8).max()
+        assert d68 <= 1e-5 * np.abs(V8).max() and d68 < d46 / 5, (name, d46, d68)
