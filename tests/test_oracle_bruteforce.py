@@ -177,3 +177,54 @@ def test_p1p1_blocks_against_brute_force():
     for kind in ("V11", "D2"):
         e1, e2 = errs[(0.5, kind)], errs[(0.25, kind)]
         assert e1 < 1e-4 and e2 < 1e-5 and e1 / e2 > 8, errs
+
+
+def potentials_brute(v, t, w, u, pt, n_space=16):
+    """Single- and double-layer potentials (Sec. 3.5) at one point (x, t) off the surface for
+    piecewise constant-in-time densities: w (p0 in space) and u (p1 in space), by Gauss on every
+    panel and Gauss-Legendre in s = t - tau over each interval (the current one graded towards
+    s = 0, where G is smooth but steep)."""
+    lam, W = tri_rule(n_space)
+    g, gw = np.polynomial.legendre.leggauss(60)
+    seg = lambda a, b: (0.5 * (b - a) * (g + 1.0) + a, 0.5 * (b - a) * gw)  # noqa: E731
+    x, tt = pt[:3], pt[3]
+    sl = dl = 0.0
+    for i in range(NT):
+        a, b = i * H, min((i + 1) * H, tt)
+        if b <= a:
+            continue
+        lo, hi = tt - b, tt - a
+        pieces = [(lo, hi)] if lo > 0 else [(0.0, hi / 64), (hi / 64, hi / 8), (hi / 8, hi / 2),
+                                            (hi / 2, hi)]
+        s = np.concatenate([seg(*pc)[0] for pc in pieces])
+        ws = np.concatenate([seg(*pc)[1] for pc in pieces])
+        for l in range(len(t)):
+            Q = v[t[l]]
+            c = np.cross(Q[1] - Q[0], Q[2] - Q[0])
+            area, n = 0.5 * np.linalg.norm(c), c / np.linalg.norm(c)
+            r = x[None, :] - lam @ Q
+            G = heat_kernel(np.linalg.norm(r, axis=1)[:, None], s[None, :])
+            sl += w[i, l] * area * (W @ (G @ ws))
+            dl += area * np.sum(W * ((G / (2.0 * s[None, :])) @ ws) * (r @ n) * (lam @ u[i, t[l]]))
+    return sl, dl
+
+
+def test_potentials_against_brute_force():
+    """The oracle's potentials (closed-form time integrals) at points inside the octahedron, with
+    its collapsed Gauss rule in space, against the brute force above: they converge together as
+    the spatial order grows (order 16: below 1e-8 relative)."""
+    from synthetic import octahedron
+    v, t = octahedron()
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal((NT, len(t)))
+    u = rng.standard_normal((NT, len(v)))
+    pts = np.array([[0.1, -0.05, 0.2, 0.37], [-0.2, 0.1, 0.0, 0.9], [0.05, 0.05, -0.1, 0.5],
+                    [0.0, 0.2, 0.1, 1.0], [0.15, 0.0, 0.0, 0.1]])
+    ref = np.array([potentials_brute(v, t, w, u, p) for p in pts])
+    err = {}
+    for order in (8, 16):
+        sl, dl = oracle.repr_eval(v, t, ALPHA, T, NT, w, u, pts, rule_kind=1, rule_order=order)
+        err[order] = (np.abs(sl - ref[:, 0]).max() / np.abs(ref[:, 0]).max(),
+                      np.abs(dl - ref[:, 1]).max() / np.abs(ref[:, 1]).max())
+    assert err[16][0] < 1e-8 and err[16][1] < 1e-7, err
+    assert err[8][0] > 100 * err[16][0] and err[8][1] > 100 * err[16][1], err
