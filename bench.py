@@ -272,6 +272,7 @@ def main():
 
     import numpy as np
     import torch
+    from paper_2102_09811_amd import measure_peaks
     from paper_2102_09811_amd import (Context, HB_OP_K, HB_OP_V, HB_PREC_MIXED, HB_SOLVE_GMRES,
                                       HB_SOLVE_MIXED_IR, HB_SOLVE_TIMEMARCH, check_mesh, learned)
     from synthetic import ball_points, exp_solution, icosphere, nodal_samples, space_time_points
@@ -370,6 +371,11 @@ def main():
                      "algorithmic_flops_per_launch": flops,
                      "frac_unordered_pairs": 0.5 * achieved / (PEAK_FP64_VALU / 1e12)},
     }
+    # the chip's vector-ALU ceilings measured on this device (microbenchmarks of the library): the
+    # roofline above is quoted against the published FP64 figure, these check it
+    out["alu_peaks_measured"] = measure_peaks()
+    log("measured peaks: FP64 FMA %(fp64_fma_tflops).1f TFLOP/s, v_rsq_f64 %(fp64_rsq_gops).0f G/s, "
+        "FP32 FMA (no packed FP32) %(fp32_fma_tflops).1f TFLOP/s" % out["alu_peaks_measured"])
     if not args.no_compare:
         log("solver comparison")
         out["solve_comparison"] = compare_solvers(ctx, b, net)

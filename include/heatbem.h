@@ -284,6 +284,15 @@ int hb_adam_step(float *params, const float *grads, float *m, float *v, int64_t 
  * [2] whole call.  Calls hipEventSynchronize. */
 int hb_last_assembly_ms(hb_ctx *ctx, double ms[3]);
 
+/* Throughput of the vector ALU of the current device: microbenchmarks, not part of the method;
+ * the ceilings the assembly and potential kernels are measured against.  out[0]: FP64 FMA rate
+ * in TFLOP/s; out[1]: v_rsq_f64 rate in G/s (each step one v_rsq_f64 on the transcendental path,
+ * which the square roots and reciprocals of the kernels use, and one v_add_f64); out[2]: FP32 FMA rate in TFLOP/s as this library is built
+ * (without packed FP32 instructions).  Independent FMA or rsq chains in 4096 x 256 threads, the
+ * best of five runs on `stream`, a few milliseconds each.  Allocates and frees 8 MiB of device
+ * memory and synchronizes.  HB_EINVAL for out == NULL, HB_ENOMEM, HB_EHIP. */
+int hb_measure_peaks(double out[3], void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,7 @@ EXPORTED = sorted(["hb_default_options", "hb_check_mesh", "hb_create", "hb_destr
                    "hb_last_error", "hb_sizes", "hb_assemble", "hb_get_blocks", "hb_apply",
                    "hb_rhs_dirichlet", "hb_rhs_neumann", "hb_solve", "hb_solve_neumann",
                    "hb_nearfield_pattern", "hb_assemble_nearfield",
-                   "hb_eval_repr", "hb_last_assembly_ms",
+                   "hb_eval_repr", "hb_last_assembly_ms", "hb_measure_peaks",
                    "hb_precond_pattern", "hb_precond_features", "hb_precond_spai",
                    "hb_precond_set", "hb_mlp_num_params", "hb_mlp_work_floats", "hb_mlp_forward",
                    "hb_mlp_backward", "hb_precond_loss", "hb_adam_step"])
@@ -90,6 +90,7 @@ def lib():
     L.hb_solve_neumann.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     L.hb_eval_repr.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
     L.hb_last_assembly_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.hb_measure_peaks.argtypes = [ctypes.POINTER(ctypes.c_double), vp]
     L.hb_precond_pattern.argtypes = [vp, vp, vp, vp]
     L.hb_precond_features.argtypes = [vp, vp, vp]
     L.hb_precond_spai.argtypes = [vp, vp, vp, vp, vp]
@@ -118,6 +119,16 @@ def default_options(**kw):
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+def measure_peaks(stream=None):
+    """Measured vector-ALU ceilings of the current device (hb_measure_peaks): FP64 FMA TFLOP/s,
+    v_rsq_f64 G/s, FP32 FMA TFLOP/s as the library is built."""
+    out = (ctypes.c_double * 3)()
+    rc = lib().hb_measure_peaks(out, _stream(stream))
+    if rc != HB_OK:
+        raise HBError(rc, "hb_measure_peaks failed")
+    return {"fp64_fma_tflops": out[0], "fp64_rsq_gops": out[1], "fp32_fma_tflops": out[2]}
 
 
 def _mesh_arrays(verts, tris):

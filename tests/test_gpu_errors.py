@@ -119,3 +119,14 @@ def test_neumann_call_order_and_arguments(torch):
     u, info = ctx.solve_neumann(b)       # zero right-hand side: zero solution, no iterations
     assert info["converged"] and float(u.abs().max()) == 0.0
     ctx.close()
+
+
+def test_measure_peaks(torch):
+    """The vector-ALU microbenchmarks return rates of the right order: at most the published
+    MI355X figures (FP64 78.6, FP32 157.3 TFLOP/s) plus measurement slack, and clearly nonzero."""
+    from paper_2102_09811_amd import measure_peaks
+    p = measure_peaks()
+    print("[gpu-test] measured peaks: %s" % p, flush=True)
+    assert 10.0 < p["fp64_fma_tflops"] < 1.1 * 78.6
+    assert 10.0 < p["fp32_fma_tflops"] < 1.1 * 157.3
+    assert 100.0 < p["fp64_rsq_gops"] < 1.1 * 78.6e3 / 2
