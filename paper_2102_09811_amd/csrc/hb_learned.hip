@@ -370,27 +370,30 @@ __global__ void k_install(const TV *__restrict__ V0, const float *__restrict__ y
 
 }  // namespace
 
-// z[k][l] = sum_s M[l][s] q[k][cols[l][s]] for every time step k
-__global__ void k_precond_apply(const double *__restrict__ M, const int32_t *__restrict__ cols,
-                                const double *__restrict__ q, double *__restrict__ z, int nt,
-                                int ne) {
+// z[k][l] = sum_s M[l][s] q[k][cols[l][s]] for every time step k: one lane per slot s (a gather
+// each, all in flight together), summed over the HB_PC_SLOTS lanes of (k, l) by a butterfly
+static_assert(HB_PC_SLOTS == 16, "the butterfly below sums 16 lanes");
+__global__ __launch_bounds__(256) void k_precond_apply(const double *__restrict__ M,
+                                                       const int32_t *__restrict__ cols,
+                                                       const double *__restrict__ q,
+                                                       double *__restrict__ z, int nt, int ne) {
   const size_t n = (size_t)nt * ne;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+  const int slot = threadIdx.x & (HB_PC_SLOTS - 1);
+  const size_t stride = (size_t)gridDim.x * blockDim.x / HB_PC_SLOTS;
+  // the loop bound is the same for the 16 lanes of a group, so each butterfly has all of them
+  for (size_t i = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) / HB_PC_SLOTS; i < n; i += stride) {
     const int k = (int)(i / ne), l = (int)(i % ne);
-    const double *qk = q + (size_t)k * ne;
-    double s = 0.0;
+    const int m = cols[l * HB_PC_SLOTS + slot];
+    double v = m >= 0 ? M[l * HB_PC_SLOTS + slot] * q[(size_t)k * ne + m] : 0.0;
 #pragma unroll
-    for (int t = 0; t < HB_PC_SLOTS; ++t) {
-      const int m = cols[l * HB_PC_SLOTS + t];
-      if (m >= 0) s = fma(M[l * HB_PC_SLOTS + t], qk[m], s);
-    }
-    z[i] = s;
+    for (int o = HB_PC_SLOTS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, HB_PC_SLOTS);
+    if (slot == 0) z[i] = v;
   }
 }
 
 int precond_apply(hb_ctx *c, const double *q, double *z, hipStream_t s) {
   const size_t n = (size_t)c->nt * c->ne;
-  hipLaunchKernelGGL(k_precond_apply, dim3(grid_for(n)), dim3(256), 0, s, c->d_pc_M, c->d_pc_cols,
+  hipLaunchKernelGGL(k_precond_apply, dim3(grid_for(n * HB_PC_SLOTS)), dim3(256), 0, s, c->d_pc_M, c->d_pc_cols,
                      q, z, c->nt, (int)c->ne);
   HB_CHECK_L(c, hipGetLastError());
   return HB_OK;
