@@ -986,7 +986,8 @@ int pc_apply(hb_ctx *c, int kind, const double *q, double *z, hipStream_t s) {
 // classical Gram-Schmidt applied twice.  The Arnoldi recurrence (Hessenberg column, Givens
 // rotations, residual estimate) stays on the device; the host learns each step's residual
 // estimate one step late through pinned memory while the next step is already queued, so the GPU
-// never waits for the host (a converged solve computes one surplus step, which is discarded).
+// never waits for the host; when the estimate extrapolated from the last two steps says that the
+// step in flight may be the last, the host waits for it instead of queueing a surplus step.
 // bnorm: ||b|| when the caller has it (computed as here: the dot kernels, then sqrt), else < 0
 int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, hipStream_t s,
           hb_solve_info *info, int precond = 0, double bnorm = -1.0) {
