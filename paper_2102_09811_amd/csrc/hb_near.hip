@@ -94,6 +94,39 @@ __device__ __forceinline__ void near_touch_block(const AsmParams &p, const Touch
   }
 }
 
+// Taylor blocks d and d + 1 of one pass (the same polynomial length N) in one sweep over the rule
+// points, sharing the geometry, the weights and the basis values
+template <int N>
+__device__ __forceinline__ void near_touch_block2(const AsmParams &p, const TouchPair &tp,
+                                                  const double *__restrict__ tab, int ntab,
+                                                  int lane, int d, const double *tscale,
+                                                  const double *taylor, const double *etab,
+                                                  double (&V)[2], double (&K)[2][3]) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b) V[b] = K[b][0] = K[b][1] = K[b][2] = 0.0;
+#pragma unroll 1
+  for (int q = lane; q < ntab; q += 64) {
+    const double a1 = tab[q], a2 = tab[ntab + q], a3 = tab[2 * ntab + q], a4 = tab[3 * ntab + q];
+    const double rx = a1 * tp.E1[0] + a2 * tp.E2[0] + a3 * tp.F1[0] + a4 * tp.F2[0];
+    const double ry = a1 * tp.E1[1] + a2 * tp.E2[1] + a3 * tp.F1[1] + a4 * tp.F2[1];
+    const double rz = a1 * tp.E1[2] + a2 * tp.E2[2] + a3 * tp.F1[2] + a4 * tp.F2[2];
+    const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
+    const double W = tab[4 * ntab + q];
+    const double rn = fma(rx, tp.n[0], fma(ry, tp.n[1], rz * tp.n[2]));
+    const double b0 = tab[5 * ntab + q], b1 = tab[6 * ntab + q], b2 = tab[7 * ntab + q];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      double v, krn;
+      vk_value<N>(p, rho2, d + b, tscale, taylor, etab, v, krn);
+      V[b] = fma(W, v, V[b]);
+      const double u = W * krn * rn;
+      K[b][0] = fma(u, b0, K[b][0]);
+      K[b][1] = fma(u, b1, K[b][1]);
+      K[b][2] = fma(u, b2, K[b][2]);
+    }
+  }
+}
+
 // Block d dispatched to the Taylor length of its table (0: closed form)
 #define HB_NEAR_DISPATCH(CALL)                                  \
   switch (d < p.dsw ? 0 : tdeg[2 * d] + 1) {                    \
@@ -166,7 +199,32 @@ __global__ __launch_bounds__(64) void k_near_touching(const AsmParams *__restric
   const int cls = __builtin_amdgcn_readfirstlane(tp.cls);
   const double *__restrict__ tab = rules.d[cls];
   const int ntab = rules.n[cls], lane = threadIdx.x;
-  for (int d = 0; d < p.nt; ++d) {
+  for (int d = 0; d < p.nt;) {
+    if (d >= p.dsw && d + 1 < p.nt) {
+      // Taylor blocks d, d + 1 (d - dsw even: one pass, one polynomial length)
+      double V[2], K[2][3];
+#define HB_CALL(N_) near_touch_block2<N_>(p, tp, tab, ntab, lane, d, tscale, taylor, etab, V, K)
+      HB_NEAR_DISPATCH(HB_CALL)
+#undef HB_CALL
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        V[b] = wsum(V[b]);
+        K[b][0] = wsum(K[b][0]);
+        K[b][1] = wsum(K[b][1]);
+        K[b][2] = wsum(K[b][2]);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const size_t o = (size_t)(d + b) * nnz + ent;
+          Vn[o] = V[b] * tp.scale;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) Kn[3 * o + t[2 + j]] = K[b][j] * tp.scale;
+        }
+      }
+      d += 2;
+      continue;
+    }
     double V, K[3];
 #define HB_CALL(N_) near_touch_block<N_>(p, tp, tab, ntab, lane, d, tscale, taylor, etab, V, K)
     HB_NEAR_DISPATCH(HB_CALL)
@@ -181,6 +239,7 @@ __global__ __launch_bounds__(64) void k_near_touching(const AsmParams *__restric
 #pragma unroll
       for (int j = 0; j < 3; ++j) Kn[3 * o + t[2 + j]] = K[j] * tp.scale;
     }
+    ++d;
   }
 }
 
