@@ -129,21 +129,41 @@ def apply_only(args):
     return 0
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(verts, tris, alpha, T, n_t):
-    """The oracle (long double, OpenMP over test rows) on a bounded sample of test rows."""
+    """The oracle's plain double-precision mode -- the method as the paper runs it on a CPU
+    (level order, one erf and one exp per point and level, OpenMP dynamic over test rows) -- on
+    bounded samples of test rows of the same workload: 16 rows on 1 thread, then 32 rows per
+    thread on every thread of the host share."""
     import numpy as np
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    rows = np.linspace(0, len(tris) - 1, 4 * threads).astype(np.int32)
-    oracle.assemble(verts, tris, alpha, T, n_t, rows=rows[:1])  # load / warm
-    t0 = time.perf_counter()
-    oracle.assemble(verts, tris, alpha, T, n_t, rows=rows)
-    dt = time.perf_counter() - t0
-    units = len(rows) * len(tris) * n_t
-    return {"value": units / dt, "unit": "pair-block integrals/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d test rows x %d trial panels x %d blocks, V and K, %.1f s" % (
-                len(rows), len(tris), n_t, dt)}
+    ne = len(tris)
+    oracle.assemble_plain(verts, tris, alpha, T, n_t, rows=np.array([0], np.int32), threads=1)
+    res = {}
+    for nth, nrows in ((1, 16), (threads, min(32 * threads, ne))):
+        rows = np.linspace(0, ne - 1, nrows).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.assemble_plain(verts, tris, alpha, T, n_t, rows=rows, threads=nth)
+        dt = time.perf_counter() - t0
+        res[nth] = (nrows * ne * n_t / dt, nrows, dt)
+        log("cpu baseline: %d thread(s), %d rows, %.1f s, %.3g units/s" % (nth, nrows, dt, res[nth][0]))
+    v1, vn = res[1], res[threads]
+    return {"value": vn[0], "unit": "pair-block integrals/s", "cores": threads,
+            "kind": "oracle", "mode": "plain double, the paper's level order (V and K fused)",
+            "value_1_thread": v1[0], "nproc": os.cpu_count(), "cpu": _cpu_model(),
+            "sample": "%d test rows x %d trial panels x %d blocks on %d threads (%.1f s); "
+                      "%d rows on 1 thread (%.1f s)" % (vn[1], ne, n_t, threads, vn[2], v1[1], v1[2])}
 
 
 def mixed_block_errors(ctx, mixed):

@@ -43,6 +43,8 @@ def lib():
         L.or_pair_blocks.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, i32, i32, _dp, _dp]
         L.or_assemble.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, _ip, i32, i32, i32,
                                   _dp, _dp]
+        L.or_assemble_plain.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, _ip, i32, i32,
+                                        _dp, _dp]
         L.or_repr.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, _dp, _dp, _dp, i32, i32, i32,
                               _dp, _dp]
         _lib = L
@@ -131,6 +133,23 @@ def assemble(verts, tris, alpha, T, n_t, rows=None, ss_order=4, method="direct",
                            V, K)
     if rc != 0:
         raise ValueError("or_assemble failed (%d)" % rc)
+    return V, K
+
+
+def assemble_plain(verts, tris, alpha, T, n_t, rows=None, ss_order=4, threads=0):
+    """The method as the paper runs it on a CPU (Sec. 5.1): double precision, level order,
+    OpenMP over test rows (threads > 0 fixes the team size).  The timed CPU baseline; its blocks
+    at large d carry the rounding of the second differences, so it is not a parity reference.
+    Same shapes as assemble()."""
+    verts, tris = _f64(verts), _i32(tris)
+    ne, nv = len(tris), len(verts)
+    rows = _i32(np.arange(ne) if rows is None else rows)
+    V = np.empty((n_t, len(rows), ne))
+    K = np.empty((n_t, len(rows), nv))
+    rc = lib().or_assemble_plain(verts.ravel(), nv, tris.ravel(), ne, float(alpha), float(T), n_t,
+                                 ss_order, rows, len(rows), int(threads), V, K)
+    if rc != 0:
+        raise ValueError("or_assemble_plain failed (%d)" % rc)
     return V, K
 
 

@@ -24,6 +24,8 @@
  *   - the second part D^{2,d}(r) of the hypersingular operator and its Galerkin blocks
  *     (p1 x p1 with n(x) . n(y))                                     (Sec. 3.3, eq. for D^{2,d})
  *   - the single layer between p1 functions, V_h^{11}                (Sec. 6.1, preconditioner of D_h)
+ *   - a plain double-precision assembly in the paper's level order, the timed CPU baseline
+ *     (Sec. 5.1; not a parity reference)
  *
  * Readings where the paper is silent (each is also listed in the design notes):
  *   - Small-argument series for the double-layer bracket (it cancels like 1/z^2 when
@@ -37,6 +39,7 @@
  *     at every level.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -672,6 +675,151 @@ int or_assemble(const double *verts, int nv, const int32_t *tris, int ne, double
   for (size_t i = 0; i < (size_t)nt * nrows * ne; ++i) V[i] = (double)VL[i];
   for (size_t i = 0; i < (size_t)nt * nrows * nv; ++i) K[i] = (double)KL[i];
   free(VL); free(KL);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Plain double-precision assembly in the paper's order (Sec. 5.1, the listing of the assembly  */
+/* structure; Tables 5.1/5.2): for each level i_t = 0 .. n_t, the test rows (OpenMP, dynamic),  */
+/* for each trial panel the kernel G^{dtau dt}(r, i_t h) and its normal derivative at every      */
+/* quadrature point in double, summed with the weights and added to blocks i_t - 1, i_t,         */
+/* i_t + 1 with the multipliers -1, 2, -1 (block 0 at level 0 with 1, plus the h G^{dtau}(r, 0)  */
+/* terms of V^0 and K^0).  No long double and no hat quadrature: this is the method as the paper */
+/* runs it, the CPU baseline that is timed, not the parity reference (its second differences    */
+/* lose digits as d grows).  The small-z series of the double-layer bracket is kept, since the   */
+/* closed form is 0/0 there.  nthreads > 0 fixes the OpenMP team size.                          */
+/* ------------------------------------------------------------------------------------------ */
+static const double PI_D = 3.14159265358979323846;
+
+static int shares_vertex(const int32_t *ta, const int32_t *tb) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (ta[i] == tb[j]) return 1;
+  return 0;
+}
+
+/* G^{dtau dt}(rho, delta) (out[0]) and alpha dG^{dtau dt}/dn_y / (r . n_y) (out[1]) in double,
+ * sharing one erf and one exp (formula summary, Sec. 4); limits at delta = 0 */
+static void f64_F_Fn(double rho, double delta, double alpha, double out[2]) {
+  if (delta <= 0.0) {
+    out[0] = rho / (8.0 * PI_D * alpha * alpha);
+    out[1] = -1.0 / (8.0 * PI_D * alpha * rho);
+    return;
+  }
+  const double z = rho / (2.0 * sqrt(alpha * delta));
+  const double ez = erf(z), gz = exp(-z * z);
+  out[0] = ((rho / (2.0 * alpha * alpha) + delta / (alpha * rho)) * ez +
+            sqrt(delta / (PI_D * alpha * alpha * alpha)) * gz) / (4.0 * PI_D);
+  if (z < 0.5) { /* the series of B(z), the closed form being 0/0 there */
+    double z2 = z * z, term = z, sum = 0.0;
+    for (int n = 0; n < 14; ++n) {
+      sum += term / ((double)(2 * n + 1) * (double)(2 * n + 3));
+      term *= -z2 / (double)(n + 1);
+    }
+    out[1] = -(4.0 / sqrt(PI_D)) * sum / (8.0 * PI_D * alpha * rho);
+  } else {
+    out[1] = -((1.0 / (2.0 * alpha) - delta / (rho * rho)) * ez +
+               sqrt(delta) / (rho * sqrt(PI_D * alpha)) * gz) / (4.0 * PI_D * rho);
+  }
+}
+
+int or_assemble_plain(const double *verts, int nv, const int32_t *tris, int ne, double alpha,
+                      double T, int nt, int ss_order, const int32_t *rows, int nrows, int nthreads,
+                      double *V, double *K) {
+  if (nt < 1 || ne < 1 || nv < 3 || alpha <= 0 || T <= 0) return -1;
+  prepare_rules(ss_order);
+  memset(V, 0, sizeof(double) * (size_t)nt * nrows * ne);
+  memset(K, 0, sizeof(double) * (size_t)nt * nrows * nv);
+  const double h = T / nt;
+  const int np = max_points(ss_order);
+  double r7[7][3], w7[7];
+  for (int i = 0; i < 7; ++i) {
+    w7[i] = (double)g_w7[i];
+    for (int k = 0; k < 3; ++k) r7[i][k] = (double)g_r7[i][k];
+  }
+  double *area = (double *)malloc(sizeof(double) * ne);
+  for (int m = 0; m < ne; ++m) {
+    tri_t A;
+    make_tri(verts, tris + 3 * m, &A);
+    area[m] = (double)A.area;
+  }
+  /* the quadrature points of every pair are formed per level, as the listing does per pair */
+  for (int it = 0; it <= nt; ++it) {
+    const double delta = it * h;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+    {
+      qpt_t *q = (qpt_t *)malloc(sizeof(qpt_t) * np);
+      double *x = (double *)malloc(sizeof(double) * 11 * np);
+      tri_t B;
+#pragma omp for schedule(dynamic)
+      for (int r = 0; r < nrows; ++r) {
+        for (int m = 0; m < ne; ++m) {
+          make_tri(verts, tris + 3 * m, &B);
+          const double nb[3] = {(double)B.n[0], (double)B.n[1], (double)B.n[2]};
+          int n;
+          if (!shares_vertex(tris + 3 * rows[r], tris + 3 * m)) {
+            /* separated pair: the 7-point rule on both panels, mapped in double (Sec. 5.2) */
+            n = 49;
+            for (int i = 0; i < 7; ++i)
+              for (int j = 0; j < 7; ++j) {
+                const int e = 7 * i + j;
+                for (int c = 0; c < 3; ++c) {
+                  double xc = 0.0, yc = 0.0;
+                  for (int k = 0; k < 3; ++k) {
+                    xc += r7[i][k] * verts[3 * tris[3 * rows[r] + k] + c];
+                    yc += r7[j][k] * verts[3 * tris[3 * m + k] + c];
+                  }
+                  x[c * np + e] = xc - yc;
+                }
+                x[3 * np + e] = w7[i] * w7[j] * area[rows[r]] * area[m];
+                for (int k = 0; k < 3; ++k) x[(4 + k) * np + e] = r7[j][k];
+              }
+          } else {
+            n = pair_points(verts, tris, rows[r], m, q);
+            for (int i = 0; i < n; ++i) { /* structure of arrays in double */
+              for (int c = 0; c < 3; ++c) x[c * np + i] = (double)(q[i].x[c] - q[i].y[c]);
+              x[3 * np + i] = (double)q[i].W;
+              for (int k = 0; k < 3; ++k) x[(4 + k) * np + i] = (double)q[i].phi[k];
+            }
+          }
+          double val = 0.0, vs = 0.0, kval[3] = {0, 0, 0}, ks[3] = {0, 0, 0};
+          for (int i = 0; i < n; ++i) {
+            const double r0 = x[i], r1 = x[np + i], r2 = x[2 * np + i], W = x[3 * np + i];
+            const double rho = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+            const double rn = r0 * nb[0] + r1 * nb[1] + r2 * nb[2];
+            double f[2];
+            f64_F_Fn(rho, delta, alpha, f);
+            val += W * f[0];
+            const double kv = W * rn * f[1];
+            for (int k = 0; k < 3; ++k) kval[k] += kv * x[(4 + k) * np + i];
+            if (it == 0) {
+              vs += W * h / (4.0 * PI_D * alpha * rho);
+              const double ksv = W * rn * h / (4.0 * PI_D * rho * rho * rho);
+              for (int k = 0; k < 3; ++k) ks[k] += ksv * x[(4 + k) * np + i];
+            }
+          }
+          /* multipliers of Tables 5.1 / 5.2 */
+          for (int tgt = 0; tgt < 3; ++tgt) {
+            int d;
+            double coef;
+            if (tgt == 0) { if (it == 0) { d = 0; coef = 1.0; } else { d = it - 1; coef = -1.0; } }
+            else if (tgt == 1) { if (it == 0 || it >= nt) continue; d = it; coef = 2.0; }
+            else { if (it >= nt - 1) continue; d = it + 1; coef = -1.0; }
+            V[((size_t)d * nrows + r) * ne + m] += coef * val;
+            for (int k = 0; k < 3; ++k)
+              K[((size_t)d * nrows + r) * nv + tris[3 * m + k]] += coef * kval[k];
+          }
+          if (it == 0) {
+            V[(size_t)r * ne + m] += vs;
+            for (int k = 0; k < 3; ++k) K[(size_t)r * nv + tris[3 * m + k]] += ks[k];
+          }
+        }
+      }
+      free(q);
+      free(x);
+    }
+  }
+  free(area);
   return 0;
 }
 

@@ -6,7 +6,10 @@
 * V_h^d is symmetric (exactly on separated pairs) and positive definite (a non-negative mixture
   of Gaussians in r is a positive-definite function);
 * the whole Dirichlet pipeline reproduces the paper's Table 6.1 (first level; second level with
-  HEATBEM_SLOW=1).
+  HEATBEM_SLOW=1);
+* the plain double-precision mode in the paper's level order (the timed CPU baseline) agrees with
+  the long-double assembly to the rounding of its second differences, and does not depend on the
+  thread count.
 """
 import os
 
@@ -29,6 +32,21 @@ def test_levels_order_equals_direct(mesh, nt):
     Vl, Kl = oracle.assemble(v, t, 0.8, 1.0, nt, method="levels")
     assert np.all(ds.block_rel_error(Vd, Vl) < 1e-13)
     assert np.all(ds.block_rel_error(Kd, Kl) < 1e-13)
+
+
+def test_plain_double_mode(cube1, c1_oracle):
+    """The CPU-baseline mode (double, level order, separated-pair points mapped in double) against
+    the long-double blocks of the 192-triangle 16-step case: its error is the rounding of the
+    second differences (growing with d), far above long double's and far below the quadrature's."""
+    V, K = c1_oracle
+    v, t = cube1
+    Vp, Kp = oracle.assemble_plain(v, t, 1.0, 1.0, 16)
+    eV, eK = ds.block_rel_error(V, Vp), ds.block_rel_error(K, Kp)
+    assert eV.max() < 1e-10 and eK.max() < 1e-10, (eV, eK)
+    assert eV[0] < 1e-14 and eK[0] < 1e-14
+    rows = np.array([0, 100], dtype=np.int32)
+    V1, K1 = oracle.assemble_plain(v, t, 1.0, 1.0, 16, rows=rows, threads=1)
+    assert np.array_equal(V1, Vp[:, rows]) and np.array_equal(K1, Kp[:, rows])
 
 
 def test_temporal_modes_agree():
