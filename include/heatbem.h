@@ -178,27 +178,42 @@ int hb_rhs_neumann(hb_ctx *ctx, const double *psi, double *b, void *stream);
 
 typedef struct hb_solve_opts {
   int32_t method;   /* HB_SOLVE_* */
-  int32_t max_iter; /* GMRES iteration cap, per refinement step for HB_SOLVE_MIXED_IR
-                       (default 500 if <= 0) */
+  int32_t max_iter; /* GMRES iteration cap over the whole solve (preconditioned phase, fallback
+                       and restarts); per inner solve for HB_SOLVE_MIXED_IR, whose fallback then
+                       gets max_iter more (default 500 if <= 0) */
   double tol;       /* relative residual ||b - V_h w|| / ||b|| target (default 1e-8 if <= 0) */
   int32_t precond;  /* GMRES methods: 1 = right-precondition with the sparse approximate inverse
                        installed by hb_precond_set, 0 = none */
-  int32_t reserved[7];
+  int32_t precond_max_iter; /* > 0: iteration cap of the preconditioned GMRES phase (for
+                               HB_SOLVE_MIXED_IR: of all its inner iterations together) before
+                               the plain double fallback takes over; 0 = no separate cap */
+  int32_t reserved[6];
 } hb_solve_opts;
 
 typedef struct hb_solve_info {
-  int32_t iterations;   /* GMRES iterations, summed over refinement steps (0 for time marching) */
-  double rel_residual;  /* ||b - V_h w|| / ||b|| recomputed in double after the solve */
+  int32_t iterations;   /* GMRES iterations, summed over all phases (0 for time marching) */
+  double rel_residual;  /* ||b - V_h w|| / ||b|| recomputed in double at the end of the solve */
   double seconds;       /* wall time of the solve (work queued before it on the stream is
                            drained before the clock starts) */
   int32_t refinements;  /* HB_SOLVE_MIXED_IR: outer refinement steps */
-  int32_t reserved[7];
+  int32_t fallback;     /* 1 if the preconditioned or mixed-precision phase ended above tol and
+                           plain double GMRES continued from its iterate */
+  int32_t restarts;     /* continuations after the first phase because the recomputed double
+                           residual was above tol (GMRES restarts, repeated time marching) */
+  int32_t reserved[5];
 } hb_solve_info;
 
 /* Solve V_h w = b for w.  b, w: device pointers, E_t x E_x, float64.  info may be NULL.
- * Returns HB_ENOCONV (w then holds the last iterate) when GMRES hits max_iter first.  All
- * methods use the block-Toeplitz product, so E_t <= 256.  The call returns once w and the
- * residual check are complete on `stream` (it synchronizes with the stream). */
+ * Residual contract (Sec. 6.1, relative accuracy in the double operator): HB_OK means that
+ * ||b - V_h w|| / ||b|| <= tol, recomputed in double with the double blocks (float storage: the
+ * float blocks with double accumulation) after the method has finished.  GMRES stops on its
+ * Arnoldi estimate; if the recomputed residual is above tol, GMRES restarts from w on the
+ * residual (within max_iter); a preconditioned (precond = 1) or HB_SOLVE_MIXED_IR phase that ends
+ * above tol hands over to plain double GMRES from its iterate (info->fallback = 1); time marching
+ * repeats its forward substitution on the residual at most three times.  Otherwise HB_ENOCONV,
+ * with w holding the last iterate.  All methods use the block-Toeplitz product, so E_t <= 256.
+ * The call returns once w and the residual check are complete on `stream` (it synchronizes with
+ * the stream). */
 int hb_solve(hb_ctx *ctx, const double *b, double *w, const hb_solve_opts *opts,
              hb_solve_info *info, void *stream);
 
@@ -208,7 +223,8 @@ int hb_solve(hb_ctx *ctx, const double *b, double *w, const hb_solve_opts *opts,
  * the operator preconditioner M_h^{-1} V_h^{11} M_h^{-1} from the right (Sec. 6.1: V_h^{11} as its
  * essential part; M_h = h blockdiag(M), M the p1 mass matrix, inverted once per context), which
  * needs HB_OP_V11 assembled.  Needs HB_OP_D assembled (HB_ESTATE).  info->rel_residual is
- * ||b - D_h u|| / ||b||.  Returns once u is complete on `stream`, as hb_solve. */
+ * ||b - D_h u|| / ||b||; the residual contract, restarts and fallback (to GMRES without the
+ * operator preconditioner) are those of hb_solve.  Returns once u is complete on `stream`. */
 int hb_solve_neumann(hb_ctx *ctx, const double *b, double *u, const hb_solve_opts *opts,
                      hb_solve_info *info, void *stream);
 

@@ -32,13 +32,15 @@ def _compile(src, obj):
 def build(verbose=True):
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
-    objs = []
-    for s in srcs:
-        o = os.path.join(BUILD, os.path.basename(s) + ".o")
-        if verbose:
-            print("[build] hipcc", os.path.basename(s), flush=True)
-        _compile(s, o)
-        objs.append(o)
+    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
+    if verbose:
+        print("[build] hipcc", " ".join(os.path.basename(s) for s in srcs), flush=True)
+    # one hipcc per source, several at a time
+    from concurrent.futures import ThreadPoolExecutor
+    jobs = max(1, min(len(srcs), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_compile, s, o) for s, o in zip(srcs, objs)]:
+            f.result()
     tmp = OUT + ".tmp%d" % os.getpid()
     subprocess.check_call([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs)
     os.replace(tmp, OUT)

@@ -45,7 +45,8 @@ class Options(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("precond", ctypes.c_int32), ("precond_max_iter", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class MLPDims(ctypes.Structure):
@@ -55,7 +56,8 @@ class MLPDims(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("refinements", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("fallback", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 _lib = None
@@ -160,6 +162,13 @@ def _stream(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _info_dict(info, rc):
+    return {"iterations": info.iterations, "rel_residual": info.rel_residual,
+            "seconds": info.seconds, "refinements": info.refinements,
+            "fallback": bool(info.fallback), "restarts": info.restarts,
+            "converged": rc == HB_OK}
 
 
 class Context:
@@ -271,7 +280,8 @@ class Context:
         self._check(lib().hb_rhs_neumann(self._h, _ptr(psi), _ptr(b), _stream(stream)))
         return b
 
-    def solve_neumann(self, b, tol=1e-8, max_iter=500, u=None, precond=False, stream=None):
+    def solve_neumann(self, b, tol=1e-8, max_iter=500, u=None, precond=False,
+                      precond_max_iter=0, stream=None):
         """D_h u = b by GMRES; b, u: (E_t, N_x); precond: the operator preconditioner
         M_h^{-1} V_h^{11} M_h^{-1} (needs HB_OP_V11 assembled)."""
         import torch
@@ -279,28 +289,28 @@ class Context:
             u = torch.empty((self.n_t, self.n_verts), dtype=torch.float64, device="cuda")
         o = SolveOpts()
         o.method, o.tol, o.max_iter, o.precond = HB_SOLVE_GMRES, tol, max_iter, int(bool(precond))
+        o.precond_max_iter = precond_max_iter
         info = SolveInfo()
         rc = lib().hb_solve_neumann(self._h, _ptr(b), _ptr(u), ctypes.byref(o), ctypes.byref(info),
                                     _stream(stream))
         if rc not in (HB_OK, HB_ENOCONV):
             self._check(rc)
-        return u, {"iterations": info.iterations, "rel_residual": info.rel_residual,
-                   "seconds": info.seconds, "converged": rc == HB_OK}
+        return u, _info_dict(info, rc)
 
     def solve(self, b, method=HB_SOLVE_GMRES, tol=1e-8, max_iter=500, w=None, precond=False,
-              stream=None):
+              precond_max_iter=0, stream=None):
+        """V_h w = b; converged means ||b - V_h w|| / ||b|| <= tol recomputed in double."""
         import torch
         if w is None:
             w = torch.empty((self.n_t, self.n_tris), dtype=torch.float64, device="cuda")
         o = SolveOpts()
         o.method, o.tol, o.max_iter, o.precond = method, tol, max_iter, int(bool(precond))
+        o.precond_max_iter = precond_max_iter
         info = SolveInfo()
         rc = lib().hb_solve(self._h, _ptr(b), _ptr(w), ctypes.byref(o), ctypes.byref(info), _stream(stream))
         if rc not in (HB_OK, HB_ENOCONV):
             self._check(rc)
-        return w, {"iterations": info.iterations, "rel_residual": info.rel_residual,
-                   "seconds": info.seconds, "refinements": info.refinements,
-                   "converged": rc == HB_OK}
+        return w, _info_dict(info, rc)
 
     # ---- learned preconditioner ----
     def precond_pattern(self, stream=None):

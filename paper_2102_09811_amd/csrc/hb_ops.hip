@@ -1154,20 +1154,27 @@ int time_march(hb_ctx *c, const double *b, double *w, hipStream_t s) {
   return HB_OK;
 }
 
+// Two vectors of n doubles behind c->d_ir (residual and correction), shared with mixed_ir
+int ensure_ir(hb_ctx *c, size_t n) {
+  const size_t need = 2 * n * sizeof(double) + 64 * sizeof(double);
+  if (c->ir_bytes >= need) return HB_OK;
+  if (c->d_ir) (void)hipFree(c->d_ir);
+  c->d_ir = nullptr;
+  c->ir_bytes = 0;
+  HB_CHECK(c, hipMalloc(&c->d_ir, need));
+  c->ir_bytes = need;
+  return HB_OK;
+}
+
 // Iterative refinement: x_{i+1} = x_i + d_i with V32 d_i ~= b - V_h x_i (GMRES on the float
-// operator to relative tolerance inner_tol); residuals in double with the double operator.
-int mixed_ir(hb_ctx *c, const double *b, double *x, double tol, int maxit, hipStream_t s,
-             hb_solve_info *info, bool precond) {
+// operator to relative tolerance inner_tol, at most maxit iterations each and `budget` in all);
+// residuals in double with the double operator.
+int mixed_ir(hb_ctx *c, const double *b, double *x, double tol, int maxit, int budget,
+             hipStream_t s, hb_solve_info *info, bool precond) {
   const size_t n = (size_t)c->nt * c->ne;
   int rc = ensure_V32(c, s);
   if (rc) return rc;
-  if (c->ir_bytes < 2 * n * sizeof(double) + 64 * sizeof(double)) {
-    if (c->d_ir) (void)hipFree(c->d_ir);
-    c->d_ir = nullptr;
-    c->ir_bytes = 0;
-    HB_CHECK(c, hipMalloc(&c->d_ir, 2 * n * sizeof(double) + 64 * sizeof(double)));
-    c->ir_bytes = 2 * n * sizeof(double) + 64 * sizeof(double);
-  }
+  if ((rc = ensure_ir(c, n))) return rc;
   double *r = c->d_ir, *dlt = r + n;
   const double inner_tol = 1e-4;
   hipLaunchKernelGGL(k_fill, dim3(grid1d(n)), dim3(256), 0, s, x, n, 0.0);
@@ -1200,8 +1207,9 @@ int mixed_ir(hb_ctx *c, const double *b, double *x, double tol, int maxit, hipSt
       conv = true;
       break;
     }
+    if (total_it >= budget) break;
     hb_solve_info in{};
-    rc = gmres(c, 1, r, dlt, inner_tol, maxit, s, &in, precond, rn);
+    rc = gmres(c, 1, r, dlt, inner_tol, std::min(maxit, budget - total_it), s, &in, precond, rn);
     if (rc != HB_OK && rc != HB_ENOCONV) return rc;
     total_it += in.iterations;
     hipLaunchKernelGGL(k_axpby, dim3(grid1d(n)), dim3(256), 0, s, 1.0, dlt, 1.0, x, n);
@@ -1213,18 +1221,74 @@ int mixed_ir(hb_ctx *c, const double *b, double *x, double tol, int maxit, hipSt
   return conv ? HB_OK : HB_ENOCONV;
 }
 
-double rel_residual(hb_ctx *c, const double *b, const double *w, hipStream_t s, int *rc,
-                    int op = 0) {
+// r = b - A w with the double operator (op 0: V_h, 2: D_h) into r; *rn = ||r||, *bn = ||b||
+int residual_norms(hb_ctx *c, int op, const double *b, const double *w, double *r, double *rn,
+                   double *bn, hipStream_t s) {
   const size_t n = (size_t)c->nt * (op == 2 ? c->nv : c->ne);
-  *rc = ensure_work(c, sizeof(double) * (2 * n + 64 + (n / kDotChunk + 2)));
-  if (*rc) return -1;
-  double *r = c->d_work + n, *partial = r + n, *dres = partial + (n / kDotChunk + 2);
-  if ((*rc = apply_V(c, op == 2 ? 2 : 0, w, r, s))) return -1;
+  const int nchunk = (int)((n + kDotChunk - 1) / kDotChunk);
+  int rc = ensure_work(c, sizeof(double) * (nchunk + 2));
+  if (rc) return rc;
+  double *partial = c->d_work, *dres = partial + nchunk;
+  if ((rc = apply_V(c, op == 2 ? 2 : 0, w, r, s))) return rc;
   hipLaunchKernelGGL(k_axpby, dim3(grid1d(n)), dim3(256), 0, s, 1.0, b, -1.0, r, n);
+  HB_CHECK(c, hipGetLastError());
   double rr, bb;
-  if ((*rc = multi_dot(c, r, 0, 1, r, n, partial, dres, &rr, s))) return -1;
-  if ((*rc = multi_dot(c, b, 0, 1, b, n, partial, dres, &bb, s))) return -1;
-  return bb > 0 ? std::sqrt(rr / bb) : 0.0;
+  if ((rc = multi_dot(c, r, 0, 1, r, n, partial, dres, &rr, s))) return rc;
+  if ((rc = multi_dot(c, b, 0, 1, b, n, partial, dres, &bb, s))) return rc;
+  *rn = std::sqrt(rr);
+  *bn = std::sqrt(bb);
+  return HB_OK;
+}
+
+// The residual contract of hb_solve / hb_solve_neumann (Sec. 6.1: the relative residual in the
+// double operator decides).  After the chosen method has produced w (rc0 its status), the
+// residual r = b - A w is recomputed in double; while ||r|| > tol ||b|| the solve continues from
+// w: GMRES on A delta = r to the tolerance that brings b - A (w + delta) below half the target,
+// w += delta (a restart), within the iteration budget; time marching repeats its exact forward
+// substitution on r (at most three times).  A preconditioned or mixed-precision phase that ended
+// without reaching the target hands over to plain double GMRES (the fallback), which also
+// carries every later restart.  HB_OK only if ||b - A w|| <= tol ||b|| at the end.
+// op: 0 V_h (pc_kind 1: the learned map), 2 D_h (pc_kind 2: the operator preconditioner).
+int enforce_residual(hb_ctx *c, int op, int method, int pc_kind, const double *b, double *w,
+                     const hb_solve_opts &o, int rc0, hb_solve_info &inf, hipStream_t s) {
+  const size_t n = (size_t)c->nt * (op == 2 ? c->nv : c->ne);
+  int rc = ensure_ir(c, n);
+  if (rc) return rc;
+  double *r = c->d_ir, *dlt = r + n;
+  double rn = 0.0, bn = 0.0;
+  if ((rc = residual_norms(c, op, b, w, r, &rn, &bn, s))) return rc;
+  const bool timemarch = method == HB_SOLVE_TIMEMARCH;
+  // the phase that produced w did not reach its target: plain double GMRES from here on
+  bool plain = rc0 == HB_ENOCONV && (pc_kind != 0 || method == HB_SOLVE_MIXED_IR);
+  if (plain) inf.fallback = 1;
+  // iterations left: mixed refinement counts max_iter per inner solve, so its fallback starts
+  // with a full budget; GMRES shares one budget over all phases
+  int used = method == HB_SOLVE_MIXED_IR ? 0 : inf.iterations;
+  while (bn > 0.0 && rn > o.tol * bn) {
+    if (timemarch) {
+      if (inf.restarts >= 3) break;
+      if ((rc = time_march(c, r, dlt, s))) return rc;
+    } else {
+      const int left = o.max_iter - used;
+      if (left <= 0) break;
+      hb_solve_info ii{};
+      const int kind = plain ? 0 : pc_kind;
+      rc = gmres(c, op, r, dlt, 0.5 * o.tol * bn / rn, left, s, &ii, kind, rn);
+      if (rc != HB_OK && rc != HB_ENOCONV) return rc;
+      used += ii.iterations;
+      inf.iterations += ii.iterations;
+      if (rc == HB_ENOCONV && kind != 0) {
+        plain = true;
+        inf.fallback = 1;
+      }
+    }
+    hipLaunchKernelGGL(k_axpby, dim3(grid1d(n)), dim3(256), 0, s, 1.0, dlt, 1.0, w, n);
+    HB_CHECK(c, hipGetLastError());
+    inf.restarts += 1;
+    if ((rc = residual_norms(c, op, b, w, r, &rn, &bn, s))) return rc;
+  }
+  inf.rel_residual = bn > 0.0 ? rn / bn : 0.0;
+  return bn == 0.0 || rn <= o.tol * bn ? HB_OK : HB_ENOCONV;
 }
 
 }  // namespace
@@ -1306,16 +1370,17 @@ int hb_solve_neumann(hb_ctx *c, const double *b, double *u, const hb_solve_opts 
   auto t0 = std::chrono::steady_clock::now();
   int rc;
   if (o.precond && (rc = ensure_minv(c, s))) return rc;
-  rc = gmres(c, 2, b, u, o.tol, o.max_iter, s, &inf, o.precond ? 2 : 0);
+  const int cap = o.precond && o.precond_max_iter > 0 ? std::min(o.precond_max_iter, o.max_iter)
+                                                      : o.max_iter;
+  rc = gmres(c, 2, b, u, o.tol, cap, s, &inf, o.precond ? 2 : 0);
+  if (rc != HB_OK && rc != HB_ENOCONV) return rc;
+  rc = enforce_residual(c, 2, HB_SOLVE_GMRES, o.precond ? 2 : 0, b, u, o, rc, inf, s);
   if (rc != HB_OK && rc != HB_ENOCONV) return rc;
   HB_CHECK(c, hipStreamSynchronize(s));
   auto t1 = std::chrono::steady_clock::now();
-  int rc2 = HB_OK;
-  inf.rel_residual = rel_residual(c, b, u, s, &rc2, 2);
-  if (rc2) return rc2;
   inf.seconds = std::chrono::duration<double>(t1 - t0).count();
   if (info) *info = inf;
-  if (rc == HB_ENOCONV) c->err = "GMRES reached max_iter before the tolerance";
+  if (rc == HB_ENOCONV) c->err = "the relative residual is above tol after max_iter iterations";
   return rc;
 }
 
@@ -1359,18 +1424,21 @@ int hb_solve(hb_ctx *c, const double *b, double *w, const hb_solve_opts *opts, h
   int rc;
   if (o.precond && !c->pc_active) return ctx_fail(c, HB_ESTATE, "no preconditioner installed");
   const bool pc = o.precond != 0;
-  if (o.method == HB_SOLVE_GMRES) rc = gmres(c, 0, b, w, o.tol, o.max_iter, s, &inf, pc);
-  else if (o.method == HB_SOLVE_MIXED_IR) rc = mixed_ir(c, b, w, o.tol, o.max_iter, s, &inf, pc);
+  const int cap = pc && o.precond_max_iter > 0 ? std::min(o.precond_max_iter, o.max_iter)
+                                               : o.max_iter;
+  if (o.method == HB_SOLVE_GMRES) rc = gmres(c, 0, b, w, o.tol, cap, s, &inf, pc);
+  else if (o.method == HB_SOLVE_MIXED_IR)
+    rc = mixed_ir(c, b, w, o.tol, o.max_iter, o.precond_max_iter > 0 ? o.precond_max_iter : INT32_MAX,
+                  s, &inf, pc);
   else rc = time_march(c, b, w, s);
+  if (rc != HB_OK && rc != HB_ENOCONV) return rc;
+  rc = enforce_residual(c, 0, o.method, pc ? 1 : 0, b, w, o, rc, inf, s);
   if (rc != HB_OK && rc != HB_ENOCONV) return rc;
   HB_CHECK(c, hipStreamSynchronize(s));
   auto t1 = std::chrono::steady_clock::now();
-  int rc2 = HB_OK;
-  inf.rel_residual = rel_residual(c, b, w, s, &rc2);
-  if (rc2) return rc2;
   inf.seconds = std::chrono::duration<double>(t1 - t0).count();
   if (info) *info = inf;
-  if (rc == HB_ENOCONV) c->err = "GMRES reached max_iter before the tolerance";
+  if (rc == HB_ENOCONV) c->err = "the relative residual is above tol after max_iter iterations";
   return rc;
 }
 

@@ -3,8 +3,10 @@
 Bar: block-relative max error e_d = max|A^d - A^d_oracle| / max|A^d_oracle| <= 1e-12 for the
 double-precision path (same quadrature rules on both sides; the oracle evaluates the exact time
 integrals in long double).  Cases span several tiles and ragged tails (E_x not a multiple of 256),
-the closed-form and Taylor blocks, the degenerate sizes E_t = 1, 2 and all-touching meshes, and the
-full 1280-triangle / 64-step workload on sampled rows.
+the closed-form and Taylor blocks including the last Taylor class (d >= 64, polynomial degree 6)
+at E_t = 70 and 130, the degenerate sizes E_t = 1, 2 and all-touching meshes, the full
+1280-triangle / 64-step workload on sampled rows and the 3072-triangle / 128-step workload on
+sampled rows (double and mixed precision).
 """
 import sys
 
@@ -39,6 +41,9 @@ CASES = {
     "tetra_nt2": (tetrahedron, 0.3, 2.0, 2, {}),
     "octa_nt3": (octahedron, 2.0, 1.0, 3, {}),
     "cube2_nt40": (lambda: cube(2), 0.5, 1.0, 40, {}),
+    "cube2_nt130": (lambda: cube(2), 1.0, 1.0, 130, {}),
+    "cube2_nt70_a03": (lambda: cube(2), 0.3, 1.0, 70, {}),
+    "octa_nt130_dsw8": (octahedron, 2.0, 1.0, 130, {"d_switch": 8}),
     "cube4_nt16": (lambda: cube(4), 1.0, 1.0, 16, {}),
     "cube4_nt16_dsw8": (lambda: cube(4), 1.0, 1.0, 16, {"d_switch": 8}),
     "cube4_nt16_dsw16": (lambda: cube(4), 1.0, 1.0, 16, {"d_switch": 16}),
@@ -86,6 +91,35 @@ def test_full_size_sampled_rows():
     eV, eK = block_rel_error(Vr, V), block_rel_error(Kr, K)
     say("icosphere3: max e_V=%.2e max e_K=%.2e" % (eV.max(), eK.max()))
     assert eV.max() <= TOL and eK.max() <= TOL
+
+
+@pytest.mark.parametrize("alpha,nrows", [(1.0, 8), (0.5, 4), (2.0, 4)])
+def test_cube3072_nt128_sampled_rows(alpha, nrows):
+    """3072-triangle cube (16 x 16 x 2 per face), 128 steps: every block of sampled test rows,
+    double-precision assembly against the oracle at 1e-12 (blocks 64..127 are the last Taylor
+    class) and the mixed-precision assembly (float separated pairs from d = 3) at 1e-6."""
+    from paper_2102_09811_amd import Context, HB_OP_K, HB_OP_V, HB_PREC_MIXED
+    import torch
+    v, t = cube(16)
+    nt = 128
+    rows = np.linspace(0, len(t) - 1, nrows).astype(np.int32)
+    say("cube16 E_x=3072 E_t=128 alpha=%g: oracle on %d rows" % (alpha, nrows))
+    Vr, Kr = oracle.assemble(v, t, alpha, 1.0, nt, rows=rows)
+    rows_t = torch.from_numpy(rows.astype(np.int64)).cuda()
+    ctx = Context(v, t, alpha, 1.0, nt)
+    out = {}
+    for prec in (0, HB_PREC_MIXED):
+        ctx.assemble(HB_OP_V | HB_OP_K, precision=prec)
+        V = ctx.blocks(HB_OP_V)[:, rows_t].cpu().numpy()
+        K = ctx.blocks(HB_OP_K)[:, rows_t].cpu().numpy()
+        out[prec] = (block_rel_error(Vr, V), block_rel_error(Kr, K))
+        torch.cuda.empty_cache()
+    ctx.close()
+    (eV, eK), (mV, mK) = out[0], out[HB_PREC_MIXED]
+    say("cube16 alpha=%g: double max e_V=%.2e (d=%d) e_K=%.2e (d=%d); mixed e_V=%.2e e_K=%.2e" % (
+        alpha, eV.max(), eV.argmax(), eK.max(), eK.argmax(), mV.max(), mK.max()))
+    assert eV.max() <= TOL and eK.max() <= TOL
+    assert mV.max() <= 1e-6 and mK.max() <= 1e-6
 
 
 def test_float_storage_and_repeatability():

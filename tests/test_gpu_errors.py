@@ -3,6 +3,7 @@ handled) by the library's host-side checks before any kernel is launched."""
 import numpy as np
 import pytest
 
+from oracle import downstream as ds
 from synthetic import cube, tetrahedron
 
 pytestmark = pytest.mark.gpu
@@ -57,6 +58,34 @@ def test_gmres_reports_no_convergence(torch):
     assert np.isfinite(w.cpu().numpy()).all()
     w, info = ctx.solve(b, tol=1e-8)
     assert info["converged"] and info["rel_residual"] <= 1e-8
+    ctx.close()
+
+
+def test_solve_fallback_and_residual_contract(torch):
+    """The plain double GMRES fallback, forced from the host: a preconditioned (or mixed inner)
+    phase capped at 2 iterations ends above tol and plain GMRES continues from its iterate.  The
+    result meets the tolerance, recomputed here with the oracle's blocks."""
+    import oracle
+    from paper_2102_09811_amd import Context, HB_SOLVE_GMRES, HB_SOLVE_MIXED_IR
+    v, t = cube(2)
+    nt = 12
+    ctx = Context(v, t, 1.0, 1.0, nt)
+    ctx.assemble()
+    _, _, y = ctx.precond_spai(exact=True)
+    ctx.precond_set(y)
+    Vr, _ = oracle.assemble(v, t, 1.0, 1.0, nt)
+    bh = np.random.default_rng(4).standard_normal((nt, len(t)))
+    b = torch.from_numpy(bh).cuda()
+    for method in (HB_SOLVE_GMRES, HB_SOLVE_MIXED_IR):
+        w, info = ctx.solve(b, method=method, tol=1e-8, precond=True, precond_max_iter=2)
+        res = np.linalg.norm(bh - ds.toeplitz_apply(Vr, w.cpu().numpy())) / np.linalg.norm(bh)
+        print("[gpu-test] method %d capped: it=%d fallback=%s restarts=%d res=%.2e (oracle %.2e)" % (
+            method, info["iterations"], info["fallback"], info["restarts"], info["rel_residual"],
+            res), flush=True)
+        assert info["fallback"] and info["converged"] and info["rel_residual"] <= 1e-8
+        assert res <= 1.01e-8
+        w, info = ctx.solve(b, method=method, tol=1e-8, precond=True)
+        assert not info["fallback"] and info["converged"] and info["rel_residual"] <= 1e-8
     ctx.close()
 
 

@@ -1,12 +1,14 @@
 """GPU parity of the hypersingular operator and the Neumann path (Sec. 3.3, 3.4) against the oracle.
 
 * D_h blocks (p1 x p1, N_x x N_x): the oracle's D^1 = T^T (alpha^2 V^d (x) I_3) T formed from
-  the GPU's own V_h blocks plus the oracle's D^2 blocks (closed form in long double), per-block
+  the oracle's V_h blocks plus the oracle's D^2 blocks (closed form in long double), per-block
   max-norm error relative to the block maximum <= 1e-12; meshes and E_t chosen so that the
   closed-form blocks (d < 8) and every Taylor degree class (d < 12, 16, 32, 64, beyond) occur,
   with ragged sizes against the 64-wide tiles;
+* V_h^{11} blocks against the oracle's, up to E_t = 70 (the last Taylor class);
 * K_h^T and D_h block-Toeplitz products, the Neumann right-hand side and the Neumann solve against
-  the oracle's numpy versions on the same blocks.
+  the oracle's numpy versions on the oracle's blocks (1e-11: the two sides' blocks differ by up to
+  1e-12 of each block's maximum).
 """
 import sys
 
@@ -41,10 +43,10 @@ CASES = {
 }
 
 
-def d_reference(ctx, v, t, alpha, nt):
-    from paper_2102_09811_amd import HB_OP_V
-    Vg = ctx.blocks(HB_OP_V).double().cpu().numpy()
-    return ds.assemble_d1(Vg, v, t, alpha) + oracle.assemble_d2(v, t, alpha, 1.0, nt)
+def d_reference(v, t, alpha, nt):
+    """D_h = D_h^1 + D_h^2 from the oracle alone (Sec. 3.3)."""
+    Vr, _ = oracle.assemble(v, t, alpha, 1.0, nt)
+    return ds.assemble_d1(Vr, v, t, alpha) + oracle.assemble_d2(v, t, alpha, 1.0, nt)
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -56,7 +58,7 @@ def test_D_blocks_match_oracle(torch, case):
     ctx = Context(v, t, alpha, 1.0, nt)
     ctx.assemble(HB_OP_V | HB_OP_K | HB_OP_D)
     Dg = ctx.blocks(HB_OP_D).cpu().numpy()
-    Dr = d_reference(ctx, v, t, alpha, nt)
+    Dr = d_reference(v, t, alpha, nt)
     e = ds.block_rel_error(Dr, Dg)
     say("  max e_D = %.2e (block %d)" % (e.max(), e.argmax()))
     assert e.max() <= 1e-12
@@ -87,25 +89,25 @@ def test_neumann_products_rhs_and_solve(torch):
     h = 1.0 / nt
     ctx = Context(v, t, alpha, 1.0, nt)
     ctx.assemble(HB_OP_V | HB_OP_K | HB_OP_D)
-    K = ctx.blocks(HB_OP_K).cpu().numpy()
-    D = ctx.blocks(HB_OP_D).cpu().numpy()
+    Vr, K = oracle.assemble(v, t, alpha, 1.0, nt)
+    D = ds.assemble_d1(Vr, v, t, alpha) + oracle.assemble_d2(v, t, alpha, 1.0, nt)
     rng = np.random.default_rng(11)
     psi = rng.standard_normal((nt, len(t)))
     psi_d = torch.from_numpy(psi).cuda()
     # K^T product
     yk = ctx.apply(HB_OP_KT, psi_d).cpu().numpy()
     yr = ds.toeplitz_apply(np.ascontiguousarray(K.transpose(0, 2, 1)), psi)
-    assert np.abs(yk - yr).max() <= 1e-12 * np.abs(yr).max()
+    assert np.abs(yk - yr).max() <= 1e-11 * np.abs(yr).max()
     # D product
     x = rng.standard_normal((nt, len(v)))
     yd = ctx.apply(HB_OP_D, torch.from_numpy(x).cuda()).cpu().numpy()
     yr = ds.toeplitz_apply(D, x)
-    assert np.abs(yd - yr).max() <= 1e-12 * np.abs(yr).max()
+    assert np.abs(yd - yr).max() <= 1e-11 * np.abs(yr).max()
     # right-hand side
     b = ctx.rhs_neumann(psi_d)
     br = ds.rhs_neumann(K, ds.mass_p0p1(v, t), psi, h)
-    assert np.abs(b.cpu().numpy() - br).max() <= 1e-12 * np.abs(br).max()
-    # solve
+    assert np.abs(b.cpu().numpy() - br).max() <= 1e-11 * np.abs(br).max()
+    # solve (against time marching on the oracle's blocks and right-hand side)
     u, info = ctx.solve_neumann(b, tol=1e-10)
     say("Neumann GMRES: %d iterations, residual %.1e" % (info["iterations"], info["rel_residual"]))
     assert info["converged"] and info["rel_residual"] <= 1e-10
@@ -122,7 +124,7 @@ def test_neumann_products_rhs_and_solve(torch):
     ctx.close()
 
 
-@pytest.mark.parametrize("case,opts", [("octa_nt12", {}), ("cube2_nt40", {}),
+@pytest.mark.parametrize("case,opts", [("octa_nt12", {}), ("cube2_nt40", {}), ("cube2_nt70", {}),
                                        ("cube4_nt16", {}), ("cube4_nt16", {"d_switch": 8})])
 def test_V11_blocks_match_oracle(torch, case, opts):
     """V_h^{11} (p1 x p1 single layer, the paper's preconditioner matrix for D_h) against the

@@ -148,8 +148,8 @@ def test_learned_preconditioner_gain():
             1e3 * il["seconds"], ie["iterations"]))
         assert il["converged"] and il["rel_residual"] <= 1e-8
         # the plain runs pass 88 steps, where y = R^{-1} g is solved on the host instead of the
-        # device; the recomputed residual may exceed the GMRES estimate by rounding
-        assert ip["converged"] and ip["rel_residual"] <= 2e-8
+        # device
+        assert ip["converged"] and ip["rel_residual"] <= 1e-8
         its_plain.append(ip["iterations"])
         its_learned.append(il["iterations"])
         its_exact.append(ie["iterations"])

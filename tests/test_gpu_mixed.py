@@ -1,16 +1,18 @@
 """Mixed precision (float separated pairs at large d, float-MFMA apply, iterative refinement)
-against the double path.
+against the oracle and against the double path.
 
-Bars: per-block max error relative to the block's max, mixed vs double assembly, <= 1e-6 for
-every d, V and K; the float apply agrees with the double apply of the same (float-rounded)
-blocks to 1e-5; the refinement solve reaches ||b - V_h w|| / ||b|| <= 1e-8 with the double
-operator.
+Bars: per-block max error relative to the block's max <= 1e-6 for every d, V and K, of the mixed
+assembly against the oracle (every row of the 192-triangle cube, sampled rows of the
+1280-triangle sphere; the 3072-triangle cube's sampled rows are in the assembly tests) and against
+the double assembly (the error the mixed path adds, reported per block); the refinement solve
+reaches ||b - V_h w|| / ||b|| <= 1e-8 with the double operator.
 """
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 from oracle import downstream as ds
 from synthetic import cube, exp_solution, icosphere, nodal_samples
 
@@ -35,7 +37,9 @@ def per_block_rel(A, B):
                                                 ("cube4", 40, 1.0, 8)])
 def test_mixed_assembly_per_block(mesh, nt, alpha, dmin):
     """Float separated pairs from the first Taylor block (d = 3, or the option mixed_d_min = 8):
-    every block within 1e-6 of the double assembly; the closed-form blocks stay identical."""
+    every block within 1e-6 of the double assembly and of the oracle; the closed-form blocks stay
+    identical to the double assembly."""
+    import torch
     from paper_2102_09811_amd import Context, HB_OP_K, HB_OP_V, HB_PREC_MIXED
     v, t = cube(4) if mesh == "cube4" else icosphere(3)
     say("mixed assembly %s nt=%d alpha=%g mixed_d_min=%s" % (mesh, nt, alpha, dmin))
@@ -53,6 +57,14 @@ def test_mixed_assembly_per_block(mesh, nt, alpha, dmin):
     assert np.all(eK[:min(d0, nt)] <= 1e-14)            # (K by atomics: summation order)
     if nt > d0:
         assert eV[d0:].max() > 0.0                       # the float path was taken
+    # against the oracle: every row of the cube, 8 rows of the sphere
+    rows = np.arange(len(t)) if mesh == "cube4" else np.linspace(0, len(t) - 1, 8).astype(np.int64)
+    Vr, Kr = oracle.assemble(v, t, alpha, 1.0, nt, rows=rows.astype(np.int32))
+    rt = torch.from_numpy(rows).cuda()
+    oV = ds.block_rel_error(Vr, Vm[:, rt].cpu().numpy())
+    oK = ds.block_rel_error(Kr, Km[:, rt].cpu().numpy())
+    say("against the oracle (%d rows): max e_V=%.2e max e_K=%.2e" % (len(rows), oV.max(), oK.max()))
+    assert oV.max() <= 1e-6 and oK.max() <= 1e-6
     ctx.close()
 
 

@@ -2,8 +2,8 @@
 
 Problem: Q = (-1, 1)^3 x (0, 1), alpha = 0.5, zero initial condition, u = G_alpha(x - y*, t) with
 y* = (0, 0, 1.5).  Meshes: 32 congruent triangles per cube face and 8 time steps, each level
-quadrisecting the triangles and bisecting the steps (192/8, 768/16, 3072/32; 12288/64 with
-HEATBEM_SLOW=1).
+quadrisecting the triangles and bisecting the steps (192/8, 768/16, 3072/32, 12288/64; the finest
+level holds 77 GB of V_h blocks and 39 GB of K_h blocks on the device).
 
 GPU: assembly of V_h and K_h, the right-hand side (1/2 M_h + K_h) g, GMRES to a relative residual
 of 1e-8 (the paper uses FGMRES at 1e-8), and the representation formula at 10^4 points in
@@ -14,7 +14,6 @@ L2(Sigma_h) errors with 8-point rules in space and time.
 Checked against the printed table: the errors of w_h and w* within 5 %, the point error within
 25 % (the paper's 10^4 points are not known; these are seeded uniform ones).
 """
-import os
 import sys
 import time
 
@@ -42,9 +41,7 @@ def test_table61_dirichlet_convergence():
     alpha, T = 0.5, 1.0
     ex = ExactSolution(alpha, (0.0, 0.0, 1.5))
     flux = lambda x, n, t: ex.flux(x, n, t)  # noqa: E731
-    levels = [(4, 8), (8, 16), (16, 32)]
-    if os.environ.get("HEATBEM_SLOW"):
-        levels.append((32, 64))
+    levels = [(4, 8), (8, 16), (16, 32), (32, 64)]
     pts = space_time_points(box_points(10000, -0.5, 0.5, seed=0), 0.25, 0.75, seed=0)
     u_exact = ex.u(pts[:, :3], pts[:, 3])
     pts_d = torch.from_numpy(pts).cuda()
@@ -75,8 +72,7 @@ def test_table61_dirichlet_convergence():
         say("  GPU: assembly %.3f s, rhs + GMRES %.3f s (%d iterations, residual %.1e), "
             "potentials %.3f s; errors on the host" % (t1 - t0, t2 - t1, info["iterations"],
                                                       info["rel_residual"], t3 - t2))
-        # GMRES stops on its estimate; the recomputed residual may exceed 1e-8 by rounding
-        assert info["converged"] and info["rel_residual"] <= 2e-8
+        assert info["converged"] and info["rel_residual"] <= 1e-8
         e_w = ds.l2_error_p0(v, t, nt, T, w, flux)
         wp = ds.project_p0p0(v, t, nt, T, flux)
         e_p = ds.l2_error_p0(v, t, nt, T, wp, flux)
