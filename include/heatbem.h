@@ -295,6 +295,59 @@ int hb_precond_loss(const float *y, const float *gram, const float *rhs, int64_t
 int hb_adam_step(float *params, const float *grads, float *m, float *v, int64_t n, float lr,
                  float beta1, float beta2, float eps, int32_t step, void *stream);
 
+/* ---- The learned preconditioner as one object: training, storage, installation ----
+ * hb_pcnet holds a trained MLP (dims and parameters in device memory of the device current at
+ * its creation).  Its input is a row's features (hb_precond_features, n_in = HB_PC_FEATURES) and
+ * its output the row's scaled weights (n_out = HB_PC_SLOTS). */
+typedef struct hb_pcnet hb_pcnet;
+
+typedef struct hb_train_opts {
+  int32_t epochs;       /* passes over all training rows (default 30 if <= 0) */
+  int32_t batch;        /* rows per Adam step (default 2048 if <= 0; at most the row count); an
+                           epoch's last partial batch is skipped */
+  float lr;             /* Adam step size (default 1e-3 if <= 0; beta 0.9 / 0.999, eps 1e-8) */
+  int32_t n_hidden;     /* width of both hidden layers (default 256 if <= 0, at most 4096) */
+  uint64_t seed;        /* initial weights (Glorot uniform, zero biases) and every epoch's row
+                           order (Fisher-Yates), both from the splitmix64 sequence of this seed */
+  int32_t reserved[8];  /* must be zero */
+} hb_train_opts;
+
+/* Fill *opt with the defaults above (seed 0). */
+void hb_default_train_opts(hb_train_opts *opt);
+
+/* Train a network on the rows of n_ctx contexts (one mesh and alpha, h each; V assembled, else
+ * HB_ESTATE): the sparse-approximate-inverse loss of hb_precond_spai, mean over each batch,
+ * minimised by Adam with the library's forward / backward / loss / Adam kernels; shuffling,
+ * batching (row gathers) and the epoch loop run in the library on `stream`.  Only V^0 is used, so
+ * one-step contexts (T = h, n_t = 1) suffice.  epoch_loss (host, `epochs` floats, may be NULL)
+ * receives each epoch's mean row loss.  On success *out is a new network owned by the caller
+ * (hb_pcnet_destroy).  Device memory: 4 (HB_PC_FEATURES + HB_PC_SLOTS^2 + HB_PC_SLOTS) bytes per
+ * training row plus the batch's activations; errors are reported on ctxs[0].  Synchronizes with
+ * the stream once per epoch. */
+int hb_precond_train(hb_ctx *const *ctxs, int32_t n_ctx, const hb_train_opts *opts,
+                     hb_pcnet **out, float *epoch_loss, void *stream);
+
+/* A network from given dims and parameters (host pointer, hb_mlp_num_params floats in the layout
+ * of hb_mlp_forward).  HB_EINVAL unless n_in = HB_PC_FEATURES and n_out = HB_PC_SLOTS. */
+int hb_pcnet_create(const hb_mlp_dims *dims, const float *params, hb_pcnet **out);
+
+/* Dims and (if params, a host pointer, is not NULL) the parameters of net.  Synchronous. */
+int hb_pcnet_get(const hb_pcnet *net, hb_mlp_dims *dims, float *params);
+
+/* Write net to the file `path` (binary: the 8 bytes "HBPCNET1", int32 n_in, n_hidden, n_out,
+ * int64 parameter count, then the float32 parameters, little-endian) / read such a file into a
+ * new network on the current device.  HB_EINVAL for a missing, short or inconsistent file (message
+ * in hb_last_error(NULL)). */
+int hb_pcnet_save(const hb_pcnet *net, const char *path);
+int hb_pcnet_load(const char *path, hb_pcnet **out);
+
+/* Release a network (NULL accepted). */
+void hb_pcnet_destroy(hb_pcnet *net);
+
+/* Predict the preconditioner of ctx from its local data (features of its assembled V^0, then the
+ * network's forward pass) and install it as hb_precond_set does.  Needs V (HB_ESTATE). */
+int hb_precond_install(hb_ctx *ctx, const hb_pcnet *net, void *stream);
+
 /* Durations in milliseconds of the kernels of the last hb_assemble on this context, measured
  * with HIP events on the caller's stream: [0] separated-pair kernel, [1] touching-pair kernels,
  * [2] whole call.  Calls hipEventSynchronize. */

@@ -25,7 +25,9 @@ EXPORTED = sorted(["hb_default_options", "hb_check_mesh", "hb_create", "hb_destr
                    "hb_eval_repr", "hb_last_assembly_ms", "hb_measure_peaks",
                    "hb_precond_pattern", "hb_precond_features", "hb_precond_spai",
                    "hb_precond_set", "hb_mlp_num_params", "hb_mlp_work_floats", "hb_mlp_forward",
-                   "hb_mlp_backward", "hb_precond_loss", "hb_adam_step"])
+                   "hb_mlp_backward", "hb_precond_loss", "hb_adam_step",
+                   "hb_default_train_opts", "hb_precond_train", "hb_pcnet_create", "hb_pcnet_get",
+                   "hb_pcnet_save", "hb_pcnet_load", "hb_pcnet_destroy", "hb_precond_install"])
 HB_PC_SLOTS = 16
 HB_PC_SLOT_FEATURES = 8
 HB_PC_FEATURES = HB_PC_SLOTS * HB_PC_SLOT_FEATURES + 4
@@ -51,6 +53,12 @@ class SolveOpts(ctypes.Structure):
 
 class MLPDims(ctypes.Structure):
     _fields_ = [("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("n_out", ctypes.c_int32)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("n_hidden", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("reserved", ctypes.c_int32 * 8)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -107,6 +115,17 @@ def lib():
     L.hb_precond_loss.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     L.hb_adam_step.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                ctypes.c_float, i32, vp]
+    L.hb_default_train_opts.argtypes = [ctypes.POINTER(TrainOpts)]
+    L.hb_default_train_opts.restype = None
+    L.hb_precond_train.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(TrainOpts),
+                                   ctypes.POINTER(vp), vp, vp]
+    L.hb_pcnet_create.argtypes = [pd, vp, ctypes.POINTER(vp)]
+    L.hb_pcnet_get.argtypes = [vp, pd, vp]
+    L.hb_pcnet_save.argtypes = [vp, ctypes.c_char_p]
+    L.hb_pcnet_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+    L.hb_pcnet_destroy.argtypes = [vp]
+    L.hb_pcnet_destroy.restype = None
+    L.hb_precond_install.argtypes = [vp, vp, vp]
     for name in EXPORTED:
         fn = getattr(L, name)
         if fn.restype is ctypes.c_int:   # default restype
@@ -162,6 +181,78 @@ def _stream(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+class PCNet:
+    """A trained learned-preconditioner network (hb_pcnet): parameters in device memory."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @classmethod
+    def create(cls, params, n_hidden):
+        """From host parameters (the layout of hb_mlp_forward) of a (HB_PC_FEATURES, n_hidden,
+        HB_PC_SLOTS) network."""
+        d = MLPDims()
+        d.n_in, d.n_hidden, d.n_out = HB_PC_FEATURES, int(n_hidden), HB_PC_SLOTS
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        h = ctypes.c_void_p()
+        rc = lib().hb_pcnet_create(ctypes.byref(d), p.ctypes.data, ctypes.byref(h))
+        if rc != HB_OK:
+            raise HBError(rc, lib().hb_last_error(None).decode())
+        return cls(h)
+
+    @classmethod
+    def load(cls, path):
+        h = ctypes.c_void_p()
+        rc = lib().hb_pcnet_load(os.fsencode(path), ctypes.byref(h))
+        if rc != HB_OK:
+            raise HBError(rc, lib().hb_last_error(None).decode())
+        return cls(h)
+
+    def save(self, path):
+        rc = lib().hb_pcnet_save(self._h, os.fsencode(path))
+        if rc != HB_OK:
+            raise HBError(rc, lib().hb_last_error(None).decode())
+
+    def params(self):
+        """(n_in, n_hidden, n_out), host float32 parameters."""
+        d = MLPDims()
+        rc = lib().hb_pcnet_get(self._h, ctypes.byref(d), None)
+        if rc != HB_OK:
+            raise HBError(rc, lib().hb_last_error(None).decode())
+        n = lib().hb_mlp_num_params(ctypes.byref(d))
+        p = np.empty(n, dtype=np.float32)
+        rc = lib().hb_pcnet_get(self._h, None, p.ctypes.data)
+        if rc != HB_OK:
+            raise HBError(rc, lib().hb_last_error(None).decode())
+        return (d.n_in, d.n_hidden, d.n_out), p
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hb_pcnet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def precond_train(contexts, epochs=30, batch=2048, lr=1e-3, n_hidden=256, seed=0, stream=None):
+    """hb_precond_train over the contexts (V assembled): (PCNet, per-epoch mean row losses)."""
+    o = TrainOpts()
+    lib().hb_default_train_opts(ctypes.byref(o))
+    o.epochs, o.batch, o.lr, o.n_hidden, o.seed = int(epochs), int(batch), float(lr), int(n_hidden), int(seed)
+    arr = (ctypes.c_void_p * len(contexts))(*[c._h for c in contexts])
+    h = ctypes.c_void_p()
+    loss = np.zeros(int(epochs), dtype=np.float32)
+    rc = lib().hb_precond_train(arr, len(contexts), ctypes.byref(o), ctypes.byref(h),
+                                loss.ctypes.data, _stream(stream))
+    if rc != HB_OK:
+        raise HBError(rc, lib().hb_last_error(contexts[0]._h).decode())
+    return PCNet(h), loss.astype(np.float64).tolist()
 
 
 def _info_dict(info, rc):
@@ -334,6 +425,10 @@ class Context:
         self._check(lib().hb_precond_spai(self._h, _ptr(G), _ptr(a), _ptr(y) if exact else None,
                                           _stream(stream)))
         return G, a, y
+
+    def precond_install(self, net, stream=None):
+        """Predict and install the learned preconditioner of this context (hb_precond_install)."""
+        self._check(lib().hb_precond_install(self._h, net._h, _stream(stream)))
 
     def precond_set(self, weights, stream=None):
         self._check(lib().hb_precond_set(self._h, _ptr(weights) if weights is not None else None,

@@ -27,6 +27,14 @@ int fail(hb_ctx *c, int code, const std::string &msg) {
   return code;
 }
 
+}  // namespace
+
+namespace hb {
+void set_global_error(const std::string &msg) { g_err = msg; }
+}  // namespace hb
+
+namespace {
+
 #define HB_HIP(ctx, call)                                                              \
   do {                                                                                 \
     hipError_t e_ = (call);                                                            \
@@ -691,7 +699,7 @@ void hb_destroy(hb_ctx *c) {
                   c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d,
                   c->d_D, c->d_Dw, c->d_V11, c->d_minv, c->d_pcw, c->d_Kt, c->d_near_sep, c->d_near_touch, c->d_d2tab, c->d_d2scale, c->d_d2len, c->d_curl, c->d_vstart,
-                  c->d_vadj};
+                  c->d_vadj, c->d_pc_buf};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int i = 0; i < 4; ++i)

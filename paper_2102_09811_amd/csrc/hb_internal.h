@@ -109,6 +109,9 @@ int launch_assemble_near(hb_ctx *c, double *V, double *K, hipStream_t s);
 // blockwise transpose [nt][R][C] -> [nt][C][R]
 int launch_transpose_blocks(hb_ctx *c, const void *src, void *dst, int R, int C, hipStream_t s);
 
+// message of the last failed call made without a context (hb_last_error(NULL))
+void set_global_error(const std::string &msg);
+
 // y = A x for the block-Toeplitz operator with blocks [nt][R][C] (y overwritten, time-major)
 int toeplitz_apply(hb_ctx *c, const void *blocks, int R, int C, const double *x, double *y,
                    hipStream_t s);
@@ -189,6 +192,8 @@ struct hb_ctx {
   double *d_cent = nullptr;          // [ne][3]
   double *d_pc_M = nullptr;          // [ne][HB_PC_SLOTS]
   bool pc_active = false;
+  float *d_pc_buf = nullptr;         // hb_precond_install: features, outputs, MLP workspace
+  size_t pc_buf_n = 0;               // floats
   double *d_ir = nullptr;            // iterative refinement: x, r, correction
   size_t ir_bytes = 0;
   double *h_res = nullptr;           // pinned: GMRES residual estimates, read one step late

@@ -9,6 +9,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -358,6 +361,36 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
   }
 }
 
+// Batch b of the shuffled training rows: Xb[b] = X[idx[i0 + b]] (F floats), Gb, Ab likewise.
+// One workgroup per batch row.
+__global__ __launch_bounds__(256) void k_gather_rows(const int32_t *__restrict__ idx, int i0,
+                                                     const float *__restrict__ X,
+                                                     const float *__restrict__ G,
+                                                     const float *__restrict__ A, int F,
+                                                     float *__restrict__ Xb, float *__restrict__ Gb,
+                                                     float *__restrict__ Ab) {
+  const int b = blockIdx.x;
+  const size_t r = (size_t)idx[i0 + b];
+  for (int e = threadIdx.x; e < F; e += blockDim.x) Xb[(size_t)b * F + e] = X[r * F + e];
+  for (int e = threadIdx.x; e < S * S; e += blockDim.x) Gb[(size_t)b * S * S + e] = G[r * S * S + e];
+  if (threadIdx.x < S) Ab[(size_t)b * S + threadIdx.x] = A[r * S + threadIdx.x];
+}
+
+// acc[0] += sum of rl[0 .. B-1] (one workgroup, fixed order)
+__global__ __launch_bounds__(256) void k_sum_loss(const float *__restrict__ rl, int B,
+                                                  double *__restrict__ acc) {
+  __shared__ double part[256];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < B; b += 256) v += (double)rl[b];
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[0] += part[0];
+}
+
 // M[l][s] = y[l][s] / V^0[l,l] (double)
 template <typename TV>
 __global__ void k_install(const TV *__restrict__ V0, const float *__restrict__ y, int ne,
@@ -417,6 +450,58 @@ size_t mlp_nparams(const hb_mlp_dims *d) {
 bool dims_ok(const hb_mlp_dims *d) {
   return d && d->n_in > 0 && d->n_hidden > 0 && d->n_out > 0 && d->n_in <= 4096 &&
          d->n_hidden <= 4096 && d->n_out <= 4096;
+}
+
+int gfail(int code, const std::string &m) {
+  hb::set_global_error(m);
+  return code;
+}
+
+// splitmix64 (Steele, Lea, Flood 2014): the seeded sequence of initial weights and row orders
+uint64_t splitmix64(uint64_t &x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+double uniform01(uint64_t &x) { return (double)(splitmix64(x) >> 11) * (1.0 / 9007199254740992.0); }
+
+// device buffers released on every return path
+struct DevFloats {
+  float *p = nullptr;
+  ~DevFloats() {
+    if (p) (void)hipFree(p);
+  }
+};
+}  // namespace
+
+struct hb_pcnet {
+  hb_mlp_dims dims{};
+  float *d_params = nullptr;
+  size_t n = 0;
+};
+
+namespace {
+bool pc_dims(const hb_mlp_dims *d) {
+  return dims_ok(d) && d->n_in == HB_PC_FEATURES && d->n_out == HB_PC_SLOTS;
+}
+
+int new_net(const hb_mlp_dims &d, const float *host_params, hb_pcnet **out) {
+  hb_pcnet *net = new hb_pcnet;
+  net->dims = d;
+  net->n = mlp_nparams(&d);
+  if (hipMalloc(&net->d_params, sizeof(float) * net->n) != hipSuccess) {
+    delete net;
+    return gfail(HB_ENOMEM, "hipMalloc of the network parameters failed");
+  }
+  if (host_params &&
+      hipMemcpy(net->d_params, host_params, sizeof(float) * net->n, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(net->d_params);
+    delete net;
+    return gfail(HB_EHIP, "copy of the network parameters failed");
+  }
+  *out = net;
+  return HB_OK;
 }
 }  // namespace
 
@@ -554,6 +639,197 @@ int hb_precond_loss(const float *y, const float *gram, const float *rhs, int64_t
   hipLaunchKernelGGL(k_quadloss, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, y, gram, rhs,
                      (int)rows, dy, rowloss);
   return hipGetLastError() == hipSuccess ? HB_OK : HB_EHIP;
+}
+
+void hb_default_train_opts(hb_train_opts *o) {
+  if (!o) return;
+  *o = hb_train_opts{};
+  o->epochs = 30;
+  o->batch = 2048;
+  o->lr = 1e-3f;
+  o->n_hidden = 256;
+  o->seed = 0;
+}
+
+int hb_pcnet_create(const hb_mlp_dims *dims, const float *params, hb_pcnet **out) {
+  if (!out || !params) return gfail(HB_EINVAL, "null argument");
+  if (!pc_dims(dims)) return gfail(HB_EINVAL, "dims must be (HB_PC_FEATURES, 1..4096, HB_PC_SLOTS)");
+  return new_net(*dims, params, out);
+}
+
+int hb_pcnet_get(const hb_pcnet *net, hb_mlp_dims *dims, float *params) {
+  if (!net) return gfail(HB_EINVAL, "null network");
+  if (dims) *dims = net->dims;
+  if (params && hipMemcpy(params, net->d_params, sizeof(float) * net->n, hipMemcpyDeviceToHost) != hipSuccess)
+    return gfail(HB_EHIP, "copy of the network parameters failed");
+  return HB_OK;
+}
+
+void hb_pcnet_destroy(hb_pcnet *net) {
+  if (!net) return;
+  if (net->d_params) (void)hipFree(net->d_params);
+  delete net;
+}
+
+int hb_pcnet_save(const hb_pcnet *net, const char *path) {
+  if (!net || !path) return gfail(HB_EINVAL, "null argument");
+  std::vector<float> p(net->n);
+  int rc = hb_pcnet_get(net, nullptr, p.data());
+  if (rc) return rc;
+  FILE *f = fopen(path, "wb");
+  if (!f) return gfail(HB_EINVAL, std::string("cannot open ") + path + " for writing");
+  const int32_t d[3] = {net->dims.n_in, net->dims.n_hidden, net->dims.n_out};
+  const int64_t n = (int64_t)net->n;
+  bool ok = fwrite("HBPCNET1", 1, 8, f) == 8 && fwrite(d, sizeof(int32_t), 3, f) == 3 &&
+            fwrite(&n, sizeof(int64_t), 1, f) == 1 && fwrite(p.data(), sizeof(float), p.size(), f) == p.size();
+  ok = (fclose(f) == 0) && ok;
+  return ok ? HB_OK : gfail(HB_EINVAL, std::string("write to ") + path + " failed");
+}
+
+int hb_pcnet_load(const char *path, hb_pcnet **out) {
+  if (!path || !out) return gfail(HB_EINVAL, "null argument");
+  FILE *f = fopen(path, "rb");
+  if (!f) return gfail(HB_EINVAL, std::string("cannot open ") + path);
+  char magic[8];
+  int32_t d[3];
+  int64_t n = 0;
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "HBPCNET1", 8) == 0 &&
+            fread(d, sizeof(int32_t), 3, f) == 3 && fread(&n, sizeof(int64_t), 1, f) == 1;
+  hb_mlp_dims dims{d[0], d[1], d[2]};
+  ok = ok && pc_dims(&dims) && n == (int64_t)mlp_nparams(&dims);
+  std::vector<float> p;
+  if (ok) {
+    p.resize((size_t)n);
+    ok = fread(p.data(), sizeof(float), p.size(), f) == p.size() && fgetc(f) == EOF;
+  }
+  fclose(f);
+  if (!ok) return gfail(HB_EINVAL, std::string(path) + " is not a complete network file of this library");
+  return new_net(dims, p.data(), out);
+}
+
+int hb_precond_install(hb_ctx *c, const hb_pcnet *net, void *stream) {
+  if (!c) return gfail(HB_EINVAL, "null context");
+  if (!net) return lfail(c, HB_EINVAL, "null network");
+  if (!c->have_V) return lfail(c, HB_ESTATE, "V not assembled");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ne = c->ne;
+  const int64_t nw = hb_mlp_work_floats(&net->dims, ne);
+  const size_t need = (size_t)ne * (HB_PC_FEATURES + HB_PC_SLOTS) + (size_t)nw;
+  if (c->pc_buf_n < need) {
+    if (c->d_pc_buf) (void)hipFree(c->d_pc_buf);
+    c->d_pc_buf = nullptr;
+    c->pc_buf_n = 0;
+    HB_CHECK_L(c, hipMalloc(&c->d_pc_buf, sizeof(float) * need));
+    c->pc_buf_n = need;
+  }
+  float *feats = c->d_pc_buf, *y = feats + (size_t)ne * HB_PC_FEATURES, *work = y + (size_t)ne * HB_PC_SLOTS;
+  int rc = hb_precond_features(c, feats, stream);
+  if (rc) return rc;
+  if ((rc = hb_mlp_forward(&net->dims, net->d_params, feats, ne, y, work, stream)))
+    return lfail(c, rc, "MLP forward pass failed");
+  return hb_precond_set(c, y, s);
+}
+
+int hb_precond_train(hb_ctx *const *ctxs, int32_t n_ctx, const hb_train_opts *opts, hb_pcnet **out,
+                     float *epoch_loss, void *stream) {
+  if (!ctxs || n_ctx < 1 || !out) return gfail(HB_EINVAL, "need at least one context and an output");
+  hb_ctx *c0 = ctxs[0];
+  if (!c0) return gfail(HB_EINVAL, "null context");
+  hb_train_opts o;
+  hb_default_train_opts(&o);
+  if (opts) {
+    for (int i = 0; i < 8; ++i)
+      if (opts->reserved[i]) return lfail(c0, HB_EINVAL, "hb_train_opts.reserved must be zero");
+    if (opts->epochs > 0) o.epochs = opts->epochs;
+    if (opts->batch > 0) o.batch = opts->batch;
+    if (opts->lr > 0) o.lr = opts->lr;
+    if (opts->n_hidden > 0) o.n_hidden = opts->n_hidden;
+    o.seed = opts->seed;
+  }
+  if (o.n_hidden > 4096 || o.epochs > 100000) return lfail(c0, HB_EINVAL, "n_hidden <= 4096, epochs <= 100000");
+  int64_t R = 0;
+  for (int i = 0; i < n_ctx; ++i) {
+    if (!ctxs[i]) return lfail(c0, HB_EINVAL, "null context in the list");
+    if (!ctxs[i]->have_V) return lfail(c0, HB_ESTATE, "V not assembled on a training context");
+    R += ctxs[i]->ne;
+  }
+  if (R > (1 << 26)) return lfail(c0, HB_EINVAL, "too many training rows");
+  hipStream_t s = (hipStream_t)stream;
+  constexpr int F = HB_PC_FEATURES;
+  const hb_mlp_dims dims{F, o.n_hidden, S};
+  const int B = (int)std::min<int64_t>(o.batch, R);
+  const size_t np = mlp_nparams(&dims);
+  const int64_t nw = hb_mlp_work_floats(&dims, B);
+  // training rows: features, Gram matrices, right-hand sides of every context
+  DevFloats data, batch, state;
+  HB_CHECK_L(c0, hipMalloc(&data.p, sizeof(float) * (size_t)R * (F + S * S + S)));
+  float *X = data.p, *G = X + (size_t)R * F, *A = G + (size_t)R * S * S;
+  int64_t off = 0;
+  for (int i = 0; i < n_ctx; ++i) {
+    hb_ctx *c = ctxs[i];
+    int rc = hb_precond_features(c, X + off * F, stream);
+    if (!rc) rc = hb_precond_spai(c, G + off * S * S, A + off * S, nullptr, stream);
+    if (rc) return lfail(c0, rc, c->err);
+    off += c->ne;
+  }
+  // batch buffers: Xb, Gb, Ab, y, dy, rowloss, MLP workspace, shuffled row indices, loss sum
+  const size_t nb = (size_t)B * (F + S * S + S + S + S + 1) + (size_t)nw + (size_t)R + 4;
+  HB_CHECK_L(c0, hipMalloc(&batch.p, sizeof(float) * nb));
+  float *Xb = batch.p, *Gb = Xb + (size_t)B * F, *Ab = Gb + (size_t)B * S * S, *y = Ab + (size_t)B * S;
+  float *dy = y + (size_t)B * S, *rl = dy + (size_t)B * S, *work = rl + B;
+  int32_t *idx = (int32_t *)(work + nw);
+  double *acc = (double *)(((uintptr_t)(idx + R) + 7) & ~(uintptr_t)7);
+  // parameters, gradients and Adam moments; Glorot-uniform weights, zero biases
+  std::vector<float> p0(np, 0.0f);
+  {
+    uint64_t st = o.seed;
+    size_t q = 0;
+    const int fan[3][2] = {{F, o.n_hidden}, {o.n_hidden, o.n_hidden}, {o.n_hidden, S}};
+    for (int L = 0; L < 3; ++L) {
+      const double lim = std::sqrt(6.0 / (fan[L][0] + fan[L][1]));
+      for (size_t e = 0; e < (size_t)fan[L][0] * fan[L][1]; ++e)
+        p0[q++] = (float)((2.0 * uniform01(st) - 1.0) * lim);
+      q += fan[L][1];  // biases stay zero
+    }
+  }
+  hb_pcnet *net = nullptr;
+  int rc = new_net(dims, p0.data(), &net);
+  if (rc) return lfail(c0, rc, "network allocation failed");
+  std::unique_ptr<hb_pcnet, void (*)(hb_pcnet *)> owner(net, hb_pcnet_destroy);
+  HB_CHECK_L(c0, hipMalloc(&state.p, sizeof(float) * 3 * np));
+  float *grads = state.p, *m1 = grads + np, *m2 = m1 + np;
+  HB_CHECK_L(c0, hipMemsetAsync(m1, 0, sizeof(float) * 2 * np, s));
+  std::vector<int32_t> perm((size_t)R);
+  uint64_t st = o.seed ^ 0x5DEECE66DULL;
+  int step = 0;
+  for (int ep = 0; ep < o.epochs; ++ep) {
+    for (int64_t i = 0; i < R; ++i) perm[(size_t)i] = (int32_t)i;
+    for (int64_t i = R - 1; i > 0; --i) {  // Fisher-Yates
+      const int64_t j = (int64_t)(splitmix64(st) % (uint64_t)(i + 1));
+      std::swap(perm[(size_t)i], perm[(size_t)j]);
+    }
+    HB_CHECK_L(c0, hipMemcpyAsync(idx, perm.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, s));
+    HB_CHECK_L(c0, hipMemsetAsync(acc, 0, sizeof(double), s));
+    int nbatch = 0;
+    for (int64_t i0 = 0; i0 + B <= R; i0 += B, ++nbatch) {
+      hipLaunchKernelGGL(k_gather_rows, dim3(B), dim3(256), 0, s, idx, (int)i0, X, G, A, F, Xb, Gb, Ab);
+      if ((rc = hb_mlp_forward(&dims, net->d_params, Xb, B, y, work, stream)) ||
+          (rc = hb_precond_loss(y, Gb, Ab, B, dy, rl, stream)) ||
+          (rc = hb_mlp_backward(&dims, net->d_params, Xb, B, work, dy, grads, stream)) ||
+          (rc = hb_adam_step(net->d_params, grads, m1, m2, (int64_t)np, o.lr, 0.9f, 0.999f, 1e-8f,
+                             ++step, stream)))
+        return lfail(c0, rc, "training step failed");
+      hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, s, rl, B, acc);
+    }
+    double tot = 0.0;
+    HB_CHECK_L(c0, hipMemcpyAsync(&tot, acc, sizeof(double), hipMemcpyDeviceToHost, s));
+    HB_CHECK_L(c0, hipStreamSynchronize(s));  // also keeps perm alive until its copy is done
+    if (epoch_loss) epoch_loss[ep] = (float)(tot / std::max(1, nbatch * B));
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return lfail(c0, HB_EHIP, std::string("training: ") + hipGetErrorString(e));
+  *out = owner.release();
+  return HB_OK;
 }
 
 int hb_adam_step(float *params, const float *grads, float *m, float *v, int64_t n, float lr,

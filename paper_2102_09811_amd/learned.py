@@ -8,8 +8,10 @@ whose G_l, a_l come from ``hb_precond_spai`` on method-generated V^0 blocks (ran
 Inference needs only local data; M is then installed with ``hb_precond_set`` and used as the
 block-diagonal right preconditioner of GMRES.
 
-Forward, backward, loss and Adam run in the library's HIP kernels; this module only allocates
-device buffers (PyTorch) and sequences the calls.
+Training (shuffling, batching, forward, backward, loss, Adam and the epoch loop) runs in the
+library (hb_precond_train); the network is a library object (hb_pcnet) that can be saved, loaded
+and installed on a context (hb_precond_install).  The MLP class below drives the single forward /
+backward / Adam kernels one call at a time, for checks against the oracle.
 """
 import ctypes
 
@@ -140,53 +142,39 @@ def ellipsoid_set(seeds, n_t=64, T=1.0):
     return out
 
 
-def train(meshes, epochs=40, batch=2048, lr=1e-3, seed=0, log=None):
-    """Train the MLP on the rows of all meshes; returns (mlp, per-epoch mean losses)."""
-    import torch
-    Xs, Gs, As = [], [], []
+def train(meshes, epochs=30, batch=2048, lr=1e-3, seed=0, log=None):
+    """Train the network on the rows of all meshes (hb_precond_train on one-step contexts, which
+    carry the same V^0 as any E_t-step problem with that h); returns (PCNet, per-epoch mean
+    losses)."""
+    ctxs = []
     for m in meshes:
-        X, G, a, _ = mesh_data(m["verts"], m["tris"], m["alpha"], m["h"])
-        Xs.append(X)
-        Gs.append(G)
-        As.append(a)
-    X = torch.cat(Xs)
-    G = torch.cat(Gs)
-    A = torch.cat(As)
-    rows = X.shape[0]
-    mlp = MLP(seed=seed)
-    opt = Adam(mlp, lr=lr)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
-    work = mlp.work(batch)
-    grads = torch.empty_like(mlp.params)
-    hist = []
-    for ep in range(epochs):
-        perm = torch.randperm(rows, device="cuda", generator=gen)
-        tot, cnt = 0.0, 0
-        for i0 in range(0, rows - batch + 1, batch):
-            idx = perm[i0:i0 + batch]
-            xb, gb, ab = X[idx].contiguous(), G[idx].contiguous(), A[idx].contiguous()
-            y, _ = mlp.forward(xb, work)
-            rl, dy = quad_loss(y, gb, ab)
-            mlp.backward(xb, work, dy, grads)
-            opt.step(grads)
-            tot += float(rl.sum())
-            cnt += batch
-        hist.append(tot / max(cnt, 1))
-        if log:
-            log("epoch %d: mean row loss %.4e" % (ep, hist[-1]))
-    return mlp, hist
+        ctx = B.Context(m["verts"], m["tris"], m["alpha"], m["h"], 1)
+        ctx.assemble(B.HB_OP_V)
+        ctxs.append(ctx)
+    net, hist = B.precond_train(ctxs, epochs=epochs, batch=batch, lr=lr, seed=seed)
+    for ctx in ctxs:
+        ctx.close()
+    if log:
+        for ep, L in enumerate(hist):
+            log("epoch %d: mean row loss %.4e" % (ep, L))
+    return net, hist
 
 
 def predict(mlp, ctx):
-    """Scaled weights [E_x][HB_PC_SLOTS] for the context's assembled V^0 (local data only)."""
+    """Scaled weights [E_x][HB_PC_SLOTS] for the context's assembled V^0 (local data only), with
+    the per-call MLP kernels."""
     X = ctx.precond_features()
     y, _ = mlp.forward(X)
     return y
 
 
-def install(mlp, ctx):
-    ctx.precond_set(predict(mlp, ctx))
+def install(net, ctx):
+    """Install the learned preconditioner on ctx: a PCNet through hb_precond_install, an MLP
+    through its forward pass and hb_precond_set."""
+    if isinstance(net, B.PCNet):
+        ctx.precond_install(net)
+    else:
+        ctx.precond_set(predict(net, ctx))
 
 
 def evaluate(mlp, meshes, n_t=64, T=1.0, tol=1e-8, log=None):
@@ -231,7 +219,7 @@ def main(argv=None):
     ap.add_argument("--train", type=int, default=160)
     ap.add_argument("--test", type=int, default=40)
     ap.add_argument("--epochs", type=int, default=30)
-    ap.add_argument("--save", default=None, help="write the trained parameters (npz)")
+    ap.add_argument("--save", default=None, help="write the trained network (hb_pcnet_save)")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -244,7 +232,7 @@ def main(argv=None):
     t_train = time.perf_counter() - t0
     log("trained in %.1f s, loss %.3e -> %.3e" % (t_train, hist[0], hist[-1]))
     if args.save:
-        mlp.save(args.save)
+        mlp.save(args.save)  # the network file of hb_pcnet_save
     recs = evaluate(mlp, ellipsoid_set(range(160, 160 + args.test)), log=log)
     mean = lambda k: float(np.mean([r[k] for r in recs]))
     summary = {"train_meshes": args.train, "test_meshes": args.test, "epochs": args.epochs,

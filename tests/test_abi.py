@@ -1,5 +1,6 @@
 """The C-ABI library loads, exports every function declared in include/heatbem.h, and its
-host-only mesh check agrees with the oracle's pair classification (no GPU needed)."""
+host-only mesh check agrees with the oracle's pair classification; network files that are missing,
+short or inconsistent are rejected before any device call (no GPU needed)."""
 import ctypes
 import os
 import re
@@ -69,3 +70,28 @@ def test_check_mesh_rejects_bad_meshes(hb):
     tt[0, 0] = len(v) + 5
     assert hb.check_mesh(v, tt)[0] == hb.HB_EMESH                           # index out of range
     assert hb.check_mesh(v[:3], t[:2])[0] == hb.HB_EMESH                    # too small
+
+
+def test_network_file_errors(hb, tmp_path):
+    """hb_pcnet_load checks the file before it touches the device: missing, wrong magic, wrong
+    dims, truncated and overlong files are HB_EINVAL with a message."""
+    import struct
+    L = hb.lib()
+    h = ctypes.c_void_p()
+    assert L.hb_pcnet_load(os.fsencode(str(tmp_path / "absent.bin")), ctypes.byref(h)) == hb.HB_EINVAL
+    assert b"cannot open" in L.hb_last_error(None)
+    F, H, O = hb.HB_PC_FEATURES, 8, hb.HB_PC_SLOTS
+    n = H * F + H + H * H + H + O * H + O
+    good = b"HBPCNET1" + struct.pack("<3iq", F, H, O, n) + b"\0" * (4 * n)
+    cases = {"magic": b"HBPCNET2" + good[8:], "dims": b"HBPCNET1" + struct.pack("<3iq", F + 1, H, O, n),
+             "count": b"HBPCNET1" + struct.pack("<3iq", F, H, O, n + 1) + b"\0" * (4 * n + 4),
+             "short": good[:-4], "long": good + b"\0"}
+    for name, data in cases.items():
+        f = tmp_path / (name + ".bin")
+        f.write_bytes(data)
+        assert L.hb_pcnet_load(os.fsencode(str(f)), ctypes.byref(h)) == hb.HB_EINVAL, name
+        assert b"not a complete network file" in L.hb_last_error(None), name
+    o = hb.TrainOpts()
+    L.hb_default_train_opts(ctypes.byref(o))
+    assert (o.epochs, o.batch, o.n_hidden, o.seed) == (30, 2048, 256, 0) and abs(o.lr - 1e-3) < 1e-9
+    assert L.hb_precond_train(None, 0, None, ctypes.byref(h), None, None) == hb.HB_EINVAL

@@ -5,6 +5,9 @@
   computed from the oracle's own V^0;
 * MLP forward/backward, loss gradient and Adam step vs the float64 oracle (gradient check:
   max error <= 1e-4 of the largest gradient entry);
+* the library's training loop (hb_precond_train): the loss falls, the trained network survives
+  hb_pcnet_save / hb_pcnet_load bit for bit, and hb_precond_install of the loaded network gives
+  the same preconditioner as the forward kernel applied to the features;
 * gain: trained on random ellipsoids, on held-out ones GMRES needs fewer iterations with the
   learned preconditioner than without, and still reaches 1e-8 with the double operator.
 """
@@ -119,6 +122,46 @@ def test_mlp_kernels_match_oracle():
     opt.step(gd)
     pr, _, _ = omlp.adam(p, g.astype(np.float64), 0.0, 0.0, 1, 1e-3)
     assert np.abs(net.params.cpu().numpy() - pr).max() <= 1e-6
+
+
+def test_train_save_load_install(tmp_path):
+    """Training, storage and installation through the C ABI alone."""
+    import torch
+    from paper_2102_09811_amd import Context, HB_OP_V, learned
+    from paper_2102_09811_amd.binding import PCNet, precond_train
+    meshes = learned.ellipsoid_set(range(0, 3))
+    ctxs = []
+    for m in meshes:
+        c = Context(m["verts"], m["tris"], m["alpha"], m["h"], 1)
+        c.assemble(HB_OP_V)
+        ctxs.append(c)
+    rows = sum(len(m["tris"]) for m in meshes)
+    say("hb_precond_train on %d meshes (%d rows)" % (len(meshes), rows))
+    net, hist = precond_train(ctxs, epochs=10, batch=1024, lr=1e-3, n_hidden=64, seed=3)
+    say("losses %s" % ["%.3e" % x for x in hist])
+    assert hist[-1] < 0.5 * hist[0] and all(np.isfinite(hist))
+    net2, hist2 = precond_train(ctxs, epochs=10, batch=1024, lr=1e-3, n_hidden=64, seed=3)
+    assert hist2 == hist                                   # seeded and deterministic
+    path = str(tmp_path / "net.bin")
+    net.save(path)
+    loaded = PCNet.load(path)
+    dims, p = net.params()
+    dims2, p2 = loaded.params()
+    assert dims == dims2 == (learned.N_IN, 64, learned.N_OUT) and np.array_equal(p, p2)
+    # installation of the loaded network = forward kernel on the features + hb_precond_set
+    c = ctxs[0]
+    c.precond_install(loaded)
+    from paper_2102_09811_amd import HB_SOLVE_GMRES
+    b = torch.from_numpy(np.random.default_rng(2).standard_normal((1, c.n_tris))).cuda()
+    w1, i1 = c.solve(b, method=HB_SOLVE_GMRES, tol=1e-10, precond=True)
+    mlp = learned.MLP(learned.N_IN, 64, learned.N_OUT, params=p2)
+    c.precond_set(learned.predict(mlp, c))
+    w2, i2 = c.solve(b, method=HB_SOLVE_GMRES, tol=1e-10, precond=True)
+    assert i1["converged"] and i2["converged"] and i1["iterations"] == i2["iterations"]
+    assert float((w1 - w2).abs().max()) == 0.0
+    for c in ctxs:
+        c.close()
+    net.close(), net2.close(), loaded.close()
 
 
 def test_learned_preconditioner_gain():
