@@ -45,6 +45,10 @@ def lib():
                                   _dp, _dp]
         L.or_assemble_plain.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, i32, _ip, i32, i32,
                                         _dp, _dp]
+        L.or_assemble_nonuniform.argtypes = [_dp, i32, _ip, i32, f64, _dp, i32, i32, _ip, i32,
+                                             _dp, _dp]
+        L.or_nu_blockfun.argtypes = [i32, _dp, _ip, _ip, i32, _dp, f64, _dp]
+        L.or_nu_blockfun.restype = None
         L.or_repr.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, _dp, _dp, _dp, i32, i32, i32,
                               _dp, _dp]
         _lib = L
@@ -151,6 +155,33 @@ def assemble_plain(verts, tris, alpha, T, n_t, rows=None, ss_order=4, threads=0)
     if rc != 0:
         raise ValueError("or_assemble_plain failed (%d)" % rc)
     return V, K
+
+
+def assemble_nonuniform(verts, tris, alpha, t_nodes, rows=None, ss_order=4):
+    """Blocks on the non-uniform time grid t_nodes (0 = t_0 < ... < t_nt): V (nb, len(rows), E_x)
+    and K (nb, len(rows), N_x), nb = nt (nt + 1) / 2, block (k, i) (0 <= i <= k < nt) at index
+    k (k + 1) / 2 + i."""
+    verts, tris, tn = _f64(verts), _i32(tris), _f64(t_nodes)
+    ne, nv, nt = len(tris), len(verts), len(tn) - 1
+    rows = _i32(np.arange(ne) if rows is None else rows)
+    nb = nt * (nt + 1) // 2
+    V = np.empty((nb, len(rows), ne))
+    K = np.empty((nb, len(rows), nv))
+    rc = lib().or_assemble_nonuniform(verts.ravel(), nv, tris.ravel(), ne, float(alpha), tn, nt,
+                                      ss_order, rows, len(rows), V, K)
+    if rc != 0:
+        raise ValueError("or_assemble_nonuniform failed (%d)" % rc)
+    return V, K
+
+
+def nu_blockfun(which, rho, k, i, t_nodes, alpha):
+    """Per-point block integrals on a grid: V^{k,i}(rho) ('V') or K^{k,i}(rho) / (r . n) ('K')."""
+    rho, k, i = np.broadcast_arrays(_f64(rho), np.asarray(k), np.asarray(i))
+    rho, k, i = _f64(rho.ravel()), _i32(k.ravel()), _i32(i.ravel())
+    out = np.empty_like(rho)
+    lib().or_nu_blockfun({"V": 0, "K": 1}[which], rho, k, i, len(rho), _f64(t_nodes), float(alpha),
+                         out)
+    return out
 
 
 def repr_eval(verts, tris, alpha, T, n_t, w, u, pts, rule_kind=0, rule_order=7):

@@ -26,6 +26,8 @@
  *   - the single layer between p1 functions, V_h^{11}                (Sec. 6.1, preconditioner of D_h)
  *   - a plain double-precision assembly in the paper's level order, the timed CPU baseline
  *     (Sec. 5.1; not a parity reference)
+ *   - blocks V^{k,i}_h, K^{k,i}_h on non-uniform time grids (the outlook of Sec. 7 with the block
+ *     integrals of Sec. 3.1, 3.2 at general interval endpoints)
  *
  * Readings where the paper is silent (each is also listed in the design notes):
  *   - Small-argument series for the double-layer bracket (it cancels like 1/z^2 when
@@ -676,6 +678,140 @@ int or_assemble(const double *verts, int nv, const int32_t *tris, int ne, double
   for (size_t i = 0; i < (size_t)nt * nrows * nv; ++i) K[i] = (double)KL[i];
   free(VL); free(KL);
   return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Non-uniform time steps (the paper's closing outlook, Sec. 7; the block integrals of Sec. 3.1  */
+/* and 3.2 at general interval endpoints).  Nodes 0 = t_0 < t_1 < ... < t_nt; test interval k is */
+/* (t_k, t_{k+1}), trial interval i is (t_i, t_{i+1}), i <= k.  The block integral               */
+/*   V^{k,i}(r) = int_{I_k} int_{I_i} G_alpha(rho, t - tau) dtau dt                             */
+/* is, since d^2 G^{dtau dt} / d delta^2 = -G_alpha, for i < k the four-term difference           */
+/*   F(t_k - t_i) + F(t_{k+1} - t_{i+1}) - F(t_{k+1} - t_i) - F(t_k - t_{i+1})   (F = G^{dtau dt}),  */
+/* and for i = k (tau < t only): h_k G^{dtau}(rho, 0) - F(h_k) + F(0); K^{k,i} / (r . n_y) the same  */
+/* with the normal derivatives.  Where the four terms cancel (the gap s1 = t_k - t_{i+1} at least */
+/* the width s4 - s1 of the support, s4 = t_{k+1} - t_i), the same integral is evaluated as      */
+/*   int_{s1}^{s4} w(s) G_alpha(rho, s) ds,                                                      */
+/* w the trapezoid that is the convolution of the two interval indicators (rising on            */
+/* [s1, s1 + min(h_k, h_i)], flat at min(h_k, h_i), falling to 0 at s4), by Gauss-Legendre with   */
+/* NU_NT nodes on each of its three linear pieces (the integrand is analytic there: its only     */
+/* singularity, s = 0, lies at least one support width to the left).                           */
+/* ------------------------------------------------------------------------------------------ */
+#define NU_NT 16
+static void nu_trapezoid(ld rho, ld s1, ld a, ld b, ld alpha, ld out[2]) {
+  static ld gx[NU_NT], gw[NU_NT];
+  static int ready = 0;
+  if (!ready) {
+#pragma omp critical(oracle_nu_init)
+    {
+      if (!ready) {
+        gauss_legendre01(NU_NT, gx, gw);
+        __sync_synchronize();
+        ready = 1;
+      }
+    }
+  }
+  const ld cG = 1.0L / ((4.0L * PI_L * alpha) * sqrtl(4.0L * PI_L * alpha));
+  const ld cK = 1.0L / (16.0L * PI_L * alpha * sqrtl(PI_L * alpha));
+  const ld mn = a < b ? a : b, mx = a < b ? b : a;
+  /* pieces [s1, s1 + mn] (w = s - s1), [s1 + mn, s1 + mx] (w = mn), [s1 + mx, s1 + a + b] (w = s4 - s) */
+  const ld lo[3] = {s1, s1 + mn, s1 + mx}, len[3] = {mn, mx - mn, mn};
+  ld sV = 0.0L, sK = 0.0L;
+  for (int piece = 0; piece < 3; ++piece) {
+    if (len[piece] <= 0.0L) continue;
+    for (int j = 0; j < NU_NT; ++j) {
+      const ld s = lo[piece] + len[piece] * gx[j];
+      const ld wt = piece == 0 ? s - s1 : (piece == 1 ? mn : s1 + a + b - s);
+      const ld e = expl(-rho * rho / (4.0L * alpha * s));
+      const ld is32 = 1.0L / (s * sqrtl(s));
+      sV += len[piece] * gw[j] * wt * cG * is32 * e;
+      sK += len[piece] * gw[j] * wt * cK * is32 / s * e;
+    }
+  }
+  out[0] = sV;
+  out[1] = sK;
+}
+
+/* V^{k,i}(r) (out[0]) and K^{k,i}(r) / (r . n_y) (out[1]) on the grid t (nt + 1 nodes). */
+void or_nu_block(ld rho, int k, int i, const double *t, ld alpha, ld out[2]) {
+  const ld hk = (ld)t[k + 1] - (ld)t[k], hi = (ld)t[i + 1] - (ld)t[i];
+  if (i == k) {
+    out[0] = hk * or_g1(rho, 0.0L, alpha) - or_F(rho, hk, alpha) + or_F(rho, 0.0L, alpha);
+    out[1] = hk * or_g1n_rn(rho, 0.0L, alpha) - or_Fn_rn(rho, hk, alpha) + or_Fn_rn(rho, 0.0L, alpha);
+    return;
+  }
+  const ld s1 = (ld)t[k] - (ld)t[i + 1], s4 = (ld)t[k + 1] - (ld)t[i];
+  if (s1 >= s4 - s1) {
+    nu_trapezoid(rho, s1, hk, hi, alpha, out);
+    return;
+  }
+  const ld d1 = (ld)t[k] - (ld)t[i], d2 = (ld)t[k + 1] - (ld)t[i + 1];
+  out[0] = or_F(rho, d1, alpha) + or_F(rho, d2, alpha) - or_F(rho, s4, alpha) - or_F(rho, s1, alpha);
+  out[1] = or_Fn_rn(rho, d1, alpha) + or_Fn_rn(rho, d2, alpha) - or_Fn_rn(rho, s4, alpha) -
+           or_Fn_rn(rho, s1, alpha);
+}
+
+/* Blocks V^{k,i}_h (p0 x p0) and K^{k,i}_h (p0 x p1) of the test rows `rows` on the grid t, all
+ * 0 <= i <= k < nt, packed by block rows: block (k, i) at index k (k + 1) / 2 + i.
+ * V out: [nb][nrows][ne], K out: [nb][nrows][nv], nb = nt (nt + 1) / 2.  The same spatial rules
+ * as or_assemble. */
+int or_assemble_nonuniform(const double *verts, int nv, const int32_t *tris, int ne, double alpha,
+                           const double *t, int nt, int ss_order, const int32_t *rows, int nrows,
+                           double *V, double *K) {
+  if (nt < 1 || ne < 1 || nv < 3 || alpha <= 0 || t[0] != 0.0) return -1;
+  for (int k = 0; k < nt; ++k)
+    if (!(t[k + 1] > t[k])) return -1;
+  prepare_rules(ss_order);
+  const int nb = nt * (nt + 1) / 2;
+  memset(V, 0, sizeof(double) * (size_t)nb * nrows * ne);
+  memset(K, 0, sizeof(double) * (size_t)nb * nrows * nv);
+  const ld al = (ld)alpha;
+#pragma omp parallel
+  {
+    qpt_t *q = (qpt_t *)malloc(sizeof(qpt_t) * max_points(ss_order));
+    ld *vd = (ld *)malloc(sizeof(ld) * nb);
+    ld *kd = (ld *)malloc(sizeof(ld) * 3 * nb);
+    tri_t B;
+#pragma omp for schedule(dynamic)
+    for (int r = 0; r < nrows; ++r) {
+      for (int m = 0; m < ne; ++m) {
+        make_tri(verts, tris + 3 * m, &B);
+        const int n = pair_points(verts, tris, rows[r], m, q);
+        for (int e = 0; e < nb; ++e) { vd[e] = 0.0L; kd[3 * e] = kd[3 * e + 1] = kd[3 * e + 2] = 0.0L; }
+        for (int j = 0; j < n; ++j) {
+          const ld rr[3] = {q[j].x[0] - q[j].y[0], q[j].x[1] - q[j].y[1], q[j].x[2] - q[j].y[2]};
+          const ld rho = sqrtl(rr[0] * rr[0] + rr[1] * rr[1] + rr[2] * rr[2]);
+          const ld rn = rr[0] * B.n[0] + rr[1] * B.n[1] + rr[2] * B.n[2];
+          for (int k = 0; k < nt; ++k)
+            for (int i = 0; i <= k; ++i) {
+              ld o[2];
+              or_nu_block(rho, k, i, t, al, o);
+              const int e = k * (k + 1) / 2 + i;
+              vd[e] += q[j].W * o[0];
+              const ld kv = q[j].W * rn * o[1];
+              for (int c = 0; c < 3; ++c) kd[3 * e + c] += kv * q[j].phi[c];
+            }
+        }
+        for (int e = 0; e < nb; ++e) {
+          V[((size_t)e * nrows + r) * ne + m] = (double)vd[e];
+          for (int c = 0; c < 3; ++c)
+            K[((size_t)e * nrows + r) * nv + tris[3 * m + c]] += (double)kd[3 * e + c];
+        }
+      }
+    }
+    free(q); free(vd); free(kd);
+  }
+  return 0;
+}
+
+/* Per-point block functions on a grid (tests): out[e] = V^{k,i}(rho_e) (which 0) or
+ * K^{k,i}(rho_e) / (r . n_y) (which 1) for the blocks (k_e, i_e). */
+void or_nu_blockfun(int which, const double *rho, const int32_t *k, const int32_t *i, int n,
+                    const double *t, double alpha, double *out) {
+  for (int e = 0; e < n; ++e) {
+    ld o[2];
+    or_nu_block((ld)rho[e], k[e], i[e], t, (ld)alpha, o);
+    out[e] = (double)o[which];
+  }
 }
 
 /* ------------------------------------------------------------------------------------------ */
