@@ -98,6 +98,30 @@ int hb_check_mesh(const double *verts, int64_t n_verts, const int32_t *tris, int
 int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t *tris,
               int64_t n_tris, double alpha, double T, int32_t n_t, const hb_options *opt);
 
+/* Context on a non-uniform time grid (the paper's outlook, Sec. 7: the block integrals of
+ * Sec. 3.1 and 3.2 at general interval endpoints).  t_nodes: host, n_t + 1 doubles,
+ * 0 = t_0 < t_1 < ... < t_{n_t} = T (finite, strictly increasing), 1 <= n_t <= 4096; other
+ * arguments as for hb_create (opt->storage must be HB_DTYPE_F64).  The Toeplitz structure is
+ * lost: the operators are block lower triangular with n_t (n_t + 1) / 2 blocks
+ *   V^{k,i}[l][m] = int_{I_k} int_{I_i} int_{gamma_l} int_{gamma_m} G_alpha(x - y, t - tau),
+ * 0 <= i <= k < n_t (I_k = (t_k, t_{k+1})), and K^{k,i} likewise (p1 trial), block (k, i)
+ * stored at index k (k + 1) / 2 + i.  Per point pair a block is either the four-term difference
+ * G^{dtau dt}(t_k - t_i) + G^{dtau dt}(t_{k+1} - t_{i+1}) - G^{dtau dt}(t_{k+1} - t_i)
+ * - G^{dtau dt}(t_k - t_{i+1}) (i < k; on the diagonal h_k G^{dtau}(r, 0) + G^{dtau dt}(r, 0)
+ * - G^{dtau dt}(r, h_k)) or, where those terms would cancel, the even Taylor series of the
+ * trapezoid-weighted kernel about the centre of its time support (same value, no cancellation).
+ * On such a context: hb_assemble (HB_OP_V | HB_OP_K, HB_PREC_FP64), hb_get_blocks (d0, nd index
+ * the packed blocks), hb_apply (HB_OP_V, HB_OP_K: y^k = sum_{i<=k} A^{k,i} x^i),
+ * hb_rhs_dirichlet (M_h = blockdiag(h_k M_x)), hb_solve (HB_SOLVE_GMRES, precond 0), hb_sizes,
+ * hb_last_assembly_ms, hb_last_error and hb_destroy work; the other entry points return
+ * HB_EINVAL. */
+int hb_create_nonuniform(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t *tris,
+                         int64_t n_tris, double alpha, const double *t_nodes, int32_t n_t,
+                         const hb_options *opt);
+
+/* 1 if ctx was created by hb_create_nonuniform, else 0 (also for NULL). */
+int hb_is_nonuniform(const hb_ctx *ctx);
+
 /* Release everything the context owns.  NULL is accepted.  Waits for the device. */
 void hb_destroy(hb_ctx *ctx);
 

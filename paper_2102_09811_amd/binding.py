@@ -19,6 +19,7 @@ HB_DTYPE_F64, HB_DTYPE_F32 = 0, 1
 HB_SOLVE_GMRES, HB_SOLVE_TIMEMARCH, HB_SOLVE_MIXED_IR = 0, 1, 2
 
 EXPORTED = sorted(["hb_default_options", "hb_check_mesh", "hb_create", "hb_destroy",
+                   "hb_create_nonuniform", "hb_is_nonuniform",
                    "hb_last_error", "hb_sizes", "hb_assemble", "hb_get_blocks", "hb_apply",
                    "hb_rhs_dirichlet", "hb_rhs_neumann", "hb_solve", "hb_solve_neumann",
                    "hb_nearfield_pattern", "hb_assemble_nearfield",
@@ -84,6 +85,9 @@ def lib():
     L.hb_default_options.restype = None
     L.hb_check_mesh.argtypes = [vp, i64, vp, i64, vp]
     L.hb_create.argtypes = [ctypes.POINTER(vp), vp, i64, vp, i64, f64, f64, i32, ctypes.POINTER(Options)]
+    L.hb_create_nonuniform.argtypes = [ctypes.POINTER(vp), vp, i64, vp, i64, f64, vp, i32,
+                                       ctypes.POINTER(Options)]
+    L.hb_is_nonuniform.argtypes = [vp]
     L.hb_destroy.argtypes = [vp]
     L.hb_destroy.restype = None
     L.hb_last_error.argtypes = [vp]
@@ -280,6 +284,7 @@ class Context:
         if rc != HB_OK:
             raise HBError(rc, lib().hb_last_error(None).decode())
         self._h = h
+        self.n_blocks = self.n_t
 
     def _check(self, rc):
         if rc != HB_OK:
@@ -314,7 +319,7 @@ class Context:
         """Blocks d0 .. d0+nd-1 of op as a (nd, rows, cols) tensor (device) or ndarray (host):
         rows E_x (V, K) or N_x (D, V11), cols E_x (V) or N_x (K, D, V11)."""
         import torch
-        nd = self.n_t - d0 if nd is None else nd
+        nd = self.n_blocks - d0 if nd is None else nd
         rows = self.n_verts if op in (HB_OP_D, HB_OP_V11) else self.n_tris
         cols = self.n_tris if op == HB_OP_V else self.n_verts
         if dtype is None:
@@ -444,3 +449,28 @@ class Context:
                                        _ptr(sl) if parts else None, _ptr(dl) if parts else None,
                                        _stream(stream)))
         return (u, sl, dl) if parts else u
+
+
+class NonuniformContext(Context):
+    """A mesh with the non-uniform time grid t_nodes (0 = t_0 < ... < t_{E_t}): block
+    lower-triangular V_h and K_h with blocks (k, i), i <= k, at index k (k + 1) / 2 + i
+    (hb_create_nonuniform)."""
+
+    def __init__(self, verts, tris, alpha, t_nodes, **opts):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("heatbem needs a HIP device")
+        v, t = _mesh_arrays(verts, tris)
+        tn = np.ascontiguousarray(t_nodes, dtype=np.float64)
+        self.n_tris, self.n_verts, self.n_t = len(t), len(v), len(tn) - 1
+        self.alpha, self.T = float(alpha), float(tn[-1])
+        self.t_nodes = tn
+        o = default_options(**opts)
+        self.storage = o.storage
+        h = ctypes.c_void_p()
+        rc = lib().hb_create_nonuniform(ctypes.byref(h), v.ctypes.data, len(v), t.ctypes.data,
+                                        len(t), self.alpha, tn.ctypes.data, self.n_t, ctypes.byref(o))
+        if rc != HB_OK:
+            raise HBError(rc, lib().hb_last_error(None).decode())
+        self._h = h
+        self.n_blocks = self.n_t * (self.n_t + 1) // 2

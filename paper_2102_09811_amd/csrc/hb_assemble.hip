@@ -261,10 +261,9 @@ struct TaylorSums {
 };
 
 template <int N>
-__device__ __forceinline__ void sym_taylor2(const AsmParams &p, const SepTabs &T, int d0, int m,
-                                            const SepLane &L, TaylorSums &R) {
+__device__ __forceinline__ void sym_taylor2(const AsmParams &p, const SepTabs &T, int d0, int d1,
+                                            int m, const SepLane &L, TaylorSums &R) {
   const int ne = p.ne;
-  const int d1 = min(d0 + 1, p.nt - 1);
   const double c0 = T.tscale[3 * d0 + 2], c1 = T.tscale[3 * d1 + 2];
   const double *cv0 = T.taylor + (size_t)(2 * d0) * kTaylorN, *ck0 = cv0 + kTaylorN;
   const double *cv1 = T.taylor + (size_t)(2 * d1) * kTaylorN, *ck1 = cv1 + kTaylorN;
@@ -312,10 +311,9 @@ __device__ __forceinline__ void sym_taylor2(const AsmParams &p, const SepTabs &T
 
 // The same in float (hardware exp, shorter series), accumulated in double per trial node.
 template <int N>
-__device__ __forceinline__ void sym_taylor2_32(const AsmParams &p, const SepTabs &T, int d0, int m,
-                                               const SepLane &L, TaylorSums &R) {
+__device__ __forceinline__ void sym_taylor2_32(const AsmParams &p, const SepTabs &T, int d0,
+                                               int d1, int m, const SepLane &L, TaylorSums &R) {
   const int ne = p.ne;
-  const int d1 = min(d0 + 1, p.nt - 1);
   const double c0 = T.tscale[3 * d0 + 2], c1 = T.tscale[3 * d1 + 2];
   const float *cv0 = T.taylor32 + (size_t)(2 * d0) * kTaylorN32, *ck0 = cv0 + kTaylorN32;
   const float *cv1 = T.taylor32 + (size_t)(2 * d1) * kTaylorN32, *ck1 = cv1 + kTaylorN32;
@@ -430,27 +428,28 @@ __global__ __launch_bounds__(256, 3) void k_separated(const AsmParams *__restric
 #pragma unroll
       for (int k = 0; k < 3; ++k) R.K1[j][k] = R.K2[j][k] = 0.0;
     }
+    const int d1 = min(d + 1, p.nt - 1);
     if (MIXED && d >= p.mixed_d_min) {
       switch (T.tdeg[2 * d + 1]) {
-        case 16: sym_taylor2_32<17>(p, T, d, m, L, R); break;
-        case 12: sym_taylor2_32<13>(p, T, d, m, L, R); break;
-        case 10: sym_taylor2_32<11>(p, T, d, m, L, R); break;
-        case 8: sym_taylor2_32<9>(p, T, d, m, L, R); break;
-        case 6: sym_taylor2_32<7>(p, T, d, m, L, R); break;
-        default: sym_taylor2_32<5>(p, T, d, m, L, R); break;
+        case 16: sym_taylor2_32<17>(p, T, d, d1, m, L, R); break;
+        case 12: sym_taylor2_32<13>(p, T, d, d1, m, L, R); break;
+        case 10: sym_taylor2_32<11>(p, T, d, d1, m, L, R); break;
+        case 8: sym_taylor2_32<9>(p, T, d, d1, m, L, R); break;
+        case 6: sym_taylor2_32<7>(p, T, d, d1, m, L, R); break;
+        default: sym_taylor2_32<5>(p, T, d, d1, m, L, R); break;
       }
     } else {
       switch (T.tdeg[2 * d]) {
-        case 28: sym_taylor2<29>(p, T, d, m, L, R); break;
-        case 24: sym_taylor2<25>(p, T, d, m, L, R); break;
-        case 20: sym_taylor2<21>(p, T, d, m, L, R); break;
-        case 18: sym_taylor2<19>(p, T, d, m, L, R); break;
-        case 16: sym_taylor2<17>(p, T, d, m, L, R); break;
-        case 14: sym_taylor2<15>(p, T, d, m, L, R); break;
-        case 12: sym_taylor2<13>(p, T, d, m, L, R); break;
-        case 10: sym_taylor2<11>(p, T, d, m, L, R); break;
-        case 8: sym_taylor2<9>(p, T, d, m, L, R); break;
-        default: sym_taylor2<7>(p, T, d, m, L, R); break;
+        case 28: sym_taylor2<29>(p, T, d, d1, m, L, R); break;
+        case 24: sym_taylor2<25>(p, T, d, d1, m, L, R); break;
+        case 20: sym_taylor2<21>(p, T, d, d1, m, L, R); break;
+        case 18: sym_taylor2<19>(p, T, d, d1, m, L, R); break;
+        case 16: sym_taylor2<17>(p, T, d, d1, m, L, R); break;
+        case 14: sym_taylor2<15>(p, T, d, d1, m, L, R); break;
+        case 12: sym_taylor2<13>(p, T, d, d1, m, L, R); break;
+        case 10: sym_taylor2<11>(p, T, d, d1, m, L, R); break;
+        case 8: sym_taylor2<9>(p, T, d, d1, m, L, R); break;
+        default: sym_taylor2<7>(p, T, d, d1, m, L, R); break;
       }
     }
     if (active) {
@@ -517,8 +516,7 @@ __device__ __forceinline__ TouchPoint touch_point(const TouchPair &tp, const dou
 template <int N>
 __device__ __forceinline__ void touch_taylor2(const AsmParams &p, const SepTabs &T,
                                               const TouchPair &tp, const double *__restrict__ tab,
-                                              int ntab, int lane, int d0, TaylorSums &R) {
-  const int d1 = min(d0 + 1, p.nt - 1);
+                                              int ntab, int lane, int d0, int d1, TaylorSums &R) {
   const double c0 = T.tscale[3 * d0 + 2], c1 = T.tscale[3 * d1 + 2];
   const double *cv0 = T.taylor + (size_t)(2 * d0) * kTaylorN, *ck0 = cv0 + kTaylorN;
   const double *cv1 = T.taylor + (size_t)(2 * d1) * kTaylorN, *ck1 = cv1 + kTaylorN;
@@ -620,17 +618,18 @@ __global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict_
 #pragma unroll
       for (int k = 0; k < 3; ++k) R.K1[j][k] = 0.0;
     }
+    const int d1 = min(d + 1, p.nt - 1);
     switch (T.tdeg[2 * d]) {
-      case 28: touch_taylor2<29>(p, T, tp, tab, ntab, lane, d, R); break;
-      case 24: touch_taylor2<25>(p, T, tp, tab, ntab, lane, d, R); break;
-      case 20: touch_taylor2<21>(p, T, tp, tab, ntab, lane, d, R); break;
-      case 18: touch_taylor2<19>(p, T, tp, tab, ntab, lane, d, R); break;
-      case 16: touch_taylor2<17>(p, T, tp, tab, ntab, lane, d, R); break;
-      case 14: touch_taylor2<15>(p, T, tp, tab, ntab, lane, d, R); break;
-      case 12: touch_taylor2<13>(p, T, tp, tab, ntab, lane, d, R); break;
-      case 10: touch_taylor2<11>(p, T, tp, tab, ntab, lane, d, R); break;
-      case 8: touch_taylor2<9>(p, T, tp, tab, ntab, lane, d, R); break;
-      default: touch_taylor2<7>(p, T, tp, tab, ntab, lane, d, R); break;
+      case 28: touch_taylor2<29>(p, T, tp, tab, ntab, lane, d, d1, R); break;
+      case 24: touch_taylor2<25>(p, T, tp, tab, ntab, lane, d, d1, R); break;
+      case 20: touch_taylor2<21>(p, T, tp, tab, ntab, lane, d, d1, R); break;
+      case 18: touch_taylor2<19>(p, T, tp, tab, ntab, lane, d, d1, R); break;
+      case 16: touch_taylor2<17>(p, T, tp, tab, ntab, lane, d, d1, R); break;
+      case 14: touch_taylor2<15>(p, T, tp, tab, ntab, lane, d, d1, R); break;
+      case 12: touch_taylor2<13>(p, T, tp, tab, ntab, lane, d, d1, R); break;
+      case 10: touch_taylor2<11>(p, T, tp, tab, ntab, lane, d, d1, R); break;
+      case 8: touch_taylor2<9>(p, T, tp, tab, ntab, lane, d, d1, R); break;
+      default: touch_taylor2<7>(p, T, tp, tab, ntab, lane, d, d1, R); break;
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
@@ -654,7 +653,313 @@ __global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict_
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Non-uniform time grids: blocks V^{k,i}, K^{k,i} (0 <= i <= k < E_t) at packed index
+// k (k + 1) / 2 + i, on the same rules and pair lists as the uniform kernels.  A closed block is,
+// per point pair, the signed sum of the brackets at its levels: the four-term difference
+// F(t_k - t_i) + F(t_{k+1} - t_{i+1}) - F(t_{k+1} - t_i) - F(t_k - t_{i+1}) of
+// F = G^{dtau dt} (Sec. 3.1) and of its normal derivative (Sec. 3.2), and on the diagonal
+// F(0) - F(h_k) plus h_k G^{dtau}(rho, 0).  A Taylor block is the even series of the
+// trapezoid-weighted kernel about the centre of its support, evaluated like the uniform Taylor
+// blocks (sym_taylor2 / touch_taylor2) from a list, two entries per pass.  Double storage only.
+// ------------------------------------------------------------------------------------------
+
+// Signed level sums of closed block cb at one point pair: sA = sum sg rho A(z), sB = sum sg B(z)/rho.
+__device__ __forceinline__ void nu_closed_point(const AsmParams &p, const NuClosed &cb, double rho,
+                                                double inv_rho, double &sA, double &sB) {
+  sA = 0.0;
+  sB = 0.0;
+#pragma unroll
+  for (int j = 0; j < kNuLev; ++j) {
+    if (j >= cb.nlev) break;
+    double rA, kB;
+    if (cb.c[j] == 0.0) {  // delta = 0: A = B = 1
+      rA = rho;
+      kB = inv_rho;
+    } else {
+      closed_level_at(p, cb.c[j], cb.s2[j], cb.s1[j], cb.t2[j], rho, inv_rho, rA, kB);
+    }
+    sA = fma(cb.sg[j], rA, sA);
+    sB = fma(cb.sg[j], kB, sB);
+  }
+}
+
+// Taylor entries b and b1 (= b + 1, or b itself at the end of the list) of an unordered
+// separated pair, with the polynomial length of entry b.
+__device__ __forceinline__ void nu_sym_taylor(const AsmParams &p, const SepTabs &T, int b, int b1,
+                                              int m, const SepLane &L, TaylorSums &R) {
+  switch (T.tdeg[2 * b]) {
+    case 28: sym_taylor2<29>(p, T, b, b1, m, L, R); break;
+    case 24: sym_taylor2<25>(p, T, b, b1, m, L, R); break;
+    case 20: sym_taylor2<21>(p, T, b, b1, m, L, R); break;
+    case 18: sym_taylor2<19>(p, T, b, b1, m, L, R); break;
+    case 16: sym_taylor2<17>(p, T, b, b1, m, L, R); break;
+    case 14: sym_taylor2<15>(p, T, b, b1, m, L, R); break;
+    case 12: sym_taylor2<13>(p, T, b, b1, m, L, R); break;
+    case 10: sym_taylor2<11>(p, T, b, b1, m, L, R); break;
+    case 8: sym_taylor2<9>(p, T, b, b1, m, L, R); break;
+    default: sym_taylor2<7>(p, T, b, b1, m, L, R); break;
+  }
+}
+
+__global__ __launch_bounds__(256, 3) void k_nu_separated(const AsmParams *__restrict__ pp, NuTabs nu,
+                                                         const int *__restrict__ tasks,
+                                                         int ntasks) {
+  const AsmParams &p = *pp;
+  __shared__ double etab[64];
+  stage_exp_tab(etab);
+  __syncthreads();
+  const double *__restrict__ geom = p.geom;
+  const SepTabs T{geom, nu.tscale, nu.taylor, nullptr, nu.tdeg, etab};
+  // task list and lane mapping of k_separated: test panel l, trial panels m0 + lane (mod E_x)
+  const int task = xcd_block() * 4 + (threadIdx.x >> 6);
+  if (task >= ntasks) return;
+  const int l = __builtin_amdgcn_readfirstlane(tasks[3 * task]);
+  const int lane = threadIdx.x & 63;
+  if (lane >= __builtin_amdgcn_readfirstlane(tasks[3 * task + 2])) return;
+  const int ne = p.ne;
+  int m = __builtin_amdgcn_readfirstlane(tasks[3 * task + 1]) + lane;
+  if (m >= ne) m -= ne;
+  const int vl[3] = {p.tris[3 * l], p.tris[3 * l + 1], p.tris[3 * l + 2]};
+  const int vm[3] = {p.tris[3 * m], p.tris[3 * m + 1], p.tris[3 * m + 2]};
+  bool touch = false;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) touch |= vl[i] == vm[j];
+  const bool active = !touch;
+  SepLane L;
+  L.xg = geom + l;
+  L.nm[0] = geom[21 * ne + m];
+  L.nm[1] = geom[22 * ne + m];
+  L.nm[2] = geom[23 * ne + m];
+  L.nl[0] = geom[21 * ne + l];
+  L.nl[1] = geom[22 * ne + l];
+  L.nl[2] = geom[23 * ne + l];
+  L.shift = active ? 0.0 : 1.0e3;
+  const double scale = geom[24 * ne + l] * geom[24 * ne + m];
+
+  // ---- closed blocks, one per pass over the 49 point pairs ----
+#pragma unroll 1
+  for (int cbi = 0; cbi < nu.n_closed; ++cbi) {
+    const NuClosed &cb = nu.closed[cbi];
+    const bool diag = cb.diag != 0;
+    double sV = 0.0, gV = 0.0, sK1[3] = {0.0, 0.0, 0.0}, sK2[3] = {0.0, 0.0, 0.0};
+    double gK1[3] = {0.0, 0.0, 0.0}, gK2[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int b = 0; b < kFarN; ++b) {
+      const double y0 = geom[(b * 3 + 0) * ne + m] + L.shift;
+      const double y1 = geom[(b * 3 + 1) * ne + m];
+      const double y2 = geom[(b * 3 + 2) * ne + m];
+      const double wb = p.w7[b];
+      double tK = 0.0, tg = 0.0;
+#pragma unroll 1
+      for (int a = 0; a < kFarN; ++a) {
+        const double rx = L.xg[(a * 3 + 0) * ne] - y0;
+        const double ry = L.xg[(a * 3 + 1) * ne] - y1;
+        const double rz = L.xg[(a * 3 + 2) * ne] - y2;
+        const double rho = sqrt(fma(rx, rx, fma(ry, ry, rz * rz)));
+        const double inv_rho = 1.0 / rho;
+        const double wa = p.w7[a];
+        const double W = wa * wb;
+        const double wrn1 = wa * fma(rx, L.nm[0], fma(ry, L.nm[1], rz * L.nm[2]));
+        const double wrn2 = -W * fma(rx, L.nl[0], fma(ry, L.nl[1], rz * L.nl[2]));
+        double sA, sB;
+        nu_closed_point(p, cb, rho, inv_rho, sA, sB);
+        sV = fma(W, sA, sV);
+        tK = fma(wrn1, sB, tK);
+        const double u = wrn2 * sB;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sK2[k] = fma(u, p.lam7[a][k], sK2[k]);
+        if (diag) {
+          gV = fma(W, inv_rho, gV);
+          const double i3 = inv_rho * inv_rho * inv_rho;
+          tg = fma(wrn1, i3, tg);
+          const double u3 = wrn2 * i3;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) gK2[k] = fma(u3, p.lam7[a][k], gK2[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double phi = wb * p.lam7[b][k];
+        sK1[k] = fma(phi, tK, sK1[k]);
+        gK1[k] = fma(phi, tg, gK1[k]);
+      }
+    }
+    if (active) {
+      const double dV = diag ? cb.kVs : 0.0, dK = diag ? cb.kKs : 0.0;
+      const double v = (dV * gV + p.kV * sV) * scale;
+      if (p.do_V) {
+        store_block<double>(p, cb.out, l, m, v);
+        store_block<double>(p, cb.out, m, l, v);
+      }
+      if (p.do_K) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          add_block_K<double>(p, cb.out, l, vm[k], (dK * gK1[k] - p.kK * sK1[k]) * scale);
+          add_block_KT<double>(p, cb.out, m, vl[k], (dK * gK2[k] - p.kK * sK2[k]) * scale);
+        }
+      }
+    }
+  }
+
+  // ---- Taylor blocks, two list entries per pass ----
+#pragma unroll 1
+  for (int b = 0; b < nu.n_taylor; b += 2) {
+    const int b1 = min(b + 1, nu.n_taylor - 1);
+    TaylorSums R;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      R.V[j] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) R.K1[j][k] = R.K2[j][k] = 0.0;
+    }
+    nu_sym_taylor(p, T, b, b1, m, L, R);
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int bj = b + j;
+        if (bj >= nu.n_taylor) break;
+        const int out = nu.tout[bj];
+        if (p.do_V) {
+          const double v = R.V[j] * T.tscale[3 * bj] * scale;
+          store_block<double>(p, out, l, m, v);
+          store_block<double>(p, out, m, l, v);
+        }
+        if (p.do_K) {
+          const double ks = T.tscale[3 * bj + 1] * scale;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            add_block_K<double>(p, out, l, vm[k], R.K1[j][k] * ks);
+            add_block_KT<double>(p, out, m, vl[k], R.K2[j][k] * ks);
+          }
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(64, 3) void k_nu_touching(const AsmParams *__restrict__ pp,
+                                                       const TouchPair *__restrict__ pairs,
+                                                       RuleTabs rules, NuTabs nu) {
+  const AsmParams &p = *pp;
+  __shared__ double etab[64];
+  stage_exp_tab(etab);
+  __syncthreads();
+  const SepTabs T{nullptr, nu.tscale, nu.taylor, nullptr, nu.tdeg, etab};
+  const TouchPair &tp = pairs[blockIdx.x];
+  const int cls = __builtin_amdgcn_readfirstlane(tp.cls);
+  const double *__restrict__ tab = rules.d[cls];
+  const int ntab = rules.n[cls];
+  const int lane = threadIdx.x;
+  const int l = tp.l, m = tp.m;
+  const int vtx[3] = {tp.vtx[0], tp.vtx[1], tp.vtx[2]};
+
+#pragma unroll 1
+  for (int cbi = 0; cbi < nu.n_closed; ++cbi) {
+    const NuClosed &cb = nu.closed[cbi];
+    const bool diag = cb.diag != 0;
+    double sV = 0.0, gV = 0.0, sK[3] = {0.0, 0.0, 0.0}, gK[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int q = lane; q < ntab; q += 64) {
+      const TouchPoint t = touch_point(tp, tab, ntab, q, true);
+      double sA, sB;
+      nu_closed_point(p, cb, t.rho, t.inv_rho, sA, sB);
+      sV = fma(t.W, sA, sV);
+      const double u = t.wrn * sB;
+      sK[0] = fma(u, t.l0, sK[0]);
+      sK[1] = fma(u, t.l1, sK[1]);
+      sK[2] = fma(u, t.l2, sK[2]);
+      if (diag) {
+        gV = fma(t.W, t.inv_rho, gV);
+        const double u3 = t.wrn * t.inv_rho * t.inv_rho * t.inv_rho;
+        gK[0] = fma(u3, t.l0, gK[0]);
+        gK[1] = fma(u3, t.l1, gK[1]);
+        gK[2] = fma(u3, t.l2, gK[2]);
+      }
+    }
+    sV = wave_sum(sV);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sK[k] = wave_sum(sK[k]);
+    if (diag) {
+      gV = wave_sum(gV);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gK[k] = wave_sum(gK[k]);
+    }
+    if (lane == 0) {
+      const double dV = diag ? cb.kVs : 0.0, dK = diag ? cb.kKs : 0.0;
+      if (p.do_V) store_block<double>(p, cb.out, l, m, (dV * gV + p.kV * sV) * tp.scale);
+      if (p.do_K) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          add_block_K<double>(p, cb.out, l, vtx[k], (dK * gK[k] - p.kK * sK[k]) * tp.scale);
+      }
+    }
+  }
+
+#pragma unroll 1
+  for (int b = 0; b < nu.n_taylor; b += 2) {
+    const int b1 = min(b + 1, nu.n_taylor - 1);
+    TaylorSums R;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      R.V[j] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) R.K1[j][k] = 0.0;
+    }
+    switch (T.tdeg[2 * b]) {
+      case 28: touch_taylor2<29>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 24: touch_taylor2<25>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 20: touch_taylor2<21>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 18: touch_taylor2<19>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 16: touch_taylor2<17>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 14: touch_taylor2<15>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 12: touch_taylor2<13>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 10: touch_taylor2<11>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 8: touch_taylor2<9>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      default: touch_taylor2<7>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      R.V[j] = wave_sum(R.V[j]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) R.K1[j][k] = wave_sum(R.K1[j][k]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int bj = b + j;
+        if (bj >= nu.n_taylor) break;
+        const int out = nu.tout[bj];
+        if (p.do_V) store_block<double>(p, out, l, m, R.V[j] * T.tscale[3 * bj] * tp.scale);
+        if (p.do_K) {
+          const double ks = T.tscale[3 * bj + 1] * tp.scale;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) add_block_K<double>(p, out, l, vtx[k], R.K1[j][k] * ks);
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
+
+void launch_nu_separated(const AsmParams *dp, const NuTabs &nu, const int32_t *tasks,
+                         int64_t ntasks, hipStream_t s) {
+  hipLaunchKernelGGL(k_nu_separated, dim3((unsigned)((ntasks + 3) / 4)), dim3(256), 0, s, dp, nu,
+                     tasks, (int)ntasks);
+}
+
+void launch_nu_touching(const AsmParams *dp, const NuTabs &nu, const TouchPair *pairs,
+                        int64_t npairs, const SSRule rules[4], hipStream_t s) {
+  RuleTabs rule{};
+  for (int c = 1; c <= 3; ++c) {
+    rule.d[c] = rules[c].d;
+    rule.n[c] = rules[c].n;
+  }
+  hipLaunchKernelGGL(k_nu_touching, dim3((unsigned)npairs), dim3(64), 0, s, dp, pairs, rule, nu);
+}
 
 template <typename TS, int D>
 static void launch_sep(dim3 grid, hipStream_t s, const AsmParams *dp, const AsmParams &hp,

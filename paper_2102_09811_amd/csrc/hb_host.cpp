@@ -614,6 +614,198 @@ int build_tables(hb_ctx *c) {
   return HB_OK;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Non-uniform time grid (the outlook of Sec. 7; block integrals of Sec. 3.1 / 3.2 at general
+// interval endpoints).  Block (k, i), i < k, is the integral of w(s) G(rho, s) over the support
+// [s1, s4] = [t_k - t_{i+1}, t_{k+1} - t_i], w the trapezoid (convolution of the indicators of
+// the two intervals, widths a = h_k and b = h_i, mass a b, symmetric about c = (s1 + s4) / 2).
+// Taylor form: with f(s) = s^{-p} e^{-rho^2/(4 alpha s)} and f^{(n)}(c) = c^{-p-n} e^{-w} Q_n(w)
+// (the uniform tables' Q_n), the odd moments of w vanish and
+//   block = (a b) c^{-p} e^{-w} sum_j m_j c^{-2j} Q_{2j}(w) / (2j)!,
+//   m_j = E[(X + Y)^{2j}],  X ~ U(-a/2, a/2), Y ~ U(-b/2, b/2).
+// The series converges for s1 > 0 like ((s4 - s1) / (s4 + s1))^{2j}.  Its truncation is bounded
+// by sum_{j > J} |m_j c^{-2j} / (2j)!| max_{0 <= w <= 128} |Q_{2j}(w)| e^{-w} (no cancellation
+// assumed); a block takes the Taylor form when this bound is below 2e-16 of its scale at some
+// degree 2J <= 28 (for V and K), else the closed four-term difference.
+// ---------------------------------------------------------------------------------------------
+constexpr int kNuJ = 24;  // terms kept for the truncation bound (degree 48)
+
+struct NuBounds {
+  std::vector<ld> Q[2][2 * kNuJ + 1];  // Q_n coefficients, p = 3/2 (V) and 5/2 (K)
+  ld M[2][2 * kNuJ + 1];               // max over the samples of |Q_n(w)| e^{-w}
+};
+
+const NuBounds &nu_bounds() {
+  static NuBounds B;
+  static bool ready = false;
+  if (ready) return B;
+  std::vector<ld> ws;
+  for (int i = 0; i <= 80; ++i) ws.push_back(0.05L * i);
+  for (int i = 1; i <= 248; ++i) ws.push_back(4.0L + 0.5L * i);
+  for (int v = 0; v < 2; ++v) {
+    const ld p = v == 0 ? 1.5L : 2.5L;
+    B.Q[v][0] = {1.0L};
+    for (int n = 0; n < 2 * kNuJ; ++n) {
+      const auto &q = B.Q[v][n];
+      std::vector<ld> r(q.size() + 1, 0.0L);
+      for (size_t j = 0; j < q.size(); ++j) {
+        r[j + 1] += q[j];
+        r[j] -= (n + p) * q[j];
+        r[j] -= (ld)j * q[j];
+      }
+      B.Q[v][n + 1] = r;
+    }
+    for (int n = 0; n <= 2 * kNuJ; ++n) {
+      ld mx = 0.0L;
+      for (ld w : ws) {
+        ld acc = 0.0L;
+        for (size_t j = B.Q[v][n].size(); j-- > 0;) acc = acc * w + B.Q[v][n][j];
+        mx = std::max(mx, fabsl(acc) * expl(-w));
+      }
+      B.M[v][n] = mx;
+    }
+  }
+  ready = true;
+  return B;
+}
+
+// m_j c^{-2j} / (2j)! for j = 0 .. kNuJ
+void nu_series_factors(ld a, ld b, ld c, ld out[kNuJ + 1]) {
+  ld ma[2 * kNuJ + 1], mb[2 * kNuJ + 1];  // E[X^n], E[Y^n] (even n)
+  for (int n = 0; n <= 2 * kNuJ; n += 2) {
+    ma[n] = powl(a / 2, n) / (n + 1);
+    mb[n] = powl(b / 2, n) / (n + 1);
+  }
+  ld fact = 1.0L;  // (2j)!
+  for (int j = 0; j <= kNuJ; ++j) {
+    if (j > 0) fact *= (ld)(2 * j - 1) * (ld)(2 * j);
+    ld m = 0.0L, binom = 1.0L;  // C(2j, 2q)
+    for (int q = 0; q <= j; ++q) {
+      m += binom * ma[2 * q] * mb[2 * (j - q)];
+      binom *= (ld)(2 * j - 2 * q) * (ld)(2 * j - 2 * q - 1) / ((ld)(2 * q + 1) * (ld)(2 * q + 2));
+    }
+    out[j] = m * powl(c, -2 * j) / fact;
+  }
+}
+
+// Smallest tabulated degree (6, 8, ..., 20, 24, 28) whose truncation bound is below tol for V and
+// K, or -1.
+int nu_taylor_degree(const ld f[kNuJ + 1]) {
+  static const int degs[] = {6, 8, 10, 12, 14, 16, 18, 20, 24, 28};
+  const NuBounds &B = nu_bounds();
+  for (int deg : degs) {
+    bool ok = true;
+    for (int v = 0; v < 2 && ok; ++v) {
+      ld tail = 0.0L;
+      for (int j = deg / 2 + 1; j <= kNuJ; ++j) tail += fabsl(f[j]) * B.M[v][2 * j];
+      ok = tail <= 2e-16L * f[0];
+    }
+    if (ok) return deg;
+  }
+  return -1;
+}
+
+void nu_level(ld al, ld delta, hb::NuClosed &cb, int j, double sg) {
+  const ld sq = sqrtl(al * delta);
+  cb.c[j] = delta > 0 ? (double)(1.0L / (2.0L * sq)) : 0.0;
+  cb.s2[j] = (double)(2.0L * al * delta);
+  cb.s1[j] = (double)(2.0L * sq / sqrtl(kPi));
+  cb.t2[j] = (double)(4.0L * sq / sqrtl(kPi));
+  cb.sg[j] = sg;
+}
+
+int build_nu_tables(hb_ctx *c) {
+  using namespace hb;
+  const int nt = c->nt;
+  const ld al = c->alpha;
+  const std::vector<double> &t = c->tnodes;
+  std::vector<NuClosed> closed;
+  struct TEntry {
+    int32_t out, deg;
+    ld a, b, cc;
+  };
+  std::vector<TEntry> tay;
+  for (int k = 0; k < nt; ++k)
+    for (int i = 0; i <= k; ++i) {
+      const int32_t out = k * (k + 1) / 2 + i;
+      const ld hk = (ld)t[k + 1] - (ld)t[k], hi = (ld)t[i + 1] - (ld)t[i];
+      if (i == k) {  // h_k G^{dtau}(rho, 0) + F(0) - F(h_k)
+        NuClosed cb{};
+        cb.out = out;
+        cb.diag = 1;
+        cb.nlev = 2;
+        nu_level(al, 0.0L, cb, 0, 1.0);
+        nu_level(al, hk, cb, 1, -1.0);
+        cb.kVs = (double)(hk / (4.0L * kPi * al));
+        cb.kKs = (double)(hk / (4.0L * kPi));
+        closed.push_back(cb);
+        continue;
+      }
+      const ld s1 = (ld)t[k] - (ld)t[i + 1], s4 = (ld)t[k + 1] - (ld)t[i];
+      if (s1 > 0) {
+        ld f[kNuJ + 1];
+        const ld cc = 0.5L * (s1 + s4);
+        nu_series_factors(hk, hi, cc, f);
+        const int deg = nu_taylor_degree(f);
+        if (deg > 0) {
+          tay.push_back({out, deg, hk, hi, cc});
+          continue;
+        }
+      }
+      // F(t_k - t_i) + F(t_{k+1} - t_{i+1}) - F(t_{k+1} - t_i) - F(t_k - t_{i+1})
+      NuClosed cb{};
+      cb.out = out;
+      cb.diag = 0;
+      cb.nlev = 4;
+      nu_level(al, (ld)t[k] - (ld)t[i], cb, 0, 1.0);
+      nu_level(al, (ld)t[k + 1] - (ld)t[i + 1], cb, 1, 1.0);
+      nu_level(al, s4, cb, 2, -1.0);
+      nu_level(al, std::max(s1, 0.0L), cb, 3, -1.0);
+      closed.push_back(cb);
+    }
+  // Taylor entries by falling degree (stable), in pairs that share the first entry's length
+  std::stable_sort(tay.begin(), tay.end(), [](const TEntry &x, const TEntry &y) { return x.deg > y.deg; });
+  const size_t nT = tay.size();
+  std::vector<double> tab(nT * 2 * kTaylorN, 0.0), tsc(nT * 3, 0.0);
+  std::vector<int32_t> tdeg(nT * 2, 0), tout(nT, 0);
+  const NuBounds &B = nu_bounds();
+  for (size_t b = 0; b < nT; ++b) {
+    const TEntry &e = tay[b];
+    const int deg = tay[b - (b & 1)].deg;  // the pass takes the first entry's length
+    ld f[kNuJ + 1];
+    nu_series_factors(e.a, e.b, e.cc, f);
+    for (int v = 0; v < 2; ++v) {
+      ld poly[kTaylorN];
+      for (int j = 0; j < kTaylorN; ++j) poly[j] = 0.0L;
+      for (int j = 0; j <= deg / 2; ++j)
+        for (size_t q = 0; q < B.Q[v][2 * j].size() && (int)q < kTaylorN; ++q) poly[q] += f[j] * B.Q[v][2 * j][q];
+      // normalised so that the scale below carries the mass a b (f[0] = 1)
+      for (int j = 0; j < kTaylorN; ++j) tab[(b * 2 + v) * kTaylorN + j] = (double)poly[j];
+    }
+    const ld mu0 = e.a * e.b;
+    tsc[3 * b + 0] = (double)(mu0 * powl(4.0L * kPi * al * e.cc, -1.5L));
+    tsc[3 * b + 1] = (double)(mu0 / (16.0L * powl(kPi * al, 1.5L) * powl(e.cc, 2.5L)));
+    tsc[3 * b + 2] = (double)(1.0L / (4.0L * al * e.cc));
+    tdeg[2 * b] = deg;
+    tdeg[2 * b + 1] = deg;
+    tout[b] = e.out;
+  }
+  std::vector<double> hs(nt);
+  for (int k = 0; k < nt; ++k) hs[k] = t[k + 1] - t[k];
+  int rc;
+  if ((rc = upload(c, (void **)&c->d_nu_closed, closed.data(), closed.size() * sizeof(NuClosed)))) return rc;
+  if (nT > 0) {
+    if ((rc = upload(c, (void **)&c->d_nu_taylor, tab.data(), tab.size() * sizeof(double)))) return rc;
+    if ((rc = upload(c, (void **)&c->d_nu_tscale, tsc.data(), tsc.size() * sizeof(double)))) return rc;
+    if ((rc = upload(c, (void **)&c->d_nu_tdeg, tdeg.data(), tdeg.size() * sizeof(int32_t)))) return rc;
+    if ((rc = upload(c, (void **)&c->d_nu_tout, tout.data(), tout.size() * sizeof(int32_t)))) return rc;
+  }
+  if ((rc = upload(c, (void **)&c->d_nu_h, hs.data(), hs.size() * sizeof(double)))) return rc;
+  c->n_nu_closed = (int32_t)closed.size();
+  c->n_nu_taylor = (int32_t)nT;
+  return HB_OK;
+}
+
 }  // namespace
 
 // =============================================================================================
@@ -640,11 +832,23 @@ int hb_check_mesh(const double *verts, int64_t n_verts, const int32_t *tris, int
 
 const char *hb_last_error(const hb_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
 
-int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t *tris,
-              int64_t n_tris, double alpha, double T, int32_t n_t, const hb_options *opt) {
+}  // extern "C"
+
+// Context creation shared by hb_create (uniform steps, t_nodes NULL) and hb_create_nonuniform.
+static int create_ctx(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t *tris,
+                      int64_t n_tris, double alpha, double T, int32_t n_t, const hb_options *opt,
+                      const double *t_nodes) {
   if (!out) return fail(nullptr, HB_EINVAL, "out is null");
   *out = nullptr;
   if (!(alpha > 0) || !std::isfinite(alpha)) return fail(nullptr, HB_EINVAL, "alpha must be > 0");
+  if (t_nodes) {
+    if (n_t < 1 || n_t > 4096) return fail(nullptr, HB_EINVAL, "n_t must be in 1..4096 on a non-uniform grid");
+    if (t_nodes[0] != 0.0) return fail(nullptr, HB_EINVAL, "t_nodes[0] must be 0");
+    for (int k = 0; k < n_t; ++k)
+      if (!(t_nodes[k + 1] > t_nodes[k]) || !std::isfinite(t_nodes[k + 1]))
+        return fail(nullptr, HB_EINVAL, "t_nodes must be finite and strictly increasing");
+    T = t_nodes[n_t];
+  }
   if (!(T > 0) || !std::isfinite(T)) return fail(nullptr, HB_EINVAL, "T must be > 0");
   if (n_t < 1 || n_t > 65536) return fail(nullptr, HB_EINVAL, "n_t must be in 1..65536");
   hb_options o;
@@ -658,12 +862,20 @@ int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t 
   if (o.mixed_d_min < 2) return fail(nullptr, HB_EINVAL, "mixed_d_min must be >= 2");
   for (int i = 0; i < 12; ++i)
     if (o.reserved[i]) return fail(nullptr, HB_EINVAL, "reserved options must be zero");
+  if (t_nodes && o.storage != HB_DTYPE_F64)
+    return fail(nullptr, HB_EINVAL, "a non-uniform grid needs HB_DTYPE_F64 storage");
   int rc = validate_mesh(nullptr, verts, n_verts, tris, n_tris);
   if (rc) return rc;
   hb_ctx *c = new hb_ctx();
   c->ne = n_tris;
   c->nv = n_verts;
   c->nt = n_t;
+  c->nb = n_t;
+  if (t_nodes) {
+    c->nu = true;
+    c->tnodes.assign(t_nodes, t_nodes + n_t + 1);
+    c->nb = (int64_t)n_t * (n_t + 1) / 2;
+  }
   c->alpha = alpha;
   c->T = T;
   c->h = T / n_t;
@@ -677,6 +889,7 @@ int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t 
     return fail(nullptr, HB_EHIP, "no HIP device");
   }
   rc = build_tables(c);
+  if (!rc && c->nu) rc = build_nu_tables(c);
   if (rc) {
     g_err = c->err;
     hb_destroy(c);
@@ -691,6 +904,22 @@ int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t 
   return HB_OK;
 }
 
+extern "C" {
+
+int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t *tris,
+              int64_t n_tris, double alpha, double T, int32_t n_t, const hb_options *opt) {
+  return create_ctx(out, verts, n_verts, tris, n_tris, alpha, T, n_t, opt, nullptr);
+}
+
+int hb_create_nonuniform(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t *tris,
+                         int64_t n_tris, double alpha, const double *t_nodes, int32_t n_t,
+                         const hb_options *opt) {
+  if (!t_nodes) return fail(nullptr, HB_EINVAL, "t_nodes is null");
+  return create_ctx(out, verts, n_verts, tris, n_tris, alpha, 0.0, n_t, opt, t_nodes);
+}
+
+int hb_is_nonuniform(const hb_ctx *c) { return c && c->nu ? 1 : 0; }
+
 void hb_destroy(hb_ctx *c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
@@ -699,7 +928,8 @@ void hb_destroy(hb_ctx *c) {
                   c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d,
                   c->d_D, c->d_Dw, c->d_V11, c->d_minv, c->d_pcw, c->d_Kt, c->d_near_sep, c->d_near_touch, c->d_d2tab, c->d_d2scale, c->d_d2len, c->d_curl, c->d_vstart,
-                  c->d_vadj, c->d_pc_buf};
+                  c->d_vadj, c->d_pc_buf, c->d_nu_closed, c->d_nu_tout, c->d_nu_tdeg, c->d_nu_taylor,
+                  c->d_nu_tscale, c->d_nu_h};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int i = 0; i < 4; ++i)
@@ -751,8 +981,62 @@ static int assemble_p1(hb_ctx *c, uint32_t ops, hipStream_t s) {
   return HB_OK;
 }
 
+// Assembly on a non-uniform grid: V^{k,i}, K^{k,i} for all 0 <= i <= k < E_t (packed), FP64.
+static int assemble_nu(hb_ctx *c, uint32_t ops, int32_t precision, hipStream_t s) {
+  if (ops & ~(HB_OP_V | HB_OP_K))
+    return fail(c, HB_EINVAL, "a non-uniform grid has HB_OP_V and HB_OP_K only");
+  if (precision != HB_PREC_FP64) return fail(c, HB_EINVAL, "a non-uniform grid is assembled in FP64 only");
+  const size_t nV = (size_t)c->nb * c->ne * c->ne, nK = (size_t)c->nb * c->ne * c->nv, esz = 8;
+  if ((ops & HB_OP_V) && !c->d_V) {
+    HB_HIP(c, hipMalloc(&c->d_V, nV * esz + hb::kBlockPad));
+    HB_HIP(c, hipMemsetAsync((char *)c->d_V + nV * esz, 0, hb::kBlockPad, s));
+  }
+  if ((ops & HB_OP_K) && !c->d_K) {
+    HB_HIP(c, hipMalloc(&c->d_K, nK * esz + hb::kBlockPad));
+    HB_HIP(c, hipMemsetAsync((char *)c->d_K + nK * esz, 0, hb::kBlockPad, s));
+  }
+  if ((ops & HB_OP_K) && !c->d_KT) HB_HIP(c, hipMalloc(&c->d_KT, nK * esz));
+  hb::AsmParams &p = c->launch;
+  p = c->params;
+  p.V = c->d_V;
+  p.K = c->d_K;
+  p.KT = c->d_KT;
+  p.do_V = (ops & HB_OP_V) ? 1 : 0;
+  p.do_K = (ops & HB_OP_K) ? 1 : 0;
+  if (!c->d_params) HB_HIP(c, hipMalloc(&c->d_params, sizeof(hb::AsmParams)));
+  HB_HIP(c, hipMemcpyAsync(c->d_params, &p, sizeof(p), hipMemcpyHostToDevice, s));
+  if (p.do_K) {
+    HB_HIP(c, hipMemsetAsync(c->d_K, 0, nK * esz, s));
+    HB_HIP(c, hipMemsetAsync(c->d_KT, 0, nK * esz, s));
+  }
+  hb::NuTabs nu{c->d_nu_closed, c->n_nu_closed, c->n_nu_taylor, c->d_nu_tout, c->d_nu_taylor,
+                c->d_nu_tscale, c->d_nu_tdeg};
+  HB_HIP(c, hipEventRecord(c->ev[0], s));
+  if (c->n_sep_tasks > 0) hb::launch_nu_separated(c->d_params, nu, c->d_sep_tasks, c->n_sep_tasks, s);
+  HB_HIP(c, hipGetLastError());
+  if (p.do_K) {
+    hb::AsmParams fold = p;  // the fold runs over the nb packed blocks
+    fold.nt = (int32_t)c->nb;
+    hb::launch_fold_KT(fold, 0, s);
+    HB_HIP(c, hipGetLastError());
+  }
+  HB_HIP(c, hipEventRecord(c->ev[1], s));
+  const int64_t ntouch = c->n_class[1] + c->n_class[2] + c->n_class[3];
+  if (ntouch > 0) hb::launch_nu_touching(c->d_params, nu, c->d_touch, ntouch, c->ss, s);
+  HB_HIP(c, hipGetLastError());
+  HB_HIP(c, hipEventRecord(c->ev[2], s));
+  if (p.do_V) c->have_V = true;
+  if (p.do_K) c->have_K = true;
+  c->timed = true;
+  return HB_OK;
+}
+
 int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
   if (!c) return fail(nullptr, HB_EINVAL, "null context");
+  if (c->nu) {
+    if (ops == 0) return fail(c, HB_EINVAL, "ops must be a non-empty subset of HB_OP_V | HB_OP_K");
+    return assemble_nu(c, ops, precision, (hipStream_t)stream);
+  }
   if (ops == 0 || (ops & ~(HB_OP_V | HB_OP_K | HB_OP_D | HB_OP_V11)))
     return fail(c, HB_EINVAL, "ops must be a non-empty subset of HB_OP_V | HB_OP_K | HB_OP_D | HB_OP_V11");
   if (precision != HB_PREC_FP64 && precision != HB_PREC_MIXED) return fail(c, HB_EINVAL, "unknown precision");
@@ -835,6 +1119,7 @@ int hb_last_assembly_ms(hb_ctx *c, double ms[3]) {
 int hb_nearfield_pattern(hb_ctx *c, double radius, int64_t *nnz, int64_t *row_start,
                          int32_t *cols) {
   if (!c || !nnz) return fail(c, HB_EINVAL, "null argument");
+  if (c->nu) return fail(c, HB_EINVAL, "not available on a non-uniform time grid");
   if (!(radius >= 0) || !std::isfinite(radius)) return fail(c, HB_EINVAL, "radius must be finite and >= 0");
   const int64_t ne = c->ne;
   // centroids binned in cells of edge max(radius, tiny): candidates come from the 27 cells around
@@ -939,7 +1224,7 @@ int hb_get_blocks(hb_ctx *c, uint32_t op, int32_t d0, int32_t nd, void *dst, int
   if (!c || !dst) return fail(c, HB_EINVAL, "null argument");
   if (op != HB_OP_V && op != HB_OP_K && op != HB_OP_D && op != HB_OP_V11)
     return fail(c, HB_EINVAL, "op must be HB_OP_V, HB_OP_K, HB_OP_D or HB_OP_V11");
-  if (d0 < 0 || nd < 0 || d0 + nd > c->nt) return fail(c, HB_EINVAL, "block range out of bounds");
+  if (d0 < 0 || nd < 0 || (int64_t)d0 + nd > c->nb) return fail(c, HB_EINVAL, "block range out of bounds");
   if (dtype != HB_DTYPE_F64 && dtype != HB_DTYPE_F32) return fail(c, HB_EINVAL, "bad dtype");
   const bool p1p1 = op == HB_OP_D || op == HB_OP_V11;
   bool have = op == HB_OP_V ? c->have_V : op == HB_OP_K ? c->have_K : op == HB_OP_D ? c->have_D : c->have_V11;

@@ -88,6 +88,39 @@ struct RuleTabs {
   int32_t n[4];
 };
 
+// ---- Non-uniform time steps (blocks V^{k,i}, K^{k,i}, 0 <= i <= k < E_t, of a graded grid) ----
+// Block (k, i) is stored at index k (k + 1) / 2 + i.  Blocks whose gap t_k - t_{i+1} is small
+// against their support are "closed" (the four-term difference of G^{dtau dt} per point); the
+// others use the even Taylor series of the trapezoid-weighted kernel about the support's centre,
+// with the tables laid out as the uniform Taylor tables (entry b of the Taylor list).
+constexpr int kNuLev = 4;            // levels of a closed block
+struct NuClosed {
+  int32_t out;                       // packed block index
+  int32_t diag;                      // 1: i = k (adds h_k G^{dtau}(rho, 0))
+  int32_t nlev, pad;
+  double c[kNuLev];                  // 1 / (2 sqrt(alpha delta)); 0 marks delta = 0 (the limit)
+  double s2[kNuLev];                 // 2 alpha delta
+  double s1[kNuLev];                 // 2 sqrt(alpha delta) / sqrt(pi)
+  double t2[kNuLev];                 // 4 sqrt(alpha delta) / sqrt(pi)
+  double sg[kNuLev];                 // +1 / -1
+  double kVs, kKs;                   // h_k / (4 pi alpha), h_k / (4 pi) (diagonal blocks)
+};
+struct NuTabs {
+  const NuClosed *closed;            // [n_closed]
+  int32_t n_closed;
+  int32_t n_taylor;                  // Taylor blocks, taken in pairs (b, b + 1)
+  const int32_t *tout;               // [n_taylor]: packed block index of Taylor entry b
+  const double *taylor;              // [n_taylor][2][kTaylorN]
+  const double *tscale;              // [n_taylor][3]: V scale, K scale, 1 / (4 alpha c_b)
+  const int32_t *tdeg;               // [n_taylor][2] (degree of the pair's first entry)
+};
+void launch_nu_separated(const AsmParams *dp, const NuTabs &nu, const int32_t *tasks,
+                         int64_t ntasks, hipStream_t s);
+void launch_nu_touching(const AsmParams *dp, const NuTabs &nu, const TouchPair *pairs,
+                        int64_t npairs, const SSRule rules[4], hipStream_t s);
+// y^k = sum_{i <= k} A^{k,i} x^i over packed blocks [nb][R][C] (y overwritten, time-major)
+int nu_apply(hb_ctx *c, const double *A, int R, int C, const double *x, double *y, hipStream_t s);
+
 // dp: device copy of p (kernels read their parameters from device memory)
 void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, const int32_t *tasks,
                                int64_t ntasks, int precision, int storage_f32, hipStream_t s);
@@ -202,4 +235,13 @@ struct hb_ctx {
   double *d_reprq = nullptr;         // potentials: Q_{2k}(w) / (2k+1)! for p = 3/2 and 5/2
   double *d_apply = nullptr;         // per-group partial results of the Toeplitz apply
   size_t apply_bytes = 0;
+  // non-uniform time grid (hb_create_nonuniform): nodes t_0 = 0 < ... < t_nt, packed blocks
+  bool nu = false;
+  std::vector<double> tnodes;
+  int64_t nb = 0;                    // blocks per operator: nt (uniform) or nt (nt + 1) / 2
+  hb::NuClosed *d_nu_closed = nullptr;
+  int32_t n_nu_closed = 0, n_nu_taylor = 0;
+  int32_t *d_nu_tout = nullptr, *d_nu_tdeg = nullptr;
+  double *d_nu_taylor = nullptr, *d_nu_tscale = nullptr;
+  double *d_nu_h = nullptr;          // [nt]: step lengths h_k
 };

@@ -527,6 +527,7 @@ int hb_precond_pattern(hb_ctx *c, int32_t *cols, int8_t *cls, void *stream) {
 
 int hb_precond_features(hb_ctx *c, float *feats, void *stream) {
   if (!c || !feats) return lfail(c, HB_EINVAL, "null argument");
+  if (c->nu) return lfail(c, HB_EINVAL, "not available on a non-uniform time grid");
   if (!c->have_V) return lfail(c, HB_ESTATE, "V not assembled");
   hipStream_t s = (hipStream_t)stream;
   const int ne = (int)c->ne;
@@ -542,6 +543,7 @@ int hb_precond_features(hb_ctx *c, float *feats, void *stream) {
 
 int hb_precond_spai(hb_ctx *c, float *gram, float *rhs, float *weights, void *stream) {
   if (!c || !gram || !rhs) return lfail(c, HB_EINVAL, "null argument");
+  if (c->nu) return lfail(c, HB_EINVAL, "not available on a non-uniform time grid");
   if (!c->have_V) return lfail(c, HB_ESTATE, "V not assembled");
   hipStream_t s = (hipStream_t)stream;
   const int ne = (int)c->ne;
@@ -557,6 +559,7 @@ int hb_precond_spai(hb_ctx *c, float *gram, float *rhs, float *weights, void *st
 
 int hb_precond_set(hb_ctx *c, const float *weights, void *stream) {
   if (!c) return lfail(c, HB_EINVAL, "null context");
+  if (c->nu) return lfail(c, HB_EINVAL, "not available on a non-uniform time grid");
   if (!weights) {
     c->pc_active = false;
     return HB_OK;
@@ -750,6 +753,7 @@ int hb_precond_train(hb_ctx *const *ctxs, int32_t n_ctx, const hb_train_opts *op
   int64_t R = 0;
   for (int i = 0; i < n_ctx; ++i) {
     if (!ctxs[i]) return lfail(c0, HB_EINVAL, "null context in the list");
+    if (ctxs[i]->nu) return lfail(c0, HB_EINVAL, "training contexts need a uniform time grid");
     if (!ctxs[i]->have_V) return lfail(c0, HB_ESTATE, "V not assembled on a training context");
     R += ctxs[i]->ne;
   }

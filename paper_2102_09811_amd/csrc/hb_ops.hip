@@ -230,6 +230,19 @@ __global__ void k_mass_half(const double *__restrict__ mass, const int32_t *__re
   }
 }
 
+// The same with step lengths h_k of a non-uniform grid: b[k][l] += h_k / 2 (M_x g^k)_l.
+__global__ void k_mass_half_steps(const double *__restrict__ mass, const int32_t *__restrict__ tris,
+                                  const double *__restrict__ g, double *__restrict__ b, int nt,
+                                  int ne, int nv, const double *__restrict__ hk) {
+  const size_t n = (size_t)nt * ne;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i / ne), l = (int)(i % ne);
+    const double *gk = g + (size_t)k * nv;
+    b[i] += 0.5 * hk[k] * (mass[3 * l] * gk[tris[3 * l]] + mass[3 * l + 1] * gk[tris[3 * l + 1]] +
+                           mass[3 * l + 2] * gk[tris[3 * l + 2]]);
+  }
+}
+
 // Neumann right-hand side: on entry b = K_h^T psi; b[k][i] <- half_h sum over the panels l at
 // vertex i of (area_l / 3) psi[k][l] - b[k][i], i.e. b = 1/2 M_h^T psi - K_h^T psi.
 __global__ void k_mass_half_T(const double *__restrict__ mass, const int32_t *__restrict__ vstart,
@@ -775,6 +788,7 @@ static ApplySplit apply_split(int R, int C, int nd) {
   return a;
 }
 
+
 // Y[k] = sum_{d in [dlo, dhi)} A^d X[k - d] with X restricted to the times [jlo, jhi); with sub,
 // y[k] -= Y[k] for k >= ksub instead of y = Y.
 template <typename TA>
@@ -833,6 +847,45 @@ int toeplitz_apply(hb_ctx *c, const void *blocks, int R, int C, const double *x,
 int toeplitz_apply32(hb_ctx *c, const float *blocks, int R, int C, const double *x, double *y,
                      hipStream_t s) {
   return launch_toeplitz<float>(c, blocks, R, C, x, y, s, 0, c->nt, 0, c->nt, false, 0);
+}
+
+// Block lower-triangular product on a non-uniform grid: y^k[r] = sum_{i <= k} sum_c A^{k,i}[r][c]
+// x^i[c], blocks packed [k (k + 1) / 2 + i][R][C].  Every block is read once (no Toeplitz reuse),
+// so the product streams the blocks from HBM: one wave per row r of block row k, the lanes over
+// the columns of each block of the row (coalesced), four independent partial sums per lane, then
+// a wave reduction.  Long block rows are launched first.
+__global__ __launch_bounds__(256) void k_nu_apply(const double *__restrict__ A,
+                                                  const double *__restrict__ x,
+                                                  double *__restrict__ y, int nt, int R, int C) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + w;
+  const int k = nt - 1 - (int)blockIdx.y;
+  if (r >= R) return;
+  const size_t blk = (size_t)R * C;
+  const double *a = A + ((size_t)k * (k + 1) / 2) * blk + (size_t)r * C;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int i = 0; i <= k; ++i, a += blk) {
+    const double *xi = x + (size_t)i * C;
+    int c = lane;
+    for (; c + 192 < C; c += 256) {
+      s0 = fma(a[c], xi[c], s0);
+      s1 = fma(a[c + 64], xi[c + 64], s1);
+      s2 = fma(a[c + 128], xi[c + 128], s2);
+      s3 = fma(a[c + 192], xi[c + 192], s3);
+    }
+    for (; c < C; c += 64) s0 = fma(a[c], xi[c], s0);
+  }
+  double sum = (s0 + s1) + (s2 + s3);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if (lane == 0) y[(size_t)k * R + r] = sum;
+}
+
+int nu_apply(hb_ctx *c, const double *A, int R, int C, const double *x, double *y, hipStream_t s) {
+  dim3 grid((unsigned)((R + 3) / 4), (unsigned)c->nt);
+  hipLaunchKernelGGL(k_nu_apply, grid, dim3(256), 0, s, A, x, y, c->nt, R, C);
+  HB_CHECK(c, hipGetLastError());
+  return HB_OK;
 }
 
 namespace {
@@ -936,6 +989,7 @@ int ctx_fail(hb_ctx *c, int code, const std::string &m) {
 // V_h x with the double blocks (op 0) or with the float copy on the float MFMA path (op 1);
 // op 2: D_h x (the Neumann system)
 int apply_V(hb_ctx *c, int op, const double *x, double *y, hipStream_t s) {
+  if (op == 0 && c->nu) return nu_apply(c, (const double *)c->d_V, (int)c->ne, (int)c->ne, x, y, s);
   if (op == 0) return toeplitz_apply(c, c->d_V, (int)c->ne, (int)c->ne, x, y, s);
   if (op == 2) return toeplitz_apply(c, c->d_D, (int)c->nv, (int)c->nv, x, y, s);
   const float *V32 = c->storage_f32 ? (const float *)c->d_V : c->d_V32;
@@ -1313,6 +1367,13 @@ int hb_apply(hb_ctx *c, uint32_t op, const double *x, double *y, void *stream) {
   if (!c) return HB_EINVAL;
   if (!x || !y) return ctx_fail(c, HB_EINVAL, "null vector");
   hipStream_t s = (hipStream_t)stream;
+  if (c->nu) {
+    if (op != HB_OP_V && op != HB_OP_K)
+      return ctx_fail(c, HB_EINVAL, "a non-uniform grid has HB_OP_V and HB_OP_K only");
+    if (op == HB_OP_V ? !c->have_V : !c->have_K) return ctx_fail(c, HB_ESTATE, "operator not assembled");
+    return nu_apply(c, (const double *)(op == HB_OP_V ? c->d_V : c->d_K), (int)c->ne,
+                    (int)(op == HB_OP_V ? c->ne : c->nv), x, y, s);
+  }
   if (op == HB_OP_D || op == HB_OP_V11) {
     if (op == HB_OP_D ? !c->have_D : !c->have_V11) return ctx_fail(c, HB_ESTATE, "operator not assembled");
     return toeplitz_apply(c, op == HB_OP_D ? c->d_D : c->d_V11, (int)c->nv, (int)c->nv, x, y, s);
@@ -1333,6 +1394,7 @@ int hb_apply(hb_ctx *c, uint32_t op, const double *x, double *y, void *stream) {
 int hb_rhs_neumann(hb_ctx *c, const double *psi, double *b, void *stream) {
   if (!c) return HB_EINVAL;
   if (!psi || !b) return ctx_fail(c, HB_EINVAL, "null vector");
+  if (c->nu) return ctx_fail(c, HB_EINVAL, "not available on a non-uniform time grid");
   if (!c->have_K) return ctx_fail(c, HB_ESTATE, "K not assembled");
   hipStream_t s = (hipStream_t)stream;
   int rc = ensure_Kt(c, s);
@@ -1349,6 +1411,7 @@ int hb_solve_neumann(hb_ctx *c, const double *b, double *u, const hb_solve_opts 
                      hb_solve_info *info, void *stream) {
   if (!c) return HB_EINVAL;
   if (!b || !u) return ctx_fail(c, HB_EINVAL, "null vector");
+  if (c->nu) return ctx_fail(c, HB_EINVAL, "not available on a non-uniform time grid");
   if (!c->have_D) return ctx_fail(c, HB_ESTATE, "D not assembled");
   hb_solve_opts o{};
   o.method = HB_SOLVE_GMRES;
@@ -1389,6 +1452,15 @@ int hb_rhs_dirichlet(hb_ctx *c, const double *g, double *b, void *stream) {
   if (!g || !b) return ctx_fail(c, HB_EINVAL, "null vector");
   if (!c->have_K) return ctx_fail(c, HB_ESTATE, "K not assembled");
   hipStream_t s = (hipStream_t)stream;
+  if (c->nu) {
+    int rc = nu_apply(c, (const double *)c->d_K, (int)c->ne, (int)c->nv, g, b, s);
+    if (rc) return rc;
+    const size_t n = (size_t)c->nt * c->ne;
+    hipLaunchKernelGGL(k_mass_half_steps, dim3(grid1d(n)), dim3(256), 0, s, c->d_mass, c->d_tris, g,
+                       b, c->nt, (int)c->ne, (int)c->nv, c->d_nu_h);
+    HB_CHECK(c, hipGetLastError());
+    return HB_OK;
+  }
   int rc = toeplitz_apply(c, c->d_K, (int)c->ne, (int)c->nv, g, b, s);
   if (rc) return rc;
   const size_t n = (size_t)c->nt * c->ne;
@@ -1414,6 +1486,8 @@ int hb_solve(hb_ctx *c, const double *b, double *w, const hb_solve_opts *opts, h
   }
   if (o.method != HB_SOLVE_GMRES && o.method != HB_SOLVE_TIMEMARCH && o.method != HB_SOLVE_MIXED_IR)
     return ctx_fail(c, HB_EINVAL, "unknown solver method");
+  if (c->nu && (o.method != HB_SOLVE_GMRES || o.precond))
+    return ctx_fail(c, HB_EINVAL, "a non-uniform grid is solved by GMRES without preconditioner");
   if (o.max_iter > 5000) return ctx_fail(c, HB_EINVAL, "max_iter must be <= 5000");
   hipStream_t s = (hipStream_t)stream;
   hb_solve_info inf{};
@@ -1445,6 +1519,7 @@ int hb_solve(hb_ctx *c, const double *b, double *w, const hb_solve_opts *opts, h
 int hb_eval_repr(hb_ctx *c, const double *pts, int64_t P, const double *w, const double *g,
                  double *u, double *sl, double *dl, void *stream) {
   if (!c) return HB_EINVAL;
+  if (c->nu) return ctx_fail(c, HB_EINVAL, "not available on a non-uniform time grid");
   if (P < 0) return ctx_fail(c, HB_EINVAL, "P must be >= 0");
   if (P == 0) return HB_OK;
   if (!pts || !w || !g || !u) return ctx_fail(c, HB_EINVAL, "null pointer");
