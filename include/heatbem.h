@@ -184,6 +184,18 @@ int hb_get_blocks(hb_ctx *ctx, uint32_t op, int32_t d0, int32_t nd, void *dst, i
  * the partial sums added in double. */
 int hb_apply(hb_ctx *ctx, uint32_t op, const double *x, double *y, void *stream);
 
+/* hb_apply without allocation, for callers that cannot allocate device memory during the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product, kernels and arguments as hb_apply, with the partial results in a fixed 32 MiB device
+ * array of the library (one per device, set up by hb_create) instead of a buffer the context
+ * allocates.  The split over workgroups is narrowed until the partial results fit; HB_EINVAL when
+ * one set of them, E_t x rows x element size (8 bytes, 4 with float storage), exceeds 32 MiB.
+ * HB_OP_KT needs the transposed blocks formed by an hb_apply(HB_OP_KT) after the last assembly of
+ * K (HB_ESTATE otherwise).  Every call on a device shares that device's array and leaves its
+ * contents behind: calls that overlap on one device (two streams, or two host threads) race, so
+ * the caller orders them. */
+int hb_apply_noalloc(hb_ctx *ctx, uint32_t op, const double *x, double *y, void *stream);
+
 /* Right-hand side of the Dirichlet system b = (1/2 M_h + K_h) g (Sec. 3.4) with
  * M_h = h blockdiag(M_x), M_x[l, j] = int phi^0_l phi^1_j.  g: device, E_t x N_x (coefficients
  * of Dirichlet data in the p1-space / p0-time space); b: device, E_t x E_x. */

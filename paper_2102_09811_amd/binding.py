@@ -21,6 +21,7 @@ HB_SOLVE_GMRES, HB_SOLVE_TIMEMARCH, HB_SOLVE_MIXED_IR = 0, 1, 2
 EXPORTED = sorted(["hb_default_options", "hb_check_mesh", "hb_create", "hb_destroy",
                    "hb_create_nonuniform", "hb_is_nonuniform",
                    "hb_last_error", "hb_sizes", "hb_assemble", "hb_get_blocks", "hb_apply",
+                   "hb_apply_noalloc",
                    "hb_rhs_dirichlet", "hb_rhs_neumann", "hb_solve", "hb_solve_neumann",
                    "hb_nearfield_pattern", "hb_assemble_nearfield",
                    "hb_eval_repr", "hb_last_assembly_ms", "hb_measure_peaks",
@@ -96,6 +97,7 @@ def lib():
     L.hb_assemble.argtypes = [vp, ctypes.c_uint32, i32, vp]
     L.hb_get_blocks.argtypes = [vp, ctypes.c_uint32, i32, i32, vp, i32, i32, vp]
     L.hb_apply.argtypes = [vp, ctypes.c_uint32, vp, vp, vp]
+    L.hb_apply_noalloc.argtypes = [vp, ctypes.c_uint32, vp, vp, vp]
     L.hb_rhs_dirichlet.argtypes = [vp, vp, vp, vp]
     L.hb_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     L.hb_rhs_neumann.argtypes = [vp, vp, vp, vp]
@@ -338,6 +340,11 @@ class Context:
             rows = self.n_verts if op in (HB_OP_D, HB_OP_KT, HB_OP_V11) else self.n_tris
             y = torch.empty((self.n_t, rows), dtype=torch.float64, device="cuda")
         self._check(lib().hb_apply(self._h, op, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def apply_noalloc(self, op, x, y, stream=None):
+        """hb_apply_noalloc: the product of apply() with the library's fixed scratch (y given)."""
+        self._check(lib().hb_apply_noalloc(self._h, op, _ptr(x), _ptr(y), _stream(stream)))
         return y
 
     def rhs_dirichlet(self, g, b=None, stream=None):

@@ -890,6 +890,7 @@ static int create_ctx(hb_ctx **out, const double *verts, int64_t n_verts, const 
   }
   rc = build_tables(c);
   if (!rc && c->nu) rc = build_nu_tables(c);
+  if (!rc) rc = hb::static_scratch_init(c);
   if (rc) {
     g_err = c->err;
     hb_destroy(c);

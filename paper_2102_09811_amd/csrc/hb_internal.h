@@ -142,6 +142,10 @@ int launch_assemble_near(hb_ctx *c, double *V, double *K, hipStream_t s);
 // blockwise transpose [nt][R][C] -> [nt][C][R]
 int launch_transpose_blocks(hb_ctx *c, const void *src, void *dst, int R, int C, hipStream_t s);
 
+// Looks up this context's device copy of the fixed scratch of hb_apply_noalloc (once per device,
+// with the device current); called by hb_create.
+int static_scratch_init(hb_ctx *c);
+
 // message of the last failed call made without a context (hb_last_error(NULL))
 void set_global_error(const std::string &msg);
 

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -776,46 +777,77 @@ struct ApplySplit {
   int rt, nchunk, cpg, groups, slices;
 };
 
-static ApplySplit apply_split(int R, int C, int nd) {
+// max_parts > 0 caps groups x slices (the partial results held at once); slices go first.
+static ApplySplit apply_split(int R, int C, int nd, int max_parts = 0) {
   ApplySplit a;
   a.rt = (R + TR - 1) / TR;
   a.nchunk = (C + kTC - 1) / kTC;
   const int want = kApplyWant;
-  const int groups = std::max(1, std::min(a.nchunk, (want + a.rt - 1) / a.rt));
+  int groups = std::max(1, std::min(a.nchunk, (want + a.rt - 1) / a.rt));
+  if (max_parts > 0) groups = std::min(groups, max_parts);
   a.cpg = (a.nchunk + groups - 1) / groups;
   a.groups = (a.nchunk + a.cpg - 1) / a.cpg;
   a.slices = std::max(1, std::min(std::max(1, nd / 8), (want + a.rt * a.groups - 1) / (a.rt * a.groups)));
+  if (max_parts > 0) a.slices = std::max(1, std::min(a.slices, max_parts / a.groups));
   return a;
 }
 
+// ------------------------------------------------------------------------------------------
+// Fixed scratch of hb_apply_noalloc: the partial results of the product live in this array
+// instead of a buffer the context allocates.  Each device holds its own copy at its own address,
+// looked up once per device (hipGetSymbolAddress, at context creation) and used through that
+// address only; the array's name is not a device address in host code.
+// ------------------------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
 
 // Y[k] = sum_{d in [dlo, dhi)} A^d X[k - d] with X restricted to the times [jlo, jhi); with sub,
 // y[k] -= Y[k] for k >= ksub instead of y = Y.
+// scratch / scratch_bytes: caller-provided room for the partial results (no allocation; the split
+// is narrowed to fit, HB_EINVAL if one part does not fit); NULL: the context's own buffer.
 template <typename TA>
 static int launch_toeplitz(hb_ctx *c, const TA *A, int R, int C, const double *x, double *y,
-                           hipStream_t s, int dlo, int dhi, int jlo, int jhi, bool sub, int ksub) {
+                           hipStream_t s, int dlo, int dhi, int jlo, int jhi, bool sub, int ksub,
+                           void *scratch_buf = nullptr, size_t scratch_bytes = 0) {
   const int nt = c->nt;
   if (nt > 256) {
     c->err = "toeplitz apply supports E_t <= 256";
     return HB_EINVAL;
   }
   const int nd = std::max(0, dhi - dlo);
+  const size_t ny = (size_t)nt * R;
+  int max_parts = 0;
+  if (scratch_buf) {
+    const size_t fit = scratch_bytes / (sizeof(TA) * ny);
+    if (fit < 1) {
+      c->err = "block-Toeplitz partial results (E_t x rows x element size) exceed the fixed scratch";
+      return HB_EINVAL;
+    }
+    max_parts = (int)std::min<size_t>(fit, 1 << 20);
+  }
   if (nd == 0) {
     if (!sub) hipLaunchKernelGGL(k_fill, dim3(grid1d((size_t)nt * R)), dim3(256), 0, s, y, (size_t)nt * R, 0.0);
     return HB_OK;
   }
-  const ApplySplit sp = apply_split(R, C, nd);
+  const ApplySplit sp = apply_split(R, C, nd, max_parts);
   const int parts = sp.groups * sp.slices;
-  const size_t ny = (size_t)nt * R;
   const size_t need = sizeof(TA) * ny * parts;
-  if (c->apply_bytes < need) {
-    if (c->d_apply) (void)hipFree(c->d_apply);
-    c->d_apply = nullptr;
-    c->apply_bytes = 0;
-    HB_CHECK(c, hipMalloc(&c->d_apply, need));
-    c->apply_bytes = need;
+  TA *P;
+  if (scratch_buf) {
+    P = (TA *)scratch_buf;
+  } else {
+    if (c->apply_bytes < need) {
+      if (c->d_apply) (void)hipFree(c->d_apply);
+      c->d_apply = nullptr;
+      c->apply_bytes = 0;
+      HB_CHECK(c, hipMalloc(&c->d_apply, need));
+      c->apply_bytes = need;
+    }
+    P = (TA *)c->d_apply;
   }
-  TA *P = (TA *)c->d_apply;
   int ntc = 1;
   while (ntc * 16 < nt) ntc *= 2;
   dim3 grid(sp.rt, sp.groups, sp.slices);
@@ -886,6 +918,30 @@ int nu_apply(hb_ctx *c, const double *A, int R, int C, const double *x, double *
   hipLaunchKernelGGL(k_nu_apply, grid, dim3(256), 0, s, A, x, y, c->nt, R, C);
   HB_CHECK(c, hipGetLastError());
   return HB_OK;
+}
+
+// Address of this device's copy of `scratch`, looked up once per device with that device current.
+int static_scratch_init(hb_ctx *c) {
+  if (c->device < 0 || c->device >= kMaxDevices) {
+    c->err = "device index beyond the fixed-scratch table";
+    return HB_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[c->device]) return HB_OK;
+  void *ptr = nullptr;
+  HB_CHECK(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) {
+    c->err = "hipGetSymbolAddress returned no address for the fixed scratch";
+    return HB_EHIP;
+  }
+  g_scratch_ptr[c->device] = ptr;
+  return HB_OK;
+}
+
+static void *static_scratch(const hb_ctx *c) {
+  if (c->device < 0 || c->device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[c->device];
 }
 
 namespace {
@@ -1389,6 +1445,46 @@ int hb_apply(hb_ctx *c, uint32_t op, const double *x, double *y, void *stream) {
   if (op == HB_OP_V ? !c->have_V : !c->have_K) return ctx_fail(c, HB_ESTATE, "operator not assembled");
   return toeplitz_apply(c, op == HB_OP_V ? c->d_V : c->d_K, (int)c->ne,
                         (int)(op == HB_OP_V ? c->ne : c->nv), x, y, s);
+}
+
+int hb_apply_noalloc(hb_ctx *c, uint32_t op, const double *x, double *y, void *stream) {
+  if (!c) return HB_EINVAL;
+  if (!x || !y) return ctx_fail(c, HB_EINVAL, "null vector");
+  if (c->nu) return ctx_fail(c, HB_EINVAL, "not available on a non-uniform time grid (hb_apply allocates nothing there)");
+  hipStream_t s = (hipStream_t)stream;
+  void *P = static_scratch(c);
+  if (!P) return ctx_fail(c, HB_ESTATE, "fixed scratch not set up on this context's device");
+  const size_t rows = (op == HB_OP_V || op == HB_OP_K) ? (size_t)c->ne : (size_t)c->nv;
+  if ((size_t)c->nt * rows * (c->storage_f32 ? sizeof(float) : sizeof(double)) > kStaticScratchBytes)
+    return ctx_fail(c, HB_EINVAL, "E_t x rows x element size exceeds the 32 MiB fixed scratch");
+  const void *blocks;
+  int R, C;
+  if (op == HB_OP_V || op == HB_OP_K) {
+    if (op == HB_OP_V ? !c->have_V : !c->have_K) return ctx_fail(c, HB_ESTATE, "operator not assembled");
+    blocks = op == HB_OP_V ? c->d_V : c->d_K;
+    R = (int)c->ne;
+    C = (int)(op == HB_OP_V ? c->ne : c->nv);
+  } else if (op == HB_OP_D || op == HB_OP_V11) {
+    if (op == HB_OP_D ? !c->have_D : !c->have_V11) return ctx_fail(c, HB_ESTATE, "operator not assembled");
+    blocks = op == HB_OP_D ? c->d_D : c->d_V11;
+    R = C = (int)c->nv;
+  } else if (op == HB_OP_KT) {
+    if (!c->have_K) return ctx_fail(c, HB_ESTATE, "operator not assembled");
+    // the transposed blocks need a buffer of their own: only an hb_apply(HB_OP_KT) made after
+    // the last assembly of K has formed them
+    if (!c->Kt_valid) return ctx_fail(c, HB_ESTATE, "K_h^T not formed since the last assembly of K (call hb_apply with HB_OP_KT once)");
+    blocks = c->d_Kt;
+    R = (int)c->nv;
+    C = (int)c->ne;
+  } else {
+    return ctx_fail(c, HB_EINVAL, "op must be HB_OP_V, HB_OP_K, HB_OP_D, HB_OP_V11 or HB_OP_KT");
+  }
+  const int nt = c->nt;
+  if (c->storage_f32)
+    return launch_toeplitz<float>(c, (const float *)blocks, R, C, x, y, s, 0, nt, 0, nt, false, 0,
+                                  P, kStaticScratchBytes);
+  return launch_toeplitz<double>(c, (const double *)blocks, R, C, x, y, s, 0, nt, 0, nt, false, 0,
+                                 P, kStaticScratchBytes);
 }
 
 int hb_rhs_neumann(hb_ctx *c, const double *psi, double *b, void *stream) {
