@@ -47,53 +47,6 @@ __device__ __forceinline__ void add_block_KT(const AsmParams &p, int d, int m, i
 
 constexpr int kLC = 2;  // closed-form levels per pass over the quadrature points
 
-// Level sums of one pass: S[0], S[1] carry levels i0-2, i0-1; S[2 + j] is level i0 + j.
-struct LevelSums {
-  double V[kLC + 2];
-  double K[kLC + 2][3];
-};
-
-// Emit the blocks completed by the pass over levels i0 .. i0+kLC-1 (clipped to D).
-template <typename TS, int D>
-__device__ __forceinline__ void emit_pass(const AsmParams &p, int i0, int l, int m,
-                                          const int vtx[3], double scale, const LevelSums &S,
-                                          double sV, const double sK[3]) {
-  const int i1 = min(i0 + kLC - 1, D);
-#pragma unroll
-  for (int j = 0; j < kLC + 1; ++j) {
-    const int d = i0 - 1 + j;              // blocks i0-1 .. i1-1
-    if (d < 0 || d > i1 - 1 || d >= D || d >= p.nt) continue;
-    const int c = d - i0 + 2;              // slot of level d
-    double v, k[3];
-    if (d == 0) {
-      v = p.kVs * sV + p.kV * (S.V[c] - S.V[c + 1]);
-#pragma unroll
-      for (int q = 0; q < 3; ++q) k[q] = p.kKs * sK[q] + p.kK * (S.K[c + 1][q] - S.K[c][q]);
-    } else {
-      v = p.kV * (2.0 * S.V[c] - S.V[c + 1] - S.V[c - 1]);
-#pragma unroll
-      for (int q = 0; q < 3; ++q) k[q] = -p.kK * (2.0 * S.K[c][q] - S.K[c + 1][q] - S.K[c - 1][q]);
-    }
-    if (p.do_V) store_block<TS>(p, d, l, m, v * scale);
-    if (p.do_K) {
-#pragma unroll
-      for (int q = 0; q < 3; ++q) add_block_K<TS>(p, d, l, vtx[q], k[q] * scale);
-    }
-  }
-}
-
-__device__ __forceinline__ void shift_carry(LevelSums &S) {
-  S.V[0] = S.V[kLC];
-  S.V[1] = S.V[kLC + 1];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    S.K[0][q] = S.K[kLC][q];
-    S.K[1][q] = S.K[kLC + 1][q];
-  }
-#pragma unroll
-  for (int j = 2; j < kLC + 2; ++j) S.V[j] = S.K[j][0] = S.K[j][1] = S.K[j][2] = 0.0;
-}
-
 // ------------------------------------------------------------------------------------------
 // Separated pairs.  Both panels use the same 7-point rule, so the ordered pairs (l, m) and (m, l)
 // share all 49 point pairs (r changes sign, rho does not): one lane evaluates the unordered pair
@@ -177,15 +130,41 @@ struct SepTabs {
   const double *__restrict__ taylor;    // [nt][2][kTaylorN]
   const float *__restrict__ taylor32;   // [nt][2][kTaylorN32]
   const int *__restrict__ tdeg;         // [nt][2]
-  const double *etab;                   // LDS: 2^{-j/64}, j < 64 (exp_neg_t)
+  const double *etab;                   // LDS: 2^{-j/64} (exp_neg_t) or 2^{j/64} (exp_neg_m)
 };
 
-// Per-lane data of an unordered separated pair.
+// Per-lane data of an unordered separated pair.  The wave's test panel l is uniform: its rule
+// nodes sit in LDS (xs[a] = x, y, z, w_a), next to the rule's barycentrics (lam[a] = lambda_0..2,
+// w_a), so the inner loop over the test nodes reads them with broadcast LDS loads.
 struct SepLane {
-  const double *xg;        // test nodes of l: xg[(a*3+c)*ne]
+  const double *xs;        // LDS [kFarN][4]: test nodes of l and the rule weight
+  const double *lam;       // LDS [kFarN][4]: barycentrics of the rule nodes and the weight
   double nm[3], nl[3];     // unit normals of m and l
   double shift;            // inactive lanes integrate a far-away copy and store nothing
 };
+
+struct RuleNode {
+  double x, y, z, w;
+};
+__device__ __forceinline__ RuleNode rule_node(const double *q, int a) {
+  const double2 u = *(const double2 *)(q + 4 * a), v = *(const double2 *)(q + 4 * a + 2);
+  return {u.x, u.y, v.x, v.y};
+}
+
+// LDS staging of the separated kernels (before any lane leaves): the workgroup's barycentric
+// table, and each wave's test-panel nodes (lanes 0 .. 20 of the wave).
+__device__ __forceinline__ void stage_test_nodes(const AsmParams &p, const double *geom, int l,
+                                                 bool valid, double *xs_wave, double *lam) {
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x < kFarN * 4) {
+    const int a = threadIdx.x >> 2, c = threadIdx.x & 3;
+    lam[threadIdx.x] = c < 3 ? p.lam7[a][c] : p.w7[a];
+  }
+  if (valid && lane < kFarN * 4) {
+    const int a = lane >> 2, c = lane & 3;
+    xs_wave[lane] = c < 3 ? geom[(size_t)(a * 3 + c) * p.ne + l] : p.w7[a];
+  }
+}
 
 template <typename TS, int D, int I0>
 __device__ __forceinline__ void sym_pass(const AsmParams &p, const SepTabs &T, int l, int m,
@@ -199,23 +178,26 @@ __device__ __forceinline__ void sym_pass(const AsmParams &p, const SepTabs &T, i
       const double y0 = T.geom[(b * 3 + 0) * ne + m] + L.shift;
       const double y1 = T.geom[(b * 3 + 1) * ne + m];
       const double y2 = T.geom[(b * 3 + 2) * ne + m];
-      const double wb = p.w7[b];
+      const RuleNode Lb = rule_node(L.lam, b);
+      const double wb = Lb.w;
       double tK[kLC], tsK = 0.0;
 #pragma unroll
       for (int j = 0; j < kLC; ++j) tK[j] = 0.0;
 #pragma unroll 1
       for (int a = 0; a < kFarN; ++a) {
-        const double rx = L.xg[(a * 3 + 0) * ne] - y0;
-        const double ry = L.xg[(a * 3 + 1) * ne] - y1;
-        const double rz = L.xg[(a * 3 + 2) * ne] - y2;
+        const RuleNode X = rule_node(L.xs, a);
+        const double rx = X.x - y0;
+        const double ry = X.y - y1;
+        const double rz = X.z - y2;
         const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
         const double rho = sqrt(rho2);
         const double inv_rho = 1.0 / rho;
-        const double wa = p.w7[a];
+        const double wa = X.w;
         const double W = wa * wb;
         const double wrn1 = wa * fma(rx, L.nm[0], fma(ry, L.nm[1], rz * L.nm[2]));
         const double wrn2 = -W * fma(rx, L.nl[0], fma(ry, L.nl[1], rz * L.nl[2]));
-        const double la0 = p.lam7[a][0], la1 = p.lam7[a][1], la2 = p.lam7[a][2];
+        const RuleNode La = rule_node(L.lam, a);
+        const double la0 = La.x, la1 = La.y, la2 = La.z;
         if constexpr (I0 == 0) {
           sV = fma(W, inv_rho, sV);
           const double i3 = inv_rho * inv_rho * inv_rho;
@@ -238,9 +220,10 @@ __device__ __forceinline__ void sym_pass(const AsmParams &p, const SepTabs &T, i
           S.K2[2 + j][2] = fma(u, la2, S.K2[2 + j][2]);
         }
       }
+      const double lb[3] = {Lb.x, Lb.y, Lb.z};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const double phi = wb * p.lam7[b][k];
+        const double phi = wb * lb[k];
 #pragma unroll
         for (int j = 0; j < kLC; ++j) S.K1[2 + j][k] = fma(phi, tK[j], S.K1[2 + j][k]);
         if constexpr (I0 == 0) sK1[k] = fma(phi, tsK, sK1[k]);
@@ -255,7 +238,9 @@ __device__ __forceinline__ void sym_pass(const AsmParams &p, const SepTabs &T, i
 // Taylor blocks d0 and d0 + 1 of an unordered separated pair (both of polynomial length N; the
 // second is a copy of the first when d0 + 1 = nt, and then not stored).  r, rho^2 and the two
 // normal products are formed once per point pair for both blocks.  Sums per block: TV (V),
-// TK1 (trial m) and TK2 (trial l).
+// TK1 (trial m) and TK2 (trial l).  The double layer's polynomial is P - P' of the single
+// layer's (K^d / (r . n) = -(alpha / rho) dV^d / drho, term by term in the series), so one
+// Horner sweep per block gives both and only the single layer's coefficients are read.
 struct TaylorSums {
   double V[2], K1[2][3], K2[2][3];
 };
@@ -265,44 +250,51 @@ __device__ __forceinline__ void sym_taylor2(const AsmParams &p, const SepTabs &T
                                             int m, const SepLane &L, TaylorSums &R) {
   const int ne = p.ne;
   const double c0 = T.tscale[3 * d0 + 2], c1 = T.tscale[3 * d1 + 2];
-  const double *cv0 = T.taylor + (size_t)(2 * d0) * kTaylorN, *ck0 = cv0 + kTaylorN;
-  const double *cv1 = T.taylor + (size_t)(2 * d1) * kTaylorN, *ck1 = cv1 + kTaylorN;
+  const double *cv0 = T.taylor + (size_t)(2 * d0) * kTaylorN;
+  const double *cv1 = T.taylor + (size_t)(2 * d1) * kTaylorN;
 #pragma unroll 1
   for (int b = 0; b < kFarN; ++b) {
     const double y0 = T.geom[(b * 3 + 0) * ne + m] + L.shift;
     const double y1 = T.geom[(b * 3 + 1) * ne + m];
     const double y2 = T.geom[(b * 3 + 2) * ne + m];
-    const double wb = p.w7[b];
+    const RuleNode Lb = rule_node(L.lam, b);
+    const double wb = Lb.w;
     double tv0 = 0.0, tv1 = 0.0, tk0 = 0.0, tk1 = 0.0;
 #pragma unroll 1
     for (int a = 0; a < kFarN; ++a) {
-      const double rx = L.xg[(a * 3 + 0) * ne] - y0;
-      const double ry = L.xg[(a * 3 + 1) * ne] - y1;
-      const double rz = L.xg[(a * 3 + 2) * ne] - y2;
+      const RuleNode X = rule_node(L.xs, a);
+      const double rx = X.x - y0;
+      const double ry = X.y - y1;
+      const double rz = X.z - y2;
       const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
-      const double wa = p.w7[a];
+      const double wa = X.w;
       const double wrn1 = wa * fma(rx, L.nm[0], fma(ry, L.nm[1], rz * L.nm[2]));
       const double wrn2 = -(wa * wb) * fma(rx, L.nl[0], fma(ry, L.nl[1], rz * L.nl[2]));
       const double w0 = rho2 * c0, w1 = rho2 * c1;
-      const double e0 = exp_neg_t(w0, T.etab), e1 = exp_neg_t(w1, T.etab);
-      const double pk0 = horner<N>(ck0, w0) * e0, pk1 = horner<N>(ck1, w1) * e1;
-      tv0 = fma(wa * e0, horner<N>(cv0, w0), tv0);
-      tv1 = fma(wa * e1, horner<N>(cv1, w1), tv1);
+      const double e0 = exp_neg_m(w0, T.etab), e1 = exp_neg_m(w1, T.etab);
+      double p0, dp0, p1, dp1;
+      horner_d<N>(cv0, w0, p0, dp0);
+      horner_d<N>(cv1, w1, p1, dp1);
+      const double pk0 = (p0 - dp0) * e0, pk1 = (p1 - dp1) * e1;
+      tv0 = fma(wa * e0, p0, tv0);
+      tv1 = fma(wa * e1, p1, tv1);
       tk0 = fma(wrn1, pk0, tk0);
       tk1 = fma(wrn1, pk1, tk1);
       const double u0 = wrn2 * pk0, u1 = wrn2 * pk1;
+      const RuleNode La = rule_node(L.lam, a);
+      const double la[3] = {La.x, La.y, La.z};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const double la = p.lam7[a][k];
-        R.K2[0][k] = fma(u0, la, R.K2[0][k]);
-        R.K2[1][k] = fma(u1, la, R.K2[1][k]);
+        R.K2[0][k] = fma(u0, la[k], R.K2[0][k]);
+        R.K2[1][k] = fma(u1, la[k], R.K2[1][k]);
       }
     }
     R.V[0] = fma(wb, tv0, R.V[0]);
     R.V[1] = fma(wb, tv1, R.V[1]);
+    const double lb[3] = {Lb.x, Lb.y, Lb.z};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double phi = wb * p.lam7[b][k];
+      const double phi = wb * lb[k];
       R.K1[0][k] = fma(phi, tk0, R.K1[0][k]);
       R.K1[1][k] = fma(phi, tk1, R.K1[1][k]);
     }
@@ -322,16 +314,18 @@ __device__ __forceinline__ void sym_taylor2_32(const AsmParams &p, const SepTabs
     const double y0 = T.geom[(b * 3 + 0) * ne + m] + L.shift;
     const double y1 = T.geom[(b * 3 + 1) * ne + m];
     const double y2 = T.geom[(b * 3 + 2) * ne + m];
-    const double wb = p.w7[b];
+    const RuleNode Lb = rule_node(L.lam, b);
+    const double wb = Lb.w;
     float tv0 = 0.0f, tv1 = 0.0f, tk0 = 0.0f, tk1 = 0.0f;
     float t20[3] = {0.0f, 0.0f, 0.0f}, t21[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll 1
     for (int a = 0; a < kFarN; ++a) {
-      const double rx = L.xg[(a * 3 + 0) * ne] - y0;
-      const double ry = L.xg[(a * 3 + 1) * ne] - y1;
-      const double rz = L.xg[(a * 3 + 2) * ne] - y2;
+      const RuleNode X = rule_node(L.xs, a);
+      const double rx = X.x - y0;
+      const double ry = X.y - y1;
+      const double rz = X.z - y2;
       const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
-      const float wa = (float)p.w7[a];
+      const float wa = (float)X.w;
       const float rn1 = wa * (float)fma(rx, L.nm[0], fma(ry, L.nm[1], rz * L.nm[2]));
       const float rn2 = -wa * (float)fma(rx, L.nl[0], fma(ry, L.nl[1], rz * L.nl[2]));
       const float w0 = (float)(rho2 * c0), w1 = (float)(rho2 * c1);
@@ -342,18 +336,20 @@ __device__ __forceinline__ void sym_taylor2_32(const AsmParams &p, const SepTabs
       tk0 = fmaf(rn1, pk0, tk0);
       tk1 = fmaf(rn1, pk1, tk1);
       const float u0 = rn2 * pk0, u1 = rn2 * pk1;
+      const RuleNode La = rule_node(L.lam, a);
+      const float la[3] = {(float)La.x, (float)La.y, (float)La.z};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const float la = (float)p.lam7[a][k];
-        t20[k] = fmaf(u0, la, t20[k]);
-        t21[k] = fmaf(u1, la, t21[k]);
+        t20[k] = fmaf(u0, la[k], t20[k]);
+        t21[k] = fmaf(u1, la[k], t21[k]);
       }
     }
     R.V[0] = fma(wb, (double)tv0, R.V[0]);
     R.V[1] = fma(wb, (double)tv1, R.V[1]);
+    const double lb[3] = {Lb.x, Lb.y, Lb.z};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double phi = wb * p.lam7[b][k];
+      const double phi = wb * lb[k];
       R.K1[0][k] = fma(phi, (double)tk0, R.K1[0][k]);
       R.K1[1][k] = fma(phi, (double)tk1, R.K1[1][k]);
       R.K2[0][k] = fma(wb, (double)t20[k], R.K2[0][k]);
@@ -372,15 +368,19 @@ __global__ __launch_bounds__(256, 3) void k_separated(const AsmParams *__restric
                                                       const int *__restrict__ tasks, int ntasks) {
   const AsmParams &p = *pp;
   __shared__ double etab[64];
-  stage_exp_tab(etab);
-  __syncthreads();
+  __shared__ double lam[kFarN * 4];
+  __shared__ double xs[4][kFarN * 4];
+  stage_exp_tab_pos(etab);
   const SepTabs T{geom, tscale, taylor, taylor32, tdeg, etab};
   // one task per wave: test panel l and up to 64 trial panels m0, m0 + 1, ... (mod E_x); every
   // unordered pair of panels occurs in exactly one task.  Consecutive rows l, l + 1 mirror their V
   // entries into neighbouring columns, so the blocks of one XCD take consecutive tasks.
   const int task = xcd_block() * 4 + (threadIdx.x >> 6);
-  if (task >= ntasks) return;
-  const int l = __builtin_amdgcn_readfirstlane(tasks[3 * task]);
+  const bool valid = task < ntasks;
+  const int l = valid ? __builtin_amdgcn_readfirstlane(tasks[3 * task]) : 0;
+  stage_test_nodes(p, geom, l, valid, xs[threadIdx.x >> 6], lam);
+  __syncthreads();
+  if (!valid) return;
   const int lane = threadIdx.x & 63;
   if (lane >= __builtin_amdgcn_readfirstlane(tasks[3 * task + 2])) return;
   const int ne = p.ne;
@@ -395,7 +395,8 @@ __global__ __launch_bounds__(256, 3) void k_separated(const AsmParams *__restric
     for (int j = 0; j < 3; ++j) touch |= vl[i] == vm[j];
   const bool active = !touch;
   SepLane L;
-  L.xg = geom + l;
+  L.xs = xs[threadIdx.x >> 6];
+  L.lam = lam;
   L.nm[0] = geom[21 * ne + m];
   L.nm[1] = geom[22 * ne + m];
   L.nm[2] = geom[23 * ne + m];
@@ -538,116 +539,332 @@ __device__ __forceinline__ void touch_taylor2(const AsmParams &p, const SepTabs 
   }
 }
 
-template <typename TS, int D, int I0>
-__device__ __forceinline__ void touching_pass(const AsmParams &p, const TouchPair &tp,
-                                              const double *__restrict__ tab, int ntab, int lane,
-                                              int l, int m, const int vtx[3], LevelSums &S,
-                                              double &sV, double sK[3]) {
+// ------------------------------------------------------------------------------------------
+// Touching pairs, one wave per pair: the lanes stride over the regularised rule's points and the
+// pair's sums are reduced over the wave, the sixteen sums of a Taylor pass through LDS (each lane
+// writes its partial sums, four lanes add up a sum's sixteen-lane quarters and combine them), so
+// that the stores are spread over the lanes.  Pairs sharing one vertex are integrated once for
+// both orders: the two sub-maps of the vertex rule are each other's x <-> y swap, and the local
+// vertex orders depend only on the shared vertex, so the order (m, l) sees the same point pairs
+// with r -> -r, trial normal n_l and the trial basis at the x points (V^d[m][l] = V^d[l][m]).
+// A list entry is a pair index, ~index for such a pair (SYM launch).
+// ------------------------------------------------------------------------------------------
+constexpr int kRedRow = 66;  // LDS row of one sum's 64 partial sums (padded against bank conflicts)
+
+// v from the lane given by the DPP control CTRL within each row of sixteen lanes
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the wave, left in every lane (bitwise equal): the rows of sixteen lanes as below, then
+// the four row sums pairwise.
+__device__ __forceinline__ double group_sum(double v);
+__device__ __forceinline__ double wave_sum64(double v) {
+  v = group_sum(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Sum over the sixteen lanes of a row, left in every lane of the row (bitwise equal): pairs
+// (lane ^ 1), quads (lane ^ 2), half rows (mirror within eight lanes), rows (mirror within
+// sixteen); each step adds two equal partial sums in either order.
+__device__ __forceinline__ double group_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return v;
+}
+
+// One rule point of a touching pair: r from the edge-vector form, the trial normal product and
+// p1 basis, and with SYM those of the order (m, l) as well.
+template <bool SYM>
+struct TouchPt {
+  double rho2, W, wrn1, wrn2, l[3], lx[3];
+};
+
+template <bool SYM>
+__device__ __forceinline__ TouchPt<SYM> touch_pt(const TouchPair &tp, const double nl[3],
+                                                 const double *__restrict__ tab, int ntab, int q) {
+  const double a1 = tab[q], a2 = tab[ntab + q], a3 = tab[2 * ntab + q], a4 = tab[3 * ntab + q];
+  const double rx = a1 * tp.E1[0] + a2 * tp.E2[0] + a3 * tp.F1[0] + a4 * tp.F2[0];
+  const double ry = a1 * tp.E1[1] + a2 * tp.E2[1] + a3 * tp.F1[1] + a4 * tp.F2[1];
+  const double rz = a1 * tp.E1[2] + a2 * tp.E2[2] + a3 * tp.F1[2] + a4 * tp.F2[2];
+  TouchPt<SYM> t;
+  t.rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
+  t.W = tab[4 * ntab + q];
+  t.wrn1 = t.W * fma(rx, tp.n[0], fma(ry, tp.n[1], rz * tp.n[2]));
+  t.l[0] = tab[5 * ntab + q];
+  t.l[1] = tab[6 * ntab + q];
+  t.l[2] = tab[7 * ntab + q];
+  if constexpr (SYM) {
+    t.wrn2 = -t.W * fma(rx, nl[0], fma(ry, nl[1], rz * nl[2]));
+    t.lx[0] = tab[8 * ntab + q];
+    t.lx[1] = tab[9 * ntab + q];
+    t.lx[2] = tab[10 * ntab + q];
+  } else {
+    t.wrn2 = 0.0;
+    t.lx[0] = t.lx[1] = t.lx[2] = 0.0;
+  }
+  return t;
+}
+
+// Per-pair data of a wave (uniform); gl: the lane.
+struct TouchGroup {
+  const TouchPair *tp;
+  const double *tab;
+  int ntab, gl, l, m;
+  int vtx[3], vtxl[3];
+  double nl[3], scale;
+};
+
+// Closed-form levels I0 .. I0+kLC-1 of a touching pair (both orders with SYM), then the blocks
+// they complete (stored by the group's first lane).
+struct TouchLevels {
+  double V[kLC + 2], K1[kLC + 2][3], K2[kLC + 2][3];
+};
+
+template <typename TS, int D, bool SYM, int I0>
+__device__ __forceinline__ void touch_closed(const AsmParams &p, const TouchGroup &G,
+                                             TouchLevels &S, double &sV, double sK1[3],
+                                             double sK2[3]) {
   if constexpr (I0 <= D) {
 #pragma unroll 1
-    for (int q = lane; q < ntab; q += 64) {
-      const TouchPoint t = touch_point(tp, tab, ntab, q, true);
+    for (int q = threadIdx.x; q < G.ntab; q += 64) {
+      const TouchPt<SYM> t = touch_pt<SYM>(*G.tp, G.nl, G.tab, G.ntab, q);
+      const double rho = sqrt(t.rho2), inv_rho = 1.0 / rho;
       if constexpr (I0 == 0) {
-        sV = fma(t.W, t.inv_rho, sV);
-        const double u = t.wrn * t.inv_rho * t.inv_rho * t.inv_rho;
-        sK[0] = fma(u, t.l0, sK[0]);
-        sK[1] = fma(u, t.l1, sK[1]);
-        sK[2] = fma(u, t.l2, sK[2]);
+        sV = fma(t.W, inv_rho, sV);
+        const double i3 = inv_rho * inv_rho * inv_rho;
+        const double u1 = t.wrn1 * i3, u2 = t.wrn2 * i3;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          sK1[k] = fma(u1, t.l[k], sK1[k]);
+          if constexpr (SYM) sK2[k] = fma(u2, t.lx[k], sK2[k]);
+        }
       }
 #pragma unroll
       for (int j = 0; j < kLC; ++j) {
         if (I0 + j > D) continue;
         double rA, kB;
-        level_terms(p, I0 + j, t.rho, t.inv_rho, rA, kB);
+        level_terms(p, I0 + j, rho, inv_rho, rA, kB);
         S.V[2 + j] = fma(t.W, rA, S.V[2 + j]);
-        const double u = t.wrn * kB;
-        S.K[2 + j][0] = fma(u, t.l0, S.K[2 + j][0]);
-        S.K[2 + j][1] = fma(u, t.l1, S.K[2 + j][1]);
-        S.K[2 + j][2] = fma(u, t.l2, S.K[2 + j][2]);
+        const double u1 = t.wrn1 * kB, u2 = t.wrn2 * kB;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          S.K1[2 + j][k] = fma(u1, t.l[k], S.K1[2 + j][k]);
+          if constexpr (SYM) S.K2[2 + j][k] = fma(u2, t.lx[k], S.K2[2 + j][k]);
+        }
       }
     }
 #pragma unroll
     for (int j = 2; j < kLC + 2; ++j) {
-      S.V[j] = wave_sum(S.V[j]);
+      S.V[j] = wave_sum64(S.V[j]);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) S.K[j][k] = wave_sum(S.K[j][k]);
+      for (int k = 0; k < 3; ++k) {
+        S.K1[j][k] = wave_sum64(S.K1[j][k]);
+        if constexpr (SYM) S.K2[j][k] = wave_sum64(S.K2[j][k]);
+      }
     }
     if constexpr (I0 == 0) {
-      sV = wave_sum(sV);
+      sV = wave_sum64(sV);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) sK[k] = wave_sum(sK[k]);
+      for (int k = 0; k < 3; ++k) {
+        sK1[k] = wave_sum64(sK1[k]);
+        if constexpr (SYM) sK2[k] = wave_sum64(sK2[k]);
+      }
     }
-    if (lane == 0) emit_pass<TS, D>(p, I0, l, m, vtx, tp.scale, S, sV, sK);
-    shift_carry(S);
-    touching_pass<TS, D, I0 + kLC>(p, tp, tab, ntab, lane, l, m, vtx, S, sV, sK);
+    if (threadIdx.x == 0) {
+      const int i1 = min(I0 + kLC - 1, D);
+#pragma unroll
+      for (int j = 0; j < kLC + 1; ++j) {
+        const int d = I0 - 1 + j;  // blocks I0-1 .. i1-1
+        if (d < 0 || d > i1 - 1 || d >= D || d >= p.nt) continue;
+        const int c = d - I0 + 2;
+        double v, k1[3], k2[3];
+        if (d == 0) {
+          v = p.kVs * sV + p.kV * (S.V[c] - S.V[c + 1]);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            k1[k] = p.kKs * sK1[k] + p.kK * (S.K1[c + 1][k] - S.K1[c][k]);
+            k2[k] = p.kKs * sK2[k] + p.kK * (S.K2[c + 1][k] - S.K2[c][k]);
+          }
+        } else {
+          v = p.kV * (2.0 * S.V[c] - S.V[c + 1] - S.V[c - 1]);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            k1[k] = -p.kK * (2.0 * S.K1[c][k] - S.K1[c + 1][k] - S.K1[c - 1][k]);
+            k2[k] = -p.kK * (2.0 * S.K2[c][k] - S.K2[c + 1][k] - S.K2[c - 1][k]);
+          }
+        }
+        if (p.do_V) {
+          store_block<TS>(p, d, G.l, G.m, v * G.scale);
+          if constexpr (SYM) store_block<TS>(p, d, G.m, G.l, v * G.scale);
+        }
+        if (p.do_K) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            add_block_K<TS>(p, d, G.l, G.vtx[k], k1[k] * G.scale);
+            if constexpr (SYM) add_block_K<TS>(p, d, G.m, G.vtxl[k], k2[k] * G.scale);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      S.V[c] = S.V[kLC + c];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        S.K1[c][k] = S.K1[kLC + c][k];
+        S.K2[c][k] = S.K2[kLC + c][k];
+      }
+    }
+#pragma unroll
+    for (int j = 2; j < kLC + 2; ++j) {
+      S.V[j] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) S.K1[j][k] = S.K2[j][k] = 0.0;
+    }
+    touch_closed<TS, D, SYM, I0 + kLC>(p, G, S, sV, sK1, sK2);
   }
 }
 
-template <typename TS, int D>
+// Taylor blocks d0 and d1 (= d0 + 1, or d0 at the end) of a touching pair: this lane's partial
+// sums over its rule points (single-layer polynomial P, double layer P - P').  R[0], R[1]: V of
+// the two blocks; R[2..7]: double-layer parts (block, trial vertex); with SYM R[10..15]: those
+// of the order (m, l).
+template <bool SYM, int N>
+__device__ __forceinline__ void touch_taylor(const SepTabs &T, const TouchGroup &G, int d0, int d1,
+                                             double R[16]) {
+  const double c0 = T.tscale[3 * d0 + 2], c1 = T.tscale[3 * d1 + 2];
+  const double *cv0 = T.taylor + (size_t)(2 * d0) * kTaylorN;
+  const double *cv1 = T.taylor + (size_t)(2 * d1) * kTaylorN;
+#pragma unroll 1
+  for (int q = G.gl; q < G.ntab; q += 64) {
+    const TouchPt<SYM> t = touch_pt<SYM>(*G.tp, G.nl, G.tab, G.ntab, q);
+    const double w0 = t.rho2 * c0, w1 = t.rho2 * c1;
+    const double e0 = exp_neg_m(w0, T.etab), e1 = exp_neg_m(w1, T.etab);
+    double p0, dp0, p1, dp1;
+    horner_d<N>(cv0, w0, p0, dp0);
+    horner_d<N>(cv1, w1, p1, dp1);
+    const double k0 = (p0 - dp0) * e0, k1 = (p1 - dp1) * e1;
+    R[0] = fma(t.W * e0, p0, R[0]);
+    R[1] = fma(t.W * e1, p1, R[1]);
+    const double u10 = t.wrn1 * k0, u11 = t.wrn1 * k1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      R[2 + k] = fma(u10, t.l[k], R[2 + k]);
+      R[5 + k] = fma(u11, t.l[k], R[5 + k]);
+    }
+    if constexpr (SYM) {
+      const double u20 = t.wrn2 * k0, u21 = t.wrn2 * k1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        R[10 + k] = fma(u20, t.lx[k], R[10 + k]);
+        R[13 + k] = fma(u21, t.lx[k], R[13 + k]);
+      }
+    }
+  }
+}
+
+template <typename TS, int D, bool SYM>
 __global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict__ pp,
                                                     const TouchPair *__restrict__ pairs,
+                                                    const int32_t *__restrict__ list, int nlist,
                                                     RuleTabs rules,
                                                     const double *__restrict__ tscale,
                                                     const double *__restrict__ taylor,
                                                     const int *__restrict__ tdeg) {
   const AsmParams &p = *pp;
   __shared__ double etab[64];
-  stage_exp_tab(etab);
+  __shared__ __align__(16) double red[16 * kRedRow];
+  stage_exp_tab_pos(etab);
   __syncthreads();
   const SepTabs T{nullptr, tscale, taylor, nullptr, tdeg, etab};
-  const TouchPair &tp = pairs[blockIdx.x];
-  // the pair's class (3 identical, 2 edge, 1 vertex) picks its regularised rule
-  const int cls = __builtin_amdgcn_readfirstlane(tp.cls);
-  const double *__restrict__ tab = rules.d[cls];
-  const int ntab = rules.n[cls];
+  TouchGroup G;
+  const int ent = __builtin_amdgcn_readfirstlane(list[blockIdx.x]);
+  const TouchPair &tp = pairs[SYM ? ~ent : ent];
+  G.tp = &tp;
+  const int cls = tp.cls;
+  G.tab = rules.d[cls];
+  G.ntab = rules.n[cls];
+  G.gl = threadIdx.x;
+  G.l = tp.l;
+  G.m = tp.m;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    G.vtx[k] = tp.vtx[k];
+    G.vtxl[k] = tp.vtxl[k];
+    G.nl[k] = SYM ? p.geom[(21 + k) * p.ne + G.l] : 0.0;
+  }
+  G.scale = tp.scale;
+
+  {
+    TouchLevels S;
+#pragma unroll
+    for (int j = 0; j < kLC + 2; ++j) {
+      S.V[j] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) S.K1[j][k] = S.K2[j][k] = 0.0;
+    }
+    double sV = 0.0, sK1[3] = {0.0, 0.0, 0.0}, sK2[3] = {0.0, 0.0, 0.0};
+    touch_closed<TS, D, SYM, 0>(p, G, S, sV, sK1, sK2);
+  }
+
+  // Taylor blocks two per pass.  Sum i of the pass ends in lane 4 i, which stores it: 0, 1 V^d[l][m]
+  // of the two blocks, 2..7 their double-layer parts (block, trial vertex), and with SYM 8, 9
+  // V^d[m][l] (the sums 0, 1 again) and 10..15 the parts of the order (m, l).
   const int lane = threadIdx.x;
-  const int l = tp.l, m = tp.m;
-  const int vtx[3] = {tp.vtx[0], tp.vtx[1], tp.vtx[2]};
-
-  LevelSums S;
-#pragma unroll
-  for (int j = 0; j < kLC + 2; ++j) S.V[j] = S.K[j][0] = S.K[j][1] = S.K[j][2] = 0.0;
-  double sV = 0.0, sK[3] = {0.0, 0.0, 0.0};
-  touching_pass<TS, D, 0>(p, tp, tab, ntab, lane, l, m, vtx, S, sV, sK);
-
+  const int i4 = lane >> 2;
+  const int j = i4 < 8 ? (i4 < 2 ? i4 : (i4 - 2) / 3) : (i4 < 10 ? i4 - 8 : (i4 - 10) / 3);
+  const int kk = i4 < 2 ? 0 : (i4 < 8 ? (i4 - 2) % 3 : (i4 < 10 ? 0 : (i4 - 10) % 3));
+  const bool isV = i4 < 2 || (i4 >= 8 && i4 < 10);
+  const int row = i4 < 8 ? G.l : G.m;
+  const int col = isV ? (i4 < 8 ? G.m : G.l) : (i4 < 8 ? G.vtx[kk] : G.vtxl[kk]);
+  const bool mine = (lane & 3) == 0 && (i4 < 8 || SYM) && (isV ? p.do_V : p.do_K);
+  const int src = (i4 == 8 || i4 == 9) ? i4 - 8 : i4;
   for (int d = D; d < p.nt; d += 2) {
-    TaylorSums R;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      R.V[j] = 0.0;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) R.K1[j][k] = 0.0;
-    }
     const int d1 = min(d + 1, p.nt - 1);
+    double R[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) R[i] = 0.0;
     switch (T.tdeg[2 * d]) {
-      case 28: touch_taylor2<29>(p, T, tp, tab, ntab, lane, d, d1, R); break;
-      case 24: touch_taylor2<25>(p, T, tp, tab, ntab, lane, d, d1, R); break;
-      case 20: touch_taylor2<21>(p, T, tp, tab, ntab, lane, d, d1, R); break;
-      case 18: touch_taylor2<19>(p, T, tp, tab, ntab, lane, d, d1, R); break;
-      case 16: touch_taylor2<17>(p, T, tp, tab, ntab, lane, d, d1, R); break;
-      case 14: touch_taylor2<15>(p, T, tp, tab, ntab, lane, d, d1, R); break;
-      case 12: touch_taylor2<13>(p, T, tp, tab, ntab, lane, d, d1, R); break;
-      case 10: touch_taylor2<11>(p, T, tp, tab, ntab, lane, d, d1, R); break;
-      case 8: touch_taylor2<9>(p, T, tp, tab, ntab, lane, d, d1, R); break;
-      default: touch_taylor2<7>(p, T, tp, tab, ntab, lane, d, d1, R); break;
+      case 28: touch_taylor<SYM, 29>(T, G, d, d1, R); break;
+      case 24: touch_taylor<SYM, 25>(T, G, d, d1, R); break;
+      case 20: touch_taylor<SYM, 21>(T, G, d, d1, R); break;
+      case 18: touch_taylor<SYM, 19>(T, G, d, d1, R); break;
+      case 16: touch_taylor<SYM, 17>(T, G, d, d1, R); break;
+      case 14: touch_taylor<SYM, 15>(T, G, d, d1, R); break;
+      case 12: touch_taylor<SYM, 13>(T, G, d, d1, R); break;
+      case 10: touch_taylor<SYM, 11>(T, G, d, d1, R); break;
+      case 8: touch_taylor<SYM, 9>(T, G, d, d1, R); break;
+      default: touch_taylor<SYM, 7>(T, G, d, d1, R); break;
     }
+    // partial sums to LDS, row i = sum i (R[8], R[9] are unused), padded rows against conflicts
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      R.V[j] = wave_sum(R.V[j]);
+    for (int i = 0; i < 16; ++i)
+      if (i != 8 && i != 9 && (SYM || i < 8)) red[i * kRedRow + lane] = R[i];
+    __syncthreads();
+    const double *q = red + src * kRedRow + 16 * (lane & 3);
+    double v = 0.0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) R.K1[j][k] = wave_sum(R.K1[j][k]);
+    for (int k = 0; k < 16; k += 2) {
+      const double2 a = *(const double2 *)(q + k);
+      v += a.x + a.y;
     }
-    if (lane == 0) {
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int dj = d + j;
-        if (dj >= p.nt) break;
-        if (p.do_V) store_block<TS>(p, dj, l, m, R.V[j] * T.tscale[3 * dj] * tp.scale);
-        if (p.do_K) {
-          const double ks = T.tscale[3 * dj + 1] * tp.scale;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) add_block_K<TS>(p, dj, l, vtx[k], R.K1[j][k] * ks);
-        }
+    v += dpp_d<0xB1>(v);  // the four quarters: quad_perm [1, 0, 3, 2], then [2, 3, 0, 1]
+    v += dpp_d<0x4E>(v);
+    __syncthreads();
+    const int dj = d + j;
+    if (mine && dj < p.nt) {
+      if (isV) {
+        store_block<TS>(p, dj, row, col, v * T.tscale[3 * dj] * G.scale);
+      } else {
+        add_block_K<TS>(p, dj, row, col, v * T.tscale[3 * dj + 1] * G.scale);
       }
     }
   }
@@ -707,14 +924,18 @@ __global__ __launch_bounds__(256, 3) void k_nu_separated(const AsmParams *__rest
                                                          int ntasks) {
   const AsmParams &p = *pp;
   __shared__ double etab[64];
-  stage_exp_tab(etab);
-  __syncthreads();
+  __shared__ double lam[kFarN * 4];
+  __shared__ double xs[4][kFarN * 4];
+  stage_exp_tab_pos(etab);
   const double *__restrict__ geom = p.geom;
   const SepTabs T{geom, nu.tscale, nu.taylor, nullptr, nu.tdeg, etab};
   // task list and lane mapping of k_separated: test panel l, trial panels m0 + lane (mod E_x)
   const int task = xcd_block() * 4 + (threadIdx.x >> 6);
-  if (task >= ntasks) return;
-  const int l = __builtin_amdgcn_readfirstlane(tasks[3 * task]);
+  const bool valid = task < ntasks;
+  const int l = valid ? __builtin_amdgcn_readfirstlane(tasks[3 * task]) : 0;
+  stage_test_nodes(p, geom, l, valid, xs[threadIdx.x >> 6], lam);
+  __syncthreads();
+  if (!valid) return;
   const int lane = threadIdx.x & 63;
   if (lane >= __builtin_amdgcn_readfirstlane(tasks[3 * task + 2])) return;
   const int ne = p.ne;
@@ -729,7 +950,8 @@ __global__ __launch_bounds__(256, 3) void k_nu_separated(const AsmParams *__rest
     for (int j = 0; j < 3; ++j) touch |= vl[i] == vm[j];
   const bool active = !touch;
   SepLane L;
-  L.xg = geom + l;
+  L.xs = xs[threadIdx.x >> 6];
+  L.lam = lam;
   L.nm[0] = geom[21 * ne + m];
   L.nm[1] = geom[22 * ne + m];
   L.nm[2] = geom[23 * ne + m];
@@ -751,16 +973,20 @@ __global__ __launch_bounds__(256, 3) void k_nu_separated(const AsmParams *__rest
       const double y0 = geom[(b * 3 + 0) * ne + m] + L.shift;
       const double y1 = geom[(b * 3 + 1) * ne + m];
       const double y2 = geom[(b * 3 + 2) * ne + m];
-      const double wb = p.w7[b];
+      const RuleNode Lb = rule_node(L.lam, b);
+      const double wb = Lb.w;
       double tK = 0.0, tg = 0.0;
 #pragma unroll 1
       for (int a = 0; a < kFarN; ++a) {
-        const double rx = L.xg[(a * 3 + 0) * ne] - y0;
-        const double ry = L.xg[(a * 3 + 1) * ne] - y1;
-        const double rz = L.xg[(a * 3 + 2) * ne] - y2;
+        const RuleNode X = rule_node(L.xs, a);
+        const double rx = X.x - y0;
+        const double ry = X.y - y1;
+        const double rz = X.z - y2;
         const double rho = sqrt(fma(rx, rx, fma(ry, ry, rz * rz)));
         const double inv_rho = 1.0 / rho;
-        const double wa = p.w7[a];
+        const double wa = X.w;
+        const RuleNode La = rule_node(L.lam, a);
+        const double la[3] = {La.x, La.y, La.z};
         const double W = wa * wb;
         const double wrn1 = wa * fma(rx, L.nm[0], fma(ry, L.nm[1], rz * L.nm[2]));
         const double wrn2 = -W * fma(rx, L.nl[0], fma(ry, L.nl[1], rz * L.nl[2]));
@@ -770,19 +996,20 @@ __global__ __launch_bounds__(256, 3) void k_nu_separated(const AsmParams *__rest
         tK = fma(wrn1, sB, tK);
         const double u = wrn2 * sB;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) sK2[k] = fma(u, p.lam7[a][k], sK2[k]);
+        for (int k = 0; k < 3; ++k) sK2[k] = fma(u, la[k], sK2[k]);
         if (diag) {
           gV = fma(W, inv_rho, gV);
           const double i3 = inv_rho * inv_rho * inv_rho;
           tg = fma(wrn1, i3, tg);
           const double u3 = wrn2 * i3;
 #pragma unroll
-          for (int k = 0; k < 3; ++k) gK2[k] = fma(u3, p.lam7[a][k], gK2[k]);
+          for (int k = 0; k < 3; ++k) gK2[k] = fma(u3, la[k], gK2[k]);
         }
       }
+      const double lb[3] = {Lb.x, Lb.y, Lb.z};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const double phi = wb * p.lam7[b][k];
+        const double phi = wb * lb[k];
         sK1[k] = fma(phi, tK, sK1[k]);
         gK1[k] = fma(phi, tg, gK1[k]);
       }
@@ -1027,16 +1254,22 @@ void launch_fold_KT(const AsmParams &p, int storage_f32, hipStream_t s) {
 }
 
 template <typename TS, int D>
-static void launch_touch(dim3 grid, hipStream_t s, const AsmParams *dp, const AsmParams &hp,
-                         const TouchPair *pairs, const RuleTabs &rule) {
-  hipLaunchKernelGGL((k_touching<TS, D>), grid, dim3(64), 0, s, dp, pairs, rule, hp.tscale,
-                     hp.taylor, hp.tdeg);
+static void launch_touch(hipStream_t s, const AsmParams *dp, const AsmParams &hp,
+                         const TouchPair *pairs, const int32_t *list, int nlist, int nsym,
+                         const RuleTabs &rule) {
+  const int n0 = nlist - nsym;
+  if (n0 > 0)
+    hipLaunchKernelGGL((k_touching<TS, D, false>), dim3(n0), dim3(64), 0, s, dp, pairs, list, n0,
+                       rule, hp.tscale, hp.taylor, hp.tdeg);
+  if (nsym > 0)
+    hipLaunchKernelGGL((k_touching<TS, D, true>), dim3(nsym), dim3(64), 0, s, dp, pairs, list + n0,
+                       nsym, rule, hp.tscale, hp.taylor, hp.tdeg);
 }
 
 void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,
-                              int64_t npairs, const SSRule rules[4], int storage_f32,
-                              hipStream_t s) {
-  dim3 grid((unsigned)npairs);
+                              const int32_t *list, int64_t nlist, int64_t nsym,
+                              const SSRule rules[4], int storage_f32, hipStream_t s) {
+  const int n = (int)nlist, ns = (int)nsym;
   RuleTabs rule{};
   for (int c = 1; c <= 3; ++c) {
     rule.d[c] = rules[c].d;
@@ -1044,16 +1277,16 @@ void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const Tou
   }
   switch (p.dsw) {
     case 16:
-      if (storage_f32) launch_touch<float, 16>(grid, s, dp, p, pairs, rule);
-      else launch_touch<double, 16>(grid, s, dp, p, pairs, rule);
+      if (storage_f32) launch_touch<float, 16>(s, dp, p, pairs, list, n, ns, rule);
+      else launch_touch<double, 16>(s, dp, p, pairs, list, n, ns, rule);
       break;
     case 8:
-      if (storage_f32) launch_touch<float, 8>(grid, s, dp, p, pairs, rule);
-      else launch_touch<double, 8>(grid, s, dp, p, pairs, rule);
+      if (storage_f32) launch_touch<float, 8>(s, dp, p, pairs, list, n, ns, rule);
+      else launch_touch<double, 8>(s, dp, p, pairs, list, n, ns, rule);
       break;
     default:
-      if (storage_f32) launch_touch<float, 3>(grid, s, dp, p, pairs, rule);
-      else launch_touch<double, 3>(grid, s, dp, p, pairs, rule);
+      if (storage_f32) launch_touch<float, 3>(s, dp, p, pairs, list, n, ns, rule);
+      else launch_touch<double, 3>(s, dp, p, pairs, list, n, ns, rule);
       break;
   }
 }

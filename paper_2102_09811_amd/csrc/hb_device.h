@@ -96,6 +96,50 @@ __device__ __forceinline__ double exp_neg_t(double w, const double *__restrict__
   return ldexp(etab[ki & 63] * q, -(ki >> 6));
 }
 
+// Copy of 2^{+j/64}, j = 0 .. 63, in the calling workgroup's LDS: 1 and 2 kExp2Tab[64 - j] (exact
+// doublings of the correctly rounded 2^{-(64-j)/64}).  The caller synchronises.
+__device__ __forceinline__ void stage_exp_tab_pos(double *etab) {
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) etab[i] = i == 0 ? 1.0 : 2.0 * kExp2Tab[64 - i];
+}
+
+// e^{-w} for w >= 0 with etab = 2^{j/64} in LDS: k = round(-64 w / ln 2) is read from the low word
+// of t = -64 w / ln 2 + 1.5 2^52 (round to nearest, exact while |k| < 2^51), r = w + k ln2 / 64
+// (the fdlibm ln2 split scaled by 1/64, |r| <= ln2 / 128), and
+// e^{-w} = 2^{k >> 6} 2^{(k & 63)/64} e^{-r} with the degree-5 Taylor polynomial of e^{-r}
+// (truncation below 4e-17 relative); inputs are clamped at 1000 where the result is 0.
+__device__ __forceinline__ double exp_neg_m(double w, const double *__restrict__ etab) {
+  constexpr double kNeg64Log2e = -92.332482616893658;  // -64 / ln 2
+  constexpr double kShift = 6755399441055744.0;         // 1.5 * 2^52
+  constexpr double kLn2Hi64 = 6.93147180369123816490e-01 / 64;
+  constexpr double kLn2Lo64 = 1.90821492927058770002e-10 / 64;
+  const double x = fmin(w, 1000.0);
+  const double t = fma(x, kNeg64Log2e, kShift);
+  const double k = t - kShift;
+  const int ki = __double2loint(t);
+  double r = fma(k, kLn2Hi64, x);
+  r = fma(k, kLn2Lo64, r);
+  double q = -1.0 / 120.0;
+  q = fma(q, r, 1.0 / 24.0);
+  q = fma(q, r, -1.0 / 6.0);
+  q = fma(q, r, 0.5);
+  q = fma(q, r, -1.0);
+  q = fma(q, r, 1.0);
+  return ldexp(etab[ki & 63] * q, ki >> 6);
+}
+
+// P(x) and P'(x) of the polynomial c[0] + c[1] x + ... + c[N-1] x^{N-1}, one Horner sweep.
+template <int N>
+__device__ __forceinline__ void horner_d(const double *__restrict__ c, double x, double &p,
+                                         double &dp) {
+  p = c[N - 1];
+  dp = p;
+  p = fma(p, x, c[N - 2]);
+#pragma unroll
+  for (int i = N - 3; i >= 0; --i) {
+    dp = fma(dp, x, p);
+    p = fma(p, x, c[i]);
+  }
+}
 
 // Workgroups are dealt to the 8 XCDs (each with its own L2) in turn.  This renumbers them so that
 // each XCD takes a contiguous range of blocks (a bijection of [0, gridDim.x)): neighbouring tasks

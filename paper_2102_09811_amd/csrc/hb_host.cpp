@@ -500,6 +500,21 @@ int build_tables(hb_ctx *c) {
   if (!c->touch.empty())
     if ((rc = upload(c, (void **)&c->d_touch, c->touch.data(), c->touch.size() * sizeof(TouchPair))))
       return rc;
+  // the touching-pair assembly takes every identical and edge pair, and each pair sharing one
+  // vertex once (l < m, marked ~index) for both of its orders
+  {
+    std::vector<int32_t> list;
+    for (size_t i = 0; i < c->touch.size(); ++i)
+      if (c->touch[i].cls != 1) list.push_back((int32_t)i);
+    const size_t n0 = list.size();
+    for (size_t i = 0; i < c->touch.size(); ++i)
+      if (c->touch[i].cls == 1 && c->touch[i].l < c->touch[i].m) list.push_back(~(int32_t)i);
+    c->n_touch_list = (int64_t)list.size();
+    c->n_touch_sym = (int64_t)(list.size() - n0);
+    if (!list.empty() &&
+        (rc = upload(c, (void **)&c->d_touch_list, list.data(), list.size() * sizeof(int32_t))))
+      return rc;
+  }
   // separated pairs, unordered, each once: test row l takes the next np(l) panels l+1, l+2, ...
   // modulo E_x (round-robin pairing: with E_x odd every row has (E_x-1)/2 partners, with E_x even
   // the rows l < E_x/2 have E_x/2 and the others E_x/2 - 1), so that all rows carry the same
@@ -924,7 +939,7 @@ int hb_is_nonuniform(const hb_ctx *c) { return c && c->nu ? 1 : 0; }
 void hb_destroy(hb_ctx *c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
-  void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_sep_tasks, c->d_taylor,
+  void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_touch_list, c->d_sep_tasks, c->d_taylor,
                   c->d_taylor32, c->d_tdeg, c->d_V32, c->d_tscale, c->d_mass,
                   c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d,
@@ -1083,9 +1098,9 @@ int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
   HB_HIP(c, hipEventRecord(c->ev[1], s));
   // all touching pairs in one launch (the list is sorted identical, edge, vertex: the longest
   // pairs start first and the classes overlap)
-  const int64_t ntouch = c->n_class[1] + c->n_class[2] + c->n_class[3];
-  if (ntouch > 0)
-    hb::launch_assemble_touching(c->d_params, p, c->d_touch, ntouch, c->ss, c->storage_f32, s);
+  if (c->n_touch_list > 0)
+    hb::launch_assemble_touching(c->d_params, p, c->d_touch, c->d_touch_list, c->n_touch_list,
+                                 c->n_touch_sym, c->ss, c->storage_f32, s);
   HB_HIP(c, hipGetLastError());
   HB_HIP(c, hipEventRecord(c->ev[2], s));
   if (p.do_V) {

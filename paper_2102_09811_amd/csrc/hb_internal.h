@@ -125,9 +125,11 @@ int nu_apply(hb_ctx *c, const double *A, int R, int C, const double *x, double *
 void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, const int32_t *tasks,
                                int64_t ntasks, int precision, int storage_f32, hipStream_t s);
 void launch_fold_KT(const AsmParams &p, int storage_f32, hipStream_t s);
+// list: entries of the touching-pair kernels, pair indices, the last nsym of them ~index for
+// pairs sharing one vertex that are integrated once for both orders (hb_ctx::d_touch_list)
 void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,
-                              int64_t npairs, const SSRule rules[4], int storage_f32,
-                              hipStream_t s);
+                              const int32_t *list, int64_t nlist, int64_t nsym,
+                              const SSRule rules[4], int storage_f32, hipStream_t s);
 
 // Hypersingular operator (Sec. 3.3): D_h^d = D_h^{1,d} + D_h^{2,d} into c->d_D (needs V_h);
 // Taylor form of D^{2,d} from block kD2Closed on, closed form below.
@@ -176,6 +178,8 @@ struct hb_ctx {
   double *d_geom = nullptr;
   int32_t *d_tris = nullptr;
   hb::TouchPair *d_touch = nullptr;
+  int32_t *d_touch_list = nullptr;   // entries of the touching-pair assembly (see the launcher)
+  int64_t n_touch_list = 0, n_touch_sym = 0;
   int32_t *d_sep_tasks = nullptr;    // [n][3]: (test panel l, first trial panel m0, lanes) per wave;
                                      // lane i takes trial panel (m0 + i) mod E_x
   int64_t n_sep_tasks = 0;
