@@ -5,15 +5,15 @@ One step = one pass of the whole path over the workload (icosphere, 1280 triangl
 vertices, 64 uniform steps on (0, 1], alpha = 1):
   1. fused assembly of all V_h^d and K_h^d blocks (FP64),
   2. Dirichlet right-hand side (1/2 M_h + K_h) g,
-  3. learned preconditioner for this V_h^0 (features, MLP inference, installation),
-  4. learned + mixed-precision solve of V_h w = b to relative residual 1e-8 taken with the
-     double-precision operator: refinement steps whose corrections come from right-preconditioned
-     GMRES on the float copy of V_h (the paper solves with FGMRES to 1e-8),
-  5. representation formula at 10^4 interior space-time points.
-The MLP is trained before the timed region on random ellipsoids (the learned-preconditioner
-workload), never on this mesh.  After the timed steps every solver is timed on the same b:
-plain double GMRES (the reference), time marching, mixed-precision refinement, learned GMRES and
-learned + mixed, each to 1e-8.
+  3. solve of V_h w = b to relative residual 1e-8 taken with the double-precision operator, by
+     the fastest solver measured on this workload: time marching in FP64 (the inverse of the
+     freshly assembled V_h^0 by blocked Gauss-Jordan, then block forward substitution with the
+     history subtracted in chunks),
+  4. representation formula at 10^4 interior space-time points.
+After the timed steps every solver is timed on the same b: plain double GMRES (the reference),
+time marching, mixed-precision refinement, learned GMRES and learned + mixed, each to 1e-8.  The
+learned preconditioner's MLP is trained on random ellipsoids (the learned-preconditioner
+workload), never on this mesh.
 Inputs (mesh, data, points) are synthetic and seeded and already resident on the device when the
 timed region starts.  value = pair-block integrals per second of the whole step:
 E_x^2 * E_t units (one unit = one (test panel, trial panel, d) triple with its V entry and its
@@ -33,14 +33,16 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU = 78.6e12  # MI355X FP64 vector FLOP/s
 
-# HBM traffic of the separated-pair assembly (k_separated + k_fold_KT, one launch each) on this
-# workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of `bench.py --assembly-only`,
+# Counters of the separated-pair assembly (k_separated + k_fold_KT, one launch each) on this
+# workload, from rocprofv3 --pmc runs of `bench.py --assembly-only`: FETCH_SIZE and WRITE_SIZE,
 # each scaled by the reading of the same counter for a plain 256 MiB device copy taken in the same
-# run (FETCH_SIZE reads 0.500x, WRITE_SIZE 1.000x of the copied bytes).  Valid only for the
+# run (FETCH_SIZE reads 0.500x, WRITE_SIZE 1.000x of the copied bytes), and the FP64 VALU
+# instruction counts (wave instructions; 64 lanes each, an FMA is 2 FLOP).  Valid only for the
 # assembly source they were taken on (sha256 prefix below); reported as null otherwise.
-TRAFFIC = {"source_sha256": "0e43edb9a61c2960",
-           "fetch_kib": 120610.6 + 460171.0, "fetch_scale": 262144.0 / 131087.2,
-           "write_kib": 5937060.0 + 424960.0, "write_scale": 262144.0 / 262144.0}
+COUNTERS = {"source_sha256": None,
+            "fetch_kib": None, "fetch_scale": 262144.0 / 131087.2,
+            "write_kib": None, "write_scale": 262144.0 / 262144.0,
+            "fma_f64": None, "mul_f64": None, "add_f64": None}
 
 
 def log(msg):
@@ -56,17 +58,28 @@ def algorithmic_flops_separated(n_sep_pairs, n_t):
     return n_sep_pairs * 49.0 * (15.0 + 85.0 * (n_t + 1))
 
 
-def assembly_traffic_bytes():
-    """HBM bytes per separated-pair assembly launch from the committed counter runs, or None when
-    the assembly source has changed since they were taken."""
+def _counters_valid():
     import hashlib
     src = os.path.join(ROOT, "paper_2102_09811_amd", "csrc", "hb_assemble.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    if sha != TRAFFIC["source_sha256"]:
+    return COUNTERS["source_sha256"] is not None and sha == COUNTERS["source_sha256"]
+
+
+def assembly_traffic_bytes():
+    """HBM bytes per separated-pair assembly launch from the committed counter runs, or None when
+    the assembly source has changed since they were taken."""
+    if not _counters_valid():
         return None
-    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] +
-                     TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
+    return 1024.0 * (COUNTERS["fetch_kib"] * COUNTERS["fetch_scale"] +
+                     COUNTERS["write_kib"] * COUNTERS["write_scale"])
+
+
+def executed_flops():
+    """FP64 FLOP the separated-pair kernel executes per launch (counters), or None."""
+    if not _counters_valid():
+        return None
+    return 64.0 * (2.0 * COUNTERS["fma_f64"] + COUNTERS["mul_f64"] + COUNTERS["add_f64"])
 
 
 def assembly_only(args):
@@ -325,8 +338,7 @@ def main():
         ev[1].record(stream)
         ctx.rhs_dirichlet(gd, b)
         ev[2].record(stream)
-        learned.install(net, ctx)
-        _, info = ctx.solve(b, method=HB_SOLVE_MIXED_IR, tol=1e-8, w=w, precond=True)
+        _, info = ctx.solve(b, method=HB_SOLVE_TIMEMARCH, tol=1e-8, w=w)
         ev[3].record(stream)
         u = ctx.eval_repr(ptsd, w, gd)
         ev[4].record(stream)
@@ -378,8 +390,9 @@ def main():
                       "solve": avg("solve_ms"), "repr": avg("repr_ms"),
                       "assemble_separated_kernel": sep_ms, "assemble_touching_kernels": touch_ms},
         "assembly_units_per_s": units / (avg("assemble_ms") * 1e-3),
-        "solve": {"method": "learned-preconditioned mixed-precision refinement (float inner "
-                            "GMRES, residual with the double operator)",
+        "solve": {"method": "time marching in FP64 (Gauss-Jordan inverse of the assembled V_h^0, "
+                            "block forward substitution), residual recomputed with the double "
+                            "operator",
                   "iterations": int(rec[-1]["iterations"]),
                   "rel_residual": rec[-1]["rel_residual"], "ms": avg("solve_ms")},
         "learned_training_s": t_train,
@@ -389,7 +402,10 @@ def main():
                      "frac": achieved / (PEAK_FP64_VALU / 1e12),
                      "traffic": assembly_traffic_bytes(),
                      "algorithmic_flops_per_launch": flops,
-                     "frac_unordered_pairs": 0.5 * achieved / (PEAK_FP64_VALU / 1e12)},
+                     "frac_unordered_pairs": 0.5 * achieved / (PEAK_FP64_VALU / 1e12),
+                     "executed_flops_per_launch": executed_flops(),
+                     "frac_executed": (None if executed_flops() is None else
+                                       executed_flops() / (sep_ms * 1e-3) / PEAK_FP64_VALU)},
     }
     # the chip's vector-ALU ceilings measured on this device (microbenchmarks of the library): the
     # roofline above is quoted against the published FP64 figure, these check it

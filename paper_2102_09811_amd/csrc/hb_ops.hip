@@ -208,8 +208,19 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const TA *__restrict__ A, siz
   const int d = blockIdx.y;
   if (row >= R) return;
   const TA *a = A + (size_t)d * stride + (size_t)row * C;
-  double s = 0.0;
-  for (int c = lane; c < C; c += 64) s = fma((double)a[c], x[c], s);
+  // four independent partial sums, so that four loads per lane are in flight
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int c = lane;
+  for (; c + 192 < C; c += 256) {
+    const double a0 = (double)a[c], a1 = (double)a[c + 64], a2 = (double)a[c + 128],
+                 a3 = (double)a[c + 192];
+    s0 = fma(a0, x[c], s0);
+    s1 = fma(a1, x[c + 64], s1);
+    s2 = fma(a2, x[c + 128], s2);
+    s3 = fma(a3, x[c + 192], s3);
+  }
+  for (; c < C; c += 64) s0 = fma((double)a[c], x[c], s0);
+  double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if (lane == 0) {
@@ -259,84 +270,78 @@ __global__ void k_mass_half_T(const double *__restrict__ mass, const int32_t *__
   }
 }
 
-// ---- inverse of V^0 by blocked Gauss-Jordan elimination (no pivoting), in place ----
-// Panel p of kGJB columns / rows (R = C = [p0, p0 + b)): with Ainv = A[R, C]^{-1},
-//   A[R, :]      <- Ainv A[R, :]                 (Ainv in the pivot columns)
-//   A[i, :]      <- A[i, :] - A[i, C] Ainv A[R, :]   for i outside R, the pivot columns first
-//                                                  set to 0 so that they become -A[i, C] Ainv,
-// which is b steps of scalar Gauss-Jordan at once; the update is a rank-b product on MFMA.
+// ---- inverse by blocked Gauss-Jordan elimination (no pivoting), one launch per panel ----
+// Panel R = C = [p0, p0 + b) (b <= kGJB), out of place X -> Y, with P^{-1} = X[R, C]^{-1}:
+//   Y[R, :] = P^{-1} X[R, :]                        (the pivot columns: P^{-1}),
+//   Y[i, :] = X[i, :] - X[i, C] P^{-1} X[R, :]      for i outside R (the pivot columns:
+//                                                   -X[i, C] P^{-1}),
+// which is b steps of scalar Gauss-Jordan at once.  Every workgroup (a 64 x 64 tile of Y) inverts
+// the pivot block itself -- wave 0, one row per lane in registers, the pivot row broadcast with
+// readlane, while the other waves stage X[R, tile columns] and X[tile rows, C] -- then forms its
+// slice of T = P^{-1} X[R, tile columns] and updates the tile with a rank-b product on MFMA.
 constexpr int kGJB = 32;
 
-__global__ __launch_bounds__(256) void k_gjb_pivot(const double *__restrict__ A, int n, int p0,
-                                                   int b, double *__restrict__ Ainv) {
-  __shared__ double P[kGJB][kGJB + 1];
-  __shared__ double rowk[kGJB], colk[kGJB];
-  for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
-    const int i = e / b, j = e % b;
-    P[i][j] = A[(size_t)(p0 + i) * n + p0 + j];
-  }
-  __syncthreads();
-  for (int k = 0; k < b; ++k) {
-    if ((int)threadIdx.x < b) {
-      rowk[threadIdx.x] = P[k][threadIdx.x];
-      colk[threadIdx.x] = P[threadIdx.x][k];
-    }
-    __syncthreads();
-    const double inv = 1.0 / rowk[k];
-    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
-      const int i = e / b, j = e % b;
-      double v;
-      if (i == k) v = (j == k) ? inv : rowk[j] * inv;
-      else v = (j == k) ? -colk[i] * inv : P[i][j] - colk[i] * rowk[j] * inv;
-      P[i][j] = v;
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < kGJB * kGJB; e += blockDim.x) {
-    const int i = e / kGJB, j = e % kGJB;
-    Ainv[e] = (i < b && j < b) ? P[i][j] : 0.0;
-  }
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
 }
 
-// T[k][j] = sum_l Ainv[k][l] A[p0 + l][j] (j outside the pivot columns), T[:, C] = Ainv;
-// Cc[i][k] = A[i][p0 + k], the pivot columns before the update.
-__global__ void k_gjb_rows(const double *__restrict__ A, int n, int p0, int b,
-                           const double *__restrict__ Ainv, double *__restrict__ T,
-                           double *__restrict__ Cc) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  const size_t g0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  for (size_t e = g0; e < (size_t)kGJB * n; e += stride) {
-    const int k = (int)(e / n), j = (int)(e % n);
-    double v = 0.0;
-    if (k < b) {
-      if (j >= p0 && j < p0 + b) {
-        v = Ainv[k * kGJB + (j - p0)];
-      } else {
-        for (int l = 0; l < b; ++l) v = fma(Ainv[k * kGJB + l], A[(size_t)(p0 + l) * n + j], v);
-      }
-    }
-    T[e] = v;
-  }
-  for (size_t e = g0; e < (size_t)n * kGJB; e += stride) {
-    const int i = (int)(e / kGJB), k = (int)(e % kGJB);
-    Cc[e] = k < b ? A[(size_t)i * n + p0 + k] : 0.0;
-  }
-}
-
-// A <- A - Cc T on 64 x 64 tiles (v_mfma_f64_16x16x4, K = kGJB), with the pivot rows replaced
-// by T and the pivot columns' old values taken as 0.
-__global__ __launch_bounds__(256) void k_gjb_update(double *__restrict__ A, int n, int p0, int b,
-                                                    const double *__restrict__ T,
-                                                    const double *__restrict__ Cc) {
+__global__ __launch_bounds__(256) void k_gj_step(const double *__restrict__ X,
+                                                 double *__restrict__ Y, int n, int p0, int b) {
+  __shared__ double Pi[kGJB][kGJB + 1];
+  __shared__ double Rr[kGJB][64 + 1];
   __shared__ double Cs[64][kGJB + 1];
   __shared__ double Ts[kGJB][64 + 1];
   const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, lm = lane & 15, lk = lane >> 4;
-  for (int e = tid; e < 64 * kGJB; e += 256) {
-    const int i = e / kGJB, k = e % kGJB;
-    Cs[i][k] = r0 + i < n ? Cc[(size_t)(r0 + i) * kGJB + k] : 0.0;
-    const int k2 = e / 64, j = e % 64;
-    Ts[k2][j] = c0 + j < n ? T[(size_t)k2 * n + c0 + j] : 0.0;
+  if (w == 0) {
+    // P padded with the identity to kGJB x kGJB; lane i holds row i (lanes >= kGJB: zeros)
+    double row[kGJB];
+#pragma unroll
+    for (int j = 0; j < kGJB; ++j)
+      row[j] = (lane < b && j < b) ? X[(size_t)(p0 + lane) * n + p0 + j] : (lane == j ? 1.0 : 0.0);
+#pragma unroll
+    for (int k = 0; k < kGJB; ++k) {
+      double pr[kGJB];
+#pragma unroll
+      for (int j = 0; j < kGJB; ++j) pr[j] = readlane_d(row[j], k);
+      const double inv = 1.0 / pr[k];
+      // row k: divided by the pivot; other rows: minus (their column-k entry / pivot) row k; the
+      // new column k: 1 / pivot in row k, -(entry / pivot) elsewhere
+      const double mult = lane == k ? 1.0 - inv : row[k] * inv;
+#pragma unroll
+      for (int j = 0; j < kGJB; ++j)
+        if (j != k) row[j] = fma(-mult, pr[j], row[j]);
+      row[k] = lane == k ? inv : -mult;
+    }
+    if (lane < kGJB) {
+#pragma unroll
+      for (int j = 0; j < kGJB; ++j) Pi[lane][j] = row[j];
+    }
+  } else {
+    for (int e = tid - 64; e < kGJB * 64; e += 192) {
+      const int k = e / 64, j = e % 64;
+      Rr[k][j] = (k < b && c0 + j < n) ? X[(size_t)(p0 + k) * n + c0 + j] : 0.0;
+    }
+    for (int e = tid - 64; e < 64 * kGJB; e += 192) {
+      const int i = e / kGJB, k = e % kGJB;
+      Cs[i][k] = (k < b && r0 + i < n) ? X[(size_t)(r0 + i) * n + p0 + k] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < kGJB * 64; e += 256) {
+    const int k = e / 64, j = e % 64, col = c0 + j;
+    double v = 0.0;
+    if (k < b) {
+      if (col >= p0 && col < p0 + b) {
+        v = Pi[k][col - p0];
+      } else {
+#pragma unroll 8
+        for (int l = 0; l < kGJB; ++l) v = fma(Pi[k][l], Rr[l][j], v);
+      }
+    }
+    Ts[k][j] = v;
   }
   __syncthreads();
   v4d acc[4];
@@ -358,9 +363,9 @@ __global__ __launch_bounds__(256) void k_gjb_update(double *__restrict__ A, int 
     for (int i = 0; i < 4; ++i) {
       const int row = r0 + 16 * w + lk + 4 * i;
       if (row >= n) continue;
-      double *dst = A + (size_t)row * n + col;
-      if (row >= p0 && row < p0 + b) *dst = T[(size_t)(row - p0) * n + col];
-      else *dst = (pcol ? 0.0 : *dst) - acc[q][i];
+      const size_t at = (size_t)row * n + col;
+      if (row >= p0 && row < p0 + b) Y[at] = Ts[row - p0][col - c0];
+      else Y[at] = (pcol ? 0.0 : X[at]) - acc[q][i];
     }
   }
 }
@@ -961,32 +966,38 @@ int gemv_batch(hb_ctx *c, const void *A, size_t stride, int R, int C, int nd, co
   return HB_OK;
 }
 
-// In-place inverse of the n x n double matrix A by blocked Gauss-Jordan elimination (no pivoting:
-// A is V_h^0 or a mass matrix, both symmetric positive definite); T, Cc, Ainv: workspace.
-void gj_invert(double *A, int n, double *T, double *Cc, double *Ainv, hipStream_t s) {
+// Inverse of the n x n double matrix held in A (overwritten by the inverse) by blocked
+// Gauss-Jordan elimination without pivoting (A is V_h^0 or a mass matrix, both symmetric positive
+// definite); B: an n x n workspace.  The panels alternate between A and B; with an odd panel count
+// the matrix is first copied to B so that the last panel writes A.
+int gj_invert(hb_ctx *c, double *A, double *B, int n, hipStream_t s) {
   const dim3 tiles((n + 63) / 64, (n + 63) / 64);
-  for (int p0 = 0; p0 < n; p0 += kGJB) {
-    const int b = std::min(kGJB, n - p0);
-    hipLaunchKernelGGL(k_gjb_pivot, dim3(1), dim3(256), 0, s, A, n, p0, b, Ainv);
-    hipLaunchKernelGGL(k_gjb_rows, dim3(grid1d((size_t)kGJB * n)), dim3(256), 0, s, A, n, p0, b,
-                       Ainv, T, Cc);
-    hipLaunchKernelGGL(k_gjb_update, tiles, dim3(256), 0, s, A, n, p0, b, T, Cc);
+  const int panels = (n + kGJB - 1) / kGJB;
+  double *X = A, *Y = B;
+  if (panels & 1) {
+    HB_CHECK(c, hipMemcpyAsync(B, A, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+    std::swap(X, Y);
   }
+  for (int p0 = 0; p0 < n; p0 += kGJB) {
+    hipLaunchKernelGGL(k_gj_step, tiles, dim3(256), 0, s, X, Y, n, p0, std::min(kGJB, n - p0));
+    std::swap(X, Y);
+  }
+  HB_CHECK(c, hipGetLastError());
+  return HB_OK;
 }
 
 int invert_v0(hb_ctx *c, hipStream_t s) {
   if (c->v0inv_valid) return HB_OK;
   const int n = (int)c->ne;
   const size_t nn = (size_t)n * n;
-  if (!c->d_v0inv)
-    HB_CHECK(c, hipMalloc(&c->d_v0inv, sizeof(double) * (nn + 2 * (size_t)kGJB * n + kGJB * kGJB)));
-  double *A = c->d_v0inv, *T = A + nn, *Cc = T + (size_t)kGJB * n, *Ainv = Cc + (size_t)kGJB * n;
+  if (!c->d_v0inv) HB_CHECK(c, hipMalloc(&c->d_v0inv, sizeof(double) * 2 * nn));
+  double *A = c->d_v0inv, *B = A + nn;
   if (c->storage_f32)
     hipLaunchKernelGGL(k_f32_to_f64, dim3(grid1d(nn)), dim3(256), 0, s, (const float *)c->d_V, A, nn);
   else
     HB_CHECK(c, hipMemcpyAsync(A, c->d_V, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-  gj_invert(A, n, T, Cc, Ainv, s);
-  HB_CHECK(c, hipGetLastError());
+  int rc = gj_invert(c, A, B, n, s);
+  if (rc) return rc;
   c->v0inv_valid = true;
   return HB_OK;
 }
@@ -998,17 +1009,19 @@ int ensure_minv(hb_ctx *c, hipStream_t s) {
   if (c->minv_valid) return HB_OK;
   const int n = (int)c->nv;
   const size_t nn = (size_t)n * n;
-  if (!c->d_minv)
-    HB_CHECK(c, hipMalloc(&c->d_minv, sizeof(double) * (nn + 2 * (size_t)kGJB * n + kGJB * kGJB)));
+  // inverse, then kBlockPad zero bytes (read by the Toeplitz product's fragment loads), then the
+  // elimination's second buffer
+  const size_t padn = kBlockPad / sizeof(double);
+  if (!c->d_minv) HB_CHECK(c, hipMalloc(&c->d_minv, sizeof(double) * (2 * nn + padn)));
   std::vector<double> M(nn, 0.0);
   for (int64_t t = 0; t < c->ne; ++t)
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b)
         M[(size_t)c->tris[3 * t + a] * n + c->tris[3 * t + b]] += c->area[t] * (a == b ? 2.0 : 1.0) / 12.0;
-  double *A = c->d_minv, *T = A + nn, *Cc = T + (size_t)kGJB * n, *Ainv = Cc + (size_t)kGJB * n;
+  double *A = c->d_minv, *B = A + nn + padn;
   HB_CHECK(c, hipMemcpyAsync(A, M.data(), sizeof(double) * nn, hipMemcpyHostToDevice, s));
-  gj_invert(A, n, T, Cc, Ainv, s);
-  // the Toeplitz product's fragment loads may read past the last row: zeros there
+  int rc = gj_invert(c, A, B, n, s);
+  if (rc) return rc;
   HB_CHECK(c, hipMemsetAsync(A + nn, 0, kBlockPad, s));
   HB_CHECK(c, hipGetLastError());
   HB_CHECK(c, hipStreamSynchronize(s));  // M lives on the host stack
