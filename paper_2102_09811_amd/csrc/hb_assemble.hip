@@ -252,6 +252,13 @@ __device__ __forceinline__ void sym_taylor2(const AsmParams &p, const SepTabs &T
   const double c0 = T.tscale[3 * d0 + 2], c1 = T.tscale[3 * d1 + 2];
   const double *cv0 = T.taylor + (size_t)(2 * d0) * kTaylorN;
   const double *cv1 = T.taylor + (size_t)(2 * d1) * kTaylorN;
+  // rho^2 clamped where e^{-w} of both blocks is 0 in double anyway (c1 <= c0, w0 >= 1000 gives
+  // w1 >= 750): the exponential's argument stays in the range of its rounding shift
+  const double r2max = 1000.0 / c0;
+  // the transposed order's double layer per test node a, weighted by the basis at a after the pass
+  double t2[2][kFarN];
+#pragma unroll
+  for (int a = 0; a < kFarN; ++a) t2[0][a] = t2[1][a] = 0.0;
 #pragma unroll 1
   for (int b = 0; b < kFarN; ++b) {
     const double y0 = T.geom[(b * 3 + 0) * ne + m] + L.shift;
@@ -260,34 +267,28 @@ __device__ __forceinline__ void sym_taylor2(const AsmParams &p, const SepTabs &T
     const RuleNode Lb = rule_node(L.lam, b);
     const double wb = Lb.w;
     double tv0 = 0.0, tv1 = 0.0, tk0 = 0.0, tk1 = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int a = 0; a < kFarN; ++a) {
       const RuleNode X = rule_node(L.xs, a);
       const double rx = X.x - y0;
       const double ry = X.y - y1;
       const double rz = X.z - y2;
-      const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
-      const double wa = X.w;
-      const double wrn1 = wa * fma(rx, L.nm[0], fma(ry, L.nm[1], rz * L.nm[2]));
-      const double wrn2 = -(wa * wb) * fma(rx, L.nl[0], fma(ry, L.nl[1], rz * L.nl[2]));
+      const double rho2 = fmin(fma(rx, rx, fma(ry, ry, rz * rz)), r2max);
+      const double rn1 = fma(rx, L.nm[0], fma(ry, L.nm[1], rz * L.nm[2]));
+      const double rn2 = -wb * fma(rx, L.nl[0], fma(ry, L.nl[1], rz * L.nl[2]));
       const double w0 = rho2 * c0, w1 = rho2 * c1;
-      const double e0 = exp_neg_m(w0, T.etab), e1 = exp_neg_m(w1, T.etab);
+      // e^{-w} times the test node's weight
+      const double e0 = X.w * exp_neg_m(w0, T.etab), e1 = X.w * exp_neg_m(w1, T.etab);
       double p0, dp0, p1, dp1;
       horner_d<N>(cv0, w0, p0, dp0);
       horner_d<N>(cv1, w1, p1, dp1);
       const double pk0 = (p0 - dp0) * e0, pk1 = (p1 - dp1) * e1;
-      tv0 = fma(wa * e0, p0, tv0);
-      tv1 = fma(wa * e1, p1, tv1);
-      tk0 = fma(wrn1, pk0, tk0);
-      tk1 = fma(wrn1, pk1, tk1);
-      const double u0 = wrn2 * pk0, u1 = wrn2 * pk1;
-      const RuleNode La = rule_node(L.lam, a);
-      const double la[3] = {La.x, La.y, La.z};
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        R.K2[0][k] = fma(u0, la[k], R.K2[0][k]);
-        R.K2[1][k] = fma(u1, la[k], R.K2[1][k]);
-      }
+      tv0 = fma(e0, p0, tv0);
+      tv1 = fma(e1, p1, tv1);
+      tk0 = fma(rn1, pk0, tk0);
+      tk1 = fma(rn1, pk1, tk1);
+      t2[0][a] = fma(rn2, pk0, t2[0][a]);
+      t2[1][a] = fma(rn2, pk1, t2[1][a]);
     }
     R.V[0] = fma(wb, tv0, R.V[0]);
     R.V[1] = fma(wb, tv1, R.V[1]);
@@ -297,6 +298,16 @@ __device__ __forceinline__ void sym_taylor2(const AsmParams &p, const SepTabs &T
       const double phi = wb * lb[k];
       R.K1[0][k] = fma(phi, tk0, R.K1[0][k]);
       R.K1[1][k] = fma(phi, tk1, R.K1[1][k]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < kFarN; ++a) {
+    const RuleNode La = rule_node(L.lam, a);
+    const double la[3] = {La.x, La.y, La.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      R.K2[0][k] = fma(t2[0][a], la[k], R.K2[0][k]);
+      R.K2[1][k] = fma(t2[1][a], la[k], R.K2[1][k]);
     }
   }
 }
@@ -359,7 +370,7 @@ __device__ __forceinline__ void sym_taylor2_32(const AsmParams &p, const SepTabs
 }
 
 template <typename TS, int D, bool MIXED>
-__global__ __launch_bounds__(256, 3) void k_separated(const AsmParams *__restrict__ pp,
+__global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restrict__ pp,
                                                       const double *__restrict__ geom,
                                                       const double *__restrict__ tscale,
                                                       const double *__restrict__ taylor,
@@ -919,7 +930,7 @@ __device__ __forceinline__ void nu_sym_taylor(const AsmParams &p, const SepTabs 
   }
 }
 
-__global__ __launch_bounds__(256, 3) void k_nu_separated(const AsmParams *__restrict__ pp, NuTabs nu,
+__global__ __launch_bounds__(256, 2) void k_nu_separated(const AsmParams *__restrict__ pp, NuTabs nu,
                                                          const int *__restrict__ tasks,
                                                          int ntasks) {
   const AsmParams &p = *pp;
