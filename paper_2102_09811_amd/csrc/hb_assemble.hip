@@ -369,6 +369,15 @@ __device__ __forceinline__ void sym_taylor2_32(const AsmParams &p, const SepTabs
   }
 }
 
+// LDS of the wave, ordered: earlier LDS operations of any lane are seen by later ones.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kSepSlots = 3 * 64;  // distinct trial vertices of one task, at most
+
 template <typename TS, int D, bool MIXED>
 __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restrict__ pp,
                                                       const double *__restrict__ geom,
@@ -376,11 +385,18 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
                                                       const double *__restrict__ taylor,
                                                       const float *__restrict__ taylor32,
                                                       const int *__restrict__ tdeg,
-                                                      const int *__restrict__ tasks, int ntasks) {
+                                                      const int *__restrict__ tasks,
+                                                      const int *__restrict__ tvstart,
+                                                      const int *__restrict__ tverts,
+                                                      const uint8_t *__restrict__ tslots,
+                                                      int ntasks) {
   const AsmParams &p = *pp;
   __shared__ double etab[64];
   __shared__ double lam[kFarN * 4];
   __shared__ double xs[4][kFarN * 4];
+  // the test row's double-layer contributions of the current pass (two blocks) per distinct
+  // trial vertex of the wave's task: added in LDS, then once per vertex to K
+  __shared__ double kacc[4][2][kSepSlots];
   stage_exp_tab_pos(etab);
   const SepTabs T{geom, tscale, taylor, taylor32, tdeg, etab};
   // one task per wave: test panel l and up to 64 trial panels m0, m0 + 1, ... (mod E_x); every
@@ -393,9 +409,11 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
   __syncthreads();
   if (!valid) return;
   const int lane = threadIdx.x & 63;
-  if (lane >= __builtin_amdgcn_readfirstlane(tasks[3 * task + 2])) return;
+  // lanes past the task's count integrate a copy of its first pair and store nothing (they stay
+  // for the per-vertex flush of the double layer)
+  const bool inrange = lane < __builtin_amdgcn_readfirstlane(tasks[3 * task + 2]);
   const int ne = p.ne;
-  int m = __builtin_amdgcn_readfirstlane(tasks[3 * task + 1]) + lane;
+  int m = __builtin_amdgcn_readfirstlane(tasks[3 * task + 1]) + (inrange ? lane : 0);
   if (m >= ne) m -= ne;
   const int vl[3] = {p.tris[3 * l], p.tris[3 * l + 1], p.tris[3 * l + 2]};
   const int vm[3] = {p.tris[3 * m], p.tris[3 * m + 1], p.tris[3 * m + 2]};
@@ -404,7 +422,15 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) touch |= vl[i] == vm[j];
-  const bool active = !touch;
+  const bool active = inrange && !touch;
+  double(*kw)[kSepSlots] = kacc[threadIdx.x >> 6];
+  const int sv0 = __builtin_amdgcn_readfirstlane(tvstart[task]);
+  const int nslots = __builtin_amdgcn_readfirstlane(tvstart[task + 1]) - sv0;
+  int slot[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) slot[k] = tslots[((size_t)task * 3 + k) * 64 + lane];
+  for (int e = lane; e < 2 * kSepSlots; e += 64) kw[e / kSepSlots][e % kSepSlots] = 0.0;
+  wave_lds_sync();
   SepLane L;
   L.xs = xs[threadIdx.x >> 6];
   L.lam = lam;
@@ -478,11 +504,25 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
           const double ks = T.tscale[3 * dj + 1] * scale;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
-            add_block_K<TS>(p, dj, l, vm[k], R.K1[j][k] * ks);
+            atomicAdd(&kw[j][slot[k]], R.K1[j][k] * ks);
             add_block_KT<TS>(p, dj, m, vl[k], R.K2[j][k] * ks);
           }
         }
       }
+    }
+    if (p.do_K) {
+      // the row's per-vertex sums of this pass to K, each vertex once, and the slots cleared
+      wave_lds_sync();
+      for (int sidx = lane; sidx < nslots; sidx += 64) {
+        const int v = tverts[sv0 + sidx];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double acc = kw[j][sidx];
+          if (acc != 0.0 && d + j < p.nt) add_block_K<TS>(p, d + j, l, v, acc);
+          kw[j][sidx] = 0.0;
+        }
+      }
+      wave_lds_sync();
     }
   }
 }
@@ -1199,34 +1239,41 @@ void launch_nu_touching(const AsmParams *dp, const NuTabs &nu, const TouchPair *
   hipLaunchKernelGGL(k_nu_touching, dim3((unsigned)npairs), dim3(64), 0, s, dp, pairs, rule, nu);
 }
 
+struct SepTasks {
+  const int32_t *tasks, *vstart, *verts;
+  const uint8_t *slots;
+  int n;
+};
+
 template <typename TS, int D>
 static void launch_sep(dim3 grid, hipStream_t s, const AsmParams *dp, const AsmParams &hp,
-                       const int32_t *tasks, int ntasks, bool mixed) {
+                       const SepTasks &t, bool mixed) {
   if (mixed)
     hipLaunchKernelGGL((k_separated<TS, D, true>), grid, dim3(256), 0, s, dp, hp.geom, hp.tscale,
-                       hp.taylor, hp.taylor32, hp.tdeg, tasks, ntasks);
+                       hp.taylor, hp.taylor32, hp.tdeg, t.tasks, t.vstart, t.verts, t.slots, t.n);
   else
     hipLaunchKernelGGL((k_separated<TS, D, false>), grid, dim3(256), 0, s, dp, hp.geom, hp.tscale,
-                       hp.taylor, hp.taylor32, hp.tdeg, tasks, ntasks);
+                       hp.taylor, hp.taylor32, hp.tdeg, t.tasks, t.vstart, t.verts, t.slots, t.n);
 }
 
 void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, const int32_t *tasks,
+                               const int32_t *vstart, const int32_t *verts, const uint8_t *slots,
                                int64_t ntasks, int precision, int storage_f32, hipStream_t s) {
   dim3 grid((unsigned)((ntasks + 3) / 4));
-  const int nt4 = (int)ntasks;
+  const SepTasks t{tasks, vstart, verts, slots, (int)ntasks};
   const bool mixed = precision == HB_PREC_MIXED;
   switch (p.dsw) {
     case 16:
-      if (storage_f32) launch_sep<float, 16>(grid, s, dp, p, tasks, nt4, mixed);
-      else launch_sep<double, 16>(grid, s, dp, p, tasks, nt4, mixed);
+      if (storage_f32) launch_sep<float, 16>(grid, s, dp, p, t, mixed);
+      else launch_sep<double, 16>(grid, s, dp, p, t, mixed);
       break;
     case 8:
-      if (storage_f32) launch_sep<float, 8>(grid, s, dp, p, tasks, nt4, mixed);
-      else launch_sep<double, 8>(grid, s, dp, p, tasks, nt4, mixed);
+      if (storage_f32) launch_sep<float, 8>(grid, s, dp, p, t, mixed);
+      else launch_sep<double, 8>(grid, s, dp, p, t, mixed);
       break;
     default:
-      if (storage_f32) launch_sep<float, 3>(grid, s, dp, p, tasks, nt4, mixed);
-      else launch_sep<double, 3>(grid, s, dp, p, tasks, nt4, mixed);
+      if (storage_f32) launch_sep<float, 3>(grid, s, dp, p, t, mixed);
+      else launch_sep<double, 3>(grid, s, dp, p, t, mixed);
       break;
   }
 }

@@ -534,6 +534,38 @@ int build_tables(hb_ctx *c) {
     if (!tasks.empty())
       if ((rc = upload(c, (void **)&c->d_sep_tasks, tasks.data(), tasks.size() * sizeof(int32_t))))
         return rc;
+    // the distinct vertices of each task's trial panels (slots, in order of first appearance) and
+    // each lane's slot of its trial panel's three vertices: the kernel gathers the test row's
+    // double-layer contributions per vertex in LDS and adds each vertex once per pass
+    std::vector<int32_t> vstart(1, 0), verts;
+    std::vector<uint8_t> slots((size_t)c->n_sep_tasks * 3 * 64, 0);
+    std::unordered_map<int32_t, int> slot_of;
+    for (int64_t t = 0; t < c->n_sep_tasks; ++t) {
+      slot_of.clear();
+      const int64_t m0 = tasks[3 * t + 1], cnt = tasks[3 * t + 2];
+      for (int64_t i = 0; i < cnt; ++i) {
+        const int64_t m = (m0 + i) % n;
+        for (int k = 0; k < 3; ++k) {
+          const int32_t v = c->tris[3 * m + k];
+          auto it = slot_of.find(v);
+          int sidx;
+          if (it == slot_of.end()) {
+            sidx = (int)slot_of.size();
+            slot_of.emplace(v, sidx);
+            verts.push_back(v);
+          } else {
+            sidx = it->second;
+          }
+          slots[((size_t)t * 3 + k) * 64 + i] = (uint8_t)sidx;  // at most 3 * 64 = 192 slots
+        }
+      }
+      vstart.push_back((int32_t)verts.size());
+    }
+    if (!tasks.empty()) {
+      if ((rc = upload(c, (void **)&c->d_sep_vstart, vstart.data(), vstart.size() * sizeof(int32_t)))) return rc;
+      if ((rc = upload(c, (void **)&c->d_sep_verts, verts.data(), verts.size() * sizeof(int32_t)))) return rc;
+      if ((rc = upload(c, (void **)&c->d_sep_slots, slots.data(), slots.size()))) return rc;
+    }
   }
   // preconditioner pattern: itself, edge neighbours, vertex neighbours by centroid distance
   {
@@ -939,7 +971,7 @@ int hb_is_nonuniform(const hb_ctx *c) { return c && c->nu ? 1 : 0; }
 void hb_destroy(hb_ctx *c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
-  void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_touch_list, c->d_sep_tasks, c->d_taylor,
+  void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_touch_list, c->d_sep_tasks, c->d_sep_vstart, c->d_sep_verts, c->d_sep_slots, c->d_taylor,
                   c->d_taylor32, c->d_tdeg, c->d_V32, c->d_tscale, c->d_mass,
                   c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d,
@@ -1088,7 +1120,8 @@ int hb_assemble(hb_ctx *c, uint32_t ops, int32_t precision, void *stream) {
   }
   HB_HIP(c, hipEventRecord(c->ev[0], s));
   if (c->n_sep_tasks > 0)
-    hb::launch_assemble_separated(c->d_params, p, c->d_sep_tasks, c->n_sep_tasks, precision,
+    hb::launch_assemble_separated(c->d_params, p, c->d_sep_tasks, c->d_sep_vstart, c->d_sep_verts,
+                                  c->d_sep_slots, c->n_sep_tasks, precision,
                                   c->storage_f32, s);
   HB_HIP(c, hipGetLastError());
   if (p.do_K) {

@@ -122,7 +122,10 @@ void launch_nu_touching(const AsmParams *dp, const NuTabs &nu, const TouchPair *
 int nu_apply(hb_ctx *c, const double *A, int R, int C, const double *x, double *y, hipStream_t s);
 
 // dp: device copy of p (kernels read their parameters from device memory)
+// tasks: (test panel, first trial panel, lanes) per wave; vstart / verts: each task's distinct
+// trial vertices (CSR); slots: [task][3][64] the slot of each lane's trial vertex k
 void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, const int32_t *tasks,
+                               const int32_t *vstart, const int32_t *verts, const uint8_t *slots,
                                int64_t ntasks, int precision, int storage_f32, hipStream_t s);
 void launch_fold_KT(const AsmParams &p, int storage_f32, hipStream_t s);
 // list: entries of the touching-pair kernels, pair indices, the last nsym of them ~index for
@@ -183,6 +186,9 @@ struct hb_ctx {
   int32_t *d_sep_tasks = nullptr;    // [n][3]: (test panel l, first trial panel m0, lanes) per wave;
                                      // lane i takes trial panel (m0 + i) mod E_x
   int64_t n_sep_tasks = 0;
+  int32_t *d_sep_vstart = nullptr;   // [n_sep_tasks + 1]: CSR of the tasks' distinct trial vertices
+  int32_t *d_sep_verts = nullptr;
+  uint8_t *d_sep_slots = nullptr;    // [n_sep_tasks][3][64]: slot of each lane's trial vertex k
   hb::SSRule ss[4];
   double *d_taylor = nullptr, *d_tscale = nullptr;
   float *d_taylor32 = nullptr;
