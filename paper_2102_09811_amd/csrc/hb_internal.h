@@ -246,7 +246,7 @@ struct hb_ctx {
   double *h_res = nullptr;           // pinned: GMRES residual estimates, read one step late
   int h_res_n = 0;
   hipEvent_t ev_step = nullptr, ev_prev = nullptr;
-  double *d_reprq = nullptr;         // potentials: Q_{2k}(w) / (2k+1)! for p = 3/2 and 5/2
+  double *d_reprq = nullptr;         // potentials: Q_{2k}(w) / (2k+1)! for p = 3/2
   double *d_apply = nullptr;         // per-group partial results of the Toeplitz apply
   size_t apply_bytes = 0;
   // non-uniform time grid (hb_create_nonuniform): nodes t_0 = 0 < ... < t_nt, packed blocks

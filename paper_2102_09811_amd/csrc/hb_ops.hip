@@ -126,7 +126,8 @@ template <typename TA, int NTC>
 __global__ __launch_bounds__(256) void k_toeplitz(const TA *__restrict__ A,
                                                   const double *__restrict__ X,
                                                   TA *__restrict__ P, int nt, int R, int C,
-                                                  int cpg, int dlo, int dhi, int jlo, int jhi) {
+                                                  int cpg, int dlo, int dhi, int jlo, int jhi,
+                                                  int klo, int khi) {
   typedef Mfma<TA> M;
   constexpr int NT = 16 * NTC;
   __shared__ TA Xs[(NT + 16) * kXS];
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(256) void k_toeplitz(const TA *__restrict__ A,
 #pragma unroll
   for (int n = 0; n < NTC; ++n) {
     const int k = 16 * n + lm;
-    if (k >= nt) continue;
+    if (k < klo || k >= khi) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int rr = blockIdx.x * TR + 16 * w + M::row(lk, i);
@@ -166,11 +167,12 @@ __global__ __launch_bounds__(256) void k_toeplitz(const TA *__restrict__ A,
   }
 }
 
-// Y[i] = sum_g P[g][i] (sub: Y[i] -= that sum, for i >= i0 only), added in double in a fixed order
+// Y[i] = sum_g P[g][i] for i in [i0, i1) (sub: Y[i] -= that sum), added in double in a fixed
+// order; n is the stride between the parts
 template <typename TP>
 __global__ void k_sum_groups(const TP *__restrict__ P, int G, size_t n, double *__restrict__ Y,
-                             int sub, size_t i0) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+                             int sub, size_t i0, size_t i1) {
+  for (size_t i = i0 + blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < i1; i += (size_t)gridDim.x * blockDim.x) {
     double s = 0.0;
     int g = 0;
     for (; g + 8 <= G; g += 8) {  // eight loads in flight, added in order
@@ -182,7 +184,7 @@ __global__ void k_sum_groups(const TP *__restrict__ P, int G, size_t n, double *
     }
     for (; g < G; ++g) s += (double)P[(size_t)g * n + i];
     if (!sub) Y[i] = s;
-    else if (i >= i0) Y[i] -= s;
+    else Y[i] -= s;
   }
 }
 
@@ -278,7 +280,7 @@ __global__ void k_mass_half_T(const double *__restrict__ mass, const int32_t *__
 // which is b steps of scalar Gauss-Jordan at once.  Every workgroup (a 64 x 64 tile of Y) inverts
 // the pivot block itself -- wave 0, one row per lane in registers, the pivot row broadcast with
 // readlane, while the other waves stage X[R, tile columns] and X[tile rows, C] -- then forms its
-// slice of T = P^{-1} X[R, tile columns] and updates the tile with a rank-b product on MFMA.
+// slice of T = P^{-1} X[R, tile columns] and updates the tile with a rank-b product, both on MFMA.
 constexpr int kGJB = 32;
 
 __device__ __forceinline__ double readlane_d(double v, int l) {
@@ -295,6 +297,17 @@ __global__ __launch_bounds__(256) void k_gj_step(const double *__restrict__ X,
   __shared__ double Ts[kGJB][64 + 1];
   const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, lm = lane & 15, lk = lane >> 4;
+  // this lane's 16 entries of the tile, loaded now so that their latency hides behind the rest
+  double xt[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int col = c0 + 16 * q + lm;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = r0 + 16 * w + lk + 4 * i;
+      xt[q][i] = (row < n && col < n) ? X[(size_t)row * n + col] : 0.0;
+    }
+  }
   if (w == 0) {
     // P padded with the identity to kGJB x kGJB; lane i holds row i (lanes >= kGJB: zeros)
     double row[kGJB];
@@ -330,18 +343,27 @@ __global__ __launch_bounds__(256) void k_gj_step(const double *__restrict__ X,
     }
   }
   __syncthreads();
-  for (int e = tid; e < kGJB * 64; e += 256) {
-    const int k = e / 64, j = e % 64, col = c0 + j;
-    double v = 0.0;
-    if (k < b) {
-      if (col >= p0 && col < p0 + b) {
-        v = Pi[k][col - p0];
-      } else {
-#pragma unroll 8
-        for (int l = 0; l < kGJB; ++l) v = fma(Pi[k][l], Rr[l][j], v);
+  // T = P^{-1} X[R, tile columns] on MFMA: wave w forms the 16 x 16 tiles (w >> 1, 2 (w & 1) + u);
+  // rows of T past b are zero (P^{-1} is padded with identity rows, the staged rows are zero)
+  {
+    const int a0 = 16 * (w >> 1);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q0 = 16 * (2 * (w & 1) + u);
+      v4d t = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < kGJB / 4; ++st)
+        t = __builtin_amdgcn_mfma_f64_16x16x4f64(Pi[a0 + lm][4 * st + lk], Rr[4 * st + lk][q0 + lm],
+                                                 t, 0, 0, 0);
+      const int col = c0 + q0 + lm;
+      const bool pcol = col >= p0 && col < p0 + b;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = a0 + lk + 4 * i;
+        // the pivot columns of Y[R, :] are P^{-1} itself
+        Ts[k][q0 + lm] = pcol ? (k < b ? Pi[k][col - p0] : 0.0) : t[i];
       }
     }
-    Ts[k][j] = v;
   }
   __syncthreads();
   v4d acc[4];
@@ -365,7 +387,7 @@ __global__ __launch_bounds__(256) void k_gj_step(const double *__restrict__ X,
       if (row >= n) continue;
       const size_t at = (size_t)row * n + col;
       if (row >= p0 && row < p0 + b) Y[at] = Ts[row - p0][col - c0];
-      else Y[at] = (pcol ? 0.0 : X[at]) - acc[q][i];
+      else Y[at] = (pcol ? 0.0 : xt[q][i]) - acc[q][i];
     }
   }
 }
@@ -559,17 +581,19 @@ inline int grid1d(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 8192
 //     int (r . n)/(2 delta) G = (r . n)/2 (4 pi alpha)^{-3/2} h s^{-5/2} e^{-w} S_{5/2}(w),
 //     S_p(w) = sum_k eps_m^{2k} / (2k+1)! Q^p_{2k}(w),  w = rho^2 / (4 alpha s),  eps_m = h / (2 s),
 //   truncated so that the dropped terms stay below ~6e-16 of the interval's scale (eps_m <=
-//   1 / (2m - 1)).  The workgroup tabulates the coefficients of S_{3/2}, S_{5/2} in w for every m
-//   in LDS; each lane then walks (panel, m, node), reusing the interval's data and coefficients
-//   for the 7 nodes of its panel.
+//   1 / (2m - 1)).  Since (r . n)/(2 delta) G carries one more power 1/delta than G, termwise
+//   Q^{5/2}_n = Q^{3/2}_n - (Q^{3/2}_n)' (the prime is d/dw), so S_{5/2} = S_{3/2} - S_{3/2}' and one
+//   Horner sweep with the derivative gives both.  The workgroup tabulates the coefficients of
+//   S_{3/2} in w for every m in LDS; each lane then walks (panel, m, node), reusing the interval's
+//   data and coefficients for the 7 nodes of its panel.
 constexpr int kReprClosed = 2;  // intervals m = 1, 2 behind the current one in closed form
 
 __device__ __forceinline__ int repr_deg(int m) {
   return m < 4 ? 20 : m < 6 ? 16 : m < 8 ? 14 : m < 16 ? 12 : m < 32 ? 10 : 8;
 }
 
-// LDS offset of the table of interval m (m >= 3): [c_m, prefV_m, prefK_m, S_3/2 coefficients,
-// S_5/2 coefficients], deg(m) + 1 coefficients each.
+// LDS offset of the table of interval m (m >= 3): [c_m, prefV_m, prefK_m, S_3/2 coefficients],
+// deg(m) + 1 coefficients.
 __device__ __forceinline__ int repr_off(int m) {
   int off = 0;
   const int lo[6] = {3, 4, 6, 8, 16, 32}, hi[6] = {4, 6, 8, 16, 32, 1 << 30};
@@ -577,51 +601,49 @@ __device__ __forceinline__ int repr_off(int m) {
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     const int n = max(0, min(m, hi[c]) - lo[c]);
-    off += n * (3 + 2 * (deg[c] + 1));
+    off += n * (3 + deg[c] + 1);
   }
   return off;
 }
 
+// Intervals m = mlo .. mhi-1 of one degree class (polynomial length N) for panel j: adds the
+// panel's single-layer sum (weights w, before the panel's area) to ps and its double-layer sum
+// (data g at the panel's vertices) to pd.
 template <int N>
 __device__ __forceinline__ void repr_taylor(const AsmParams &p, const double *__restrict__ tab,
                                             const double *__restrict__ w,
                                             const double *__restrict__ g, int k, int mlo, int mhi,
-                                            int j, int v0, int v1, int v2, double area,
+                                            int j, int v0, int v1, int v2,
                                             const double (&r2)[kFarN], const double (&rn)[kFarN],
-                                            const double *etab, double &accs, double &accd) {
+                                            const double *etab, double &ps, double &pd) {
   const int ne = p.ne, nv = p.nv;
+  const double *T = tab + repr_off(mlo);
 #pragma unroll 1
-  for (int m = mlo; m < mhi; ++m) {
-    const double *T = tab + repr_off(m);
+  for (int m = mlo; m < mhi; ++m, T += 3 + N) {
     const double cm = T[0];
     const int i = k - m;
-    const double wi = w[(size_t)i * ne + j] * T[1] * area;
+    const double wi = w[(size_t)i * ne + j] * T[1];
     const double *gi = g + (size_t)i * nv;
-    const double pk = T[2] * area;
-    const double g0 = gi[v0] * pk, g1 = gi[v1] * pk, g2 = gi[v2] * pk;
-    double e[kFarN];
-    {
-      double c[N];
+    const double pk = T[2];
+    const double g0 = gi[v0], g1 = gi[v1], g2 = gi[v2];
+    double c[N];
 #pragma unroll
-      for (int n = 0; n < N; ++n) c[n] = T[3 + n];
+    for (int n = 0; n < N; ++n) c[n] = T[3 + n];
+    double sV = 0.0, sK0 = 0.0, sK1 = 0.0, sK2 = 0.0;
 #pragma unroll
-      for (int q = 0; q < kFarN; ++q) {
-        const double x = r2[q] * cm;
-        e[q] = exp_neg_t(x, etab);
-        accs = fma(p.w7[q] * wi * e[q], horner<N>(c, x), accs);
-      }
+    for (int q = 0; q < kFarN; ++q) {
+      const double x = r2[q] * cm;
+      const double ew = exp_neg_m(x, etab) * p.w7[q];
+      double P, dP;
+      horner_d<N>(c, x, P, dP);
+      sV = fma(ew, P, sV);
+      const double u = ew * rn[q] * (P - dP);
+      sK0 = fma(p.lam7[q][0], u, sK0);
+      sK1 = fma(p.lam7[q][1], u, sK1);
+      sK2 = fma(p.lam7[q][2], u, sK2);
     }
-    {
-      double c[N];
-#pragma unroll
-      for (int n = 0; n < N; ++n) c[n] = T[3 + N + n];
-#pragma unroll
-      for (int q = 0; q < kFarN; ++q) {
-        const double x = r2[q] * cm;
-        const double gq = fma(p.lam7[q][0], g0, fma(p.lam7[q][1], g1, p.lam7[q][2] * g2));
-        accd = fma(p.w7[q] * rn[q] * gq * e[q], horner<N>(c, x), accd);
-      }
-    }
+    ps = fma(wi, sV, ps);
+    pd = fma(pk, fma(g0, sK0, fma(g1, sK1, g2 * sK2)), pd);
   }
 }
 
@@ -644,33 +666,32 @@ __global__ __launch_bounds__(256, 2) void k_repr(const AsmParams *__restrict__ p
   if (eps < 0.0) eps = 0.0;
   constexpr double kPi = 3.14159265358979323846;
   __shared__ double etab[64];
-  stage_exp_tab(etab);
+  stage_exp_tab_pos(etab);
   // the series' coefficient table Q, staged once per workgroup
-  constexpr int kQn = 2 * kReprQ * (kReprDeg + 1);
+  constexpr int kQn = kReprQ * (kReprDeg + 1);
   __shared__ double qs[kQn];
   for (int i = threadIdx.x; i < kQn; i += blockDim.x) qs[i] = qtab[i];
   __syncthreads();
-  // per-interval tables: one thread per (interval m, series, coefficient), so that the long
-  // tables of the near intervals are spread over the workgroup
-  constexpr int kItems = 2 * (kReprDeg + 1);
+  // per-interval tables: one thread per (interval m, coefficient), so that the long tables of
+  // the near intervals are spread over the workgroup
+  constexpr int kItems = kReprDeg + 1;
   const int nitems = max(0, k - kReprClosed) * kItems;
   for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
     const int m = kReprClosed + 1 + it / kItems;
-    const int pq = (it % kItems) / (kReprDeg + 1), jj = it % (kReprDeg + 1);
-    const int D = repr_deg(m), N = D + 1;
-    if (jj >= N) continue;
+    const int jj = it % kItems;
+    const int D = repr_deg(m);
+    if (jj > D) continue;
     double *T = tab + repr_off(m);
     const double sm = (m - 0.5) * h + eps;
     const double em = h / (2.0 * sm), e2 = em * em;
-    if (pq == 0 && jj == 0) {
+    if (jj == 0) {
       T[0] = 1.0 / (4.0 * al * sm);
       T[1] = 4.0 * kPi * al * h * pow(4.0 * kPi * al * sm, -1.5);
       T[2] = 2.0 * kPi * pow(4.0 * kPi * al, -1.5) * h * pow(sm, -2.5);
     }
-    const double *Q = qs + pq * kReprQ * (kReprDeg + 1);
     double c = 0.0;
-    for (int kk = D / 2; kk >= 0; --kk) c = fma(c, e2, 2 * kk >= jj ? Q[kk * (kReprDeg + 1) + jj] : 0.0);
-    T[3 + pq * N + jj] = c;
+    for (int kk = D / 2; kk >= 0; --kk) c = fma(c, e2, 2 * kk >= jj ? qs[kk * (kReprDeg + 1) + jj] : 0.0);
+    T[3 + jj] = c;
   }
   __syncthreads();
 
@@ -730,12 +751,15 @@ __global__ __launch_bounds__(256, 2) void k_repr(const AsmParams *__restrict__ p
     }
     // Taylor form for m = 3 .. k, by degree class
     const int m0 = kReprClosed + 1;
-    repr_taylor<21>(p, tab, w, g, k, m0, min(k + 1, 4), j, v0, v1, v2, area, r2, rn, etab, accs, accd);
-    repr_taylor<17>(p, tab, w, g, k, 4, min(k + 1, 6), j, v0, v1, v2, area, r2, rn, etab, accs, accd);
-    repr_taylor<15>(p, tab, w, g, k, 6, min(k + 1, 8), j, v0, v1, v2, area, r2, rn, etab, accs, accd);
-    repr_taylor<13>(p, tab, w, g, k, 8, min(k + 1, 16), j, v0, v1, v2, area, r2, rn, etab, accs, accd);
-    repr_taylor<11>(p, tab, w, g, k, 16, min(k + 1, 32), j, v0, v1, v2, area, r2, rn, etab, accs, accd);
-    repr_taylor<9>(p, tab, w, g, k, 32, k + 1, j, v0, v1, v2, area, r2, rn, etab, accs, accd);
+    double ps = 0.0, pd = 0.0;
+    repr_taylor<21>(p, tab, w, g, k, m0, min(k + 1, 4), j, v0, v1, v2, r2, rn, etab, ps, pd);
+    repr_taylor<17>(p, tab, w, g, k, 4, min(k + 1, 6), j, v0, v1, v2, r2, rn, etab, ps, pd);
+    repr_taylor<15>(p, tab, w, g, k, 6, min(k + 1, 8), j, v0, v1, v2, r2, rn, etab, ps, pd);
+    repr_taylor<13>(p, tab, w, g, k, 8, min(k + 1, 16), j, v0, v1, v2, r2, rn, etab, ps, pd);
+    repr_taylor<11>(p, tab, w, g, k, 16, min(k + 1, 32), j, v0, v1, v2, r2, rn, etab, ps, pd);
+    repr_taylor<9>(p, tab, w, g, k, 32, k + 1, j, v0, v1, v2, r2, rn, etab, ps, pd);
+    accs = fma(area, ps, accs);
+    accd = fma(area, pd, accd);
   }
   __shared__ double red[2][4];
 #pragma unroll
@@ -810,14 +834,18 @@ static void *g_scratch_ptr[kMaxDevices];
 static std::mutex g_scratch_mu;
 
 // Y[k] = sum_{d in [dlo, dhi)} A^d X[k - d] with X restricted to the times [jlo, jhi); with sub,
-// y[k] -= Y[k] for k >= ksub instead of y = Y.
+// y[k] -= Y[k] for ksub <= k < khi (khi < 0: E_t) instead of y = Y.  ntw > 0: x and y hold a
+// window of ntw time steps (the product sees no earlier times).
 // scratch / scratch_bytes: caller-provided room for the partial results (no allocation; the split
 // is narrowed to fit, HB_EINVAL if one part does not fit); NULL: the context's own buffer.
 template <typename TA>
 static int launch_toeplitz(hb_ctx *c, const TA *A, int R, int C, const double *x, double *y,
                            hipStream_t s, int dlo, int dhi, int jlo, int jhi, bool sub, int ksub,
-                           void *scratch_buf = nullptr, size_t scratch_bytes = 0) {
-  const int nt = c->nt;
+                           void *scratch_buf = nullptr, size_t scratch_bytes = 0, int khi = -1,
+                           int ntw = -1) {
+  const int nt = ntw > 0 ? ntw : c->nt;
+  const int klo = sub ? ksub : 0;
+  if (khi < 0 || !sub) khi = nt;
   if (nt > 256) {
     c->err = "toeplitz apply supports E_t <= 256";
     return HB_EINVAL;
@@ -858,7 +886,7 @@ static int launch_toeplitz(hb_ctx *c, const TA *A, int R, int C, const double *x
   dim3 grid(sp.rt, sp.groups, sp.slices);
 #define HB_TOEP(NTC_)                                                                          \
   hipLaunchKernelGGL((k_toeplitz<TA, NTC_>), grid, dim3(256), 0, s, A, x, P, nt, R, C, sp.cpg, \
-                     dlo, dhi, jlo, jhi)
+                     dlo, dhi, jlo, jhi, klo, khi)
   switch (ntc) {
     case 1: HB_TOEP(1); break;
     case 2: HB_TOEP(2); break;
@@ -867,8 +895,9 @@ static int launch_toeplitz(hb_ctx *c, const TA *A, int R, int C, const double *x
     default: HB_TOEP(16); break;
   }
 #undef HB_TOEP
-  hipLaunchKernelGGL(k_sum_groups<TA>, dim3(grid1d(ny)), dim3(256), 0, s, P, parts, ny, y,
-                     sub ? 1 : 0, (size_t)ksub * R);
+  if (khi > klo)
+    hipLaunchKernelGGL(k_sum_groups<TA>, dim3(grid1d((size_t)(khi - klo) * R)), dim3(256), 0, s, P,
+                       parts, ny, y, sub ? 1 : 0, (size_t)klo * R, (size_t)khi * R);
   HB_CHECK(c, hipGetLastError());
   return HB_OK;
 }
@@ -1236,10 +1265,47 @@ int gmres(hb_ctx *c, int op, const double *b, double *x, double tol, int maxit, 
 }
 
 // Time marching (Sec. 3: the block lower-triangular system solved step by step): w^k = (V^0)^{-1}
-// (b^k - sum_{d>=1} V^d w^{k-d}).  Steps go in chunks of B ~ sqrt(E_t): inside a chunk the
-// history of the chunk's own steps is subtracted block by block (d < B); after the chunk, one
-// windowed Toeplitz product subtracts its steps' contribution from every later step.  Each block
-// is then read about E_t / B + B / 2 times instead of E_t / 2 times.
+// (b^k - sum_{d>=1} V^d w^{k-d}).  The steps [k0, k1) are split in halves: the first half is
+// solved, one windowed Toeplitz product subtracts its contribution from the second half's right
+// sides (blocks d = 1 .. k1 - k0 - 1, sources [k0, km), targets [km, k1)), then the second half is
+// solved.  Runs of at most kTmLeaf steps go step by step, their own history subtracted block by
+// block.  Every level of the halving reads each block about once, so the blocks are streamed
+// about log2(E_t / kTmLeaf) + kTmLeaf / 2 + 1 times in all instead of E_t / 2 times; each product
+// sees only its window of n steps, so its MFMA work covers n, not E_t, output times.
+constexpr int kTmLeaf = 4;
+
+static int tm_solve(hb_ctx *c, double *r, double *w, int k0, int k1, hipStream_t s) {
+  const int ne = (int)c->ne;
+  const size_t blk = (size_t)ne * ne;
+  int rc;
+  if (k1 - k0 <= kTmLeaf) {
+    const void *V1 = (const char *)c->d_V + blk * (c->storage_f32 ? 4 : 8);
+    for (int k = k0; k < k1; ++k) {
+      // w^k = (V^0)^{-1} r^k
+      if ((rc = gemv_batch(c, c->d_v0inv, 0, ne, ne, 1, r + (size_t)k * ne, w + (size_t)k * ne,
+                           1.0, 0.0, 0, s)))
+        return rc;
+      // r^{k+d} -= V^d w^k inside the run, d = 1 .. k1-1-k
+      if ((rc = gemv_batch(c, V1, blk, ne, ne, k1 - 1 - k, w + (size_t)k * ne,
+                           r + (size_t)(k + 1) * ne, -1.0, 1.0, (size_t)ne, s)))
+        return rc;
+    }
+    return HB_OK;
+  }
+  const int km = k0 + (k1 - k0) / 2, n = k1 - k0, h = km - k0;
+  if ((rc = tm_solve(c, r, w, k0, km, s))) return rc;
+  // the window [k0, k1): sources [0, h), targets [h, n)
+  double *wv = w + (size_t)k0 * ne, *rv = r + (size_t)k0 * ne;
+  if (c->storage_f32)
+    rc = launch_toeplitz<float>(c, (const float *)c->d_V, ne, ne, wv, rv, s, 1, n, 0, h, true, h,
+                                nullptr, 0, n, n);
+  else
+    rc = launch_toeplitz<double>(c, (const double *)c->d_V, ne, ne, wv, rv, s, 1, n, 0, h, true, h,
+                                 nullptr, 0, n, n);
+  if (rc) return rc;
+  return tm_solve(c, r, w, km, k1, s);
+}
+
 int time_march(hb_ctx *c, const double *b, double *w, hipStream_t s) {
   const int nt = c->nt, ne = (int)c->ne;
   const size_t n = (size_t)nt * ne;
@@ -1248,33 +1314,7 @@ int time_march(hb_ctx *c, const double *b, double *w, hipStream_t s) {
   if ((rc = ensure_work(c, sizeof(double) * n))) return rc;
   double *r = c->d_work;
   HB_CHECK(c, hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  const size_t blk = (size_t)ne * ne;
-  const void *V1 = (const char *)c->d_V + blk * (c->storage_f32 ? 4 : 8);
-  const int B = std::max(1, (int)std::lround(std::sqrt((double)nt)));
-  for (int k0 = 0; k0 < nt; k0 += B) {
-    const int k1 = std::min(k0 + B, nt);
-    for (int k = k0; k < k1; ++k) {
-      // w^k = (V^0)^{-1} r^k
-      if ((rc = gemv_batch(c, c->d_v0inv, 0, ne, ne, 1, r + (size_t)k * ne, w + (size_t)k * ne,
-                           1.0, 0.0, 0, s)))
-        return rc;
-      // r^{k+d} -= V^d w^k inside the chunk, d = 1 .. k1-1-k
-      if ((rc = gemv_batch(c, V1, blk, ne, ne, k1 - 1 - k, w + (size_t)k * ne,
-                           r + (size_t)(k + 1) * ne, -1.0, 1.0, (size_t)ne, s)))
-        return rc;
-    }
-    if (k1 < nt) {
-      // r^{k'} -= sum_d V^d w^{k'-d} for k' >= k1, sources k0 .. k1-1, d = 1 .. nt-1-k0
-      if (c->storage_f32)
-        rc = launch_toeplitz<float>(c, (const float *)c->d_V, ne, ne, w, r, s, 1, nt - k0, k0, k1,
-                                    true, k1);
-      else
-        rc = launch_toeplitz<double>(c, (const double *)c->d_V, ne, ne, w, r, s, 1, nt - k0, k0,
-                                     k1, true, k1);
-      if (rc) return rc;
-    }
-  }
-  return HB_OK;
+  return tm_solve(c, r, w, 0, nt, s);
 }
 
 // Two vectors of n doubles behind c->d_ir (residual and correction), shared with mixed_ir
@@ -1639,18 +1679,19 @@ int hb_eval_repr(hb_ctx *c, const double *pts, int64_t P, const double *w, const
     HB_CHECK(c, hipMemcpy(c->d_params_repr, &c->params, sizeof(AsmParams), hipMemcpyHostToDevice));
   }
   if (!c->d_reprq) {
-    // Q^p_{2k}(w) / (2k+1)! for p = 3/2, 5/2 (Q_0 = 1, Q_{n+1} = (w - n - p) Q_n - w Q_n'), the
-    // building blocks of the interval averages of the potentials' time integrals
-    std::vector<double> q(2 * kReprQ * (kReprDeg + 1), 0.0);
-    for (int pq = 0; pq < 2; ++pq) {
-      const long double pw = pq == 0 ? 1.5L : 2.5L;
+    // Q_{2k}(w) / (2k+1)! for p = 3/2 (Q_0 = 1, Q_{n+1} = (w - n - p) Q_n - w Q_n'), the building
+    // blocks of the interval averages of the potentials' time integrals (the double layer's
+    // series follows from these by S_{5/2} = S_{3/2} - S_{3/2}')
+    std::vector<double> q(kReprQ * (kReprDeg + 1), 0.0);
+    {
+      const long double pw = 1.5L;
       std::vector<long double> cur(1, 1.0L);
       long double fact = 1.0L;  // (n+1)! for n = 0
       for (int n = 0; n <= kReprDeg; ++n) {
         if (n > 0) fact *= (long double)(n + 1);
         if (n % 2 == 0)
           for (size_t jj = 0; jj < cur.size(); ++jj)
-            q[((size_t)pq * kReprQ + n / 2) * (kReprDeg + 1) + jj] = (double)(cur[jj] / fact);
+            q[(size_t)(n / 2) * (kReprDeg + 1) + jj] = (double)(cur[jj] / fact);
         std::vector<long double> nx(cur.size() + 1, 0.0L);
         for (size_t jj = 0; jj < cur.size(); ++jj) {
           nx[jj + 1] += cur[jj];
@@ -1668,11 +1709,11 @@ int hb_eval_repr(hb_ctx *c, const double *pts, int64_t P, const double *w, const
     const int lo[6] = {3, 4, 6, 8, 16, 32}, hi[6] = {4, 6, 8, 16, 32, 1 << 30};
     const int deg[6] = {20, 16, 14, 12, 10, 8};
     for (int cl = 0; cl < 6; ++cl)
-      moff += std::max(0, std::min(c->nt + 1, hi[cl]) - lo[cl]) * (3 + 2 * (deg[cl] + 1));
+      moff += std::max(0, std::min(c->nt + 1, hi[cl]) - lo[cl]) * (3 + deg[cl] + 1);
   }
   const size_t lds = std::max<size_t>(8, sizeof(double) * (size_t)moff);
   // 160 KiB of LDS per workgroup, less the kernel's static arrays (Q, the exp table, the reduction)
-  if (lds + sizeof(double) * (2 * kReprQ * (kReprDeg + 1) + 64 + 8) > 160 * 1024)
+  if (lds + sizeof(double) * (kReprQ * (kReprDeg + 1) + 64 + 8) > 160 * 1024)
     return ctx_fail(c, HB_EINVAL, "E_t too large for the potential kernel");
   hipLaunchKernelGGL(k_repr, dim3((unsigned)P), dim3(256), lds, s, c->d_params_repr, c->d_reprq,
                      pts, w, g, u, sl, dl);

@@ -124,8 +124,8 @@ def test_solvers_reach_tolerance(torch, c1, method):
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_time_marching_long(torch, storage):
-    """E_t = 70 (chunks of 8 steps, the last one partial): time marching against the oracle's LU
-    time marching on the same blocks, double and float block storage."""
+    """E_t = 70 (halved down to runs of at most 4 steps, uneven halves): time marching against
+    the oracle's LU time marching on the same blocks, double and float block storage."""
     from paper_2102_09811_amd import Context, HB_DTYPE_F32, HB_OP_V, HB_SOLVE_TIMEMARCH
     v, t = cube(2)
     nt = 70
