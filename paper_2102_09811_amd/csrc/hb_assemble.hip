@@ -130,7 +130,7 @@ struct SepTabs {
   const double *__restrict__ taylor;    // [nt][2][kTaylorN]
   const float *__restrict__ taylor32;   // [nt][2][kTaylorN32]
   const int *__restrict__ tdeg;         // [nt][2]
-  const double *etab;                   // LDS: 2^{-j/64} (exp_neg_t) or 2^{j/64} (exp_neg_m)
+  const double *etab;                   // LDS: 2^{-j/64} (exp_neg_t) or 2^{j/256} (exp_neg_m)
 };
 
 // Per-lane data of an unordered separated pair.  The wave's test panel l is uniform: its rule
@@ -245,16 +245,18 @@ struct TaylorSums {
   double V[2], K1[2][3], K2[2][3];
 };
 
-template <int N>
+template <int N, bool WCLAMP = false>
 __device__ __forceinline__ void sym_taylor2(const AsmParams &p, const SepTabs &T, int d0, int d1,
                                             int m, const SepLane &L, TaylorSums &R) {
   const int ne = p.ne;
   const double c0 = T.tscale[3 * d0 + 2], c1 = T.tscale[3 * d1 + 2];
   const double *cv0 = T.taylor + (size_t)(2 * d0) * kTaylorN;
   const double *cv1 = T.taylor + (size_t)(2 * d1) * kTaylorN;
-  // rho^2 clamped where e^{-w} of both blocks is 0 in double anyway (c1 <= c0, w0 >= 1000 gives
-  // w1 >= 750): the exponential's argument stays in the range of its rounding shift
-  const double r2max = 1000.0 / c0;
+  // rho^2 clamped where e^{-w} of both blocks is 0 in double anyway (w >= 1000 for the smaller of
+  // c0, c1): on uniform grids the other block's w stays below 1000 (d0 + 1) / d0 <= 1334 and both
+  // exponentials take their argument unclamped; on non-uniform grids (WCLAMP) the ratio of the
+  // two factors is not bounded and the exponentials clamp w themselves
+  const double r2max = 1000.0 / fmin(c0, c1);
   // the transposed order's double layer per test node a, weighted by the basis at a after the pass
   double t2[2][kFarN];
 #pragma unroll
@@ -278,7 +280,8 @@ __device__ __forceinline__ void sym_taylor2(const AsmParams &p, const SepTabs &T
       const double rn2 = -wb * fma(rx, L.nl[0], fma(ry, L.nl[1], rz * L.nl[2]));
       const double w0 = rho2 * c0, w1 = rho2 * c1;
       // e^{-w} times the test node's weight
-      const double e0 = X.w * exp_neg_m(w0, T.etab), e1 = X.w * exp_neg_m(w1, T.etab);
+      const double e0 = X.w * (WCLAMP ? exp_neg_m(w0, T.etab) : exp_neg_mu(w0, T.etab));
+      const double e1 = X.w * (WCLAMP ? exp_neg_m(w1, T.etab) : exp_neg_mu(w1, T.etab));
       double p0, dp0, p1, dp1;
       horner_d<N>(cv0, w0, p0, dp0);
       horner_d<N>(cv1, w1, p1, dp1);
@@ -391,7 +394,7 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
                                                       const uint8_t *__restrict__ tslots,
                                                       int ntasks) {
   const AsmParams &p = *pp;
-  __shared__ double etab[64];
+  __shared__ double etab[kExpTabN];
   __shared__ double lam[kFarN * 4];
   __shared__ double xs[4][kFarN * 4];
   // the test row's double-layer contributions of the current pass (two blocks) per distinct
@@ -831,7 +834,7 @@ __global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict_
                                                     const double *__restrict__ taylor,
                                                     const int *__restrict__ tdeg) {
   const AsmParams &p = *pp;
-  __shared__ double etab[64];
+  __shared__ double etab[kExpTabN];
   __shared__ __align__(16) double red[16 * kRedRow];
   stage_exp_tab_pos(etab);
   __syncthreads();
@@ -957,16 +960,16 @@ __device__ __forceinline__ void nu_closed_point(const AsmParams &p, const NuClos
 __device__ __forceinline__ void nu_sym_taylor(const AsmParams &p, const SepTabs &T, int b, int b1,
                                               int m, const SepLane &L, TaylorSums &R) {
   switch (T.tdeg[2 * b]) {
-    case 28: sym_taylor2<29>(p, T, b, b1, m, L, R); break;
-    case 24: sym_taylor2<25>(p, T, b, b1, m, L, R); break;
-    case 20: sym_taylor2<21>(p, T, b, b1, m, L, R); break;
-    case 18: sym_taylor2<19>(p, T, b, b1, m, L, R); break;
-    case 16: sym_taylor2<17>(p, T, b, b1, m, L, R); break;
-    case 14: sym_taylor2<15>(p, T, b, b1, m, L, R); break;
-    case 12: sym_taylor2<13>(p, T, b, b1, m, L, R); break;
-    case 10: sym_taylor2<11>(p, T, b, b1, m, L, R); break;
-    case 8: sym_taylor2<9>(p, T, b, b1, m, L, R); break;
-    default: sym_taylor2<7>(p, T, b, b1, m, L, R); break;
+    case 28: sym_taylor2<29, true>(p, T, b, b1, m, L, R); break;
+    case 24: sym_taylor2<25, true>(p, T, b, b1, m, L, R); break;
+    case 20: sym_taylor2<21, true>(p, T, b, b1, m, L, R); break;
+    case 18: sym_taylor2<19, true>(p, T, b, b1, m, L, R); break;
+    case 16: sym_taylor2<17, true>(p, T, b, b1, m, L, R); break;
+    case 14: sym_taylor2<15, true>(p, T, b, b1, m, L, R); break;
+    case 12: sym_taylor2<13, true>(p, T, b, b1, m, L, R); break;
+    case 10: sym_taylor2<11, true>(p, T, b, b1, m, L, R); break;
+    case 8: sym_taylor2<9, true>(p, T, b, b1, m, L, R); break;
+    default: sym_taylor2<7, true>(p, T, b, b1, m, L, R); break;
   }
 }
 
@@ -974,7 +977,7 @@ __global__ __launch_bounds__(256, 2) void k_nu_separated(const AsmParams *__rest
                                                          const int *__restrict__ tasks,
                                                          int ntasks) {
   const AsmParams &p = *pp;
-  __shared__ double etab[64];
+  __shared__ double etab[kExpTabN];
   __shared__ double lam[kFarN * 4];
   __shared__ double xs[4][kFarN * 4];
   stage_exp_tab_pos(etab);

@@ -665,7 +665,7 @@ __global__ __launch_bounds__(256, 2) void k_repr(const AsmParams *__restrict__ p
   double eps = t - k * h;
   if (eps < 0.0) eps = 0.0;
   constexpr double kPi = 3.14159265358979323846;
-  __shared__ double etab[64];
+  __shared__ double etab[kExpTabN];
   stage_exp_tab_pos(etab);
   // the series' coefficient table Q, staged once per workgroup
   constexpr int kQn = kReprQ * (kReprDeg + 1);
@@ -1713,7 +1713,7 @@ int hb_eval_repr(hb_ctx *c, const double *pts, int64_t P, const double *w, const
   }
   const size_t lds = std::max<size_t>(8, sizeof(double) * (size_t)moff);
   // 160 KiB of LDS per workgroup, less the kernel's static arrays (Q, the exp table, the reduction)
-  if (lds + sizeof(double) * (kReprQ * (kReprDeg + 1) + 64 + 8) > 160 * 1024)
+  if (lds + sizeof(double) * (kReprQ * (kReprDeg + 1) + kExpTabN + 8) > 160 * 1024)
     return ctx_fail(c, HB_EINVAL, "E_t too large for the potential kernel");
   hipLaunchKernelGGL(k_repr, dim3((unsigned)P), dim3(256), lds, s, c->d_params_repr, c->d_reprq,
                      pts, w, g, u, sl, dl);
