@@ -21,6 +21,7 @@
 #include "hb_closed.h"
 #include "hb_device.h"
 #include "hb_internal.h"
+#include "hb_sep.h"
 
 namespace hb {
 namespace {
@@ -142,29 +143,6 @@ struct SepLane {
   double nm[3], nl[3];     // unit normals of m and l
   double shift;            // inactive lanes integrate a far-away copy and store nothing
 };
-
-struct RuleNode {
-  double x, y, z, w;
-};
-__device__ __forceinline__ RuleNode rule_node(const double *q, int a) {
-  const double2 u = *(const double2 *)(q + 4 * a), v = *(const double2 *)(q + 4 * a + 2);
-  return {u.x, u.y, v.x, v.y};
-}
-
-// LDS staging of the separated kernels (before any lane leaves): the workgroup's barycentric
-// table, and each wave's test-panel nodes (lanes 0 .. 20 of the wave).
-__device__ __forceinline__ void stage_test_nodes(const AsmParams &p, const double *geom, int l,
-                                                 bool valid, double *xs_wave, double *lam) {
-  const int lane = threadIdx.x & 63;
-  if (threadIdx.x < kFarN * 4) {
-    const int a = threadIdx.x >> 2, c = threadIdx.x & 3;
-    lam[threadIdx.x] = c < 3 ? p.lam7[a][c] : p.w7[a];
-  }
-  if (valid && lane < kFarN * 4) {
-    const int a = lane >> 2, c = lane & 3;
-    xs_wave[lane] = c < 3 ? geom[(size_t)(a * 3 + c) * p.ne + l] : p.w7[a];
-  }
-}
 
 template <typename TS, int D, int I0>
 __device__ __forceinline__ void sym_pass(const AsmParams &p, const SepTabs &T, int l, int m,
@@ -372,14 +350,6 @@ __device__ __forceinline__ void sym_taylor2_32(const AsmParams &p, const SepTabs
   }
 }
 
-// LDS of the wave, ordered: earlier LDS operations of any lane are seen by later ones.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-constexpr int kSepSlots = 3 * 64;  // distinct trial vertices of one task, at most
 
 template <typename TS, int D, bool MIXED>
 __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restrict__ pp,
@@ -605,13 +575,6 @@ __device__ __forceinline__ void touch_taylor2(const AsmParams &p, const SepTabs 
 // ------------------------------------------------------------------------------------------
 constexpr int kRedRow = 66;  // LDS row of one sum's 64 partial sums (padded against bank conflicts)
 
-// v from the lane given by the DPP control CTRL within each row of sixteen lanes
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
 
 // Sum over the wave, left in every lane (bitwise equal): the rows of sixteen lanes as below, then
 // the four row sums pairwise.

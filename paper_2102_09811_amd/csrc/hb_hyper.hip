@@ -25,6 +25,7 @@
 #include "hb_closed.h"
 #include "hb_device.h"
 #include "hb_internal.h"
+#include "hb_sep.h"
 
 namespace hb {
 namespace {
@@ -61,181 +62,245 @@ __device__ __forceinline__ double v_closed(const AsmParams &p, double rho, int d
                  rA_level(p, d - 1, rho, ir));
 }
 
-// Kernel value at rho^2 for block d (N = 0: closed form; else the Taylor polynomial with N
-// coefficients, scale sc, w = rho^2 cw)
-template <int KIND, int N>
-__device__ __forceinline__ double kern_value(const AsmParams &p, double rho2, int d, double ah,
-                                             double cw, double sc, const double *__restrict__ tab,
-                                             const double *etab) {
-  if constexpr (N == 0) {
-    if constexpr (KIND == kKindD2) return d2_closed(p, sqrt(rho2), d);
-    else return v_closed(p, sqrt(rho2), d);
-  } else {
-    const double w = rho2 * cw;
-    return sc * exp_neg_t(w, etab) * horner<N>(tab, w);
-  }
-}
-
-// Per-block Taylor data of kind KIND: polynomial, its length, scale and w factor
+// Per-block Taylor data: the V_h tables (V^{11}) and the odd tables of D^{2,d}, their lengths,
+// scales and w factors
 struct P1Tabs {
   const double *tscale, *d2tab, *d2scale, *taylor;
   const int32_t *d2len, *tdeg;
 };
 
-template <int KIND>
-__device__ __forceinline__ int block_len(const AsmParams &p, const P1Tabs &T, int d) {
-  if constexpr (KIND == kKindD2) return d < kD2Closed ? 0 : T.d2len[d];
-  else return d < p.dsw ? 0 : T.tdeg[2 * d] + 1;
-}
+// ---- separated pairs ----
+// The task list of the V_h / K_h assembly: one wave per task, test panel l uniform (its rule nodes
+// in LDS), up to 64 trial panels m0, m0 + 1, ... (mod E_x), each unordered pair once.  A pair's
+// block is S[i][j] = sum_{a, b} w_a w_b lambda_a,i lambda_b,j k(x_a - y_b) (test vertex i of l,
+// trial vertex j of m): per trial node b the test-node sums u_i = sum_a w_a lambda_a,i k are
+// formed, then weighted by the trial basis.  The closed-form blocks go one per pass, the Taylor
+// blocks two per pass sharing r and rho^2.  Contributions to row vl[i] of the workspace W are
+// summed per distinct trial vertex of the task in LDS and added to W once per vertex and pass.
+struct P1Lane {
+  const double *xs;   // LDS [kFarN][4]: test nodes of l and the rule weight
+  const double *lam;  // LDS [kFarN][4]: barycentrics of the rule nodes and the weight
+  double shift;       // inactive lanes integrate a far-away copy and store nothing
+};
 
 template <int KIND>
-__device__ __forceinline__ void block_tab(const P1Tabs &T, int d, double &cw, double &sc,
-                                          const double *&tab) {
-  cw = T.tscale[3 * d + 2];
-  if constexpr (KIND == kKindD2) {
-    sc = T.d2scale[d];
-    tab = T.d2tab + (size_t)d * kTaylorND;
-  } else {
-    sc = T.tscale[3 * d];
-    tab = T.taylor + (size_t)(2 * d) * kTaylorN;
-  }
-}
-
-// One block d of a separated pair: S[a][b] = sum over the 7 x 7 point pairs of the weights, the
-// kernel and the test / trial barycentrics.
-template <int KIND, int N>
-__device__ __forceinline__ void p1_sep_block(const AsmParams &p, int l, int m, int d, double ah,
-                                             const P1Tabs &T, const double *etab, double S[3][3]) {
+__device__ __forceinline__ void p1_closed_block(const AsmParams &p, int m, int d, const P1Lane &L,
+                                                double S[3][3]) {
   const int ne = p.ne;
-  double cw = 0.0, sc = 0.0;
-  const double *tab = nullptr;
-  if constexpr (N > 0) block_tab<KIND>(T, d, cw, sc, tab);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) S[i][j] = 0.0;
 #pragma unroll 1
-  for (int a = 0; a < kFarN; ++a) {
-    const double x0 = p.geom[(a * 3 + 0) * ne + l], x1 = p.geom[(a * 3 + 1) * ne + l],
-                 x2 = p.geom[(a * 3 + 2) * ne + l];
-    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+  for (int b = 0; b < kFarN; ++b) {
+    const double y0 = p.geom[(b * 3 + 0) * ne + m] + L.shift;
+    const double y1 = p.geom[(b * 3 + 1) * ne + m];
+    const double y2 = p.geom[(b * 3 + 2) * ne + m];
+    double u[3] = {0.0, 0.0, 0.0};
 #pragma unroll 1
-    for (int b = 0; b < kFarN; ++b) {
-      const double rx = x0 - p.geom[(b * 3 + 0) * ne + m];
-      const double ry = x1 - p.geom[(b * 3 + 1) * ne + m];
-      const double rz = x2 - p.geom[(b * 3 + 2) * ne + m];
-      const double v = p.w7[b] * kern_value<KIND, N>(p, fma(rx, rx, fma(ry, ry, rz * rz)), d, ah, cw, sc, tab, etab);
-      t0 = fma(v, p.lam7[b][0], t0);
-      t1 = fma(v, p.lam7[b][1], t1);
-      t2 = fma(v, p.lam7[b][2], t2);
+    for (int a = 0; a < kFarN; ++a) {
+      const RuleNode X = rule_node(L.xs, a);
+      const double rx = X.x - y0, ry = X.y - y1, rz = X.z - y2;
+      const double rho = sqrt(fma(rx, rx, fma(ry, ry, rz * rz)));
+      const double k = X.w * (KIND == kKindD2 ? d2_closed(p, rho, d) : v_closed(p, rho, d));
+      const RuleNode La = rule_node(L.lam, a);
+      u[0] = fma(La.x, k, u[0]);
+      u[1] = fma(La.y, k, u[1]);
+      u[2] = fma(La.z, k, u[2]);
     }
+    const RuleNode Lb = rule_node(L.lam, b);
+    const double phi[3] = {Lb.w * Lb.x, Lb.w * Lb.y, Lb.w * Lb.z};
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double wa = p.w7[a] * p.lam7[a][i];
-      S[i][0] = fma(wa, t0, S[i][0]);
-      S[i][1] = fma(wa, t1, S[i][1]);
-      S[i][2] = fma(wa, t2, S[i][2]);
-    }
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) S[i][j] = fma(phi[j], u[i], S[i][j]);
   }
 }
 
-// One block of a separated / touching pair as a functor templated on the polynomial length.
+// Taylor polynomial, its scale and w factor of block d
 template <int KIND>
-struct SepBlock {
-  const AsmParams &p;
-  int l, m, d;
-  double ah;
-  const P1Tabs &T;
-  const double *etab;
-  double (&S)[3][3];
-  template <int N>
-  __device__ __forceinline__ void operator()() const {
-    p1_sep_block<KIND, N>(p, l, m, d, ah, T, etab, S);
+__device__ __forceinline__ const double *p1_poly(const P1Tabs &T, int d, double &cw, double &sc) {
+  cw = T.tscale[3 * d + 2];
+  if constexpr (KIND == kKindD2) {
+    sc = T.d2scale[d];
+    return T.d2tab + (size_t)d * kTaylorND;
+  } else {
+    sc = T.tscale[3 * d];
+    return T.taylor + (size_t)(2 * d) * kTaylorN;
   }
-};
+}
 
+// Taylor blocks d0 and d1 (d1 = d0 + 1, or d0 itself at the end) with the polynomial length N of
+// block d0 (the tables hold block d1 at that length, or zeros past its own).
 template <int KIND, int N>
-__device__ __forceinline__ void p1_touch_block(const AsmParams &p, const TouchPair &tp,
-                                               const double *__restrict__ tab, int ntab, int lane,
-                                               int d, double ah, const P1Tabs &T,
-                                               const double *etab, double S[9]);
-
-template <int KIND>
-struct TouchBlock {
-  const AsmParams &p;
-  const TouchPair &tp;
-  const double *tab;
-  int ntab, lane, d;
-  double ah;
-  const P1Tabs &T;
-  const double *etab;
-  double (&S)[9];
-  template <int N>
-  __device__ __forceinline__ void operator()() const {
-    p1_touch_block<KIND, N>(p, tp, tab, ntab, lane, d, ah, T, etab, S);
+__device__ __forceinline__ void p1_taylor2(const AsmParams &p, const P1Tabs &T, int d0, int d1,
+                                           int m, const P1Lane &L, const double *etab,
+                                           double S0[3][3], double S1[3][3]) {
+  const int ne = p.ne;
+  double cw0, sc0, cw1, sc1;
+  const double *c0 = p1_poly<KIND>(T, d0, cw0, sc0);
+  const double *c1 = p1_poly<KIND>(T, d1, cw1, sc1);
+  // rho^2 clamped where e^{-w} of both blocks is 0 anyway (w >= 1000 for the smaller factor; the
+  // larger one is at most (d0 + 1) / d0 times it)
+  const double r2max = 1000.0 / fmin(cw0, cw1);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) S0[i][j] = S1[i][j] = 0.0;
+#pragma unroll 1
+  for (int b = 0; b < kFarN; ++b) {
+    const double y0 = p.geom[(b * 3 + 0) * ne + m] + L.shift;
+    const double y1 = p.geom[(b * 3 + 1) * ne + m];
+    const double y2 = p.geom[(b * 3 + 2) * ne + m];
+    double u0[3] = {0.0, 0.0, 0.0}, u1[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < kFarN; ++a) {
+      const RuleNode X = rule_node(L.xs, a);
+      const double rx = X.x - y0, ry = X.y - y1, rz = X.z - y2;
+      const double rho2 = fmin(fma(rx, rx, fma(ry, ry, rz * rz)), r2max);
+      const double w0 = rho2 * cw0, w1 = rho2 * cw1;
+      const double k0 = X.w * exp_neg_mu(w0, etab) * horner<N>(c0, w0);
+      const double k1 = X.w * exp_neg_mu(w1, etab) * horner<N>(c1, w1);
+      const RuleNode La = rule_node(L.lam, a);
+      u0[0] = fma(La.x, k0, u0[0]);
+      u0[1] = fma(La.y, k0, u0[1]);
+      u0[2] = fma(La.z, k0, u0[2]);
+      u1[0] = fma(La.x, k1, u1[0]);
+      u1[1] = fma(La.y, k1, u1[1]);
+      u1[2] = fma(La.z, k1, u1[2]);
+    }
+    const RuleNode Lb = rule_node(L.lam, b);
+    const double phi[3] = {Lb.w * Lb.x, Lb.w * Lb.y, Lb.w * Lb.z};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        S0[i][j] = fma(phi[j], u0[i], S0[i][j]);
+        S1[i][j] = fma(phi[j], u1[i], S1[i][j]);
+      }
   }
-};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      S0[i][j] *= sc0;
+      S1[i][j] *= sc1;
+    }
+}
 
-// Dispatch of one block to the polynomial length of its table (0: closed form).
-template <int KIND, typename F>
-__device__ __forceinline__ void by_len(int len, F &&f) {
-  switch (len) {
-    case 0: f.template operator()<0>(); break;
-    case 29: if constexpr (KIND == kKindV11) f.template operator()<29>(); break;
-    case 25: if constexpr (KIND == kKindV11) f.template operator()<25>(); break;
-    case 21: if constexpr (KIND == kKindV11) f.template operator()<21>(); break;
-    case 19: if constexpr (KIND == kKindV11) f.template operator()<19>(); break;
-    case 17: if constexpr (KIND == kKindV11) f.template operator()<17>(); break;
-    case 16: if constexpr (KIND == kKindD2) f.template operator()<16>(); break;
-    case 15: if constexpr (KIND == kKindV11) f.template operator()<15>(); break;
-    case 14: if constexpr (KIND == kKindD2) f.template operator()<14>(); break;
-    case 13: if constexpr (KIND == kKindV11) f.template operator()<13>(); break;
-    case 12: if constexpr (KIND == kKindD2) f.template operator()<12>(); break;
-    case 11: if constexpr (KIND == kKindV11) f.template operator()<11>(); break;
-    case 10: if constexpr (KIND == kKindD2) f.template operator()<10>(); break;
-    case 9: if constexpr (KIND == kKindV11) f.template operator()<9>(); break;
-    case 8: if constexpr (KIND == kKindD2) f.template operator()<8>(); break;
-    default: if constexpr (KIND == kKindV11) f.template operator()<7>(); break;
+// Dispatch of a Taylor pass to the polynomial length of its first block.
+template <int KIND>
+__device__ __forceinline__ void p1_taylor_pass(const AsmParams &p, const P1Tabs &T, int d0, int d1,
+                                               int m, const P1Lane &L, const double *etab,
+                                               double S0[3][3], double S1[3][3]) {
+  if constexpr (KIND == kKindD2) {
+    switch (T.d2len[d0]) {
+      case 16: p1_taylor2<KIND, 16>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 14: p1_taylor2<KIND, 14>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 12: p1_taylor2<KIND, 12>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 10: p1_taylor2<KIND, 10>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      default: p1_taylor2<KIND, 8>(p, T, d0, d1, m, L, etab, S0, S1); break;
+    }
+  } else {
+    switch (T.tdeg[2 * d0]) {
+      case 28: p1_taylor2<KIND, 29>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 24: p1_taylor2<KIND, 25>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 20: p1_taylor2<KIND, 21>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 18: p1_taylor2<KIND, 19>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 16: p1_taylor2<KIND, 17>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 14: p1_taylor2<KIND, 15>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 12: p1_taylor2<KIND, 13>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 10: p1_taylor2<KIND, 11>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 8: p1_taylor2<KIND, 9>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      default: p1_taylor2<KIND, 7>(p, T, d0, d1, m, L, etab, S0, S1); break;
+    }
   }
 }
 
 template <int KIND, typename TS>
-__global__ __launch_bounds__(256) void k_p1_separated(const AsmParams *__restrict__ pp, P1Tabs T,
-                                                      const int32_t *__restrict__ tasks,
-                                                      int ntasks, TS *__restrict__ W) {
+__global__ __launch_bounds__(256, 2) void k_p1_separated(const AsmParams *__restrict__ pp, P1Tabs T,
+                                                         const int32_t *__restrict__ tasks,
+                                                         const int *__restrict__ tvstart,
+                                                         const int *__restrict__ tverts,
+                                                         const uint8_t *__restrict__ tslots,
+                                                         int ntasks, TS *__restrict__ W) {
   const AsmParams &p = *pp;
-  __shared__ double etab[64];
-  stage_exp_tab(etab);
+  __shared__ double etab[kExpTabN];
+  __shared__ double lam[kFarN * 4];
+  __shared__ double xs[4][kFarN * 4];
+  // the pass's contributions (up to two blocks) to rows vl[0..2] per distinct trial vertex
+  __shared__ double wacc[4][2][3][kSepSlots];
+  stage_exp_tab_pos(etab);
+  const int task = xcd_block() * 4 + (threadIdx.x >> 6);
+  const bool valid = task < ntasks;
+  const int l = valid ? __builtin_amdgcn_readfirstlane(tasks[3 * task]) : 0;
+  stage_test_nodes(p, p.geom, l, valid, xs[threadIdx.x >> 6], lam);
   __syncthreads();
-  const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (task >= ntasks) return;
-  const int l = __builtin_amdgcn_readfirstlane(tasks[3 * task]);
+  if (!valid) return;
   const int lane = threadIdx.x & 63;
-  if (lane >= __builtin_amdgcn_readfirstlane(tasks[3 * task + 2])) return;
+  // lanes past the task's count integrate a copy of its first pair and store nothing (they stay
+  // for the per-vertex flush)
+  const bool inrange = lane < __builtin_amdgcn_readfirstlane(tasks[3 * task + 2]);
   const int ne = p.ne, nv = p.nv;
-  int m = __builtin_amdgcn_readfirstlane(tasks[3 * task + 1]) + lane;
+  int m = __builtin_amdgcn_readfirstlane(tasks[3 * task + 1]) + (inrange ? lane : 0);
   if (m >= ne) m -= ne;
   const int vl[3] = {p.tris[3 * l], p.tris[3 * l + 1], p.tris[3 * l + 2]};
   const int vm[3] = {p.tris[3 * m], p.tris[3 * m + 1], p.tris[3 * m + 2]};
+  bool touch = false;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-      if (vl[i] == vm[j]) return;  // touching: handled by the regularised rules
+    for (int j = 0; j < 3; ++j) touch |= vl[i] == vm[j];  // touching: the regularised rules
+  const bool active = inrange && !touch;
+  double(*acc)[3][kSepSlots] = wacc[threadIdx.x >> 6];
+  const int sv0 = __builtin_amdgcn_readfirstlane(tvstart[task]);
+  const int nslots = __builtin_amdgcn_readfirstlane(tvstart[task + 1]) - sv0;
+  int slot[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) slot[k] = tslots[((size_t)task * 3 + k) * 64 + lane];
+  for (int e = lane; e < 2 * 3 * kSepSlots; e += 64) (&acc[0][0][0])[e] = 0.0;
+  wave_lds_sync();
   const double nn = KIND == kKindD2 ? p.geom[21 * ne + l] * p.geom[21 * ne + m] +
                                           p.geom[22 * ne + l] * p.geom[22 * ne + m] +
                                           p.geom[23 * ne + l] * p.geom[23 * ne + m]
                                     : 1.0;
   const double scale = nn * p.geom[24 * ne + l] * p.geom[24 * ne + m];
-  const double ah = p.alpha * p.h;
-  for (int d = 0; d < p.nt; ++d) {
-    double S[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-    by_len<KIND>(block_len<KIND>(p, T, d), SepBlock<KIND>{p, l, m, d, ah, T, etab, S});
-    TS *Wb = W + (size_t)d * nv * nv;
+  P1Lane L{xs[threadIdx.x >> 6], lam, active ? 0.0 : 1.0e3};
+  // blocks [d, d + nb) of this pass into LDS, then each vertex's sums to W once
+  auto emit = [&](int d, int nb, double S0[3][3], double S1[3][3]) {
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) atomicAdd(&Wb[(size_t)vl[i] * nv + vm[j]], (TS)(scale * S[i][j]));
+        for (int k = 0; k < 3; ++k) {
+          atomicAdd(&acc[0][i][slot[k]], scale * S0[i][k]);
+          if (nb > 1) atomicAdd(&acc[1][i][slot[k]], scale * S1[i][k]);
+        }
+    }
+    wave_lds_sync();
+    for (int sidx = lane; sidx < nslots; sidx += 64) {
+      const int v = tverts[sv0 + sidx];
+      for (int j = 0; j < nb; ++j)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const double a = acc[j][i][sidx];
+          if (a != 0.0) atomicAdd(&W[((size_t)(d + j) * nv + vl[i]) * nv + v], (TS)a);
+          acc[j][i][sidx] = 0.0;
+        }
+    }
+    wave_lds_sync();
+  };
+  const int nclosed = KIND == kKindD2 ? min(kD2Closed, p.nt) : min(p.dsw, p.nt);
+  for (int d = 0; d < nclosed; ++d) {
+    double S[3][3];
+    p1_closed_block<KIND>(p, m, d, L, S);
+    emit(d, 1, S, S);
+  }
+  for (int d = nclosed; d < p.nt; d += 2) {
+    double S0[3][3], S1[3][3];
+    const int d1 = min(d + 1, p.nt - 1);
+    p1_taylor_pass<KIND>(p, T, d, d1, m, L, etab, S0, S1);
+    emit(d, d1 > d ? 2 : 1, S0, S1);
   }
 }
 
@@ -258,67 +323,157 @@ __global__ __launch_bounds__(256) void k_sym_blocks(const TS *__restrict__ W, TS
   }
 }
 
-template <int KIND, int N>
-__device__ __forceinline__ void p1_touch_block(const AsmParams &p, const TouchPair &tp,
-                                               const double *__restrict__ tab, int ntab, int lane,
-                                               int d, double ah, const P1Tabs &T,
-                                               const double *etab, double S[9]) {
-  double cw = 0.0, sc = 0.0;
-  const double *poly = nullptr;
-  if constexpr (N > 0) block_tab<KIND>(T, d, cw, sc, poly);
+// ---- touching pairs ----
+// One wave per list entry: identical and edge-sharing pairs per ordered pair, vertex-sharing pairs
+// once for both orders (SYM: their rule serves the swapped pair with test and trial exchanged, so
+// the block of the order (m, l) is the transpose).  Lanes stride over the rule points; blocks go
+// one per pass in closed form, two per pass in Taylor form.  The pass's 18 sums (two blocks x 3
+// test x 3 trial vertices) leave the lanes through LDS: row i holds the 64 partial sums of sum i,
+// lanes 2 i and 2 i + 1 add its halves and lane 2 i stores it.
+constexpr int kP1Sums = 18;
+constexpr int kP1RedRow = 66;  // LDS row of one sum's partial sums (padded against bank conflicts)
+
+template <int KIND, int N>  // N = 0: block d0 in closed form (d1 unused)
+__device__ __forceinline__ void p1_touch_pass(const AsmParams &p, const P1Tabs &T,
+                                              const TouchPair &tp, const double *__restrict__ tab,
+                                              int ntab, int d0, int d1, const double *etab,
+                                              double R[kP1Sums]) {
+  double cw0 = 0.0, sc0 = 1.0, cw1 = 0.0, sc1 = 1.0, r2max = 0.0;
+  const double *c0 = nullptr, *c1 = nullptr;
+  if constexpr (N > 0) {
+    c0 = p1_poly<KIND>(T, d0, cw0, sc0);
+    c1 = p1_poly<KIND>(T, d1, cw1, sc1);
+    r2max = 1000.0 / fmin(cw0, cw1);
+  }
 #pragma unroll
-  for (int k = 0; k < 9; ++k) S[k] = 0.0;
+  for (int i = 0; i < kP1Sums; ++i) R[i] = 0.0;
 #pragma unroll 1
-  for (int q = lane; q < ntab; q += 64) {
+  for (int q = threadIdx.x; q < ntab; q += 64) {
     const double a1 = tab[q], a2 = tab[ntab + q], a3 = tab[2 * ntab + q], a4 = tab[3 * ntab + q];
     const double rx = a1 * tp.E1[0] + a2 * tp.E2[0] + a3 * tp.F1[0] + a4 * tp.F2[0];
     const double ry = a1 * tp.E1[1] + a2 * tp.E2[1] + a3 * tp.F1[1] + a4 * tp.F2[1];
     const double rz = a1 * tp.E1[2] + a2 * tp.E2[2] + a3 * tp.F1[2] + a4 * tp.F2[2];
-    const double v = tab[4 * ntab + q] *
-                     kern_value<KIND, N>(p, fma(rx, rx, fma(ry, ry, rz * rz)), d, ah, cw, sc, poly, etab);
-    const double ly0 = tab[5 * ntab + q], ly1 = tab[6 * ntab + q], ly2 = tab[7 * ntab + q];
+    const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
+    const double W = tab[4 * ntab + q];
+    const double ly[3] = {tab[5 * ntab + q], tab[6 * ntab + q], tab[7 * ntab + q]};
+    const double lx[3] = {tab[8 * ntab + q], tab[9 * ntab + q], tab[10 * ntab + q]};
+    double k0, k1 = 0.0;
+    if constexpr (N == 0) {
+      const double rho = sqrt(rho2);
+      k0 = W * (KIND == kKindD2 ? d2_closed(p, rho, d0) : v_closed(p, rho, d0));
+    } else {
+      const double r2 = fmin(rho2, r2max);
+      const double w0 = r2 * cw0, w1 = r2 * cw1;
+      k0 = W * exp_neg_mu(w0, etab) * horner<N>(c0, w0);
+      k1 = W * exp_neg_mu(w1, etab) * horner<N>(c1, w1);
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const double u = v * tab[(8 + i) * ntab + q];
-      S[3 * i + 0] = fma(u, ly0, S[3 * i + 0]);
-      S[3 * i + 1] = fma(u, ly1, S[3 * i + 1]);
-      S[3 * i + 2] = fma(u, ly2, S[3 * i + 2]);
+      const double u0 = k0 * lx[i], u1 = k1 * lx[i];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        R[3 * i + k] = fma(u0, ly[k], R[3 * i + k]);
+        if constexpr (N > 0) R[9 + 3 * i + k] = fma(u1, ly[k], R[9 + 3 * i + k]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    R[i] *= sc0;
+    R[9 + i] *= sc1;
+  }
+}
+
+// Dispatch of a pass to the polynomial length of its first block (0: closed form).
+template <int KIND>
+__device__ __forceinline__ void p1_touch_dispatch(const AsmParams &p, const P1Tabs &T,
+                                                  const TouchPair &tp, const double *tab, int ntab,
+                                                  int len, int d0, int d1, const double *etab,
+                                                  double R[kP1Sums]) {
+  if constexpr (KIND == kKindD2) {
+    switch (len) {
+      case 0: p1_touch_pass<KIND, 0>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 16: p1_touch_pass<KIND, 16>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 14: p1_touch_pass<KIND, 14>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 12: p1_touch_pass<KIND, 12>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 10: p1_touch_pass<KIND, 10>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      default: p1_touch_pass<KIND, 8>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+    }
+  } else {
+    switch (len) {
+      case 0: p1_touch_pass<KIND, 0>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 29: p1_touch_pass<KIND, 29>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 25: p1_touch_pass<KIND, 25>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 21: p1_touch_pass<KIND, 21>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 19: p1_touch_pass<KIND, 19>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 17: p1_touch_pass<KIND, 17>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 15: p1_touch_pass<KIND, 15>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 13: p1_touch_pass<KIND, 13>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 11: p1_touch_pass<KIND, 11>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 9: p1_touch_pass<KIND, 9>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      default: p1_touch_pass<KIND, 7>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
     }
   }
 }
 
-template <int KIND, typename TS>
-__global__ __launch_bounds__(64) void k_p1_touching(const AsmParams *__restrict__ pp,
-                                                    const TouchPair *__restrict__ pairs,
-                                                    RuleTabs rules, P1Tabs T, TS *__restrict__ D) {
+template <int KIND, typename TS, bool SYM>
+__global__ __launch_bounds__(64, 3) void k_p1_touching(const AsmParams *__restrict__ pp,
+                                                       const TouchPair *__restrict__ pairs,
+                                                       const int32_t *__restrict__ list,
+                                                       RuleTabs rules, P1Tabs T,
+                                                       TS *__restrict__ D) {
   const AsmParams &p = *pp;
-  __shared__ double etab[64];
-  stage_exp_tab(etab);
+  __shared__ double etab[kExpTabN];
+  __shared__ __align__(16) double red[kP1Sums * kP1RedRow];
+  stage_exp_tab_pos(etab);
   __syncthreads();
-  const TouchPair &tp = pairs[blockIdx.x];
+  const int ent = __builtin_amdgcn_readfirstlane(list[blockIdx.x]);
+  const TouchPair &tp = pairs[SYM ? ~ent : ent];
   const int cls = __builtin_amdgcn_readfirstlane(tp.cls);
   const double *__restrict__ tab = rules.d[cls];
   const int ntab = rules.n[cls];
   const int lane = threadIdx.x, nv = p.nv;
-  const double ah = p.alpha * p.h, f = tp.scale * (KIND == kKindD2 ? tp.nn : 1.0);
-  for (int d = 0; d < p.nt; ++d) {
-    double S[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    by_len<KIND>(block_len<KIND>(p, T, d), TouchBlock<KIND>{p, tp, tab, ntab, lane, d, ah, T, etab, S});
+  const double f = tp.scale * (KIND == kKindD2 ? tp.nn : 1.0);
+  // the sum this lane stores: lane 2 i, sum i = (block j, test vertex ii, trial vertex kk)
+  const int si = lane >> 1, sj = si / 9, sii = (si % 9) / 3, skk = si % 3;
+  const bool mine = (lane & 1) == 0 && si < kP1Sums;
+  const int row = mine ? tp.vtxl[sii] : 0, col = mine ? tp.vtx[skk] : 0;
+  const int nclosed = KIND == kKindD2 ? min(kD2Closed, p.nt) : min(p.dsw, p.nt);
+  for (int d = 0; d < p.nt;) {
+    const bool closed = d < nclosed;
+    const int d1 = closed ? d : min(d + 1, p.nt - 1);
+    const int nb = closed || d1 == d ? 1 : 2;
+    const int len = closed ? 0 : (KIND == kKindD2 ? T.d2len[d] : T.tdeg[2 * d] + 1);
+    double R[kP1Sums];
+    p1_touch_dispatch<KIND>(p, T, tp, tab, ntab, len, d, d1, etab, R);
 #pragma unroll
-    for (int k = 0; k < 9; ++k)
+    for (int i = 0; i < kP1Sums; ++i) red[i * kP1RedRow + lane] = R[i];
+    __syncthreads();
+    double v = 0.0;
+    if (si < kP1Sums) {
+      const double *q = red + si * kP1RedRow + 32 * (lane & 1);
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) S[k] += __shfl_xor(S[k], o, 64);
-    if (lane < 9) {
-      double v = S[0];
-#pragma unroll
-      for (int k = 1; k < 9; ++k)
-        if (lane == k) v = S[k];
-      atomicAdd(&D[((size_t)d * nv + tp.vtxl[lane / 3]) * nv + tp.vtx[lane % 3]], (TS)(f * v));
+      for (int k = 0; k < 32; k += 2) {
+        const double2 a = *(const double2 *)(q + k);
+        v += a.x + a.y;
+      }
     }
+    v += dpp_d<0xB1>(v);  // quad_perm [1, 0, 3, 2]: the two halves
+    __syncthreads();
+    if (mine && sj < nb) {
+      TS *Dd = D + (size_t)(d + sj) * nv * nv;
+      atomicAdd(&Dd[(size_t)row * nv + col], (TS)(f * v));
+      if constexpr (SYM) atomicAdd(&Dd[(size_t)col * nv + row], (TS)(f * v));
+    }
+    d += nb;
   }
 }
 
 // D[d][i][j] += alpha^2 sum_{(n, a) at i} sum_{(m, b) at j} curl_a(n) . curl_b(m) V[d][n][m]
+// One thread per j, one workgroup per (i, d): the panels at j and their curls are loaded once
+// (kD1Chunk at a time, in registers), then each panel n at i (uniform) meets them all.
+constexpr int kD1Chunk = 8;
+
 template <typename TS>
 __global__ __launch_bounds__(256) void k_d1(const TS *__restrict__ V, TS *__restrict__ D,
                                             const double *__restrict__ curl,
@@ -328,16 +483,27 @@ __global__ __launch_bounds__(256) void k_d1(const TS *__restrict__ V, TS *__rest
   const int j = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y, d = blockIdx.z;
   if (j >= nv) return;
   const TS *Vd = V + (size_t)d * ne * ne;
-  const int j0 = vstart[j], j1 = vstart[j + 1];
+  const int i0 = vstart[i], i1 = vstart[i + 1], j0 = vstart[j], j1 = vstart[j + 1];
   double acc = 0.0;
-  for (int s = vstart[i]; s < vstart[i + 1]; ++s) {
-    const int n = vadj[2 * s], a = vadj[2 * s + 1];
-    const double c0 = curl[9 * n + 3 * a], c1 = curl[9 * n + 3 * a + 1], c2 = curl[9 * n + 3 * a + 2];
-    const TS *row = Vd + (size_t)n * ne;
-    for (int t = j0; t < j1; ++t) {
-      const int m = vadj[2 * t], b = vadj[2 * t + 1];
-      const double dot = c0 * curl[9 * m + 3 * b] + c1 * curl[9 * m + 3 * b + 1] + c2 * curl[9 * m + 3 * b + 2];
-      acc = fma(dot, (double)row[m], acc);
+  for (int t0 = j0; t0 < j1; t0 += kD1Chunk) {
+    int mm[kD1Chunk];
+    double cx[kD1Chunk], cy[kD1Chunk], cz[kD1Chunk];
+#pragma unroll
+    for (int u = 0; u < kD1Chunk; ++u) {
+      const bool in = t0 + u < j1;
+      const int m = in ? vadj[2 * (t0 + u)] : 0, b = in ? vadj[2 * (t0 + u) + 1] : 0;
+      mm[u] = m;
+      cx[u] = in ? curl[9 * m + 3 * b] : 0.0;  // zero curls: the padding adds nothing
+      cy[u] = in ? curl[9 * m + 3 * b + 1] : 0.0;
+      cz[u] = in ? curl[9 * m + 3 * b + 2] : 0.0;
+    }
+    for (int s = i0; s < i1; ++s) {
+      const int n = vadj[2 * s], a = vadj[2 * s + 1];
+      const double c0 = curl[9 * n + 3 * a], c1 = curl[9 * n + 3 * a + 1], c2 = curl[9 * n + 3 * a + 2];
+      const TS *row = Vd + (size_t)n * ne;
+#pragma unroll
+      for (int u = 0; u < kD1Chunk; ++u)
+        acc = fma(fma(c0, cx[u], fma(c1, cy[u], c2 * cz[u])), (double)row[mm[u]], acc);
     }
   }
   TS *out = D + ((size_t)d * nv + i) * nv + j;
@@ -374,17 +540,24 @@ int assemble_p1p1(hb_ctx *c, TS *out, hipStream_t s) {
   if (hipMemsetAsync(W, 0, nD * sizeof(TS), s) != hipSuccess) return HB_EHIP;
   if (c->n_sep_tasks > 0)
     hipLaunchKernelGGL((k_p1_separated<KIND, TS>), dim3((unsigned)((c->n_sep_tasks + 3) / 4)),
-                       dim3(256), 0, s, c->d_params, T, c->d_sep_tasks, (int)c->n_sep_tasks, W);
+                       dim3(256), 0, s, c->d_params, T, c->d_sep_tasks, c->d_sep_vstart,
+                       c->d_sep_verts, c->d_sep_slots, (int)c->n_sep_tasks, W);
   const dim3 tiles((nv + 63) / 64, (nv + 63) / 64, nt);
   hipLaunchKernelGGL((k_sym_blocks<TS>), tiles, dim3(256), 0, s, W, out, nv);
-  if (!c->touch.empty()) {
+  if (c->n_touch_list > 0) {
     RuleTabs rt{};
     for (int k = 1; k <= 3; ++k) {
       rt.d[k] = c->ss[k].d;
       rt.n[k] = c->ss[k].n;
     }
-    hipLaunchKernelGGL((k_p1_touching<KIND, TS>), dim3((unsigned)c->touch.size()), dim3(64), 0, s,
-                       c->d_params, c->d_touch, rt, T, out);
+    // the touching list: identical and edge pairs of both orders, then the vertex pairs once
+    const int nsym = (int)c->n_touch_sym, n0 = (int)c->n_touch_list - nsym;
+    if (n0 > 0)
+      hipLaunchKernelGGL((k_p1_touching<KIND, TS, false>), dim3((unsigned)n0), dim3(64), 0, s,
+                         c->d_params, c->d_touch, c->d_touch_list, rt, T, out);
+    if (nsym > 0)
+      hipLaunchKernelGGL((k_p1_touching<KIND, TS, true>), dim3((unsigned)nsym), dim3(64), 0, s,
+                         c->d_params, c->d_touch, c->d_touch_list + n0, rt, T, out);
   }
   return hipGetLastError() == hipSuccess ? HB_OK : HB_EHIP;
 }
