@@ -598,7 +598,12 @@ int build_tables(hb_ctx *c) {
   // hypersingular operator: odd Taylor tables of D^{2,d} (d >= kD2Closed), their scales, the
   // surface curls of the local p1 basis and the vertex -> (panel, local index) lists
   {
-    auto d2deg = [](int d) { return d < 12 ? 14 : d < 16 ? 12 : d < 32 ? 10 : d < 64 ? 8 : 6; };
+    // degrees from the truncation bound (dropped terms below ~1.5e-15 of the block scale,
+    // e^{-w}-weighted over w in [0, 128]); their changes fall on even d, so the blocks of a pass
+    // (kD2Closed + 2k, kD2Closed + 2k + 1) share one length
+    auto d2deg = [](int d) {
+      return d < 6 ? 22 : d < 8 ? 18 : d < 12 ? 14 : d < 16 ? 12 : d < 32 ? 10 : d < 64 ? 8 : 6;
+    };
     std::vector<double> d2tab((size_t)c->nt * kTaylorND, 0.0), d2sc(c->nt, 0.0);
     std::vector<int32_t> d2len(c->nt, 0);
     for (int d = kD2Closed; d < c->nt; ++d) {

@@ -14,8 +14,9 @@
 //     a polynomial in w tabulated on the host; no cancelling differences remain.
 // Blocks (Sec. 3.3, Galerkin matrix D_h^2): p1 test x p1 trial with n(x) . n(y), the same rules as
 // V_h.  Separated pairs: the task list of the V_h / K_h assembly (test panel l and up to 64
-// trial panels, each unordered pair once), Radon's rule on both panels, contributions added to the workspace row block of l; then
-// D^2 = W + W^T.  Touching pairs: one wave per ordered pair, the regularised rule of its class.
+// trial panels, each unordered pair once), Radon's rule on both panels, contributions added to
+// the workspace row block of l; then D^2 = W + W^T.  Touching pairs: one wave per pair (vertex
+// pairs once for both orders), the regularised rule of its class.
 // D_h^{1,d} = T^T (alpha^2 V^d (x) I_3) T (Sec. 3.3, eq. for D_h^{1,d}) is added entry by entry
 // from V_h^d and the surface curls of the local p1 basis.
 // The same p1 x p1 kernels assemble V_h^{11}, the single layer between p1 functions (the matrix
@@ -195,6 +196,8 @@ __device__ __forceinline__ void p1_taylor_pass(const AsmParams &p, const P1Tabs 
                                                double S0[3][3], double S1[3][3]) {
   if constexpr (KIND == kKindD2) {
     switch (T.d2len[d0]) {
+      case 24: p1_taylor2<KIND, 24>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 20: p1_taylor2<KIND, 20>(p, T, d0, d1, m, L, etab, S0, S1); break;
       case 16: p1_taylor2<KIND, 16>(p, T, d0, d1, m, L, etab, S0, S1); break;
       case 14: p1_taylor2<KIND, 14>(p, T, d0, d1, m, L, etab, S0, S1); break;
       case 12: p1_taylor2<KIND, 12>(p, T, d0, d1, m, L, etab, S0, S1); break;
@@ -393,6 +396,8 @@ __device__ __forceinline__ void p1_touch_dispatch(const AsmParams &p, const P1Ta
   if constexpr (KIND == kKindD2) {
     switch (len) {
       case 0: p1_touch_pass<KIND, 0>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 24: p1_touch_pass<KIND, 24>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 20: p1_touch_pass<KIND, 20>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
       case 16: p1_touch_pass<KIND, 16>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
       case 14: p1_touch_pass<KIND, 14>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
       case 12: p1_touch_pass<KIND, 12>(p, T, tp, tab, ntab, d0, d1, etab, R); break;

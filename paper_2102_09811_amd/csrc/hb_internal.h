@@ -136,8 +136,8 @@ void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const Tou
 
 // Hypersingular operator (Sec. 3.3): D_h^d = D_h^{1,d} + D_h^{2,d} into c->d_D (needs V_h);
 // Taylor form of D^{2,d} from block kD2Closed on, closed form below.
-constexpr int kD2Closed = 8;
-constexpr int kTaylorND = 16;        // coefficients of the odd Taylor polynomial of D^{2,d}, d >= 8
+constexpr int kD2Closed = 4;
+constexpr int kTaylorND = 24;        // coefficients of the odd Taylor polynomial of D^{2,d}, d >= 4
 int launch_assemble_d(hb_ctx *c, hipStream_t s);
 // V_h^{11}: the single layer between p1 test and trial functions (the paper's preconditioner
 // matrix for D_h, Sec. 6.1) into c->d_V11, same rules and temporal forms as V_h

@@ -3,7 +3,8 @@
 * D_h blocks (p1 x p1, N_x x N_x): the oracle's D^1 = T^T (alpha^2 V^d (x) I_3) T formed from
   the oracle's V_h blocks plus the oracle's D^2 blocks (closed form in long double), per-block
   max-norm error relative to the block maximum <= 1e-12; meshes and E_t chosen so that the
-  closed-form blocks (d < 8) and every Taylor degree class (d < 12, 16, 32, 64, beyond) occur,
+  closed-form blocks (d < 4) and every Taylor degree class (d < 6, 8, 12, 16, 32, 64, beyond)
+  occur,
   with ragged sizes against the 64-wide tiles;
 * V_h^{11} blocks against the oracle's, up to E_t = 70 (the last Taylor class);
 * K_h^T and D_h block-Toeplitz products, the Neumann right-hand side and the Neumann solve against
