@@ -269,7 +269,7 @@ int hb_solve_neumann(hb_ctx *ctx, const double *b, double *u, const hb_solve_opt
  * the caller's concern).  w: E_t x E_x Neumann coefficients, g: E_t x N_x Dirichlet
  * coefficients, u: P outputs.  All device pointers, float64.  The spatial rule is the 7-point
  * rule of hb_assemble.  sl / dl may be NULL; otherwise they receive V~ w and W g.  Each point's
- * interval coefficients live in one workgroup's LDS, which bounds E_t at about 900 (HB_EINVAL
+ * interval coefficients live in one workgroup's LDS, which bounds E_t at about 1650 (HB_EINVAL
  * beyond). */
 int hb_eval_repr(hb_ctx *ctx, const double *pts, int64_t P, const double *w, const double *g,
                  double *u, double *sl, double *dl, void *stream);

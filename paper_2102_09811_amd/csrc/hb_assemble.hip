@@ -606,23 +606,24 @@ struct TouchPt {
 
 template <bool SYM>
 __device__ __forceinline__ TouchPt<SYM> touch_pt(const TouchPair &tp, const double nl[3],
-                                                 const double *__restrict__ tab, int ntab, int q) {
-  const double a1 = tab[q], a2 = tab[ntab + q], a3 = tab[2 * ntab + q], a4 = tab[3 * ntab + q];
+                                                 const RuleCols &col, unsigned q) {
+  const unsigned off = 8u * q;
+  const double a1 = col.at(0, off), a2 = col.at(1, off), a3 = col.at(2, off), a4 = col.at(3, off);
   const double rx = a1 * tp.E1[0] + a2 * tp.E2[0] + a3 * tp.F1[0] + a4 * tp.F2[0];
   const double ry = a1 * tp.E1[1] + a2 * tp.E2[1] + a3 * tp.F1[1] + a4 * tp.F2[1];
   const double rz = a1 * tp.E1[2] + a2 * tp.E2[2] + a3 * tp.F1[2] + a4 * tp.F2[2];
   TouchPt<SYM> t;
   t.rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
-  t.W = tab[4 * ntab + q];
+  t.W = col.at(4, off);
   t.wrn1 = t.W * fma(rx, tp.n[0], fma(ry, tp.n[1], rz * tp.n[2]));
-  t.l[0] = tab[5 * ntab + q];
-  t.l[1] = tab[6 * ntab + q];
-  t.l[2] = tab[7 * ntab + q];
+  t.l[0] = col.at(5, off);
+  t.l[1] = col.at(6, off);
+  t.l[2] = col.at(7, off);
   if constexpr (SYM) {
     t.wrn2 = -t.W * fma(rx, nl[0], fma(ry, nl[1], rz * nl[2]));
-    t.lx[0] = tab[8 * ntab + q];
-    t.lx[1] = tab[9 * ntab + q];
-    t.lx[2] = tab[10 * ntab + q];
+    t.lx[0] = col.at(8, off);
+    t.lx[1] = col.at(9, off);
+    t.lx[2] = col.at(10, off);
   } else {
     t.wrn2 = 0.0;
     t.lx[0] = t.lx[1] = t.lx[2] = 0.0;
@@ -633,7 +634,7 @@ __device__ __forceinline__ TouchPt<SYM> touch_pt(const TouchPair &tp, const doub
 // Per-pair data of a wave (uniform); gl: the lane.
 struct TouchGroup {
   const TouchPair *tp;
-  const double *tab;
+  RuleCols col;
   int ntab, gl, l, m;
   int vtx[3], vtxl[3];
   double nl[3], scale;
@@ -652,7 +653,7 @@ __device__ __forceinline__ void touch_closed(const AsmParams &p, const TouchGrou
   if constexpr (I0 <= D) {
 #pragma unroll 1
     for (int q = threadIdx.x; q < G.ntab; q += 64) {
-      const TouchPt<SYM> t = touch_pt<SYM>(*G.tp, G.nl, G.tab, G.ntab, q);
+      const TouchPt<SYM> t = touch_pt<SYM>(*G.tp, G.nl, G.col, q);
       const double rho = sqrt(t.rho2), inv_rho = 1.0 / rho;
       if constexpr (I0 == 0) {
         sV = fma(t.W, inv_rho, sV);
@@ -762,7 +763,7 @@ __device__ __forceinline__ void touch_taylor(const SepTabs &T, const TouchGroup 
   const double *cv1 = T.taylor + (size_t)(2 * d1) * kTaylorN;
 #pragma unroll 1
   for (int q = G.gl; q < G.ntab; q += 64) {
-    const TouchPt<SYM> t = touch_pt<SYM>(*G.tp, G.nl, G.tab, G.ntab, q);
+    const TouchPt<SYM> t = touch_pt<SYM>(*G.tp, G.nl, G.col, q);
     const double w0 = t.rho2 * c0, w1 = t.rho2 * c1;
     const double e0 = exp_neg_m(w0, T.etab), e1 = exp_neg_m(w1, T.etab);
     double p0, dp0, p1, dp1;
@@ -807,8 +808,8 @@ __global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict_
   const TouchPair &tp = pairs[SYM ? ~ent : ent];
   G.tp = &tp;
   const int cls = tp.cls;
-  G.tab = rules.d[cls];
   G.ntab = rules.n[cls];
+  G.col = RuleCols(rules.d[cls], G.ntab);
   G.gl = threadIdx.x;
   G.l = tp.l;
   G.m = tp.m;

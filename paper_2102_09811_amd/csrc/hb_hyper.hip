@@ -338,8 +338,8 @@ constexpr int kP1RedRow = 66;  // LDS row of one sum's partial sums (padded agai
 
 template <int KIND, int N>  // N = 0: block d0 in closed form (d1 unused)
 __device__ __forceinline__ void p1_touch_pass(const AsmParams &p, const P1Tabs &T,
-                                              const TouchPair &tp, const double *__restrict__ tab,
-                                              int ntab, int d0, int d1, const double *etab,
+                                              const TouchPair &tp, const RuleCols &col, int ntab,
+                                              int d0, int d1, const double *etab,
                                               double R[kP1Sums]) {
   double cw0 = 0.0, sc0 = 1.0, cw1 = 0.0, sc1 = 1.0, r2max = 0.0;
   const double *c0 = nullptr, *c1 = nullptr;
@@ -352,14 +352,15 @@ __device__ __forceinline__ void p1_touch_pass(const AsmParams &p, const P1Tabs &
   for (int i = 0; i < kP1Sums; ++i) R[i] = 0.0;
 #pragma unroll 1
   for (int q = threadIdx.x; q < ntab; q += 64) {
-    const double a1 = tab[q], a2 = tab[ntab + q], a3 = tab[2 * ntab + q], a4 = tab[3 * ntab + q];
+    const unsigned off = 8u * q;
+    const double a1 = col.at(0, off), a2 = col.at(1, off), a3 = col.at(2, off), a4 = col.at(3, off);
     const double rx = a1 * tp.E1[0] + a2 * tp.E2[0] + a3 * tp.F1[0] + a4 * tp.F2[0];
     const double ry = a1 * tp.E1[1] + a2 * tp.E2[1] + a3 * tp.F1[1] + a4 * tp.F2[1];
     const double rz = a1 * tp.E1[2] + a2 * tp.E2[2] + a3 * tp.F1[2] + a4 * tp.F2[2];
     const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
-    const double W = tab[4 * ntab + q];
-    const double ly[3] = {tab[5 * ntab + q], tab[6 * ntab + q], tab[7 * ntab + q]};
-    const double lx[3] = {tab[8 * ntab + q], tab[9 * ntab + q], tab[10 * ntab + q]};
+    const double W = col.at(4, off);
+    const double ly[3] = {col.at(5, off), col.at(6, off), col.at(7, off)};
+    const double lx[3] = {col.at(8, off), col.at(9, off), col.at(10, off)};
     double k0, k1 = 0.0;
     if constexpr (N == 0) {
       const double rho = sqrt(rho2);
@@ -390,33 +391,33 @@ __device__ __forceinline__ void p1_touch_pass(const AsmParams &p, const P1Tabs &
 // Dispatch of a pass to the polynomial length of its first block (0: closed form).
 template <int KIND>
 __device__ __forceinline__ void p1_touch_dispatch(const AsmParams &p, const P1Tabs &T,
-                                                  const TouchPair &tp, const double *tab, int ntab,
-                                                  int len, int d0, int d1, const double *etab,
-                                                  double R[kP1Sums]) {
+                                                  const TouchPair &tp, const RuleCols &col,
+                                                  int ntab, int len, int d0, int d1,
+                                                  const double *etab, double R[kP1Sums]) {
   if constexpr (KIND == kKindD2) {
     switch (len) {
-      case 0: p1_touch_pass<KIND, 0>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 24: p1_touch_pass<KIND, 24>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 20: p1_touch_pass<KIND, 20>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 16: p1_touch_pass<KIND, 16>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 14: p1_touch_pass<KIND, 14>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 12: p1_touch_pass<KIND, 12>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 10: p1_touch_pass<KIND, 10>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      default: p1_touch_pass<KIND, 8>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 0: p1_touch_pass<KIND, 0>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 24: p1_touch_pass<KIND, 24>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 20: p1_touch_pass<KIND, 20>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 16: p1_touch_pass<KIND, 16>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 14: p1_touch_pass<KIND, 14>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 12: p1_touch_pass<KIND, 12>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 10: p1_touch_pass<KIND, 10>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      default: p1_touch_pass<KIND, 8>(p, T, tp, col, ntab, d0, d1, etab, R); break;
     }
   } else {
     switch (len) {
-      case 0: p1_touch_pass<KIND, 0>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 29: p1_touch_pass<KIND, 29>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 25: p1_touch_pass<KIND, 25>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 21: p1_touch_pass<KIND, 21>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 19: p1_touch_pass<KIND, 19>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 17: p1_touch_pass<KIND, 17>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 15: p1_touch_pass<KIND, 15>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 13: p1_touch_pass<KIND, 13>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 11: p1_touch_pass<KIND, 11>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      case 9: p1_touch_pass<KIND, 9>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
-      default: p1_touch_pass<KIND, 7>(p, T, tp, tab, ntab, d0, d1, etab, R); break;
+      case 0: p1_touch_pass<KIND, 0>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 29: p1_touch_pass<KIND, 29>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 25: p1_touch_pass<KIND, 25>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 21: p1_touch_pass<KIND, 21>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 19: p1_touch_pass<KIND, 19>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 17: p1_touch_pass<KIND, 17>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 15: p1_touch_pass<KIND, 15>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 13: p1_touch_pass<KIND, 13>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 11: p1_touch_pass<KIND, 11>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 9: p1_touch_pass<KIND, 9>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      default: p1_touch_pass<KIND, 7>(p, T, tp, col, ntab, d0, d1, etab, R); break;
     }
   }
 }
@@ -435,14 +436,14 @@ __global__ __launch_bounds__(64, 3) void k_p1_touching(const AsmParams *__restri
   const int ent = __builtin_amdgcn_readfirstlane(list[blockIdx.x]);
   const TouchPair &tp = pairs[SYM ? ~ent : ent];
   const int cls = __builtin_amdgcn_readfirstlane(tp.cls);
-  const double *__restrict__ tab = rules.d[cls];
   const int ntab = rules.n[cls];
+  const RuleCols col(rules.d[cls], ntab);
   const int lane = threadIdx.x, nv = p.nv;
   const double f = tp.scale * (KIND == kKindD2 ? tp.nn : 1.0);
   // the sum this lane stores: lane 2 i, sum i = (block j, test vertex ii, trial vertex kk)
   const int si = lane >> 1, sj = si / 9, sii = (si % 9) / 3, skk = si % 3;
   const bool mine = (lane & 1) == 0 && si < kP1Sums;
-  const int row = mine ? tp.vtxl[sii] : 0, col = mine ? tp.vtx[skk] : 0;
+  const int drow = mine ? tp.vtxl[sii] : 0, dcol = mine ? tp.vtx[skk] : 0;
   const int nclosed = KIND == kKindD2 ? min(kD2Closed, p.nt) : min(p.dsw, p.nt);
   for (int d = 0; d < p.nt;) {
     const bool closed = d < nclosed;
@@ -450,7 +451,7 @@ __global__ __launch_bounds__(64, 3) void k_p1_touching(const AsmParams *__restri
     const int nb = closed || d1 == d ? 1 : 2;
     const int len = closed ? 0 : (KIND == kKindD2 ? T.d2len[d] : T.tdeg[2 * d] + 1);
     double R[kP1Sums];
-    p1_touch_dispatch<KIND>(p, T, tp, tab, ntab, len, d, d1, etab, R);
+    p1_touch_dispatch<KIND>(p, T, tp, col, ntab, len, d, d1, etab, R);
 #pragma unroll
     for (int i = 0; i < kP1Sums; ++i) red[i * kP1RedRow + lane] = R[i];
     __syncthreads();
@@ -467,8 +468,8 @@ __global__ __launch_bounds__(64, 3) void k_p1_touching(const AsmParams *__restri
     __syncthreads();
     if (mine && sj < nb) {
       TS *Dd = D + (size_t)(d + sj) * nv * nv;
-      atomicAdd(&Dd[(size_t)row * nv + col], (TS)(f * v));
-      if constexpr (SYM) atomicAdd(&Dd[(size_t)col * nv + row], (TS)(f * v));
+      atomicAdd(&Dd[(size_t)drow * nv + dcol], (TS)(f * v));
+      if constexpr (SYM) atomicAdd(&Dd[(size_t)dcol * nv + drow], (TS)(f * v));
     }
     d += nb;
   }

@@ -38,6 +38,21 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 constexpr int kSepSlots = 3 * 64;  // distinct trial vertices of one task, at most
 
+// The 11 columns of a regularised rule table (SoA [11][n]) as uniform base pointers: a lane reads
+// entry q of column k at base k + 8 q bytes, one 32-bit offset for all columns, so the loads need
+// no per-column address arithmetic.
+struct RuleCols {
+  const char *c[11];
+  RuleCols() = default;
+  __device__ RuleCols(const double *tab, int n) {
+#pragma unroll
+    for (int k = 0; k < 11; ++k) c[k] = (const char *)(tab + (size_t)k * n);
+  }
+  __device__ __forceinline__ double at(int k, unsigned off) const {
+    return *(const double *)(c[k] + off);
+  }
+};
+
 // v from the lane given by the DPP control CTRL within each row of sixteen lanes
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {

@@ -91,7 +91,8 @@ def test_solve_fallback_and_residual_contract(torch):
 
 def test_time_limits(torch):
     """E_t = 300: assembly works; the Toeplitz product (and so every solver) refuses E_t > 256;
-    potentials still work.  E_t = 1000: the potentials refuse (LDS table)."""
+    potentials still work.  E_t = 2000: the potentials refuse (their per-interval table, 12
+    doubles per interval, no longer fits in one workgroup's LDS)."""
     from paper_2102_09811_amd import HB_EINVAL, HB_OP_V, Context, HBError
     v, t = tetrahedron()
     ctx = Context(v, t, 1.0, 1.0, 300)
@@ -110,9 +111,9 @@ def test_time_limits(torch):
     empty = torch.zeros((0, 4), dtype=torch.float64, device="cuda")
     assert ctx.eval_repr(empty, x, g).numel() == 0
     ctx.close()
-    ctx = Context(v, t, 1.0, 1.0, 1000)
-    x = torch.zeros((1000, len(t)), dtype=torch.float64, device="cuda")
-    g = torch.zeros((1000, len(v)), dtype=torch.float64, device="cuda")
+    ctx = Context(v, t, 1.0, 1.0, 2000)
+    x = torch.zeros((2000, len(t)), dtype=torch.float64, device="cuda")
+    g = torch.zeros((2000, len(v)), dtype=torch.float64, device="cuda")
     with pytest.raises(HBError) as e:
         ctx.eval_repr(pts, x, g)
     assert e.value.code == HB_EINVAL
