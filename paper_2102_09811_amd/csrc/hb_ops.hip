@@ -199,7 +199,11 @@ __global__ void k_fill(double *__restrict__ y, size_t n, double v) {
 }
 
 // y_{row} = sum_c A[row][c] x[c], one wave per row; batched over nd matrices A + d * stride
-// writing out[(k_out0 + d) * R + row] = beta * out + alpha * y.
+// writing out[(k_out0 + d) * R + row] = beta * out + alpha * y.  A lane reads kGemvBatch columns
+// 64 apart per round, all loads issued before the products, so a row of up to 64 kGemvBatch
+// columns costs one memory latency rather than one per group of columns.
+constexpr int kGemvBatch = 20;
+
 template <typename TA>
 __global__ __launch_bounds__(256) void k_gemv_rows(const TA *__restrict__ A, size_t stride,
                                                    const double *__restrict__ x, double *out,
@@ -210,24 +214,25 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const TA *__restrict__ A, siz
   const int d = blockIdx.y;
   if (row >= R) return;
   const TA *a = A + (size_t)d * stride + (size_t)row * C;
-  // four independent partial sums, so that four loads per lane are in flight
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int c = lane;
-  for (; c + 192 < C; c += 256) {
-    const double a0 = (double)a[c], a1 = (double)a[c + 64], a2 = (double)a[c + 128],
-                 a3 = (double)a[c + 192];
-    s0 = fma(a0, x[c], s0);
-    s1 = fma(a1, x[c + 64], s1);
-    s2 = fma(a2, x[c + 128], s2);
-    s3 = fma(a3, x[c + 192], s3);
-  }
-  for (; c < C; c += 64) s0 = fma((double)a[c], x[c], s0);
-  double s = (s0 + s1) + (s2 + s3);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < C; c0 += 64 * kGemvBatch) {
+    TA av[kGemvBatch];
+    double xv[kGemvBatch];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    for (int u = 0; u < kGemvBatch; ++u) {
+      const int c = c0 + lane + 64 * u;
+      av[u] = c < C ? a[c] : TA(0);
+      xv[u] = c < C ? x[c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kGemvBatch; ++u) s[u & 3] = fma((double)av[u], xv[u], s[u & 3]);
+  }
+  double t = (s[0] + s[1]) + (s[2] + s[3]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
   if (lane == 0) {
     double *o = out + (size_t)d * out_stride + row;
-    *o = beta * (*o) + alpha * s;
+    *o = beta == 0.0 ? alpha * t : beta * (*o) + alpha * t;  // beta = 0: out is not read
   }
 }
 
