@@ -24,7 +24,8 @@ constexpr int kFarN = 7;             // Radon 7-point rule
 constexpr int kReprDeg = 20;         // largest degree of the potentials' Taylor polynomials
 constexpr int kReprQ = kReprDeg / 2 + 1;
 // Zeroed bytes behind every block array read by the Toeplitz product (V, K and the float copy of
-// V): its fragment loads may run up to 31 entries past the last row of the last block.
+// V): its fragment loads may run up to one column chunk less one entry past the last row of the
+// last block (checked where the chunk width is defined).
 constexpr size_t kBlockPad = 256;
 
 // Per-level constants of the closed form at delta_i = i h (i = 0 .. d_switch).

@@ -44,6 +44,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int TR = 64;   // rows per workgroup
 constexpr int kTC = 32;  // columns per chunk
 constexpr int kXS = kTC + 1;
+constexpr int kFE = kTC / 4;  // fragment entries per lane (consecutive columns of one row)
+static_assert(kBlockPad >= (kTC - 1) * sizeof(double), "fragment loads past the last row");
 
 template <typename TA> struct Mfma;
 template <> struct Mfma<double> {
@@ -65,26 +67,26 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int lk, int i) { return 4 * lk + i; }
 };
 
-// This lane's 8 consecutive entries of a block row.  No bounds test: rows past the block are
+// This lane's kFE consecutive entries of a block row.  No bounds test: rows past the block are
 // clamped by the caller (their outputs are never stored), entries past the row end belong to the
 // next row or to the zeroed tail of the storage (hb_internal.h: kBlockPad) and meet zeros of the
-// staged X, so every fragment is two (float) or four (double) plain 16-byte loads.
+// staged X, so every fragment is kFE / 4 (float) or kFE / 2 (double) plain 16-byte loads.
 template <typename TA>
-__device__ __forceinline__ void load_frag(TA (&a)[8], const TA *__restrict__ p) {
-  __builtin_memcpy(a, p, 8 * sizeof(TA));
+__device__ __forceinline__ void load_frag(TA (&a)[kFE], const TA *__restrict__ p) {
+  __builtin_memcpy(a, p, kFE * sizeof(TA));
 }
 
 // MFMA steps of block d with fragment a for the time chunks NS..NTC-1 (sources outside the
 // requested time window are staged as zeros, so no chunk needs a runtime skip: a data-dependent
 // branch here costs the accumulators their registers).
 template <typename TA, int NTC, int NS>
-__device__ __forceinline__ void toeplitz_block(typename Mfma<TA>::acc_t (&acc)[NTC], const TA (&a)[8],
+__device__ __forceinline__ void toeplitz_block(typename Mfma<TA>::acc_t (&acc)[NTC], const TA (&a)[kFE],
                                                const TA *Xs, int d, int lm, int lk) {
 #pragma unroll
   for (int n = NS; n < NTC; ++n) {
-    const TA *xb = Xs + (16 + 16 * n + lm - d) * kXS + 8 * lk;
+    const TA *xb = Xs + (16 + 16 * n + lm - d) * kXS + kFE * lk;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) acc[n] = Mfma<TA>::mma(a[s], xb[s], acc[n]);
+    for (int s = 0; s < kFE; ++s) acc[n] = Mfma<TA>::mma(a[s], xb[s], acc[n]);
   }
 }
 
@@ -95,26 +97,26 @@ __device__ __forceinline__ void toeplitz_block(typename Mfma<TA>::acc_t (&acc)[N
 template <typename TA, int NTC, int NS>
 struct ToeplitzRange {
   typedef typename Mfma<TA>::acc_t acc_t;
-  static __device__ __forceinline__ void run(acc_t (&acc)[NTC], TA (&a)[8], const TA *Xs,
+  static __device__ __forceinline__ void run(acc_t (&acc)[NTC], TA (&a)[kFE], const TA *Xs,
                                              const TA *arow, size_t blk, int d0, int d1, int ds,
                                              int lm, int lk) {
     if constexpr (NS < NTC) {
       const int lo = max(d0, 16 * NS), dhi = min(d1, 16 * NS + 16);
       int d = d0 + (lo - d0 + ds - 1) / ds * ds;
       for (; d + ds < dhi; d += 2 * ds) {
-        TA b[8];
+        TA b[kFE];
         load_frag(b, arow + (size_t)(d + ds) * blk);
         toeplitz_block<TA, NTC, NS>(acc, a, Xs, d, lm, lk);
         if (d + 2 * ds < d1) load_frag(a, arow + (size_t)(d + 2 * ds) * blk);
         toeplitz_block<TA, NTC, NS>(acc, b, Xs, d + ds, lm, lk);
       }
       if (d < dhi) {
-        TA b[8];
+        TA b[kFE];
         if (d + ds < d1) load_frag(b, arow + (size_t)(d + ds) * blk);
         toeplitz_block<TA, NTC, NS>(acc, a, Xs, d, lm, lk);
         if (d + ds < d1) {
 #pragma unroll
-          for (int s = 0; s < 8; ++s) a[s] = b[s];
+          for (int s = 0; s < kFE; ++s) a[s] = b[s];
         }
       }
       ToeplitzRange<TA, NTC, NS + 1>::run(acc, a, Xs, arow, blk, d0, d1, ds, lm, lk);
@@ -149,8 +151,8 @@ __global__ __launch_bounds__(256) void k_toeplitz(const TA *__restrict__ A,
       Xs[row * kXS + col] = (j >= jlo && j < jhi && c < C) ? (TA)X[(size_t)j * C + c] : TA(0);
     }
     __syncthreads();
-    const TA *arow = A + (size_t)min(r, R - 1) * C + c0 + 8 * lk;
-    TA a[8];
+    const TA *arow = A + (size_t)min(r, R - 1) * C + c0 + kFE * lk;
+    TA a[kFE];
     load_frag(a, arow + (size_t)d0 * blk);
     ToeplitzRange<TA, NTC, 0>::run(acc, a, Xs, arow, blk, d0, d1, ds, lm, lk);
   }
