@@ -40,9 +40,9 @@ PEAK_FP64_VALU = 78.6e12  # MI355X FP64 vector FLOP/s
 # instruction counts (wave instructions; 64 lanes each, an FMA is 2 FLOP).  Valid only for the
 # assembly sources they were taken on (sha256 prefix of COUNTER_SOURCES below); reported as null
 # otherwise.
-COUNTERS = {"source_sha256": "927d2df16b706d9b",
-            "fetch_kib": 10272.125 + 460173.375, "fetch_scale": 262144.0 / 131088.0625,
-            "write_kib": 2949150.8125 + 424960.0, "write_scale": 262144.0 / 262144.0,
+COUNTERS = {"source_sha256": "802ce66a537337a6",
+            "fetch_kib": 10477.375 + 460173.5, "fetch_scale": 262144.0 / 131088.0,
+            "write_kib": 2948809.5 + 424960.0, "write_scale": 262144.0 / 262144.0,
             "fma_f64": 1.46995711e9, "mul_f64": 2.7930831e8, "add_f64": 1.449856e8}
 COUNTER_SOURCES = ("hb_assemble.hip", "hb_sep.h", "hb_device.h", "hb_closed.h", "hb_internal.h")
 
