@@ -288,6 +288,41 @@ def nearfield_timings(ctx, stream, radius=0.35):
     return {"radius": radius, "pairs": int(len(cols)), "ms": ms, "pair_blocks_per_s": units / (ms * 1e-3)}
 
 
+def nonuniform_timings(verts, tris, alpha, n_t, stream, gamma=1.5):
+    """Non-uniform time grid (outside the timed step): the same mesh on the graded nodes
+    t_j = (j / E_t)^gamma, assembly of all E_t (E_t + 1) / 2 blocks V^{k,i}, K^{k,i}, the
+    block-triangular product and GMRES to 1e-8 on a smooth right-hand side."""
+    import numpy as np
+    import torch
+    from paper_2102_09811_amd import HB_OP_K, HB_OP_V, NonuniformContext
+    tn = (np.arange(n_t + 1) / n_t) ** gamma
+    ctx = NonuniformContext(verts, tris, alpha, tn)
+    ctx.assemble(HB_OP_V | HB_OP_K)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.assemble(HB_OP_V | HB_OP_K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    units = float(len(tris)) ** 2 * n_t * (n_t + 1) / 2
+    x = torch.from_numpy(np.random.default_rng(7).standard_normal((n_t, len(tris)))).cuda()
+    ctx.apply(HB_OP_V, x)
+    e0.record(stream)
+    y = ctx.apply(HB_OP_V, x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    apply_ms = e0.elapsed_time(e1)
+    w, info = ctx.solve(y, tol=1e-8)
+    ctx.close()
+    log("non-uniform grid (t_j = (j/%d)^%g): assembly %.2f ms (%.3g pair-block integrals/s), "
+        "product %.3f ms, GMRES %d it %.2f ms" % (n_t, gamma, ms, units / (ms * 1e-3), apply_ms,
+                                                  info["iterations"], info["seconds"] * 1e3))
+    return {"grid": "t_j = (j / %d)^%g" % (n_t, gamma), "blocks": n_t * (n_t + 1) // 2,
+            "assemble_ms": ms, "units_per_s": units / (ms * 1e-3), "apply_V_ms": apply_ms,
+            "gmres": {"ms": info["seconds"] * 1e3, "iterations": info["iterations"],
+                      "rel_residual": info["rel_residual"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -444,6 +479,7 @@ def main():
         del mixed
         out["neumann"] = neumann_timings(ctx, stream)
         out["nearfield"] = nearfield_timings(ctx, stream)
+        out["nonuniform"] = nonuniform_timings(verts, tris, alpha, n_t, stream)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(verts, tris, alpha, T, n_t)

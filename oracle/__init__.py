@@ -14,8 +14,9 @@ It shares no code with ``paper_2102_09811_amd`` and does not import it.
   GMRES, L2 / l2 errors.
 """
 from .core import (lib, build, temporal, blockfun, triangle_rule, ss_rule, gauss_legendre01,
-                   pair_points, assemble, assemble_plain, assemble_nonuniform, nu_blockfun, assemble_d2, assemble_v11, pair_blocks, repr_eval)
+                   pair_points, assemble, assemble_plain, assemble_nonuniform, nu_blockfun, assemble_d2, assemble_v11, pair_blocks, repr_eval,
+                   repr_eval_nonuniform)
 from . import downstream
 
 __all__ = ["lib", "build", "temporal", "blockfun", "triangle_rule", "ss_rule",
-           "gauss_legendre01", "pair_points", "assemble", "assemble_plain", "assemble_nonuniform", "nu_blockfun", "assemble_d2", "assemble_v11", "pair_blocks", "repr_eval", "downstream"]
+           "gauss_legendre01", "pair_points", "assemble", "assemble_plain", "assemble_nonuniform", "nu_blockfun", "assemble_d2", "assemble_v11", "pair_blocks", "repr_eval", "repr_eval_nonuniform", "downstream"]

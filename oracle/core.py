@@ -51,6 +51,8 @@ def lib():
         L.or_nu_blockfun.restype = None
         L.or_repr.argtypes = [_dp, i32, _ip, i32, f64, f64, i32, _dp, _dp, _dp, i32, i32, i32,
                               _dp, _dp]
+        L.or_repr_nonuniform.argtypes = [_dp, i32, _ip, i32, f64, _dp, i32, _dp, _dp, _dp, i32,
+                                         i32, i32, _dp, _dp]
         _lib = L
     return _lib
 
@@ -196,6 +198,21 @@ def repr_eval(verts, tris, alpha, T, n_t, w, u, pts, rule_kind=0, rule_order=7):
                        rule_order, sl, dl)
     if rc != 0:
         raise ValueError("or_repr failed")
+    return sl, dl
+
+
+def repr_eval_nonuniform(verts, tris, alpha, t_nodes, w, u, pts, rule_kind=0, rule_order=7):
+    """V~w and Wu at space-time points (P, 4) on the non-uniform grid t_nodes (0 = t_0 < ... <
+    t_nt); w (nt, E_x) and u (nt, N_x) hold one row per interval [t_i, t_{i+1}]."""
+    verts, tris, tn = _f64(verts), _i32(tris), _f64(t_nodes)
+    w, u, pts = _f64(w), _f64(u), _f64(pts)
+    P = len(pts)
+    sl, dl = np.empty(P), np.empty(P)
+    rc = lib().or_repr_nonuniform(verts.ravel(), len(verts), tris.ravel(), len(tris), float(alpha),
+                                  tn, len(tn) - 1, w.ravel(), u.ravel(), pts.ravel(), P, rule_kind,
+                                  rule_order, sl, dl)
+    if rc != 0:
+        raise ValueError("or_repr_nonuniform failed")
     return sl, dl
 
 

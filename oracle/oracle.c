@@ -1099,6 +1099,64 @@ int or_repr(const double *verts, int nv, const int32_t *tris, int ne, double alp
   return 0;
 }
 
+/* The same on a non-uniform time grid t[0] = 0 < t[1] < ... < t[nt] (the paper's outlook, Sec. 7,
+ * with the time integrals of Sec. 3.5 over general intervals): w, u hold one row per interval
+ * [t_i, t_{i+1}]; at a point with t_k <= t < t_{k+1} the intervals i < k are integrated over
+ * s = t - tau in (t - t_{i+1}, t - t_i) and the current interval k over (0, t - t_k).  Rule and
+ * outputs as or_repr. */
+int or_repr_nonuniform(const double *verts, int nv, const int32_t *tris, int ne, double alpha,
+                       const double *tn, int nt, const double *w, const double *u,
+                       const double *pts, int P, int rule_kind, int rule_order, double *sl,
+                       double *dl) {
+  (void)nv;
+  if (nt < 1 || tn[0] != 0.0) return -1;
+  for (int k = 0; k < nt; ++k)
+    if (!(tn[k + 1] > tn[k])) return -1;
+  double lam[3 * 4096], wq[4096];
+  int nq = or_triangle_rule(rule_kind, rule_order, lam, wq);
+  if (nq <= 0) return -1;
+  ld al = (ld)alpha;
+#pragma omp parallel for schedule(dynamic)
+  for (int p = 0; p < P; ++p) {
+    ld x[3] = {pts[4 * p], pts[4 * p + 1], pts[4 * p + 2]}, t = pts[4 * p + 3];
+    int k = 0; /* largest k <= nt with t_k <= t */
+    while (k < nt && (ld)tn[k + 1] <= t) ++k;
+    ld accs = 0.0L, accd = 0.0L;
+    for (int j = 0; j < ne; ++j) {
+      tri_t B;
+      make_tri(verts, tris + 3 * j, &B);
+      for (int q = 0; q < nq; ++q) {
+        ld y[3], r[3];
+        for (int c = 0; c < 3; ++c) {
+          y[c] = lam[3 * q] * B.v[0][c] + lam[3 * q + 1] * B.v[1][c] + lam[3 * q + 2] * B.v[2][c];
+          r[c] = x[c] - y[c];
+        }
+        ld rho = sqrtl(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        ld rn = r[0] * B.n[0] + r[1] * B.n[1] + r[2] * B.n[2];
+        ld Wq = wq[q] * B.area;
+        ld ws = 0.0L, wd[3] = {0, 0, 0};
+        for (int i = 0; i < k; ++i) {
+          ld s_lo = t - (ld)tn[i + 1], s_hi = t - (ld)tn[i];
+          ws += w[(size_t)i * ne + j] * time_int_G(rho, s_lo, s_hi, al);
+          ld gn = time_int_Gn_rn(rho, s_lo, s_hi, al);
+          for (int c = 0; c < 3; ++c) wd[c] += u[(size_t)i * nv + tris[3 * j + c]] * gn;
+        }
+        if (k < nt && t > (ld)tn[k]) {
+          ld s_hi = t - (ld)tn[k];
+          ws += w[(size_t)k * ne + j] * time_int_G(rho, 0.0L, s_hi, al);
+          ld gn = time_int_Gn_rn(rho, 0.0L, s_hi, al);
+          for (int c = 0; c < 3; ++c) wd[c] += u[(size_t)k * nv + tris[3 * j + c]] * gn;
+        }
+        accs += Wq * ws;
+        accd += Wq * rn * (lam[3 * q] * wd[0] + lam[3 * q + 1] * wd[1] + lam[3 * q + 2] * wd[2]);
+      }
+    }
+    sl[p] = (double)accs;
+    dl[p] = (double)accd;
+  }
+  return 0;
+}
+
 /* ---- vectorised temporal functions for tests (double in/out, long double inside) ---- */
 void or_temporal(int which, const double *rho, const double *delta, int n, double alpha,
                  double *out) {

@@ -125,3 +125,47 @@ def test_assembled_blocks_split_interval():
                 else:
                     B = A2[e(k2, j)] + A2[e(k2, j + 1)]
                 assert np.abs(A[e(k, j)] - B).max() <= 1e-13 * np.abs(A[e(k, j)]).max(), k
+
+
+def _repr_inputs(nt, seed):
+    v, t = octahedron()
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((nt, len(t)))
+    u = rng.standard_normal((nt, len(v)))
+    return v, t, w, u
+
+
+def test_repr_uniform_grid_matches_uniform_oracle():
+    """The non-uniform representation formula on the uniform grid t_j = j T / nt equals the
+    uniform oracle's (points in the current interval, at grid times, at t = 0 and t = T)."""
+    nt, T, alpha = 7, 1.3, 0.8
+    v, t, w, u = _repr_inputs(nt, 41)
+    ts = [0.0, 0.05, T / nt, 2.5 * T / nt, 0.999, T]
+    pts = np.array([[0.1, -0.05, 0.12, s] for s in ts] + [[-0.2, 0.1, 0.0, 0.77]])
+    sl0, dl0 = oracle.repr_eval(v, t, alpha, T, nt, w, u, pts)
+    sl1, dl1 = oracle.repr_eval_nonuniform(v, t, alpha, np.arange(nt + 1) * (T / nt), w, u, pts)
+    assert np.abs(sl1 - sl0).max() <= 1e-14 * np.abs(sl0).max()
+    assert np.abs(dl1 - dl0).max() <= 1e-14 * np.abs(dl0).max()
+
+
+@pytest.mark.parametrize("coarse", ["uniform", "graded"])
+def test_repr_refined_grid_with_repeated_data(coarse):
+    """Splitting every interval at an interior point and repeating its data on both halves leaves
+    the potentials unchanged (additivity of the time integrals); from a uniform coarse grid this
+    ties the non-uniform formula to the uniform oracle."""
+    alpha = 0.6
+    tn = np.linspace(0.0, 1.0, 6) if coarse == "uniform" else GRID
+    nt = len(tn) - 1
+    v, t, w, u = _repr_inputs(nt, 43)
+    rng = np.random.default_rng(44)
+    cut = tn[:-1] + (0.2 + 0.6 * rng.random(nt)) * np.diff(tn)
+    fine = np.sort(np.concatenate([tn, cut]))
+    rep = np.repeat(np.arange(nt), 2)
+    pts = np.array([[0.05, 0.1, -0.1, s] for s in (0.03, tn[2], 0.5 * (tn[3] + cut[3]), 0.97, 1.0)])
+    if coarse == "uniform":
+        slc, dlc = oracle.repr_eval(v, t, alpha, 1.0, nt, w, u, pts)
+    else:
+        slc, dlc = oracle.repr_eval_nonuniform(v, t, alpha, tn, w, u, pts)
+    slf, dlf = oracle.repr_eval_nonuniform(v, t, alpha, fine, w[rep], u[rep], pts)
+    assert np.abs(slf - slc).max() <= 1e-13 * np.abs(slc).max()
+    assert np.abs(dlf - dlc).max() <= 1e-13 * np.abs(dlc).max()
