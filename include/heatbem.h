@@ -112,9 +112,9 @@ int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t 
  * trapezoid-weighted kernel about the centre of its time support (same value, no cancellation).
  * On such a context: hb_assemble (HB_OP_V | HB_OP_K, HB_PREC_FP64), hb_get_blocks (d0, nd index
  * the packed blocks), hb_apply (HB_OP_V, HB_OP_K: y^k = sum_{i<=k} A^{k,i} x^i),
- * hb_rhs_dirichlet (M_h = blockdiag(h_k M_x)), hb_solve (HB_SOLVE_GMRES, precond 0), hb_sizes,
- * hb_last_assembly_ms, hb_last_error and hb_destroy work; the other entry points return
- * HB_EINVAL. */
+ * hb_rhs_dirichlet (M_h = blockdiag(h_k M_x)), hb_solve (HB_SOLVE_GMRES, precond 0),
+ * hb_eval_repr (closed-form time integrals over the intervals), hb_sizes, hb_last_assembly_ms,
+ * hb_last_error and hb_destroy work; the other entry points return HB_EINVAL. */
 int hb_create_nonuniform(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t *tris,
                          int64_t n_tris, double alpha, const double *t_nodes, int32_t n_t,
                          const hb_options *opt);
@@ -270,7 +270,9 @@ int hb_solve_neumann(hb_ctx *ctx, const double *b, double *u, const hb_solve_opt
  * coefficients, u: P outputs.  All device pointers, float64.  The spatial rule is the 7-point
  * rule of hb_assemble.  sl / dl may be NULL; otherwise they receive V~ w and W g.  Each point's
  * interval coefficients live in one workgroup's LDS, which bounds E_t at about 1650 (HB_EINVAL
- * beyond). */
+ * beyond).  On a non-uniform context (hb_create_nonuniform) the rows of w and g belong to the
+ * intervals [t_k, t_{k+1}] and every interval is integrated in closed form (the paper's outlook,
+ * Sec. 7, with the time integrals of Sec. 3.5 over general intervals). */
 int hb_eval_repr(hb_ctx *ctx, const double *pts, int64_t P, const double *w, const double *g,
                  double *u, double *sl, double *dl, void *stream);
 

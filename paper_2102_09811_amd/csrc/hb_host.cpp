@@ -853,6 +853,8 @@ int build_nu_tables(hb_ctx *c) {
     if ((rc = upload(c, (void **)&c->d_nu_tout, tout.data(), tout.size() * sizeof(int32_t)))) return rc;
   }
   if ((rc = upload(c, (void **)&c->d_nu_h, hs.data(), hs.size() * sizeof(double)))) return rc;
+  if ((rc = upload(c, (void **)&c->d_nu_t, c->tnodes.data(), c->tnodes.size() * sizeof(double))))
+    return rc;
   c->n_nu_closed = (int32_t)closed.size();
   c->n_nu_taylor = (int32_t)nT;
   return HB_OK;
@@ -982,7 +984,7 @@ void hb_destroy(hb_ctx *c) {
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d,
                   c->d_D, c->d_Dw, c->d_V11, c->d_minv, c->d_pcw, c->d_Kt, c->d_near_sep, c->d_near_touch, c->d_d2tab, c->d_d2scale, c->d_d2len, c->d_curl, c->d_vstart,
                   c->d_vadj, c->d_pc_buf, c->d_nu_closed, c->d_nu_tout, c->d_nu_tdeg, c->d_nu_taylor,
-                  c->d_nu_tscale, c->d_nu_h};
+                  c->d_nu_tscale, c->d_nu_h, c->d_nu_t};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int i = 0; i < 4; ++i)

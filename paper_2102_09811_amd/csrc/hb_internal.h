@@ -259,4 +259,5 @@ struct hb_ctx {
   int32_t *d_nu_tout = nullptr, *d_nu_tdeg = nullptr;
   double *d_nu_taylor = nullptr, *d_nu_tscale = nullptr;
   double *d_nu_h = nullptr;          // [nt]: step lengths h_k
+  double *d_nu_t = nullptr;          // [nt + 1]: the time nodes t_k
 };

@@ -789,6 +789,107 @@ __global__ __launch_bounds__(256, 2) void k_repr(const AsmParams *__restrict__ p
   }
 }
 
+// Potentials on a non-uniform time grid t_0 = 0 < ... < t_{E_t} (the paper's outlook, Sec. 7, with
+// the time integrals of Sec. 3.5 over general intervals): one workgroup per point (x, t), lanes
+// over panels.  With t_k <= t < t_{k+1}, interval i < k is seen at s = t - tau in
+// [t - t_{i+1}, t - t_i] and the current interval k at [0, t - t_k]; every interval in closed form
+// (differences of erfc and of D(z) = erfc(z) + 2 z e^{-z^2} / sqrt(pi) at its two ends, each end's
+// values shared by the two intervals that meet there).  The breakpoint factors
+// 1 / (2 sqrt(alpha (t - t_b))) sit in LDS; a lane walks its panel's breakpoints from t back to 0
+// and carries the previous end's values per rule node.
+__global__ __launch_bounds__(256) void k_nu_repr(const AsmParams *__restrict__ pp,
+                                                 const double *__restrict__ tn,
+                                                 const double *__restrict__ pts,
+                                                 const double *__restrict__ w,
+                                                 const double *__restrict__ g,
+                                                 double *__restrict__ u, double *__restrict__ sl,
+                                                 double *__restrict__ dl) {
+  extern __shared__ double czs[];  // [E_t + 1]: 1 / (2 sqrt(alpha (t - t_b))), 0 where t = t_b
+  const AsmParams &p = *pp;
+  const int pid = blockIdx.x;
+  const double px = pts[4 * pid], py = pts[4 * pid + 1], pz = pts[4 * pid + 2], t = pts[4 * pid + 3];
+  const int ne = p.ne, nv = p.nv, nt = p.nt;
+  // k: the largest index <= E_t with t_k <= t (t_0 = 0 <= t)
+  int lo = 0, hi = nt;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tn[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const int k = lo;
+  const double c_al = 1.0 / (2.0 * sqrt(p.alpha));
+  for (int b = threadIdx.x; b <= k; b += blockDim.x) {
+    const double s = t - tn[b];
+    czs[b] = s > 0.0 ? c_al / sqrt(s) : 0.0;
+  }
+  __syncthreads();
+  constexpr double kTwoInvSqrtPi = 1.1283791670955125739;
+  double accs = 0.0, accd = 0.0;
+  for (int j = threadIdx.x; j < ne; j += blockDim.x) {
+    const double area = p.geom[24 * ne + j];
+    const double n0 = p.geom[21 * ne + j], n1 = p.geom[22 * ne + j], n2 = p.geom[23 * ne + j];
+    const int v0 = p.tris[3 * j], v1 = p.tris[3 * j + 1], v2 = p.tris[3 * j + 2];
+    double rho[kFarN], rn[kFarN], ecp[kFarN], Dp[kFarN], sv[kFarN], sd[kFarN];
+#pragma unroll
+    for (int q = 0; q < kFarN; ++q) {
+      const double rx = px - p.geom[(q * 3 + 0) * ne + j];
+      const double ry = py - p.geom[(q * 3 + 1) * ne + j];
+      const double rz = pz - p.geom[(q * 3 + 2) * ne + j];
+      rho[q] = sqrt(fma(rx, rx, fma(ry, ry, rz * rz)));
+      rn[q] = fma(rx, n0, fma(ry, n1, rz * n2));
+      ecp[q] = Dp[q] = sv[q] = sd[q] = 0.0;  // the values at s = 0
+    }
+#pragma unroll 1
+    for (int b = k; b >= 0; --b) {
+      const double cz = czs[b];
+      // interval b ends at this breakpoint (none for b = E_t)
+      const bool has = b < nt;
+      const double wb = has ? w[(size_t)b * ne + j] : 0.0;
+      const double *gb = g + (size_t)(has ? b : 0) * nv;
+      const double g0 = has ? gb[v0] : 0.0, g1 = has ? gb[v1] : 0.0, g2 = has ? gb[v2] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kFarN; ++q) {
+        double ec = 0.0, D = 0.0;
+        if (cz > 0.0) {
+          const double z = rho[q] * cz;
+          ec = erfc(z);
+          D = ec + kTwoInvSqrtPi * z * exp_neg(z * z);
+        }
+        sv[q] = fma(wb, ec - ecp[q], sv[q]);
+        const double gq = fma(p.lam7[q][0], g0, fma(p.lam7[q][1], g1, p.lam7[q][2] * g2));
+        sd[q] = fma(gq, D - Dp[q], sd[q]);
+        ecp[q] = ec;
+        Dp[q] = D;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kFarN; ++q) {
+      const double Wq = p.w7[q] * area, ir = 1.0 / rho[q];
+      accs = fma(Wq * ir, sv[q], accs);
+      accd = fma(Wq * rn[q] * (ir * ir * ir), sd[q], accd);
+    }
+  }
+  __shared__ double red[2][4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    accs += __shfl_xor(accs, o, 64);
+    accd += __shfl_xor(accd, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = accs;
+    red[1][threadIdx.x >> 6] = accd;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    constexpr double kInv4Pi = 0.079577471545947667884;
+    const double s = (red[0][0] + red[0][1] + red[0][2] + red[0][3]) * kInv4Pi / p.alpha;
+    const double d = (red[1][0] + red[1][1] + red[1][2] + red[1][3]) * kInv4Pi;
+    u[pid] = s - d;
+    if (sl) sl[pid] = s;
+    if (dl) dl[pid] = d;
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // host helpers
 // ------------------------------------------------------------------------------------------
@@ -1675,7 +1776,6 @@ int hb_solve(hb_ctx *c, const double *b, double *w, const hb_solve_opts *opts, h
 int hb_eval_repr(hb_ctx *c, const double *pts, int64_t P, const double *w, const double *g,
                  double *u, double *sl, double *dl, void *stream) {
   if (!c) return HB_EINVAL;
-  if (c->nu) return ctx_fail(c, HB_EINVAL, "not available on a non-uniform time grid");
   if (P < 0) return ctx_fail(c, HB_EINVAL, "P must be >= 0");
   if (P == 0) return HB_OK;
   if (!pts || !w || !g || !u) return ctx_fail(c, HB_EINVAL, "null pointer");
@@ -1684,6 +1784,15 @@ int hb_eval_repr(hb_ctx *c, const double *pts, int64_t P, const double *w, const
   if (!c->d_params_repr) {
     HB_CHECK(c, hipMalloc(&c->d_params_repr, sizeof(AsmParams)));
     HB_CHECK(c, hipMemcpy(c->d_params_repr, &c->params, sizeof(AsmParams), hipMemcpyHostToDevice));
+  }
+  if (c->nu) {
+    const size_t lds = sizeof(double) * ((size_t)c->nt + 1);
+    if (lds + sizeof(double) * 8 > 160 * 1024)
+      return ctx_fail(c, HB_EINVAL, "E_t too large for the potential kernel");
+    hipLaunchKernelGGL(k_nu_repr, dim3((unsigned)P), dim3(256), lds, s, c->d_params_repr,
+                       c->d_nu_t, pts, w, g, u, sl, dl);
+    HB_CHECK(c, hipGetLastError());
+    return HB_OK;
   }
   if (!c->d_reprq) {
     // Q_{2k}(w) / (2k+1)! for p = 3/2 (Q_0 = 1, Q_{n+1} = (w - n - p) Q_n - w Q_n'), the building

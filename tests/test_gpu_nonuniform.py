@@ -8,6 +8,7 @@ integrals of Sec. 3.1 and 3.2 at general interval endpoints) against the oracle,
 * a uniform grid through this path reproduces the oracle's Toeplitz blocks V^{k-i}, K^{k-i};
 * the block lower-triangular product, the right-hand side (1/2 M_h + K_h) g with
   M_h = blockdiag(h_k M_x), and GMRES to 1e-8 against numpy on the oracle's blocks;
+* the potentials (Sec. 3.5 over general intervals) against the oracle's closed forms;
 * the entry points that a non-uniform context does not support return HB_EINVAL.
 """
 import sys
@@ -168,9 +169,33 @@ def test_nu_unsupported_entry_points(torch):
     with pytest.raises(HBError) as ei:
         ctx.solve(b, method=HB_SOLVE_TIMEMARCH)
     assert ei.value.code == -1
-    pts = torch.zeros((1, 4), dtype=torch.float64, device="cuda")
-    g = torch.zeros((ctx.n_t, ctx.n_verts), dtype=torch.float64, device="cuda")
-    with pytest.raises(HBError) as ei:
-        ctx.eval_repr(pts, b, g)
-    assert ei.value.code == -1
     ctx.close()
+
+
+@pytest.mark.parametrize("case", ["octa_irregular9", "cube2_graded12"])
+def test_nu_repr_matches_oracle(torch, case):
+    """Potentials V~w and W g on the non-uniform grid against the oracle (long double closed
+    forms) at points inside the mesh, at t = 0, at grid times, inside intervals and at t = T."""
+    from paper_2102_09811_amd import NonuniformContext
+    mesh, tn, alpha, _, _ = CASES[case]
+    v, t = mesh()
+    nt = len(tn) - 1
+    rng = np.random.default_rng(17)
+    w = rng.standard_normal((nt, len(t)))
+    g = rng.standard_normal((nt, len(v)))
+    c = v.mean(axis=0)
+    times = [0.0, tn[1], 0.5 * (tn[2] + tn[3]), tn[nt // 2], 0.9 * tn[-1] + 0.1 * tn[-2], tn[-1]]
+    pts = np.array([[c[0] + 0.1 * rng.standard_normal(), c[1] + 0.1 * rng.standard_normal(),
+                     c[2] + 0.1 * rng.standard_normal(), s] for s in times for _ in range(3)])
+    say("nonuniform potentials %s: %d points" % (case, len(pts)))
+    sl_r, dl_r = oracle.repr_eval_nonuniform(v, t, alpha, tn, w, g, pts)
+    ctx = NonuniformContext(v, t, alpha, tn)
+    u, sl, dl = ctx.eval_repr(torch.from_numpy(pts).cuda(), torch.from_numpy(w).cuda(),
+                              torch.from_numpy(g).cuda(), parts=True)
+    ctx.close()
+    sl, dl, u = sl.cpu().numpy(), dl.cpu().numpy(), u.cpu().numpy()
+    es = np.abs(sl - sl_r).max() / np.abs(sl_r).max()
+    ed = np.abs(dl - dl_r).max() / np.abs(dl_r).max()
+    eu = np.abs(u - (sl_r - dl_r)).max() / np.abs(sl_r - dl_r).max()
+    say("  single layer %.2e, double layer %.2e, u %.2e" % (es, ed, eu))
+    assert es <= 1e-11 and ed <= 1e-11 and eu <= 1e-11
