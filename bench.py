@@ -291,10 +291,11 @@ def nearfield_timings(ctx, stream, radius=0.35):
 def nonuniform_timings(verts, tris, alpha, n_t, stream, gamma=1.5):
     """Non-uniform time grid (outside the timed step): the same mesh on the graded nodes
     t_j = (j / E_t)^gamma, assembly of all E_t (E_t + 1) / 2 blocks V^{k,i}, K^{k,i}, the
-    block-triangular product and GMRES to 1e-8 on a smooth right-hand side."""
+    block-triangular product, GMRES to 1e-8 and time marching (its first call inverts every
+    V^{k,k}) on the same right-hand side."""
     import numpy as np
     import torch
-    from paper_2102_09811_amd import HB_OP_K, HB_OP_V, NonuniformContext
+    from paper_2102_09811_amd import HB_OP_K, HB_OP_V, HB_SOLVE_TIMEMARCH, NonuniformContext
     tn = (np.arange(n_t + 1) / n_t) ** gamma
     ctx = NonuniformContext(verts, tris, alpha, tn)
     ctx.assemble(HB_OP_V | HB_OP_K)
@@ -313,14 +314,19 @@ def nonuniform_timings(verts, tris, alpha, n_t, stream, gamma=1.5):
     torch.cuda.synchronize()
     apply_ms = e0.elapsed_time(e1)
     w, info = ctx.solve(y, tol=1e-8)
+    _, tm1 = ctx.solve(y, method=HB_SOLVE_TIMEMARCH, tol=1e-8)
+    _, tm2 = ctx.solve(y, method=HB_SOLVE_TIMEMARCH, tol=1e-8)
     ctx.close()
     log("non-uniform grid (t_j = (j/%d)^%g): assembly %.2f ms (%.3g pair-block integrals/s), "
-        "product %.3f ms, GMRES %d it %.2f ms" % (n_t, gamma, ms, units / (ms * 1e-3), apply_ms,
-                                                  info["iterations"], info["seconds"] * 1e3))
+        "product %.3f ms, GMRES %d it %.2f ms, time marching %.2f ms (with the inverses %.2f ms)"
+        % (n_t, gamma, ms, units / (ms * 1e-3), apply_ms, info["iterations"],
+           info["seconds"] * 1e3, tm2["seconds"] * 1e3, tm1["seconds"] * 1e3))
     return {"grid": "t_j = (j / %d)^%g" % (n_t, gamma), "blocks": n_t * (n_t + 1) // 2,
             "assemble_ms": ms, "units_per_s": units / (ms * 1e-3), "apply_V_ms": apply_ms,
             "gmres": {"ms": info["seconds"] * 1e3, "iterations": info["iterations"],
-                      "rel_residual": info["rel_residual"]}}
+                      "rel_residual": info["rel_residual"]},
+            "time_marching": {"ms": tm2["seconds"] * 1e3, "ms_with_inverses": tm1["seconds"] * 1e3,
+                              "rel_residual": tm2["rel_residual"]}}
 
 
 def main():

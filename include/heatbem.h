@@ -112,7 +112,8 @@ int hb_create(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t 
  * trapezoid-weighted kernel about the centre of its time support (same value, no cancellation).
  * On such a context: hb_assemble (HB_OP_V | HB_OP_K, HB_PREC_FP64), hb_get_blocks (d0, nd index
  * the packed blocks), hb_apply (HB_OP_V, HB_OP_K: y^k = sum_{i<=k} A^{k,i} x^i),
- * hb_rhs_dirichlet (M_h = blockdiag(h_k M_x)), hb_solve (HB_SOLVE_GMRES, precond 0),
+ * hb_rhs_dirichlet (M_h = blockdiag(h_k M_x)), hb_solve (HB_SOLVE_GMRES or HB_SOLVE_TIMEMARCH,
+ * the latter with the inverses of every V^{k,k}, precond 0),
  * hb_eval_repr (closed-form time integrals over the intervals), hb_sizes, hb_last_assembly_ms,
  * hb_last_error and hb_destroy work; the other entry points return HB_EINVAL. */
 int hb_create_nonuniform(hb_ctx **out, const double *verts, int64_t n_verts, const int32_t *tris,

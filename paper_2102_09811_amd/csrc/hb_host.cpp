@@ -1080,7 +1080,10 @@ static int assemble_nu(hb_ctx *c, uint32_t ops, int32_t precision, hipStream_t s
   if (ntouch > 0) hb::launch_nu_touching(c->d_params, nu, c->d_touch, ntouch, c->ss, s);
   HB_HIP(c, hipGetLastError());
   HB_HIP(c, hipEventRecord(c->ev[2], s));
-  if (p.do_V) c->have_V = true;
+  if (p.do_V) {
+    c->have_V = true;
+    c->v0inv_valid = false;  // the inverses of the diagonal blocks V^{k,k}
+  }
   if (p.do_K) c->have_K = true;
   c->timed = true;
   return HB_OK;

@@ -232,7 +232,8 @@ struct hb_ctx {
   // solver workspace
   double *d_work = nullptr;
   size_t work_bytes = 0;
-  double *d_v0inv = nullptr;         // inverse of V^0 (time marching)
+  double *d_v0inv = nullptr;         // inverse of V^0 (time marching; on a non-uniform grid
+                                     // the inverses of all V^{k,k}, [nt][E_x][E_x])
   bool v0inv_valid = false;          // cleared whenever V is reassembled
   // learned preconditioner: row pattern, centroids, installed weights
   int32_t *d_pc_cols = nullptr;      // [ne][HB_PC_SLOTS]

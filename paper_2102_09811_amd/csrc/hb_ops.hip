@@ -297,7 +297,11 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 }
 
 __global__ __launch_bounds__(256) void k_gj_step(const double *__restrict__ X,
-                                                 double *__restrict__ Y, int n, int p0, int b) {
+                                                 double *__restrict__ Y, int n, int p0, int b,
+                                                 size_t zs) {
+  // blockIdx.z: the matrix of a batch, zs doubles apart
+  X += blockIdx.z * zs;
+  Y += blockIdx.z * zs;
   __shared__ double Pi[kGJB][kGJB + 1];
   __shared__ double Rr[kGJB][64 + 1];
   __shared__ double Cs[64][kGJB + 1];
@@ -1055,6 +1059,38 @@ __global__ __launch_bounds__(256) void k_nu_apply(const double *__restrict__ A,
   if (lane == 0) y[(size_t)k * R + r] = sum;
 }
 
+// Time marching on a non-uniform grid, the history of step k: r^k -= sum_{i<k} V^{k,i} w^i over
+// the block row k (packed blocks k (k + 1) / 2 .. k (k + 1) / 2 + k - 1, consecutive), one wave
+// per row, kGemvBatch column loads of a round in flight per lane.
+__global__ __launch_bounds__(256) void k_nu_hist(const double *__restrict__ A,
+                                                 const double *__restrict__ x,
+                                                 double *__restrict__ r, int k, int R, int C) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= R) return;
+  const size_t blk = (size_t)R * C;
+  const double *a = A + ((size_t)k * (k + 1) / 2) * blk + (size_t)row * C;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < k; ++i, a += blk) {
+    const double *xi = x + (size_t)i * C;
+    for (int c0 = 0; c0 < C; c0 += 64 * kGemvBatch) {
+      double av[kGemvBatch], xv[kGemvBatch];
+#pragma unroll
+      for (int u = 0; u < kGemvBatch; ++u) {
+        const int c = c0 + lane + 64 * u;
+        av[u] = c < C ? a[c] : 0.0;
+        xv[u] = c < C ? xi[c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kGemvBatch; ++u) s[u & 3] = fma(av[u], xv[u], s[u & 3]);
+    }
+  }
+  double t = (s[0] + s[1]) + (s[2] + s[3]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  if (lane == 0) r[(size_t)k * R + row] -= t;
+}
+
 int nu_apply(hb_ctx *c, const double *A, int R, int C, const double *x, double *y, hipStream_t s) {
   dim3 grid((unsigned)((R + 3) / 4), (unsigned)c->nt);
   hipLaunchKernelGGL(k_nu_apply, grid, dim3(256), 0, s, A, x, y, c->nt, R, C);
@@ -1107,16 +1143,18 @@ int gemv_batch(hb_ctx *c, const void *A, size_t stride, int R, int C, int nd, co
 // Gauss-Jordan elimination without pivoting (A is V_h^0 or a mass matrix, both symmetric positive
 // definite); B: an n x n workspace.  The panels alternate between A and B; with an odd panel count
 // the matrix is first copied to B so that the last panel writes A.
-int gj_invert(hb_ctx *c, double *A, double *B, int n, hipStream_t s) {
-  const dim3 tiles((n + 63) / 64, (n + 63) / 64);
+int gj_invert(hb_ctx *c, double *A, double *B, int n, hipStream_t s, int nmat = 1) {
+  // nmat > 1: a batch of nmat matrices n * n doubles apart in A (and in B), inverted together
+  const dim3 tiles((n + 63) / 64, (n + 63) / 64, nmat);
+  const size_t zs = (size_t)n * n;
   const int panels = (n + kGJB - 1) / kGJB;
   double *X = A, *Y = B;
   if (panels & 1) {
-    HB_CHECK(c, hipMemcpyAsync(B, A, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+    HB_CHECK(c, hipMemcpyAsync(B, A, sizeof(double) * zs * nmat, hipMemcpyDeviceToDevice, s));
     std::swap(X, Y);
   }
   for (int p0 = 0; p0 < n; p0 += kGJB) {
-    hipLaunchKernelGGL(k_gj_step, tiles, dim3(256), 0, s, X, Y, n, p0, std::min(kGJB, n - p0));
+    hipLaunchKernelGGL(k_gj_step, tiles, dim3(256), 0, s, X, Y, n, p0, std::min(kGJB, n - p0), zs);
     std::swap(X, Y);
   }
   HB_CHECK(c, hipGetLastError());
@@ -1127,6 +1165,19 @@ int invert_v0(hb_ctx *c, hipStream_t s) {
   if (c->v0inv_valid) return HB_OK;
   const int n = (int)c->ne;
   const size_t nn = (size_t)n * n;
+  if (c->nu) {
+    // every diagonal block V^{k,k} (packed index k (k + 1) / 2 + k), inverted as one batch
+    const int nt = c->nt;
+    if (!c->d_v0inv) HB_CHECK(c, hipMalloc(&c->d_v0inv, sizeof(double) * 2 * nn * nt));
+    double *A = c->d_v0inv, *B = A + nn * nt;
+    for (int k = 0; k < nt; ++k)
+      HB_CHECK(c, hipMemcpyAsync(A + (size_t)k * nn, (const double *)c->d_V + ((size_t)k * (k + 1) / 2 + k) * nn,
+                                 sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    int rc = gj_invert(c, A, B, n, s, nt);
+    if (rc) return rc;
+    c->v0inv_valid = true;
+    return HB_OK;
+  }
   if (!c->d_v0inv) HB_CHECK(c, hipMalloc(&c->d_v0inv, sizeof(double) * 2 * nn));
   double *A = c->d_v0inv, *B = A + nn;
   if (c->storage_f32)
@@ -1422,6 +1473,21 @@ int time_march(hb_ctx *c, const double *b, double *w, hipStream_t s) {
   if ((rc = ensure_work(c, sizeof(double) * n))) return rc;
   double *r = c->d_work;
   HB_CHECK(c, hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  if (c->nu) {
+    // non-uniform grid: w^k = (V^{k,k})^{-1} (b^k - sum_{i<k} V^{k,i} w^i), step by step
+    const size_t nn = (size_t)ne * ne;
+    for (int k = 0; k < nt; ++k) {
+      if (k > 0) {
+        hipLaunchKernelGGL(k_nu_hist, dim3((unsigned)((ne + 3) / 4)), dim3(256), 0, s,
+                           (const double *)c->d_V, (const double *)w, r, k, ne, ne);
+        HB_CHECK(c, hipGetLastError());
+      }
+      if ((rc = gemv_batch(c, c->d_v0inv + k * nn, 0, ne, ne, 1, r + (size_t)k * ne,
+                           w + (size_t)k * ne, 1.0, 0.0, 0, s)))
+        return rc;
+    }
+    return HB_OK;
+  }
   return tm_solve(c, r, w, 0, nt, s);
 }
 
@@ -1743,8 +1809,9 @@ int hb_solve(hb_ctx *c, const double *b, double *w, const hb_solve_opts *opts, h
   }
   if (o.method != HB_SOLVE_GMRES && o.method != HB_SOLVE_TIMEMARCH && o.method != HB_SOLVE_MIXED_IR)
     return ctx_fail(c, HB_EINVAL, "unknown solver method");
-  if (c->nu && (o.method != HB_SOLVE_GMRES || o.precond))
-    return ctx_fail(c, HB_EINVAL, "a non-uniform grid is solved by GMRES without preconditioner");
+  if (c->nu && (o.method == HB_SOLVE_MIXED_IR || o.precond))
+    return ctx_fail(c, HB_EINVAL,
+                    "a non-uniform grid is solved by GMRES or time marching without preconditioner");
   if (o.max_iter > 5000) return ctx_fail(c, HB_EINVAL, "max_iter must be <= 5000");
   hipStream_t s = (hipStream_t)stream;
   hb_solve_info inf{};

@@ -7,7 +7,8 @@ integrals of Sec. 3.1 and 3.2 at general interval endpoints) against the oracle,
   weight, an independent evaluation of the same integral;
 * a uniform grid through this path reproduces the oracle's Toeplitz blocks V^{k-i}, K^{k-i};
 * the block lower-triangular product, the right-hand side (1/2 M_h + K_h) g with
-  M_h = blockdiag(h_k M_x), and GMRES to 1e-8 against numpy on the oracle's blocks;
+  M_h = blockdiag(h_k M_x), GMRES to 1e-8 and time marching (inverses of every V^{k,k}) against
+  numpy on the oracle's blocks;
 * the potentials (Sec. 3.5 over general intervals) against the oracle's closed forms;
 * the entry points that a non-uniform context does not support return HB_EINVAL.
 """
@@ -99,7 +100,7 @@ def test_nu_uniform_grid_reproduces_toeplitz(torch):
 
 
 def test_nu_apply_rhs_and_solve(torch):
-    from paper_2102_09811_amd import HB_OP_K, HB_OP_V, NonuniformContext
+    from paper_2102_09811_amd import HB_OP_K, HB_OP_V, HB_SOLVE_TIMEMARCH, NonuniformContext
     v, t = octahedron()
     tn, alpha = GRID, 0.7
     nt, ne, nv = len(tn) - 1, len(t), len(v)
@@ -140,17 +141,23 @@ def test_nu_apply_rhs_and_solve(torch):
         rhs = br[k] - sum(Vr[k * (k + 1) // 2 + i] @ wr[i] for i in range(k))
         wr[k] = np.linalg.solve(Vr[k * (k + 1) // 2 + k], rhs)
     e4 = np.abs(w - wr).max() / np.abs(wr).max()
+    # time marching: the inverses of all V^{k,k} (one batched Gauss-Jordan), then step by step
+    wt, info_t = ctx.solve(torch.from_numpy(br).cuda(), method=HB_SOLVE_TIMEMARCH, tol=1e-8)
+    wt = wt.cpu().numpy()
+    e5 = np.abs(wt - wr).max() / np.abs(wr).max()
     ctx.close()
     say("  apply V %.2e, K %.2e; rhs %.2e; GMRES %d it, residual (oracle blocks) %.2e, "
-        "solution %.2e" % (e1, e2, e3, info["iterations"], res, e4))
+        "solution %.2e; time marching: residual %.2e, solution %.2e"
+        % (e1, e2, e3, info["iterations"], res, e4, info_t["rel_residual"], e5))
     assert e1 <= 1e-12 and e2 <= 1e-12 and e3 <= 1e-12
     assert info["converged"] and info["rel_residual"] <= 1e-8 and res <= 1.01e-8
     assert e4 <= 1e-6
+    assert info_t["converged"] and info_t["rel_residual"] <= 1e-12 and e5 <= 1e-10
 
 
 def test_nu_unsupported_entry_points(torch):
     from paper_2102_09811_amd import (HB_DTYPE_F32, HB_OP_D, HB_OP_K, HB_OP_V, HB_PREC_MIXED,
-                                      HB_SOLVE_TIMEMARCH, HBError, NonuniformContext)
+                                      HB_SOLVE_MIXED_IR, HBError, NonuniformContext)
     v, t = octahedron()
     with pytest.raises(HBError) as ei:  # nodes must start at 0 and increase
         NonuniformContext(v, t, 1.0, np.array([0.0, 0.5, 0.5, 1.0]))
@@ -167,7 +174,7 @@ def test_nu_unsupported_entry_points(torch):
     ctx.assemble(HB_OP_V | HB_OP_K)
     b = torch.ones((ctx.n_t, ctx.n_tris), dtype=torch.float64, device="cuda")
     with pytest.raises(HBError) as ei:
-        ctx.solve(b, method=HB_SOLVE_TIMEMARCH)
+        ctx.solve(b, method=HB_SOLVE_MIXED_IR)
     assert ei.value.code == -1
     ctx.close()
 
