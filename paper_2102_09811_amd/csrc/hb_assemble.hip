@@ -796,13 +796,13 @@ __global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict_
                                                     RuleTabs rules,
                                                     const double *__restrict__ tscale,
                                                     const double *__restrict__ taylor,
-                                                    const int *__restrict__ tdeg) {
+                                                    const int *__restrict__ tlen) {
   const AsmParams &p = *pp;
   __shared__ double etab[kExpTabN];
   __shared__ __align__(16) double red[16 * kRedRow];
   stage_exp_tab_pos(etab);
   __syncthreads();
-  const SepTabs T{nullptr, tscale, taylor, nullptr, tdeg, etab};
+  const SepTabs T{nullptr, tscale, taylor, nullptr, nullptr, etab};
   TouchGroup G;
   const int ent = __builtin_amdgcn_readfirstlane(list[blockIdx.x]);
   const TouchPair &tp = pairs[SYM ? ~ent : ent];
@@ -850,17 +850,22 @@ __global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict_
     double R[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) R[i] = 0.0;
-    switch (T.tdeg[2 * d]) {
-      case 28: touch_taylor<SYM, 29>(T, G, d, d1, R); break;
-      case 24: touch_taylor<SYM, 25>(T, G, d, d1, R); break;
-      case 20: touch_taylor<SYM, 21>(T, G, d, d1, R); break;
-      case 18: touch_taylor<SYM, 19>(T, G, d, d1, R); break;
-      case 16: touch_taylor<SYM, 17>(T, G, d, d1, R); break;
-      case 14: touch_taylor<SYM, 15>(T, G, d, d1, R); break;
-      case 12: touch_taylor<SYM, 13>(T, G, d, d1, R); break;
-      case 10: touch_taylor<SYM, 11>(T, G, d, d1, R); break;
-      case 8: touch_taylor<SYM, 9>(T, G, d, d1, R); break;
-      default: touch_taylor<SYM, 7>(T, G, d, d1, R); break;
+    // the pass's polynomial length (one of kTouchLens, chosen on the host for this mesh)
+    switch (tlen[d]) {
+      case 5: touch_taylor<SYM, 5>(T, G, d, d1, R); break;
+      case 6: touch_taylor<SYM, 6>(T, G, d, d1, R); break;
+      case 7: touch_taylor<SYM, 7>(T, G, d, d1, R); break;
+      case 8: touch_taylor<SYM, 8>(T, G, d, d1, R); break;
+      case 9: touch_taylor<SYM, 9>(T, G, d, d1, R); break;
+      case 10: touch_taylor<SYM, 10>(T, G, d, d1, R); break;
+      case 11: touch_taylor<SYM, 11>(T, G, d, d1, R); break;
+      case 13: touch_taylor<SYM, 13>(T, G, d, d1, R); break;
+      case 15: touch_taylor<SYM, 15>(T, G, d, d1, R); break;
+      case 17: touch_taylor<SYM, 17>(T, G, d, d1, R); break;
+      case 19: touch_taylor<SYM, 19>(T, G, d, d1, R); break;
+      case 21: touch_taylor<SYM, 21>(T, G, d, d1, R); break;
+      case 25: touch_taylor<SYM, 25>(T, G, d, d1, R); break;
+      default: touch_taylor<SYM, 29>(T, G, d, d1, R); break;
     }
     // partial sums to LDS, row i = sum i (R[8], R[9] are unused), padded rows against conflicts
 #pragma unroll
@@ -1285,10 +1290,10 @@ static void launch_touch(hipStream_t s, const AsmParams *dp, const AsmParams &hp
   const int n0 = nlist - nsym;
   if (n0 > 0)
     hipLaunchKernelGGL((k_touching<TS, D, false>), dim3(n0), dim3(64), 0, s, dp, pairs, list, n0,
-                       rule, hp.tscale, hp.taylor, hp.tdeg);
+                       rule, hp.tscale, hp.taylor, hp.tlen_touch);
   if (nsym > 0)
     hipLaunchKernelGGL((k_touching<TS, D, true>), dim3(nsym), dim3(64), 0, s, dp, pairs, list + n0,
-                       nsym, rule, hp.tscale, hp.taylor, hp.tdeg);
+                       nsym, rule, hp.tscale, hp.taylor, hp.tlen_touch);
 }
 
 void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,

@@ -364,6 +364,28 @@ void taylor_poly_odd(int d, int deg, ld *out, int len) {
   }
 }
 
+// Shortest length N of the series polynomial c[0 .. len-1] in w whose dropped terms stay below
+// tol |c_0| for every w in [0, wmax], for the polynomial and for its derivative (the double-layer
+// kernel takes P - P'), both weighted by the factor e^{-w} the kernels multiply with.  Bounded
+// cell by cell on a grid: on [w_i, w_{i+1}] the powers are at most their values at w_{i+1} and
+// e^{-w} at most e^{-w_i}.
+int taylor_len(const ld *c, int len, ld wmax, ld tol) {
+  constexpr int kCells = 256;
+  const ld bound = tol * fabsl(c[0]);
+  for (int N = 1; N < len; ++N) {
+    bool ok = true;
+    for (int i = 0; i < kCells && ok; ++i) {
+      const ld w0 = wmax * i / kCells, w1 = wmax * (i + 1) / kCells;
+      ld tail = 0.0L;
+      for (int n = N; n < len; ++n)
+        tail += fabsl(c[n]) * (powl(w1, (ld)n) + (ld)n * powl(w1, (ld)(n - 1)));
+      ok = expl(-w0) * tail <= bound;
+    }
+    if (ok) return N;
+  }
+  return len;
+}
+
 int upload(hb_ctx *c, void **dst, const void *src, size_t bytes) {
   HB_HIP(c, hipMalloc(dst, bytes));
   HB_HIP(c, hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
@@ -430,13 +452,32 @@ int build_tables(hb_ctx *c) {
   auto pass_start = [&](int d) { return d - ((d - p.dsw) & 1); };
   std::vector<double> tay((size_t)c->nt * 2 * kTaylorN, 0.0), tsc((size_t)c->nt * 3, 0.0);
   std::vector<float> tay32((size_t)c->nt * 2 * kTaylorN32, 0.0f);
-  std::vector<int32_t> tdeg((size_t)c->nt * 2, 0);
+  std::vector<int32_t> tdeg((size_t)c->nt * 2, 0), tlen_touch((size_t)c->nt, 0);
+  // Touching pairs see distances rho up to the largest vertex distance of two triangles that
+  // share a vertex, so at block d their w = rho^2 c_d stays below rho_max^2 / (4 alpha d h): the
+  // terms of high power in w are negligible there, and their pass uses a shorter prefix of the
+  // same polynomial (dropped part below 1e-16 of the block scale, on top of the truncation of the
+  // series itself).
+  ld rho2_touch = 0.0L;
+  for (const TouchPair &tp : c->touch)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double *x = &c->verts[3 * c->tris[3 * tp.l + i]], *y = &c->verts[3 * c->tris[3 * tp.m + j]];
+        ld r2 = 0.0L;
+        for (int k = 0; k < 3; ++k) r2 += ((ld)x[k] - y[k]) * ((ld)x[k] - y[k]);
+        rho2_touch = std::max(rho2_touch, r2);
+      }
   for (int d = std::max(1, p.dsw); d < c->nt; ++d) {
     ld pv[kTaylorN], pk[kTaylorN];
     tdeg[2 * d] = deg64(pass_start(d));
     tdeg[2 * d + 1] = deg32(pass_start(d));
     taylor_poly(1.5L, d, pv, tdeg[2 * d]);
     taylor_poly(2.5L, d, pk, tdeg[2 * d]);
+    {
+      const int need = taylor_len(pv, tdeg[2 * d] + 1, rho2_touch / (4.0L * al * d * h), 1e-16L);
+      int32_t &L = tlen_touch[pass_start(d)];
+      L = std::max<int32_t>(L, need);
+    }
     for (int j = 0; j < kTaylorN; ++j) {
       tay[((size_t)d * 2 + 0) * kTaylorN + j] = (double)pv[j];
       tay[((size_t)d * 2 + 1) * kTaylorN + j] = (double)pk[j];
@@ -457,6 +498,14 @@ int build_tables(hb_ctx *c) {
   if ((rc = upload(c, (void **)&c->d_tscale, tsc.data(), tsc.size() * sizeof(double)))) return rc;
   if ((rc = upload(c, (void **)&c->d_taylor32, tay32.data(), tay32.size() * sizeof(float)))) return rc;
   if ((rc = upload(c, (void **)&c->d_tdeg, tdeg.data(), tdeg.size() * sizeof(int32_t)))) return rc;
+  for (int32_t &L : tlen_touch) {
+    if (L == 0) continue;
+    for (int n : kTouchLens)
+      if (n >= L) { L = n; break; }
+    L = std::min<int32_t>(L, kTaylorN);
+  }
+  if ((rc = upload(c, (void **)&c->d_tlen_touch, tlen_touch.data(), tlen_touch.size() * sizeof(int32_t))))
+    return rc;
 
 
   // geometry SoA: far-rule nodes, normal, area
@@ -660,6 +709,7 @@ int build_tables(hb_ctx *c) {
   p.taylor = c->d_taylor;
   p.taylor32 = c->d_taylor32;
   p.tdeg = c->d_tdeg;
+  p.tlen_touch = c->d_tlen_touch;
   p.tscale = c->d_tscale;
   p.geom = c->d_geom;
   p.tris = c->d_tris;
@@ -979,7 +1029,7 @@ void hb_destroy(hb_ctx *c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
   void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_touch_list, c->d_sep_tasks, c->d_sep_vstart, c->d_sep_verts, c->d_sep_slots, c->d_taylor,
-                  c->d_taylor32, c->d_tdeg, c->d_V32, c->d_tscale, c->d_mass,
+                  c->d_taylor32, c->d_tdeg, c->d_tlen_touch, c->d_V32, c->d_tscale, c->d_mass,
                   c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d,
                   c->d_D, c->d_Dw, c->d_V11, c->d_minv, c->d_pcw, c->d_Kt, c->d_near_sep, c->d_near_touch, c->d_d2tab, c->d_d2scale, c->d_d2len, c->d_curl, c->d_vstart,

@@ -16,6 +16,9 @@ namespace hb {
 // 0 .. d_switch; later blocks use the Taylor form, whose degree falls as d grows (28 at d = 3).
 constexpr int kTaylorDeg = 28;       // largest degree of the Taylor polynomial in w = rho^2/(4 alpha d h)
 constexpr int kTaylorN = kTaylorDeg + 1;
+// Polynomial lengths the touching-pair kernel is instantiated for (ascending; the host rounds a
+// pass's length up to one of them).
+constexpr int kTouchLens[] = {5, 6, 7, 8, 9, 10, 11, 13, 15, 17, 19, 21, 25, 29};
 constexpr int kTaylorDeg32 = 16;     // largest degree of the float evaluation (mixed precision)
 constexpr int kTaylorN32 = kTaylorDeg32 + 1;
 constexpr int kSeriesN = 14;         // terms of the small-z series of the brackets A(z), B(z)
@@ -53,6 +56,8 @@ struct AsmParams {
   const double *taylor;        // [nt][2][kTaylorN] Taylor polynomials in w (V, K), d >= dsw
   const float *taylor32;       // [nt][2][kTaylorN32] shorter series for the float path
   const int32_t *tdeg;         // [nt][2]: polynomial degree of block d, double and float path
+  const int32_t *tlen_touch;   // [nt]: polynomial length of the touching pairs' pass from block d
+                               // (their distances are short, so the series in w is cut earlier)
   const double *tscale;        // [nt][3]: V scale, K scale, c_d = 1/(4 alpha d h)
   const double *geom;          // SoA [25][ne]: far nodes (q*3+c), normal (21..23), area (24)
   const int32_t *tris;         // [ne][3]
@@ -193,7 +198,7 @@ struct hb_ctx {
   hb::SSRule ss[4];
   double *d_taylor = nullptr, *d_tscale = nullptr;
   float *d_taylor32 = nullptr;
-  int32_t *d_tdeg = nullptr;
+  int32_t *d_tdeg = nullptr, *d_tlen_touch = nullptr;
   float *d_V32 = nullptr;            // float copy of V for the mixed-precision inner solver
   bool V32_valid = false;
   double *d_mass = nullptr;          // p0 x p1 mass, [ne][3] = area/3 per local vertex
