@@ -132,6 +132,7 @@ struct SepTabs {
   const float *__restrict__ taylor32;   // [nt][2][kTaylorN32]
   const int *__restrict__ tdeg;         // [nt][2]
   const double *etab;                   // LDS: 2^{-j/64} (exp_neg_t) or 2^{j/256} (exp_neg_m)
+  const int *__restrict__ tlen;         // [nt]: length of the double pass from block d (k_separated)
 };
 
 // Per-lane data of an unordered separated pair.  The wave's test panel l is uniform: its rule
@@ -358,6 +359,7 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
                                                       const double *__restrict__ taylor,
                                                       const float *__restrict__ taylor32,
                                                       const int *__restrict__ tdeg,
+                                                      const int *__restrict__ tlen,
                                                       const int *__restrict__ tasks,
                                                       const int *__restrict__ tvstart,
                                                       const int *__restrict__ tverts,
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
   // trial vertex of the wave's task: added in LDS, then once per vertex to K
   __shared__ double kacc[4][2][kSepSlots];
   stage_exp_tab_pos(etab);
-  const SepTabs T{geom, tscale, taylor, taylor32, tdeg, etab};
+  const SepTabs T{geom, tscale, taylor, taylor32, tdeg, etab, tlen};
   // one task per wave: test panel l and up to 64 trial panels m0, m0 + 1, ... (mod E_x); every
   // unordered pair of panels occurs in exactly one task.  Consecutive rows l, l + 1 mirror their V
   // entries into neighbouring columns, so the blocks of one XCD take consecutive tasks.
@@ -450,17 +452,22 @@ __global__ __launch_bounds__(256, 2) void k_separated(const AsmParams *__restric
         default: sym_taylor2_32<5>(p, T, d, d1, m, L, R); break;
       }
     } else {
-      switch (T.tdeg[2 * d]) {
-        case 28: sym_taylor2<29>(p, T, d, d1, m, L, R); break;
-        case 24: sym_taylor2<25>(p, T, d, d1, m, L, R); break;
-        case 20: sym_taylor2<21>(p, T, d, d1, m, L, R); break;
-        case 18: sym_taylor2<19>(p, T, d, d1, m, L, R); break;
-        case 16: sym_taylor2<17>(p, T, d, d1, m, L, R); break;
-        case 14: sym_taylor2<15>(p, T, d, d1, m, L, R); break;
-        case 12: sym_taylor2<13>(p, T, d, d1, m, L, R); break;
-        case 10: sym_taylor2<11>(p, T, d, d1, m, L, R); break;
-        case 8: sym_taylor2<9>(p, T, d, d1, m, L, R); break;
-        default: sym_taylor2<7>(p, T, d, d1, m, L, R); break;
+      // the pass's polynomial length (one of kPolyLens, chosen on the host for this mesh)
+      switch (T.tlen[d]) {
+        case 5: sym_taylor2<5>(p, T, d, d1, m, L, R); break;
+        case 6: sym_taylor2<6>(p, T, d, d1, m, L, R); break;
+        case 7: sym_taylor2<7>(p, T, d, d1, m, L, R); break;
+        case 8: sym_taylor2<8>(p, T, d, d1, m, L, R); break;
+        case 9: sym_taylor2<9>(p, T, d, d1, m, L, R); break;
+        case 10: sym_taylor2<10>(p, T, d, d1, m, L, R); break;
+        case 11: sym_taylor2<11>(p, T, d, d1, m, L, R); break;
+        case 13: sym_taylor2<13>(p, T, d, d1, m, L, R); break;
+        case 15: sym_taylor2<15>(p, T, d, d1, m, L, R); break;
+        case 17: sym_taylor2<17>(p, T, d, d1, m, L, R); break;
+        case 19: sym_taylor2<19>(p, T, d, d1, m, L, R); break;
+        case 21: sym_taylor2<21>(p, T, d, d1, m, L, R); break;
+        case 25: sym_taylor2<25>(p, T, d, d1, m, L, R); break;
+        default: sym_taylor2<29>(p, T, d, d1, m, L, R); break;
       }
     }
     if (active) {
@@ -850,7 +857,7 @@ __global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict_
     double R[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) R[i] = 0.0;
-    // the pass's polynomial length (one of kTouchLens, chosen on the host for this mesh)
+    // the pass's polynomial length (one of kPolyLens, chosen on the host for this mesh)
     switch (tlen[d]) {
       case 5: touch_taylor<SYM, 5>(T, G, d, d1, R); break;
       case 6: touch_taylor<SYM, 6>(T, G, d, d1, R); break;
@@ -1222,10 +1229,10 @@ static void launch_sep(dim3 grid, hipStream_t s, const AsmParams *dp, const AsmP
                        const SepTasks &t, bool mixed) {
   if (mixed)
     hipLaunchKernelGGL((k_separated<TS, D, true>), grid, dim3(256), 0, s, dp, hp.geom, hp.tscale,
-                       hp.taylor, hp.taylor32, hp.tdeg, t.tasks, t.vstart, t.verts, t.slots, t.n);
+                       hp.taylor, hp.taylor32, hp.tdeg, hp.tlen_sep, t.tasks, t.vstart, t.verts, t.slots, t.n);
   else
     hipLaunchKernelGGL((k_separated<TS, D, false>), grid, dim3(256), 0, s, dp, hp.geom, hp.tscale,
-                       hp.taylor, hp.taylor32, hp.tdeg, t.tasks, t.vstart, t.verts, t.slots, t.n);
+                       hp.taylor, hp.taylor32, hp.tdeg, hp.tlen_sep, t.tasks, t.vstart, t.verts, t.slots, t.n);
 }
 
 void launch_assemble_separated(const AsmParams *dp, const AsmParams &p, const int32_t *tasks,

@@ -452,12 +452,33 @@ int build_tables(hb_ctx *c) {
   auto pass_start = [&](int d) { return d - ((d - p.dsw) & 1); };
   std::vector<double> tay((size_t)c->nt * 2 * kTaylorN, 0.0), tsc((size_t)c->nt * 3, 0.0);
   std::vector<float> tay32((size_t)c->nt * 2 * kTaylorN32, 0.0f);
-  std::vector<int32_t> tdeg((size_t)c->nt * 2, 0), tlen_touch((size_t)c->nt, 0);
-  // Touching pairs see distances rho up to the largest vertex distance of two triangles that
-  // share a vertex, so at block d their w = rho^2 c_d stays below rho_max^2 / (4 alpha d h): the
-  // terms of high power in w are negligible there, and their pass uses a shorter prefix of the
-  // same polynomial (dropped part below 1e-16 of the block scale, on top of the truncation of the
-  // series itself).
+  std::vector<int32_t> tdeg((size_t)c->nt * 2, 0), tlen_sep((size_t)c->nt, 0),
+      tlen_touch((size_t)c->nt, 0);
+  // At block d a pair at distance rho evaluates the polynomial at w = rho^2 c_d, c_d =
+  // 1 / (4 alpha d h).  Bounding rho bounds w, and where w stays small the terms of high power in
+  // w are negligible: each pass then uses the shortest prefix of the same polynomial whose
+  // dropped part stays below 1e-16 of the block scale (on top of the truncation of the series
+  // itself).  Separated pairs: rho is at most twice the largest distance of a vertex from the
+  // centre of the mesh's bounding box.  Touching pairs: rho is at most the largest vertex distance
+  // of two triangles that share a vertex.
+  ld rho2_sep = 0.0L;
+  {
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) lo[k] = hi[k] = c->verts[k];
+    for (size_t v = 0; v < c->verts.size() / 3; ++v)
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = std::min(lo[k], c->verts[3 * v + k]);
+        hi[k] = std::max(hi[k], c->verts[3 * v + k]);
+      }
+    for (size_t v = 0; v < c->verts.size() / 3; ++v) {
+      ld r2 = 0.0L;
+      for (int k = 0; k < 3; ++k) {
+        const ld x = (ld)c->verts[3 * v + k] - 0.5L * ((ld)lo[k] + hi[k]);
+        r2 += x * x;
+      }
+      rho2_sep = std::max(rho2_sep, 4.0L * r2);
+    }
+  }
   ld rho2_touch = 0.0L;
   for (const TouchPair &tp : c->touch)
     for (int i = 0; i < 3; ++i)
@@ -474,9 +495,10 @@ int build_tables(hb_ctx *c) {
     taylor_poly(1.5L, d, pv, tdeg[2 * d]);
     taylor_poly(2.5L, d, pk, tdeg[2 * d]);
     {
-      const int need = taylor_len(pv, tdeg[2 * d] + 1, rho2_touch / (4.0L * al * d * h), 1e-16L);
-      int32_t &L = tlen_touch[pass_start(d)];
-      L = std::max<int32_t>(L, need);
+      const ld cd = 1.0L / (4.0L * al * d * h);
+      int32_t &Ls = tlen_sep[pass_start(d)], &Lt = tlen_touch[pass_start(d)];
+      Ls = std::max<int32_t>(Ls, taylor_len(pv, tdeg[2 * d] + 1, rho2_sep * cd, 1e-16L));
+      Lt = std::max<int32_t>(Lt, taylor_len(pv, tdeg[2 * d] + 1, rho2_touch * cd, 1e-16L));
     }
     for (int j = 0; j < kTaylorN; ++j) {
       tay[((size_t)d * 2 + 0) * kTaylorN + j] = (double)pv[j];
@@ -498,12 +520,15 @@ int build_tables(hb_ctx *c) {
   if ((rc = upload(c, (void **)&c->d_tscale, tsc.data(), tsc.size() * sizeof(double)))) return rc;
   if ((rc = upload(c, (void **)&c->d_taylor32, tay32.data(), tay32.size() * sizeof(float)))) return rc;
   if ((rc = upload(c, (void **)&c->d_tdeg, tdeg.data(), tdeg.size() * sizeof(int32_t)))) return rc;
-  for (int32_t &L : tlen_touch) {
-    if (L == 0) continue;
-    for (int n : kTouchLens)
-      if (n >= L) { L = n; break; }
-    L = std::min<int32_t>(L, kTaylorN);
-  }
+  for (auto *tl : {&tlen_sep, &tlen_touch})
+    for (int32_t &L : *tl) {
+      if (L == 0) continue;
+      for (int n : kPolyLens)
+        if (n >= L) { L = n; break; }
+      L = std::min<int32_t>(L, kTaylorN);
+    }
+  if ((rc = upload(c, (void **)&c->d_tlen_sep, tlen_sep.data(), tlen_sep.size() * sizeof(int32_t))))
+    return rc;
   if ((rc = upload(c, (void **)&c->d_tlen_touch, tlen_touch.data(), tlen_touch.size() * sizeof(int32_t))))
     return rc;
 
@@ -654,17 +679,32 @@ int build_tables(hb_ctx *c) {
       return d < 6 ? 22 : d < 8 ? 18 : d < 12 ? 14 : d < 16 ? 12 : d < 32 ? 10 : d < 64 ? 8 : 6;
     };
     std::vector<double> d2tab((size_t)c->nt * kTaylorND, 0.0), d2sc(c->nt, 0.0);
-    std::vector<int32_t> d2len(c->nt, 0);
+    // per pass the shortest prefix for the pairs' distance bound, as for V_h and K_h above
+    std::vector<int32_t> d2len((size_t)c->nt * 2, 0);
     for (int d = kD2Closed; d < c->nt; ++d) {
       ld poly[kTaylorND];
       const int deg = d2deg(d);
-      d2len[d] = deg + 2;
       taylor_poly_odd(d, deg, poly, kTaylorND);
+      const int ps = d - ((d - kD2Closed) & 1);
+      const ld cd = 1.0L / (4.0L * al * d * h);
+      for (int t = 0; t < 2; ++t) {
+        int32_t &L = d2len[2 * ps + t];
+        L = std::max<int32_t>(L, taylor_len(poly, deg + 2, (t ? rho2_touch : rho2_sep) * cd, 1e-16L));
+      }
       for (int j = 0; j < kTaylorND; ++j) d2tab[(size_t)d * kTaylorND + j] = (double)poly[j];
       d2sc[d] = (double)(al * h * powl(4.0L * kPi * al * d * h, -1.5L));
     }
     if ((rc = upload(c, (void **)&c->d_d2tab, d2tab.data(), d2tab.size() * sizeof(double)))) return rc;
     if ((rc = upload(c, (void **)&c->d_d2scale, d2sc.data(), d2sc.size() * sizeof(double)))) return rc;
+    for (int d = kD2Closed; d < c->nt; ++d)
+      for (int t = 0; t < 2; ++t) {
+        int32_t &L = d2len[2 * d + t];
+        if (L == 0) continue;
+        const int full = d2deg(d) + 2;
+        for (int n : kD2Lens)
+          if (n >= L) { L = n; break; }
+        L = std::min(L, full);
+      }
     if ((rc = upload(c, (void **)&c->d_d2len, d2len.data(), d2len.size() * sizeof(int32_t)))) return rc;
     const size_t ne_ = c->ne;
     std::vector<double> curl(9 * ne_);
@@ -709,6 +749,7 @@ int build_tables(hb_ctx *c) {
   p.taylor = c->d_taylor;
   p.taylor32 = c->d_taylor32;
   p.tdeg = c->d_tdeg;
+  p.tlen_sep = c->d_tlen_sep;
   p.tlen_touch = c->d_tlen_touch;
   p.tscale = c->d_tscale;
   p.geom = c->d_geom;
@@ -1029,7 +1070,7 @@ void hb_destroy(hb_ctx *c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
   void *ptrs[] = {c->d_params, c->d_params_repr, c->d_geom, c->d_tris, c->d_touch, c->d_touch_list, c->d_sep_tasks, c->d_sep_vstart, c->d_sep_verts, c->d_sep_slots, c->d_taylor,
-                  c->d_taylor32, c->d_tdeg, c->d_tlen_touch, c->d_V32, c->d_tscale, c->d_mass,
+                  c->d_taylor32, c->d_tdeg, c->d_tlen_sep, c->d_tlen_touch, c->d_V32, c->d_tscale, c->d_mass,
                   c->d_V, c->d_K, c->d_KT, c->d_work, c->d_v0inv, c->d_apply, c->d_ir,
                   c->d_pc_cols, c->d_pc_cls, c->d_cent, c->d_pc_M, c->d_reprq, c->ss[1].d, c->ss[2].d, c->ss[3].d,
                   c->d_D, c->d_Dw, c->d_V11, c->d_minv, c->d_pcw, c->d_Kt, c->d_near_sep, c->d_near_touch, c->d_d2tab, c->d_d2scale, c->d_d2len, c->d_curl, c->d_vstart,

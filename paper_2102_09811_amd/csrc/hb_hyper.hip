@@ -67,7 +67,8 @@ __device__ __forceinline__ double v_closed(const AsmParams &p, double rho, int d
 // scales and w factors
 struct P1Tabs {
   const double *tscale, *d2tab, *d2scale, *taylor;
-  const int32_t *d2len, *tdeg;
+  const int32_t *d2len;                 // [nt][2]: D^{2,d} pass lengths, separated and touching
+  const int32_t *tlen_sep, *tlen_touch; // [nt]: V_h pass lengths, separated and touching
 };
 
 // ---- separated pairs ----
@@ -195,27 +196,33 @@ __device__ __forceinline__ void p1_taylor_pass(const AsmParams &p, const P1Tabs 
                                                int m, const P1Lane &L, const double *etab,
                                                double S0[3][3], double S1[3][3]) {
   if constexpr (KIND == kKindD2) {
-    switch (T.d2len[d0]) {
-      case 24: p1_taylor2<KIND, 24>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      case 20: p1_taylor2<KIND, 20>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      case 16: p1_taylor2<KIND, 16>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      case 14: p1_taylor2<KIND, 14>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      case 12: p1_taylor2<KIND, 12>(p, T, d0, d1, m, L, etab, S0, S1); break;
+    switch (T.d2len[2 * d0]) {  // one of kD2Lens
+      case 4: p1_taylor2<KIND, 4>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 6: p1_taylor2<KIND, 6>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 8: p1_taylor2<KIND, 8>(p, T, d0, d1, m, L, etab, S0, S1); break;
       case 10: p1_taylor2<KIND, 10>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      default: p1_taylor2<KIND, 8>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 12: p1_taylor2<KIND, 12>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 14: p1_taylor2<KIND, 14>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 16: p1_taylor2<KIND, 16>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 20: p1_taylor2<KIND, 20>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      default: p1_taylor2<KIND, 24>(p, T, d0, d1, m, L, etab, S0, S1); break;
     }
   } else {
-    switch (T.tdeg[2 * d0]) {
-      case 28: p1_taylor2<KIND, 29>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      case 24: p1_taylor2<KIND, 25>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      case 20: p1_taylor2<KIND, 21>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      case 18: p1_taylor2<KIND, 19>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      case 16: p1_taylor2<KIND, 17>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      case 14: p1_taylor2<KIND, 15>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      case 12: p1_taylor2<KIND, 13>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      case 10: p1_taylor2<KIND, 11>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      case 8: p1_taylor2<KIND, 9>(p, T, d0, d1, m, L, etab, S0, S1); break;
-      default: p1_taylor2<KIND, 7>(p, T, d0, d1, m, L, etab, S0, S1); break;
+    switch (T.tlen_sep[d0]) {  // one of kPolyLens
+      case 5: p1_taylor2<KIND, 5>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 6: p1_taylor2<KIND, 6>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 7: p1_taylor2<KIND, 7>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 8: p1_taylor2<KIND, 8>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 9: p1_taylor2<KIND, 9>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 10: p1_taylor2<KIND, 10>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 11: p1_taylor2<KIND, 11>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 13: p1_taylor2<KIND, 13>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 15: p1_taylor2<KIND, 15>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 17: p1_taylor2<KIND, 17>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 19: p1_taylor2<KIND, 19>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 21: p1_taylor2<KIND, 21>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      case 25: p1_taylor2<KIND, 25>(p, T, d0, d1, m, L, etab, S0, S1); break;
+      default: p1_taylor2<KIND, 29>(p, T, d0, d1, m, L, etab, S0, S1); break;
     }
   }
 }
@@ -395,29 +402,35 @@ __device__ __forceinline__ void p1_touch_dispatch(const AsmParams &p, const P1Ta
                                                   int ntab, int len, int d0, int d1,
                                                   const double *etab, double R[kP1Sums]) {
   if constexpr (KIND == kKindD2) {
-    switch (len) {
+    switch (len) {  // 0 or one of kD2Lens
       case 0: p1_touch_pass<KIND, 0>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 24: p1_touch_pass<KIND, 24>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 20: p1_touch_pass<KIND, 20>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 16: p1_touch_pass<KIND, 16>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 14: p1_touch_pass<KIND, 14>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 12: p1_touch_pass<KIND, 12>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 4: p1_touch_pass<KIND, 4>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 6: p1_touch_pass<KIND, 6>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 8: p1_touch_pass<KIND, 8>(p, T, tp, col, ntab, d0, d1, etab, R); break;
       case 10: p1_touch_pass<KIND, 10>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      default: p1_touch_pass<KIND, 8>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 12: p1_touch_pass<KIND, 12>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 14: p1_touch_pass<KIND, 14>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 16: p1_touch_pass<KIND, 16>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 20: p1_touch_pass<KIND, 20>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      default: p1_touch_pass<KIND, 24>(p, T, tp, col, ntab, d0, d1, etab, R); break;
     }
   } else {
-    switch (len) {
+    switch (len) {  // 0 or one of kPolyLens
       case 0: p1_touch_pass<KIND, 0>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 29: p1_touch_pass<KIND, 29>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 25: p1_touch_pass<KIND, 25>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 21: p1_touch_pass<KIND, 21>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 19: p1_touch_pass<KIND, 19>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 17: p1_touch_pass<KIND, 17>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 15: p1_touch_pass<KIND, 15>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 13: p1_touch_pass<KIND, 13>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 11: p1_touch_pass<KIND, 11>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 5: p1_touch_pass<KIND, 5>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 6: p1_touch_pass<KIND, 6>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 7: p1_touch_pass<KIND, 7>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 8: p1_touch_pass<KIND, 8>(p, T, tp, col, ntab, d0, d1, etab, R); break;
       case 9: p1_touch_pass<KIND, 9>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      default: p1_touch_pass<KIND, 7>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 10: p1_touch_pass<KIND, 10>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 11: p1_touch_pass<KIND, 11>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 13: p1_touch_pass<KIND, 13>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 15: p1_touch_pass<KIND, 15>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 17: p1_touch_pass<KIND, 17>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 19: p1_touch_pass<KIND, 19>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 21: p1_touch_pass<KIND, 21>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 25: p1_touch_pass<KIND, 25>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      default: p1_touch_pass<KIND, 29>(p, T, tp, col, ntab, d0, d1, etab, R); break;
     }
   }
 }
@@ -449,7 +462,7 @@ __global__ __launch_bounds__(64, 3) void k_p1_touching(const AsmParams *__restri
     const bool closed = d < nclosed;
     const int d1 = closed ? d : min(d + 1, p.nt - 1);
     const int nb = closed || d1 == d ? 1 : 2;
-    const int len = closed ? 0 : (KIND == kKindD2 ? T.d2len[d] : T.tdeg[2 * d] + 1);
+    const int len = closed ? 0 : (KIND == kKindD2 ? T.d2len[2 * d + 1] : T.tlen_touch[d]);
     double R[kP1Sums];
     p1_touch_dispatch<KIND>(p, T, tp, col, ntab, len, d, d1, etab, R);
 #pragma unroll
@@ -542,7 +555,8 @@ int assemble_p1p1(hb_ctx *c, TS *out, hipStream_t s) {
   const int nt = c->nt, nv = (int)c->nv;
   const size_t nD = (size_t)nt * nv * nv;
   TS *W = (TS *)c->d_Dw;
-  P1Tabs T{c->d_tscale, c->d_d2tab, c->d_d2scale, c->d_taylor, c->d_d2len, c->d_tdeg};
+  P1Tabs T{c->d_tscale, c->d_d2tab, c->d_d2scale, c->d_taylor, c->d_d2len, c->d_tlen_sep,
+           c->d_tlen_touch};
   if (hipMemsetAsync(W, 0, nD * sizeof(TS), s) != hipSuccess) return HB_EHIP;
   if (c->n_sep_tasks > 0)
     hipLaunchKernelGGL((k_p1_separated<KIND, TS>), dim3((unsigned)((c->n_sep_tasks + 3) / 4)),

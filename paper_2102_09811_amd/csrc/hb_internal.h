@@ -16,9 +16,11 @@ namespace hb {
 // 0 .. d_switch; later blocks use the Taylor form, whose degree falls as d grows (28 at d = 3).
 constexpr int kTaylorDeg = 28;       // largest degree of the Taylor polynomial in w = rho^2/(4 alpha d h)
 constexpr int kTaylorN = kTaylorDeg + 1;
-// Polynomial lengths the touching-pair kernel is instantiated for (ascending; the host rounds a
-// pass's length up to one of them).
-constexpr int kTouchLens[] = {5, 6, 7, 8, 9, 10, 11, 13, 15, 17, 19, 21, 25, 29};
+// Polynomial lengths the double-precision Taylor passes of k_separated and k_touching are
+// instantiated for (ascending; the host rounds a pass's length up to one of them).
+constexpr int kPolyLens[] = {5, 6, 7, 8, 9, 10, 11, 13, 15, 17, 19, 21, 25, 29};
+// The same for the odd polynomials of D^{2,d} in the hypersingular kernels.
+constexpr int kD2Lens[] = {4, 6, 8, 10, 12, 14, 16, 20, 24};
 constexpr int kTaylorDeg32 = 16;     // largest degree of the float evaluation (mixed precision)
 constexpr int kTaylorN32 = kTaylorDeg32 + 1;
 constexpr int kSeriesN = 14;         // terms of the small-z series of the brackets A(z), B(z)
@@ -56,8 +58,10 @@ struct AsmParams {
   const double *taylor;        // [nt][2][kTaylorN] Taylor polynomials in w (V, K), d >= dsw
   const float *taylor32;       // [nt][2][kTaylorN32] shorter series for the float path
   const int32_t *tdeg;         // [nt][2]: polynomial degree of block d, double and float path
-  const int32_t *tlen_touch;   // [nt]: polynomial length of the touching pairs' pass from block d
-                               // (their distances are short, so the series in w is cut earlier)
+  const int32_t *tlen_sep;     // [nt]: polynomial length of the separated pairs' pass from block d
+                               // (bounded by the mesh's extent)
+  const int32_t *tlen_touch;   // [nt]: the same for the touching pairs (their distances are short,
+                               // so the series in w is cut earlier)
   const double *tscale;        // [nt][3]: V scale, K scale, c_d = 1/(4 alpha d h)
   const double *geom;          // SoA [25][ne]: far nodes (q*3+c), normal (21..23), area (24)
   const int32_t *tris;         // [ne][3]
@@ -198,7 +202,7 @@ struct hb_ctx {
   hb::SSRule ss[4];
   double *d_taylor = nullptr, *d_tscale = nullptr;
   float *d_taylor32 = nullptr;
-  int32_t *d_tdeg = nullptr, *d_tlen_touch = nullptr;
+  int32_t *d_tdeg = nullptr, *d_tlen_sep = nullptr, *d_tlen_touch = nullptr;
   float *d_V32 = nullptr;            // float copy of V for the mixed-precision inner solver
   bool V32_valid = false;
   double *d_mass = nullptr;          // p0 x p1 mass, [ne][3] = area/3 per local vertex
@@ -223,7 +227,8 @@ struct hb_ctx {
   bool Kt_valid = false;
   double *d_d2tab = nullptr;         // [nt][kTaylorND]: odd Taylor polynomial of D^{2,d}
   double *d_d2scale = nullptr;       // [nt]: alpha h (4 pi alpha d h)^{-3/2}
-  int32_t *d_d2len = nullptr;        // [nt]: coefficients used at block d (0 below kD2Closed)
+  int32_t *d_d2len = nullptr;        // [nt][2]: coefficients used by the pass from block d,
+                                     // separated and touching pairs (0 below kD2Closed)
   double *d_curl = nullptr;          // [ne][3][3]: surface curls of the local p1 basis
   int32_t *d_vstart = nullptr;       // [nv+1] CSR vertex -> (panel, local index)
   int32_t *d_vadj = nullptr;         // [3 ne][2]
