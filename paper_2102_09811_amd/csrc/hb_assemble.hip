@@ -796,22 +796,16 @@ __device__ __forceinline__ void touch_taylor(const SepTabs &T, const TouchGroup 
   }
 }
 
+// One list entry (a wave): ent indexes pairs (SYM: ~index of a vertex pair, both orders).
 template <typename TS, int D, bool SYM>
-__global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict__ pp,
-                                                    const TouchPair *__restrict__ pairs,
-                                                    const int32_t *__restrict__ list, int nlist,
-                                                    RuleTabs rules,
-                                                    const double *__restrict__ tscale,
-                                                    const double *__restrict__ taylor,
-                                                    const int *__restrict__ tlen) {
-  const AsmParams &p = *pp;
-  __shared__ double etab[kExpTabN];
-  __shared__ __align__(16) double red[16 * kRedRow];
-  stage_exp_tab_pos(etab);
-  __syncthreads();
+__device__ __forceinline__ void touch_entry(const AsmParams &p, const TouchPair *__restrict__ pairs,
+                                            int ent, const RuleTabs &rules,
+                                            const double *__restrict__ tscale,
+                                            const double *__restrict__ taylor,
+                                            const int *__restrict__ tlen, const double *etab,
+                                            double *red) {
   const SepTabs T{nullptr, tscale, taylor, nullptr, nullptr, etab};
   TouchGroup G;
-  const int ent = __builtin_amdgcn_readfirstlane(list[blockIdx.x]);
   const TouchPair &tp = pairs[SYM ? ~ent : ent];
   G.tp = &tp;
   const int cls = tp.cls;
@@ -898,6 +892,30 @@ __global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict_
       }
     }
   }
+}
+
+// All touching pairs in one launch, one wave per list entry: the first n0 entries are identical
+// and edge-sharing pairs (one order each), the rest vertex-sharing pairs (both orders).  The
+// longest entries come first (identical pairs have the largest rule), so the short vertex-pair
+// waves fill the machine at the end instead of each class leaving its own partial last round.
+template <typename TS, int D>
+__global__ __launch_bounds__(64, 3) void k_touching(const AsmParams *__restrict__ pp,
+                                                    const TouchPair *__restrict__ pairs,
+                                                    const int32_t *__restrict__ list, int n0,
+                                                    RuleTabs rules,
+                                                    const double *__restrict__ tscale,
+                                                    const double *__restrict__ taylor,
+                                                    const int *__restrict__ tlen) {
+  const AsmParams &p = *pp;
+  __shared__ double etab[kExpTabN];
+  __shared__ __align__(16) double red[16 * kRedRow];
+  stage_exp_tab_pos(etab);
+  __syncthreads();
+  const int ent = __builtin_amdgcn_readfirstlane(list[blockIdx.x]);
+  if ((int)blockIdx.x < n0)
+    touch_entry<TS, D, false>(p, pairs, ent, rules, tscale, taylor, tlen, etab, red);
+  else
+    touch_entry<TS, D, true>(p, pairs, ent, rules, tscale, taylor, tlen, etab, red);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1295,12 +1313,9 @@ static void launch_touch(hipStream_t s, const AsmParams *dp, const AsmParams &hp
                          const TouchPair *pairs, const int32_t *list, int nlist, int nsym,
                          const RuleTabs &rule) {
   const int n0 = nlist - nsym;
-  if (n0 > 0)
-    hipLaunchKernelGGL((k_touching<TS, D, false>), dim3(n0), dim3(64), 0, s, dp, pairs, list, n0,
-                       rule, hp.tscale, hp.taylor, hp.tlen_touch);
-  if (nsym > 0)
-    hipLaunchKernelGGL((k_touching<TS, D, true>), dim3(nsym), dim3(64), 0, s, dp, pairs, list + n0,
-                       nsym, rule, hp.tscale, hp.taylor, hp.tlen_touch);
+  if (nlist > 0)
+    hipLaunchKernelGGL((k_touching<TS, D>), dim3(nlist), dim3(64), 0, s, dp, pairs, list, n0, rule,
+                       hp.tscale, hp.taylor, hp.tlen_touch);
 }
 
 void launch_assemble_touching(const AsmParams *dp, const AsmParams &p, const TouchPair *pairs,
