@@ -435,18 +435,13 @@ __device__ __forceinline__ void p1_touch_dispatch(const AsmParams &p, const P1Ta
   }
 }
 
+// One list entry (a wave): ent indexes pairs (SYM: ~index of a vertex pair, both orders).
 template <int KIND, typename TS, bool SYM>
-__global__ __launch_bounds__(64, 3) void k_p1_touching(const AsmParams *__restrict__ pp,
-                                                       const TouchPair *__restrict__ pairs,
-                                                       const int32_t *__restrict__ list,
-                                                       RuleTabs rules, P1Tabs T,
-                                                       TS *__restrict__ D) {
-  const AsmParams &p = *pp;
-  __shared__ double etab[kExpTabN];
-  __shared__ __align__(16) double red[kP1Sums * kP1RedRow];
-  stage_exp_tab_pos(etab);
-  __syncthreads();
-  const int ent = __builtin_amdgcn_readfirstlane(list[blockIdx.x]);
+__device__ __forceinline__ void p1_touch_entry(const AsmParams &p,
+                                               const TouchPair *__restrict__ pairs, int ent,
+                                               const RuleTabs &rules, const P1Tabs &T,
+                                               TS *__restrict__ D, const double *etab,
+                                               double *red) {
   const TouchPair &tp = pairs[SYM ? ~ent : ent];
   const int cls = __builtin_amdgcn_readfirstlane(tp.cls);
   const int ntab = rules.n[cls];
@@ -486,6 +481,26 @@ __global__ __launch_bounds__(64, 3) void k_p1_touching(const AsmParams *__restri
     }
     d += nb;
   }
+}
+
+// All touching pairs in one launch: the first n0 list entries one order each (identical and edge
+// pairs, the longest rules first), the rest vertex pairs for both orders.
+template <int KIND, typename TS>
+__global__ __launch_bounds__(64, 3) void k_p1_touching(const AsmParams *__restrict__ pp,
+                                                       const TouchPair *__restrict__ pairs,
+                                                       const int32_t *__restrict__ list, int n0,
+                                                       RuleTabs rules, P1Tabs T,
+                                                       TS *__restrict__ D) {
+  const AsmParams &p = *pp;
+  __shared__ double etab[kExpTabN];
+  __shared__ __align__(16) double red[kP1Sums * kP1RedRow];
+  stage_exp_tab_pos(etab);
+  __syncthreads();
+  const int ent = __builtin_amdgcn_readfirstlane(list[blockIdx.x]);
+  if ((int)blockIdx.x < n0)
+    p1_touch_entry<KIND, TS, false>(p, pairs, ent, rules, T, D, etab, red);
+  else
+    p1_touch_entry<KIND, TS, true>(p, pairs, ent, rules, T, D, etab, red);
 }
 
 // D[d][i][j] += alpha^2 sum_{(n, a) at i} sum_{(m, b) at j} curl_a(n) . curl_b(m) V[d][n][m]
@@ -572,12 +587,8 @@ int assemble_p1p1(hb_ctx *c, TS *out, hipStream_t s) {
     }
     // the touching list: identical and edge pairs of both orders, then the vertex pairs once
     const int nsym = (int)c->n_touch_sym, n0 = (int)c->n_touch_list - nsym;
-    if (n0 > 0)
-      hipLaunchKernelGGL((k_p1_touching<KIND, TS, false>), dim3((unsigned)n0), dim3(64), 0, s,
-                         c->d_params, c->d_touch, c->d_touch_list, rt, T, out);
-    if (nsym > 0)
-      hipLaunchKernelGGL((k_p1_touching<KIND, TS, true>), dim3((unsigned)nsym), dim3(64), 0, s,
-                         c->d_params, c->d_touch, c->d_touch_list + n0, rt, T, out);
+    hipLaunchKernelGGL((k_p1_touching<KIND, TS>), dim3((unsigned)c->n_touch_list), dim3(64), 0, s,
+                       c->d_params, c->d_touch, c->d_touch_list, n0, rt, T, out);
   }
   return hipGetLastError() == hipSuccess ? HB_OK : HB_EHIP;
 }
