@@ -605,7 +605,10 @@ __device__ __forceinline__ double group_sum(double v) {
 }
 
 // One rule point of a touching pair: r from the edge-vector form, the trial normal product and
-// p1 basis, and with SYM those of the order (m, l) as well.
+// p1 basis, and with SYM those of the order (m, l) as well.  SYM entries are vertex pairs, whose
+// rule stores the reference coordinates themselves, c = (x1, x2, -y1, -y2): both barycentric
+// triples follow from them, (1 - y1, y1 - y2, y2) and (1 - x1, x1 - x2, x2), instead of being
+// loaded (5 table reads per point instead of 11).
 template <bool SYM>
 struct TouchPt {
   double rho2, W, wrn1, wrn2, l[3], lx[3];
@@ -615,23 +618,35 @@ template <bool SYM>
 __device__ __forceinline__ TouchPt<SYM> touch_pt(const TouchPair &tp, const double nl[3],
                                                  const RuleCols &col, unsigned q) {
   const unsigned off = 8u * q;
-  const double a1 = col.at(0, off), a2 = col.at(1, off), a3 = col.at(2, off), a4 = col.at(3, off);
-  const double rx = a1 * tp.E1[0] + a2 * tp.E2[0] + a3 * tp.F1[0] + a4 * tp.F2[0];
-  const double ry = a1 * tp.E1[1] + a2 * tp.E2[1] + a3 * tp.F1[1] + a4 * tp.F2[1];
-  const double rz = a1 * tp.E1[2] + a2 * tp.E2[2] + a3 * tp.F1[2] + a4 * tp.F2[2];
+  // the third coordinate is zero in the identical and edge rules (the other entries)
+  const double a1 = col.at(0, off), a2 = col.at(1, off), a3 = SYM ? col.at(2, off) : 0.0,
+               a4 = col.at(3, off);
+  double rx = a1 * tp.E1[0] + a2 * tp.E2[0], ry = a1 * tp.E1[1] + a2 * tp.E2[1],
+         rz = a1 * tp.E1[2] + a2 * tp.E2[2];
+  if constexpr (SYM) {
+    rx += a3 * tp.F1[0];
+    ry += a3 * tp.F1[1];
+    rz += a3 * tp.F1[2];
+  }
+  rx += a4 * tp.F2[0];
+  ry += a4 * tp.F2[1];
+  rz += a4 * tp.F2[2];
   TouchPt<SYM> t;
   t.rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
   t.W = col.at(4, off);
   t.wrn1 = t.W * fma(rx, tp.n[0], fma(ry, tp.n[1], rz * tp.n[2]));
-  t.l[0] = col.at(5, off);
-  t.l[1] = col.at(6, off);
-  t.l[2] = col.at(7, off);
   if constexpr (SYM) {
+    t.l[0] = 1.0 + a3;
+    t.l[1] = a4 - a3;
+    t.l[2] = -a4;
     t.wrn2 = -t.W * fma(rx, nl[0], fma(ry, nl[1], rz * nl[2]));
-    t.lx[0] = col.at(8, off);
-    t.lx[1] = col.at(9, off);
-    t.lx[2] = col.at(10, off);
+    t.lx[0] = 1.0 - a1;
+    t.lx[1] = a1 - a2;
+    t.lx[2] = a2;
   } else {
+    t.l[0] = col.at(5, off);
+    t.l[1] = col.at(6, off);
+    t.l[2] = col.at(7, off);
     t.wrn2 = 0.0;
     t.lx[0] = t.lx[1] = t.lx[2] = 0.0;
   }
