@@ -616,11 +616,12 @@ struct TouchPt {
 
 template <bool SYM>
 __device__ __forceinline__ TouchPt<SYM> touch_pt(const TouchPair &tp, const double nl[3],
-                                                 const RuleCols &col, unsigned q) {
+                                                 const RuleCols &col, int cls, unsigned q) {
   const unsigned off = 8u * q;
-  // the third coordinate is zero in the identical and edge rules (the other entries)
+  // the third coordinate is zero in the identical and edge rules (the other entries), the
+  // fourth in the identical rule; the edge rule's fourth is -y2, minus the last trial barycentric
   const double a1 = col.at(0, off), a2 = col.at(1, off), a3 = SYM ? col.at(2, off) : 0.0,
-               a4 = col.at(3, off);
+               a4 = (!SYM && cls == 3) ? 0.0 : col.at(3, off);
   double rx = a1 * tp.E1[0] + a2 * tp.E2[0], ry = a1 * tp.E1[1] + a2 * tp.E2[1],
          rz = a1 * tp.E1[2] + a2 * tp.E2[2];
   if constexpr (SYM) {
@@ -646,7 +647,7 @@ __device__ __forceinline__ TouchPt<SYM> touch_pt(const TouchPair &tp, const doub
   } else {
     t.l[0] = col.at(5, off);
     t.l[1] = col.at(6, off);
-    t.l[2] = col.at(7, off);
+    t.l[2] = cls == 2 ? -a4 : col.at(7, off);
     t.wrn2 = 0.0;
     t.lx[0] = t.lx[1] = t.lx[2] = 0.0;
   }
@@ -657,7 +658,7 @@ __device__ __forceinline__ TouchPt<SYM> touch_pt(const TouchPair &tp, const doub
 struct TouchGroup {
   const TouchPair *tp;
   RuleCols col;
-  int ntab, gl, l, m;
+  int cls, ntab, gl, l, m;
   int vtx[3], vtxl[3];
   double nl[3], scale;
 };
@@ -675,7 +676,7 @@ __device__ __forceinline__ void touch_closed(const AsmParams &p, const TouchGrou
   if constexpr (I0 <= D) {
 #pragma unroll 1
     for (int q = threadIdx.x; q < G.ntab; q += 64) {
-      const TouchPt<SYM> t = touch_pt<SYM>(*G.tp, G.nl, G.col, q);
+      const TouchPt<SYM> t = touch_pt<SYM>(*G.tp, G.nl, G.col, G.cls, q);
       const double rho = sqrt(t.rho2), inv_rho = 1.0 / rho;
       if constexpr (I0 == 0) {
         sV = fma(t.W, inv_rho, sV);
@@ -785,7 +786,7 @@ __device__ __forceinline__ void touch_taylor(const SepTabs &T, const TouchGroup 
   const double *cv1 = T.taylor + (size_t)(2 * d1) * kTaylorN;
 #pragma unroll 1
   for (int q = G.gl; q < G.ntab; q += 64) {
-    const TouchPt<SYM> t = touch_pt<SYM>(*G.tp, G.nl, G.col, q);
+    const TouchPt<SYM> t = touch_pt<SYM>(*G.tp, G.nl, G.col, G.cls, q);
     const double w0 = t.rho2 * c0, w1 = t.rho2 * c1;
     const double e0 = exp_neg_m(w0, T.etab), e1 = exp_neg_m(w1, T.etab);
     double p0, dp0, p1, dp1;
@@ -823,7 +824,8 @@ __device__ __forceinline__ void touch_entry(const AsmParams &p, const TouchPair 
   TouchGroup G;
   const TouchPair &tp = pairs[SYM ? ~ent : ent];
   G.tp = &tp;
-  const int cls = tp.cls;
+  const int cls = __builtin_amdgcn_readfirstlane(tp.cls);
+  G.cls = cls;
   G.ntab = rules.n[cls];
   G.col = RuleCols(rules.d[cls], G.ntab);
   G.gl = threadIdx.x;
