@@ -345,8 +345,8 @@ constexpr int kP1RedRow = 66;  // LDS row of one sum's partial sums (padded agai
 
 template <int KIND, int N>  // N = 0: block d0 in closed form (d1 unused)
 __device__ __forceinline__ void p1_touch_pass(const AsmParams &p, const P1Tabs &T,
-                                              const TouchPair &tp, const RuleCols &col, int ntab,
-                                              int d0, int d1, const double *etab,
+                                              const TouchPair &tp, const RuleCols &col, int cls,
+                                              int ntab, int d0, int d1, const double *etab,
                                               double R[kP1Sums]) {
   double cw0 = 0.0, sc0 = 1.0, cw1 = 0.0, sc1 = 1.0, r2max = 0.0;
   const double *c0 = nullptr, *c1 = nullptr;
@@ -360,14 +360,32 @@ __device__ __forceinline__ void p1_touch_pass(const AsmParams &p, const P1Tabs &
 #pragma unroll 1
   for (int q = threadIdx.x; q < ntab; q += 64) {
     const unsigned off = 8u * q;
-    const double a1 = col.at(0, off), a2 = col.at(1, off), a3 = col.at(2, off), a4 = col.at(3, off);
+    // (cls is uniform) the vertex rule stores the reference coordinates c = (x1, x2, -y1, -y2),
+    // from which both barycentric triples follow; the identical rule's third and fourth and the
+    // edge rule's third coordinate are zero, and the edge rule's fourth is -y2
+    const double a1 = col.at(0, off), a2 = col.at(1, off);
+    const double a3 = cls == 1 ? col.at(2, off) : 0.0, a4 = cls == 3 ? 0.0 : col.at(3, off);
     const double rx = a1 * tp.E1[0] + a2 * tp.E2[0] + a3 * tp.F1[0] + a4 * tp.F2[0];
     const double ry = a1 * tp.E1[1] + a2 * tp.E2[1] + a3 * tp.F1[1] + a4 * tp.F2[1];
     const double rz = a1 * tp.E1[2] + a2 * tp.E2[2] + a3 * tp.F1[2] + a4 * tp.F2[2];
     const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
     const double W = col.at(4, off);
-    const double ly[3] = {col.at(5, off), col.at(6, off), col.at(7, off)};
-    const double lx[3] = {col.at(8, off), col.at(9, off), col.at(10, off)};
+    double ly[3], lx[3];
+    if (cls == 1) {
+      ly[0] = 1.0 + a3;
+      ly[1] = a4 - a3;
+      ly[2] = -a4;
+      lx[0] = 1.0 - a1;
+      lx[1] = a1 - a2;
+      lx[2] = a2;
+    } else {
+      ly[0] = col.at(5, off);
+      ly[1] = col.at(6, off);
+      ly[2] = cls == 2 ? -a4 : col.at(7, off);
+      lx[0] = col.at(8, off);
+      lx[1] = col.at(9, off);
+      lx[2] = col.at(10, off);
+    }
     double k0, k1 = 0.0;
     if constexpr (N == 0) {
       const double rho = sqrt(rho2);
@@ -399,38 +417,38 @@ __device__ __forceinline__ void p1_touch_pass(const AsmParams &p, const P1Tabs &
 template <int KIND>
 __device__ __forceinline__ void p1_touch_dispatch(const AsmParams &p, const P1Tabs &T,
                                                   const TouchPair &tp, const RuleCols &col,
-                                                  int ntab, int len, int d0, int d1,
+                                                  int cls, int ntab, int len, int d0, int d1,
                                                   const double *etab, double R[kP1Sums]) {
   if constexpr (KIND == kKindD2) {
     switch (len) {  // 0 or one of kD2Lens
-      case 0: p1_touch_pass<KIND, 0>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 4: p1_touch_pass<KIND, 4>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 6: p1_touch_pass<KIND, 6>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 8: p1_touch_pass<KIND, 8>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 10: p1_touch_pass<KIND, 10>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 12: p1_touch_pass<KIND, 12>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 14: p1_touch_pass<KIND, 14>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 16: p1_touch_pass<KIND, 16>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 20: p1_touch_pass<KIND, 20>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      default: p1_touch_pass<KIND, 24>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 0: p1_touch_pass<KIND, 0>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 4: p1_touch_pass<KIND, 4>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 6: p1_touch_pass<KIND, 6>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 8: p1_touch_pass<KIND, 8>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 10: p1_touch_pass<KIND, 10>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 12: p1_touch_pass<KIND, 12>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 14: p1_touch_pass<KIND, 14>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 16: p1_touch_pass<KIND, 16>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 20: p1_touch_pass<KIND, 20>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      default: p1_touch_pass<KIND, 24>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
     }
   } else {
     switch (len) {  // 0 or one of kPolyLens
-      case 0: p1_touch_pass<KIND, 0>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 5: p1_touch_pass<KIND, 5>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 6: p1_touch_pass<KIND, 6>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 7: p1_touch_pass<KIND, 7>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 8: p1_touch_pass<KIND, 8>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 9: p1_touch_pass<KIND, 9>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 10: p1_touch_pass<KIND, 10>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 11: p1_touch_pass<KIND, 11>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 13: p1_touch_pass<KIND, 13>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 15: p1_touch_pass<KIND, 15>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 17: p1_touch_pass<KIND, 17>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 19: p1_touch_pass<KIND, 19>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 21: p1_touch_pass<KIND, 21>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      case 25: p1_touch_pass<KIND, 25>(p, T, tp, col, ntab, d0, d1, etab, R); break;
-      default: p1_touch_pass<KIND, 29>(p, T, tp, col, ntab, d0, d1, etab, R); break;
+      case 0: p1_touch_pass<KIND, 0>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 5: p1_touch_pass<KIND, 5>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 6: p1_touch_pass<KIND, 6>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 7: p1_touch_pass<KIND, 7>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 8: p1_touch_pass<KIND, 8>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 9: p1_touch_pass<KIND, 9>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 10: p1_touch_pass<KIND, 10>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 11: p1_touch_pass<KIND, 11>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 13: p1_touch_pass<KIND, 13>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 15: p1_touch_pass<KIND, 15>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 17: p1_touch_pass<KIND, 17>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 19: p1_touch_pass<KIND, 19>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 21: p1_touch_pass<KIND, 21>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      case 25: p1_touch_pass<KIND, 25>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
+      default: p1_touch_pass<KIND, 29>(p, T, tp, col, cls, ntab, d0, d1, etab, R); break;
     }
   }
 }
@@ -459,7 +477,7 @@ __device__ __forceinline__ void p1_touch_entry(const AsmParams &p,
     const int nb = closed || d1 == d ? 1 : 2;
     const int len = closed ? 0 : (KIND == kKindD2 ? T.d2len[2 * d + 1] : T.tlen_touch[d]);
     double R[kP1Sums];
-    p1_touch_dispatch<KIND>(p, T, tp, col, ntab, len, d, d1, etab, R);
+    p1_touch_dispatch<KIND>(p, T, tp, col, cls, ntab, len, d, d1, etab, R);
 #pragma unroll
     for (int i = 0; i < kP1Sums; ++i) red[i * kP1RedRow + lane] = R[i];
     __syncthreads();
