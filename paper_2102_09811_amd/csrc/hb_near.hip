@@ -33,7 +33,7 @@ __device__ __forceinline__ void vk_value(const AsmParams &p, double rho2, int d,
     }
   } else {
     const double w = rho2 * tscale[3 * d + 2];
-    const double e = exp_neg_t(w, etab);
+    const double e = exp_neg_m(w, etab);
     const double *cv = taylor + (size_t)(2 * d) * kTaylorN;
     v = tscale[3 * d] * e * horner<N>(cv, w);
     krn = tscale[3 * d + 1] * e * horner<N>(cv + kTaylorN, w);
@@ -69,9 +69,31 @@ __device__ __forceinline__ void near_sep_block(const AsmParams &p, int l, int m,
   }
 }
 
+// Rule point q of class cls (uniform): the reference coordinates and the trial barycentrics.  The
+// vertex rule stores the coordinates c = (x1, x2, -y1, -y2) themselves, so its barycentrics
+// (1 - y1, y1 - y2, y2) follow from them; the identical rule's third and fourth and the edge
+// rule's third coordinate are zero, and the edge rule's fourth is -y2.
+__device__ __forceinline__ void rule_entries(const double *__restrict__ tab, int ntab, int cls,
+                                             int q, double &a1, double &a2, double &a3, double &a4,
+                                             double &b0, double &b1, double &b2) {
+  a1 = tab[q];
+  a2 = tab[ntab + q];
+  a3 = cls == 1 ? tab[2 * ntab + q] : 0.0;
+  a4 = cls == 3 ? 0.0 : tab[3 * ntab + q];
+  if (cls == 1) {
+    b0 = 1.0 + a3;
+    b1 = a4 - a3;
+    b2 = -a4;
+  } else {
+    b0 = tab[5 * ntab + q];
+    b1 = tab[6 * ntab + q];
+    b2 = cls == 2 ? -a4 : tab[7 * ntab + q];
+  }
+}
+
 template <int N>
 __device__ __forceinline__ void near_touch_block(const AsmParams &p, const TouchPair &tp,
-                                                 const double *__restrict__ tab, int ntab,
+                                                 const double *__restrict__ tab, int ntab, int cls,
                                                  int lane, int d, const double *tscale,
                                                  const double *taylor, const double *etab,
                                                  double &V, double K[3]) {
@@ -79,7 +101,8 @@ __device__ __forceinline__ void near_touch_block(const AsmParams &p, const Touch
   K[0] = K[1] = K[2] = 0.0;
 #pragma unroll 1
   for (int q = lane; q < ntab; q += 64) {
-    const double a1 = tab[q], a2 = tab[ntab + q], a3 = tab[2 * ntab + q], a4 = tab[3 * ntab + q];
+    double a1, a2, a3, a4, b0, b1, b2;
+    rule_entries(tab, ntab, cls, q, a1, a2, a3, a4, b0, b1, b2);
     const double rx = a1 * tp.E1[0] + a2 * tp.E2[0] + a3 * tp.F1[0] + a4 * tp.F2[0];
     const double ry = a1 * tp.E1[1] + a2 * tp.E2[1] + a3 * tp.F1[1] + a4 * tp.F2[1];
     const double rz = a1 * tp.E1[2] + a2 * tp.E2[2] + a3 * tp.F1[2] + a4 * tp.F2[2];
@@ -88,9 +111,9 @@ __device__ __forceinline__ void near_touch_block(const AsmParams &p, const Touch
     const double W = tab[4 * ntab + q];
     V = fma(W, v, V);
     const double u = W * krn * fma(rx, tp.n[0], fma(ry, tp.n[1], rz * tp.n[2]));
-    K[0] = fma(u, tab[5 * ntab + q], K[0]);
-    K[1] = fma(u, tab[6 * ntab + q], K[1]);
-    K[2] = fma(u, tab[7 * ntab + q], K[2]);
+    K[0] = fma(u, b0, K[0]);
+    K[1] = fma(u, b1, K[1]);
+    K[2] = fma(u, b2, K[2]);
   }
 }
 
@@ -98,7 +121,7 @@ __device__ __forceinline__ void near_touch_block(const AsmParams &p, const Touch
 // points, sharing the geometry, the weights and the basis values
 template <int N>
 __device__ __forceinline__ void near_touch_block2(const AsmParams &p, const TouchPair &tp,
-                                                  const double *__restrict__ tab, int ntab,
+                                                  const double *__restrict__ tab, int ntab, int cls,
                                                   int lane, int d, const double *tscale,
                                                   const double *taylor, const double *etab,
                                                   double (&V)[2], double (&K)[2][3]) {
@@ -106,14 +129,14 @@ __device__ __forceinline__ void near_touch_block2(const AsmParams &p, const Touc
   for (int b = 0; b < 2; ++b) V[b] = K[b][0] = K[b][1] = K[b][2] = 0.0;
 #pragma unroll 1
   for (int q = lane; q < ntab; q += 64) {
-    const double a1 = tab[q], a2 = tab[ntab + q], a3 = tab[2 * ntab + q], a4 = tab[3 * ntab + q];
+    double a1, a2, a3, a4, b0, b1, b2;
+    rule_entries(tab, ntab, cls, q, a1, a2, a3, a4, b0, b1, b2);
     const double rx = a1 * tp.E1[0] + a2 * tp.E2[0] + a3 * tp.F1[0] + a4 * tp.F2[0];
     const double ry = a1 * tp.E1[1] + a2 * tp.E2[1] + a3 * tp.F1[1] + a4 * tp.F2[1];
     const double rz = a1 * tp.E1[2] + a2 * tp.E2[2] + a3 * tp.F1[2] + a4 * tp.F2[2];
     const double rho2 = fma(rx, rx, fma(ry, ry, rz * rz));
     const double W = tab[4 * ntab + q];
     const double rn = fma(rx, tp.n[0], fma(ry, tp.n[1], rz * tp.n[2]));
-    const double b0 = tab[5 * ntab + q], b1 = tab[6 * ntab + q], b2 = tab[7 * ntab + q];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       double v, krn;
@@ -127,33 +150,38 @@ __device__ __forceinline__ void near_touch_block2(const AsmParams &p, const Touc
   }
 }
 
-// Block d dispatched to the Taylor length of its table (0: closed form)
-#define HB_NEAR_DISPATCH(CALL)                                  \
-  switch (d < p.dsw ? 0 : tdeg[2 * d] + 1) {                    \
-    case 0: CALL(0); break;                                     \
-    case 29: CALL(29); break;                                   \
-    case 25: CALL(25); break;                                   \
-    case 21: CALL(21); break;                                   \
-    case 19: CALL(19); break;                                   \
-    case 17: CALL(17); break;                                   \
-    case 15: CALL(15); break;                                   \
-    case 13: CALL(13); break;                                   \
-    case 11: CALL(11); break;                                   \
-    case 9: CALL(9); break;                                     \
-    default: CALL(7); break;                                    \
+// Block d dispatched to the polynomial length of its pass (0: closed form; tlen: the pair class's
+// distance-bounded lengths, one of kPolyLens, indexed by the first block of the pass)
+#define HB_NEAR_DISPATCH(CALL)                                           \
+  switch (d < p.dsw ? 0 : tlen[d - ((d - p.dsw) & 1)]) {                \
+    case 0: CALL(0); break;                                              \
+    case 5: CALL(5); break;                                              \
+    case 6: CALL(6); break;                                              \
+    case 7: CALL(7); break;                                              \
+    case 8: CALL(8); break;                                              \
+    case 9: CALL(9); break;                                              \
+    case 10: CALL(10); break;                                            \
+    case 11: CALL(11); break;                                            \
+    case 13: CALL(13); break;                                            \
+    case 15: CALL(15); break;                                            \
+    case 17: CALL(17); break;                                            \
+    case 19: CALL(19); break;                                            \
+    case 21: CALL(21); break;                                            \
+    case 25: CALL(25); break;                                            \
+    default: CALL(29); break;                                            \
   }
 
 // one lane per separated near pair (l, m) = sep[e] -> entry index ent[e]
 __global__ __launch_bounds__(256) void k_near_separated(const AsmParams *__restrict__ pp,
                                                         const double *__restrict__ tscale,
                                                         const double *__restrict__ taylor,
-                                                        const int32_t *__restrict__ tdeg,
+                                                        const int32_t *__restrict__ tlen,
                                                         const int32_t *__restrict__ sep, int nsep,
                                                         int64_t nnz, double *__restrict__ Vn,
                                                         double *__restrict__ Kn) {
   const AsmParams &p = *pp;
-  __shared__ double etab[64];
-  stage_exp_tab(etab);
+  __shared__ double etab[kExpTabN];
+  stage_exp_tab_pos(etab);
   __syncthreads();
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= nsep) return;
@@ -185,13 +213,13 @@ __global__ __launch_bounds__(64) void k_near_touching(const AsmParams *__restric
                                                       RuleTabs rules,
                                                       const double *__restrict__ tscale,
                                                       const double *__restrict__ taylor,
-                                                      const int32_t *__restrict__ tdeg,
+                                                      const int32_t *__restrict__ tlen,
                                                       const int32_t *__restrict__ tch,
                                                       int64_t nnz, double *__restrict__ Vn,
                                                       double *__restrict__ Kn) {
   const AsmParams &p = *pp;
-  __shared__ double etab[64];
-  stage_exp_tab(etab);
+  __shared__ double etab[kExpTabN];
+  stage_exp_tab_pos(etab);
   __syncthreads();
   const int32_t *t = tch + 5 * blockIdx.x;
   const TouchPair &tp = pairs[t[0]];
@@ -203,7 +231,7 @@ __global__ __launch_bounds__(64) void k_near_touching(const AsmParams *__restric
     if (d >= p.dsw && d + 1 < p.nt) {
       // Taylor blocks d, d + 1 (d - dsw even: one pass, one polynomial length)
       double V[2], K[2][3];
-#define HB_CALL(N_) near_touch_block2<N_>(p, tp, tab, ntab, lane, d, tscale, taylor, etab, V, K)
+#define HB_CALL(N_) near_touch_block2<N_>(p, tp, tab, ntab, cls, lane, d, tscale, taylor, etab, V, K)
       HB_NEAR_DISPATCH(HB_CALL)
 #undef HB_CALL
 #pragma unroll
@@ -226,7 +254,7 @@ __global__ __launch_bounds__(64) void k_near_touching(const AsmParams *__restric
       continue;
     }
     double V, K[3];
-#define HB_CALL(N_) near_touch_block<N_>(p, tp, tab, ntab, lane, d, tscale, taylor, etab, V, K)
+#define HB_CALL(N_) near_touch_block<N_>(p, tp, tab, ntab, cls, lane, d, tscale, taylor, etab, V, K)
     HB_NEAR_DISPATCH(HB_CALL)
 #undef HB_CALL
     V = wsum(V);
@@ -248,7 +276,7 @@ __global__ __launch_bounds__(64) void k_near_touching(const AsmParams *__restric
 int launch_assemble_near(hb_ctx *c, double *V, double *K, hipStream_t s) {
   if (c->near_nsep > 0)
     hipLaunchKernelGGL(k_near_separated, dim3((unsigned)((c->near_nsep + 255) / 256)), dim3(256), 0,
-                       s, c->d_params, c->d_tscale, c->d_taylor, c->d_tdeg, c->d_near_sep,
+                       s, c->d_params, c->d_tscale, c->d_taylor, c->d_tlen_sep, c->d_near_sep,
                        (int)c->near_nsep, c->near_nnz, V, K);
   if (c->near_ntouch > 0) {
     RuleTabs rt{};
@@ -257,7 +285,7 @@ int launch_assemble_near(hb_ctx *c, double *V, double *K, hipStream_t s) {
       rt.n[k] = c->ss[k].n;
     }
     hipLaunchKernelGGL(k_near_touching, dim3((unsigned)c->near_ntouch), dim3(64), 0, s,
-                       c->d_params, c->d_touch, rt, c->d_tscale, c->d_taylor, c->d_tdeg,
+                       c->d_params, c->d_touch, rt, c->d_tscale, c->d_taylor, c->d_tlen_touch,
                        c->d_near_touch, c->near_nnz, V, K);
   }
   return hipGetLastError() == hipSuccess ? HB_OK : HB_EHIP;
