@@ -970,17 +970,21 @@ __device__ __forceinline__ void nu_closed_point(const AsmParams &p, const NuClos
 // separated pair, with the polynomial length of entry b.
 __device__ __forceinline__ void nu_sym_taylor(const AsmParams &p, const SepTabs &T, int b, int b1,
                                               int m, const SepLane &L, TaylorSums &R) {
-  switch (T.tdeg[2 * b]) {
-    case 28: sym_taylor2<29, true>(p, T, b, b1, m, L, R); break;
-    case 24: sym_taylor2<25, true>(p, T, b, b1, m, L, R); break;
-    case 20: sym_taylor2<21, true>(p, T, b, b1, m, L, R); break;
-    case 18: sym_taylor2<19, true>(p, T, b, b1, m, L, R); break;
-    case 16: sym_taylor2<17, true>(p, T, b, b1, m, L, R); break;
-    case 14: sym_taylor2<15, true>(p, T, b, b1, m, L, R); break;
-    case 12: sym_taylor2<13, true>(p, T, b, b1, m, L, R); break;
-    case 10: sym_taylor2<11, true>(p, T, b, b1, m, L, R); break;
-    case 8: sym_taylor2<9, true>(p, T, b, b1, m, L, R); break;
-    default: sym_taylor2<7, true>(p, T, b, b1, m, L, R); break;
+  switch (T.tdeg[2 * b]) {  // the pass's length for separated pairs, one of kPolyLens
+    case 5: sym_taylor2<5, true>(p, T, b, b1, m, L, R); break;
+    case 6: sym_taylor2<6, true>(p, T, b, b1, m, L, R); break;
+    case 7: sym_taylor2<7, true>(p, T, b, b1, m, L, R); break;
+    case 8: sym_taylor2<8, true>(p, T, b, b1, m, L, R); break;
+    case 9: sym_taylor2<9, true>(p, T, b, b1, m, L, R); break;
+    case 10: sym_taylor2<10, true>(p, T, b, b1, m, L, R); break;
+    case 11: sym_taylor2<11, true>(p, T, b, b1, m, L, R); break;
+    case 13: sym_taylor2<13, true>(p, T, b, b1, m, L, R); break;
+    case 15: sym_taylor2<15, true>(p, T, b, b1, m, L, R); break;
+    case 17: sym_taylor2<17, true>(p, T, b, b1, m, L, R); break;
+    case 19: sym_taylor2<19, true>(p, T, b, b1, m, L, R); break;
+    case 21: sym_taylor2<21, true>(p, T, b, b1, m, L, R); break;
+    case 25: sym_taylor2<25, true>(p, T, b, b1, m, L, R); break;
+    default: sym_taylor2<29, true>(p, T, b, b1, m, L, R); break;
   }
 }
 
@@ -1200,17 +1204,21 @@ __global__ __launch_bounds__(64, 3) void k_nu_touching(const AsmParams *__restri
 #pragma unroll
       for (int k = 0; k < 3; ++k) R.K1[j][k] = 0.0;
     }
-    switch (T.tdeg[2 * b]) {
-      case 28: touch_taylor2<29>(p, T, tp, tab, ntab, lane, b, b1, R); break;
-      case 24: touch_taylor2<25>(p, T, tp, tab, ntab, lane, b, b1, R); break;
-      case 20: touch_taylor2<21>(p, T, tp, tab, ntab, lane, b, b1, R); break;
-      case 18: touch_taylor2<19>(p, T, tp, tab, ntab, lane, b, b1, R); break;
-      case 16: touch_taylor2<17>(p, T, tp, tab, ntab, lane, b, b1, R); break;
-      case 14: touch_taylor2<15>(p, T, tp, tab, ntab, lane, b, b1, R); break;
-      case 12: touch_taylor2<13>(p, T, tp, tab, ntab, lane, b, b1, R); break;
-      case 10: touch_taylor2<11>(p, T, tp, tab, ntab, lane, b, b1, R); break;
-      case 8: touch_taylor2<9>(p, T, tp, tab, ntab, lane, b, b1, R); break;
-      default: touch_taylor2<7>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+    switch (T.tdeg[2 * b + 1]) {  // the pass's length for touching pairs, one of kPolyLens
+      case 5: touch_taylor2<5>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 6: touch_taylor2<6>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 7: touch_taylor2<7>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 8: touch_taylor2<8>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 9: touch_taylor2<9>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 10: touch_taylor2<10>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 11: touch_taylor2<11>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 13: touch_taylor2<13>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 15: touch_taylor2<15>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 17: touch_taylor2<17>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 19: touch_taylor2<19>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 21: touch_taylor2<21>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      case 25: touch_taylor2<25>(p, T, tp, tab, ntab, lane, b, b1, R); break;
+      default: touch_taylor2<29>(p, T, tp, tab, ntab, lane, b, b1, R); break;
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {

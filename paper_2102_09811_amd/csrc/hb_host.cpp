@@ -488,6 +488,8 @@ int build_tables(hb_ctx *c) {
         for (int k = 0; k < 3; ++k) r2 += ((ld)x[k] - y[k]) * ((ld)x[k] - y[k]);
         rho2_touch = std::max(rho2_touch, r2);
       }
+  c->rho2_sep = (double)rho2_sep;
+  c->rho2_touch = (double)rho2_touch;
   for (int d = std::max(1, p.dsw); d < c->nt; ++d) {
     ld pv[kTaylorN], pk[kTaylorN];
     tdeg[2 * d] = deg64(pass_start(d));
@@ -924,15 +926,33 @@ int build_nu_tables(hb_ctx *c) {
         for (size_t q = 0; q < B.Q[v][2 * j].size() && (int)q < kTaylorN; ++q) poly[q] += f[j] * B.Q[v][2 * j][q];
       // normalised so that the scale below carries the mass a b (f[0] = 1)
       for (int j = 0; j < kTaylorN; ++j) tab[(b * 2 + v) * kTaylorN + j] = (double)poly[j];
+      // the pass's lengths for the two pair classes' distance bounds, as on uniform grids (the
+      // double layer takes P - P' of the single layer's polynomial, v = 0)
+      if (v == 0) {
+        const ld cw = 1.0L / (4.0L * al * e.cc);
+        const size_t b0 = b - (b & 1);
+        tdeg[2 * b0] = std::max<int32_t>(tdeg[2 * b0], taylor_len(poly, deg + 1, (ld)c->rho2_sep * cw, 1e-16L));
+        tdeg[2 * b0 + 1] =
+            std::max<int32_t>(tdeg[2 * b0 + 1], taylor_len(poly, deg + 1, (ld)c->rho2_touch * cw, 1e-16L));
+      }
     }
     const ld mu0 = e.a * e.b;
     tsc[3 * b + 0] = (double)(mu0 * powl(4.0L * kPi * al * e.cc, -1.5L));
     tsc[3 * b + 1] = (double)(mu0 / (16.0L * powl(kPi * al, 1.5L) * powl(e.cc, 2.5L)));
     tsc[3 * b + 2] = (double)(1.0L / (4.0L * al * e.cc));
-    tdeg[2 * b] = deg;
-    tdeg[2 * b + 1] = deg;
     tout[b] = e.out;
   }
+  // round each pass's lengths up to an instantiated one (never past the first entry's degree + 1)
+  // and give both entries of the pass the same values
+  for (size_t b = 0; b < nT; b += 2)
+    for (int t = 0; t < 2; ++t) {
+      int32_t L = tdeg[2 * b + t];
+      for (int n : kPolyLens)
+        if (n >= L) { L = n; break; }
+      L = std::min<int32_t>(L, tay[b].deg + 1);
+      tdeg[2 * b + t] = L;
+      if (b + 1 < nT) tdeg[2 * (b + 1) + t] = L;
+    }
   std::vector<double> hs(nt);
   for (int k = 0; k < nt; ++k) hs[k] = t[k + 1] - t[k];
   int rc;

@@ -122,7 +122,9 @@ struct NuTabs {
   const int32_t *tout;               // [n_taylor]: packed block index of Taylor entry b
   const double *taylor;              // [n_taylor][2][kTaylorN]
   const double *tscale;              // [n_taylor][3]: V scale, K scale, 1 / (4 alpha c_b)
-  const int32_t *tdeg;               // [n_taylor][2] (degree of the pair's first entry)
+  const int32_t *tdeg;               // [n_taylor][2]: polynomial length of the pass (b, b + 1) that
+                                     // entry b belongs to, separated and touching pairs (one of
+                                     // kPolyLens: the pair's distance-bounded prefix)
 };
 void launch_nu_separated(const AsmParams *dp, const NuTabs &nu, const int32_t *tasks,
                          int64_t ntasks, hipStream_t s);
@@ -268,6 +270,7 @@ struct hb_ctx {
   hb::NuClosed *d_nu_closed = nullptr;
   int32_t n_nu_closed = 0, n_nu_taylor = 0;
   int32_t *d_nu_tout = nullptr, *d_nu_tdeg = nullptr;
+  double rho2_sep = 0.0, rho2_touch = 0.0;  // squared distance bounds of separated and touching pairs
   double *d_nu_taylor = nullptr, *d_nu_tscale = nullptr;
   double *d_nu_h = nullptr;          // [nt]: step lengths h_k
   double *d_nu_t = nullptr;          // [nt + 1]: the time nodes t_k
