@@ -40,9 +40,9 @@ PEAK_FP64_VALU = 78.6e12  # MI355X FP64 vector FLOP/s
 # instruction counts (wave instructions; 64 lanes each, an FMA is 2 FLOP).  Valid only for the
 # assembly sources they were taken on (sha256 prefix of COUNTER_SOURCES below); reported as null
 # otherwise.
-COUNTERS = {"source_sha256": "4d22f15358b041d5",
-            "fetch_kib": 14409.6875 + 460173.4375, "fetch_scale": 262144.0 / 131086.0625,
-            "write_kib": 2951712.65625 + 424960.0, "write_scale": 262144.0 / 262144.0,
+COUNTERS = {"source_sha256": "08cfbc323ac7b64f",
+            "fetch_kib": 13657.1875 + 460173.0625, "fetch_scale": 262144.0 / 131086.125,
+            "write_kib": 2950251.34375 + 424960.0, "write_scale": 262144.0 / 262144.0,
             "fma_f64": 1.35706111e9, "mul_f64": 2.7930831e8, "add_f64": 1.449856e8}
 COUNTER_SOURCES = ("hb_assemble.hip", "hb_sep.h", "hb_device.h", "hb_closed.h", "hb_internal.h")
 
