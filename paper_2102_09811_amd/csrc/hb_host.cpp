@@ -368,22 +368,28 @@ void taylor_poly_odd(int d, int deg, ld *out, int len) {
 // tol |c_0| for every w in [0, wmax], for the polynomial and for its derivative (the double-layer
 // kernel takes P - P'), both weighted by the factor e^{-w} the kernels multiply with.  Bounded
 // cell by cell on a grid: on [w_i, w_{i+1}] the powers are at most their values at w_{i+1} and
-// e^{-w} at most e^{-w_i}.
+// e^{-w} at most e^{-w_i}.  Per cell the tail is accumulated from the top term down; the first
+// term at which it passes the bound is the last one the cell needs.
 int taylor_len(const ld *c, int len, ld wmax, ld tol) {
   constexpr int kCells = 256;
   const ld bound = tol * fabsl(c[0]);
-  for (int N = 1; N < len; ++N) {
-    bool ok = true;
-    for (int i = 0; i < kCells && ok; ++i) {
-      const ld w0 = wmax * i / kCells, w1 = wmax * (i + 1) / kCells;
-      ld tail = 0.0L;
-      for (int n = N; n < len; ++n)
-        tail += fabsl(c[n]) * (powl(w1, (ld)n) + (ld)n * powl(w1, (ld)(n - 1)));
-      ok = expl(-w0) * tail <= bound;
+  int need = 1;
+  for (int i = 0; i < kCells && need < len; ++i) {
+    const ld w0 = wmax * i / kCells, w1 = wmax * (i + 1) / kCells;
+    const ld lim = bound / expl(-w0);  // +inf once e^{-w0} is 0: nothing is needed there
+    ld pw[hb::kTaylorN + 1];
+    pw[0] = 1.0L;
+    for (int n = 1; n < len; ++n) pw[n] = pw[n - 1] * w1;
+    ld tail = 0.0L;
+    for (int n = len - 1; n >= 1; --n) {
+      tail += fabsl(c[n]) * (pw[n] + (ld)n * pw[n - 1]);
+      if (!(tail <= lim)) {
+        need = std::max(need, n + 1);
+        break;
+      }
     }
-    if (ok) return N;
   }
-  return len;
+  return need;
 }
 
 int upload(hb_ctx *c, void **dst, const void *src, size_t bytes) {
